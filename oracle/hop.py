@@ -1,0 +1,140 @@
+"""Grid hopping: sphere tracing along the N^2 cell columns of the grid,
+continuing past the surface, then marching cubes on the cells reached.
+
+Paper, Section 3: rays R_ij start at the first cell centroid of column
+(i, j) (eq. cells) and advance by |f| (eq. iter); a cell is polygonized when
+the bound is small enough (eq. polydist) and the march resumes at the next
+cell until the ray leaves the volume (Algorithm 1).
+
+Hop rule used here (cell-quantised form of eq. iter): at the centroid c of
+cell (i, j, k), d = |f(c)| and s = floor(d / h).
+  s >= 1:  the ray skips s cells, k <- k + s;
+  s == 0:  cell (i, j, k) is a candidate for marching cubes, k <- k + 1;
+the ray ends once k >= N.  Every point of cells k .. k+s-1 of the column lies
+within h*sqrt(1/2 + (s - 1/2)^2) < s*h <= d of c, i.e. inside the open ball
+of radius d around c, which holds no zero of a distance bound: the skipped
+cells hold no sign change and no sign-change cell is missed.
+
+Columns are independent, so the oracle advances all live columns together
+(one numpy step per hop); `hop_column` is the same rule for one column as a
+plain loop.
+"""
+import numpy as np
+
+from . import mc
+
+
+def centroid_f64(lo, h, idx):
+    """Cell centroid coordinate lo + (idx + 1/2) h (eq. cells, generalised)."""
+    return np.float64(lo) + (np.asarray(idx, dtype=np.float64) + 0.5) * np.float64(h)
+
+
+def centroid_f32(lo, h, idx):
+    """Float32 centroid: m = (idx + 0.5f) * h rounded, then lo + m rounded."""
+    t = np.asarray(idx).astype(np.float32) + np.float32(0.5)
+    return np.float32(lo) + t * np.float32(h)
+
+
+def hop(sdb, n, lo, h, precision="f64", columns=None):
+    """Run the hop rule over every column (or the given column ids i*N + j).
+
+    Returns (candidate cell ids sorted, number of bound evaluations, per-column
+    evaluation counts).  precision "f32" is the twin of the GPU float32
+    formula: float32 coordinates, float32 f, s = floor(d * inv_h) in float32
+    with inv_h = float32(1/h), and the step capped at N.
+    """
+    if columns is None:
+        columns = np.arange(n * n, dtype=np.int64)
+    columns = np.asarray(columns, dtype=np.int64)
+    ci, cj = columns // n, columns % n
+    if precision == "f64":
+        x, y = centroid_f64(lo, h, ci), centroid_f64(lo, h, cj)
+    else:
+        x, y = centroid_f32(lo, h, ci), centroid_f32(lo, h, cj)
+        inv_h = np.float32(1.0 / np.float64(np.float32(h)))
+    k = np.zeros(len(columns), dtype=np.int64)
+    live = np.arange(len(columns))
+    evals = np.zeros(len(columns), dtype=np.int64)
+    cand = []
+    while live.size:
+        kk = k[live]
+        if precision == "f64":
+            f = sdb.f64(np.stack([x[live], y[live], centroid_f64(lo, h, kk)], axis=1))
+            s = np.floor(np.abs(f) / np.float64(h))
+        else:
+            f = sdb.f32(x[live], y[live], centroid_f32(lo, h, kk))
+            s = np.floor(np.abs(f) * inv_h)
+        if not np.all(np.isfinite(f)):
+            raise FloatingPointError("non-finite distance bound value")
+        evals[live] += 1
+        hit = s == 0
+        cand.append(columns[live[hit]] * n + kk[hit])
+        step = np.where(hit, 1, np.minimum(s, n)).astype(np.int64)
+        k[live] = kk + step
+        live = live[k[live] < n]
+    cells = np.sort(np.concatenate(cand)) if cand else np.zeros(0, np.int64)
+    return cells, int(evals.sum()), evals
+
+
+def hop_column(f_at_centroid, n, h):
+    """The hop rule along one column as a plain loop: f_at_centroid(k) -> f.
+    Returns (candidate k list, evaluation count)."""
+    k, evals, cand = 0, 0, []
+    while k < n:
+        d = abs(f_at_centroid(k))
+        evals += 1
+        s = int(np.floor(d / h))
+        if s == 0:
+            cand.append(k)
+            k += 1
+        else:
+            k += min(s, n)
+    return cand, evals
+
+
+def corner_points(n, cells):
+    """Distinct lattice points (i, j, k) that are corners of the given cells."""
+    cells = np.asarray(cells, dtype=np.int64)
+    i, j, k = cells // (n * n), (cells // n) % n, cells % n
+    n1 = n + 1
+    pid = np.concatenate([((i + dx) * n1 + (j + dy)) * n1 + (k + dz)
+                          for (dx, dy, dz) in mc.CORNER])
+    return np.unique(pid)
+
+
+class HopResult:
+    def __init__(self, mesh, candidates, hop_evals, corner_evals, column_evals):
+        self.mesh = mesh
+        self.candidates = candidates
+        self.hop_evals = hop_evals
+        self.corner_evals = corner_evals
+        self.column_evals = column_evals
+
+    @property
+    def evals(self):
+        return self.hop_evals + self.corner_evals
+
+
+def gridhop(sdb, n, lo, h, precision="f64"):
+    """Grid hopping followed by marching cubes on the candidate cells.
+
+    Corner values are evaluated once per distinct lattice point of the
+    candidates; their count is the corner evaluation count.
+    """
+    cells, hop_evals, col_evals = hop(sdb, n, lo, h, precision)
+    pid = corner_points(n, cells)
+    n1 = n + 1
+    a, b, c = pid // (n1 * n1), (pid // n1) % n1, pid % n1
+    if precision == "f64":
+        P = np.stack([mc.lattice_coords_f64(n, lo, h, v) for v in (a, b, c)], axis=1)
+        fv = sdb.f64(P) if len(pid) else np.zeros(0)
+    else:
+        xs = [mc.lattice_coords_f32(n, lo, h, v) for v in (a, b, c)]
+        fv = sdb.f32(*xs).astype(np.float64) if len(pid) else np.zeros(0)
+
+    def corner_value(i, j, k):
+        q = (i * n1 + j) * n1 + k
+        return fv[np.searchsorted(pid, q)]
+
+    mesh = mc.polygonize(n, lo, h, cells, corner_value)
+    return HopResult(mesh, cells, hop_evals, len(pid), col_evals)

@@ -1,0 +1,232 @@
+"""Signed distance bounds, FP64, with an FP32 twin.
+
+An SDB f satisfies |f(x)| <= distance from x to the zero set of f, negative
+inside (Section 1, Hart's definition).  A 1-Lipschitz function is one.
+
+Primitive distances are written from geometry:
+  sphere   ||q|| - r
+  box      u = |q| - b:  ||max(u, 0)|| + min(max_i u_i, 0)     (exact distance)
+  boxbound max_i u_i       the max over the six face planes (Section 4.2, eq. boxdist)
+  torus    sqrt((sqrt(q_x^2 + q_z^2) - R)^2 + q_y^2) - r
+  capsule  ||q - (0, 0, clamp(q_z, -a, a))|| - r
+  plane    n . p - d       (Section 4.1, eq. plane)
+and combined by the minimum, which is the union of the shapes (Section 4.3).
+
+The FP32 twin evaluates the same expressions in numpy float32 in a fixed
+order, one rounding per operation and no fused multiply-add; numpy's float32
+sqrt, division, min, max and abs are correctly rounded or exact.  The float32
+op order is documented beside each twin function.
+"""
+import numpy as np
+
+PRIM_SPHERE, PRIM_BOX, PRIM_TORUS, PRIM_CAPSULE, PRIM_PLANE, PRIM_BOXBOUND = 0, 1, 2, 3, 4, 5
+
+
+# ------------------------------------------------------------------------- FP64
+def prim_f64(rec, P):
+    """Distance bound of one primitive record at points P (n x 3), FP64."""
+    rec = np.asarray(rec, dtype=np.float64)
+    t = int(rec[0])
+    c = rec[1:4]
+    M = rec[4:13].reshape(3, 3)
+    a0, a1, a2 = rec[13], rec[14], rec[15]
+    if t == PRIM_PLANE:
+        return P @ M[0] - a0
+    q = (P - c) @ M.T
+    if t == PRIM_SPHERE:
+        return np.linalg.norm(q, axis=1) - a0
+    if t == PRIM_BOX:
+        u = np.abs(q) - np.array([a0, a1, a2])
+        return np.linalg.norm(np.maximum(u, 0.0), axis=1) + np.minimum(u.max(axis=1), 0.0)
+    if t == PRIM_BOXBOUND:
+        u = np.abs(q) - np.array([a0, a1, a2])
+        return u.max(axis=1)
+    if t == PRIM_TORUS:
+        ring = np.hypot(q[:, 0], q[:, 2]) - a0
+        return np.hypot(ring, q[:, 1]) - a1
+    if t == PRIM_CAPSULE:
+        w = q.copy()
+        w[:, 2] = q[:, 2] - np.clip(q[:, 2], -a0, a0)
+        return np.linalg.norm(w, axis=1) - a1
+    raise ValueError(f"unknown primitive type {t}")
+
+
+def union_f64(recs, P):
+    """Min-union of primitive records (Section 4.3), FP64."""
+    P = np.asarray(P, dtype=np.float64)
+    f = prim_f64(recs[0], P)
+    for r in recs[1:]:
+        f = np.minimum(f, prim_f64(r, P))
+    return f
+
+
+# ------------------------------------------------------------------ FP32 twin
+def prim_f32(rec, x, y, z):
+    """One primitive at float32 coordinate arrays, GPU op order.
+
+    d = p - c;  q_r = (M_r0*d_x + M_r1*d_y) + M_r2*d_z for r = 0, 1, 2
+    sphere:  sqrt((q_x*q_x + q_y*q_y) + q_z*q_z) - r
+    box:     u_i = |q_i| - b_i;  m_i = max(u_i, 0)
+             sqrt((m_x*m_x + m_y*m_y) + m_z*m_z) + min(max(u_x, max(u_y, u_z)), 0)
+    boxbound max(u_x, max(u_y, u_z))
+    torus:   s = sqrt(q_x*q_x + q_z*q_z) - R;  sqrt(s*s + q_y*q_y) - r
+    capsule: w = q_z - min(max(q_z, -a), a);  sqrt((q_x*q_x + q_y*q_y) + w*w) - r
+    plane:   ((n_x*x + n_y*y) + n_z*z) - d
+    """
+    rec = np.asarray(rec, dtype=np.float32)
+    t = int(rec[0])
+    M = rec[4:13]
+    a0, a1, a2 = rec[13], rec[14], rec[15]
+    if t == PRIM_PLANE:
+        return ((M[0] * x + M[1] * y) + M[2] * z) - a0
+    dx, dy, dz = x - rec[1], y - rec[2], z - rec[3]
+    qx = (M[0] * dx + M[1] * dy) + M[2] * dz
+    qy = (M[3] * dx + M[4] * dy) + M[5] * dz
+    qz = (M[6] * dx + M[7] * dy) + M[8] * dz
+    if t == PRIM_SPHERE:
+        return np.sqrt((qx * qx + qy * qy) + qz * qz) - a0
+    if t in (PRIM_BOX, PRIM_BOXBOUND):
+        ux, uy, uz = np.abs(qx) - a0, np.abs(qy) - a1, np.abs(qz) - a2
+        inner = np.maximum(ux, np.maximum(uy, uz))
+        if t == PRIM_BOXBOUND:
+            return inner
+        mx, my, mz = np.maximum(ux, np.float32(0)), np.maximum(uy, np.float32(0)), np.maximum(uz, np.float32(0))
+        return np.sqrt((mx * mx + my * my) + mz * mz) + np.minimum(inner, np.float32(0))
+    if t == PRIM_TORUS:
+        s = np.sqrt(qx * qx + qz * qz) - a0
+        return np.sqrt(s * s + qy * qy) - a1
+    if t == PRIM_CAPSULE:
+        w = qz - np.minimum(np.maximum(qz, -a0), a0)
+        return np.sqrt((qx * qx + qy * qy) + w * w) - a1
+    raise ValueError(f"unknown primitive type {t}")
+
+
+def union_f32(recs, x, y, z):
+    """Min-union in float32, primitives taken in record order."""
+    x = np.asarray(x, dtype=np.float32)
+    y = np.asarray(y, dtype=np.float32)
+    z = np.asarray(z, dtype=np.float32)
+    f = prim_f32(recs[0], x, y, z)
+    for r in recs[1:]:
+        f = np.minimum(f, prim_f32(r, x, y, z))
+    return f
+
+
+# ---------------------------------------------------------------------- network
+def features_f64(P, omegas):
+    """gamma(p) = [p, then per frequency: sin(w p_x,y,z), cos(w p_x,y,z)], FP64."""
+    P = np.asarray(P, dtype=np.float64)
+    cols = [P]
+    for w in np.asarray(omegas, dtype=np.float64):
+        cols.append(np.sin(w * P))
+        cols.append(np.cos(w * P))
+    return np.concatenate(cols, axis=1)
+
+
+def softplus(x):
+    """log(1 + e^x), evaluated stably."""
+    return np.logaddexp(0.0, x)
+
+
+def sigmoid(x):
+    return 0.5 * (1.0 + np.tanh(0.5 * x))
+
+
+def mlp_forward_f64(net, P, keep=False):
+    """Raw network output NN(gamma(p)) in FP64 (eq. nnsdb); optionally the
+    pre-activations and activations of every layer."""
+    a = features_f64(P, net["omegas"])
+    acts, pres = [a], []
+    Ws, bs = net["weights"], net["biases"]
+    for l in range(len(Ws)):
+        z = a @ np.asarray(Ws[l], dtype=np.float64).T + np.asarray(bs[l], dtype=np.float64)
+        pres.append(z)
+        a = softplus(z) if l < len(Ws) - 1 else z
+        acts.append(a)
+    out = a[:, 0]
+    return (out, pres, acts) if keep else out
+
+
+def mlp_input_grad_f64(net, P):
+    """d NN(gamma(p)) / d p, FP64, by the chain rule through every layer."""
+    P = np.asarray(P, dtype=np.float64)
+    _, pres, acts = mlp_forward_f64(net, P, keep=True)
+    Ws = [np.asarray(W, dtype=np.float64) for W in net["weights"]]
+    g = np.ones((P.shape[0], 1))
+    for l in range(len(Ws) - 1, -1, -1):
+        g = g @ Ws[l]                      # d out / d a_{l}
+        if l > 0:
+            g = g * sigmoid(pres[l - 1])   # softplus' = sigmoid
+    # g = d out / d gamma; chain into p
+    grad = g[:, 0:3].copy()
+    for kk, w in enumerate(np.asarray(net["omegas"], dtype=np.float64)):
+        gs = g[:, 3 + 6 * kk: 6 + 6 * kk]
+        gc = g[:, 6 + 6 * kk: 9 + 6 * kk]
+        grad += gs * w * np.cos(w * P) - gc * w * np.sin(w * P)
+    return grad
+
+
+def neural_f64(net, P):
+    """f(p) = a_s (||p|| - r0) + a_n NN(gamma(p)) + b, FP64 with the stored coefficients."""
+    P = np.asarray(P, dtype=np.float64)
+    nn = mlp_forward_f64(net, P)
+    return (np.float64(net["a_s"]) * (np.linalg.norm(P, axis=1) - np.float64(net["r0"]))
+            + np.float64(net["a_n"]) * nn + np.float64(net["b"]))
+
+
+# ------------------------------------------------------------------- dispatch
+class SDB:
+    """A distance bound with FP64 evaluation and, for analytic scenes, an FP32 twin."""
+
+    def __init__(self, kind, data):
+        self.kind = kind
+        self.data = data
+
+    @staticmethod
+    def prims(recs):
+        return SDB("prims", np.asarray(recs, dtype=np.float32))
+
+    @staticmethod
+    def neural(net):
+        return SDB("neural", net)
+
+    def f64(self, P):
+        if self.kind == "prims":
+            return union_f64(self.data, P)
+        return neural_f64(self.data, P)
+
+    def f32(self, x, y, z):
+        if self.kind != "prims":
+            raise NotImplementedError("the FP32 twin exists for analytic scenes only")
+        return union_f32(self.data, x, y, z)
+
+    def scaled(self, factor):
+        """factor * f: with factor > 1 this is no longer a distance bound."""
+        base = self
+
+        class _Scaled(SDB):
+            def f64(s, P):
+                return factor * base.f64(P)
+
+            def f32(s, x, y, z):
+                return np.float32(factor) * base.f32(x, y, z)
+
+        return _Scaled(self.kind, self.data)
+
+
+def calibrate_network(net, probe, amplitude, r0):
+    """Scale constants of the neural bound, FP64.
+
+    u = NN/S with S the product of the layers' largest singular values;
+    mu_u, sigma_u the mean and standard deviation of u over the probe points;
+    g = ||p|| - r0 + amplitude (u - mu_u)/sigma_u and L_hat = max |grad g|
+    over the probe.  A learned bound is shrunk by a factor found empirically
+    (Section 5.2); here the shrink is lambda * L_hat.
+    """
+    S = float(np.prod([np.linalg.svd(np.asarray(W, dtype=np.float64), compute_uv=False)[0]
+                       for W in net["weights"]]))
+    P = np.asarray(probe, dtype=np.float64)
+    u = mlp_forward_f64(net, P) / S
+    mu, sigma = float(u.mean()), float(u.std())
+    grad = P / np.linalg.norm(P, axis=1, keepdims=True) + (amplitude / (sigma * S)) * mlp_input_grad_f64(net, P)
+    return {"S": S, "mu_u": mu, "sigma_u": sigma, "L_hat": float(np.linalg.norm(grad, axis=1).max())}

@@ -1,0 +1,206 @@
+"""Pins of the oracle's grid hopper against the paper's analysis and against
+enumeration.
+
+* Plane perpendicular to the rays (Section 4.1, case 1): one approach step,
+  then the distance doubles each step; the per-column count has a closed form.
+* Plane parallel to the rays (case 2): a column at distance s*h takes
+  ceil(N/s) steps; the total is compared with the paper's N^2 (1 + 2 H_N).
+* O(N^2 log N) growth (Sections 3-4) versus N^3 for enumeration.
+* Grid hopping and enumeration give identical meshes (Section 5).
+* A scaled-up function (not a distance bound) makes the hopper miss cells
+  (Section 5.2), and the max-of-planes box bound (eq. boxdist) gives the same
+  mesh as the exact box distance with more evaluations (Section 4.2).
+* Sphere: watertight, Euler characteristic 2, area and volume converge to
+  pi and pi/6 at second order.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hop, mc, mesh, sdb
+
+
+def _mesh_equal(a, b):
+    return (np.array_equal(a.cells, b.cells) and np.array_equal(a.cases, b.cases)
+            and np.array_equal(a.tris, b.tris) and np.array_equal(a.edge_ids, b.edge_ids))
+
+
+@pytest.mark.parametrize("n", [16, 64, 256, 1024])
+def test_plane_perpendicular_closed_form(n):
+    C = 0.1234
+    _, lo, h = W.grid(n)
+    lo, h = float(lo), float(h)
+    S = sdb.SDB.prims(W.plane_scene((0, 0, 1), C))
+    cols = np.arange(0, n * n, max(1, n * n // 64))
+    cells, total, per_col = hop.hop(S, n, lo, h, columns=cols)
+    # approach: the exact distance lands in the cell holding C in one step
+    z0 = lo + 0.5 * h
+    k1 = math.floor((C - z0) / h)
+    frac = (C - z0) / h - k1
+    assert 0 < frac < 1
+    # then cells k1 and k1+1 are within h of the plane; afterwards the distance
+    # from the plane is (m - frac) h at cell k1 + m, so the steps are 1, 2, 4, ...
+    escape = 0
+    k = k1 + 2
+    while k < n:
+        escape += 1
+        k += math.floor(k - k1 - frac)
+    expected = 1 + 2 + escape
+    assert (per_col == expected).all()
+    assert expected == round(math.log2(n)) + 2        # doubling: log2 N escape steps
+    assert len(cells) == 2 * len(cols)
+
+
+@pytest.mark.parametrize("n", [16, 64, 256])
+def test_plane_parallel_count_and_harmonic_bound(n):
+    C = 0.1234
+    _, lo, h = W.grid(n)
+    lo, h = float(lo), float(h)
+    S = sdb.SDB.prims(W.plane_scene((1, 0, 0), C))
+    cells, total, per_col = hop.hop(S, n, lo, h)
+    xs = lo + (np.arange(n) + 0.5) * h
+    s = np.floor(np.abs(xs - C) / h).astype(int)
+    expected_per_x = np.where(s == 0, n, np.ceil(n / np.maximum(s, 1)))
+    assert total == n * int(expected_per_x.sum())
+    H = sum(1.0 / i for i in range(1, n + 1))
+    ratio = total / (n * n * (1 + 2 * H))
+    assert 0.9 < ratio < 1.1                          # the paper's estimate is approximate
+    # the candidates are exactly the columns whose centre line is within h of x = C
+    assert len(cells) == n * n * int((s == 0).sum())
+
+
+def test_evaluation_count_grows_like_n2_log_n():
+    S = sdb.SDB.prims(W.sphere_scene())
+    ns = [16, 32, 64, 128, 256]
+    per_col = []
+    for n in ns:
+        _, total, _ = hop.hop(S, *W.grid(n))
+        per_col.append(total / n ** 2)
+    x = np.log2(ns)
+    slope, icpt = np.polyfit(x, per_col, 1)
+    pred = slope * x + icpt
+    r2 = 1 - ((per_col - pred) ** 2).sum() / ((per_col - np.mean(per_col)) ** 2).sum()
+    assert r2 > 0.99
+    assert 0.8 < slope < 1.3                          # about one more step per doubling
+    # enumeration evaluates (N+1)^3 points, about N per column: the advantage
+    # of hopping grows with every doubling of N
+    adv = [(n + 1) ** 3 / n ** 2 / c for n, c in zip(ns, per_col)]
+    assert np.all(np.diff(adv) > 0) and adv[-1] > 20
+
+
+def test_general_plane_logarithmic():
+    nrm = np.array([0.3, -0.4, -0.866])
+    S = sdb.SDB.prims(W.plane_scene(nrm, 0.05))
+    vals = [hop.hop(S, *W.grid(n))[1] / n ** 2 for n in (16, 32, 64, 128)]
+    d = np.diff(vals)
+    assert np.all(d > 0) and np.all(d < 3.0)          # bounded increment per doubling
+
+
+@pytest.mark.parametrize("scene,n", [("sphere", 16), ("sphere", 64), ("csg0", 32), ("csg1", 64),
+                                     ("csg2", 48), ("box", 40)])
+def test_hop_equals_enumeration(scene, n):
+    recs = {"sphere": W.sphere_scene(), "csg0": W.csg_scene(0), "csg1": W.csg_scene(1),
+            "csg2": W.csg_scene(2), "box": W.box_scene((0.31, 0.2, 0.45), (0.05, -0.1, 0.02))}[scene]
+    S = sdb.SDB.prims(recs)
+    g = W.grid(n)
+    dense, _ = mc.enumerate_mesh(S, *g)
+    hr = hop.gridhop(S, *g)
+    assert len(dense.cells) > 0
+    assert _mesh_equal(dense, hr.mesh)
+    assert np.isin(dense.cells, hr.candidates).all()
+    np.testing.assert_array_equal(dense.ts, hr.mesh.ts)
+
+
+def test_hop_equals_enumeration_neural():
+    S = sdb.SDB.neural(W.neural_scene(0, 64))
+    g = W.grid(32)
+    dense, _ = mc.enumerate_mesh(S, *g)
+    hr = hop.gridhop(S, *g)
+    assert _mesh_equal(dense, hr.mesh)
+    assert len(dense.cells) > 500
+
+
+def test_vectorised_hopper_matches_plain_loop():
+    recs = W.csg_scene(0)
+    S = sdb.SDB.prims(recs)
+    n, lo, h = W.grid(32)
+    lo, h = float(lo), float(h)
+    rng = np.random.default_rng(7)
+    cols = rng.choice(n * n, 40, replace=False)
+    cells, _, per_col = hop.hop(S, n, lo, h, columns=cols)
+    for q, c in enumerate(cols):
+        i, j = divmod(int(c), n)
+        x, y = lo + (i + 0.5) * h, lo + (j + 0.5) * h
+
+        def f(k):
+            return float(sdb.union_f64(recs, np.array([[x, y, lo + (k + 0.5) * h]]))[0])
+
+        ks, ev = hop.hop_column(f, n, h)
+        assert ev == per_col[q]
+        mine = cells[(cells // n) == c] % n
+        assert list(mine) == ks
+
+
+def test_scaled_function_misses_cells():
+    # 2 f overestimates the distance: hops jump over surface cells
+    base = sdb.SDB.prims(W.sphere_scene())
+    g = W.grid(64)
+    dense, _ = mc.enumerate_mesh(base, *g)
+    cells, _, _ = hop.hop(base.scaled(2.0), *g)
+    missed = np.setdiff1d(dense.cells, cells)
+    assert len(missed) > 1000
+    # 1/2 f is still a bound: nothing missed, more evaluations
+    cells_half, ev_half, _ = hop.hop(base.scaled(0.5), *g)
+    _, ev_full, _ = hop.hop(base, *g)
+    assert np.isin(dense.cells, cells_half).all() and ev_half > ev_full
+
+
+def test_box_bound_same_mesh_more_evaluations():
+    half, ctr = (0.3, 0.45, 0.2), (0.02, -0.05, 0.11)
+    g = W.grid(64)
+    exact = hop.gridhop(sdb.SDB.prims(W.box_scene(half, ctr)), *g)
+    bound = hop.gridhop(sdb.SDB.prims(W.box_scene(half, ctr, bound=True)), *g)
+    assert np.array_equal(exact.mesh.cells, bound.mesh.cells)
+    assert np.array_equal(exact.mesh.tris, bound.mesh.tris)
+    assert bound.hop_evals > exact.hop_evals
+
+
+def test_sphere_closed_forms_converge():
+    S = sdb.SDB.prims(W.sphere_scene(0.5))
+    ea, ev = [], []
+    for n in (16, 32, 64, 128):
+        m = hop.gridhop(S, *W.grid(n)).mesh
+        P, T = m.positions(), m.tri_vertex_index()
+        assert mesh.is_closed_oriented(T)
+        assert mesh.euler_characteristic(T) == 2
+        ea.append(abs(mesh.area(P, T) - math.pi))
+        ev.append(abs(mesh.volume(P, T) - math.pi / 6))
+        # vertices lie on the sphere up to the interpolation error O(h^2)
+        r = np.linalg.norm(P, axis=1)
+        assert np.abs(r - 0.5).max() < 0.5 * (2.0 / n) ** 2
+    for e in (ea, ev):
+        ratios = np.array(e[:-1]) / np.array(e[1:])
+        assert np.all((ratios > 3.0) & (ratios < 5.0))   # second order in h
+
+
+def test_fp32_twin_agrees_with_fp64():
+    recs = W.csg_scene(0)
+    S = sdb.SDB.prims(recs)
+    n, lo, h = W.grid(64)
+    rng = np.random.default_rng(0)
+    P = rng.uniform(-1, 1, size=(20000, 3)).astype(np.float32)
+    f32 = S.f32(P[:, 0], P[:, 1], P[:, 2]).astype(np.float64)
+    f64 = S.f64(P.astype(np.float64))
+    assert np.abs(f32 - f64).max() < 2e-6
+    a = hop.gridhop(S, n, lo, h, precision="f32")
+    b = hop.gridhop(S, n, lo, h, precision="f64")
+    assert _mesh_equal(a.mesh, b.mesh)
+    # t = f_a/(f_a - f_b) amplifies the float32 rounding of f by 1/|f_a - f_b|:
+    # nearly all vertices agree to 1e-5 of an edge, none by more than 1e-3
+    dt = np.abs(a.mesh.ts - b.mesh.ts)
+    assert dt.max() < 1e-3 and (dt > 1e-5).mean() < 1e-3
+    # twin centroids are exact for power-of-two grids
+    np.testing.assert_array_equal(hop.centroid_f32(lo, h, np.arange(n)).astype(np.float64),
+                                  hop.centroid_f64(lo, h, np.arange(n)))

@@ -1,0 +1,201 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU path.
+
+This module only draws parameters: primitive placements and sizes, network
+weights, point sets and grid descriptions.  It evaluates no distance bound,
+hops no ray and polygonizes no cell; both the oracle and the HIP path take
+what it returns as plain inputs.
+
+Every floating-point parameter is rounded to float32 here, once, so that the
+FP64 oracle and the FP32 GPU path see identical parameter values and differ
+only in arithmetic.
+
+Primitive record layout (float32, PRIM_STRIDE = 16 per primitive):
+  [0]     type code (PRIM_*)
+  [1:4]   centre c
+  [4:13]  3x3 matrix M, row-major; the local point is q = M (p - c)
+  [13:16] shape parameters, per type:
+          sphere    (r, 0, 0)
+          box       (bx, by, bz) half extents       (exact Euclidean distance)
+          torus     (R, r, 0)   ring in the local xz plane, axis = local y
+          capsule   (a, r, 0)   segment [-a, a] on the local z axis
+          plane     (d, 0, 0)   f = n . p - d with n = first row of M, c = 0
+          boxbound  (bx, by, bz) max of the six face-plane distances
+"""
+import json
+import os
+
+import numpy as np
+
+PRIM_SPHERE, PRIM_BOX, PRIM_TORUS, PRIM_CAPSULE, PRIM_PLANE, PRIM_BOXBOUND = 0, 1, 2, 3, 4, 5
+PRIM_STRIDE = 16
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------------------- grid
+def grid(n, lo=-1.0, extent=2.0):
+    """Cell grid over the cube [lo, lo + n*h]^3 with h = extent/n, as float32.
+
+    The paper's grid is the unit cube centred at the origin, split into N^3
+    cells (Section 3, eq. cells).  The workloads use lo = -1, extent = 2; for
+    power-of-two n every centroid and lattice coordinate is exact in float32.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    return int(n), np.float32(lo), np.float32(np.float64(extent) / n)
+
+
+# ---------------------------------------------------------------------- primitives
+def _record(ptype, centre, mat, params):
+    r = np.zeros(PRIM_STRIDE, dtype=np.float32)
+    r[0] = ptype
+    r[1:4] = np.asarray(centre, dtype=np.float64)
+    r[4:13] = np.asarray(mat, dtype=np.float64).reshape(9)
+    r[13:13 + len(params)] = np.asarray(params, dtype=np.float64)
+    return r
+
+
+def _quat_to_local(qv):
+    """Rotation R from a unit quaternion (w, x, y, z); returns M = R^T (world -> local)."""
+    w, x, y, z = qv
+    R = np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+    ])
+    return R.T
+
+
+def sphere_scene(radius=0.5, centre=(0.0, 0.0, 0.0)):
+    """Exact sphere f(p) = ||p - c|| - r as a one-primitive union."""
+    return _record(PRIM_SPHERE, centre, np.eye(3), (radius,))[None, :]
+
+
+def plane_scene(normal, offset):
+    """Plane f(p) = n . p - d with a unit normal (Section 4.1, eq. plane)."""
+    n = np.asarray(normal, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    m = np.zeros((3, 3))
+    m[0] = n
+    return _record(PRIM_PLANE, (0.0, 0.0, 0.0), m, (offset,))[None, :]
+
+
+def box_scene(half, centre=(0.0, 0.0, 0.0), bound=False):
+    """Axis-aligned box: exact distance, or the max-of-planes bound of eq. boxdist."""
+    return _record(PRIM_BOXBOUND if bound else PRIM_BOX, centre, np.eye(3), half)[None, :]
+
+
+def csg_scene(seed=0, n_prim=12):
+    """Min-union of n_prim seeded primitives (Section 4.3 union by min).
+
+    Type of primitive i is i mod 4 (sphere, box, torus, capsule).  Per
+    primitive, in this order: centre ~ U[-0.6, 0.6]^3, a quaternion from
+    N(0, I_4) normalised (uniform rotation), then the size parameters:
+      sphere  r ~ U[0.1, 0.3]
+      box     half extents ~ U[0.05, 0.2]^3
+      torus   R ~ U[0.1, 0.25], r ~ U[0.03, 0.08]
+      capsule a ~ U[0.05, 0.2], r ~ U[0.03, 0.1]
+    """
+    rng = np.random.default_rng(seed)
+    recs = []
+    for i in range(n_prim):
+        t = i % 4
+        c = rng.uniform(-0.6, 0.6, size=3)
+        qv = rng.standard_normal(4)
+        qv = qv / np.linalg.norm(qv)
+        m = _quat_to_local(qv)
+        if t == 0:
+            recs.append(_record(PRIM_SPHERE, c, m, (rng.uniform(0.1, 0.3),)))
+        elif t == 1:
+            recs.append(_record(PRIM_BOX, c, m, rng.uniform(0.05, 0.2, size=3)))
+        elif t == 2:
+            recs.append(_record(PRIM_TORUS, c, m, (rng.uniform(0.1, 0.25), rng.uniform(0.03, 0.08))))
+        else:
+            recs.append(_record(PRIM_CAPSULE, c, m, (rng.uniform(0.05, 0.2), rng.uniform(0.03, 0.1))))
+    return np.stack(recs)
+
+
+# -------------------------------------------------------------------------- network
+def fourier_omegas(n_freq=16):
+    """Angular frequencies w_k = 2^(k/4) rad per unit, k = 0..n_freq-1 (float32)."""
+    return (2.0 ** (np.arange(n_freq) / 4.0)).astype(np.float32)
+
+
+def mlp_net(seed=0, width=256, depth=4, n_freq=16):
+    """Random-weight MLP  gamma(p) -> depth x [width, softplus] -> 1.
+
+    gamma(p) = [p_x, p_y, p_z, then for each k: sin(w_k p_x), sin(w_k p_y),
+    sin(w_k p_z), cos(w_k p_x), cos(w_k p_y), cos(w_k p_z)], 3 + 6 n_freq
+    features.  Weights W_l (fan_out x fan_in) ~ N(0, 1/fan_in), drawn in layer
+    order from default_rng(seed); biases zero.  All float32.
+    """
+    rng = np.random.default_rng(seed)
+    dims = [3 + 6 * n_freq] + [width] * depth + [1]
+    weights, biases = [], []
+    for l in range(len(dims) - 1):
+        fan_in, fan_out = dims[l], dims[l + 1]
+        weights.append((rng.standard_normal((fan_out, fan_in)) / np.sqrt(fan_in)).astype(np.float32))
+        biases.append(np.zeros(fan_out, dtype=np.float32))
+    return {"omegas": fourier_omegas(n_freq), "weights": weights, "biases": biases}
+
+
+def probe_points(seed=3, n=65536):
+    """Uniform points in [-1, 1]^3 used to calibrate a network's scale."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, 3))
+
+
+def loss_targets(seed=1, n=4096, radius=0.4):
+    """Points on a sphere of the given radius: radius * z/||z||, z ~ N(0, I_3)."""
+    z = np.random.default_rng(seed).standard_normal((n, 3))
+    return (radius * z / np.linalg.norm(z, axis=1, keepdims=True)).astype(np.float32)
+
+
+NEURAL_LAMBDA = 1.5      # shrink factor of a learned bound (Section 5.2)
+NEURAL_R0 = 0.5          # radius of the sphere prior that places the surface
+NEURAL_AMPLITUDE = 0.05  # amplitude of the standardised network perturbation
+
+
+def neural_calibration_path():
+    return os.path.join(_HERE, "neural_calibration.json")
+
+
+def neural_scene(seed=0, width=256, depth=4, n_freq=16):
+    """Neural bound  f(p) = a_s (||p|| - r0) + a_n NN(gamma(p)) + b.
+
+    The coefficients come from a stored calibration of this exact network
+    (keyed by seed/width/depth/n_freq): with u = NN/S, S the product of the
+    layers' spectral norms, g = ||p|| - r0 + A (u - mu_u)/sigma_u and
+    f = g / (lambda L), where mu_u, sigma_u are the mean and deviation of u
+    over probe_points() and L the largest |grad g| there.  Hence
+    a_s = 1/(lambda L), a_n = A/(sigma_u S lambda L), b = -A mu_u/(sigma_u lambda L).
+    """
+    net = mlp_net(seed, width, depth, n_freq)
+    key = f"seed{seed}_w{width}_d{depth}_f{n_freq}"
+    with open(neural_calibration_path()) as fh:
+        cal = json.load(fh)
+    if key not in cal:
+        raise KeyError(f"no calibration stored for network {key}")
+    c = cal[key]
+    lam_l = NEURAL_LAMBDA * c["L_hat"]
+    net["r0"] = np.float32(NEURAL_R0)
+    net["a_s"] = np.float32(1.0 / lam_l)
+    net["a_n"] = np.float32(NEURAL_AMPLITUDE / (c["sigma_u"] * c["S"] * lam_l))
+    net["b"] = np.float32(-NEURAL_AMPLITUDE * c["mu_u"] / (c["sigma_u"] * lam_l))
+    net["calibration"] = c
+    return net
+
+
+# -------------------------------------------------------------------------- batch
+def batch_scenes(seed=2, n_shapes=64):
+    """Mixed batch: N_s ~ choice{64,128,256,512}; even s a CSG union of
+    n_prim ~ U{4..16} primitives (seed 2000+s), odd s an MLP of width
+    ~ choice{64,128,256} (seed 1000+s)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_shapes):
+        n = int(rng.choice([64, 128, 256, 512]))
+        if s % 2 == 0:
+            out.append({"kind": "csg", "n": n, "seed": 2000 + s, "n_prim": int(rng.integers(4, 17))})
+        else:
+            out.append({"kind": "mlp", "n": n, "seed": 1000 + s, "width": int(rng.choice([64, 128, 256]))})
+    return out
