@@ -1,0 +1,184 @@
+/*
+ * gh.h - grid hopping polygonizer for MI355X (gfx950), C ABI.
+ *
+ * The method (Markus & Suznjevic, "Theoretical and Empirical Analysis of a
+ * Fast Algorithm for Extracting Polygons from Signed Distance Bounds"):
+ * sphere tracing along the N^2 axis-aligned cell columns of an N^3 grid,
+ * continued past the surface (Section 3, eq. iter and Algorithm 1), then
+ * marching cubes on the cells the rays stop in.  Each step evaluates the
+ * signed distance bound f at the centroid of cell (i, j, k) of the column and
+ * skips s = floor(|f|/h) cells; s == 0 marks the cell as a candidate and moves
+ * on by one.  Section 5 requires the same mesh as marching cubes over every
+ * cell ("enumeration", Section 2), which gh_dense provides for comparison.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers are DEVICE pointers unless their name ends in _h (host).
+ *  - Every call enqueues work on `stream` (a hipStream_t) and returns without
+ *    synchronizing, except sdb_describe, which waits for its upload.
+ *  - The library allocates no device memory.  The caller owns every buffer:
+ *    descriptor blobs, workspaces, counters and outputs.
+ *  - Argument errors are detected on the host before anything is enqueued
+ *    and returned synchronously (GH_EINVAL, GH_EUNSUPPORTED); gh_last_error()
+ *    then describes them.  Launch failures return GH_EHIP.
+ *  - Data-dependent errors (an output or workspace capacity exceeded, a
+ *    non-finite bound value) are reported asynchronously in gh_counters.flags.
+ *    On overflow the counts still hold the sizes required and nothing is
+ *    written past any capacity; the caller re-runs with larger buffers.
+ *  - Calls that share a workspace or counters must be ordered on one stream.
+ *
+ * Grid: cube [lo, lo + n*h]^3 split into n^3 cells (Section 3, eq. cells, with
+ * the unit cube generalised to any origin and step).  Lattice point
+ * P(a, b, c) = lo + (a, b, c)*h, 0 <= a, b, c <= n; cell (i, j, k) spans
+ * P(i, j, k)..P(i+1, j+1, k+1), centroid lo + (i + 1/2, j + 1/2, k + 1/2)*h.
+ * Rays run along +z, one per column (i, j) (Section 3, the rays R_ij).
+ * Ids: cell (i*n + j)*n + k; lattice point (a*(n+1) + b)*(n+1) + c;
+ * lattice edge 3*point + axis (0 = x, 1 = y, 2 = z) from its lower end.
+ * Supported: 1 <= n <= 2048.
+ *
+ * Arithmetic: the analytic bounds are evaluated in float32 with one rounding
+ * per operation in a documented order (no contraction); the hop test
+ * s = floor(|f| * inv_h), inv_h = float32(1/h), is taken in float32; vertex
+ * parameters t = f_a/(f_a - f_b) are float32.
+ */
+#ifndef GH_H
+#define GH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GH_OK = 0,
+  GH_EINVAL = -1,        /* bad argument (null pointer, size, grid) */
+  GH_ECAPACITY = -2,     /* a caller buffer or workspace is too small */
+  GH_EHIP = -3,          /* the HIP runtime reported an error */
+  GH_EUNSUPPORTED = -4,  /* valid but not supported (e.g. n > 2048) */
+  GH_ENONFINITE = -5     /* the bound returned NaN or Inf */
+} gh_status;
+
+/* Bits of gh_counters.flags (asynchronous data errors). */
+#define GH_FLAG_CAPACITY 1u  /* some output/workspace capacity was exceeded */
+#define GH_FLAG_NONFINITE 2u /* a bound value was NaN or Inf */
+#define GH_FLAG_INTERNAL 4u  /* inconsistent workspace contents (a library bug) */
+
+typedef struct {
+  int32_t n;  /* cells per axis */
+  float lo;   /* cube origin (all three axes) */
+  float h;    /* cell edge length, > 0 */
+} gh_grid;
+
+/* Device-resident statistics and data-error flags of a polygonization.
+ * gh_hop (and gh_dense) reset the whole struct; gh_mc fills the rest. */
+typedef struct {
+  int64_t n_hop_evals;    /* bound evaluations by the hop (gh_dense: (n+1)^3) */
+  int64_t n_cand;         /* candidate cells (gh_dense: sign-change cells) */
+  int64_t n_corner;       /* distinct lattice points of candidates, evaluated once */
+  int64_t n_cells;        /* cells that produced triangles */
+  int64_t n_vert;         /* welded vertices (one per crossing lattice edge) */
+  int64_t n_tri;          /* triangles */
+  int64_t n_reeval;       /* float32 re-evaluations taken by the bf16 network path */
+  uint32_t flags;         /* GH_FLAG_* */
+  uint32_t reserved;
+} gh_counters;
+
+/* ----------------------------------------------------------------- bounds */
+enum { GH_SDB_PRIMS = 1, GH_SDB_MLP = 2 };
+enum { GH_PREC_FP32 = 0, GH_PREC_BF16 = 1 };
+
+/* Primitive record: 16 float32 values.
+ *  [0] type: 0 sphere, 1 box (exact), 2 torus, 3 capsule, 4 plane,
+ *            5 box bound (max of six face planes, Section 4.2 eq. boxdist)
+ *  [1..3] centre c;  [4..12] 3x3 matrix M row-major, local q = M (p - c)
+ *  [13..15] sphere (r), box/box bound (bx, by, bz), torus (R, r) about local y,
+ *           capsule (a, r) on local z in [-a, a], plane (d) with f = M_row0 . p - d.
+ * The bound is the minimum over the records (union, Section 4.3). */
+#define GH_PRIM_FLOATS 16
+
+typedef struct {
+  int32_t kind;                  /* GH_SDB_PRIMS or GH_SDB_MLP */
+  /* GH_SDB_PRIMS */
+  int32_t n_prim;                /* 1 .. 64 */
+  const float* prims_h;          /* n_prim * GH_PRIM_FLOATS, host */
+  /* GH_SDB_MLP (eq. nnsdb): f = a_s (||p|| - r0) + a_n NN(gamma(p)) + b,
+   * gamma(p) = [p, for each k: sin(w_k p_x,y,z), cos(w_k p_x,y,z)],
+   * NN = W_D ... softplus(W_1 gamma + b_1) ... + b_D, D = depth + 1 layers. */
+  int32_t n_freq;                /* 0 .. 16 */
+  int32_t width;                 /* 64, 128 or 256 */
+  int32_t depth;                 /* hidden layers, 1 .. 8 */
+  int32_t precision;             /* GH_PREC_FP32 or GH_PREC_BF16 */
+  const float* omegas_h;         /* n_freq, host */
+  const float* const* weights_h; /* depth+1 host arrays, row-major fan_out x fan_in */
+  const float* const* biases_h;  /* depth+1 host arrays of fan_out */
+  float a_s, r0, a_n, b;
+  float bf16_margin;             /* eps_b >= max |f_bf16 - f_fp32|, used by the hop test */
+} gh_sdb_spec;
+
+/* Opaque, caller-owned, plain-old-data handle filled by sdb_describe.  It
+ * refers to the device blob, which must outlive every call that uses it. */
+typedef struct {
+  uint64_t opaque[24];
+} gh_sdb_desc;
+
+/* Validate a bound and pack it into the caller's device blob.
+ * spec_h: host.  dev_blob: device memory of blob_bytes (may be NULL to query
+ * the size, written to *blob_needed_h).  desc_h: host, filled on success.
+ * Uploads on `stream` and waits for the upload.  Returns GH_ECAPACITY when
+ * blob_bytes < *blob_needed_h, GH_EINVAL / GH_EUNSUPPORTED on a bad spec. */
+gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_bytes,
+                       size_t* blob_needed_h, gh_sdb_desc* desc_h, void* stream);
+
+/* Workspace bytes for gh_hop/gh_mc on this grid, holding up to corner_cap
+ * distinct corner points (corner_cap <= 0 selects 16*(n+1)^2). */
+gh_status gh_workspace_size(const gh_grid* grid_h, int64_t corner_cap, size_t* bytes_h);
+
+/* Grid hopping over all n^2 columns (Section 3, Algorithm 1).  Records the
+ * candidate cells in the workspace and resets *ctr, then sets n_hop_evals,
+ * n_cand and flags.  ws: device, ws_bytes >= gh_workspace_size(grid, corner_cap). */
+gh_status gh_hop(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
+                 int64_t corner_cap, gh_counters* ctr, void* stream);
+
+/* Marching cubes on the cells recorded in ws by gh_hop or gh_dense
+ * (Section 5: every reached cell is polygonized by marching cubes).
+ * Evaluates the bound once per distinct corner point, welds one vertex per
+ * crossing lattice edge and writes:
+ *   verts     [vert_cap][3] float32 positions, ordered by lattice edge id
+ *   vert_edge [vert_cap] int64 lattice edge id of each vertex (may be NULL)
+ *   vert_t    [vert_cap] float32 edge parameter t (may be NULL)
+ *   tris      [tri_cap][3] int32 vertex indices, facing from f < 0 to f >= 0,
+ *             grouped by cell in cell-id order
+ *   cells     [cell_cap] int64 ids of cells with triangles, ascending (may be NULL)
+ *   cases     [cell_cap] uint8 inside-corner mask of those cells, corner
+ *             dx + 2 dy + 4 dz inside when f < 0 (may be NULL)
+ * Sets n_corner, n_cells, n_vert, n_tri; GH_FLAG_CAPACITY if any capacity
+ * (including the workspace corner_cap) was too small. */
+gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
+                int64_t corner_cap, float* verts, int64_t* vert_edge, float* vert_t, int64_t vert_cap,
+                int32_t* tris, int64_t tri_cap, int64_t* cells, uint8_t* cases, int64_t cell_cap,
+                gh_counters* ctr, void* stream);
+
+/* Enumeration baseline (Section 2): evaluates f at every lattice point into
+ * dense (device, (n+1)^3 float32, layout [c][a][b]), records every
+ * sign-change cell in ws as the candidate set and resets *ctr.  gh_mc then
+ * polygonizes exactly as after gh_hop. */
+gh_status gh_dense(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
+                   int64_t corner_cap, float* dense, gh_counters* ctr, void* stream);
+
+/* Export the candidate cells recorded in ws as ascending int64 cell ids into
+ * out[cap]; the count is n_cand of *ctr.  Sets GH_FLAG_CAPACITY if cap is
+ * too small. */
+gh_status gh_candidates(const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
+                        int64_t* out, int64_t cap, gh_counters* ctr, void* stream);
+
+/* Evaluate the bound at m points xyz [m][3] (device) into f [m] (device). */
+gh_status gh_eval_points(const gh_sdb_desc* desc_h, const float* xyz, float* f, int64_t m, void* stream);
+
+/* Human-readable description of the last synchronous error on this thread. */
+const char* gh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GH_H */

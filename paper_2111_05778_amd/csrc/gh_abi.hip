@@ -1,0 +1,201 @@
+// C ABI of the grid hopping polygonizer: argument checks, workspace
+// carving and kernel launches.  No device memory is allocated here.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "gh.h"
+#include "gh_launch.h"
+#include "gh_layout.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gh_status fail(gh_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+gh_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return GH_OK;
+  return fail(GH_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static_assert(sizeof(gh::DevSdb) <= sizeof(gh_sdb_desc), "descriptor does not fit");
+
+gh_status read_desc(const gh_sdb_desc* desc_h, gh::DevSdb* d) {
+  if (!desc_h) return fail(GH_EINVAL, "desc is NULL");
+  memcpy(d, desc_h, sizeof(*d));
+  if (d->magic != gh::kDescMagic) return fail(GH_EINVAL, "desc was not filled by sdb_describe");
+  return GH_OK;
+}
+
+gh_status read_grid(const gh_grid* grid_h, gh::Grid* g) {
+  if (!grid_h) return fail(GH_EINVAL, "grid is NULL");
+  if (grid_h->n < 1) return fail(GH_EINVAL, "grid n = %d must be >= 1", grid_h->n);
+  if (grid_h->n > gh::kMaxN) return fail(GH_EUNSUPPORTED, "grid n = %d exceeds %d", grid_h->n, gh::kMaxN);
+  if (!(grid_h->h > 0.f) || !isfinite(grid_h->h)) return fail(GH_EINVAL, "grid h must be finite and > 0");
+  if (!isfinite(grid_h->lo) || !isfinite(grid_h->lo + grid_h->n * grid_h->h))
+    return fail(GH_EINVAL, "grid extent is not finite");
+  g->n = grid_h->n;
+  g->lo = grid_h->lo;
+  g->h = grid_h->h;
+  g->inv_h = (float)(1.0 / (double)grid_h->h);
+  return GH_OK;
+}
+
+int64_t default_cap(int n) { return 16 * (int64_t)(n + 1) * (n + 1); }
+
+gh_status carve(const gh::Grid& g, void* ws, size_t ws_bytes, int64_t cap, gh::Workspace* w) {
+  if (!ws) return fail(GH_EINVAL, "workspace is NULL");
+  if (cap <= 0) cap = default_cap(g.n);
+  if (cap >= (int64_t)1 << 31) return fail(GH_EUNSUPPORTED, "corner_cap %lld too large", (long long)cap);
+  const size_t need = gh::workspace_layout(g.n, cap, nullptr, nullptr);
+  if (ws_bytes < need)
+    return fail(GH_ECAPACITY, "workspace of %zu bytes, %zu needed for n=%d corner_cap=%lld", ws_bytes, need, g.n,
+                (long long)cap);
+  if (((uintptr_t)ws) & 255) return fail(GH_EINVAL, "workspace must be 256-byte aligned");
+  gh::workspace_layout(g.n, cap, ws, w);
+  return GH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gh_last_error(void) { return g_last_error.c_str(); }
+
+gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_bytes, size_t* blob_needed_h,
+                       gh_sdb_desc* desc_h, void* stream) {
+  if (!spec_h) return fail(GH_EINVAL, "spec is NULL");
+  if (spec_h->kind != GH_SDB_PRIMS)
+    return fail(GH_EUNSUPPORTED, "bound kind %d is not supported by this build", spec_h->kind);
+  const int np = spec_h->n_prim;
+  if (np < 1 || np > gh::kMaxPrims) return fail(GH_EINVAL, "n_prim = %d must be in [1, %d]", np, gh::kMaxPrims);
+  if (!spec_h->prims_h) return fail(GH_EINVAL, "prims_h is NULL");
+  for (int p = 0; p < np; ++p) {
+    const float* r = spec_h->prims_h + (size_t)p * GH_PRIM_FLOATS;
+    const float t = r[0];
+    if (!(t == 0.f || t == 1.f || t == 2.f || t == 3.f || t == 4.f || t == 5.f))
+      return fail(GH_EINVAL, "primitive %d has unknown type %g", p, (double)t);
+    for (int q = 1; q < GH_PRIM_FLOATS; ++q)
+      if (!isfinite(r[q])) return fail(GH_EINVAL, "primitive %d parameter %d is not finite", p, q);
+  }
+  const size_t need = (size_t)np * GH_PRIM_FLOATS * sizeof(float);
+  if (blob_needed_h) *blob_needed_h = need;
+  if (!dev_blob) return desc_h ? fail(GH_EINVAL, "dev_blob is NULL") : GH_OK;
+  if (blob_bytes < need) return fail(GH_ECAPACITY, "blob of %zu bytes, %zu needed", blob_bytes, need);
+  if (!desc_h) return fail(GH_EINVAL, "desc is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  gh_status st = hip_status(hipMemcpyAsync(dev_blob, spec_h->prims_h, need, hipMemcpyHostToDevice, s), "upload");
+  if (st != GH_OK) return st;
+  st = hip_status(hipStreamSynchronize(s), "upload sync");
+  if (st != GH_OK) return st;
+  gh::DevSdb d{};
+  d.magic = gh::kDescMagic;
+  d.kind = GH_SDB_PRIMS;
+  d.n_prim = np;
+  d.prims = (const float*)dev_blob;
+  memset(desc_h, 0, sizeof(*desc_h));
+  memcpy(desc_h, &d, sizeof(d));
+  return GH_OK;
+}
+
+gh_status gh_workspace_size(const gh_grid* grid_h, int64_t corner_cap, size_t* bytes_h) {
+  gh::Grid g;
+  gh_status st = read_grid(grid_h, &g);
+  if (st != GH_OK) return st;
+  if (!bytes_h) return fail(GH_EINVAL, "bytes_h is NULL");
+  if (corner_cap <= 0) corner_cap = default_cap(g.n);
+  if (corner_cap >= (int64_t)1 << 31) return fail(GH_EUNSUPPORTED, "corner_cap too large");
+  *bytes_h = gh::workspace_layout(g.n, corner_cap, nullptr, nullptr);
+  return GH_OK;
+}
+
+gh_status gh_hop(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
+                 gh_counters* ctr, void* stream) {
+  gh::DevSdb d;
+  gh::Grid g;
+  gh::Workspace w;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
+  if ((st = carve(g, ws, ws_bytes, corner_cap, &w)) != GH_OK) return st;
+  if (!ctr) return fail(GH_EINVAL, "counters are NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearAll, s), "clear")) != GH_OK) return st;
+  return hip_status(gh::launch_hop(d, g, w, ctr, s), "hop");
+}
+
+gh_status gh_dense(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
+                   float* dense, gh_counters* ctr, void* stream) {
+  gh::DevSdb d;
+  gh::Grid g;
+  gh::Workspace w;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
+  if ((st = carve(g, ws, ws_bytes, corner_cap, &w)) != GH_OK) return st;
+  if (!ctr || !dense) return fail(GH_EINVAL, "counters or dense buffer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearAll, s), "clear")) != GH_OK) return st;
+  return hip_status(gh::launch_dense(d, g, w, dense, ctr, s), "dense");
+}
+
+gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
+                float* verts, int64_t* vert_edge, float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap,
+                int64_t* cells, uint8_t* cases, int64_t cell_cap, gh_counters* ctr, void* stream) {
+  gh::DevSdb d;
+  gh::Grid g;
+  gh::Workspace w;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
+  if ((st = carve(g, ws, ws_bytes, corner_cap, &w)) != GH_OK) return st;
+  if (!ctr) return fail(GH_EINVAL, "counters are NULL");
+  if (vert_cap < 0 || tri_cap < 0 || cell_cap < 0) return fail(GH_EINVAL, "negative capacity");
+  if ((vert_cap > 0 && !verts) || (tri_cap > 0 && !tris)) return fail(GH_EINVAL, "output buffer is NULL");
+  if (tri_cap >= ((int64_t)1 << 31) || vert_cap >= ((int64_t)1 << 31))
+    return fail(GH_EUNSUPPORTED, "capacities must stay below 2^31");
+  if (!cells && !cases) cell_cap = 0;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearMc, s), "clear")) != GH_OK) return st;
+  return hip_status(gh::launch_mc(d, g, w, verts, vert_edge, vert_t, vert_cap, tris, tri_cap, cells, cases, cell_cap,
+                                  ctr, s),
+                    "mc");
+}
+
+gh_status gh_candidates(const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap, int64_t* out,
+                        int64_t cap, gh_counters* ctr, void* stream) {
+  gh::Grid g;
+  gh::Workspace w;
+  gh_status st;
+  if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
+  if ((st = carve(g, ws, ws_bytes, corner_cap, &w)) != GH_OK) return st;
+  if (!ctr || (cap > 0 && !out) || cap < 0) return fail(GH_EINVAL, "bad output or counters");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearCands, s), "clear")) != GH_OK) return st;
+  return hip_status(gh::launch_candidates(g, w, out, cap, ctr, s), "candidates");
+}
+
+gh_status gh_eval_points(const gh_sdb_desc* desc_h, const float* xyz, float* f, int64_t m, void* stream) {
+  gh::DevSdb d;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if (m < 0) return fail(GH_EINVAL, "negative point count");
+  if (m == 0) return GH_OK;
+  if (!xyz || !f) return fail(GH_EINVAL, "points or output is NULL");
+  return hip_status(gh::launch_eval_points(d, xyz, f, m, (hipStream_t)stream), "eval");
+}
+
+}  // extern "C"

@@ -1,0 +1,186 @@
+// Device-side building blocks shared by the kernels: grid and bound
+// descriptors, the analytic bound evaluator, wave/block reductions and a
+// single-pass block scan with decoupled look-back.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gh.h"
+
+namespace gh {
+
+constexpr int kBlock = 256;  // threads per block in every tiled kernel (4 waves)
+constexpr int kMaxN = 2048;
+constexpr int kMaxPrims = 64;
+
+enum : int { kPrimSphere = 0, kPrimBox = 1, kPrimTorus = 2, kPrimCapsule = 3, kPrimPlane = 4, kPrimBoxBound = 5 };
+
+struct Grid {
+  int n;        // cells per axis
+  float lo;     // origin
+  float h;      // cell size
+  float inv_h;  // float32(1/h), computed in double and rounded once
+};
+
+// Cell centroid coordinate lo + (idx + 1/2) h (eq. cells): one rounded
+// product and one rounded sum, no contraction.
+__device__ __forceinline__ float centroid(const Grid& g, int idx) {
+  return g.lo + ((float)idx + 0.5f) * g.h;
+}
+// Lattice coordinate lo + idx h.
+__device__ __forceinline__ float lattice(const Grid& g, int idx) { return g.lo + (float)idx * g.h; }
+
+// ------------------------------------------------------------ analytic bound
+// One primitive record (16 floats) at p, float32, one rounding per operation
+// in exactly this order (the oracle's twin follows the same order):
+//   d = p - c;  q_r = (M_r0 d_x + M_r1 d_y) + M_r2 d_z
+//   sphere   sqrt((qx qx + qy qy) + qz qz) - r
+//   box      u = |q| - b;  sqrt((mx mx + my my) + mz mz) + min(max(ux, max(uy, uz)), 0), m = max(u, 0)
+//   boxbound max(ux, max(uy, uz))                         (Section 4.2, eq. boxdist)
+//   torus    s = sqrt(qx qx + qz qz) - R;  sqrt(s s + qy qy) - r
+//   capsule  w = qz - min(max(qz, -a), a);  sqrt((qx qx + qy qy) + w w) - r
+//   plane    ((n_x x + n_y y) + n_z z) - d                 (Section 4.1, eq. plane)
+__device__ __forceinline__ float prim_eval(const float* __restrict__ r, float x, float y, float z) {
+  const int t = (int)r[0];
+  if (t == kPrimPlane) return ((r[4] * x + r[5] * y) + r[6] * z) - r[13];
+  const float dx = x - r[1], dy = y - r[2], dz = z - r[3];
+  const float qx = (r[4] * dx + r[5] * dy) + r[6] * dz;
+  const float qy = (r[7] * dx + r[8] * dy) + r[9] * dz;
+  const float qz = (r[10] * dx + r[11] * dy) + r[12] * dz;
+  if (t == kPrimSphere) return sqrtf((qx * qx + qy * qy) + qz * qz) - r[13];
+  if (t == kPrimTorus) {
+    const float s = sqrtf(qx * qx + qz * qz) - r[13];
+    return sqrtf(s * s + qy * qy) - r[14];
+  }
+  if (t == kPrimCapsule) {
+    const float w = qz - fminf(fmaxf(qz, -r[13]), r[13]);
+    return sqrtf((qx * qx + qy * qy) + w * w) - r[14];
+  }
+  const float ux = fabsf(qx) - r[13], uy = fabsf(qy) - r[14], uz = fabsf(qz) - r[15];
+  const float inner = fmaxf(ux, fmaxf(uy, uz));
+  if (t == kPrimBoxBound) return inner;
+  const float mx = fmaxf(ux, 0.f), my = fmaxf(uy, 0.f), mz = fmaxf(uz, 0.f);
+  return sqrtf((mx * mx + my * my) + mz * mz) + fminf(inner, 0.f);
+}
+
+// Min-union of the records in order (Section 4.3).  The record pointer and
+// count are uniform across the wave, so the parameters come in through
+// scalar loads and the type branches do not diverge.
+struct PrimsEval {
+  const float* __restrict__ prims;
+  int n_prim;
+  __device__ __forceinline__ float operator()(float x, float y, float z) const {
+    float f = prim_eval(prims, x, y, z);
+    for (int p = 1; p < n_prim; ++p) f = fminf(f, prim_eval(prims + p * GH_PRIM_FLOATS, x, y, z));
+    return f;
+  }
+};
+
+// --------------------------------------------------------- wave/block sums
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+  const int l = lane_id();
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t o = __shfl_up(v, d, 64);
+    if (l >= d) v += o;
+  }
+  return v;
+}
+
+// Adds v (per thread) over the block and atomically into *dst (one atomic per block).
+__device__ __forceinline__ void block_add_u64(uint64_t v, unsigned long long* dst) {
+  __shared__ uint64_t s_part[kBlock / 64];
+  v = wave_sum_u64(v);
+  if (lane_id() == 0) s_part[wave_id()] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += s_part[w];
+    if (t) atomicAdd(dst, (unsigned long long)t);
+  }
+}
+
+// ------------------------------------------------ single-pass block scan
+// Tiles are taken in ticket order (an atomic counter), so a tile only ever
+// waits on tiles that started before it: the scan cannot deadlock.  Each
+// tile publishes one 64-bit word per state change: status in the top two
+// bits (1 = own aggregate, 2 = inclusive prefix), value in the low 62 bits.
+constexpr uint64_t kScanAgg = 1ull << 62;
+constexpr uint64_t kScanPrefix = 2ull << 62;
+constexpr uint64_t kScanValMask = (1ull << 62) - 1;
+
+__device__ __forceinline__ int acquire_tile(unsigned int* ticket) {
+  __shared__ int s_tile;
+  if (threadIdx.x == 0) s_tile = (int)atomicAdd(ticket, 1u);
+  __syncthreads();
+  return s_tile;
+}
+
+struct ScanOut {
+  uint64_t excl;   // exclusive prefix of this thread over the whole grid
+  uint64_t total;  // inclusive prefix at the end of this tile
+};
+
+// The wait for a predecessor is bounded: should it ever exceed kSpinLimit
+// polls (only possible through a library bug), *err gets GH_FLAG_INTERNAL and
+// the tile carries on with a partial prefix; every write stays inside its
+// capacity check, so the result is flagged rather than the device hung.
+constexpr int kSpinLimit = 1 << 24;
+
+__device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* flags, int tile, unsigned int* err) {
+  __shared__ uint64_t s_wave[kBlock / 64];
+  __shared__ uint64_t s_prev;
+  const uint64_t incl = wave_incl_scan_u64(v);
+  if (lane_id() == 63) s_wave[wave_id()] = incl;
+  __syncthreads();
+  uint64_t wave_off = 0, agg = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    const uint64_t s = s_wave[w];
+    if (w < wave_id()) wave_off += s;
+    agg += s;
+  }
+  if (threadIdx.x == 0) {
+    uint64_t prev = 0;
+    if (tile == 0) {
+      __hip_atomic_store(&flags[0], kScanPrefix | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&flags[tile], kScanAgg | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int j = tile - 1;
+      int spins = 0;
+      while (true) {
+        const uint64_t f = __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t st = f & ~kScanValMask;
+        if (st == 0) {
+          if (++spins > kSpinLimit) {
+            atomicOr(err, GH_FLAG_INTERNAL);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        prev += f & kScanValMask;
+        if (st == kScanPrefix || j == 0) break;  // tile 0 always publishes a prefix
+        --j;
+      }
+      __hip_atomic_store(&flags[tile], kScanPrefix | ((prev + agg) & kScanValMask), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_prev = prev;
+  }
+  __syncthreads();
+  ScanOut o;
+  o.excl = s_prev + wave_off + incl - v;
+  o.total = s_prev + agg;
+  return o;
+}
+
+}  // namespace gh

@@ -1,0 +1,596 @@
+// Grid hopping and marching-cubes kernels for gfx950, with host launchers.
+//
+// Pipeline of one polygonization (all on one stream):
+//   k_clear      reset counters and look-back words
+//   k_hop        one lane per ray column: hop rule, candidate bitmap
+//   k_corners    per lattice column: distinct corners of candidate cells,
+//                single-pass scan -> CSR offsets, corner list
+//   k_eval       bound at every corner, one lane per corner
+//   k_verts      per lattice column: crossing edges owned by each corner,
+//                scan -> one welded vertex per crossing lattice edge
+//   k_tris       per cell column: case byte, triangles from the table,
+//                scan -> triangle and cell emit
+// Enumeration replaces k_hop by k_dense_eval + k_dense_classify.
+
+#include <float.h>
+
+#include "gh_device.h"
+#include "gh_launch.h"
+#include "gh_layout.h"
+#include "mc_table.h"
+
+namespace gh {
+
+__constant__ McTable g_mc = kMcTable;
+
+// ------------------------------------------------------------------ clear
+// Zeroes scan[begin, end), the given tickets and, per mode, the counters:
+// all of them before a hop, the marching-cubes ones before gh_mc.
+__global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, unsigned int* __restrict__ ticket,
+                        unsigned ticket_mask, gh_counters* __restrict__ ctr, int mode) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = begin + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < end; i += stride) scan[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 8 && ((ticket_mask >> threadIdx.x) & 1)) ticket[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (mode == kClearAll) {
+      ctr->n_hop_evals = 0;
+      ctr->n_cand = 0;
+      ctr->n_reeval = 0;
+      ctr->flags = 0;
+      ctr->reserved = 0;
+    }
+    if (mode == kClearAll || mode == kClearMc) {
+      ctr->n_corner = 0;
+      ctr->n_cells = 0;
+      ctr->n_vert = 0;
+      ctr->n_tri = 0;
+      ctr->flags &= ~GH_FLAG_CAPACITY;
+    }
+  }
+}
+
+// --------------------------------------------------------------------- hop
+// Ray columns are tiled 16 x 16 per block; each wave takes an 8 x 8 patch so
+// that its lanes trace neighbouring rays with similar step counts.
+__device__ __forceinline__ void hop_tile_column(int n, int& i, int& j) {
+  const int ntx = (n + 15) >> 4;
+  const int ti = blockIdx.x / ntx, tj = blockIdx.x - ti * ntx;
+  const int w = wave_id(), l = lane_id();
+  i = ti * 16 + (w >> 1) * 8 + (l >> 3);
+  j = tj * 16 + (w & 1) * 8 + (l & 7);
+}
+
+// Hop rule (Section 3, eq. iter, cell-quantised): at the centroid of cell k,
+// s = floor(|f| * inv_h); s >= 1 skips s cells, s == 0 marks cell k as a
+// candidate and moves to k + 1; the ray ends when k >= n.
+template <class Eval>
+__global__ __launch_bounds__(kBlock) void k_hop(Eval ev, Grid g, uint64_t* __restrict__ colmask,
+                                                uint32_t* __restrict__ colbits, gh_counters* __restrict__ ctr) {
+  const int n = g.n;
+  int i, j;
+  hop_tile_column(n, i, j);
+  uint64_t evals = 0, cands = 0;
+  bool bad = false;
+  if (i < n && j < n) {
+    const size_t ncol = (size_t)n * n, col = (size_t)i * n + j;
+    const float x = centroid(g, i), y = centroid(g, j);
+    const float nf = (float)n;
+    int k = 0, wi = 0;
+    uint32_t word = 0;
+    uint64_t mask = 0;
+    while (k < n) {
+      const float f = ev(x, y, centroid(g, k));
+      ++evals;
+      const float d = fabsf(f);
+      if (!(d <= FLT_MAX)) {
+        bad = true;
+        break;
+      }
+      const float s = floorf(d * g.inv_h);
+      if (s == 0.f) {
+        const int kw = k >> 5;
+        if (kw != wi) {
+          if (word) {
+            colbits[(size_t)wi * ncol + col] = word;
+            mask |= 1ull << wi;
+          }
+          word = 0;
+          wi = kw;
+        }
+        word |= 1u << (k & 31);
+        ++cands;
+        ++k;
+      } else {
+        k += (int)fminf(s, nf);
+      }
+    }
+    if (word) {
+      colbits[(size_t)wi * ncol + col] = word;
+      mask |= 1ull << wi;
+    }
+    colmask[col] = mask;
+  }
+  if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
+  block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
+}
+
+// ------------------------------------------------------------ enumeration
+// Bound at every lattice point, layout [c][a][b] (b fastest).
+template <class Eval>
+__global__ __launch_bounds__(kBlock) void k_dense_eval(Eval ev, Grid g, float* __restrict__ dense) {
+  const int n1 = g.n + 1;
+  const size_t total = (size_t)n1 * n1 * n1;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const int b = (int)(idx % n1);
+    const size_t r = idx / n1;
+    const int a = (int)(r % n1), c = (int)(r / n1);
+    dense[idx] = ev(lattice(g, a), lattice(g, b), lattice(g, c));
+  }
+}
+
+// Every cell whose eight corners do not share one side becomes a candidate.
+__global__ __launch_bounds__(kBlock) void k_dense_classify(Grid g, const float* __restrict__ dense,
+                                                           uint64_t* __restrict__ colmask,
+                                                           uint32_t* __restrict__ colbits,
+                                                           gh_counters* __restrict__ ctr) {
+  const int n = g.n, n1 = n + 1;
+  const size_t ncol = (size_t)n * n;
+  const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t cands = 0;
+  bool bad = false;
+  if (col < ncol) {
+    const int i = (int)(col / n), j = (int)(col % n);
+    const size_t plane = (size_t)n1 * n1;
+    const size_t o00 = (size_t)i * n1 + j, o01 = o00 + 1, o10 = o00 + n1, o11 = o10 + 1;
+    auto side = [&](size_t o) {
+      const float f = dense[o];
+      bad |= !(fabsf(f) <= FLT_MAX);
+      return (unsigned)(f < 0.f);
+    };
+    unsigned lowc = side(o00) + side(o01) + side(o10) + side(o11);
+    uint64_t mask = 0;
+    uint32_t word = 0;
+    for (int k = 0; k < n; ++k) {
+      const size_t base = (size_t)(k + 1) * plane;
+      const unsigned upc = side(base + o00) + side(base + o01) + side(base + o10) + side(base + o11);
+      const unsigned inside = lowc + upc;
+      if (inside != 0 && inside != 8) {
+        word |= 1u << (k & 31);
+        ++cands;
+      }
+      if ((k & 31) == 31 || k == n - 1) {
+        if (word) {
+          colbits[(size_t)(k >> 5) * ncol + col] = word;
+          mask |= 1ull << (k >> 5);
+        }
+        word = 0;
+      }
+      lowc = upc;
+    }
+    colmask[col] = mask;
+  }
+  if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr->n_hop_evals = (int64_t)n1 * n1 * n1;
+}
+
+// -------------------------------------------------------- candidate export
+__global__ __launch_bounds__(kBlock) void k_candidates(Grid g, Workspace ws, int64_t* __restrict__ out, int64_t cap,
+                                                      gh_counters* __restrict__ ctr) {
+  const int n = g.n;
+  const size_t ncol = (size_t)n * n;
+  const int tile = acquire_tile(&ws.ticket[kTicketCands]);
+  const size_t col = (size_t)tile * kBlock + threadIdx.x;
+  uint64_t m = 0;
+  uint64_t cnt = 0;
+  if (col < ncol) {
+    m = ws.colmask[col];
+    for (uint64_t r = m; r; r &= r - 1) cnt += __popc(ws.colbits[(size_t)__builtin_ctzll(r) * ncol + col]);
+  }
+  const ScanOut so = block_scan_lookback(cnt, scan_cands(ws), tile, &ctr->flags);
+  if (col < ncol && so.excl + cnt <= (uint64_t)cap) {
+    int64_t o = (int64_t)so.excl;
+    for (uint64_t r = m; r; r &= r - 1) {
+      const int w = __builtin_ctzll(r);
+      for (uint32_t b = ws.colbits[(size_t)w * ncol + col]; b; b &= b - 1)
+        out[o++] = (int64_t)col * n + 32 * w + __builtin_ctz(b);
+    }
+  }
+  if (threadIdx.x == 0 && tile == (int)ws.tiles_col - 1 && so.total > (uint64_t)cap)
+    atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+}
+
+// ------------------------------------------------------------------ corners
+// Candidate words of the (up to four) cell columns around lattice column (a, b).
+struct LatAdj {
+  size_t col[4];
+  uint64_t mask[4];
+  int cnt;
+  uint64_t uni;
+};
+
+__device__ __forceinline__ LatAdj lat_adjacent(int n, int a, int b, const uint64_t* __restrict__ colmask) {
+  LatAdj A;
+  A.cnt = 0;
+  A.uni = 0;
+#pragma unroll
+  for (int di = -1; di <= 0; ++di)
+#pragma unroll
+    for (int dj = -1; dj <= 0; ++dj) {
+      const int i = a + di, j = b + dj;
+      if (i >= 0 && i < n && j >= 0 && j < n) {
+        const size_t c = (size_t)i * n + j;
+        const uint64_t m = colmask[c];
+        if (m) {
+          A.col[A.cnt] = c;
+          A.mask[A.cnt] = m;
+          A.uni |= m;
+          ++A.cnt;
+        }
+      }
+    }
+  return A;
+}
+
+__device__ __forceinline__ uint32_t adj_cell_word(const LatAdj& A, const uint32_t* __restrict__ colbits,
+                                                  size_t ncol, int w) {
+  uint32_t v = 0;
+  if (w < 0 || w >= 64) return 0;
+  for (int q = 0; q < A.cnt; ++q)
+    if ((A.mask[q] >> w) & 1) v |= colbits[(size_t)w * ncol + A.col[q]];
+  return v;
+}
+
+// Lattice points k of column (a, b) that are corners of a candidate cell:
+// cell k of an adjacent column has corners k and k + 1.
+__device__ __forceinline__ uint32_t corner_word(const LatAdj& A, const uint32_t* __restrict__ colbits, size_t ncol,
+                                                int w) {
+  const uint32_t cur = adj_cell_word(A, colbits, ncol, w);
+  const uint32_t prev = adj_cell_word(A, colbits, ncol, w - 1);
+  return cur | (cur << 1) | (prev >> 31);
+}
+
+template <class F>
+__device__ __forceinline__ void for_corner_words(const LatAdj& A, F&& fn) {
+  const uint64_t cw = A.uni | (A.uni << 1);
+  for (uint64_t r = cw; r; r &= r - 1) fn(__builtin_ctzll(r));
+  if ((A.uni >> 63) & 1) fn(64);
+}
+
+__global__ __launch_bounds__(kBlock) void k_corners(Grid g, Workspace ws, gh_counters* __restrict__ ctr) {
+  const int n = g.n, n1 = n + 1;
+  const size_t ncol = (size_t)n * n, nl = (size_t)n1 * n1;
+  const int tile = acquire_tile(&ws.ticket[kTicketCorners]);
+  const size_t L = (size_t)tile * kBlock + threadIdx.x;
+  LatAdj A;
+  A.cnt = 0;
+  A.uni = 0;
+  uint64_t cnt = 0;
+  if (L < nl) {
+    A = lat_adjacent(n, (int)(L / n1), (int)(L % n1), ws.colmask);
+    for_corner_words(A, [&](int w) { cnt += __popc(corner_word(A, ws.colbits, ncol, w)); });
+  }
+  const ScanOut so = block_scan_lookback(cnt, scan_corners(ws), tile, &ctr->flags);
+  if (L < nl) {
+    ws.lstart[L] = (int64_t)so.excl;
+    if (so.excl + cnt <= (uint64_t)ws.cap) {
+      int64_t o = (int64_t)so.excl;
+      for_corner_words(A, [&](int w) {
+        for (uint32_t b = corner_word(A, ws.colbits, ncol, w); b; b &= b - 1) {
+          ws.ck[o] = 32 * w + __builtin_ctz(b);
+          ws.cl[o] = (int32_t)L;
+          ++o;
+        }
+      });
+    }
+  }
+  if (threadIdx.x == 0 && tile == (int)ws.tiles_lat - 1) {
+    ws.lstart[nl] = (int64_t)so.total;
+    ctr->n_corner = (int64_t)so.total;
+    if (so.total > (uint64_t)ws.cap) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+  }
+}
+
+// Bound value at each corner point, one lane per corner.
+template <class Eval>
+__global__ __launch_bounds__(kBlock) void k_eval_corners(Eval ev, Grid g, Workspace ws,
+                                                         const gh_counters* __restrict__ ctr) {
+  const int64_t m = ctr->n_corner;
+  if (m > ws.cap) return;
+  const int n1 = g.n + 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < m; c += stride) {
+    const int L = ws.cl[c];
+    const int a = L / n1, b = L - a * n1;
+    ws.cf[c] = ev(lattice(g, a), lattice(g, b), lattice(g, ws.ck[c]));
+  }
+}
+
+// ------------------------------------------------------------------ vertices
+// Crossing edges owned by each corner (a, b, k): the x edge to (a+1, b, k),
+// the y edge to (a, b+1, k) and the z edge to (a, b, k+1), when both ends
+// are corners and their signs differ.  Merge-walks the sorted corner lists
+// of columns (a+1, b) and (a, b+1).
+struct VertWalk {
+  int64_t s0, e0, sx, ex, sy, ey;
+};
+
+__device__ __forceinline__ unsigned cross_mask(const Workspace& ws, int64_t i, const VertWalk& V, int64_t& px,
+                                               int64_t& py) {
+  const int k = ws.ck[i];
+  const bool neg = ws.cf[i] < 0.f;
+  unsigned m = 0;
+  while (px < V.ex && ws.ck[px] < k) ++px;
+  if (px < V.ex && ws.ck[px] == k && ((ws.cf[px] < 0.f) != neg)) m |= 1u;
+  while (py < V.ey && ws.ck[py] < k) ++py;
+  if (py < V.ey && ws.ck[py] == k && ((ws.cf[py] < 0.f) != neg)) m |= 2u;
+  if (i + 1 < V.e0 && ws.ck[i + 1] == k + 1 && ((ws.cf[i + 1] < 0.f) != neg)) m |= 4u;
+  return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* __restrict__ verts,
+                                                  int64_t* __restrict__ vert_edge, float* __restrict__ vert_t,
+                                                  int64_t vert_cap, gh_counters* __restrict__ ctr) {
+  const int n = g.n, n1 = n + 1;
+  const size_t nl = (size_t)n1 * n1;
+  const int tile = acquire_tile(&ws.ticket[kTicketVerts]);
+  if (ctr->n_corner > ws.cap) return;  // uniform over the grid: no tile waits on this one
+  const size_t L = (size_t)tile * kBlock + threadIdx.x;
+  VertWalk V{0, 0, 0, 0, 0, 0};
+  int a = 0, b = 0;
+  uint64_t cnt = 0;
+  if (L < nl) {
+    a = (int)(L / n1);
+    b = (int)(L % n1);
+    V.s0 = ws.lstart[L];
+    V.e0 = ws.lstart[L + 1];
+    if (a < n) {
+      V.sx = ws.lstart[L + n1];
+      V.ex = ws.lstart[L + n1 + 1];
+    }
+    if (b < n) {
+      V.sy = ws.lstart[L + 1];
+      V.ey = ws.lstart[L + 2];
+    }
+    int64_t px = V.sx, py = V.sy;
+    for (int64_t i = V.s0; i < V.e0; ++i) cnt += __popc(cross_mask(ws, i, V, px, py));
+  }
+  const ScanOut so = block_scan_lookback(cnt, scan_verts(ws), tile, &ctr->flags);
+  if (L < nl && V.e0 > V.s0) {
+    const bool room = so.excl + cnt <= (uint64_t)vert_cap;
+    int64_t v = (int64_t)so.excl;
+    int64_t px = V.sx, py = V.sy;
+    const float xa = lattice(g, a), ya = lattice(g, b);
+    for (int64_t i = V.s0; i < V.e0; ++i) {
+      const unsigned m = cross_mask(ws, i, V, px, py);
+      ws.cinfo[i] = (v << 3) | (int64_t)m;
+      if (!m || !room) {
+        v += __popc(m);
+        continue;
+      }
+      const int k = ws.ck[i];
+      const float fa = ws.cf[i], za = lattice(g, k);
+      const int64_t pid = ((int64_t)L * n1 + k) * 3;
+      for (int axis = 0; axis < 3; ++axis) {
+        if (!((m >> axis) & 1)) continue;
+        const float fb = axis == 0 ? ws.cf[px] : (axis == 1 ? ws.cf[py] : ws.cf[i + 1]);
+        const float t = fa / (fa - fb);
+        float px3 = xa, py3 = ya, pz3 = za;
+        if (axis == 0) px3 = xa + t * g.h;
+        if (axis == 1) py3 = ya + t * g.h;
+        if (axis == 2) pz3 = za + t * g.h;
+        verts[3 * v + 0] = px3;
+        verts[3 * v + 1] = py3;
+        verts[3 * v + 2] = pz3;
+        if (vert_edge) vert_edge[v] = pid + axis;
+        if (vert_t) vert_t[v] = t;
+        ++v;
+      }
+    }
+  }
+  if (threadIdx.x == 0 && tile == (int)ws.tiles_lat - 1) {
+    ctr->n_vert = (int64_t)so.total;
+    if (so.total > (uint64_t)vert_cap) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+  }
+}
+
+// ----------------------------------------------------------------- triangles
+// Per candidate cell: the eight corner indices from four merge pointers into
+// the corner lists of lattice columns (i+dx, j+dy), the case byte, and the
+// table's triangles; each triangle vertex is the welded vertex of the cell
+// edge, found at the edge's lower corner.
+struct CellWalk {
+  int64_t p[4];  // corner index of k in lattice column (i+dx, j+dy), slot dx + 2 dy
+  int64_t e[4];  // end of that column's corner list
+};
+
+// Case byte of cell k; false when a corner is missing from the lists, which
+// consistent workspace contents never produce (the caller then flags it).
+__device__ __forceinline__ bool cell_case(const Workspace& ws, int k, CellWalk& C, unsigned& cs) {
+  cs = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    while (C.p[q] < C.e[q] && ws.ck[C.p[q]] < k) ++C.p[q];
+    if (C.p[q] + 1 >= C.e[q] || ws.ck[C.p[q]] != k || ws.ck[C.p[q] + 1] != k + 1) return false;
+    cs |= (unsigned)(ws.cf[C.p[q]] < 0.f) << q;
+    cs |= (unsigned)(ws.cf[C.p[q] + 1] < 0.f) << (q + 4);
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* __restrict__ tris, int64_t tri_cap,
+                                                 int64_t* __restrict__ cells, uint8_t* __restrict__ cases,
+                                                 int64_t cell_cap, int64_t vert_cap,
+                                                 gh_counters* __restrict__ ctr) {
+  __shared__ McCase s_mc[256];
+  s_mc[threadIdx.x] = g_mc.c[threadIdx.x];
+  __syncthreads();
+  const int n = g.n, n1 = n + 1;
+  const size_t ncol = (size_t)n * n;
+  const int tile = acquire_tile(&ws.ticket[kTicketTris]);
+  if (ctr->n_corner > ws.cap) return;
+  const size_t col = (size_t)tile * kBlock + threadIdx.x;
+  uint64_t m = 0;
+  int i = 0, j = 0;
+  CellWalk C0{{0, 0, 0, 0}, {0, 0, 0, 0}};
+  bool broken = false;
+  uint64_t ntri = 0, ncell = 0;
+  if (col < ncol) {
+    i = (int)(col / n);
+    j = (int)(col % n);
+    m = ws.colmask[col];
+    if (m) {
+      const size_t L = (size_t)i * n1 + j;
+      C0.p[0] = ws.lstart[L];
+      C0.p[1] = ws.lstart[L + n1];
+      C0.p[2] = ws.lstart[L + 1];
+      C0.p[3] = ws.lstart[L + n1 + 1];
+      C0.e[0] = ws.lstart[L + 1];
+      C0.e[1] = ws.lstart[L + n1 + 1];
+      C0.e[2] = ws.lstart[L + 2];
+      C0.e[3] = ws.lstart[L + n1 + 2];
+      CellWalk C = C0;
+      for (uint64_t r = m; r; r &= r - 1) {
+        const int w = __builtin_ctzll(r);
+        for (uint32_t bits = ws.colbits[(size_t)w * ncol + col]; bits; bits &= bits - 1) {
+          const int k = 32 * w + __builtin_ctz(bits);
+          unsigned cs;
+          if (!cell_case(ws, k, C, cs)) {
+            broken = true;
+            continue;
+          }
+          const unsigned nt = s_mc[cs].ntri;
+          ntri += nt;
+          ncell += nt ? 1 : 0;
+        }
+      }
+    }
+  }
+  // (cells << 31) | triangles: both stay below 2^31 for any mesh the outputs can index
+  const ScanOut so = block_scan_lookback((ncell << 31) | ntri, scan_tris(ws), tile, &ctr->flags);
+  const bool verts_ok = ctr->n_vert <= vert_cap;
+  if (col < ncol && m && verts_ok) {
+    int64_t t = (int64_t)(so.excl & 0x7fffffffull);
+    int64_t c = (int64_t)(so.excl >> 31);
+    const bool room_t = t + (int64_t)ntri <= tri_cap;
+    const bool room_c = c + (int64_t)ncell <= cell_cap;
+    CellWalk C = C0;
+    for (uint64_t r = m; r; r &= r - 1) {
+      const int w = __builtin_ctzll(r);
+      for (uint32_t bits = ws.colbits[(size_t)w * ncol + col]; bits; bits &= bits - 1) {
+        const int k = 32 * w + __builtin_ctz(bits);
+        unsigned cs;
+        if (!cell_case(ws, k, C, cs)) continue;
+        const McCase mcc = s_mc[cs];
+        if (!mcc.ntri) continue;
+        if (room_c) {
+          if (cells) cells[c] = (int64_t)col * n + k;
+          if (cases) cases[c] = (uint8_t)cs;
+        }
+        ++c;
+        if (!room_t) continue;
+        for (unsigned q = 0; q < mcc.ntri; ++q) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            const int e = (int)((mcc.tri >> (12 * q + 4 * v)) & 15);
+            const int lc = mc_edge_lower(e), axis = e >> 2;
+            const int64_t gi = C.p[(lc & 1) + 2 * ((lc >> 1) & 1)] + (lc >> 2);
+            const int64_t info = ws.cinfo[gi];
+            tris[3 * t + v] = (int32_t)((info >> 3) + __popc((unsigned)(info & 7) & ((1u << axis) - 1u)));
+          }
+          ++t;
+        }
+      }
+    }
+  }
+  if (broken) atomicOr(&ctr->flags, GH_FLAG_INTERNAL);
+  if (threadIdx.x == 0 && tile == (int)ws.tiles_col - 1) {
+    const int64_t tt = (int64_t)(so.total & 0x7fffffffull), tc = (int64_t)(so.total >> 31);
+    ctr->n_tri = tt;
+    ctr->n_cells = tc;
+    if (tt > tri_cap || (cells && tc > cell_cap) || (cases && tc > cell_cap)) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+  }
+}
+
+// Bound at arbitrary points.
+template <class Eval>
+__global__ __launch_bounds__(kBlock) void k_eval_points(Eval ev, const float* __restrict__ xyz, float* __restrict__ f,
+                                                        int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += stride)
+    f[p] = ev(xyz[3 * p], xyz[3 * p + 1], xyz[3 * p + 2]);
+}
+
+// ================================================================ launchers
+static int persistent_blocks(int64_t work) {
+  const int64_t want = (work + kBlock - 1) / kBlock;
+  return (int)(want < 1 ? 1 : (want > 2048 ? 2048 : want));
+}
+
+hipError_t launch_clear(const Workspace& ws, gh_counters* ctr, ClearMode mode, hipStream_t s) {
+  size_t begin = 0, end = scan_words(ws);
+  unsigned tmask = 0xffu;
+  if (mode == kClearMc) {
+    end = (size_t)(scan_cands(ws) - ws.scan);
+    tmask = (1u << kTicketCorners) | (1u << kTicketVerts) | (1u << kTicketTris);
+  } else if (mode == kClearCands) {
+    begin = (size_t)(scan_cands(ws) - ws.scan);
+    tmask = 1u << kTicketCands;
+  }
+  hipLaunchKernelGGL(k_clear, dim3(persistent_blocks((int64_t)(end - begin))), dim3(kBlock), 0, s, ws.scan, begin,
+                     end, ws.ticket, tmask, ctr, (int)mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, hipStream_t s) {
+  const int nt = (g.n + 15) / 16;
+  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_hop<PrimsEval>, dim3(nt * nt), dim3(kBlock), 0, s, PrimsEval{d.prims, d.n_prim}, g, ws.colmask,
+                     ws.colbits, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, float* dense, gh_counters* ctr,
+                        hipStream_t s) {
+  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
+  const int64_t n1 = g.n + 1;
+  const int64_t total = n1 * n1 * n1;
+  const int64_t blocks = (total + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_dense_eval<PrimsEval>, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(kBlock), 0, s,
+                     PrimsEval{d.prims, d.n_prim}, g, dense);
+  const int64_t ncol = (int64_t)g.n * g.n;
+  hipLaunchKernelGGL(k_dense_classify, dim3((unsigned)((ncol + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g, dense,
+                     ws.colmask, ws.colbits, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_candidates(const Grid& g, const Workspace& ws, int64_t* out, int64_t cap, gh_counters* ctr,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_candidates, dim3((unsigned)ws.tiles_col), dim3(kBlock), 0, s, g, ws, out, cap, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float* verts, int64_t* vert_edge,
+                     float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap, int64_t* cells,
+                     uint8_t* cases, int64_t cell_cap, gh_counters* ctr, hipStream_t s) {
+  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_corners, dim3((unsigned)ws.tiles_lat), dim3(kBlock), 0, s, g, ws, ctr);
+  hipLaunchKernelGGL(k_eval_corners<PrimsEval>, dim3(persistent_blocks(ws.cap)), dim3(kBlock), 0, s,
+                     PrimsEval{d.prims, d.n_prim}, g, ws, ctr);
+  hipLaunchKernelGGL(k_verts, dim3((unsigned)ws.tiles_lat), dim3(kBlock), 0, s, g, ws, verts, vert_edge, vert_t,
+                     vert_cap, ctr);
+  hipLaunchKernelGGL(k_tris, dim3((unsigned)ws.tiles_col), dim3(kBlock), 0, s, g, ws, tris, tri_cap, cells, cases,
+                     cell_cap, vert_cap, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_points(const DevSdb& d, const float* xyz, float* f, int64_t m, hipStream_t s) {
+  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_eval_points<PrimsEval>, dim3(persistent_blocks(m)), dim3(kBlock), 0, s,
+                     PrimsEval{d.prims, d.n_prim}, xyz, f, m);
+  return hipGetLastError();
+}
+
+}  // namespace gh

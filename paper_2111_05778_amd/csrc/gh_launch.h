@@ -1,0 +1,35 @@
+// Host-side launchers of the kernels, and the device view of a bound.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gh.h"
+#include "gh_device.h"
+#include "gh_layout.h"
+
+namespace gh {
+
+// What the kernels need to evaluate a bound; lives inside gh_sdb_desc.
+struct DevSdb {
+  uint32_t magic;
+  int32_t kind;
+  int32_t n_prim;
+  int32_t pad;
+  const float* prims;  // device, n_prim * GH_PRIM_FLOATS
+};
+constexpr uint32_t kDescMagic = 0x67687364u;  // "ghsd"
+
+enum ClearMode { kClearAll = 0, kClearMc = 1, kClearCands = 2 };
+
+hipError_t launch_clear(const Workspace& ws, gh_counters* ctr, ClearMode mode, hipStream_t s);
+hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, hipStream_t s);
+hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, float* dense, gh_counters* ctr,
+                        hipStream_t s);
+hipError_t launch_candidates(const Grid& g, const Workspace& ws, int64_t* out, int64_t cap, gh_counters* ctr,
+                             hipStream_t s);
+hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float* verts, int64_t* vert_edge,
+                     float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap, int64_t* cells,
+                     uint8_t* cases, int64_t cell_cap, gh_counters* ctr, hipStream_t s);
+hipError_t launch_eval_points(const DevSdb& d, const float* xyz, float* f, int64_t m, hipStream_t s);
+
+}  // namespace gh

@@ -1,0 +1,134 @@
+"""ctypes binding of libgh.so: the C ABI of include/gh.h, name for name.
+
+Only argument marshalling happens here.  Device buffers are torch tensors
+(passed by data_ptr) and streams are torch streams; every computation runs
+in the library's HIP kernels.  Importing fails loudly when the library has
+not been built: there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgh.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2111_05778_amd.build`")
+lib = ctypes.CDLL(_LIB_PATH)
+
+GH_OK, GH_EINVAL, GH_ECAPACITY, GH_EHIP, GH_EUNSUPPORTED, GH_ENONFINITE = 0, -1, -2, -3, -4, -5
+GH_FLAG_CAPACITY, GH_FLAG_NONFINITE, GH_FLAG_INTERNAL = 1, 2, 4
+GH_SDB_PRIMS, GH_SDB_MLP = 1, 2
+GH_PREC_FP32, GH_PREC_BF16 = 0, 1
+GH_PRIM_FLOATS = 16
+
+EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_mc", "gh_dense", "gh_candidates",
+           "gh_eval_points", "gh_last_error"]
+
+
+class gh_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("lo", ctypes.c_float), ("h", ctypes.c_float)]
+
+
+class gh_counters(ctypes.Structure):
+    _fields_ = [("n_hop_evals", ctypes.c_int64), ("n_cand", ctypes.c_int64), ("n_corner", ctypes.c_int64),
+                ("n_cells", ctypes.c_int64), ("n_vert", ctypes.c_int64), ("n_tri", ctypes.c_int64),
+                ("n_reeval", ctypes.c_int64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+COUNTER_FIELDS = [f for f, _ in gh_counters._fields_ if f != "reserved"]
+
+
+class gh_sdb_spec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_prim", ctypes.c_int32), ("prims_h", ctypes.POINTER(ctypes.c_float)),
+                ("n_freq", ctypes.c_int32), ("width", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("omegas_h", ctypes.POINTER(ctypes.c_float)),
+                ("weights_h", ctypes.POINTER(ctypes.POINTER(ctypes.c_float))),
+                ("biases_h", ctypes.POINTER(ctypes.POINTER(ctypes.c_float))),
+                ("a_s", ctypes.c_float), ("r0", ctypes.c_float), ("a_n", ctypes.c_float), ("b", ctypes.c_float),
+                ("bf16_margin", ctypes.c_float)]
+
+
+class gh_sdb_desc(ctypes.Structure):
+    _fields_ = [("opaque", ctypes.c_uint64 * 24)]
+
+
+_vp, _i64, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+_P = ctypes.POINTER
+
+lib.sdb_describe.argtypes = [_P(gh_sdb_spec), _vp, _sz, _P(_sz), _P(gh_sdb_desc), _vp]
+lib.gh_workspace_size.argtypes = [_P(gh_grid), _i64, _P(_sz)]
+lib.gh_hop.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp]
+lib.gh_mc.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64,
+                      _vp, _vp]
+lib.gh_dense.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp]
+lib.gh_candidates.argtypes = [_P(gh_grid), _vp, _sz, _i64, _vp, _i64, _vp, _vp]
+lib.gh_eval_points.argtypes = [_P(gh_sdb_desc), _vp, _vp, _i64, _vp]
+lib.gh_last_error.restype = ctypes.c_char_p
+for _name in EXPORTS[:-1]:
+    getattr(lib, _name).restype = ctypes.c_int
+
+
+class GhError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib.gh_last_error().decode(errors="replace")
+        super().__init__(f"{where} returned {status}: {msg}")
+
+
+def check(status, where):
+    if status != GH_OK:
+        raise GhError(status, where)
+
+
+def ptr(t):
+    """Device pointer of a tensor, or NULL for None."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_grid(n, lo, h):
+    return gh_grid(int(n), float(lo), float(h))
+
+
+# ------------------------------------------------------------ thin wrappers
+def sdb_describe(spec, dev_blob, blob_bytes, desc, stream=None):
+    need = _sz(0)
+    st = lib.sdb_describe(ctypes.byref(spec), ptr(dev_blob), blob_bytes, ctypes.byref(need),
+                          ctypes.byref(desc) if desc is not None else None, stream_handle(stream))
+    return st, need.value
+
+
+def gh_workspace_size(grid, corner_cap=0):
+    out = _sz(0)
+    check(lib.gh_workspace_size(ctypes.byref(grid), int(corner_cap), ctypes.byref(out)), "gh_workspace_size")
+    return out.value
+
+
+def gh_hop(desc, grid, ws, corner_cap, ctr, stream=None):
+    return lib.gh_hop(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
+                      int(corner_cap), ptr(ctr), stream_handle(stream))
+
+
+def gh_dense(desc, grid, ws, corner_cap, dense, ctr, stream=None):
+    return lib.gh_dense(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
+                        int(corner_cap), ptr(dense), ptr(ctr), stream_handle(stream))
+
+
+def gh_mc(desc, grid, ws, corner_cap, verts, vert_edge, vert_t, vert_cap, tris, tri_cap, cells, cases, cell_cap,
+          ctr, stream=None):
+    return lib.gh_mc(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
+                     int(corner_cap), ptr(verts), ptr(vert_edge), ptr(vert_t), int(vert_cap), ptr(tris),
+                     int(tri_cap), ptr(cells), ptr(cases), int(cell_cap), ptr(ctr), stream_handle(stream))
+
+
+def gh_candidates(grid, ws, corner_cap, out, cap, ctr, stream=None):
+    return lib.gh_candidates(ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(), int(corner_cap),
+                             ptr(out), int(cap), ptr(ctr), stream_handle(stream))
+
+
+def gh_eval_points(desc, xyz, f, m, stream=None):
+    return lib.gh_eval_points(ctypes.byref(desc), ptr(xyz), ptr(f), int(m), stream_handle(stream))

@@ -1,0 +1,142 @@
+"""Device buffers and call sequences around the C ABI.
+
+`Bound` uploads a distance bound once (sdb_describe); `Polygonizer` owns the
+workspace, counters and outputs for one grid and enqueues gh_hop (or
+gh_dense) followed by gh_mc on a torch stream.  `run()` waits, reads the
+counters, and re-runs with larger buffers when a capacity was too small.
+Every step of the method runs in the library's kernels.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import native as N
+
+
+class Bound:
+    """A bound packed into a device blob; keep it alive while it is used."""
+
+    def __init__(self, spec, keep, device):
+        self.spec = spec
+        self._keep = keep
+        st, need = N.sdb_describe(spec, None, 0, None)
+        N.check(st, "sdb_describe(size)")
+        self.blob = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+        self.desc = N.gh_sdb_desc()
+        st, _ = N.sdb_describe(spec, self.blob, need, self.desc)
+        N.check(st, "sdb_describe")
+
+    @staticmethod
+    def prims(records, device="cuda"):
+        """Min-union of primitive records (n x 16 float32, see include/gh.h)."""
+        rec = np.ascontiguousarray(np.asarray(records, dtype=np.float32).reshape(-1, N.GH_PRIM_FLOATS))
+        spec = N.gh_sdb_spec()
+        spec.kind = N.GH_SDB_PRIMS
+        spec.n_prim = rec.shape[0]
+        spec.prims_h = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        return Bound(spec, [rec], device)
+
+    def eval(self, xyz):
+        """Bound values at points (m x 3 float32 device tensor)."""
+        xyz = xyz.contiguous()
+        f = torch.empty(xyz.shape[0], dtype=torch.float32, device=xyz.device)
+        N.check(N.gh_eval_points(self.desc, xyz, f, xyz.shape[0]), "gh_eval_points")
+        return f
+
+
+def counters_dict(ctr):
+    v = ctr.cpu().numpy()
+    out = {name: int(v[q]) for q, name in enumerate(N.COUNTER_FIELDS[:-1])}
+    out["flags"] = int(v[7]) & 0xFFFFFFFF
+    return out
+
+
+class Mesh:
+    def __init__(self, verts, vert_edge, vert_t, tris, cells, cases, counters):
+        self.verts, self.vert_edge, self.vert_t = verts, vert_edge, vert_t
+        self.tris, self.cells, self.cases = tris, cells, cases
+        self.counters = counters
+
+
+class Polygonizer:
+    """Buffers and call sequence for one bound on one grid (n, lo, h)."""
+
+    def __init__(self, bound, n, lo, h, corner_cap=0, vert_cap=0, tri_cap=0, cell_cap=0, device="cuda",
+                 keep_cells=True, keep_edges=True):
+        self.bound = bound
+        self.grid = N.make_grid(n, lo, h)
+        self.n = int(n)
+        self.device = torch.device(device)
+        n1 = self.n + 1
+        self.corner_cap = int(corner_cap) if corner_cap > 0 else 16 * n1 * n1
+        self.vert_cap = int(vert_cap) if vert_cap > 0 else 8 * n1 * n1
+        self.tri_cap = int(tri_cap) if tri_cap > 0 else 2 * self.vert_cap
+        self.cell_cap = int(cell_cap) if cell_cap > 0 else self.tri_cap
+        self.keep_cells, self.keep_edges = keep_cells, keep_edges
+        self.ctr = torch.zeros(8, dtype=torch.int64, device=self.device)
+        self.dense_buf = None
+        self._alloc()
+
+    def _alloc(self):
+        dev = self.device
+        ws_bytes = N.gh_workspace_size(self.grid, self.corner_cap)
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        self.verts = torch.empty((self.vert_cap, 3), dtype=torch.float32, device=dev)
+        self.vert_edge = torch.empty(self.vert_cap, dtype=torch.int64, device=dev) if self.keep_edges else None
+        self.vert_t = torch.empty(self.vert_cap, dtype=torch.float32, device=dev) if self.keep_edges else None
+        self.tris = torch.empty((self.tri_cap, 3), dtype=torch.int32, device=dev)
+        self.cells = torch.empty(self.cell_cap, dtype=torch.int64, device=dev) if self.keep_cells else None
+        self.cases = torch.empty(self.cell_cap, dtype=torch.uint8, device=dev) if self.keep_cells else None
+
+    # ---------------------------------------------------------- enqueue only
+    def enqueue_hop(self, stream=None):
+        N.check(N.gh_hop(self.bound.desc, self.grid, self.ws, self.corner_cap, self.ctr, stream), "gh_hop")
+
+    def enqueue_dense(self, stream=None):
+        if self.dense_buf is None:
+            n1 = self.n + 1
+            self.dense_buf = torch.empty(n1 * n1 * n1, dtype=torch.float32, device=self.device)
+        N.check(N.gh_dense(self.bound.desc, self.grid, self.ws, self.corner_cap, self.dense_buf, self.ctr, stream),
+                "gh_dense")
+
+    def enqueue_mc(self, stream=None):
+        N.check(N.gh_mc(self.bound.desc, self.grid, self.ws, self.corner_cap, self.verts, self.vert_edge,
+                        self.vert_t, self.vert_cap, self.tris, self.tri_cap, self.cells, self.cases,
+                        self.cell_cap if self.keep_cells else 0, self.ctr, stream), "gh_mc")
+
+    # ------------------------------------------------------------ blocking
+    def run(self, dense=False, stream=None, max_retries=3):
+        for _ in range(max_retries + 1):
+            (self.enqueue_dense if dense else self.enqueue_hop)(stream)
+            self.enqueue_mc(stream)
+            torch.cuda.synchronize(self.device)
+            c = counters_dict(self.ctr)
+            if c["flags"] & N.GH_FLAG_INTERNAL:
+                raise RuntimeError("gh_mc found inconsistent workspace contents")
+            if c["flags"] & N.GH_FLAG_NONFINITE:
+                raise FloatingPointError("the bound returned a non-finite value")
+            if not c["flags"] & N.GH_FLAG_CAPACITY:
+                return self.result(c)
+            self.corner_cap = max(self.corner_cap, int(c["n_corner"] * 1.25) + 64)
+            self.vert_cap = max(self.vert_cap, int(c["n_vert"] * 1.25) + 64)
+            self.tri_cap = max(self.tri_cap, int(c["n_tri"] * 1.25) + 64)
+            self.cell_cap = max(self.cell_cap, int(c["n_cells"] * 1.25) + 64)
+            self._alloc()
+        raise RuntimeError("capacity retries exhausted")
+
+    def result(self, c=None):
+        c = c or counters_dict(self.ctr)
+        nv, nt, nc = c["n_vert"], c["n_tri"], c["n_cells"]
+        return Mesh(self.verts[:nv], self.vert_edge[:nv] if self.keep_edges else None,
+                    self.vert_t[:nv] if self.keep_edges else None, self.tris[:nt],
+                    self.cells[:nc] if self.keep_cells else None, self.cases[:nc] if self.keep_cells else None, c)
+
+    def candidates(self, stream=None):
+        """Candidate cell ids recorded by the last hop (ascending int64)."""
+        c = counters_dict(self.ctr)
+        out = torch.empty(max(c["n_cand"], 1), dtype=torch.int64, device=self.device)
+        N.check(N.gh_candidates(self.grid, self.ws, self.corner_cap, out, c["n_cand"], self.ctr, stream),
+                "gh_candidates")
+        torch.cuda.synchronize(self.device)
+        return out[:c["n_cand"]]

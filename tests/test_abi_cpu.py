@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/gh.h declares, and rejects bad arguments before
+enqueuing anything."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+N = pytest.importorskip("paper_2111_05778_amd.native", reason="libgh.so not built")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gh.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:gh_status|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert {"sdb_describe", "gh_hop", "gh_mc", "gh_dense", "gh_last_error"} <= set(names)
+    for name in names:
+        assert hasattr(N.lib, name), name
+    assert sorted(N.EXPORTS) == sorted(names)
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(N.gh_counters) == 64
+    assert ctypes.sizeof(N.gh_grid) == 12
+    assert ctypes.sizeof(N.gh_sdb_desc) == 192
+
+
+def test_workspace_size_grows_with_grid_and_cap():
+    a = N.gh_workspace_size(N.make_grid(64, -1, 2 / 64), 1000)
+    b = N.gh_workspace_size(N.make_grid(128, -1, 2 / 128), 1000)
+    c = N.gh_workspace_size(N.make_grid(128, -1, 2 / 128), 100000)
+    assert 0 < a < b < c
+    assert abs((c - b) - 99000 * 20) < 4 * 256   # 20 bytes per corner, up to alignment
+
+
+@pytest.mark.parametrize("n,h", [(0, 0.1), (-3, 0.1), (16, 0.0), (16, float("nan")), (16, -1.0)])
+def test_bad_grid_rejected(n, h):
+    out = ctypes.c_size_t(0)
+    st = N.lib.gh_workspace_size(ctypes.byref(N.gh_grid(n, -1.0, h)), 0, ctypes.byref(out))
+    assert st == N.GH_EINVAL
+    assert len(N.lib.gh_last_error()) > 0
+
+
+def test_too_large_grid_unsupported():
+    out = ctypes.c_size_t(0)
+    assert N.lib.gh_workspace_size(ctypes.byref(N.gh_grid(4096, -1.0, 2 / 4096)), 0, ctypes.byref(out)) == \
+        N.GH_EUNSUPPORTED
+
+
+def _spec(recs):
+    recs = np.ascontiguousarray(recs, dtype=np.float32)
+    s = N.gh_sdb_spec()
+    s.kind = N.GH_SDB_PRIMS
+    s.n_prim = recs.shape[0]
+    s.prims_h = recs.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    return s, recs
+
+
+def test_describe_size_query_and_validation():
+    s, keep = _spec(W.csg_scene(0))
+    need = ctypes.c_size_t(0)
+    assert N.lib.sdb_describe(ctypes.byref(s), None, 0, ctypes.byref(need), None, None) == N.GH_OK
+    assert need.value == 12 * 16 * 4
+    bad = keep.copy()
+    bad[3, 0] = 9.0                       # unknown primitive type
+    s2, keep2 = _spec(bad)
+    assert N.lib.sdb_describe(ctypes.byref(s2), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
+    bad = keep.copy()
+    bad[1, 5] = np.inf
+    s3, keep3 = _spec(bad)
+    assert N.lib.sdb_describe(ctypes.byref(s3), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
+    s.n_prim = 0
+    assert N.lib.sdb_describe(ctypes.byref(s), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
+
+
+def test_calls_reject_unfilled_descriptor_and_null_buffers():
+    desc = N.gh_sdb_desc()
+    g = N.make_grid(16, -1, 0.125)
+    st = N.lib.gh_hop(ctypes.byref(desc), ctypes.byref(g), ctypes.c_void_p(256), 1 << 30, 0, ctypes.c_void_p(512), None)
+    assert st == N.GH_EINVAL and b"sdb_describe" in N.lib.gh_last_error()
+    st = N.lib.gh_candidates(ctypes.byref(g), None, 0, 0, None, 0, None, None)
+    assert st == N.GH_EINVAL
+
+
+def test_workspace_too_small_is_capacity_error():
+    desc = N.gh_sdb_desc()
+    # a descriptor must pass validation first; use the grid check path of gh_candidates instead
+    g = N.make_grid(16, -1, 0.125)
+    st = N.lib.gh_candidates(ctypes.byref(g), ctypes.c_void_p(256), 1024, 0, ctypes.c_void_p(512), 1,
+                             ctypes.c_void_p(1024), None)
+    assert st == N.GH_ECAPACITY
+    del desc
