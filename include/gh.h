@@ -175,6 +175,18 @@ gh_status gh_candidates(const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_
 /* Evaluate the bound at m points xyz [m][3] (device) into f [m] (device). */
 gh_status gh_eval_points(const gh_sdb_desc* desc_h, const float* xyz, float* f, int64_t m, void* stream);
 
+/* Launch shapes of the kernels, process-wide (an autotuner sets them).
+ * Fields left at 0 keep the built-in choice. */
+typedef struct {
+  int32_t hop_lanes_per_ray; /* lanes tracing one ray together: 1, 2, 4 or 8 */
+  int32_t reserved[7];
+} gh_tuning;
+
+/* Replace the process-wide launch shapes; GH_EINVAL for unsupported values. */
+gh_status gh_set_tuning(const gh_tuning* tuning_h);
+/* Read the launch shapes in effect. */
+gh_status gh_get_tuning(gh_tuning* tuning_h);
+
 /* Human-readable description of the last synchronous error on this thread. */
 const char* gh_last_error(void);
 

@@ -6,7 +6,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <atomic>
 #include <string>
+#include <vector>
 
 #include "gh.h"
 #include "gh_launch.h"
@@ -15,6 +18,7 @@
 namespace {
 
 thread_local std::string g_last_error;
+std::atomic<int> g_hop_lanes{0};
 
 gh_status fail(gh_status st, const char* fmt, ...) {
   char buf[512];
@@ -75,6 +79,22 @@ extern "C" {
 
 const char* gh_last_error(void) { return g_last_error.c_str(); }
 
+gh_status gh_set_tuning(const gh_tuning* t) {
+  if (!t) return fail(GH_EINVAL, "tuning is NULL");
+  const int r = t->hop_lanes_per_ray;
+  if (!(r == 0 || r == 1 || r == 2 || r == 4 || r == 8))
+    return fail(GH_EINVAL, "hop_lanes_per_ray = %d must be 0, 1, 2, 4 or 8", r);
+  g_hop_lanes.store(r, std::memory_order_relaxed);
+  return GH_OK;
+}
+
+gh_status gh_get_tuning(gh_tuning* t) {
+  if (!t) return fail(GH_EINVAL, "tuning is NULL");
+  memset(t, 0, sizeof(*t));
+  t->hop_lanes_per_ray = g_hop_lanes.load(std::memory_order_relaxed);
+  return GH_OK;
+}
+
 gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_bytes, size_t* blob_needed_h,
                        gh_sdb_desc* desc_h, void* stream) {
   if (!spec_h) return fail(GH_EINVAL, "spec is NULL");
@@ -88,16 +108,39 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
     const float t = r[0];
     if (!(t == 0.f || t == 1.f || t == 2.f || t == 3.f || t == 4.f || t == 5.f))
       return fail(GH_EINVAL, "primitive %d has unknown type %g", p, (double)t);
-    for (int q = 1; q < GH_PRIM_FLOATS; ++q)
-      if (!isfinite(r[q])) return fail(GH_EINVAL, "primitive %d parameter %d is not finite", p, q);
+    // Bounded magnitudes keep every intermediate finite or +inf, never NaN:
+    // |M q| <= 3e33 and sums of squares can only overflow towards +inf.
+    for (int q = 1; q < GH_PRIM_FLOATS; ++q) {
+      const float lim = (q >= 4 && q <= 12) ? 1e3f : 1e30f;
+      if (!(fabsf(r[q]) <= lim))
+        return fail(GH_EINVAL, "primitive %d parameter %d = %g is not finite or exceeds %g", p, q, (double)r[q],
+                    (double)lim);
+    }
   }
   const size_t need = (size_t)np * GH_PRIM_FLOATS * sizeof(float);
   if (blob_needed_h) *blob_needed_h = need;
   if (!dev_blob) return desc_h ? fail(GH_EINVAL, "dev_blob is NULL") : GH_OK;
   if (blob_bytes < need) return fail(GH_ECAPACITY, "blob of %zu bytes, %zu needed", blob_bytes, need);
   if (!desc_h) return fail(GH_EINVAL, "desc is NULL");
+  // Group the records by type (stable): the union's minimum does not depend
+  // on the order, and the kernels then loop over one type at a time.
+  std::vector<float> sorted((size_t)np * GH_PRIM_FLOATS);
+  gh::PrimGroups groups{};
+  {
+    size_t o = 0;
+    for (int t = 0; t < gh::kPrimTypes; ++t) {
+      groups.start[t] = (int)(o / GH_PRIM_FLOATS);
+      for (int p = 0; p < np; ++p) {
+        const float* r = spec_h->prims_h + (size_t)p * GH_PRIM_FLOATS;
+        if ((int)r[0] != t) continue;
+        std::copy(r, r + GH_PRIM_FLOATS, sorted.begin() + o);
+        o += GH_PRIM_FLOATS;
+      }
+    }
+    groups.start[gh::kPrimTypes] = np;
+  }
   hipStream_t s = (hipStream_t)stream;
-  gh_status st = hip_status(hipMemcpyAsync(dev_blob, spec_h->prims_h, need, hipMemcpyHostToDevice, s), "upload");
+  gh_status st = hip_status(hipMemcpyAsync(dev_blob, sorted.data(), need, hipMemcpyHostToDevice, s), "upload");
   if (st != GH_OK) return st;
   st = hip_status(hipStreamSynchronize(s), "upload sync");
   if (st != GH_OK) return st;
@@ -106,6 +149,7 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
   d.kind = GH_SDB_PRIMS;
   d.n_prim = np;
   d.prims = (const float*)dev_blob;
+  d.groups = groups;
   memset(desc_h, 0, sizeof(*desc_h));
   memcpy(desc_h, &d, sizeof(d));
   return GH_OK;
@@ -134,7 +178,7 @@ gh_status gh_hop(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, siz
   if (!ctr) return fail(GH_EINVAL, "counters are NULL");
   hipStream_t s = (hipStream_t)stream;
   if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearAll, s), "clear")) != GH_OK) return st;
-  return hip_status(gh::launch_hop(d, g, w, ctr, s), "hop");
+  return hip_status(gh::launch_hop(d, g, w, ctr, g_hop_lanes.load(std::memory_order_relaxed), s), "hop");
 }
 
 gh_status gh_dense(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,

@@ -41,39 +41,77 @@ __device__ __forceinline__ float lattice(const Grid& g, int idx) { return g.lo +
 //   torus    s = sqrt(qx qx + qz qz) - R;  sqrt(s s + qy qy) - r
 //   capsule  w = qz - min(max(qz, -a), a);  sqrt((qx qx + qy qy) + w w) - r
 //   plane    ((n_x x + n_y y) + n_z z) - d                 (Section 4.1, eq. plane)
-__device__ __forceinline__ float prim_eval(const float* __restrict__ r, float x, float y, float z) {
-  const int t = (int)r[0];
-  if (t == kPrimPlane) return ((r[4] * x + r[5] * y) + r[6] * z) - r[13];
-  const float dx = x - r[1], dy = y - r[2], dz = z - r[3];
-  const float qx = (r[4] * dx + r[5] * dy) + r[6] * dz;
-  const float qy = (r[7] * dx + r[8] * dy) + r[9] * dz;
-  const float qz = (r[10] * dx + r[11] * dy) + r[12] * dz;
-  if (t == kPrimSphere) return sqrtf((qx * qx + qy * qy) + qz * qz) - r[13];
-  if (t == kPrimTorus) {
-    const float s = sqrtf(qx * qx + qz * qz) - r[13];
-    return sqrtf(s * s + qy * qy) - r[14];
+// The type is a template argument: callers loop over primitives grouped by
+// type, so no branch on the type sits inside the loop.
+template <int T>
+__device__ __forceinline__ float prim_eval_t(const float* __restrict__ r, float x, float y, float z) {
+  if constexpr (T == kPrimPlane) {
+    return ((r[4] * x + r[5] * y) + r[6] * z) - r[13];
+  } else {
+    const float dx = x - r[1], dy = y - r[2], dz = z - r[3];
+    const float qx = (r[4] * dx + r[5] * dy) + r[6] * dz;
+    const float qy = (r[7] * dx + r[8] * dy) + r[9] * dz;
+    const float qz = (r[10] * dx + r[11] * dy) + r[12] * dz;
+    if constexpr (T == kPrimSphere) {
+      return sqrtf((qx * qx + qy * qy) + qz * qz) - r[13];
+    } else if constexpr (T == kPrimTorus) {
+      const float s = sqrtf(qx * qx + qz * qz) - r[13];
+      return sqrtf(s * s + qy * qy) - r[14];
+    } else if constexpr (T == kPrimCapsule) {
+      const float w = qz - fminf(fmaxf(qz, -r[13]), r[13]);
+      return sqrtf((qx * qx + qy * qy) + w * w) - r[14];
+    } else {
+      const float ux = fabsf(qx) - r[13], uy = fabsf(qy) - r[14], uz = fabsf(qz) - r[15];
+      const float inner = fmaxf(ux, fmaxf(uy, uz));
+      if constexpr (T == kPrimBoxBound) {
+        return inner;
+      } else {
+        const float mx = fmaxf(ux, 0.f), my = fmaxf(uy, 0.f), mz = fmaxf(uz, 0.f);
+        return sqrtf((mx * mx + my * my) + mz * mz) + fminf(inner, 0.f);
+      }
+    }
   }
-  if (t == kPrimCapsule) {
-    const float w = qz - fminf(fmaxf(qz, -r[13]), r[13]);
-    return sqrtf((qx * qx + qy * qy) + w * w) - r[14];
-  }
-  const float ux = fabsf(qx) - r[13], uy = fabsf(qy) - r[14], uz = fabsf(qz) - r[15];
-  const float inner = fmaxf(ux, fmaxf(uy, uz));
-  if (t == kPrimBoxBound) return inner;
-  const float mx = fmaxf(ux, 0.f), my = fmaxf(uy, 0.f), mz = fmaxf(uz, 0.f);
-  return sqrtf((mx * mx + my * my) + mz * mz) + fminf(inner, 0.f);
 }
 
-// Min-union of the records in order (Section 4.3).  The record pointer and
-// count are uniform across the wave, so the parameters come in through
-// scalar loads and the type branches do not diverge.
+constexpr int kPrimTypes = 6;
+
+// Primitives sorted by type: group t occupies records [start[t], start[t+1]).
+// The minimum is exact and commutative, so the order of the union does not
+// change a single bit of the result (parameters are validated on the host so
+// that no primitive can produce NaN).
+struct PrimGroups {
+  int start[kPrimTypes + 1];
+};
+
+template <int T, class F>
+__device__ __forceinline__ void for_prims_of_type(const PrimGroups& g, int first, int step, F&& fn) {
+  for (int p = g.start[T] + first; p < g.start[T + 1]; p += step) fn(p);
+}
+
+// Union over the primitives p = first, first + step, ... of every group.
+template <class Rec>
+__device__ __forceinline__ float union_strided(const PrimGroups& g, Rec rec, int first, int step, float x, float y,
+                                               float z) {
+  float f = __builtin_inff();
+  for_prims_of_type<kPrimSphere>(g, first, step, [&](int p) { f = fminf(f, prim_eval_t<kPrimSphere>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimBox>(g, first, step, [&](int p) { f = fminf(f, prim_eval_t<kPrimBox>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimTorus>(g, first, step, [&](int p) { f = fminf(f, prim_eval_t<kPrimTorus>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimCapsule>(g, first, step,
+                                  [&](int p) { f = fminf(f, prim_eval_t<kPrimCapsule>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimPlane>(g, first, step, [&](int p) { f = fminf(f, prim_eval_t<kPrimPlane>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimBoxBound>(g, first, step,
+                                   [&](int p) { f = fminf(f, prim_eval_t<kPrimBoxBound>(rec(p), x, y, z)); });
+  return f;
+}
+
+// Min-union evaluated by one lane, parameters read through the scalar cache
+// (the record pointer is uniform across the wave).
 struct PrimsEval {
   const float* __restrict__ prims;
-  int n_prim;
+  PrimGroups groups;
   __device__ __forceinline__ float operator()(float x, float y, float z) const {
-    float f = prim_eval(prims, x, y, z);
-    for (int p = 1; p < n_prim; ++p) f = fminf(f, prim_eval(prims + p * GH_PRIM_FLOATS, x, y, z));
-    return f;
+    const float* __restrict__ base = prims;
+    return union_strided(groups, [base](int p) { return base + p * GH_PRIM_FLOATS; }, 0, 1, x, y, z);
   }
 };
 
@@ -95,7 +133,8 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
   return v;
 }
 
-// Adds v (per thread) over the block and atomically into *dst (one atomic per block).
+// Adds v (per thread) over the block and atomically into *dst (one atomic per
+// block).  The closing barrier lets the next call reuse the partials safely.
 __device__ __forceinline__ void block_add_u64(uint64_t v, unsigned long long* dst) {
   __shared__ uint64_t s_part[kBlock / 64];
   v = wave_sum_u64(v);
@@ -106,6 +145,7 @@ __device__ __forceinline__ void block_add_u64(uint64_t v, unsigned long long* ds
     for (int w = 0; w < kBlock / 64; ++w) t += s_part[w];
     if (t) atomicAdd(dst, (unsigned long long)t);
   }
+  __syncthreads();
 }
 
 // ------------------------------------------------ single-pass block scan
@@ -129,11 +169,15 @@ struct ScanOut {
   uint64_t total;  // inclusive prefix at the end of this tile
 };
 
-// The wait for a predecessor is bounded: should it ever exceed kSpinLimit
-// polls (only possible through a library bug), *err gets GH_FLAG_INTERNAL and
-// the tile carries on with a partial prefix; every write stays inside its
-// capacity check, so the result is flagged rather than the device hung.
-constexpr int kSpinLimit = 1 << 24;
+// Wave 0 of the tile does the look-back, 64 predecessors per round: lane m
+// reads the word of tile base - m.  The closest predecessor holding an
+// inclusive prefix ends the walk; until it is found, every word in between
+// must at least hold its aggregate.  Tiles before 0 read as prefix 0.
+// The wait is bounded: should it exceed kSpinLimit rounds (only possible
+// through a library bug), *err gets GH_FLAG_INTERNAL and the tile carries on
+// with a partial prefix; every write stays inside its capacity check, so the
+// result is flagged rather than the device hung.
+constexpr int kSpinLimit = 1 << 22;
 
 __device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* flags, int tile, unsigned int* err) {
   __shared__ uint64_t s_wave[kBlock / 64];
@@ -148,33 +192,43 @@ __device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* fla
     if (w < wave_id()) wave_off += s;
     agg += s;
   }
-  if (threadIdx.x == 0) {
+  if (wave_id() == 0) {
+    const int l = lane_id();
     uint64_t prev = 0;
     if (tile == 0) {
-      __hip_atomic_store(&flags[0], kScanPrefix | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (l == 0)
+        __hip_atomic_store(&flags[0], kScanPrefix | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      __hip_atomic_store(&flags[tile], kScanAgg | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int j = tile - 1;
+      if (l == 0)
+        __hip_atomic_store(&flags[tile], kScanAgg | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int base = tile - 1;
       int spins = 0;
       while (true) {
-        const uint64_t f = __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int j = base - l;
+        const uint64_t f =
+            j >= 0 ? __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanPrefix;
         const uint64_t st = f & ~kScanValMask;
-        if (st == 0) {
+        const uint64_t pre = __ballot(st == kScanPrefix);
+        const uint64_t empty = __ballot(st == 0);
+        const int first = pre ? __builtin_ctzll(pre) : 64;
+        const uint64_t need = first == 64 ? ~0ull : ((2ull << first) - 1ull);  // lanes 0..first
+        if (empty & need) {
           if (++spins > kSpinLimit) {
-            atomicOr(err, GH_FLAG_INTERNAL);
+            if (l == 0) atomicOr(err, GH_FLAG_INTERNAL);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
-        prev += f & kScanValMask;
-        if (st == kScanPrefix || j == 0) break;  // tile 0 always publishes a prefix
-        --j;
+        prev += wave_sum_u64(l <= first ? (f & kScanValMask) : 0ull);
+        if (first < 64) break;
+        base -= 64;
       }
-      __hip_atomic_store(&flags[tile], kScanPrefix | ((prev + agg) & kScanValMask), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      if (l == 0)
+        __hip_atomic_store(&flags[tile], kScanPrefix | ((prev + agg) & kScanValMask), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
-    s_prev = prev;
+    if (l == 0) s_prev = prev;
   }
   __syncthreads();
   ScanOut o;

@@ -50,28 +50,47 @@ __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, u
 }
 
 // --------------------------------------------------------------------- hop
-// Ray columns are tiled 16 x 16 per block; each wave takes an 8 x 8 patch so
-// that its lanes trace neighbouring rays with similar step counts.
-__device__ __forceinline__ void hop_tile_column(int n, int& i, int& j) {
-  const int ntx = (n + 15) >> 4;
-  const int ti = blockIdx.x / ntx, tj = blockIdx.x - ti * ntx;
-  const int w = wave_id(), l = lane_id();
-  i = ti * 16 + (w >> 1) * 8 + (l >> 3);
-  j = tj * 16 + (w & 1) * 8 + (l & 7);
-}
+// R lanes trace one ray together: lane q of the group evaluates primitives
+// q, q + R, q + 2R, ... of each type group (records staged in LDS) and a
+// butterfly over the R lanes forms the union's minimum, which every lane of
+// the group then holds bit for bit.  This divides the latency of one hop
+// step by about R; it matters because the kernel lasts as long as its
+// longest column, and a ray grazing a flat face steps cell by cell (the
+// plane-parallel case of Section 4.1 costs N steps on such a column).
+// A wave covers a compact patch of columns whose step counts are similar.
+template <int R>
+struct HopShape {
+  static constexpr int kWaveRays = 64 / R;
+  static constexpr int kWaveW = R == 1 ? 8 : (R == 2 ? 8 : (R == 4 ? 4 : 4));
+  static constexpr int kWaveH = kWaveRays / kWaveW;
+  static constexpr int kBlockH = 2 * kWaveH, kBlockW = 2 * kWaveW;
+};
 
 // Hop rule (Section 3, eq. iter, cell-quantised): at the centroid of cell k,
 // s = floor(|f| * inv_h); s >= 1 skips s cells, s == 0 marks cell k as a
 // candidate and moves to k + 1; the ray ends when k >= n.
-template <class Eval>
-__global__ __launch_bounds__(kBlock) void k_hop(Eval ev, Grid g, uint64_t* __restrict__ colmask,
-                                                uint32_t* __restrict__ colbits, gh_counters* __restrict__ ctr) {
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_hop_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
+                                                      uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
+                                                      gh_counters* __restrict__ ctr) {
+  using S = HopShape<R>;
+  __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
+  const int np = groups.start[kPrimTypes];
+  for (int t = threadIdx.x; t < np * (GH_PRIM_FLOATS / 4); t += kBlock)
+    s_rec[t] = reinterpret_cast<const float4*>(prims)[t];
+  __syncthreads();
+  const float* srec = reinterpret_cast<const float*>(s_rec);
+
   const int n = g.n;
-  int i, j;
-  hop_tile_column(n, i, j);
+  const int nbw = (n + S::kBlockW - 1) / S::kBlockW;
+  const int bi = blockIdx.x / nbw, bj = blockIdx.x - bi * nbw;
+  const int w = wave_id(), l = lane_id();
+  const int r = l / R, q = l % R;
+  const int i = bi * S::kBlockH + (w >> 1) * S::kWaveH + r / S::kWaveW;
+  const int j = bj * S::kBlockW + (w & 1) * S::kWaveW + r % S::kWaveW;
   uint64_t evals = 0, cands = 0;
   bool bad = false;
-  if (i < n && j < n) {
+  if (i < n && j < n) {  // uniform over the R lanes of a ray
     const size_t ncol = (size_t)n * n, col = (size_t)i * n + j;
     const float x = centroid(g, i), y = centroid(g, j);
     const float nf = (float)n;
@@ -79,7 +98,10 @@ __global__ __launch_bounds__(kBlock) void k_hop(Eval ev, Grid g, uint64_t* __res
     uint32_t word = 0;
     uint64_t mask = 0;
     while (k < n) {
-      const float f = ev(x, y, centroid(g, k));
+      float f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y,
+                              centroid(g, k));
+#pragma unroll
+      for (int m = 1; m < R; m <<= 1) f = fminf(f, __shfl_xor(f, m, 64));
       ++evals;
       const float d = fabsf(f);
       if (!(d <= FLT_MAX)) {
@@ -90,10 +112,8 @@ __global__ __launch_bounds__(kBlock) void k_hop(Eval ev, Grid g, uint64_t* __res
       if (s == 0.f) {
         const int kw = k >> 5;
         if (kw != wi) {
-          if (word) {
-            colbits[(size_t)wi * ncol + col] = word;
-            mask |= 1ull << wi;
-          }
+          if (word && q == 0) colbits[(size_t)wi * ncol + col] = word;
+          if (word) mask |= 1ull << wi;
           word = 0;
           wi = kw;
         }
@@ -104,25 +124,32 @@ __global__ __launch_bounds__(kBlock) void k_hop(Eval ev, Grid g, uint64_t* __res
         k += (int)fminf(s, nf);
       }
     }
-    if (word) {
-      colbits[(size_t)wi * ncol + col] = word;
-      mask |= 1ull << wi;
+    if (q == 0) {
+      if (word) {
+        colbits[(size_t)wi * ncol + col] = word;
+        mask |= 1ull << wi;
+      }
+      colmask[col] = mask;
     }
-    colmask[col] = mask;
   }
-  if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  if (q != 0) evals = cands = 0;
+  if (bad && q == 0) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
   block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
   block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
 }
 
 // ------------------------------------------------------------ enumeration
-// Bound at every lattice point, layout [c][a][b] (b fastest).
+// Bound at every lattice point, layout [c][a][b] (b fastest); also clears the
+// column masks that k_dense_classify sets.
 template <class Eval>
-__global__ __launch_bounds__(kBlock) void k_dense_eval(Eval ev, Grid g, float* __restrict__ dense) {
+__global__ __launch_bounds__(kBlock) void k_dense_eval(Eval ev, Grid g, float* __restrict__ dense,
+                                                       uint64_t* __restrict__ colmask) {
   const int n1 = g.n + 1;
-  const size_t total = (size_t)n1 * n1 * n1;
+  const size_t total = (size_t)n1 * n1 * n1, ncol = (size_t)g.n * g.n;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+  const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (size_t c = t0; c < ncol; c += stride) colmask[c] = 0;
+  for (size_t idx = t0; idx < total; idx += stride) {
     const int b = (int)(idx % n1);
     const size_t r = idx / n1;
     const int a = (int)(r % n1), c = (int)(r / n1);
@@ -131,45 +158,43 @@ __global__ __launch_bounds__(kBlock) void k_dense_eval(Eval ev, Grid g, float* _
 }
 
 // Every cell whose eight corners do not share one side becomes a candidate.
+// One thread builds one 32-cell word of one column: lanes run over adjacent
+// columns, so each lattice plane is read in coalesced rows.
 __global__ __launch_bounds__(kBlock) void k_dense_classify(Grid g, const float* __restrict__ dense,
                                                            uint64_t* __restrict__ colmask,
                                                            uint32_t* __restrict__ colbits,
                                                            gh_counters* __restrict__ ctr) {
   const int n = g.n, n1 = n + 1;
   const size_t ncol = (size_t)n * n;
-  const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int words = (n + 31) >> 5;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t col = tid % ncol;
+  const int w = (int)(tid / ncol);
   uint64_t cands = 0;
   bool bad = false;
-  if (col < ncol) {
+  if (w < words) {
     const int i = (int)(col / n), j = (int)(col % n);
     const size_t plane = (size_t)n1 * n1;
-    const size_t o00 = (size_t)i * n1 + j, o01 = o00 + 1, o10 = o00 + n1, o11 = o10 + 1;
-    auto side = [&](size_t o) {
-      const float f = dense[o];
-      bad |= !(fabsf(f) <= FLT_MAX);
-      return (unsigned)(f < 0.f);
+    const size_t o00 = (size_t)i * n1 + j, o10 = o00 + n1;
+    auto side4 = [&](size_t base) {
+      const float f0 = dense[base + o00], f1 = dense[base + o00 + 1], f2 = dense[base + o10], f3 = dense[base + o10 + 1];
+      bad |= !(fabsf(f0) <= FLT_MAX) | !(fabsf(f1) <= FLT_MAX) | !(fabsf(f2) <= FLT_MAX) | !(fabsf(f3) <= FLT_MAX);
+      return (unsigned)(f0 < 0.f) + (unsigned)(f1 < 0.f) + (unsigned)(f2 < 0.f) + (unsigned)(f3 < 0.f);
     };
-    unsigned lowc = side(o00) + side(o01) + side(o10) + side(o11);
-    uint64_t mask = 0;
+    const int k0 = 32 * w, k1 = min(n, k0 + 32);
+    unsigned lowc = side4((size_t)k0 * plane);
     uint32_t word = 0;
-    for (int k = 0; k < n; ++k) {
-      const size_t base = (size_t)(k + 1) * plane;
-      const unsigned upc = side(base + o00) + side(base + o01) + side(base + o10) + side(base + o11);
+    for (int k = k0; k < k1; ++k) {
+      const unsigned upc = side4((size_t)(k + 1) * plane);
       const unsigned inside = lowc + upc;
-      if (inside != 0 && inside != 8) {
-        word |= 1u << (k & 31);
-        ++cands;
-      }
-      if ((k & 31) == 31 || k == n - 1) {
-        if (word) {
-          colbits[(size_t)(k >> 5) * ncol + col] = word;
-          mask |= 1ull << (k >> 5);
-        }
-        word = 0;
-      }
+      if (inside != 0 && inside != 8) word |= 1u << (k - k0);
       lowc = upc;
     }
-    colmask[col] = mask;
+    if (word) {
+      colbits[(size_t)w * ncol + col] = word;
+      atomicOr((unsigned long long*)&colmask[col], 1ull << w);
+      cands = __popc(word);
+    }
   }
   if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
   block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
@@ -203,34 +228,28 @@ __global__ __launch_bounds__(kBlock) void k_candidates(Grid g, Workspace ws, int
 }
 
 // ------------------------------------------------------------------ corners
-// Candidate words of the (up to four) cell columns around lattice column (a, b).
+// Candidate words of the (up to four) cell columns around lattice column
+// (a, b); a missing or empty column has mask 0.  Fixed-size and unrolled so
+// that everything stays in registers.
 struct LatAdj {
   size_t col[4];
   uint64_t mask[4];
-  int cnt;
   uint64_t uni;
 };
 
 __device__ __forceinline__ LatAdj lat_adjacent(int n, int a, int b, const uint64_t* __restrict__ colmask) {
   LatAdj A;
-  A.cnt = 0;
   A.uni = 0;
 #pragma unroll
-  for (int di = -1; di <= 0; ++di)
-#pragma unroll
-    for (int dj = -1; dj <= 0; ++dj) {
-      const int i = a + di, j = b + dj;
-      if (i >= 0 && i < n && j >= 0 && j < n) {
-        const size_t c = (size_t)i * n + j;
-        const uint64_t m = colmask[c];
-        if (m) {
-          A.col[A.cnt] = c;
-          A.mask[A.cnt] = m;
-          A.uni |= m;
-          ++A.cnt;
-        }
-      }
-    }
+  for (int q = 0; q < 4; ++q) {
+    const int i = a - 1 + (q >> 1), j = b - 1 + (q & 1);
+    const bool ok = i >= 0 && i < n && j >= 0 && j < n;
+    const size_t c = ok ? (size_t)i * n + j : 0;
+    const uint64_t m = ok ? colmask[c] : 0ull;
+    A.col[q] = c;
+    A.mask[q] = m;
+    A.uni |= m;
+  }
   return A;
 }
 
@@ -238,7 +257,8 @@ __device__ __forceinline__ uint32_t adj_cell_word(const LatAdj& A, const uint32_
                                                   size_t ncol, int w) {
   uint32_t v = 0;
   if (w < 0 || w >= 64) return 0;
-  for (int q = 0; q < A.cnt; ++q)
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
     if ((A.mask[q] >> w) & 1) v |= colbits[(size_t)w * ncol + A.col[q]];
   return v;
 }
@@ -264,9 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_corners(Grid g, Workspace ws, gh_cou
   const size_t ncol = (size_t)n * n, nl = (size_t)n1 * n1;
   const int tile = acquire_tile(&ws.ticket[kTicketCorners]);
   const size_t L = (size_t)tile * kBlock + threadIdx.x;
-  LatAdj A;
-  A.cnt = 0;
-  A.uni = 0;
+  LatAdj A{{0, 0, 0, 0}, {0, 0, 0, 0}, 0};
   uint64_t cnt = 0;
   if (L < nl) {
     A = lat_adjacent(n, (int)(L / n1), (int)(L % n1), ws.colmask);
@@ -496,7 +514,9 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
           for (int v = 0; v < 3; ++v) {
             const int e = (int)((mcc.tri >> (12 * q + 4 * v)) & 15);
             const int lc = mc_edge_lower(e), axis = e >> 2;
-            const int64_t gi = C.p[(lc & 1) + 2 * ((lc >> 1) & 1)] + (lc >> 2);
+            const int slot = (lc & 1) + 2 * ((lc >> 1) & 1);
+            const int64_t base = slot == 0 ? C.p[0] : (slot == 1 ? C.p[1] : (slot == 2 ? C.p[2] : C.p[3]));
+            const int64_t gi = base + (lc >> 2);
             const int64_t info = ws.cinfo[gi];
             tris[3 * t + v] = (int32_t)((info >> 3) + __popc((unsigned)(info & 7) & ((1u << axis) - 1u)));
           }
@@ -544,11 +564,25 @@ hipError_t launch_clear(const Workspace& ws, gh_counters* ctr, ClearMode mode, h
   return hipGetLastError();
 }
 
-hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, hipStream_t s) {
-  const int nt = (g.n + 15) / 16;
-  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_hop<PrimsEval>, dim3(nt * nt), dim3(kBlock), 0, s, PrimsEval{d.prims, d.n_prim}, g, ws.colmask,
+template <int R>
+static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, hipStream_t s) {
+  using S = HopShape<R>;
+  const int nbh = (g.n + S::kBlockH - 1) / S::kBlockH, nbw = (g.n + S::kBlockW - 1) / S::kBlockW;
+  hipLaunchKernelGGL(k_hop_prims<R>, dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
                      ws.colbits, ctr);
+}
+
+hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, int lanes_per_ray,
+                      hipStream_t s) {
+  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
+  if (lanes_per_ray <= 0) lanes_per_ray = 4;
+  switch (lanes_per_ray) {
+    case 1: launch_hop_r<1>(d, g, ws, ctr, s); break;
+    case 2: launch_hop_r<2>(d, g, ws, ctr, s); break;
+    case 4: launch_hop_r<4>(d, g, ws, ctr, s); break;
+    case 8: launch_hop_r<8>(d, g, ws, ctr, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -559,10 +593,11 @@ hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, flo
   const int64_t total = n1 * n1 * n1;
   const int64_t blocks = (total + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_dense_eval<PrimsEval>, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(kBlock), 0, s,
-                     PrimsEval{d.prims, d.n_prim}, g, dense);
-  const int64_t ncol = (int64_t)g.n * g.n;
-  hipLaunchKernelGGL(k_dense_classify, dim3((unsigned)((ncol + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g, dense,
-                     ws.colmask, ws.colbits, ctr);
+                     PrimsEval{d.prims, d.groups}, g, dense, ws.colmask);
+  const int64_t words = (g.n + 31) / 32;
+  const int64_t threads = (int64_t)g.n * g.n * words;
+  hipLaunchKernelGGL(k_dense_classify, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g,
+                     dense, ws.colmask, ws.colbits, ctr);
   return hipGetLastError();
 }
 
@@ -578,7 +613,7 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
   if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_corners, dim3((unsigned)ws.tiles_lat), dim3(kBlock), 0, s, g, ws, ctr);
   hipLaunchKernelGGL(k_eval_corners<PrimsEval>, dim3(persistent_blocks(ws.cap)), dim3(kBlock), 0, s,
-                     PrimsEval{d.prims, d.n_prim}, g, ws, ctr);
+                     PrimsEval{d.prims, d.groups}, g, ws, ctr);
   hipLaunchKernelGGL(k_verts, dim3((unsigned)ws.tiles_lat), dim3(kBlock), 0, s, g, ws, verts, vert_edge, vert_t,
                      vert_cap, ctr);
   hipLaunchKernelGGL(k_tris, dim3((unsigned)ws.tiles_col), dim3(kBlock), 0, s, g, ws, tris, tri_cap, cells, cases,
@@ -589,7 +624,7 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
 hipError_t launch_eval_points(const DevSdb& d, const float* xyz, float* f, int64_t m, hipStream_t s) {
   if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_eval_points<PrimsEval>, dim3(persistent_blocks(m)), dim3(kBlock), 0, s,
-                     PrimsEval{d.prims, d.n_prim}, xyz, f, m);
+                     PrimsEval{d.prims, d.groups}, xyz, f, m);
   return hipGetLastError();
 }
 

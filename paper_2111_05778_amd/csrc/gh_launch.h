@@ -15,14 +15,17 @@ struct DevSdb {
   int32_t kind;
   int32_t n_prim;
   int32_t pad;
-  const float* prims;  // device, n_prim * GH_PRIM_FLOATS
+  const float* prims;  // device, n_prim * GH_PRIM_FLOATS, sorted by type
+  PrimGroups groups;   // type t occupies records [start[t], start[t+1])
 };
 constexpr uint32_t kDescMagic = 0x67687364u;  // "ghsd"
 
 enum ClearMode { kClearAll = 0, kClearMc = 1, kClearCands = 2 };
 
 hipError_t launch_clear(const Workspace& ws, gh_counters* ctr, ClearMode mode, hipStream_t s);
-hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, hipStream_t s);
+// lanes_per_ray: 1, 2, 4 or 8 lanes trace one ray together (0 = default).
+hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, int lanes_per_ray,
+                      hipStream_t s);
 hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, float* dense, gh_counters* ctr,
                         hipStream_t s);
 hipError_t launch_candidates(const Grid& g, const Workspace& ws, int64_t* out, int64_t cap, gh_counters* ctr,

@@ -22,7 +22,7 @@ GH_PREC_FP32, GH_PREC_BF16 = 0, 1
 GH_PRIM_FLOATS = 16
 
 EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_mc", "gh_dense", "gh_candidates",
-           "gh_eval_points", "gh_last_error"]
+           "gh_eval_points", "gh_set_tuning", "gh_get_tuning", "gh_last_error"]
 
 
 class gh_grid(ctypes.Structure):
@@ -48,6 +48,10 @@ class gh_sdb_spec(ctypes.Structure):
                 ("bf16_margin", ctypes.c_float)]
 
 
+class gh_tuning(ctypes.Structure):
+    _fields_ = [("hop_lanes_per_ray", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
 class gh_sdb_desc(ctypes.Structure):
     _fields_ = [("opaque", ctypes.c_uint64 * 24)]
 
@@ -63,6 +67,8 @@ lib.gh_mc.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _v
 lib.gh_dense.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp]
 lib.gh_candidates.argtypes = [_P(gh_grid), _vp, _sz, _i64, _vp, _i64, _vp, _vp]
 lib.gh_eval_points.argtypes = [_P(gh_sdb_desc), _vp, _vp, _i64, _vp]
+lib.gh_set_tuning.argtypes = [_P(gh_tuning)]
+lib.gh_get_tuning.argtypes = [_P(gh_tuning)]
 lib.gh_last_error.restype = ctypes.c_char_p
 for _name in EXPORTS[:-1]:
     getattr(lib, _name).restype = ctypes.c_int
@@ -132,3 +138,15 @@ def gh_candidates(grid, ws, corner_cap, out, cap, ctr, stream=None):
 
 def gh_eval_points(desc, xyz, f, m, stream=None):
     return lib.gh_eval_points(ctypes.byref(desc), ptr(xyz), ptr(f), int(m), stream_handle(stream))
+
+
+def gh_set_tuning(hop_lanes_per_ray=0):
+    t = gh_tuning()
+    t.hop_lanes_per_ray = int(hop_lanes_per_ray)
+    check(lib.gh_set_tuning(ctypes.byref(t)), "gh_set_tuning")
+
+
+def gh_get_tuning():
+    t = gh_tuning()
+    check(lib.gh_get_tuning(ctypes.byref(t)), "gh_get_tuning")
+    return {"hop_lanes_per_ray": t.hop_lanes_per_ray}

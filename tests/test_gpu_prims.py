@@ -225,3 +225,39 @@ def test_empty_scene(gh):
     # sphere entirely outside the grid: no candidates, no mesh
     out = _run(gh, W.sphere_scene(0.2, centre=(5.0, 5.0, 5.0)), *W.grid(40))
     assert out["ctr"]["n_cand"] == 0 and out["ctr"]["n_tri"] == 0 and out["ctr"]["n_corner"] == 0
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+def test_every_hop_shape_matches_twin(gh, lanes):
+    native, P = gh
+    recs = W.csg_scene(1)
+    g = W.grid(100)
+    native.gh_set_tuning(hop_lanes_per_ray=lanes)
+    try:
+        out = _run(gh, recs, *g)
+    finally:
+        native.gh_set_tuning(0)
+    ref = ohop.gridhop(osdb.SDB.prims(recs), *g, precision="f32")
+    _check_against_twin(out, ref, *[float(x) for x in g])
+
+
+def test_counters_repeatable_full_size(gh):
+    # per-block partial sums are reused by consecutive reductions; repeated
+    # runs and every hop shape must give the oracle's exact counts
+    native, P = gh
+    n, lo, h = W.grid(512)
+    recs = W.csg_scene(0)
+    cells, total, _ = ohop.hop(osdb.SDB.prims(recs), n, lo, h, precision="f32")
+    b = P.Bound.prims(recs)
+    import torch
+    try:
+        for lanes in (1, 2, 4, 8):
+            native.gh_set_tuning(lanes)
+            poly = P.Polygonizer(b, n, lo, h, keep_cells=False)
+            for _ in range(3):
+                poly.enqueue_hop()
+                torch.cuda.synchronize()
+                c = P.counters_dict(poly.ctr)
+                assert c["n_hop_evals"] == total and c["n_cand"] == len(cells), (lanes, c)
+    finally:
+        native.gh_set_tuning(0)
