@@ -279,43 +279,83 @@ __device__ __forceinline__ void for_corner_words(const LatAdj& A, F&& fn) {
   if ((A.uni >> 63) & 1) fn(64);
 }
 
+// List index of corner (L, k), or -1 when (L, k) is not a corner.
+__device__ __forceinline__ int64_t corner_index(const Workspace& ws, size_t nl, size_t L, int k) {
+  const int w = k >> 5;
+  const bool present = w < 64 ? ((ws.lmask[L] >> w) & 1) : (ws.lmhi[L] & 1);
+  if (!present) return -1;
+  const size_t o = (size_t)w * nl + L;
+  const uint32_t word = ws.lbits[o];
+  const uint32_t bit = 1u << (k & 31);
+  if (!(word & bit)) return -1;
+  return (int64_t)ws.lwst[o] + __popc(word & (bit - 1u));
+}
+
+// One thread per lattice column (a, b): its corner words, their starting
+// list indices, its corners, and, when (a, b) is also a cell column, its
+// candidate cells.  One packed scan: (candidates << 31) | corners.
 __global__ __launch_bounds__(kBlock) void k_corners(Grid g, Workspace ws, gh_counters* __restrict__ ctr) {
   const int n = g.n, n1 = n + 1;
   const size_t ncol = (size_t)n * n, nl = (size_t)n1 * n1;
   const int tile = acquire_tile(&ws.ticket[kTicketCorners]);
   const size_t L = (size_t)tile * kBlock + threadIdx.x;
   LatAdj A{{0, 0, 0, 0}, {0, 0, 0, 0}, 0};
-  uint64_t cnt = 0;
+  int a = 0, b = 0;
+  uint64_t ncorner = 0, ncand = 0, own = 0;
+  size_t own_col = 0;
   if (L < nl) {
-    A = lat_adjacent(n, (int)(L / n1), (int)(L % n1), ws.colmask);
-    for_corner_words(A, [&](int w) { cnt += __popc(corner_word(A, ws.colbits, ncol, w)); });
+    a = (int)(L / n1);
+    b = (int)(L % n1);
+    A = lat_adjacent(n, a, b, ws.colmask);
+    for_corner_words(A, [&](int w) { ncorner += __popc(corner_word(A, ws.colbits, ncol, w)); });
+    if (a < n && b < n) {  // cell column (a, b) is slot 3 of the adjacency
+      own = A.mask[3];
+      own_col = A.col[3];
+      for (uint64_t r = own; r; r &= r - 1) ncand += __popc(ws.colbits[(size_t)__builtin_ctzll(r) * ncol + own_col]);
+    }
   }
-  const ScanOut so = block_scan_lookback(cnt, scan_corners(ws), tile, &ctr->flags);
+  const ScanOut so = block_scan_lookback((ncand << 31) | ncorner, scan_corners(ws), tile, &ctr->flags);
+  const uint64_t c0 = so.excl & 0x7fffffffull, k0 = so.excl >> 31;
   if (L < nl) {
-    ws.lstart[L] = (int64_t)so.excl;
-    if (so.excl + cnt <= (uint64_t)ws.cap) {
-      int64_t o = (int64_t)so.excl;
+    uint64_t lm = 0;
+    uint32_t hi = 0;
+    if (c0 + ncorner <= (uint64_t)ws.cap) {
+      int64_t o = (int64_t)c0;
       for_corner_words(A, [&](int w) {
-        for (uint32_t b = corner_word(A, ws.colbits, ncol, w); b; b &= b - 1) {
-          ws.ck[o] = 32 * w + __builtin_ctz(b);
+        const uint32_t cw = corner_word(A, ws.colbits, ncol, w);
+        if (!cw) return;
+        if (w < 64) lm |= 1ull << w; else hi = 1u;
+        ws.lbits[(size_t)w * nl + L] = cw;
+        ws.lwst[(size_t)w * nl + L] = (int32_t)o;
+        for (uint32_t bb = cw; bb; bb &= bb - 1) {
+          ws.ck[o] = 32 * w + __builtin_ctz(bb);
           ws.cl[o] = (int32_t)L;
           ++o;
         }
       });
+      int64_t oc = (int64_t)k0;
+      for (uint64_t r = own; r; r &= r - 1) {
+        const int w = __builtin_ctzll(r);
+        for (uint32_t bb = ws.colbits[(size_t)w * ncol + own_col]; bb; bb &= bb - 1)
+          ws.cand[oc++] = (int64_t)own_col * n + 32 * w + __builtin_ctz(bb);
+      }
     }
+    ws.lmask[L] = lm;
+    ws.lmhi[L] = hi;
   }
   if (threadIdx.x == 0 && tile == (int)ws.tiles_lat - 1) {
-    ws.lstart[nl] = (int64_t)so.total;
-    ctr->n_corner = (int64_t)so.total;
-    if (so.total > (uint64_t)ws.cap) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+    const int64_t tc = (int64_t)(so.total & 0x7fffffffull), tk = (int64_t)(so.total >> 31);
+    ws.nlist[0] = tc;
+    ws.nlist[1] = tk;
+    ctr->n_corner = tc;
+    if (tc > ws.cap) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
   }
 }
 
 // Bound value at each corner point, one lane per corner.
 template <class Eval>
-__global__ __launch_bounds__(kBlock) void k_eval_corners(Eval ev, Grid g, Workspace ws,
-                                                         const gh_counters* __restrict__ ctr) {
-  const int64_t m = ctr->n_corner;
+__global__ __launch_bounds__(kBlock) void k_eval_corners(Eval ev, Grid g, Workspace ws) {
+  const int64_t m = ws.nlist[0];
   if (m > ws.cap) return;
   const int n1 = g.n + 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -326,112 +366,109 @@ __global__ __launch_bounds__(kBlock) void k_eval_corners(Eval ev, Grid g, Worksp
   }
 }
 
-// ------------------------------------------------------------------ vertices
-// Crossing edges owned by each corner (a, b, k): the x edge to (a+1, b, k),
-// the y edge to (a, b+1, k) and the z edge to (a, b, k+1), when both ends
-// are corners and their signs differ.  Merge-walks the sorted corner lists
-// of columns (a+1, b) and (a, b+1).
-struct VertWalk {
-  int64_t s0, e0, sx, ex, sy, ey;
-};
+// Persistent blocks take tiles of a list in ticket order until the list
+// (of `count` items) is exhausted; the single-pass scan stays deadlock-free
+// because a tile only waits on tiles already taken by running blocks.
+__device__ __forceinline__ int next_tile(unsigned int* ticket) {
+  __shared__ int s_next;
+  __syncthreads();
+  if (threadIdx.x == 0) s_next = (int)atomicAdd(ticket, 1u);
+  __syncthreads();
+  return s_next;
+}
 
-__device__ __forceinline__ unsigned cross_mask(const Workspace& ws, int64_t i, const VertWalk& V, int64_t& px,
-                                               int64_t& py) {
-  const int k = ws.ck[i];
-  const bool neg = ws.cf[i] < 0.f;
-  unsigned m = 0;
-  while (px < V.ex && ws.ck[px] < k) ++px;
-  if (px < V.ex && ws.ck[px] == k && ((ws.cf[px] < 0.f) != neg)) m |= 1u;
-  while (py < V.ey && ws.ck[py] < k) ++py;
-  if (py < V.ey && ws.ck[py] == k && ((ws.cf[py] < 0.f) != neg)) m |= 2u;
-  if (i + 1 < V.e0 && ws.ck[i + 1] == k + 1 && ((ws.cf[i + 1] < 0.f) != neg)) m |= 4u;
-  return m;
+// ------------------------------------------------------------------ vertices
+// One thread per corner (a, b, k): the crossing edges it owns are the x edge
+// to (a+1, b, k), the y edge to (a, b+1, k) and the z edge to (a, b, k+1),
+// when the far end is a corner too and the signs differ.
+__device__ __forceinline__ unsigned cross_mask(const Workspace& ws, const Grid& g, size_t nl, int64_t ci, int64_t m,
+                                               int64_t& ix, int64_t& iy) {
+  const int n = g.n, n1 = n + 1;
+  const int L = ws.cl[ci], k = ws.ck[ci];
+  const int a = L / n1, b = L - a * n1;
+  const bool neg = ws.cf[ci] < 0.f;
+  unsigned msk = 0;
+  ix = a < n ? corner_index(ws, nl, (size_t)L + n1, k) : -1;
+  iy = b < n ? corner_index(ws, nl, (size_t)L + 1, k) : -1;
+  if (ix >= 0 && ((ws.cf[ix] < 0.f) != neg)) msk |= 1u;
+  if (iy >= 0 && ((ws.cf[iy] < 0.f) != neg)) msk |= 2u;
+  if (ci + 1 < m && ws.cl[ci + 1] == L && ws.ck[ci + 1] == k + 1 && ((ws.cf[ci + 1] < 0.f) != neg)) msk |= 4u;
+  return msk;
 }
 
 __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* __restrict__ verts,
                                                   int64_t* __restrict__ vert_edge, float* __restrict__ vert_t,
                                                   int64_t vert_cap, gh_counters* __restrict__ ctr) {
-  const int n = g.n, n1 = n + 1;
+  const int64_t m = ws.nlist[0];
+  if (m > ws.cap) return;  // uniform: the corners overflowed, nothing to do
+  const int n1 = g.n + 1;
   const size_t nl = (size_t)n1 * n1;
-  const int tile = acquire_tile(&ws.ticket[kTicketVerts]);
-  if (ctr->n_corner > ws.cap) return;  // uniform over the grid: no tile waits on this one
-  const size_t L = (size_t)tile * kBlock + threadIdx.x;
-  VertWalk V{0, 0, 0, 0, 0, 0};
-  int a = 0, b = 0;
-  uint64_t cnt = 0;
-  if (L < nl) {
-    a = (int)(L / n1);
-    b = (int)(L % n1);
-    V.s0 = ws.lstart[L];
-    V.e0 = ws.lstart[L + 1];
-    if (a < n) {
-      V.sx = ws.lstart[L + n1];
-      V.ex = ws.lstart[L + n1 + 1];
-    }
-    if (b < n) {
-      V.sy = ws.lstart[L + 1];
-      V.ey = ws.lstart[L + 2];
-    }
-    int64_t px = V.sx, py = V.sy;
-    for (int64_t i = V.s0; i < V.e0; ++i) cnt += __popc(cross_mask(ws, i, V, px, py));
-  }
-  const ScanOut so = block_scan_lookback(cnt, scan_verts(ws), tile, &ctr->flags);
-  if (L < nl && V.e0 > V.s0) {
-    const bool room = so.excl + cnt <= (uint64_t)vert_cap;
-    int64_t v = (int64_t)so.excl;
-    int64_t px = V.sx, py = V.sy;
-    const float xa = lattice(g, a), ya = lattice(g, b);
-    for (int64_t i = V.s0; i < V.e0; ++i) {
-      const unsigned m = cross_mask(ws, i, V, px, py);
-      ws.cinfo[i] = (v << 3) | (int64_t)m;
-      if (!m || !room) {
-        v += __popc(m);
-        continue;
-      }
-      const int k = ws.ck[i];
-      const float fa = ws.cf[i], za = lattice(g, k);
-      const int64_t pid = ((int64_t)L * n1 + k) * 3;
-      for (int axis = 0; axis < 3; ++axis) {
-        if (!((m >> axis) & 1)) continue;
-        const float fb = axis == 0 ? ws.cf[px] : (axis == 1 ? ws.cf[py] : ws.cf[i + 1]);
-        const float t = fa / (fa - fb);
-        float px3 = xa, py3 = ya, pz3 = za;
-        if (axis == 0) px3 = xa + t * g.h;
-        if (axis == 1) py3 = ya + t * g.h;
-        if (axis == 2) pz3 = za + t * g.h;
-        verts[3 * v + 0] = px3;
-        verts[3 * v + 1] = py3;
-        verts[3 * v + 2] = pz3;
-        if (vert_edge) vert_edge[v] = pid + axis;
-        if (vert_t) vert_t[v] = t;
-        ++v;
+  const int ntiles = (int)((m + kBlock - 1) / kBlock);
+  if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) ctr->n_vert = 0;
+  for (;;) {
+    const int tile = next_tile(&ws.ticket[kTicketVerts]);
+    if (tile >= ntiles) break;
+    const int64_t ci = (int64_t)tile * kBlock + threadIdx.x;
+    unsigned msk = 0;
+    int64_t ix = -1, iy = -1;
+    if (ci < m) msk = cross_mask(ws, g, nl, ci, m, ix, iy);
+    const ScanOut so = block_scan_lookback(__popc(msk), scan_verts(ws), tile, &ctr->flags);
+    if (ci < m) {
+      const int64_t v0 = (int64_t)so.excl;
+      ws.cinfo[ci] = (v0 << 3) | (int64_t)msk;
+      if (msk && v0 + __popc(msk) <= vert_cap) {
+        const int L = ws.cl[ci], k = ws.ck[ci];
+        const int a = L / n1, b = L - a * n1;
+        const float fa = ws.cf[ci];
+        const float xa = lattice(g, a), ya = lattice(g, b), za = lattice(g, k);
+        const int64_t pid = ((int64_t)L * n1 + k) * 3;
+        int64_t v = v0;
+#pragma unroll
+        for (int axis = 0; axis < 3; ++axis) {
+          if (!((msk >> axis) & 1)) continue;
+          const int64_t far = axis == 0 ? ix : (axis == 1 ? iy : ci + 1);
+          const float fb = ws.cf[far];
+          const float t = fa / (fa - fb);
+          verts[3 * v + 0] = axis == 0 ? xa + t * g.h : xa;
+          verts[3 * v + 1] = axis == 1 ? ya + t * g.h : ya;
+          verts[3 * v + 2] = axis == 2 ? za + t * g.h : za;
+          if (vert_edge) vert_edge[v] = pid + axis;
+          if (vert_t) vert_t[v] = t;
+          ++v;
+        }
       }
     }
-  }
-  if (threadIdx.x == 0 && tile == (int)ws.tiles_lat - 1) {
-    ctr->n_vert = (int64_t)so.total;
-    if (so.total > (uint64_t)vert_cap) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+    if (threadIdx.x == 0 && tile == ntiles - 1) {
+      ctr->n_vert = (int64_t)so.total;
+      if (so.total > (uint64_t)vert_cap) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+    }
   }
 }
 
 // ----------------------------------------------------------------- triangles
-// Per candidate cell: the eight corner indices from four merge pointers into
-// the corner lists of lattice columns (i+dx, j+dy), the case byte, and the
-// table's triangles; each triangle vertex is the welded vertex of the cell
-// edge, found at the edge's lower corner.
-struct CellWalk {
-  int64_t p[4];  // corner index of k in lattice column (i+dx, j+dy), slot dx + 2 dy
-  int64_t e[4];  // end of that column's corner list
+// One thread per candidate cell (i, j, k): list indices of its corners in
+// the four lattice columns (i+dx, j+dy) (the corner at k+1 follows the one
+// at k in the list), the case byte, and the table's triangles; each triangle
+// vertex is the welded vertex of the cell edge, found at its lower corner.
+struct CellCorners {
+  int64_t p[4];  // list index of corner (i+dx, j+dy, k), slot dx + 2 dy
 };
 
-// Case byte of cell k; false when a corner is missing from the lists, which
-// consistent workspace contents never produce (the caller then flags it).
-__device__ __forceinline__ bool cell_case(const Workspace& ws, int k, CellWalk& C, unsigned& cs) {
+__device__ __forceinline__ bool cell_corners(const Workspace& ws, int n, size_t nl, int64_t cell, CellCorners& C,
+                                             unsigned& cs, int& k) {
+  const int n1 = n + 1;
+  const int64_t col = cell / n;
+  k = (int)(cell - col * n);
+  const int i = (int)(col / n), j = (int)(col - (int64_t)i * n);
+  const size_t L = (size_t)i * n1 + j;
+  C.p[0] = corner_index(ws, nl, L, k);
+  C.p[1] = corner_index(ws, nl, L + n1, k);
+  C.p[2] = corner_index(ws, nl, L + 1, k);
+  C.p[3] = corner_index(ws, nl, L + n1 + 1, k);
   cs = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    while (C.p[q] < C.e[q] && ws.ck[C.p[q]] < k) ++C.p[q];
-    if (C.p[q] + 1 >= C.e[q] || ws.ck[C.p[q]] != k || ws.ck[C.p[q] + 1] != k + 1) return false;
+    if (C.p[q] < 0) return false;
     cs |= (unsigned)(ws.cf[C.p[q]] < 0.f) << q;
     cs |= (unsigned)(ws.cf[C.p[q] + 1] < 0.f) << (q + 4);
   }
@@ -445,93 +482,61 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
   __shared__ McCase s_mc[256];
   s_mc[threadIdx.x] = g_mc.c[threadIdx.x];
   __syncthreads();
-  const int n = g.n, n1 = n + 1;
-  const size_t ncol = (size_t)n * n;
-  const int tile = acquire_tile(&ws.ticket[kTicketTris]);
-  if (ctr->n_corner > ws.cap) return;
-  const size_t col = (size_t)tile * kBlock + threadIdx.x;
-  uint64_t m = 0;
-  int i = 0, j = 0;
-  CellWalk C0{{0, 0, 0, 0}, {0, 0, 0, 0}};
-  bool broken = false;
-  uint64_t ntri = 0, ncell = 0;
-  if (col < ncol) {
-    i = (int)(col / n);
-    j = (int)(col % n);
-    m = ws.colmask[col];
-    if (m) {
-      const size_t L = (size_t)i * n1 + j;
-      C0.p[0] = ws.lstart[L];
-      C0.p[1] = ws.lstart[L + n1];
-      C0.p[2] = ws.lstart[L + 1];
-      C0.p[3] = ws.lstart[L + n1 + 1];
-      C0.e[0] = ws.lstart[L + 1];
-      C0.e[1] = ws.lstart[L + n1 + 1];
-      C0.e[2] = ws.lstart[L + 2];
-      C0.e[3] = ws.lstart[L + n1 + 2];
-      CellWalk C = C0;
-      for (uint64_t r = m; r; r &= r - 1) {
-        const int w = __builtin_ctzll(r);
-        for (uint32_t bits = ws.colbits[(size_t)w * ncol + col]; bits; bits &= bits - 1) {
-          const int k = 32 * w + __builtin_ctz(bits);
-          unsigned cs;
-          if (!cell_case(ws, k, C, cs)) {
-            broken = true;
-            continue;
-          }
-          const unsigned nt = s_mc[cs].ntri;
-          ntri += nt;
-          ncell += nt ? 1 : 0;
-        }
-      }
-    }
-  }
-  // (cells << 31) | triangles: both stay below 2^31 for any mesh the outputs can index
-  const ScanOut so = block_scan_lookback((ncell << 31) | ntri, scan_tris(ws), tile, &ctr->flags);
+  if (ws.nlist[0] > ws.cap) return;
+  const int64_t m = ws.nlist[1];
+  const int n = g.n;
+  const size_t nl = (size_t)(n + 1) * (n + 1);
   const bool verts_ok = ctr->n_vert <= vert_cap;
-  if (col < ncol && m && verts_ok) {
-    int64_t t = (int64_t)(so.excl & 0x7fffffffull);
-    int64_t c = (int64_t)(so.excl >> 31);
-    const bool room_t = t + (int64_t)ntri <= tri_cap;
-    const bool room_c = c + (int64_t)ncell <= cell_cap;
-    CellWalk C = C0;
-    for (uint64_t r = m; r; r &= r - 1) {
-      const int w = __builtin_ctzll(r);
-      for (uint32_t bits = ws.colbits[(size_t)w * ncol + col]; bits; bits &= bits - 1) {
-        const int k = 32 * w + __builtin_ctz(bits);
-        unsigned cs;
-        if (!cell_case(ws, k, C, cs)) continue;
+  const int ntiles = (int)((m + kBlock - 1) / kBlock);
+  if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    ctr->n_tri = 0;
+    ctr->n_cells = 0;
+  }
+  bool broken = false;
+  for (;;) {
+    const int tile = next_tile(&ws.ticket[kTicketTris]);
+    if (tile >= ntiles) break;
+    const int64_t q = (int64_t)tile * kBlock + threadIdx.x;
+    CellCorners C{{0, 0, 0, 0}};
+    unsigned cs = 0, nt = 0;
+    int k = 0;
+    int64_t cell = 0;
+    if (q < m) {
+      cell = ws.cand[q];
+      if (cell_corners(ws, n, nl, cell, C, cs, k)) nt = s_mc[cs].ntri;
+      else broken = true;
+    }
+    // (cells << 31) | triangles: both stay below 2^31 for any mesh the outputs can index
+    const ScanOut so = block_scan_lookback(((uint64_t)(nt ? 1 : 0) << 31) | nt, scan_tris(ws), tile, &ctr->flags);
+    if (nt && verts_ok) {
+      const int64_t t0 = (int64_t)(so.excl & 0x7fffffffull), c = (int64_t)(so.excl >> 31);
+      if (c < cell_cap) {
+        if (cells) cells[c] = cell;
+        if (cases) cases[c] = (uint8_t)cs;
+      }
+      if (t0 + (int64_t)nt <= tri_cap) {
         const McCase mcc = s_mc[cs];
-        if (!mcc.ntri) continue;
-        if (room_c) {
-          if (cells) cells[c] = (int64_t)col * n + k;
-          if (cases) cases[c] = (uint8_t)cs;
-        }
-        ++c;
-        if (!room_t) continue;
-        for (unsigned q = 0; q < mcc.ntri; ++q) {
+        for (unsigned tq = 0; tq < nt; ++tq) {
 #pragma unroll
           for (int v = 0; v < 3; ++v) {
-            const int e = (int)((mcc.tri >> (12 * q + 4 * v)) & 15);
+            const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
             const int lc = mc_edge_lower(e), axis = e >> 2;
             const int slot = (lc & 1) + 2 * ((lc >> 1) & 1);
             const int64_t base = slot == 0 ? C.p[0] : (slot == 1 ? C.p[1] : (slot == 2 ? C.p[2] : C.p[3]));
-            const int64_t gi = base + (lc >> 2);
-            const int64_t info = ws.cinfo[gi];
-            tris[3 * t + v] = (int32_t)((info >> 3) + __popc((unsigned)(info & 7) & ((1u << axis) - 1u)));
+            const int64_t info = ws.cinfo[base + (lc >> 2)];
+            tris[3 * (t0 + tq) + v] = (int32_t)((info >> 3) + __popc((unsigned)(info & 7) & ((1u << axis) - 1u)));
           }
-          ++t;
         }
       }
     }
+    if (threadIdx.x == 0 && tile == ntiles - 1) {
+      const int64_t tt = (int64_t)(so.total & 0x7fffffffull), tc = (int64_t)(so.total >> 31);
+      ctr->n_tri = tt;
+      ctr->n_cells = tc;
+      if (tt > tri_cap || ((cells || cases) && tc > cell_cap)) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+    }
   }
   if (broken) atomicOr(&ctr->flags, GH_FLAG_INTERNAL);
-  if (threadIdx.x == 0 && tile == (int)ws.tiles_col - 1) {
-    const int64_t tt = (int64_t)(so.total & 0x7fffffffull), tc = (int64_t)(so.total >> 31);
-    ctr->n_tri = tt;
-    ctr->n_cells = tc;
-    if (tt > tri_cap || (cells && tc > cell_cap) || (cases && tc > cell_cap)) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
-  }
 }
 
 // Bound at arbitrary points.
@@ -611,13 +616,13 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
                      float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap, int64_t* cells,
                      uint8_t* cases, int64_t cell_cap, gh_counters* ctr, hipStream_t s) {
   if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
+  const int lists = (int)(ws.tiles_cap < 1024 ? (ws.tiles_cap < 1 ? 1 : ws.tiles_cap) : 1024);
   hipLaunchKernelGGL(k_corners, dim3((unsigned)ws.tiles_lat), dim3(kBlock), 0, s, g, ws, ctr);
   hipLaunchKernelGGL(k_eval_corners<PrimsEval>, dim3(persistent_blocks(ws.cap)), dim3(kBlock), 0, s,
-                     PrimsEval{d.prims, d.groups}, g, ws, ctr);
-  hipLaunchKernelGGL(k_verts, dim3((unsigned)ws.tiles_lat), dim3(kBlock), 0, s, g, ws, verts, vert_edge, vert_t,
-                     vert_cap, ctr);
-  hipLaunchKernelGGL(k_tris, dim3((unsigned)ws.tiles_col), dim3(kBlock), 0, s, g, ws, tris, tri_cap, cells, cases,
-                     cell_cap, vert_cap, ctr);
+                     PrimsEval{d.prims, d.groups}, g, ws);
+  hipLaunchKernelGGL(k_verts, dim3(lists), dim3(kBlock), 0, s, g, ws, verts, vert_edge, vert_t, vert_cap, ctr);
+  hipLaunchKernelGGL(k_tris, dim3(lists), dim3(kBlock), 0, s, g, ws, tris, tri_cap, cells, cases, cell_cap, vert_cap,
+                     ctr);
   return hipGetLastError();
 }
 

@@ -2,9 +2,11 @@
 //
 // Candidate cells are kept per ray column as a bitmap over k (the hop writes
 // only the non-zero 32-bit words and a 64-bit mask saying which words exist),
-// so nothing has to be cleared between runs.  Corner points are stored per
-// lattice column (a, b) in CSR form sorted by k; each corner carries its
-// bound value and the index of its first welded vertex.
+// so nothing has to be cleared between runs.  Corner points are listed by
+// lattice column (a, b), then k; per lattice column a word bitmap over k with
+// the list index of each word's first corner gives any corner's list index
+// in O(1).  Each corner carries its bound value and the index of its first
+// welded vertex.
 #pragma once
 
 #include <stddef.h>
@@ -19,16 +21,23 @@ namespace gh {
 struct Workspace {
   uint64_t* colmask;   // [n*n] bit w set when word w of the column bitmap was written
   uint32_t* colbits;   // [W][n*n] candidate bitmap words, word-major (W = ceil(n/32))
-  int64_t* lstart;     // [(n+1)^2 + 1] first corner of each lattice column
-  int32_t* ck;         // [cap] k of each corner
+  uint64_t* lmask;     // [(n+1)^2] bit w set when corner word w of lattice column L exists (w < 64)
+  uint32_t* lmhi;      // [(n+1)^2] bit 0: corner word 64 exists (n = 2048 only)
+  uint32_t* lbits;     // [W1][(n+1)^2] corner words (k bits), written where non-zero (W1 = ceil((n+1)/32))
+  int32_t* lwst;       // [W1][(n+1)^2] index of the first corner of that word in the corner list
+  int32_t* ck;         // [cap] k of each corner (list ordered by lattice column, then k)
   int32_t* cl;         // [cap] lattice column a*(n+1) + b of each corner
   float* cf;           // [cap] bound value at the corner
   int64_t* cinfo;      // [cap] (first vertex index << 3) | crossing mask (x=1, y=2, z=4)
-  uint64_t* scan;      // look-back words: corners, vertices, triangles, candidates
+  int64_t* cand;       // [cap] candidate cell ids in ascending order (never more than the corners)
+  int64_t* nlist;      // [2] corners, candidates in the lists
+  uint64_t* scan;      // look-back words: corners, vertices, triangles, candidates export
   unsigned int* ticket;// [8] tile tickets (one per scan) and spare
   int64_t cap;         // corner capacity
   int64_t tiles_lat;   // tiles over lattice columns
   int64_t tiles_col;   // tiles over cell columns
+  int64_t tiles_cap;   // tiles over a list of cap items
+  int words1;          // W1
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -36,9 +45,10 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Computes the layout; with base == nullptr only the size is produced.
 inline size_t workspace_layout(int n, int64_t cap, void* base, Workspace* ws) {
   const size_t n2 = (size_t)n * n, n1 = (size_t)n + 1, nl = n1 * n1;
-  const size_t words = ((size_t)n + 31) / 32;
+  const size_t words = ((size_t)n + 31) / 32, words1 = ((size_t)n + 32) / 32;
   const int64_t tiles_lat = (int64_t)((nl + 255) / 256);
   const int64_t tiles_col = (int64_t)((n2 + 255) / 256);
+  const int64_t tiles_cap = (int64_t)(((size_t)cap + 255) / 256);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -47,28 +57,40 @@ inline size_t workspace_layout(int n, int64_t cap, void* base, Workspace* ws) {
   };
   const size_t o_mask = take(n2 * 8);
   const size_t o_bits = take(words * n2 * 4);
-  const size_t o_lstart = take((nl + 1) * 8);
+  const size_t o_lmask = take(nl * 8);
+  const size_t o_lmhi = take(nl * 4);
+  const size_t o_lbits = take(words1 * nl * 4);
+  const size_t o_lwst = take(words1 * nl * 4);
   const size_t o_ck = take((size_t)cap * 4);
   const size_t o_cl = take((size_t)cap * 4);
   const size_t o_cf = take((size_t)cap * 4);
   const size_t o_ci = take((size_t)cap * 8);
-  const size_t scan_words = (size_t)(2 * tiles_lat + 2 * tiles_col);
+  const size_t o_cand = take((size_t)cap * 8);
+  const size_t o_nlist = take(2 * 8);
+  const size_t scan_words = (size_t)(tiles_lat + 2 * tiles_cap + tiles_col);
   const size_t o_scan = take(scan_words * 8);
   const size_t o_ticket = take(8 * sizeof(unsigned int));
   if (base && ws) {
     char* b = (char*)base;
     ws->colmask = (uint64_t*)(b + o_mask);
     ws->colbits = (uint32_t*)(b + o_bits);
-    ws->lstart = (int64_t*)(b + o_lstart);
+    ws->lmask = (uint64_t*)(b + o_lmask);
+    ws->lmhi = (uint32_t*)(b + o_lmhi);
+    ws->lbits = (uint32_t*)(b + o_lbits);
+    ws->lwst = (int32_t*)(b + o_lwst);
     ws->ck = (int32_t*)(b + o_ck);
     ws->cl = (int32_t*)(b + o_cl);
     ws->cf = (float*)(b + o_cf);
     ws->cinfo = (int64_t*)(b + o_ci);
+    ws->cand = (int64_t*)(b + o_cand);
+    ws->nlist = (int64_t*)(b + o_nlist);
     ws->scan = (uint64_t*)(b + o_scan);
     ws->ticket = (unsigned int*)(b + o_ticket);
     ws->cap = cap;
     ws->tiles_lat = tiles_lat;
     ws->tiles_col = tiles_col;
+    ws->tiles_cap = tiles_cap;
+    ws->words1 = (int)words1;
   }
   return off;
 }
@@ -76,9 +98,11 @@ inline size_t workspace_layout(int n, int64_t cap, void* base, Workspace* ws) {
 // Offsets of the four look-back arrays inside Workspace::scan.
 __host__ __device__ inline uint64_t* scan_corners(const Workspace& w) { return w.scan; }
 __host__ __device__ inline uint64_t* scan_verts(const Workspace& w) { return w.scan + w.tiles_lat; }
-__host__ __device__ inline uint64_t* scan_tris(const Workspace& w) { return w.scan + 2 * w.tiles_lat; }
-__host__ __device__ inline uint64_t* scan_cands(const Workspace& w) { return w.scan + 2 * w.tiles_lat + w.tiles_col; }
-inline size_t scan_words(const Workspace& w) { return (size_t)(2 * w.tiles_lat + 2 * w.tiles_col); }
+__host__ __device__ inline uint64_t* scan_tris(const Workspace& w) { return w.scan + w.tiles_lat + w.tiles_cap; }
+__host__ __device__ inline uint64_t* scan_cands(const Workspace& w) {
+  return w.scan + w.tiles_lat + 2 * w.tiles_cap;
+}
+inline size_t scan_words(const Workspace& w) { return (size_t)(w.tiles_lat + 2 * w.tiles_cap + w.tiles_col); }
 
 enum { kTicketCorners = 0, kTicketVerts = 1, kTicketTris = 2, kTicketCands = 3 };
 
