@@ -159,12 +159,17 @@ gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size
                 int32_t* tris, int64_t tri_cap, int64_t* cells, uint8_t* cases, int64_t cell_cap,
                 gh_counters* ctr, void* stream);
 
-/* Enumeration baseline (Section 2): evaluates f at every lattice point into
- * dense (device, (n+1)^3 float32, layout [c][a][b]), records every
- * sign-change cell in ws as the candidate set and resets *ctr.  gh_mc then
- * polygonizes exactly as after gh_hop. */
+/* Enumeration baseline (Section 2): evaluates f at every lattice point,
+ * keeps only the signs in `signs` (device, gh_dense_signs_size bytes,
+ * layout [w][a*(n+1) + b], bit c%32 of word w = c/32 set when
+ * f(P(a, b, c)) < 0), records every sign-change cell in ws as the candidate
+ * set and resets *ctr (n_hop_evals = (n+1)^3).  gh_mc then polygonizes
+ * exactly as after gh_hop. */
 gh_status gh_dense(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
-                   int64_t corner_cap, float* dense, gh_counters* ctr, void* stream);
+                   int64_t corner_cap, uint32_t* signs, gh_counters* ctr, void* stream);
+
+/* Bytes of the sign buffer of gh_dense: ceil((n+1)/32) * (n+1)^2 * 4. */
+gh_status gh_dense_signs_size(const gh_grid* grid_h, size_t* bytes_h);
 
 /* Export the candidate cells recorded in ws as ascending int64 cell ids into
  * out[cap]; the count is n_cand of *ctr.  Sets GH_FLAG_CAPACITY if cap is

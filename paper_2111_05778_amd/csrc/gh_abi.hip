@@ -155,6 +155,16 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
   return GH_OK;
 }
 
+gh_status gh_dense_signs_size(const gh_grid* grid_h, size_t* bytes_h) {
+  gh::Grid g;
+  gh_status st = read_grid(grid_h, &g);
+  if (st != GH_OK) return st;
+  if (!bytes_h) return fail(GH_EINVAL, "bytes_h is NULL");
+  const size_t n1 = (size_t)g.n + 1;
+  *bytes_h = ((size_t)g.n + 32) / 32 * n1 * n1 * sizeof(uint32_t);
+  return GH_OK;
+}
+
 gh_status gh_workspace_size(const gh_grid* grid_h, int64_t corner_cap, size_t* bytes_h) {
   gh::Grid g;
   gh_status st = read_grid(grid_h, &g);
@@ -182,7 +192,7 @@ gh_status gh_hop(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, siz
 }
 
 gh_status gh_dense(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
-                   float* dense, gh_counters* ctr, void* stream) {
+                   uint32_t* signs, gh_counters* ctr, void* stream) {
   gh::DevSdb d;
   gh::Grid g;
   gh::Workspace w;
@@ -190,10 +200,10 @@ gh_status gh_dense(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, s
   if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
   if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
   if ((st = carve(g, ws, ws_bytes, corner_cap, &w)) != GH_OK) return st;
-  if (!ctr || !dense) return fail(GH_EINVAL, "counters or dense buffer is NULL");
+  if (!ctr || !signs) return fail(GH_EINVAL, "counters or sign buffer is NULL");
   hipStream_t s = (hipStream_t)stream;
   if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearAll, s), "clear")) != GH_OK) return st;
-  return hip_status(gh::launch_dense(d, g, w, dense, ctr, s), "dense");
+  return hip_status(gh::launch_dense(d, g, w, signs, ctr, s), "dense");
 }
 
 gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,

@@ -149,41 +149,40 @@ __device__ __forceinline__ void block_add_u64(uint64_t v, unsigned long long* ds
 }
 
 // ------------------------------------------------ single-pass block scan
-// Tiles are taken in ticket order (an atomic counter), so a tile only ever
-// waits on tiles that started before it: the scan cannot deadlock.  Each
-// tile publishes one 64-bit word per state change: status in the top two
+// A tile publishes one 64-bit word per state change: status in the top two
 // bits (1 = own aggregate, 2 = inclusive prefix), value in the low 62 bits.
+// Tiles are taken in increasing order by block-strided loops over a grid of
+// co-resident blocks, so every tile a block waits on is being processed.
 constexpr uint64_t kScanAgg = 1ull << 62;
 constexpr uint64_t kScanPrefix = 2ull << 62;
 constexpr uint64_t kScanValMask = (1ull << 62) - 1;
-
-__device__ __forceinline__ int acquire_tile(unsigned int* ticket) {
-  __shared__ int s_tile;
-  if (threadIdx.x == 0) s_tile = (int)atomicAdd(ticket, 1u);
-  __syncthreads();
-  return s_tile;
-}
 
 struct ScanOut {
   uint64_t excl;   // exclusive prefix of this thread over the whole grid
   uint64_t total;  // inclusive prefix at the end of this tile
 };
 
-// Wave 0 of the tile does the look-back, 64 predecessors per round: lane m
-// reads the word of tile base - m.  The closest predecessor holding an
-// inclusive prefix ends the walk; until it is found, every word in between
-// must at least hold its aggregate.  Tiles before 0 read as prefix 0.
-// The wait is bounded: should it exceed kSpinLimit rounds (only possible
-// through a library bug), *err gets GH_FLAG_INTERNAL and the tile carries on
-// with a partial prefix; every write stays inside its capacity check, so the
-// result is flagged rather than the device hung.
+// The whole block does the look-back, kBlock * 4 predecessors per round:
+// thread t reads the words of tiles base - 4t - r, r = 0..3 (distance 0 is
+// the closest).  The closest predecessor holding an inclusive prefix ends
+// the walk; every word before it must at least hold its aggregate, else the
+// round is retried.  Tiles before 0 read as prefix 0.  All tiles of a kernel
+// start at about the same time, so one wide round replaces a long chain of
+// narrow ones.  The wait is bounded: should it exceed kSpinLimit rounds
+// (only possible through a library bug), *err gets GH_FLAG_INTERNAL and the
+// tile carries on with a partial prefix; every write stays inside its
+// capacity check, so the result is flagged rather than the device hung.
 constexpr int kSpinLimit = 1 << 22;
+constexpr int kLookWindow = kBlock * 4;
 
 __device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* flags, int tile, unsigned int* err) {
   __shared__ uint64_t s_wave[kBlock / 64];
+  __shared__ uint64_t s_sum[kBlock / 64];
+  __shared__ int s_first, s_empty;
   __shared__ uint64_t s_prev;
   const uint64_t incl = wave_incl_scan_u64(v);
   if (lane_id() == 63) s_wave[wave_id()] = incl;
+  if (threadIdx.x == 0) s_prev = 0;
   __syncthreads();
   uint64_t wave_off = 0, agg = 0;
 #pragma unroll
@@ -192,43 +191,67 @@ __device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* fla
     if (w < wave_id()) wave_off += s;
     agg += s;
   }
-  if (wave_id() == 0) {
-    const int l = lane_id();
-    uint64_t prev = 0;
-    if (tile == 0) {
-      if (l == 0)
-        __hip_atomic_store(&flags[0], kScanPrefix | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      if (l == 0)
-        __hip_atomic_store(&flags[tile], kScanAgg | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int base = tile - 1;
-      int spins = 0;
-      while (true) {
-        const int j = base - l;
-        const uint64_t f =
-            j >= 0 ? __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanPrefix;
-        const uint64_t st = f & ~kScanValMask;
-        const uint64_t pre = __ballot(st == kScanPrefix);
-        const uint64_t empty = __ballot(st == 0);
-        const int first = pre ? __builtin_ctzll(pre) : 64;
-        const uint64_t need = first == 64 ? ~0ull : ((2ull << first) - 1ull);  // lanes 0..first
-        if (empty & need) {
-          if (++spins > kSpinLimit) {
-            if (l == 0) atomicOr(err, GH_FLAG_INTERNAL);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        prev += wave_sum_u64(l <= first ? (f & kScanValMask) : 0ull);
-        if (first < 64) break;
-        base -= 64;
+  if (tile == 0) {
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&flags[0], kScanPrefix | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&flags[tile], kScanAgg | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int base = tile - 1;
+    int spins = 0;
+    while (true) {
+      uint64_t f[4];
+      int first = kLookWindow;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 4 * (int)threadIdx.x + r;
+        const int j = base - pos;
+        f[r] = j >= 0 ? __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanPrefix;
+        if ((f[r] & ~kScanValMask) == kScanPrefix && pos < first) first = pos;
       }
-      if (l == 0)
-        __hip_atomic_store(&flags[tile], kScanPrefix | ((prev + agg) & kScanValMask), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x == 0) {
+        s_first = kLookWindow;
+        s_empty = 0;
+      }
+      __syncthreads();
+      if (first < kLookWindow) atomicMin(&s_first, first);
+      __syncthreads();
+      first = s_first;
+      uint64_t part = 0;
+      bool empty = false;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 4 * (int)threadIdx.x + r;
+        if (pos > first) continue;
+        if ((f[r] & ~kScanValMask) == 0) empty = true;
+        part += f[r] & kScanValMask;
+      }
+      if (empty) s_empty = 1;
+      part = wave_sum_u64(part);
+      if (lane_id() == 0) s_sum[wave_id()] = part;
+      __syncthreads();
+      const bool retry = s_empty != 0;
+      if (retry) {
+        if (++spins > kSpinLimit) {
+          if (threadIdx.x == 0) atomicOr(err, GH_FLAG_INTERNAL);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        __syncthreads();
+        continue;
+      }
+      if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += s_sum[w];
+        s_prev += t;
+      }
+      __syncthreads();
+      if (first < kLookWindow) break;
+      base -= kLookWindow;
     }
-    if (l == 0) s_prev = prev;
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&flags[tile], kScanPrefix | ((s_prev + agg) & kScanValMask), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   ScanOut o;

@@ -139,66 +139,83 @@ __global__ __launch_bounds__(kBlock) void k_hop_prims(const float* __restrict__ 
 }
 
 // ------------------------------------------------------------ enumeration
-// Bound at every lattice point, layout [c][a][b] (b fastest); also clears the
+// Bound at every lattice point (Section 2, enumeration).  Classifying cells
+// needs only the signs, so each wave evaluates 64 consecutive points c of
+// one lattice column L and ballots them into two sign words of
+// signs[W1][(n+1)^2] (bit set: f < 0).  Marching cubes re-evaluates the
+// corners of the cells it keeps, exactly as after a hop.  Also clears the
 // column masks that k_dense_classify sets.
 template <class Eval>
-__global__ __launch_bounds__(kBlock) void k_dense_eval(Eval ev, Grid g, float* __restrict__ dense,
-                                                       uint64_t* __restrict__ colmask) {
+__global__ __launch_bounds__(kBlock) void k_dense_eval(Eval ev, Grid g, uint32_t* __restrict__ signs,
+                                                       uint64_t* __restrict__ colmask,
+                                                       gh_counters* __restrict__ ctr) {
   const int n1 = g.n + 1;
-  const size_t total = (size_t)n1 * n1 * n1, ncol = (size_t)g.n * g.n;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t nl = (size_t)n1 * n1, ncol = (size_t)g.n * g.n;
+  const int chunks = (n1 + 63) / 64, words1 = (g.n + 32) / 32;
+  const size_t waves = nl * chunks;
+  const size_t wstride = (size_t)gridDim.x * (kBlock / 64);
   const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (size_t c = t0; c < ncol; c += stride) colmask[c] = 0;
-  for (size_t idx = t0; idx < total; idx += stride) {
-    const int b = (int)(idx % n1);
-    const size_t r = idx / n1;
-    const int a = (int)(r % n1), c = (int)(r / n1);
-    dense[idx] = ev(lattice(g, a), lattice(g, b), lattice(g, c));
+  for (size_t c = t0; c < ncol; c += (size_t)gridDim.x * blockDim.x) colmask[c] = 0;
+  bool bad = false;
+  for (size_t wv = (size_t)blockIdx.x * (kBlock / 64) + wave_id(); wv < waves; wv += wstride) {
+    const size_t L = wv % nl;
+    const int chunk = (int)(wv / nl);
+    const int a = (int)(L / n1), b = (int)(L % n1);
+    const int c = 64 * chunk + lane_id();
+    bool neg = false;
+    if (c < n1) {
+      const float f = ev(lattice(g, a), lattice(g, b), lattice(g, c));
+      neg = f < 0.f;
+      bad |= !(fabsf(f) <= FLT_MAX);
+    }
+    const uint64_t m = __ballot(neg);
+    if (lane_id() == 0) {
+      signs[(size_t)(2 * chunk) * nl + L] = (uint32_t)m;
+      if (2 * chunk + 1 < words1) signs[(size_t)(2 * chunk + 1) * nl + L] = (uint32_t)(m >> 32);
+    }
   }
+  if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr->n_hop_evals = (int64_t)n1 * n1 * n1;
 }
 
 // Every cell whose eight corners do not share one side becomes a candidate.
-// One thread builds one 32-cell word of one column: lanes run over adjacent
-// columns, so each lattice plane is read in coalesced rows.
-__global__ __launch_bounds__(kBlock) void k_dense_classify(Grid g, const float* __restrict__ dense,
+// One thread builds one 32-cell word of one column from the sign words of
+// its four lattice columns: cell k mixes signs when the OR over its corners
+// (bits k and k+1 of each column) differs from their AND.
+__global__ __launch_bounds__(kBlock) void k_dense_classify(Grid g, const uint32_t* __restrict__ signs,
                                                            uint64_t* __restrict__ colmask,
                                                            uint32_t* __restrict__ colbits,
                                                            gh_counters* __restrict__ ctr) {
   const int n = g.n, n1 = n + 1;
-  const size_t ncol = (size_t)n * n;
-  const int words = (n + 31) >> 5;
+  const size_t ncol = (size_t)n * n, nl = (size_t)n1 * n1;
+  const int words = (n + 31) >> 5, words1 = (n + 32) >> 5;
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t col = tid % ncol;
   const int w = (int)(tid / ncol);
   uint64_t cands = 0;
-  bool bad = false;
   if (w < words) {
     const int i = (int)(col / n), j = (int)(col % n);
-    const size_t plane = (size_t)n1 * n1;
-    const size_t o00 = (size_t)i * n1 + j, o10 = o00 + n1;
-    auto side4 = [&](size_t base) {
-      const float f0 = dense[base + o00], f1 = dense[base + o00 + 1], f2 = dense[base + o10], f3 = dense[base + o10 + 1];
-      bad |= !(fabsf(f0) <= FLT_MAX) | !(fabsf(f1) <= FLT_MAX) | !(fabsf(f2) <= FLT_MAX) | !(fabsf(f3) <= FLT_MAX);
-      return (unsigned)(f0 < 0.f) + (unsigned)(f1 < 0.f) + (unsigned)(f2 < 0.f) + (unsigned)(f3 < 0.f);
-    };
-    const int k0 = 32 * w, k1 = min(n, k0 + 32);
-    unsigned lowc = side4((size_t)k0 * plane);
-    uint32_t word = 0;
-    for (int k = k0; k < k1; ++k) {
-      const unsigned upc = side4((size_t)(k + 1) * plane);
-      const unsigned inside = lowc + upc;
-      if (inside != 0 && inside != 8) word |= 1u << (k - k0);
-      lowc = upc;
+    const size_t L = (size_t)i * n1 + j;
+    const size_t Ls[4] = {L, L + 1, L + n1, L + n1 + 1};
+    uint32_t o = 0, an = ~0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t cur = signs[(size_t)w * nl + Ls[q]];
+      const uint32_t nxt = w + 1 < words1 ? signs[(size_t)(w + 1) * nl + Ls[q]] : 0u;
+      const uint32_t up = (cur >> 1) | (nxt << 31);  // bit k: sign at k + 1
+      o |= cur | up;
+      an &= cur & up;
     }
+    uint32_t word = o & ~an;
+    const int valid = n - 32 * w;
+    if (valid < 32) word &= (1u << valid) - 1u;
     if (word) {
       colbits[(size_t)w * ncol + col] = word;
       atomicOr((unsigned long long*)&colmask[col], 1ull << w);
       cands = __popc(word);
     }
   }
-  if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
   block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctr->n_hop_evals = (int64_t)n1 * n1 * n1;
 }
 
 // -------------------------------------------------------- candidate export
@@ -206,7 +223,8 @@ __global__ __launch_bounds__(kBlock) void k_candidates(Grid g, Workspace ws, int
                                                       gh_counters* __restrict__ ctr) {
   const int n = g.n;
   const size_t ncol = (size_t)n * n;
-  const int tile = acquire_tile(&ws.ticket[kTicketCands]);
+  for (int tile = blockIdx.x; tile < (int)ws.tiles_col; tile += gridDim.x) {
+  __syncthreads();
   const size_t col = (size_t)tile * kBlock + threadIdx.x;
   uint64_t m = 0;
   uint64_t cnt = 0;
@@ -225,6 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_candidates(Grid g, Workspace ws, int
   }
   if (threadIdx.x == 0 && tile == (int)ws.tiles_col - 1 && so.total > (uint64_t)cap)
     atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+  }
 }
 
 // ------------------------------------------------------------------ corners
@@ -297,7 +316,8 @@ __device__ __forceinline__ int64_t corner_index(const Workspace& ws, size_t nl, 
 __global__ __launch_bounds__(kBlock) void k_corners(Grid g, Workspace ws, gh_counters* __restrict__ ctr) {
   const int n = g.n, n1 = n + 1;
   const size_t ncol = (size_t)n * n, nl = (size_t)n1 * n1;
-  const int tile = acquire_tile(&ws.ticket[kTicketCorners]);
+  for (int tile = blockIdx.x; tile < (int)ws.tiles_lat; tile += gridDim.x) {
+  __syncthreads();
   const size_t L = (size_t)tile * kBlock + threadIdx.x;
   LatAdj A{{0, 0, 0, 0}, {0, 0, 0, 0}, 0};
   int a = 0, b = 0;
@@ -350,6 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_corners(Grid g, Workspace ws, gh_cou
     ctr->n_corner = tc;
     if (tc > ws.cap) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
   }
+  }
 }
 
 // Bound value at each corner point, one lane per corner.
@@ -364,17 +385,6 @@ __global__ __launch_bounds__(kBlock) void k_eval_corners(Eval ev, Grid g, Worksp
     const int a = L / n1, b = L - a * n1;
     ws.cf[c] = ev(lattice(g, a), lattice(g, b), lattice(g, ws.ck[c]));
   }
-}
-
-// Persistent blocks take tiles of a list in ticket order until the list
-// (of `count` items) is exhausted; the single-pass scan stays deadlock-free
-// because a tile only waits on tiles already taken by running blocks.
-__device__ __forceinline__ int next_tile(unsigned int* ticket) {
-  __shared__ int s_next;
-  __syncthreads();
-  if (threadIdx.x == 0) s_next = (int)atomicAdd(ticket, 1u);
-  __syncthreads();
-  return s_next;
 }
 
 // ------------------------------------------------------------------ vertices
@@ -396,6 +406,11 @@ __device__ __forceinline__ unsigned cross_mask(const Workspace& ws, const Grid& 
   return msk;
 }
 
+// Each thread takes kItems consecutive list entries, so a tile covers
+// kBlock * kItems entries and the entries keep their order in the output.
+constexpr int kItems = 4;
+constexpr int kTileItems = kBlock * kItems;
+
 __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* __restrict__ verts,
                                                   int64_t* __restrict__ vert_edge, float* __restrict__ vert_t,
                                                   int64_t vert_cap, gh_counters* __restrict__ ctr) {
@@ -403,40 +418,50 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
   if (m > ws.cap) return;  // uniform: the corners overflowed, nothing to do
   const int n1 = g.n + 1;
   const size_t nl = (size_t)n1 * n1;
-  const int ntiles = (int)((m + kBlock - 1) / kBlock);
+  const int ntiles = (int)((m + kTileItems - 1) / kTileItems);
   if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) ctr->n_vert = 0;
-  for (;;) {
-    const int tile = next_tile(&ws.ticket[kTicketVerts]);
-    if (tile >= ntiles) break;
-    const int64_t ci = (int64_t)tile * kBlock + threadIdx.x;
-    unsigned msk = 0;
-    int64_t ix = -1, iy = -1;
-    if (ci < m) msk = cross_mask(ws, g, nl, ci, m, ix, iy);
-    const ScanOut so = block_scan_lookback(__popc(msk), scan_verts(ws), tile, &ctr->flags);
-    if (ci < m) {
-      const int64_t v0 = (int64_t)so.excl;
-      ws.cinfo[ci] = (v0 << 3) | (int64_t)msk;
-      if (msk && v0 + __popc(msk) <= vert_cap) {
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();
+    const int64_t c0 = (int64_t)tile * kTileItems + (int64_t)threadIdx.x * kItems;
+    unsigned msk[kItems];
+    int64_t ix[kItems], iy[kItems];
+    unsigned cnt = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      msk[r] = 0;
+      ix[r] = iy[r] = -1;
+      if (c0 + r < m) msk[r] = cross_mask(ws, g, nl, c0 + r, m, ix[r], iy[r]);
+      cnt += __popc(msk[r]);
+    }
+    const ScanOut so = block_scan_lookback(cnt, scan_verts(ws), tile, &ctr->flags);
+    int64_t v = (int64_t)so.excl;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const int64_t ci = c0 + r;
+      if (ci >= m) break;
+      ws.cinfo[ci] = (v << 3) | (int64_t)msk[r];
+      if (msk[r] && v + __popc(msk[r]) <= vert_cap) {
         const int L = ws.cl[ci], k = ws.ck[ci];
         const int a = L / n1, b = L - a * n1;
         const float fa = ws.cf[ci];
         const float xa = lattice(g, a), ya = lattice(g, b), za = lattice(g, k);
         const int64_t pid = ((int64_t)L * n1 + k) * 3;
-        int64_t v = v0;
+        int64_t vv = v;
 #pragma unroll
         for (int axis = 0; axis < 3; ++axis) {
-          if (!((msk >> axis) & 1)) continue;
-          const int64_t far = axis == 0 ? ix : (axis == 1 ? iy : ci + 1);
+          if (!((msk[r] >> axis) & 1)) continue;
+          const int64_t far = axis == 0 ? ix[r] : (axis == 1 ? iy[r] : ci + 1);
           const float fb = ws.cf[far];
           const float t = fa / (fa - fb);
-          verts[3 * v + 0] = axis == 0 ? xa + t * g.h : xa;
-          verts[3 * v + 1] = axis == 1 ? ya + t * g.h : ya;
-          verts[3 * v + 2] = axis == 2 ? za + t * g.h : za;
-          if (vert_edge) vert_edge[v] = pid + axis;
-          if (vert_t) vert_t[v] = t;
-          ++v;
+          verts[3 * vv + 0] = axis == 0 ? xa + t * g.h : xa;
+          verts[3 * vv + 1] = axis == 1 ? ya + t * g.h : ya;
+          verts[3 * vv + 2] = axis == 2 ? za + t * g.h : za;
+          if (vert_edge) vert_edge[vv] = pid + axis;
+          if (vert_t) vert_t[vv] = t;
+          ++vv;
         }
       }
+      v += __popc(msk[r]);
     }
     if (threadIdx.x == 0 && tile == ntiles - 1) {
       ctr->n_vert = (int64_t)so.total;
@@ -487,47 +512,61 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
   const int n = g.n;
   const size_t nl = (size_t)(n + 1) * (n + 1);
   const bool verts_ok = ctr->n_vert <= vert_cap;
-  const int ntiles = (int)((m + kBlock - 1) / kBlock);
+  const int ntiles = (int)((m + kTileItems - 1) / kTileItems);
   if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
     ctr->n_tri = 0;
     ctr->n_cells = 0;
   }
   bool broken = false;
-  for (;;) {
-    const int tile = next_tile(&ws.ticket[kTicketTris]);
-    if (tile >= ntiles) break;
-    const int64_t q = (int64_t)tile * kBlock + threadIdx.x;
-    CellCorners C{{0, 0, 0, 0}};
-    unsigned cs = 0, nt = 0;
-    int k = 0;
-    int64_t cell = 0;
-    if (q < m) {
-      cell = ws.cand[q];
-      if (cell_corners(ws, n, nl, cell, C, cs, k)) nt = s_mc[cs].ntri;
-      else broken = true;
-    }
-    // (cells << 31) | triangles: both stay below 2^31 for any mesh the outputs can index
-    const ScanOut so = block_scan_lookback(((uint64_t)(nt ? 1 : 0) << 31) | nt, scan_tris(ws), tile, &ctr->flags);
-    if (nt && verts_ok) {
-      const int64_t t0 = (int64_t)(so.excl & 0x7fffffffull), c = (int64_t)(so.excl >> 31);
-      if (c < cell_cap) {
-        if (cells) cells[c] = cell;
-        if (cases) cases[c] = (uint8_t)cs;
-      }
-      if (t0 + (int64_t)nt <= tri_cap) {
-        const McCase mcc = s_mc[cs];
-        for (unsigned tq = 0; tq < nt; ++tq) {
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();
+    const int64_t q0 = (int64_t)tile * kTileItems + (int64_t)threadIdx.x * kItems;
+    CellCorners C[kItems];
+    unsigned cs[kItems], nt[kItems];
+    int64_t cell[kItems];
+    uint64_t pack = 0;
 #pragma unroll
-          for (int v = 0; v < 3; ++v) {
-            const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
-            const int lc = mc_edge_lower(e), axis = e >> 2;
-            const int slot = (lc & 1) + 2 * ((lc >> 1) & 1);
-            const int64_t base = slot == 0 ? C.p[0] : (slot == 1 ? C.p[1] : (slot == 2 ? C.p[2] : C.p[3]));
-            const int64_t info = ws.cinfo[base + (lc >> 2)];
-            tris[3 * (t0 + tq) + v] = (int32_t)((info >> 3) + __popc((unsigned)(info & 7) & ((1u << axis) - 1u)));
+    for (int r = 0; r < kItems; ++r) {
+      cs[r] = nt[r] = 0;
+      cell[r] = 0;
+      C[r] = CellCorners{{0, 0, 0, 0}};
+      if (q0 + r < m) {
+        int k;
+        cell[r] = ws.cand[q0 + r];
+        if (cell_corners(ws, n, nl, cell[r], C[r], cs[r], k)) nt[r] = s_mc[cs[r]].ntri;
+        else broken = true;
+      }
+      // (cells << 31) | triangles: both stay below 2^31 for any mesh the outputs can index
+      pack += ((uint64_t)(nt[r] ? 1 : 0) << 31) | nt[r];
+    }
+    const ScanOut so = block_scan_lookback(pack, scan_tris(ws), tile, &ctr->flags);
+    int64_t t0 = (int64_t)(so.excl & 0x7fffffffull), c = (int64_t)(so.excl >> 31);
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      if (!nt[r]) continue;
+      if (verts_ok) {
+        if (c < cell_cap) {
+          if (cells) cells[c] = cell[r];
+          if (cases) cases[c] = (uint8_t)cs[r];
+        }
+        if (t0 + (int64_t)nt[r] <= tri_cap) {
+          const McCase mcc = s_mc[cs[r]];
+          for (unsigned tq = 0; tq < nt[r]; ++tq) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+              const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
+              const int lc = mc_edge_lower(e), axis = e >> 2;
+              const int slot = (lc & 1) + 2 * ((lc >> 1) & 1);
+              const int64_t base =
+                  slot == 0 ? C[r].p[0] : (slot == 1 ? C[r].p[1] : (slot == 2 ? C[r].p[2] : C[r].p[3]));
+              const int64_t info = ws.cinfo[base + (lc >> 2)];
+              tris[3 * (t0 + tq) + v] = (int32_t)((info >> 3) + __popc((unsigned)(info & 7) & ((1u << axis) - 1u)));
+            }
           }
         }
       }
+      t0 += nt[r];
+      ++c;
     }
     if (threadIdx.x == 0 && tile == ntiles - 1) {
       const int64_t tt = (int64_t)(so.total & 0x7fffffffull), tc = (int64_t)(so.total >> 31);
@@ -591,24 +630,47 @@ hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_co
   return hipGetLastError();
 }
 
-hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, float* dense, gh_counters* ctr,
+hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, uint32_t* signs, gh_counters* ctr,
                         hipStream_t s) {
   if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
   const int64_t n1 = g.n + 1;
-  const int64_t total = n1 * n1 * n1;
-  const int64_t blocks = (total + kBlock - 1) / kBlock;
+  const int64_t waves = n1 * n1 * ((n1 + 63) / 64);
+  const int64_t blocks = (waves + 3) / 4;
   hipLaunchKernelGGL(k_dense_eval<PrimsEval>, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(kBlock), 0, s,
-                     PrimsEval{d.prims, d.groups}, g, dense, ws.colmask);
+                     PrimsEval{d.prims, d.groups}, g, signs, ws.colmask, ctr);
   const int64_t words = (g.n + 31) / 32;
   const int64_t threads = (int64_t)g.n * g.n * words;
   hipLaunchKernelGGL(k_dense_classify, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g,
-                     dense, ws.colmask, ws.colbits, ctr);
+                     signs, ws.colmask, ws.colbits, ctr);
   return hipGetLastError();
+}
+
+// Look-back kernels run block-strided over their tiles with a grid no larger
+// than the number of blocks the device holds at once: every tile a block
+// waits on then belongs to a resident block that only waits on earlier
+// tiles, so the scan always makes progress (no ticket counter needed).
+template <class K>
+static int resident_grid(K kernel, int64_t tiles) {
+  static thread_local int cache_dev = -1;
+  static thread_local int cus = 0;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev != cache_dev) {
+    hipDeviceProp_t prop;
+    cus = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 1;
+    cache_dev = dev;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  const int64_t cap = (int64_t)cus * (per_cu < 4 ? per_cu : 4);
+  const int64_t gsz = tiles < cap ? tiles : cap;
+  return (int)(gsz < 1 ? 1 : gsz);
 }
 
 hipError_t launch_candidates(const Grid& g, const Workspace& ws, int64_t* out, int64_t cap, gh_counters* ctr,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_candidates, dim3((unsigned)ws.tiles_col), dim3(kBlock), 0, s, g, ws, out, cap, ctr);
+  hipLaunchKernelGGL(k_candidates, dim3(resident_grid(k_candidates, ws.tiles_col)), dim3(kBlock), 0, s, g, ws, out,
+                     cap, ctr);
   return hipGetLastError();
 }
 
@@ -616,13 +678,14 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
                      float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap, int64_t* cells,
                      uint8_t* cases, int64_t cell_cap, gh_counters* ctr, hipStream_t s) {
   if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
-  const int lists = (int)(ws.tiles_cap < 1024 ? (ws.tiles_cap < 1 ? 1 : ws.tiles_cap) : 1024);
-  hipLaunchKernelGGL(k_corners, dim3((unsigned)ws.tiles_lat), dim3(kBlock), 0, s, g, ws, ctr);
+  const int64_t list_tiles = (ws.cap + kTileItems - 1) / kTileItems;
+  hipLaunchKernelGGL(k_corners, dim3(resident_grid(k_corners, ws.tiles_lat)), dim3(kBlock), 0, s, g, ws, ctr);
   hipLaunchKernelGGL(k_eval_corners<PrimsEval>, dim3(persistent_blocks(ws.cap)), dim3(kBlock), 0, s,
                      PrimsEval{d.prims, d.groups}, g, ws);
-  hipLaunchKernelGGL(k_verts, dim3(lists), dim3(kBlock), 0, s, g, ws, verts, vert_edge, vert_t, vert_cap, ctr);
-  hipLaunchKernelGGL(k_tris, dim3(lists), dim3(kBlock), 0, s, g, ws, tris, tri_cap, cells, cases, cell_cap, vert_cap,
-                     ctr);
+  hipLaunchKernelGGL(k_verts, dim3(resident_grid(k_verts, list_tiles)), dim3(kBlock), 0, s, g, ws, verts, vert_edge,
+                     vert_t, vert_cap, ctr);
+  hipLaunchKernelGGL(k_tris, dim3(resident_grid(k_tris, list_tiles)), dim3(kBlock), 0, s, g, ws, tris, tri_cap, cells,
+                     cases, cell_cap, vert_cap, ctr);
   return hipGetLastError();
 }
 

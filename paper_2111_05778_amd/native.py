@@ -21,7 +21,7 @@ GH_SDB_PRIMS, GH_SDB_MLP = 1, 2
 GH_PREC_FP32, GH_PREC_BF16 = 0, 1
 GH_PRIM_FLOATS = 16
 
-EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_mc", "gh_dense", "gh_candidates",
+EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
            "gh_eval_points", "gh_set_tuning", "gh_get_tuning", "gh_last_error"]
 
 
@@ -65,6 +65,7 @@ lib.gh_hop.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp]
 lib.gh_mc.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64,
                       _vp, _vp]
 lib.gh_dense.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp]
+lib.gh_dense_signs_size.argtypes = [_P(gh_grid), _P(_sz)]
 lib.gh_candidates.argtypes = [_P(gh_grid), _vp, _sz, _i64, _vp, _i64, _vp, _vp]
 lib.gh_eval_points.argtypes = [_P(gh_sdb_desc), _vp, _vp, _i64, _vp]
 lib.gh_set_tuning.argtypes = [_P(gh_tuning)]
@@ -119,9 +120,15 @@ def gh_hop(desc, grid, ws, corner_cap, ctr, stream=None):
                       int(corner_cap), ptr(ctr), stream_handle(stream))
 
 
-def gh_dense(desc, grid, ws, corner_cap, dense, ctr, stream=None):
+def gh_dense(desc, grid, ws, corner_cap, signs, ctr, stream=None):
     return lib.gh_dense(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
-                        int(corner_cap), ptr(dense), ptr(ctr), stream_handle(stream))
+                        int(corner_cap), ptr(signs), ptr(ctr), stream_handle(stream))
+
+
+def gh_dense_signs_size(grid):
+    out = _sz(0)
+    check(lib.gh_dense_signs_size(ctypes.byref(grid), ctypes.byref(out)), "gh_dense_signs_size")
+    return out.value
 
 
 def gh_mc(desc, grid, ws, corner_cap, verts, vert_edge, vert_t, vert_cap, tris, tri_cap, cells, cases, cell_cap,

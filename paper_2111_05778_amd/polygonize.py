@@ -95,8 +95,8 @@ class Polygonizer:
 
     def enqueue_dense(self, stream=None):
         if self.dense_buf is None:
-            n1 = self.n + 1
-            self.dense_buf = torch.empty(n1 * n1 * n1, dtype=torch.float32, device=self.device)
+            nb = N.gh_dense_signs_size(self.grid)
+            self.dense_buf = torch.empty(nb // 4, dtype=torch.int32, device=self.device)
         N.check(N.gh_dense(self.bound.desc, self.grid, self.ws, self.corner_cap, self.dense_buf, self.ctr, stream),
                 "gh_dense")
 
