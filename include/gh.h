@@ -86,7 +86,14 @@ typedef struct {
 
 /* ----------------------------------------------------------------- bounds */
 enum { GH_SDB_PRIMS = 1, GH_SDB_MLP = 2 };
-enum { GH_PREC_FP32 = 0, GH_PREC_BF16 = 1 };
+/* Network arithmetic on the matrix cores, all with FP32 accumulation:
+ *   FP32    v_mfma_f32_32x32x2f32 on float activations and weights
+ *   BF16    v_mfma_f32_32x32x16_bf16 on bf16 activations and weights
+ *   BF16X3  the bf16 instruction on hi + lo bf16 splits (hi*hi + hi*lo + lo*hi)
+ * In both bf16 modes every decision a value feeds (the hop test, corner and
+ * lattice signs) is re-evaluated in FP32 when it lies within bf16_margin of
+ * changing, so schedules and signs are the FP32 ones (n_reeval counts). */
+enum { GH_PREC_FP32 = 0, GH_PREC_BF16 = 1, GH_PREC_BF16X3 = 2 };
 
 /* Primitive record: 16 float32 values.
  *  [0] type: 0 sphere, 1 box (exact), 2 torus, 3 capsule, 4 plane,
@@ -108,12 +115,12 @@ typedef struct {
   int32_t n_freq;                /* 0 .. 16 */
   int32_t width;                 /* 64, 128 or 256 */
   int32_t depth;                 /* hidden layers, 1 .. 8 */
-  int32_t precision;             /* GH_PREC_FP32 or GH_PREC_BF16 */
+  int32_t precision;             /* GH_PREC_FP32, GH_PREC_BF16 or GH_PREC_BF16X3 */
   const float* omegas_h;         /* n_freq, host */
   const float* const* weights_h; /* depth+1 host arrays, row-major fan_out x fan_in */
   const float* const* biases_h;  /* depth+1 host arrays of fan_out */
   float a_s, r0, a_n, b;
-  float bf16_margin;             /* eps_b >= max |f_bf16 - f_fp32|, used by the hop test */
+  float bf16_margin;             /* eps >= max |f_bf16 - f_fp32| (bf16 modes) */
 } gh_sdb_spec;
 
 /* Opaque, caller-owned, plain-old-data handle filled by sdb_describe.  It

@@ -73,6 +73,135 @@ gh_status carve(const gh::Grid& g, void* ws, size_t ws_bytes, int64_t cap, gh::W
   return GH_OK;
 }
 
+uint16_t to_bf16(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even; values are finite
+  return (uint16_t)(u >> 16);
+}
+
+bool finite_bounded(float v, float lim) { return fabsf(v) <= lim; }
+
+// Packs the network into the blob: bf16 and f32 B fragments of every hidden
+// layer (exact 32x32 MFMA operand order, zero-padded K), biases, output
+// weights and frequencies.
+gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes, size_t* blob_needed_h,
+                       gh_sdb_desc* desc_h, void* stream) {
+  const int F = sp->n_freq, W = sp->width, D = sp->depth;
+  if (F < 0 || F > 16) return fail(GH_EINVAL, "n_freq = %d must be in [0, 16]", F);
+  if (!(W == 64 || W == 128 || W == 256)) return fail(GH_EUNSUPPORTED, "width %d: supported 64, 128, 256", W);
+  if (D < 1 || D > 8) return fail(GH_EINVAL, "depth = %d must be in [1, 8]", D);
+  if (!(sp->precision == GH_PREC_FP32 || sp->precision == GH_PREC_BF16 || sp->precision == GH_PREC_BF16X3))
+    return fail(GH_EINVAL, "precision %d unknown", sp->precision);
+  if (!sp->weights_h || !sp->biases_h || (F > 0 && !sp->omegas_h)) return fail(GH_EINVAL, "network arrays are NULL");
+  const float scal[] = {sp->a_s, sp->r0, sp->a_n, sp->b, sp->bf16_margin};
+  for (float v : scal)
+    if (!finite_bounded(v, 1e6f)) return fail(GH_EINVAL, "network scalar not finite or above 1e6");
+  if (sp->bf16_margin < 0.f) return fail(GH_EINVAL, "bf16_margin must be >= 0");
+  const int k1 = 3 + 6 * F;
+  for (int l = 0; l <= D; ++l) {
+    const int fi = l == 0 ? k1 : W, fo = l == D ? 1 : W;
+    if (!sp->weights_h[l] || !sp->biases_h[l]) return fail(GH_EINVAL, "layer %d arrays are NULL", l);
+    for (int q = 0; q < fi * fo; ++q)
+      if (!finite_bounded(sp->weights_h[l][q], 1e6f)) return fail(GH_EINVAL, "layer %d weight not finite", l);
+    for (int q = 0; q < fo; ++q)
+      if (!finite_bounded(sp->biases_h[l][q], 1e6f)) return fail(GH_EINVAL, "layer %d bias not finite", l);
+  }
+  for (int q = 0; q < F; ++q)
+    if (!finite_bounded(sp->omegas_h[q], 1e4f)) return fail(GH_EINVAL, "frequency %d not finite", q);
+  size_t nb = 0, nf = 0;
+  for (int l = 0; l < D; ++l) {
+    nb += gh::mlp_layer_elems(l, k1, W, gh::kPrecBf16);
+    nf += gh::mlp_layer_elems(l, k1, W, gh::kPrecF32);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = gh::align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t o_wb = take(nb * 2), o_wbl = take(nb * 2), o_wf = take(nf * 4), o_bias = take((size_t)D * W * 4), o_wout = take((size_t)W * 4),
+               o_om = take(16 * 4);
+  const size_t need = off;
+  if (blob_needed_h) *blob_needed_h = need;
+  if (!dev_blob) return desc_h ? fail(GH_EINVAL, "dev_blob is NULL") : GH_OK;
+  if (blob_bytes < need) return fail(GH_ECAPACITY, "blob of %zu bytes, %zu needed", blob_bytes, need);
+  if (!desc_h) return fail(GH_EINVAL, "desc is NULL");
+  std::vector<unsigned char> host(need, 0);
+  uint16_t* wb = (uint16_t*)(host.data() + o_wb);
+  uint16_t* wbl = (uint16_t*)(host.data() + o_wbl);
+  float* wf = (float*)(host.data() + o_wf);
+  for (int l = 0; l < D; ++l) {
+    const float* Wl = sp->weights_h[l];  // W x fan_in, row-major
+    const int fi = l == 0 ? k1 : W;
+    const int CT = W / 32;
+    // bf16: fragment (kt, ct), lane, element i -> W[ct*32 + lane%32][kt*16 + 8*(lane/32) + i]
+    {
+      const int K = gh::mlp_k0(k1, gh::kPrecBf16) * (l == 0) + W * (l != 0);
+      uint16_t* dst = wb + gh::mlp_layer_offset(l, k1, W, gh::kPrecBf16);
+      uint16_t* dstl = wbl + gh::mlp_layer_offset(l, k1, W, gh::kPrecBf16);
+      for (int kt = 0; kt < K / 16; ++kt)
+        for (int ct = 0; ct < CT; ++ct)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int i = 0; i < 8; ++i) {
+              const int col = ct * 32 + lane % 32, k = kt * 16 + 8 * (lane / 32) + i;
+              const float v = k < fi ? Wl[(size_t)col * fi + k] : 0.f;
+              const uint16_t hi = to_bf16(v);
+              uint32_t hb = (uint32_t)hi << 16;
+              float hv;
+              memcpy(&hv, &hb, 4);
+              dst[((size_t)(kt * CT + ct) * 64 + lane) * 8 + i] = hi;
+              dstl[((size_t)(kt * CT + ct) * 64 + lane) * 8 + i] = to_bf16(v - hv);
+            }
+    }
+    // f32: fragment (kt, ct), lane -> W[ct*32 + lane%32][2*kt + lane/32]
+    {
+      const int K = gh::mlp_k0(k1, gh::kPrecF32) * (l == 0) + W * (l != 0);
+      float* dst = wf + gh::mlp_layer_offset(l, k1, W, gh::kPrecF32);
+      for (int kt = 0; kt < K / 2; ++kt)
+        for (int ct = 0; ct < CT; ++ct)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int col = ct * 32 + lane % 32, k = 2 * kt + lane / 32;
+            dst[(size_t)(kt * CT + ct) * 64 + lane] = k < fi ? Wl[(size_t)col * fi + k] : 0.f;
+          }
+    }
+    memcpy(host.data() + o_bias + (size_t)l * W * 4, sp->biases_h[l], (size_t)W * 4);
+  }
+  memcpy(host.data() + o_wout, sp->weights_h[D], (size_t)W * 4);
+  if (F > 0) memcpy(host.data() + o_om, sp->omegas_h, (size_t)F * 4);
+  hipStream_t s = (hipStream_t)stream;
+  gh_status st = hip_status(hipMemcpyAsync(dev_blob, host.data(), need, hipMemcpyHostToDevice, s), "upload");
+  if (st != GH_OK) return st;
+  st = hip_status(hipStreamSynchronize(s), "upload sync");
+  if (st != GH_OK) return st;
+  gh::DevSdb d{};
+  d.magic = gh::kDescMagic;
+  d.kind = GH_SDB_MLP;
+  char* b = (char*)dev_blob;
+  gh::MlpDesc& m = d.mlp;
+  m.wb = (const uint16_t*)(b + o_wb);
+  m.wbl = (const uint16_t*)(b + o_wbl);
+  m.wf = (const float*)(b + o_wf);
+  m.bias = (const float*)(b + o_bias);
+  m.wout = (const float*)(b + o_wout);
+  m.omegas = (const float*)(b + o_om);
+  m.F = F;
+  m.W = W;
+  m.depth = D;
+  m.k1 = k1;
+  m.precision = sp->precision == GH_PREC_BF16 ? gh::kPrecBf16
+                : (sp->precision == GH_PREC_BF16X3 ? gh::kPrecBf16x3 : gh::kPrecF32);
+  m.a_s = sp->a_s;
+  m.r0 = sp->r0;
+  m.a_n = sp->a_n;
+  m.b = sp->b;
+  m.b_out = sp->biases_h[D][0];
+  m.eps = sp->bf16_margin;
+  memset(desc_h, 0, sizeof(*desc_h));
+  memcpy(desc_h, &d, sizeof(d));
+  return GH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -98,6 +227,7 @@ gh_status gh_get_tuning(gh_tuning* t) {
 gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_bytes, size_t* blob_needed_h,
                        gh_sdb_desc* desc_h, void* stream) {
   if (!spec_h) return fail(GH_EINVAL, "spec is NULL");
+  if (spec_h->kind == GH_SDB_MLP) return describe_mlp(spec_h, dev_blob, blob_bytes, blob_needed_h, desc_h, stream);
   if (spec_h->kind != GH_SDB_PRIMS)
     return fail(GH_EUNSUPPORTED, "bound kind %d is not supported by this build", spec_h->kind);
   const int np = spec_h->n_prim;

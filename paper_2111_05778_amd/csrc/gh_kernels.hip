@@ -618,6 +618,7 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
 
 hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, int lanes_per_ray,
                       hipStream_t s) {
+  if (d.kind == GH_SDB_MLP) return launch_mlp(3, d, g, &ws, nullptr, nullptr, nullptr, 0, ctr, s);
   if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
   if (lanes_per_ray <= 0) lanes_per_ray = 4;
   switch (lanes_per_ray) {
@@ -632,12 +633,18 @@ hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_co
 
 hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, uint32_t* signs, gh_counters* ctr,
                         hipStream_t s) {
-  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
-  const int64_t n1 = g.n + 1;
-  const int64_t waves = n1 * n1 * ((n1 + 63) / 64);
-  const int64_t blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL(k_dense_eval<PrimsEval>, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(kBlock), 0, s,
-                     PrimsEval{d.prims, d.groups}, g, signs, ws.colmask, ctr);
+  if (d.kind == GH_SDB_MLP) {
+    const hipError_t e = launch_mlp(2, d, g, &ws, signs, nullptr, nullptr, 0, ctr, s);
+    if (e != hipSuccess) return e;
+  } else if (d.kind == GH_SDB_PRIMS) {
+    const int64_t n1 = g.n + 1;
+    const int64_t waves = n1 * n1 * ((n1 + 63) / 64);
+    const int64_t blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL(k_dense_eval<PrimsEval>, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(kBlock), 0,
+                       s, PrimsEval{d.prims, d.groups}, g, signs, ws.colmask, ctr);
+  } else {
+    return hipErrorInvalidValue;
+  }
   const int64_t words = (g.n + 31) / 32;
   const int64_t threads = (int64_t)g.n * g.n * words;
   hipLaunchKernelGGL(k_dense_classify, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g,
@@ -677,11 +684,16 @@ hipError_t launch_candidates(const Grid& g, const Workspace& ws, int64_t* out, i
 hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float* verts, int64_t* vert_edge,
                      float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap, int64_t* cells,
                      uint8_t* cases, int64_t cell_cap, gh_counters* ctr, hipStream_t s) {
-  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
+  if (d.kind != GH_SDB_PRIMS && d.kind != GH_SDB_MLP) return hipErrorInvalidValue;
   const int64_t list_tiles = (ws.cap + kTileItems - 1) / kTileItems;
   hipLaunchKernelGGL(k_corners, dim3(resident_grid(k_corners, ws.tiles_lat)), dim3(kBlock), 0, s, g, ws, ctr);
-  hipLaunchKernelGGL(k_eval_corners<PrimsEval>, dim3(persistent_blocks(ws.cap)), dim3(kBlock), 0, s,
-                     PrimsEval{d.prims, d.groups}, g, ws);
+  if (d.kind == GH_SDB_MLP) {
+    const hipError_t e = launch_mlp(1, d, g, &ws, nullptr, nullptr, nullptr, 0, ctr, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_eval_corners<PrimsEval>, dim3(persistent_blocks(ws.cap)), dim3(kBlock), 0, s,
+                       PrimsEval{d.prims, d.groups}, g, ws);
+  }
   hipLaunchKernelGGL(k_verts, dim3(resident_grid(k_verts, list_tiles)), dim3(kBlock), 0, s, g, ws, verts, vert_edge,
                      vert_t, vert_cap, ctr);
   hipLaunchKernelGGL(k_tris, dim3(resident_grid(k_tris, list_tiles)), dim3(kBlock), 0, s, g, ws, tris, tri_cap, cells,
@@ -690,6 +702,7 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
 }
 
 hipError_t launch_eval_points(const DevSdb& d, const float* xyz, float* f, int64_t m, hipStream_t s) {
+  if (d.kind == GH_SDB_MLP) return launch_mlp(0, d, Grid{}, nullptr, nullptr, xyz, f, m, nullptr, s);
   if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_eval_points<PrimsEval>, dim3(persistent_blocks(m)), dim3(kBlock), 0, s,
                      PrimsEval{d.prims, d.groups}, xyz, f, m);

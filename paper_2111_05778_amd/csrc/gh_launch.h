@@ -6,6 +6,7 @@
 #include "gh.h"
 #include "gh_device.h"
 #include "gh_layout.h"
+#include "gh_mlp.h"
 
 namespace gh {
 
@@ -17,6 +18,7 @@ struct DevSdb {
   int32_t pad;
   const float* prims;  // device, n_prim * GH_PRIM_FLOATS, sorted by type
   PrimGroups groups;   // type t occupies records [start[t], start[t+1])
+  MlpDesc mlp;         // GH_SDB_MLP: packed network in the blob
 };
 constexpr uint32_t kDescMagic = 0x67687364u;  // "ghsd"
 
@@ -34,5 +36,8 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
                      float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap, int64_t* cells,
                      uint8_t* cases, int64_t cell_cap, gh_counters* ctr, hipStream_t s);
 hipError_t launch_eval_points(const DevSdb& d, const float* xyz, float* f, int64_t m, hipStream_t s);
+// Network kernels: what = 0 points, 1 corner list, 2 enumeration signs, 3 hop.
+hipError_t launch_mlp(int what, const DevSdb& d, const Grid& g, const Workspace* ws, uint32_t* signs,
+                      const float* xyz, float* f, int64_t count, gh_counters* ctr, hipStream_t s);
 
 }  // namespace gh

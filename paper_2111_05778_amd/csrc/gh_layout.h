@@ -104,6 +104,6 @@ __host__ __device__ inline uint64_t* scan_cands(const Workspace& w) {
 }
 inline size_t scan_words(const Workspace& w) { return (size_t)(w.tiles_lat + 2 * w.tiles_cap + w.tiles_col); }
 
-enum { kTicketCorners = 0, kTicketVerts = 1, kTicketTris = 2, kTicketCands = 3 };
+enum { kTicketCorners = 0, kTicketVerts = 1, kTicketTris = 2, kTicketCands = 3, kTicketRays = 4 };
 
 }  // namespace gh

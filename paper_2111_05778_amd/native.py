@@ -18,7 +18,7 @@ lib = ctypes.CDLL(_LIB_PATH)
 GH_OK, GH_EINVAL, GH_ECAPACITY, GH_EHIP, GH_EUNSUPPORTED, GH_ENONFINITE = 0, -1, -2, -3, -4, -5
 GH_FLAG_CAPACITY, GH_FLAG_NONFINITE, GH_FLAG_INTERNAL = 1, 2, 4
 GH_SDB_PRIMS, GH_SDB_MLP = 1, 2
-GH_PREC_FP32, GH_PREC_BF16 = 0, 1
+GH_PREC_FP32, GH_PREC_BF16, GH_PREC_BF16X3 = 0, 1, 2
 GH_PRIM_FLOATS = 16
 
 EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",

@@ -37,12 +37,47 @@ class Bound:
         spec.prims_h = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         return Bound(spec, [rec], device)
 
+    @staticmethod
+    def mlp(net, precision="bf16", margin=0.0, device="cuda"):
+        """Neural bound f = a_s (||p|| - r0) + a_n NN(gamma(p)) + b.
+
+        net: dict with "omegas" (F), "weights" (depth+1 arrays, fan_out x
+        fan_in), "biases", and the scalars "a_s", "r0", "a_n", "b".
+        margin: eps >= |f_bf16 - f_fp32| for the bf16 hop test."""
+        ws = [np.ascontiguousarray(np.asarray(w, dtype=np.float32)) for w in net["weights"]]
+        bs = [np.ascontiguousarray(np.asarray(b, dtype=np.float32)) for b in net["biases"]]
+        om = np.ascontiguousarray(np.asarray(net["omegas"], dtype=np.float32))
+        fp = ctypes.POINTER(ctypes.c_float)
+        wptr = (fp * len(ws))(*[w.ctypes.data_as(fp) for w in ws])
+        bptr = (fp * len(bs))(*[b.ctypes.data_as(fp) for b in bs])
+        spec = N.gh_sdb_spec()
+        spec.kind = N.GH_SDB_MLP
+        spec.n_freq = len(om)
+        spec.width = ws[0].shape[0]
+        spec.depth = len(ws) - 1
+        spec.precision = {"fp32": N.GH_PREC_FP32, "bf16": N.GH_PREC_BF16, "bf16x3": N.GH_PREC_BF16X3}[precision]
+        spec.omegas_h = om.ctypes.data_as(fp)
+        spec.weights_h = wptr
+        spec.biases_h = bptr
+        spec.a_s, spec.r0, spec.a_n, spec.b = (float(net[k]) for k in ("a_s", "r0", "a_n", "b"))
+        spec.bf16_margin = float(margin)
+        return Bound(spec, [ws, bs, om, wptr, bptr], device)
+
     def eval(self, xyz):
         """Bound values at points (m x 3 float32 device tensor)."""
         xyz = xyz.contiguous()
         f = torch.empty(xyz.shape[0], dtype=torch.float32, device=xyz.device)
         N.check(N.gh_eval_points(self.desc, xyz, f, xyz.shape[0]), "gh_eval_points")
         return f
+
+
+def bf16_margin(net, points, precision="bf16", factor=2.0, device="cuda"):
+    """Margin of the bf16 decisions: factor * max |f_bf16 - f_fp32| over the
+    given points, both values from the library's own evaluators."""
+    pts = torch.as_tensor(np.asarray(points, dtype=np.float32), device=device)
+    f32 = Bound.mlp(net, "fp32", device=device).eval(pts)
+    fb = Bound.mlp(net, precision, device=device).eval(pts)
+    return float(factor * (fb - f32).abs().max().item())
 
 
 def counters_dict(ctr):

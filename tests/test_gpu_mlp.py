@@ -1,0 +1,190 @@
+"""GPU parity of the neural bound (eq. nnsdb with the sphere prior) against
+the FP64 oracle, through the C ABI.
+
+* FP32 evaluator (MFMA f32): values within 2e-5 of FP64; the FP32 mesh has
+  the oracle's sign-change cells once cells with a corner closer to zero
+  than four times the measured FP32 error are set aside (count reported).
+* bf16 evaluators (MFMA bf16, FP32 accumulation; plain and hi/lo split):
+  with the measured margin eps the hop takes exactly the FP32 schedule and
+  every corner sign is the FP32 sign (ambiguous values are re-evaluated in
+  FP32), so cells, cases and triangles equal the FP32 path's; the vertices
+  differ only through t.
+* bf16 meshes within 0.5 h (Hausdorff) of the FP64 oracle's mesh.
+* Full size N = 512, width 256, split bf16: closed oriented mesh whose
+  vertices lie on the FP64 surface to within a quarter cell.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hop as ohop
+from oracle import mc as omc
+from oracle import mesh as omesh
+from oracle import sdb as osdb
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gh():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_05778_amd import native, polygonize
+    return native, polygonize
+
+
+def _canon(tri_e):
+    r = np.argmin(tri_e, axis=1)
+    t = np.take_along_axis(tri_e, (r[:, None] + np.arange(3)) % 3, axis=1)
+    return t[np.lexsort((t[:, 2], t[:, 1], t[:, 0]))]
+
+
+def _run(gh, bound, n, lo, h, dense=False):
+    native, P = gh
+    poly = P.Polygonizer(bound, n, lo, h)
+    m = poly.run(dense=dense)
+    out = {"cand": poly.candidates().cpu().numpy(), "ctr": m.counters,
+           "verts": m.verts.cpu().numpy().astype(np.float64), "edge": m.vert_edge.cpu().numpy(),
+           "tris": m.tris.cpu().numpy().astype(np.int64), "cells": m.cells.cpu().numpy(),
+           "cases": m.cases.cpu().numpy()}
+    out["tri_e"] = _canon(out["edge"][out["tris"]]) if len(out["tris"]) else np.zeros((0, 3), np.int64)
+    return out
+
+
+def _closed_oriented(tris):
+    v = int(tris.max()) + 1
+    d = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    key = d[:, 0] * v + d[:, 1]
+    return len(np.unique(key)) == len(key) and np.isin(d[:, 1] * v + d[:, 0], key).all()
+
+
+def _points(n=20000, seed=5):
+    return np.random.default_rng(seed).uniform(-1, 1, (n, 3)).astype(np.float32)
+
+
+@pytest.mark.parametrize("width", [64, 128, 256])
+def test_fp32_values_match_fp64(gh, width):
+    import torch
+    native, P = gh
+    net = W.neural_scene(0, width)
+    pts = _points()
+    f = P.Bound.mlp(net, "fp32").eval(torch.from_numpy(pts).cuda()).cpu().numpy().astype(np.float64)
+    ref = osdb.neural_f64(net, pts.astype(np.float64))
+    err = np.abs(f - ref).max()
+    print(f"width {width}: max |f32 - f64| = {err:.3e}", flush=True)
+    assert err < 2e-5
+
+
+@pytest.mark.parametrize("width", [64, 256])
+def test_bf16_values_close_to_fp64(gh, width):
+    import torch
+    native, P = gh
+    net = W.neural_scene(0, width)
+    pts = _points()
+    ref = osdb.neural_f64(net, pts.astype(np.float64))
+    errs = {}
+    for prec in ("bf16", "bf16x3"):
+        f = P.Bound.mlp(net, prec).eval(torch.from_numpy(pts).cuda()).cpu().numpy().astype(np.float64)
+        errs[prec] = np.abs(f - ref).max()
+    m3 = P.bf16_margin(net, W.probe_points(seed=3, n=65536), "bf16x3")
+    print(f"width {width}: max |f - f64| bf16 {errs['bf16']:.3e}, bf16x3 {errs['bf16x3']:.3e}; "
+          f"bf16x3 margin {m3:.3e}", flush=True)
+    assert errs["bf16"] < 2e-2
+    # the split keeps the margin far below the 0.134 h guard of the hop rule at N = 512
+    assert errs["bf16x3"] < 1e-4 and m3 < 0.05 * 0.134 * (2.0 / 512)
+
+
+@pytest.mark.parametrize("width,n", [(64, 64), (256, 48)])
+def test_fp32_mesh_matches_fp64_oracle(gh, width, n):
+    import torch
+    native, P = gh
+    net = W.neural_scene(0, width)
+    g = W.grid(n)
+    out = _run(gh, P.Bound.mlp(net, "fp32"), *g)
+    ref = ohop.gridhop(osdb.SDB.neural(net), *g)
+    # exclusion threshold from the measured FP32 error at the oracle's corners
+    pid = ohop.corner_points(n, ref.candidates)
+    n1 = n + 1
+    a, b, c = pid // (n1 * n1), (pid // n1) % n1, pid % n1
+    P64 = np.stack([omc.lattice_coords_f64(n, g[1], g[2], v) for v in (a, b, c)], axis=1)
+    f64 = osdb.neural_f64(net, P64)
+    f32 = P.Bound.mlp(net, "fp32").eval(torch.from_numpy(P64.astype(np.float32)).cuda()).cpu().numpy()
+    thr = max(1e-6 * float(g[2]), 2.0 ** -20, 4 * np.abs(f32 - f64).max())
+    near_pid = set(pid[np.abs(f64) < thr].tolist())
+
+    def near(cells):
+        out_ = []
+        for cell in cells:
+            i, j, k = cell // (n * n), (cell // n) % n, cell % n
+            ids = [((i + dx) * n1 + (j + dy)) * n1 + (k + dz) for dx in (0, 1) for dy in (0, 1) for dz in (0, 1)]
+            out_.append(any(q in near_pid for q in ids))
+        return np.array(out_, dtype=bool)
+
+    ga, oa = out["cells"], ref.mesh.cells
+    print(f"width {width} n {n}: thr {thr:.2e}, gpu cells {len(ga)}, oracle {len(oa)}, "
+          f"excluded {int(near(ga).sum())}/{int(near(oa).sum())}", flush=True)
+    np.testing.assert_array_equal(ga[~near(ga)], oa[~near(oa)])
+    # evaluation counts agree up to float rounding at floor() boundaries
+    assert abs(out["ctr"]["n_hop_evals"] - ref.hop_evals) <= 1e-3 * ref.hop_evals
+
+
+@pytest.mark.parametrize("prec,width,n", [("bf16", 256, 64), ("bf16", 64, 128), ("bf16x3", 128, 96),
+                                          ("bf16x3", 256, 128)])
+def test_bf16_takes_the_fp32_schedule_and_signs(gh, prec, width, n):
+    native, P = gh
+    net = W.neural_scene(0, width)
+    margin = P.bf16_margin(net, W.probe_points(seed=3, n=65536), prec)
+    g = W.grid(n)
+    a = _run(gh, P.Bound.mlp(net, "fp32"), *g)
+    b = _run(gh, P.Bound.mlp(net, prec, margin=margin), *g)
+    print(f"{prec} width {width} n {n}: margin {margin:.2e}, evals {b['ctr']['n_hop_evals']}, "
+          f"re-evaluated {b['ctr']['n_reeval']}", flush=True)
+    np.testing.assert_array_equal(a["cand"], b["cand"])
+    assert a["ctr"]["n_hop_evals"] == b["ctr"]["n_hop_evals"]
+    for key in ("cells", "cases", "edge", "tri_e"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_bf16_mesh_within_half_cell_of_fp64(gh, prec):
+    native, P = gh
+    net = W.neural_scene(0, 256)
+    n, lo, h = W.grid(64)
+    margin = P.bf16_margin(net, W.probe_points(seed=3, n=65536), prec)
+    out = _run(gh, P.Bound.mlp(net, prec, margin=margin), n, lo, h)
+    ref = ohop.gridhop(osdb.SDB.neural(net), n, lo, h).mesh
+    T = np.searchsorted(out["edge"], out["tri_e"])
+    hd = omesh.hausdorff(out["verts"], T, ref.positions(), ref.tri_vertex_index())
+    print(f"{prec}: Hausdorff {hd:.3e} = {hd / float(h):.4f} h", flush=True)
+    assert hd <= 0.5 * float(h)
+    assert _closed_oriented(T)
+
+
+def test_bf16_dense_equals_hop(gh):
+    native, P = gh
+    net = W.neural_scene(0, 64)
+    g = W.grid(48)
+    margin = P.bf16_margin(net, W.probe_points(seed=3, n=65536))
+    bnd = P.Bound.mlp(net, "bf16", margin=margin)
+    a, b = _run(gh, bnd, *g), _run(gh, bnd, *g, dense=True)
+    for key in ("cells", "cases", "edge", "tri_e"):
+        np.testing.assert_array_equal(a[key], b[key])
+    assert b["ctr"]["n_hop_evals"] == 49 ** 3
+
+
+def test_full_size_bf16x3_n512(gh):
+    native, P = gh
+    net = W.neural_scene(0, 256)
+    n, lo, h = W.grid(512)
+    margin = P.bf16_margin(net, W.probe_points(seed=3, n=65536), "bf16x3")
+    out = _run(gh, P.Bound.mlp(net, "bf16x3", margin=margin), n, lo, h)
+    c = out["ctr"]
+    print(f"N=512 neural bf16x3 margin {margin:.2e}: {c}", flush=True)
+    T = np.searchsorted(out["edge"], out["tri_e"])
+    assert _closed_oriented(T)
+    rng = np.random.default_rng(0)
+    sel = rng.choice(len(out["verts"]), 4096, replace=False)
+    f = osdb.neural_f64(net, out["verts"][sel])
+    assert np.abs(f).max() <= 0.25 * float(h)
+    assert c["n_reeval"] < 0.01 * c["n_hop_evals"]
