@@ -184,6 +184,28 @@ gh_status gh_dense_signs_size(const gh_grid* grid_h, size_t* bytes_h);
 gh_status gh_candidates(const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
                         int64_t* out, int64_t cap, gh_counters* ctr, void* stream);
 
+/* Number of network parameters (GH_SDB_MLP): sum over layers of
+ * (fan_in + 1) * fan_out, in the order W_0, b_0, W_1, b_1, ..., W_D, b_D
+ * (each W row-major fan_out x fan_in). */
+gh_status gh_param_count(const gh_sdb_desc* desc_h, int64_t* count_h);
+
+/* Workspace bytes of gh_backward for this network and corner capacity. */
+gh_status gh_backward_workspace_size(const gh_sdb_desc* desc_h, int64_t corner_cap, size_t* bytes_h);
+
+/* Adjoint of a loss on the vertices of the last gh_mc on ws (network bounds).
+ * A vertex on lattice edge a -> b sits at P_a + t h e_axis, t = f_a/(f_a - f_b);
+ * the corner values get the cotangents (dL/dv . e) h dt/df, and the
+ * network's parameters dL/dtheta = a_n sum_c gbar_c dNN(P_c)/dtheta by
+ * back-propagation in FP32 on the matrix cores.  The cell set is piecewise
+ * constant in theta and is not differentiated.
+ *   dL_dverts  [n_vert][3] device, in the vertex order of gh_mc
+ *   dL_dtheta  [gh_param_count] device, overwritten
+ *   bws        device workspace of gh_backward_workspace_size bytes
+ * The result is deterministic (fixed summation order). */
+gh_status gh_backward(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
+                      int64_t corner_cap, const float* dL_dverts, float* dL_dtheta, void* bws, size_t bws_bytes,
+                      gh_counters* ctr, void* stream);
+
 /* Evaluate the bound at m points xyz [m][3] (device) into f [m] (device). */
 gh_status gh_eval_points(const gh_sdb_desc* desc_h, const float* xyz, float* f, int64_t m, void* stream);
 

@@ -120,7 +120,8 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
     off = gh::align_up(off + bytes, 256);
     return o;
   };
-  const size_t o_wb = take(nb * 2), o_wbl = take(nb * 2), o_wf = take(nf * 4), o_bias = take((size_t)D * W * 4), o_wout = take((size_t)W * 4),
+  const size_t nft = (size_t)(D - 1) * W * W;
+  const size_t o_wb = take(nb * 2), o_wbl = take(nb * 2), o_wf = take(nf * 4), o_wft = take(nft * 4 + 4), o_bias = take((size_t)D * W * 4), o_wout = take((size_t)W * 4),
                o_om = take(16 * 4);
   const size_t need = off;
   if (blob_needed_h) *blob_needed_h = need;
@@ -165,6 +166,14 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
             dst[(size_t)(kt * CT + ct) * 64 + lane] = k < fi ? Wl[(size_t)col * fi + k] : 0.f;
           }
     }
+    // transposed f32 (l >= 1): fragment (ks, kt), lane -> W[2*ks + lane/32][kt*32 + lane%32]
+    if (l >= 1) {
+      float* dst = (float*)(host.data() + o_wft) + (size_t)(l - 1) * W * W;
+      for (int ks = 0; ks < W / 2; ++ks)
+        for (int kt = 0; kt < CT; ++kt)
+          for (int lane = 0; lane < 64; ++lane)
+            dst[(size_t)(ks * CT + kt) * 64 + lane] = Wl[(size_t)(2 * ks + lane / 32) * W + kt * 32 + lane % 32];
+    }
     memcpy(host.data() + o_bias + (size_t)l * W * 4, sp->biases_h[l], (size_t)W * 4);
   }
   memcpy(host.data() + o_wout, sp->weights_h[D], (size_t)W * 4);
@@ -182,6 +191,7 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.wb = (const uint16_t*)(b + o_wb);
   m.wbl = (const uint16_t*)(b + o_wbl);
   m.wf = (const float*)(b + o_wf);
+  m.wft = (const float*)(b + o_wft);
   m.bias = (const float*)(b + o_bias);
   m.wout = (const float*)(b + o_wout);
   m.omegas = (const float*)(b + o_om);
@@ -370,6 +380,47 @@ gh_status gh_candidates(const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_
   hipStream_t s = (hipStream_t)stream;
   if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearCands, s), "clear")) != GH_OK) return st;
   return hip_status(gh::launch_candidates(g, w, out, cap, ctr, s), "candidates");
+}
+
+gh_status gh_param_count(const gh_sdb_desc* desc_h, int64_t* count_h) {
+  gh::DevSdb d;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if (d.kind != GH_SDB_MLP) return fail(GH_EUNSUPPORTED, "parameters exist for network bounds only");
+  if (!count_h) return fail(GH_EINVAL, "count_h is NULL");
+  *count_h = gh::mlp_param_count(d.mlp);
+  return GH_OK;
+}
+
+gh_status gh_backward_workspace_size(const gh_sdb_desc* desc_h, int64_t corner_cap, size_t* bytes_h) {
+  gh::DevSdb d;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if (d.kind != GH_SDB_MLP) return fail(GH_EUNSUPPORTED, "the adjoint exists for network bounds only");
+  if (!bytes_h) return fail(GH_EINVAL, "bytes_h is NULL");
+  if (corner_cap <= 0) return fail(GH_EINVAL, "corner_cap must be the workspace's (> 0)");
+  *bytes_h = gh::backward_layout(d.mlp, corner_cap, nullptr, nullptr);
+  return GH_OK;
+}
+
+gh_status gh_backward(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
+                      const float* dL_dverts, float* dL_dtheta, void* bws, size_t bws_bytes, gh_counters* ctr,
+                      void* stream) {
+  gh::DevSdb d;
+  gh::Grid g;
+  gh::Workspace w;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if (d.kind != GH_SDB_MLP) return fail(GH_EUNSUPPORTED, "the adjoint exists for network bounds only");
+  if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
+  if ((st = carve(g, ws, ws_bytes, corner_cap, &w)) != GH_OK) return st;
+  if (!dL_dverts || !dL_dtheta || !ctr || !bws) return fail(GH_EINVAL, "NULL buffer");
+  if (((uintptr_t)bws) & 255) return fail(GH_EINVAL, "backward workspace must be 256-byte aligned");
+  const size_t need = gh::backward_layout(d.mlp, w.cap, nullptr, nullptr);
+  if (bws_bytes < need) return fail(GH_ECAPACITY, "backward workspace of %zu bytes, %zu needed", bws_bytes, need);
+  gh::BackwardWs bw;
+  gh::backward_layout(d.mlp, w.cap, bws, &bw);
+  return hip_status(gh::launch_backward(d, g, w, bw, dL_dverts, dL_dtheta, ctr, (hipStream_t)stream), "backward");
 }
 
 gh_status gh_eval_points(const gh_sdb_desc* desc_h, const float* xyz, float* f, int64_t m, void* stream) {

@@ -298,18 +298,6 @@ __device__ __forceinline__ void for_corner_words(const LatAdj& A, F&& fn) {
   if ((A.uni >> 63) & 1) fn(64);
 }
 
-// List index of corner (L, k), or -1 when (L, k) is not a corner.
-__device__ __forceinline__ int64_t corner_index(const Workspace& ws, size_t nl, size_t L, int k) {
-  const int w = k >> 5;
-  const bool present = w < 64 ? ((ws.lmask[L] >> w) & 1) : (ws.lmhi[L] & 1);
-  if (!present) return -1;
-  const size_t o = (size_t)w * nl + L;
-  const uint32_t word = ws.lbits[o];
-  const uint32_t bit = 1u << (k & 31);
-  if (!(word & bit)) return -1;
-  return (int64_t)ws.lwst[o] + __popc(word & (bit - 1u));
-}
-
 // One thread per lattice column (a, b): its corner words, their starting
 // list indices, its corners, and, when (a, b) is also a cell column, its
 // candidate cells.  One packed scan: (candidates << 31) | corners.

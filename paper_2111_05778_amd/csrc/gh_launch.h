@@ -36,6 +36,23 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
                      float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap, int64_t* cells,
                      uint8_t* cases, int64_t cell_cap, gh_counters* ctr, hipStream_t s);
 hipError_t launch_eval_points(const DevSdb& d, const float* xyz, float* f, int64_t m, hipStream_t s);
+// Workspace of the adjoint (gh_backward).
+constexpr int kVjpBlocks = 256;  // blocks of the network VJP, each with its own partial gradient
+struct BackwardWs {
+  int32_t* cidx;     // [cap] corners with a non-zero cotangent
+  float* cval;       // [cap] their cotangents
+  int64_t* ccount;   // number of them
+  uint64_t* flags;   // look-back words of the compaction
+  size_t nflags;
+  float* zs;         // [kVjpBlocks][depth][64][W] pre-activations of the block's tile
+  float* part;       // [kVjpBlocks][nparams] partial gradients
+  int64_t nparams;
+};
+int64_t mlp_param_count(const MlpDesc& m);
+size_t backward_layout(const MlpDesc& m, int64_t cap, void* base, BackwardWs* bw);
+hipError_t launch_backward(const DevSdb& d, const Grid& g, const Workspace& ws, const BackwardWs& bw,
+                           const float* dldv, float* dldtheta, gh_counters* ctr, hipStream_t s);
+
 // Network kernels: what = 0 points, 1 corner list, 2 enumeration signs, 3 hop.
 hipError_t launch_mlp(int what, const DevSdb& d, const Grid& g, const Workspace* ws, uint32_t* signs,
                       const float* xyz, float* f, int64_t count, gh_counters* ctr, hipStream_t s);

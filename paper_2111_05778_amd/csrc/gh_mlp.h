@@ -38,6 +38,7 @@ struct MlpDesc {
   const uint16_t* wb;   // bf16 bits, packed B fragments of every hidden layer
   const uint16_t* wbl;  // bf16 bits of the remainders w - bf16(w), same packing
   const float* wf;      // float, packed B fragments of every hidden layer
+  const float* wft;     // float, packed B fragments of W_l itself (l >= 1), for the adjoint
   const float* bias;    // [depth][W]
   const float* wout;    // [W]
   const float* omegas;  // [F]
@@ -153,8 +154,9 @@ __device__ __forceinline__ void mlp_features(const MlpDesc& m, MlpSmem& sm, int 
 }
 
 // One hidden layer: act[:, :K] x W_l^T -> bias + softplus -> act[:, :W].
+// With zout, the pre-activations are also stored there ([rows][W], FP32).
 template <int P, int W>
-__device__ __forceinline__ void mlp_layer(const MlpDesc& m, MlpSmem& sm, int l, int nrt) {
+__device__ __forceinline__ void mlp_layer(const MlpDesc& m, MlpSmem& sm, int l, int nrt, float* zout = nullptr) {
   using S = MlpShape<P, W>;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int K = l == 0 ? mlp_k0(m.k1, P) : W;
@@ -228,7 +230,9 @@ __device__ __forceinline__ void mlp_layer(const MlpDesc& m, MlpSmem& sm, int l, 
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
         const int row = (rt0 + rt) * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
-        act_store<P>(sm, row, col, softplus_t<P>(acc[rt][ct][t] + bv));
+        const float z = acc[rt][ct][t] + bv;
+        if (zout) zout[row * W + col] = z;
+        act_store<P>(sm, row, col, softplus_t<P>(z));
       }
     }
   }

@@ -22,7 +22,8 @@ GH_PREC_FP32, GH_PREC_BF16, GH_PREC_BF16X3 = 0, 1, 2
 GH_PRIM_FLOATS = 16
 
 EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
-           "gh_eval_points", "gh_set_tuning", "gh_get_tuning", "gh_last_error"]
+           "gh_eval_points", "gh_set_tuning", "gh_get_tuning", "gh_param_count", "gh_backward_workspace_size",
+           "gh_backward", "gh_last_error"]
 
 
 class gh_grid(ctypes.Structure):
@@ -68,6 +69,9 @@ lib.gh_dense.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp,
 lib.gh_dense_signs_size.argtypes = [_P(gh_grid), _P(_sz)]
 lib.gh_candidates.argtypes = [_P(gh_grid), _vp, _sz, _i64, _vp, _i64, _vp, _vp]
 lib.gh_eval_points.argtypes = [_P(gh_sdb_desc), _vp, _vp, _i64, _vp]
+lib.gh_param_count.argtypes = [_P(gh_sdb_desc), _P(_i64)]
+lib.gh_backward_workspace_size.argtypes = [_P(gh_sdb_desc), _i64, _P(_sz)]
+lib.gh_backward.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp, _sz, _vp, _vp]
 lib.gh_set_tuning.argtypes = [_P(gh_tuning)]
 lib.gh_get_tuning.argtypes = [_P(gh_tuning)]
 lib.gh_last_error.restype = ctypes.c_char_p
@@ -157,3 +161,22 @@ def gh_get_tuning():
     t = gh_tuning()
     check(lib.gh_get_tuning(ctypes.byref(t)), "gh_get_tuning")
     return {"hop_lanes_per_ray": t.hop_lanes_per_ray}
+
+
+def gh_param_count(desc):
+    out = _i64(0)
+    check(lib.gh_param_count(ctypes.byref(desc), ctypes.byref(out)), "gh_param_count")
+    return out.value
+
+
+def gh_backward_workspace_size(desc, corner_cap):
+    out = _sz(0)
+    check(lib.gh_backward_workspace_size(ctypes.byref(desc), int(corner_cap), ctypes.byref(out)),
+          "gh_backward_workspace_size")
+    return out.value
+
+
+def gh_backward(desc, grid, ws, corner_cap, dL_dverts, dL_dtheta, bws, ctr, stream=None):
+    return lib.gh_backward(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
+                           int(corner_cap), ptr(dL_dverts), ptr(dL_dtheta), ptr(bws),
+                           bws.numel() * bws.element_size(), ptr(ctr), stream_handle(stream))
