@@ -209,6 +209,47 @@ gh_status gh_backward(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws
 /* Evaluate the bound at m points xyz [m][3] (device) into f [m] (device). */
 gh_status gh_eval_points(const gh_sdb_desc* desc_h, const float* xyz, float* f, int64_t m, void* stream);
 
+/* ---------------------------------------------------------------- batches
+ * Many bounds on their own grids in one persistent hop launch: work items
+ * (a block tile of ray columns for an analytic bound, a range of rays for a
+ * network) are ordered by estimated cost, longest first, and persistent
+ * blocks take them from one counter; then every shape gets its marching
+ * cubes.  All network bounds of a batch share one precision. */
+typedef struct {
+  gh_sdb_desc desc;                 /* from sdb_describe */
+  gh_grid grid;
+  void* ws;                         /* device workspace of this shape */
+  size_t ws_bytes;
+  int64_t corner_cap;
+  float* verts;                     /* outputs as for gh_mc */
+  int64_t* vert_edge;
+  float* vert_t;
+  int64_t vert_cap;
+  int32_t* tris;
+  int64_t tri_cap;
+  int64_t* cells;
+  uint8_t* cases;
+  int64_t cell_cap;
+  gh_counters* ctr;                 /* device, per shape */
+} gh_batch_item;
+
+typedef struct gh_batch gh_batch;   /* host object of a planned batch */
+
+/* Device bytes of the plan (shape table, work items, item counter). */
+gh_status gh_batch_buffer_size(int n_shapes, const gh_batch_item* items_h, size_t* bytes_h);
+/* Plan a batch into dev_buf (uploads on stream and waits).  The items' buffers
+ * must outlive the plan. */
+gh_status gh_batch_create(int n_shapes, const gh_batch_item* items_h, void* dev_buf, size_t dev_bytes,
+                          void* stream, gh_batch** batch_h);
+/* Enqueue one run: reset counters, batched hop, marching cubes per shape. */
+gh_status gh_batch_run(gh_batch* batch, void* stream);
+/* Capture one run into a hipGraph (replaces a previous capture). */
+gh_status gh_batch_capture(gh_batch* batch, void* stream);
+/* Launch the captured graph on stream. */
+gh_status gh_batch_replay(gh_batch* batch, void* stream);
+gh_status gh_batch_item_count(const gh_batch* batch, int64_t* n_items_h);
+gh_status gh_batch_destroy(gh_batch* batch);
+
 /* Launch shapes of the kernels, process-wide (an autotuner sets them).
  * Fields left at 0 keep the built-in choice. */
 typedef struct {

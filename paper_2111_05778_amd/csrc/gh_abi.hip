@@ -382,6 +382,19 @@ gh_status gh_candidates(const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_
   return hip_status(gh::launch_candidates(g, w, out, cap, ctr, s), "candidates");
 }
 
+gh_status gh_batch_validate_item(const gh_batch_item* it, int index, gh::DevSdb* d, gh::Grid* g, gh::Workspace* w) {
+  gh_status st;
+  if (!it) return fail(GH_EINVAL, "batch item %d is NULL", index);
+  if ((st = read_desc(&it->desc, d)) != GH_OK) return st;
+  if ((st = read_grid(&it->grid, g)) != GH_OK) return st;
+  if ((st = carve(*g, it->ws, it->ws_bytes, it->corner_cap, w)) != GH_OK) return st;
+  if (!it->ctr) return fail(GH_EINVAL, "batch item %d has no counters", index);
+  if (it->vert_cap < 0 || it->tri_cap < 0 || it->cell_cap < 0) return fail(GH_EINVAL, "negative capacity");
+  if ((it->vert_cap > 0 && !it->verts) || (it->tri_cap > 0 && !it->tris))
+    return fail(GH_EINVAL, "batch item %d output buffer is NULL", index);
+  return GH_OK;
+}
+
 gh_status gh_param_count(const gh_sdb_desc* desc_h, int64_t* count_h) {
   gh::DevSdb d;
   gh_status st;

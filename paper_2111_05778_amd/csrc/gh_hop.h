@@ -1,0 +1,251 @@
+// Hop kernels' device functions, shared by the single-bound and the batched
+// launches: the analytic hop over one block tile of ray columns, and the
+// network hop over a pool of rays fed by a ray source.
+#pragma once
+
+#include <float.h>
+
+#include "gh_device.h"
+#include "gh_layout.h"
+#include "gh_mlp.h"
+
+namespace gh {
+
+// --------------------------------------------------------------------- hop
+// R lanes trace one ray together: lane q of the group evaluates primitives
+// q, q + R, q + 2R, ... of each type group (records staged in LDS) and a
+// butterfly over the R lanes forms the union's minimum, which every lane of
+// the group then holds bit for bit.  This divides the latency of one hop
+// step by about R; it matters because the kernel lasts as long as its
+// longest column, and a ray grazing a flat face steps cell by cell (the
+// plane-parallel case of Section 4.1 costs N steps on such a column).
+// A wave covers a compact patch of columns whose step counts are similar.
+template <int R>
+struct HopShape {
+  static constexpr int kWaveRays = 64 / R;
+  static constexpr int kWaveW = R == 1 ? 8 : (R == 2 ? 8 : (R == 4 ? 4 : 4));
+  static constexpr int kWaveH = kWaveRays / kWaveW;
+  static constexpr int kBlockH = 2 * kWaveH, kBlockW = 2 * kWaveW;
+};
+
+// Hop rule (Section 3, eq. iter, cell-quantised): at the centroid of cell k,
+// s = floor(|f| * inv_h); s >= 1 skips s cells, s == 0 marks cell k as a
+// candidate and moves to k + 1; the ray ends when k >= n.  One block tile of
+// columns; srec holds the primitive records in LDS.
+template <int R>
+__device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
+                                               uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
+                                               gh_counters* __restrict__ ctr, int tile) {
+  using S = HopShape<R>;
+  const int n = g.n;
+  const int nbw = (n + S::kBlockW - 1) / S::kBlockW;
+  const int bi = tile / nbw, bj = tile - bi * nbw;
+  const int w = wave_id(), l = lane_id();
+  const int r = l / R, q = l % R;
+  const int i = bi * S::kBlockH + (w >> 1) * S::kWaveH + r / S::kWaveW;
+  const int j = bj * S::kBlockW + (w & 1) * S::kWaveW + r % S::kWaveW;
+  uint64_t evals = 0, cands = 0;
+  bool bad = false;
+  if (i < n && j < n) {  // uniform over the R lanes of a ray
+    const size_t ncol = (size_t)n * n, col = (size_t)i * n + j;
+    const float x = centroid(g, i), y = centroid(g, j);
+    const float nf = (float)n;
+    int k = 0, wi = 0;
+    uint32_t word = 0;
+    uint64_t mask = 0;
+    while (k < n) {
+      float f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y,
+                              centroid(g, k));
+#pragma unroll
+      for (int m = 1; m < R; m <<= 1) f = fminf(f, __shfl_xor(f, m, 64));
+      ++evals;
+      const float d = fabsf(f);
+      if (!(d <= FLT_MAX)) {
+        bad = true;
+        break;
+      }
+      const float s = floorf(d * g.inv_h);
+      if (s == 0.f) {
+        const int kw = k >> 5;
+        if (kw != wi) {
+          if (word && q == 0) colbits[(size_t)wi * ncol + col] = word;
+          if (word) mask |= 1ull << wi;
+          word = 0;
+          wi = kw;
+        }
+        word |= 1u << (k & 31);
+        ++cands;
+        ++k;
+      } else {
+        k += (int)fminf(s, nf);
+      }
+    }
+    if (q == 0) {
+      if (word) {
+        colbits[(size_t)wi * ncol + col] = word;
+        mask |= 1ull << wi;
+      }
+      colmask[col] = mask;
+    }
+  }
+  if (q != 0) evals = cands = 0;
+  if (bad && q == 0) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
+  block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
+}
+
+// Copies the primitive records into LDS (then one barrier).
+__device__ __forceinline__ void stage_prims(float4* s_rec, const float* __restrict__ prims, int np) {
+  for (int t = threadIdx.x; t < np * (GH_PRIM_FLOATS / 4); t += kBlock) s_rec[t] = reinterpret_cast<const float4*>(prims)[t];
+  __syncthreads();
+}
+
+// Rank of this thread among the threads of the block with pred set, and
+// their total.  Contains two barriers: every thread must call it.
+__device__ __forceinline__ int block_rank(bool pred, int* s_cnt, int& total) {
+  const uint64_t bal = __ballot(pred);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) s_cnt[w] = __popcll(bal);
+  __syncthreads();
+  int before = 0;
+  total = 0;
+#pragma unroll
+  for (int q = 0; q < kBlock / 64; ++q) {
+    const int c = s_cnt[q];
+    if (q < w) before += c;
+    total += c;
+  }
+  __syncthreads();
+  return before + __popcll(bal & ((1ull << lane) - 1ull));
+}
+
+// FP32 re-evaluation of the points (x, y, z) of the threads with amb set, in
+// tiles of kF32Rows; returns f updated for those threads.
+template <int W>
+__device__ __forceinline__ float reeval_fp32(const MlpDesc& m, MlpSmem& sm, int* s_cnt, bool amb, float x, float y,
+                                             float z, float f, uint64_t& reevals) {
+  int namb;
+  const int arow = block_rank(amb, s_cnt, namb);
+  for (int base = 0; base < namb; base += kF32Rows) {
+    const bool mine = amb && arow >= base && arow < base + kF32Rows;
+    if (mine) {
+      sm.pts[arow - base][0] = x;
+      sm.pts[arow - base][1] = y;
+      sm.pts[arow - base][2] = z;
+    }
+    __syncthreads();
+    mlp_tile<kPrecF32, W>(m, sm, namb - base < kF32Rows ? namb - base : kF32Rows);
+    if (mine) f = sm.f[arow - base];
+    __syncthreads();
+  }
+  reevals += amb ? 1 : 0;
+  return f;
+}
+
+// A block keeps a pool of R rays (one per owner thread, R = tile rows).  Each
+// round it refills finished slots from the ray source (rays [first, end) of
+// the column order, taken through src.take), packs the live rays into the
+// first rows, evaluates their current hop points as one tile (only the row
+// tiles in use), certifies the bf16 values and applies the hop rule (Section
+// 3, eq. iter, cell-quantised).
+template <int P, int W, class Src>
+__device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, uint64_t* __restrict__ colmask,
+                                             uint32_t* __restrict__ colbits, gh_counters* __restrict__ ctr,
+                                             MlpSmem& sm, int* s_cnt, unsigned int* s_base, Src src) {
+  constexpr int R = mlp_rows<P>();
+  const int n = g.n;
+  const size_t ncol = (size_t)n * n;
+  const bool owner = (int)threadIdx.x < R;
+  const float nf = (float)n;
+  bool active = false, bad = false;
+  size_t col = 0;
+  int k = 0, wi = 0;
+  uint32_t word = 0;
+  uint64_t mask = 0;
+  float x = 0.f, y = 0.f;
+  uint64_t evals = 0, cands = 0, reevals = 0;
+  for (;;) {
+    // refill finished slots with the next rays
+    int total;
+    const bool want = owner && !active;
+    const int fr = block_rank(want, s_cnt, total);
+    if (threadIdx.x == 0) *s_base = total ? src.take((unsigned)total) : 0u;
+    __syncthreads();
+    if (want) {
+      const int64_t idx = src.first + (int64_t)*s_base + fr;
+      if (idx < src.end) {
+        active = true;
+        col = (size_t)idx;
+        x = centroid(g, (int)(idx / n));
+        y = centroid(g, (int)(idx % n));
+        k = 0;
+        wi = 0;
+        word = 0;
+        mask = 0;
+      }
+    }
+    // pack the live rays into rows [0, nact)
+    int nact;
+    const bool live = owner && active;
+    const int row = block_rank(live, s_cnt, nact);
+    if (nact == 0) break;  // uniform: the queue is empty and every slot is idle
+    const float z = centroid(g, k);
+    if (live) {
+      sm.pts[row][0] = x;
+      sm.pts[row][1] = y;
+      sm.pts[row][2] = z;
+    }
+    __syncthreads();
+    mlp_tile<P, W>(m, sm, nact);
+    float d = live ? fabsf(sm.f[row]) : 0.f;
+    __syncthreads();
+    if constexpr (P != kPrecF32) {
+      bool amb = false;
+      if (live && d <= FLT_MAX)
+        amb = floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
+      d = fabsf(reeval_fp32<W>(m, sm, s_cnt, amb, x, y, z, d, reevals));
+    }
+    if (live) {
+      ++evals;
+      bool done = false;
+      if (!(d <= FLT_MAX)) {
+        bad = true;
+        done = true;
+      } else {
+        const float s = floorf(d * g.inv_h);
+        if (s == 0.f) {
+          const int kw = k >> 5;
+          if (kw != wi) {
+            if (word) {
+              colbits[(size_t)wi * ncol + col] = word;
+              mask |= 1ull << wi;
+            }
+            word = 0;
+            wi = kw;
+          }
+          word |= 1u << (k & 31);
+          ++cands;
+          ++k;
+        } else {
+          k += (int)fminf(s, nf);
+        }
+        done = k >= n;
+      }
+      if (done) {
+        if (word) {
+          colbits[(size_t)wi * ncol + col] = word;
+          mask |= 1ull << wi;
+        }
+        colmask[col] = mask;
+        active = false;
+      }
+    }
+  }
+  if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
+  block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
+  block_add_u64(reevals, (unsigned long long*)&ctr->n_reeval);
+}
+
+
+}  // namespace gh

@@ -17,6 +17,7 @@
 #include "gh_device.h"
 #include "gh_launch.h"
 #include "gh_layout.h"
+#include "gh_hop.h"
 #include "mc_table.h"
 
 namespace gh {
@@ -50,92 +51,13 @@ __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, u
 }
 
 // --------------------------------------------------------------------- hop
-// R lanes trace one ray together: lane q of the group evaluates primitives
-// q, q + R, q + 2R, ... of each type group (records staged in LDS) and a
-// butterfly over the R lanes forms the union's minimum, which every lane of
-// the group then holds bit for bit.  This divides the latency of one hop
-// step by about R; it matters because the kernel lasts as long as its
-// longest column, and a ray grazing a flat face steps cell by cell (the
-// plane-parallel case of Section 4.1 costs N steps on such a column).
-// A wave covers a compact patch of columns whose step counts are similar.
-template <int R>
-struct HopShape {
-  static constexpr int kWaveRays = 64 / R;
-  static constexpr int kWaveW = R == 1 ? 8 : (R == 2 ? 8 : (R == 4 ? 4 : 4));
-  static constexpr int kWaveH = kWaveRays / kWaveW;
-  static constexpr int kBlockH = 2 * kWaveH, kBlockW = 2 * kWaveW;
-};
-
-// Hop rule (Section 3, eq. iter, cell-quantised): at the centroid of cell k,
-// s = floor(|f| * inv_h); s >= 1 skips s cells, s == 0 marks cell k as a
-// candidate and moves to k + 1; the ray ends when k >= n.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_hop_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                       uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                       gh_counters* __restrict__ ctr) {
-  using S = HopShape<R>;
   __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
-  const int np = groups.start[kPrimTypes];
-  for (int t = threadIdx.x; t < np * (GH_PRIM_FLOATS / 4); t += kBlock)
-    s_rec[t] = reinterpret_cast<const float4*>(prims)[t];
-  __syncthreads();
-  const float* srec = reinterpret_cast<const float*>(s_rec);
-
-  const int n = g.n;
-  const int nbw = (n + S::kBlockW - 1) / S::kBlockW;
-  const int bi = blockIdx.x / nbw, bj = blockIdx.x - bi * nbw;
-  const int w = wave_id(), l = lane_id();
-  const int r = l / R, q = l % R;
-  const int i = bi * S::kBlockH + (w >> 1) * S::kWaveH + r / S::kWaveW;
-  const int j = bj * S::kBlockW + (w & 1) * S::kWaveW + r % S::kWaveW;
-  uint64_t evals = 0, cands = 0;
-  bool bad = false;
-  if (i < n && j < n) {  // uniform over the R lanes of a ray
-    const size_t ncol = (size_t)n * n, col = (size_t)i * n + j;
-    const float x = centroid(g, i), y = centroid(g, j);
-    const float nf = (float)n;
-    int k = 0, wi = 0;
-    uint32_t word = 0;
-    uint64_t mask = 0;
-    while (k < n) {
-      float f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y,
-                              centroid(g, k));
-#pragma unroll
-      for (int m = 1; m < R; m <<= 1) f = fminf(f, __shfl_xor(f, m, 64));
-      ++evals;
-      const float d = fabsf(f);
-      if (!(d <= FLT_MAX)) {
-        bad = true;
-        break;
-      }
-      const float s = floorf(d * g.inv_h);
-      if (s == 0.f) {
-        const int kw = k >> 5;
-        if (kw != wi) {
-          if (word && q == 0) colbits[(size_t)wi * ncol + col] = word;
-          if (word) mask |= 1ull << wi;
-          word = 0;
-          wi = kw;
-        }
-        word |= 1u << (k & 31);
-        ++cands;
-        ++k;
-      } else {
-        k += (int)fminf(s, nf);
-      }
-    }
-    if (q == 0) {
-      if (word) {
-        colbits[(size_t)wi * ncol + col] = word;
-        mask |= 1ull << wi;
-      }
-      colmask[col] = mask;
-    }
-  }
-  if (q != 0) evals = cands = 0;
-  if (bad && q == 0) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
-  block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
-  block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
+  stage_prims(s_rec, prims, groups.start[kPrimTypes]);
+  hop_prims_tile<R>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, ctr, blockIdx.x);
 }
 
 // ------------------------------------------------------------ enumeration

@@ -13,51 +13,10 @@
 #include "gh_device.h"
 #include "gh_launch.h"
 #include "gh_layout.h"
+#include "gh_hop.h"
 #include "gh_mlp.h"
 
 namespace gh {
-
-// Rank of this thread among the threads of the block with pred set, and
-// their total.  Contains two barriers: every thread must call it.
-__device__ __forceinline__ int block_rank(bool pred, int* s_cnt, int& total) {
-  const uint64_t bal = __ballot(pred);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) s_cnt[w] = __popcll(bal);
-  __syncthreads();
-  int before = 0;
-  total = 0;
-#pragma unroll
-  for (int q = 0; q < kBlock / 64; ++q) {
-    const int c = s_cnt[q];
-    if (q < w) before += c;
-    total += c;
-  }
-  __syncthreads();
-  return before + __popcll(bal & ((1ull << lane) - 1ull));
-}
-
-// FP32 re-evaluation of the points (x, y, z) of the threads with amb set, in
-// tiles of kF32Rows; returns f updated for those threads.
-template <int W>
-__device__ __forceinline__ float reeval_fp32(const MlpDesc& m, MlpSmem& sm, int* s_cnt, bool amb, float x, float y,
-                                             float z, float f, uint64_t& reevals) {
-  int namb;
-  const int arow = block_rank(amb, s_cnt, namb);
-  for (int base = 0; base < namb; base += kF32Rows) {
-    const bool mine = amb && arow >= base && arow < base + kF32Rows;
-    if (mine) {
-      sm.pts[arow - base][0] = x;
-      sm.pts[arow - base][1] = y;
-      sm.pts[arow - base][2] = z;
-    }
-    __syncthreads();
-    mlp_tile<kPrecF32, W>(m, sm, namb - base < kF32Rows ? namb - base : kF32Rows);
-    if (mine) f = sm.f[arow - base];
-    __syncthreads();
-  }
-  reevals += amb ? 1 : 0;
-  return f;
-}
 
 // ------------------------------------------------------------- point lists
 template <int P, int W>
@@ -167,11 +126,13 @@ __global__ __launch_bounds__(kBlock) void k_mlp_dense(MlpDesc m, Grid g, uint32_
 }
 
 // --------------------------------------------------------------------- hop
-// A block keeps a pool of R rays (one per owner thread, R = tile rows).  Each
-// round it refills finished slots from a global ray counter, packs the live
-// rays into the first rows, evaluates their current hop points as one tile
-// (only the row tiles in use), certifies the bf16 values and applies the hop
-// rule (Section 3, eq. iter, cell-quantised).
+// Rays from a global counter over all n^2 columns.
+struct QueueRays {
+  unsigned int* queue;
+  int64_t first, end;
+  __device__ unsigned int take(unsigned int k) const { return atomicAdd(queue, k); }
+};
+
 template <int P, int W>
 __global__ __launch_bounds__(kBlock) void k_hop_mlp(MlpDesc m, Grid g, uint64_t* __restrict__ colmask,
                                                     uint32_t* __restrict__ colbits, unsigned int* __restrict__ queue,
@@ -179,100 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_mlp(MlpDesc m, Grid g, uint64_t*
   __shared__ MlpSmem sm;
   __shared__ int s_cnt[kBlock / 64];
   __shared__ unsigned int s_base;
-  constexpr int R = mlp_rows<P>();
-  const int n = g.n;
-  const int64_t nrays = (int64_t)n * n;
-  const size_t ncol = (size_t)nrays;
-  const bool owner = (int)threadIdx.x < R;
-  const float nf = (float)n;
-  bool active = false, bad = false;
-  size_t col = 0;
-  int k = 0, wi = 0;
-  uint32_t word = 0;
-  uint64_t mask = 0;
-  float x = 0.f, y = 0.f;
-  uint64_t evals = 0, cands = 0, reevals = 0;
-  for (;;) {
-    // refill finished slots with the next rays
-    int total;
-    const bool want = owner && !active;
-    const int fr = block_rank(want, s_cnt, total);
-    if (threadIdx.x == 0) s_base = total ? atomicAdd(queue, (unsigned)total) : 0u;
-    __syncthreads();
-    if (want) {
-      const int64_t idx = (int64_t)s_base + fr;
-      if (idx < nrays) {
-        active = true;
-        col = (size_t)idx;
-        x = centroid(g, (int)(idx / n));
-        y = centroid(g, (int)(idx % n));
-        k = 0;
-        wi = 0;
-        word = 0;
-        mask = 0;
-      }
-    }
-    // pack the live rays into rows [0, nact)
-    int nact;
-    const bool live = owner && active;
-    const int row = block_rank(live, s_cnt, nact);
-    if (nact == 0) break;  // uniform: the queue is empty and every slot is idle
-    const float z = centroid(g, k);
-    if (live) {
-      sm.pts[row][0] = x;
-      sm.pts[row][1] = y;
-      sm.pts[row][2] = z;
-    }
-    __syncthreads();
-    mlp_tile<P, W>(m, sm, nact);
-    float d = live ? fabsf(sm.f[row]) : 0.f;
-    __syncthreads();
-    if constexpr (P != kPrecF32) {
-      bool amb = false;
-      if (live && d <= FLT_MAX)
-        amb = floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
-      d = fabsf(reeval_fp32<W>(m, sm, s_cnt, amb, x, y, z, d, reevals));
-    }
-    if (live) {
-      ++evals;
-      bool done = false;
-      if (!(d <= FLT_MAX)) {
-        bad = true;
-        done = true;
-      } else {
-        const float s = floorf(d * g.inv_h);
-        if (s == 0.f) {
-          const int kw = k >> 5;
-          if (kw != wi) {
-            if (word) {
-              colbits[(size_t)wi * ncol + col] = word;
-              mask |= 1ull << wi;
-            }
-            word = 0;
-            wi = kw;
-          }
-          word |= 1u << (k & 31);
-          ++cands;
-          ++k;
-        } else {
-          k += (int)fminf(s, nf);
-        }
-        done = k >= n;
-      }
-      if (done) {
-        if (word) {
-          colbits[(size_t)wi * ncol + col] = word;
-          mask |= 1ull << wi;
-        }
-        colmask[col] = mask;
-        active = false;
-      }
-    }
-  }
-  if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
-  block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
-  block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
-  block_add_u64(reevals, (unsigned long long*)&ctr->n_reeval);
+  hop_mlp_pool<P, W>(m, g, colmask, colbits, ctr, sm, s_cnt, &s_base, QueueRays{queue, 0, (int64_t)g.n * g.n});
 }
 
 // ================================================================ launchers

@@ -23,7 +23,8 @@ GH_PRIM_FLOATS = 16
 
 EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
            "gh_eval_points", "gh_set_tuning", "gh_get_tuning", "gh_param_count", "gh_backward_workspace_size",
-           "gh_backward", "gh_last_error"]
+           "gh_backward", "gh_batch_buffer_size", "gh_batch_create", "gh_batch_run", "gh_batch_capture",
+           "gh_batch_replay", "gh_batch_item_count", "gh_batch_destroy", "gh_last_error"]
 
 
 class gh_grid(ctypes.Structure):
@@ -57,6 +58,14 @@ class gh_sdb_desc(ctypes.Structure):
     _fields_ = [("opaque", ctypes.c_uint64 * 24)]
 
 
+class gh_batch_item(ctypes.Structure):
+    _fields_ = [("desc", gh_sdb_desc), ("grid", gh_grid), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+                ("corner_cap", ctypes.c_int64), ("verts", ctypes.c_void_p), ("vert_edge", ctypes.c_void_p),
+                ("vert_t", ctypes.c_void_p), ("vert_cap", ctypes.c_int64), ("tris", ctypes.c_void_p),
+                ("tri_cap", ctypes.c_int64), ("cells", ctypes.c_void_p), ("cases", ctypes.c_void_p),
+                ("cell_cap", ctypes.c_int64), ("ctr", ctypes.c_void_p)]
+
+
 _vp, _i64, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
 _P = ctypes.POINTER
 
@@ -72,6 +81,13 @@ lib.gh_eval_points.argtypes = [_P(gh_sdb_desc), _vp, _vp, _i64, _vp]
 lib.gh_param_count.argtypes = [_P(gh_sdb_desc), _P(_i64)]
 lib.gh_backward_workspace_size.argtypes = [_P(gh_sdb_desc), _i64, _P(_sz)]
 lib.gh_backward.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp, _sz, _vp, _vp]
+lib.gh_batch_buffer_size.argtypes = [ctypes.c_int, _P(gh_batch_item), _P(_sz)]
+lib.gh_batch_create.argtypes = [ctypes.c_int, _P(gh_batch_item), _vp, _sz, _vp, _P(_vp)]
+lib.gh_batch_run.argtypes = [_vp, _vp]
+lib.gh_batch_capture.argtypes = [_vp, _vp]
+lib.gh_batch_replay.argtypes = [_vp, _vp]
+lib.gh_batch_item_count.argtypes = [_vp, _P(_i64)]
+lib.gh_batch_destroy.argtypes = [_vp]
 lib.gh_set_tuning.argtypes = [_P(gh_tuning)]
 lib.gh_get_tuning.argtypes = [_P(gh_tuning)]
 lib.gh_last_error.restype = ctypes.c_char_p
@@ -180,3 +196,38 @@ def gh_backward(desc, grid, ws, corner_cap, dL_dverts, dL_dtheta, bws, ctr, stre
     return lib.gh_backward(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
                            int(corner_cap), ptr(dL_dverts), ptr(dL_dtheta), ptr(bws),
                            bws.numel() * bws.element_size(), ptr(ctr), stream_handle(stream))
+
+
+def gh_batch_buffer_size(items):
+    out = _sz(0)
+    check(lib.gh_batch_buffer_size(len(items), items, ctypes.byref(out)), "gh_batch_buffer_size")
+    return out.value
+
+
+def gh_batch_create(items, buf, stream=None):
+    handle = _vp()
+    check(lib.gh_batch_create(len(items), items, ptr(buf), buf.numel(), stream_handle(stream), ctypes.byref(handle)),
+          "gh_batch_create")
+    return handle
+
+
+def gh_batch_run(handle, stream=None):
+    return lib.gh_batch_run(handle, stream_handle(stream))
+
+
+def gh_batch_capture(handle, stream=None):
+    return lib.gh_batch_capture(handle, stream_handle(stream))
+
+
+def gh_batch_replay(handle, stream=None):
+    return lib.gh_batch_replay(handle, stream_handle(stream))
+
+
+def gh_batch_item_count(handle):
+    out = _i64(0)
+    check(lib.gh_batch_item_count(handle, ctypes.byref(out)), "gh_batch_item_count")
+    return out.value
+
+
+def gh_batch_destroy(handle):
+    return lib.gh_batch_destroy(handle)

@@ -175,3 +175,85 @@ class Polygonizer:
                 "gh_candidates")
         torch.cuda.synchronize(self.device)
         return out[:c["n_cand"]]
+
+
+class BatchPolygonizer:
+    """Many (bound, grid) pairs through gh_batch_*: one persistent hop launch,
+    marching cubes per shape, optionally replayed from a captured hipGraph.
+
+    shapes: list of (Bound, n, lo, h).  Buffers are sized like Polygonizer's
+    defaults; run() re-plans with larger buffers when a capacity was short."""
+
+    def __init__(self, shapes, device="cuda", keep_cells=True):
+        self.device = torch.device(device)
+        self.polys = [Polygonizer(b, n, lo, h, device=self.device, keep_cells=keep_cells) for (b, n, lo, h) in shapes]
+        self._plan()
+
+    def _plan(self):
+        self.items = (N.gh_batch_item * len(self.polys))()
+        for it, p in zip(self.items, self.polys):
+            it.desc = p.bound.desc
+            it.grid = p.grid
+            it.ws, it.ws_bytes, it.corner_cap = p.ws.data_ptr(), p.ws.numel(), p.corner_cap
+            it.verts, it.vert_cap = p.verts.data_ptr(), p.vert_cap
+            it.vert_edge = p.vert_edge.data_ptr() if p.vert_edge is not None else None
+            it.vert_t = p.vert_t.data_ptr() if p.vert_t is not None else None
+            it.tris, it.tri_cap = p.tris.data_ptr(), p.tri_cap
+            it.cells = p.cells.data_ptr() if p.cells is not None else None
+            it.cases = p.cases.data_ptr() if p.cases is not None else None
+            it.cell_cap = p.cell_cap if p.keep_cells else 0
+            it.ctr = p.ctr.data_ptr()
+        self.buf = torch.empty(N.gh_batch_buffer_size(self.items), dtype=torch.uint8, device=self.device)
+        self.handle = N.gh_batch_create(self.items, self.buf)
+        self.captured = False
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            N.gh_batch_destroy(h)
+
+    def item_count(self):
+        return N.gh_batch_item_count(self.handle)
+
+    def enqueue(self, stream=None):
+        N.check(N.gh_batch_run(self.handle, stream), "gh_batch_run")
+
+    def capture(self):
+        """Records the batch into a hipGraph.  Capture needs a stream other
+        than the null stream, so the graph lives on a side stream that
+        replay() orders after, and before, torch's current stream."""
+        self.graph_stream = torch.cuda.Stream(self.device)
+        self.graph_stream.wait_stream(torch.cuda.current_stream(self.device))
+        N.check(N.gh_batch_capture(self.handle, self.graph_stream), "gh_batch_capture")
+        self.captured = True
+
+    def replay(self):
+        cur = torch.cuda.current_stream(self.device)
+        self.graph_stream.wait_stream(cur)
+        N.check(N.gh_batch_replay(self.handle, self.graph_stream), "gh_batch_replay")
+        cur.wait_stream(self.graph_stream)
+
+    def run(self, max_retries=3):
+        for _ in range(max_retries + 1):
+            self.enqueue()
+            torch.cuda.synchronize(self.device)
+            cs = [counters_dict(p.ctr) for p in self.polys]
+            if any(c["flags"] & (N.GH_FLAG_INTERNAL | N.GH_FLAG_NONFINITE) for c in cs):
+                raise RuntimeError(f"batch flags: {[c['flags'] for c in cs]}")
+            short = [c["flags"] & N.GH_FLAG_CAPACITY for c in cs]
+            if not any(short):
+                return [p.result(c) for p, c in zip(self.polys, cs)]
+            for p, c, sh in zip(self.polys, cs, short):
+                if sh:
+                    p.corner_cap = max(p.corner_cap, int(c["n_corner"] * 1.25) + 64)
+                    p.vert_cap = max(p.vert_cap, int(c["n_vert"] * 1.25) + 64)
+                    p.tri_cap = max(p.tri_cap, int(c["n_tri"] * 1.25) + 64)
+                    p.cell_cap = max(p.cell_cap, int(c["n_cells"] * 1.25) + 64)
+                    p._alloc()
+            N.gh_batch_destroy(self.handle)
+            self.handle = None
+            self._plan()
+        raise RuntimeError("capacity retries exhausted")
+
+    def results(self):
+        return [p.result() for p in self.polys]

@@ -33,7 +33,7 @@ def _gpu_grad(torch, net, n, lo, h, targets, precision="fp32", margin=0.0):
         nearest = torch.cdist(V, Q).argmin(dim=1)
     L = ((V - Q[nearest]) ** 2).sum(dim=1).mean()
     L.backward()
-    return float(L), theta.grad.detach().cpu().numpy().astype(np.float64)
+    return float(L.detach()), theta.grad.detach().cpu().numpy().astype(np.float64)
 
 
 @pytest.mark.parametrize("width,n", [(64, 48), (256, 64)])
