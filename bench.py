@@ -10,6 +10,13 @@ marching cubes on every cell, same emit) is timed beside it.
 Prints one JSON line.  Extra objects:
   roofline      the hop kernel against the FP32 VALU peak of the chip
   cpu_baseline  the oracle (FP64 numpy, one thread) on the same workload
+  neural        the network bound (width 256, depth 4, 16 frequencies) at
+                N = 512 in split bf16 on MFMA, with its own MFMA roofline
+                and the enumeration path beside it
+  backward      the adjoint of the mean squared vertex-to-target loss for the
+                same network at N = 256, FP32 forward (milliseconds)
+  batch         64 bounds on grids of 64..512, one persistent hop launch plus
+                marching cubes per shape, replayed from a hipGraph
 """
 import argparse
 import hashlib
@@ -26,6 +33,7 @@ sys.path.insert(0, ROOT)
 # an FMA as two operations and packed math as two more).
 PEAK_FP32_OPS = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
+PEAK_BF16_MFMA = 2.5e15   # dense, no sparsity
 
 # FP32 operations per evaluation of each primitive type, counted from the
 # formula in include/gh.h (add, sub, mul, min, max, abs, neg, sqrt each 1):
@@ -44,9 +52,15 @@ def ops_per_eval(records):
     return sum(OPS[t] for t in types) + (len(types) - 1)   # plus the union minima
 
 
+def mlp_flop_per_point(width, depth, n_freq):
+    """Multiply-adds x 2 of one network evaluation (features, hidden layers, output)."""
+    k1 = 3 + 6 * n_freq
+    return 2 * (k1 * width + (depth - 1) * width * width + width)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("gh_kernels.hip", "gh_device.h"):
+    for name in ("gh_kernels.hip", "gh_device.h", "gh_hop.h"):
         with open(os.path.join(ROOT, "paper_2111_05778_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -84,6 +98,124 @@ def cpu_baseline(recs, n, lo, h):
             "sample": f"the full workload (N={n}, all {n * n} columns), best of 2 runs, {t:.2f} s"}
 
 
+def event_ms(stream, fn, reps):
+    """Mean duration (ms) of fn's enqueued work over reps runs, by HIP events
+    on the stream it enqueues on."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps
+
+
+def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", dense=True):
+    import torch
+
+    import workloads as W
+    from paper_2111_05778_amd.polygonize import Bound, Polygonizer, bf16_margin
+    net = W.neural_scene(0, width)
+    n, lo, h = W.grid(n)
+    margin = bf16_margin(net, W.probe_points(seed=3, n=65536), precision) if precision != "fp32" else 0.0
+    poly = Polygonizer(Bound.mlp(net, precision, margin=margin, device=dev), n, lo, h, device=dev, keep_cells=False)
+    c0 = dict(poly.run().counters)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(warmup):
+        poly.enqueue_hop()
+        poly.enqueue_mc()
+    hop_ms = event_ms(stream, poly.enqueue_hop, steps)
+    mc_ms = event_ms(stream, poly.enqueue_mc, steps)
+    fpp = mlp_flop_per_point(width, 4, 16)
+    flop = c0["n_hop_evals"] * fpp
+    out = {"workload": f"mlp_w{width}_d4_f16_seed0_n{n}", "precision": precision, "margin": margin,
+           "value": n ** 3 / ((hop_ms + mc_ms) * 1e-3), "unit": "cells/s", "hop_ms": hop_ms, "mc_ms": mc_ms,
+           "counters": {k: c0[k] for k in ("n_hop_evals", "n_reeval", "n_corner", "n_vert", "n_tri")},
+           "roofline": {"bound": "mfma", "kernel": "k_hop_mlp", "achieved": flop / (hop_ms * 1e-3) / 1e12,
+                        "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
+                        "frac": flop / (hop_ms * 1e-3) / PEAK_BF16_MFMA, "traffic": None,
+                        "flop_per_point": fpp, "per_launch_flop": flop}}
+    if dense:
+        poly.enqueue_dense()
+        poly.enqueue_mc()
+        torch.cuda.synchronize(dev)
+        d_ms = event_ms(stream, lambda: (poly.enqueue_dense(), poly.enqueue_mc()), 1)
+        out["dense_ms"] = d_ms
+        out["speedup_vs_dense"] = d_ms / (hop_ms + mc_ms)
+    return out
+
+
+def backward_section(dev, steps, warmup, n=256, width=256):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2111_05778_amd import native as N
+    from paper_2111_05778_amd.polygonize import Bound, Polygonizer
+    net = W.neural_scene(0, width)
+    n, lo, h = W.grid(n)
+    poly = Polygonizer(Bound.mlp(net, "fp32", device=dev), n, lo, h, device=dev)
+    mesh = poly.run()
+    V = mesh.verts
+    Q = torch.tensor(W.loss_targets().astype(np.float32), device=dev)
+    nearest = torch.cdist(V, Q).argmin(dim=1)
+    dV = (2.0 / V.shape[0]) * (V - Q[nearest])
+    desc = poly.bound.desc
+    P = N.gh_param_count(desc)
+    grad = torch.empty(P, dtype=torch.float32, device=dev)
+    bws = torch.empty(N.gh_backward_workspace_size(desc, poly.corner_cap), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def bwd():
+        N.check(N.gh_backward(desc, poly.grid, poly.ws, poly.corner_cap, dV, grad, bws, poly.ctr), "gh_backward")
+
+    for _ in range(warmup):
+        bwd()
+    fwd_ms = event_ms(stream, lambda: (poly.enqueue_hop(), poly.enqueue_mc()), steps)
+    bwd()
+    bwd_ms = event_ms(stream, bwd, steps)
+    return {"workload": f"mlp_w{width}_d4_f16_seed0_n{n}_fp32", "backward_ms": bwd_ms, "forward_ms": fwd_ms,
+            "n_vert": int(V.shape[0]), "params": P, "grad_norm": float(grad.norm())}
+
+
+def batch_section(dev, steps, warmup, precision="bf16x3"):
+    import torch
+
+    import workloads as W
+    from paper_2111_05778_amd.polygonize import BatchPolygonizer, Bound, bf16_margin
+    scenes = W.batch_scenes()
+    probe = W.probe_points(seed=3, n=65536)
+    shapes = []
+    for sc in scenes:
+        n, lo, h = W.grid(sc["n"])
+        if sc["kind"] == "csg":
+            b = Bound.prims(W.csg_scene(sc["seed"], sc["n_prim"]), dev)
+        else:
+            net = W.neural_scene(sc["seed"], sc["width"])
+            b = Bound.mlp(net, precision, margin=bf16_margin(net, probe, precision), device=dev)
+        shapes.append((b, n, lo, h))
+    batch = BatchPolygonizer(shapes, device=dev, keep_cells=False)
+    res = batch.run()
+    ref = [dict(m.counters) for m in res]
+    batch.capture()
+    for _ in range(warmup):
+        batch.replay()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.replay()
+    torch.cuda.synchronize(dev)
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    from paper_2111_05778_amd.polygonize import counters_dict
+    for p, c in zip(batch.polys, ref):
+        assert counters_dict(p.ctr)["n_tri"] == c["n_tri"]
+    cells = sum(sc["n"] ** 3 for sc in scenes)
+    return {"workload": "batch64_seed2", "precision": precision, "shapes": len(scenes), "cells": cells,
+            "work_items": batch.item_count(), "ms_per_step": ms, "value": cells / (ms * 1e-3), "unit": "cells/s",
+            "n_tri": sum(c["n_tri"] for c in ref)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,7 +225,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes five times (the known-size kernel "
+                         "that scales the HBM counters) and exit")
+    ap.add_argument("--sections", default="neural,backward,batch",
+                    help="extra workloads to measure after the headline one (comma list, or none)")
     args = ap.parse_args()
+    sections = [x for x in args.sections.split(",") if x and x != "none"]
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (each ray column is "
               f"independent, the multi-GPU split is described in DESIGN.md)", file=sys.stderr)
@@ -101,10 +239,19 @@ def main():
 
     import torch
 
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        x = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize(dev)
+        print(json.dumps({"copy_bytes": args.copy_calibration, "launches": 5}), flush=True)
+        return
+
     import workloads as W
     from paper_2111_05778_amd.polygonize import Bound, Polygonizer
 
-    dev = torch.device("cuda:0")
     n, lo, h = W.grid(args.n)
     recs = W.csg_scene(args.seed)
     poly = Polygonizer(Bound.prims(recs, dev), n, lo, h, device=dev, keep_cells=False)
@@ -160,7 +307,7 @@ def main():
                 "mc_ms": 1e3 * sum(t_mc) / len(t_mc)}
 
     out = {
-        "metric": "grid cells/s polygonized (N^3/t) at N=512",
+        "metric": "grid cells/s polygonized (N\u00b3/t) at N=512 + backward ms; vs dense MC",
         "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
@@ -172,6 +319,14 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(recs, n, lo, h),
     }
+    sw = max(1, args.warmup)
+    if "neural" in sections:
+        out["neural"] = neural_section(dev, max(3, args.steps // 4), sw, dense=not args.no_dense)
+    if "backward" in sections:
+        out["backward"] = backward_section(dev, max(3, args.steps // 4), sw)
+        out["backward_ms"] = out["backward"]["backward_ms"]
+    if "batch" in sections:
+        out["batch"] = batch_section(dev, max(3, args.steps // 4), sw)
     print(json.dumps(out), flush=True)
 
 
