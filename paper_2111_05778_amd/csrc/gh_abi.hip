@@ -109,11 +109,9 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   }
   for (int q = 0; q < F; ++q)
     if (!finite_bounded(sp->omegas_h[q], 1e4f)) return fail(GH_EINVAL, "frequency %d not finite", q);
-  size_t nb = 0, nf = 0;
-  for (int l = 0; l < D; ++l) {
-    nb += gh::mlp_layer_elems(l, k1, W, gh::kPrecBf16);
-    nf += gh::mlp_layer_elems(l, k1, W, gh::kPrecF32);
-  }
+  const size_t nb = gh::mlpa_layer_offset(D, W);
+  size_t nf = 0;
+  for (int l = 0; l < D; ++l) nf += gh::mlp_layer_elems(l, k1, W);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -121,44 +119,55 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
     return o;
   };
   const size_t nft = (size_t)(D - 1) * W * W;
-  const size_t o_wb = take(nb * 2), o_wbl = take(nb * 2), o_wf = take(nf * 4), o_wft = take(nft * 4 + 4), o_bias = take((size_t)D * W * 4), o_wout = take((size_t)W * 4),
-               o_om = take(16 * 4);
+  const size_t o_wa = take(nb * 2), o_wal = take(nb * 2), o_wf = take(nf * 4), o_wft = take(nft * 4 + 4),
+               o_bias = take((size_t)D * W * 4), o_wout = take((size_t)W * 4), o_om = take(16 * 4),
+               o_omrev = take(16 * 4);
   const size_t need = off;
   if (blob_needed_h) *blob_needed_h = need;
   if (!dev_blob) return desc_h ? fail(GH_EINVAL, "dev_blob is NULL") : GH_OK;
   if (blob_bytes < need) return fail(GH_ECAPACITY, "blob of %zu bytes, %zu needed", blob_bytes, need);
   if (!desc_h) return fail(GH_EINVAL, "desc is NULL");
   std::vector<unsigned char> host(need, 0);
-  uint16_t* wb = (uint16_t*)(host.data() + o_wb);
-  uint16_t* wbl = (uint16_t*)(host.data() + o_wbl);
+  uint16_t* wa = (uint16_t*)(host.data() + o_wa);
+  uint16_t* wal = (uint16_t*)(host.data() + o_wal);
   float* wf = (float*)(host.data() + o_wf);
+  // Frequencies in turns per unit for the register evaluator's hardware sine.
+  {
+    float* om = (float*)(host.data() + o_omrev);
+    for (int q = 0; q < F; ++q) om[q] = (float)((double)sp->omegas_h[q] / (2.0 * M_PI));
+  }
   for (int l = 0; l < D; ++l) {
     const float* Wl = sp->weights_h[l];  // W x fan_in, row-major
     const int fi = l == 0 ? k1 : W;
     const int CT = W / 32;
-    // bf16: fragment (kt, ct), lane, element i -> W[ct*32 + lane%32][kt*16 + 8*(lane/32) + i]
+    // bf16 A fragments: (k-step s, m-tile c), lane, element i ->
+    //   W_l[32c + lane%32][input of slot 16s + 8(lane/32) + i]; for l >= 1 the
+    //   slot holds the permuted feature (the previous tile's register order).
     {
-      const int K = gh::mlp_k0(k1, gh::kPrecBf16) * (l == 0) + W * (l != 0);
-      uint16_t* dst = wb + gh::mlp_layer_offset(l, k1, W, gh::kPrecBf16);
-      uint16_t* dstl = wbl + gh::mlp_layer_offset(l, k1, W, gh::kPrecBf16);
-      for (int kt = 0; kt < K / 16; ++kt)
-        for (int ct = 0; ct < CT; ++ct)
+      const int KS = l == 0 ? gh::kK0Steps : W / 16;
+      uint16_t* dst = wa + gh::mlpa_layer_offset(l, W);
+      uint16_t* dstl = wal + gh::mlpa_layer_offset(l, W);
+      for (int ks = 0; ks < KS; ++ks)
+        for (int c = 0; c < CT; ++c)
           for (int lane = 0; lane < 64; ++lane)
             for (int i = 0; i < 8; ++i) {
-              const int col = ct * 32 + lane % 32, k = kt * 16 + 8 * (lane / 32) + i;
-              const float v = k < fi ? Wl[(size_t)col * fi + k] : 0.f;
+              const int q = 8 * (lane / 32) + i;
+              const int k = 16 * ks + (l == 0 ? q : gh::mlpa_slot_feature(q));
+              const int row = c * 32 + lane % 32;
+              const float v = k < fi ? Wl[(size_t)row * fi + k] : 0.f;
               const uint16_t hi = to_bf16(v);
               uint32_t hb = (uint32_t)hi << 16;
               float hv;
               memcpy(&hv, &hb, 4);
-              dst[((size_t)(kt * CT + ct) * 64 + lane) * 8 + i] = hi;
-              dstl[((size_t)(kt * CT + ct) * 64 + lane) * 8 + i] = to_bf16(v - hv);
+              const size_t o = ((size_t)(ks * CT + c) * 64 + lane) * 8 + i;
+              dst[o] = hi;
+              dstl[o] = to_bf16(v - hv);
             }
     }
     // f32: fragment (kt, ct), lane -> W[ct*32 + lane%32][2*kt + lane/32]
     {
-      const int K = gh::mlp_k0(k1, gh::kPrecF32) * (l == 0) + W * (l != 0);
-      float* dst = wf + gh::mlp_layer_offset(l, k1, W, gh::kPrecF32);
+      const int K = l == 0 ? gh::mlp_k0(k1) : W;
+      float* dst = wf + gh::mlp_layer_offset(l, k1, W);
       for (int kt = 0; kt < K / 2; ++kt)
         for (int ct = 0; ct < CT; ++ct)
           for (int lane = 0; lane < 64; ++lane) {
@@ -188,8 +197,9 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   d.kind = GH_SDB_MLP;
   char* b = (char*)dev_blob;
   gh::MlpDesc& m = d.mlp;
-  m.wb = (const uint16_t*)(b + o_wb);
-  m.wbl = (const uint16_t*)(b + o_wbl);
+  m.wa = (const uint16_t*)(b + o_wa);
+  m.wal = (const uint16_t*)(b + o_wal);
+  m.omrev = (const float*)(b + o_omrev);
   m.wf = (const float*)(b + o_wf);
   m.wft = (const float*)(b + o_wft);
   m.bias = (const float*)(b + o_bias);

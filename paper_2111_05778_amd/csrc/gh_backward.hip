@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_cotangents(Grid g, Workspace ws, con
 
 // ------------------------------------------------------------- network VJP
 struct VjpSmem {
-  MlpSmem fw;                         // activations (FP32 layout), points
+  MlpSmemF32 fw;                         // activations (FP32 layout), points
   float g[kVjpRows * kF32Stride];     // dL/dz of the current layer
   float gout[kVjpRows];               // dL/dNN per row
 };
@@ -131,7 +131,7 @@ __device__ __forceinline__ void vjp_dw(VjpSmem& sm, float* __restrict__ part, in
     for (int rs = 0; rs < kVjpRows / 2; ++rs) {
       const int r = 2 * rs + (lane >> 5);
       const float av = sm.g[r * kF32Stride + ot * 32 + (lane & 31)];
-      const float bv = sm.fw.act.af[r * kF32Stride + kt * 32 + (lane & 31)];
+      const float bv = sm.fw.af[r * kF32Stride + kt * 32 + (lane & 31)];
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
     const int kk = kt * 32 + (lane & 31);
@@ -220,12 +220,12 @@ __global__ __launch_bounds__(kBlock) void k_mlp_vjp(MlpDesc m, Grid g, Workspace
     }
     __syncthreads();
     // forward, keeping the pre-activations
-    mlp_features<kPrecF32>(m, sm.fw, kVjpRows);
-    for (int l = 0; l < D; ++l) mlp_layer<kPrecF32, W>(m, sm.fw, l, kVjpRows / 32, zs + (size_t)l * kVjpRows * W);
+    mlp_features_f32(m, sm.fw, kVjpRows);
+    for (int l = 0; l < D; ++l) mlp_layer_f32<W>(m, sm.fw, l, kVjpRows / 32, zs + (size_t)l * kVjpRows * W);
     // output layer: dW_D[o] += sum_r gout_r act_D[r][o], db_D += sum_r gout_r
     for (int o = t; o < W; o += kBlock) {
       float s = 0.f;
-      for (int r = 0; r < kVjpRows; ++r) s += sm.gout[r] * sm.fw.act.af[r * kF32Stride + o];
+      for (int r = 0; r < kVjpRows; ++r) s += sm.gout[r] * sm.fw.af[r * kF32Stride + o];
       part[offW(D) + o] += s;
     }
     if (t == 0) {
@@ -243,12 +243,12 @@ __global__ __launch_bounds__(kBlock) void k_mlp_vjp(MlpDesc m, Grid g, Workspace
     for (int l = D - 1; l >= 0; --l) {
       // input of layer l back into act
       if (l == 0) {
-        mlp_features<kPrecF32>(m, sm.fw, kVjpRows);
+        mlp_features_f32(m, sm.fw, kVjpRows);
       } else {
         const float* __restrict__ zp = zs + (size_t)(l - 1) * kVjpRows * W;
         for (int e = t; e < kVjpRows * W; e += kBlock) {
           const int r = e / W, c = e - r * W;
-          sm.fw.act.af[r * kF32Stride + c] = softplus_t<kPrecF32>(zp[r * W + c]);
+          sm.fw.af[r * kF32Stride + c] = softplus_f32(zp[r * W + c]);
         }
         __syncthreads();
       }

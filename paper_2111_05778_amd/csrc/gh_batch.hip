@@ -65,7 +65,7 @@ __global__ void k_batch_clear(const BatchShape* __restrict__ shapes, int n_shape
 }
 
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_hop_batched(const BatchShape* __restrict__ shapes,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_hop_batched(const BatchShape* __restrict__ shapes,
                                                         const WorkItem* __restrict__ items, int n_items,
                                                         unsigned int* __restrict__ head) {
   __shared__ MlpSmem sm;

@@ -142,12 +142,21 @@ __device__ __forceinline__ float reeval_fp32(const MlpDesc& m, MlpSmem& sm, int*
   return f;
 }
 
-// A block keeps a pool of R rays (one per owner thread, R = tile rows).  Each
-// round it refills finished slots from the ray source (rays [first, end) of
-// the column order, taken through src.take), packs the live rays into the
-// first rows, evaluates their current hop points as one tile (only the row
-// tiles in use), certifies the bf16 values and applies the hop rule (Section
-// 3, eq. iter, cell-quantised).
+// A block keeps a pool of kBlock rays (one per thread), twice a tile of the
+// bf16 precisions.  Each round it refills finished slots from the ray source
+// (rays [first, end) of the column order, taken through src.take), then
+// evaluates one tile:
+//  * normally the current hop points of up to R live rays (R = tile rows),
+//    packed into the first rows, in the kernel's precision; in the bf16
+//    precisions a value whose hop decision is ambiguous within the margin
+//    (floor((d - eps)/h) != floor((d + eps)/h)) is not used: its ray waits
+//    for an FP32 value;
+//  * an FP32 tile of up to kF32Rows waiting rays once that many wait, or
+//    when every live ray waits.
+// Deferring the FP32 values fills their tiles instead of paying a mostly
+// empty FP32 tile in every round that meets one ambiguous value.  The hop
+// rule (Section 3, eq. iter, cell-quantised) is applied to every value used,
+// so the schedule is the FP32 one.
 template <int P, int W, class Src>
 __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, uint64_t* __restrict__ colmask,
                                              uint32_t* __restrict__ colbits, gh_counters* __restrict__ ctr,
@@ -155,15 +164,51 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
   constexpr int R = mlp_rows<P>();
   const int n = g.n;
   const size_t ncol = (size_t)n * n;
-  const bool owner = (int)threadIdx.x < R;
+  const bool owner = true;  // every thread owns one slot of the pool
   const float nf = (float)n;
-  bool active = false, bad = false;
+  bool active = false, pend = false, bad = false;
   size_t col = 0;
   int k = 0, wi = 0;
   uint32_t word = 0;
   uint64_t mask = 0;
   float x = 0.f, y = 0.f;
   uint64_t evals = 0, cands = 0, reevals = 0;
+  // Hop rule with the value d at (x, y, centroid k); ends the ray when done.
+  auto advance = [&](float d) {
+    ++evals;
+    bool done = false;
+    if (!(d <= FLT_MAX)) {
+      bad = true;
+      done = true;
+    } else {
+      const float s = floorf(d * g.inv_h);
+      if (s == 0.f) {
+        const int kw = k >> 5;
+        if (kw != wi) {
+          if (word) {
+            colbits[(size_t)wi * ncol + col] = word;
+            mask |= 1ull << wi;
+          }
+          word = 0;
+          wi = kw;
+        }
+        word |= 1u << (k & 31);
+        ++cands;
+        ++k;
+      } else {
+        k += (int)fminf(s, nf);
+      }
+      done = k >= n;
+    }
+    if (done) {
+      if (word) {
+        colbits[(size_t)wi * ncol + col] = word;
+        mask |= 1ull << wi;
+      }
+      colmask[col] = mask;
+      active = false;
+    }
+  };
   for (;;) {
     // refill finished slots with the next rays
     int total;
@@ -175,6 +220,7 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
       const int64_t idx = src.first + (int64_t)*s_base + fr;
       if (idx < src.end) {
         active = true;
+        pend = false;
         col = (size_t)idx;
         x = centroid(g, (int)(idx / n));
         y = centroid(g, (int)(idx % n));
@@ -184,61 +230,49 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
         mask = 0;
       }
     }
-    // pack the live rays into rows [0, nact)
-    int nact;
-    const bool live = owner && active;
-    const int row = block_rank(live, s_cnt, nact);
-    if (nact == 0) break;  // uniform: the queue is empty and every slot is idle
+    int nrun, npend = 0;
+    const bool ready = owner && active && !pend;
+    const int row = block_rank(ready, s_cnt, nrun);
+    const bool run = ready && row < R;  // the first R ready rays form this round's tile
+    nrun = nrun < R ? nrun : R;
+    int prow = 0;
+    if constexpr (P != kPrecF32) prow = block_rank(owner && active && pend, s_cnt, npend);
+    if (nrun == 0 && npend == 0) break;  // uniform: the queue is empty and every slot is idle
     const float z = centroid(g, k);
-    if (live) {
+    if (npend >= kF32Rows || nrun == 0) {
+      // FP32 values for up to kF32Rows waiting rays
+      const bool mine = owner && active && pend && prow < kF32Rows;
+      if (mine) {
+        sm.pts[prow][0] = x;
+        sm.pts[prow][1] = y;
+        sm.pts[prow][2] = z;
+      }
+      __syncthreads();
+      mlp_tile<kPrecF32, W>(m, sm, npend < kF32Rows ? npend : kF32Rows);
+      const float d = mine ? fabsf(sm.f[prow]) : 0.f;
+      __syncthreads();
+      if (mine) {
+        ++reevals;
+        pend = false;
+        advance(d);
+      }
+      continue;
+    }
+    if (run) {
       sm.pts[row][0] = x;
       sm.pts[row][1] = y;
       sm.pts[row][2] = z;
     }
     __syncthreads();
-    mlp_tile<P, W>(m, sm, nact);
-    float d = live ? fabsf(sm.f[row]) : 0.f;
+    mlp_tile<P, W>(m, sm, nrun);
+    const float d = run ? fabsf(sm.f[row]) : 0.f;
     __syncthreads();
-    if constexpr (P != kPrecF32) {
+    if (run) {
       bool amb = false;
-      if (live && d <= FLT_MAX)
-        amb = floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
-      d = fabsf(reeval_fp32<W>(m, sm, s_cnt, amb, x, y, z, d, reevals));
-    }
-    if (live) {
-      ++evals;
-      bool done = false;
-      if (!(d <= FLT_MAX)) {
-        bad = true;
-        done = true;
-      } else {
-        const float s = floorf(d * g.inv_h);
-        if (s == 0.f) {
-          const int kw = k >> 5;
-          if (kw != wi) {
-            if (word) {
-              colbits[(size_t)wi * ncol + col] = word;
-              mask |= 1ull << wi;
-            }
-            word = 0;
-            wi = kw;
-          }
-          word |= 1u << (k & 31);
-          ++cands;
-          ++k;
-        } else {
-          k += (int)fminf(s, nf);
-        }
-        done = k >= n;
-      }
-      if (done) {
-        if (word) {
-          colbits[(size_t)wi * ncol + col] = word;
-          mask |= 1ull << wi;
-        }
-        colmask[col] = mask;
-        active = false;
-      }
+      if constexpr (P != kPrecF32)
+        amb = d <= FLT_MAX && floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
+      if (amb) pend = true;
+      else advance(d);
     }
   }
   if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
@@ -246,6 +280,5 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
   block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
   block_add_u64(reevals, (unsigned long long*)&ctr->n_reeval);
 }
-
 
 }  // namespace gh

@@ -4,18 +4,25 @@
 // sphere prior that places the surface), gamma(p) = [p, sin(w_k p), cos(w_k p)],
 // NN = w_out . softplus(W_D ... softplus(W_1 gamma + b_1) ... + b_D) + b_out.
 //
-// A block of four waves evaluates a tile of points: the features go to LDS,
-// every hidden layer is a [rows x K] x [K x W] product on MFMA with FP32
-// accumulation, its epilogue adds the bias, applies softplus and writes the
-// next layer's input back to LDS, and a final FP32 dot gives NN.  Three
-// precisions share the structure:
-//   BF16:   v_mfma_f32_32x32x16_bf16, activations stored as bf16, 128 rows
-//   BF16x3: the same instruction three times per product on hi/lo bf16
-//           splits of activations and weights (hi*hi + hi*lo + lo*hi, FP32
-//           accumulation): about 2^-16 relative error, 64 rows
-//   FP32:   v_mfma_f32_32x32x2f32,    activations stored as f32,   64 rows
-// Weights arrive pre-packed (sdb_describe) in the exact operand order of a
-// 32 x 32 B fragment: one 16-byte (bf16) or 4-byte (f32) load per lane.
+// Two evaluators share the tile interface (points in sm.pts, values to sm.f):
+//
+// bf16 precisions (128 points per block, 32 per wave): the weights are the A
+// operand and the activations the B operand of v_mfma_f32_32x32x16_bf16, so a
+// wave holds every activation of its 32 points in registers from the
+// features to the output dot, with no LDS traffic.  A layer's 32 x 32 output
+// tile leaves lane l with 16 features of point l % 32; those registers are
+// exactly the next layer's B fragments once the input features of that layer
+// are permuted inside each group of 16 (swap of index bits 3 and 2), and
+// sdb_describe packs the weights in that permuted order.  The epilogue adds
+// the bias, applies softplus with the hardware exp2/log2, and converts with
+// the hardware bf16 rounding.
+//   BF16:   one product per fragment pair, activations and weights bf16
+//   BF16x3: hi/lo bf16 splits of both, hi*hi + hi*lo + lo*hi with FP32
+//           accumulation: about 2^-16 relative error
+//
+// FP32 (64 points per block): activations in LDS, v_mfma_f32_32x32x2f32 with
+// the weights as B fragments; used for the FP32 bound, for re-evaluation of
+// ambiguous bf16 values, and by the adjoint (which keeps pre-activations).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,80 +31,104 @@
 namespace gh {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kMlpBlock = 256;
 constexpr int kMlpMaxK = 256;           // widest layer input (features pad to <= 112)
 constexpr int kBf16Rows = 128, kF32Rows = 64;
-constexpr int kBf16Stride = kMlpMaxK + 8;  // bf16 elements per LDS row (16-byte pad)
 constexpr int kF32Stride = kMlpMaxK + 1;   // floats per LDS row (odd: no bank conflicts)
+constexpr int kK0Steps = 7;                // bf16 first layer: 7 k-steps of 16 = 112 inputs
+constexpr int kK0Mfma = 16 * kK0Steps;     // (3 + 6F <= 99 features, zero padded)
+constexpr int kK0Store = 8;                // k-steps stored for the first layer (the 8th is zero)
+constexpr int kChunkSteps = 2;             // k-steps per LDS chunk of A fragments
+constexpr int kStageElems = kChunkSteps * (kMlpMaxK / 32) * 512;  // bf16 per chunk buffer (W = 256)
 
 enum : int { kPrecF32 = 0, kPrecBf16 = 1, kPrecBf16x3 = 2 };
 
 struct MlpDesc {
-  const uint16_t* wb;   // bf16 bits, packed B fragments of every hidden layer
-  const uint16_t* wbl;  // bf16 bits of the remainders w - bf16(w), same packing
+  const uint16_t* wa;   // bf16 bits, packed A fragments of every hidden layer (register evaluator)
+  const uint16_t* wal;  // bf16 bits of the remainders w - bf16(w), same packing
   const float* wf;      // float, packed B fragments of every hidden layer
   const float* wft;     // float, packed B fragments of W_l itself (l >= 1), for the adjoint
   const float* bias;    // [depth][W]
   const float* wout;    // [W]
   const float* omegas;  // [F]
+  const float* omrev;   // [16] w_k / 2pi (turns per unit; zero past F), for the hardware sine
   int F, W, depth, k1;  // k1 = 3 + 6F features
   int precision;
   float a_s, r0, a_n, b, b_out;
   float eps;            // |f_bf16 - f_fp32| bound used by the hop test
 };
 
-// Padded first-layer depth of each precision's K steps.
-__host__ __device__ constexpr int mlp_k0(int k1, int prec) { return prec != kPrecF32 ? (k1 + 15) / 16 * 16 : (k1 + 1) / 2 * 2; }
-__host__ __device__ constexpr int mlp_kstep(int prec) { return prec != kPrecF32 ? 16 : 2; }
-template <int P>
-__host__ __device__ constexpr int mlp_rows() { return P == kPrecBf16 ? kBf16Rows : kF32Rows; }
-// Elements of the packed fragments of layer l (0 = features -> W).
-__host__ __device__ inline size_t mlp_layer_elems(int l, int k1, int W, int prec) {
-  const int K = l == 0 ? mlp_k0(k1, prec) : W;
-  return (size_t)K * W;
+// Input feature of a hidden layer (l >= 1) that sits in slot q (0..15) of a
+// 16-wide k-step of the register evaluator: bits 3 and 2 of q swap places.
+__host__ __device__ constexpr int mlpa_slot_feature(int q) {
+  return (((q >> 2) & 1) << 3) | (((q >> 3) & 1) << 2) | (q & 3);
 }
-__host__ __device__ inline size_t mlp_layer_offset(int l, int k1, int W, int prec) {
-  return l == 0 ? 0 : mlp_layer_elems(0, k1, W, prec) + (size_t)(l - 1) * W * W;
+// Offset (bf16 elements) of layer l's A fragments: [k-step][m-tile][lane][8].
+__host__ __device__ inline size_t mlpa_layer_offset(int l, int W) {
+  return l == 0 ? 0 : (size_t)16 * kK0Store * W + (size_t)(l - 1) * W * W;
 }
 
-// LDS of one tile evaluation.  The activation layouts overlay; BF16x3 keeps
-// the hi parts in rows [0, 64) and the lo parts in rows [64, 128).
+// FP32 evaluator: padded first-layer depth (k-steps of 2) and fragment offsets.
+__host__ __device__ constexpr int mlp_k0(int k1) { return (k1 + 1) / 2 * 2; }
+template <int P>
+__host__ __device__ constexpr int mlp_rows() { return P == kPrecF32 ? kF32Rows : kBf16Rows; }
+__host__ __device__ inline size_t mlp_layer_elems(int l, int k1, int W) {
+  const int K = l == 0 ? mlp_k0(k1) : W;
+  return (size_t)K * W;
+}
+__host__ __device__ inline size_t mlp_layer_offset(int l, int k1, int W) {
+  return l == 0 ? 0 : mlp_layer_elems(0, k1, W) + (size_t)(l - 1) * W * W;
+}
+
+// LDS of one tile evaluation: FP32 activations (FP32 evaluator) or, in the
+// same bytes, two chunk buffers of A fragments with their lo parts (register
+// evaluator); the activation exchange of split tiles; the points and values
+// of up to 128 rows; partial output dots.
 struct MlpSmem {
   union {
-    uint16_t ab[kBf16Rows * kBf16Stride];
     float af[kF32Rows * kF32Stride];
-  } act;
+    uint16_t stage[2][2][kStageElems];
+  };
+  uint4 xch[2][2][kMlpMaxK / 16][64];  // split tiles: B fragments [group][hi/lo][k-step][lane]
   float pts[kBf16Rows][3];
   float f[kBf16Rows];
   float part[4][kBf16Rows];
 };
 
-__device__ __forceinline__ uint16_t f2bf(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (values are finite)
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// The FP32 evaluator's part alone (for kernels that never run the register
+// evaluator).
+struct MlpSmemF32 {
+  float af[kF32Rows * kF32Stride];
+  float pts[kBf16Rows][3];
+  float f[kBf16Rows];
+  float part[4][kBf16Rows];
+};
 
-// softplus(z) = max(z, 0) + log(1 + e^-|z|).  The BF16 path rounds the result
-// to bf16 right after, so it uses the hardware exp/log; the FP32 path uses
-// the accurate library functions.
-template <int P>
-__device__ __forceinline__ float softplus_t(float z) {
-  if constexpr (P == kPrecBf16) {  // rounded to bf16 right after
-    return fmaxf(z, 0.f) + __logf(1.f + __expf(-fabsf(z)));
-  } else {
-    return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z)));
-  }
+// softplus(z) = max(z, 0) + log(1 + e^-|z|) with the accurate library
+// functions (FP32 evaluator).
+__device__ __forceinline__ float softplus_f32(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+
+// The same with the hardware base-2 exponential and logarithm (about 1 ulp
+// each): absolute error near 2e-7, far below the bf16 roundings that follow.
+__device__ __forceinline__ float softplus_hw(float z) {
+  const float e = __builtin_amdgcn_exp2f(-fabsf(z) * 1.44269504088896341f);
+  return fmaf(__builtin_amdgcn_logf(1.f + e), 0.693147180559945309f, fmaxf(z, 0.f));
 }
 
-// Wave partition of the rows x W output into 32 x 32 tiles (4 waves).
-template <int P, int W>
+// Final value from NN (both evaluators).
+__device__ __forceinline__ float mlp_value(const MlpDesc& m, float x, float y, float z, float nn) {
+  const float rad = sqrtf((x * x + y * y) + z * z);
+  return (m.a_s * (rad - m.r0) + m.a_n * nn) + m.b;
+}
+
+// =========================================================== FP32 evaluator
+// Wave partition of the 64 x W output into 32 x 32 tiles (4 waves).
+template <int W>
 struct MlpShape {
-  static constexpr int kRows = mlp_rows<P>();
-  static constexpr int RT = kRows / 32;
+  static constexpr int RT = kF32Rows / 32;
   static constexpr int CT = W / 32;
   static constexpr int NC = CT >= 4 ? CT / 4 : 1;
   static constexpr int NR = CT >= 4 ? RT : RT / 2;
@@ -105,38 +136,13 @@ struct MlpShape {
   __device__ static int rt0(int w) { return CT >= 4 ? 0 : (w >> 1) * NR; }
 };
 
-// Stores activation a of (row, col) in the layout of precision P.
-template <int P>
-__device__ __forceinline__ void act_store(MlpSmem& sm, int row, int col, float a) {
-  if constexpr (P == kPrecBf16) {
-    sm.act.ab[row * kBf16Stride + col] = f2bf(a);
-  } else if constexpr (P == kPrecBf16x3) {
-    const uint16_t hi = f2bf(a);
-    sm.act.ab[row * kBf16Stride + col] = hi;
-    sm.act.ab[(row + kF32Rows) * kBf16Stride + col] = f2bf(a - bf2f(hi));
-  } else {
-    sm.act.af[row * kF32Stride + col] = a;
-  }
-}
-template <int P>
-__device__ __forceinline__ float act_load(const MlpSmem& sm, int row, int col) {
-  if constexpr (P == kPrecBf16) {
-    return bf2f(sm.act.ab[row * kBf16Stride + col]);
-  } else if constexpr (P == kPrecBf16x3) {
-    return bf2f(sm.act.ab[row * kBf16Stride + col]) + bf2f(sm.act.ab[(row + kF32Rows) * kBf16Stride + col]);
-  } else {
-    return sm.act.af[row * kF32Stride + col];
-  }
-}
-
 // Features of rows [0, nrows) from sm.pts into the activation buffer
 // (columns [k1, K0) are zero), then one sync.
-template <int P>
-__device__ __forceinline__ void mlp_features(const MlpDesc& m, MlpSmem& sm, int nrows) {
-  constexpr int kRows = mlp_rows<P>();
-  const int K0 = mlp_k0(m.k1, P);
+template <class Sm>
+__device__ __forceinline__ void mlp_features_f32(const MlpDesc& m, Sm& sm, int nrows) {
+  const int K0 = mlp_k0(m.k1);
   const int per_row = 3 + 3 * m.F;  // p, then (sin, cos) for each (frequency, axis)
-  for (int e = threadIdx.x; e < kRows * per_row; e += blockDim.x) {
+  for (int e = threadIdx.x; e < kF32Rows * per_row; e += blockDim.x) {
     const int r = e / per_row, q = e - r * per_row;
     float v0 = 0.f, v1 = 0.f;
     const int c0 = q < 3 ? q : 3 + 6 * ((q - 3) / 3) + (q - 3) % 3;
@@ -145,22 +151,22 @@ __device__ __forceinline__ void mlp_features(const MlpDesc& m, MlpSmem& sm, int 
       if (q < 3) v0 = sm.pts[r][q];
       else sincosf(m.omegas[(q - 3) / 3] * sm.pts[r][(q - 3) % 3], &v0, &v1);
     }
-    act_store<P>(sm, r, c0, v0);
-    if (c1 >= 0) act_store<P>(sm, r, c1, v1);
+    sm.af[r * kF32Stride + c0] = v0;
+    if (c1 >= 0) sm.af[r * kF32Stride + c1] = v1;
   }
-  for (int e = threadIdx.x; e < kRows * (K0 - m.k1); e += blockDim.x)
-    act_store<P>(sm, e / (K0 - m.k1), m.k1 + e % (K0 - m.k1), 0.f);
+  for (int e = threadIdx.x; e < kF32Rows * (K0 - m.k1); e += blockDim.x)
+    sm.af[(e / (K0 - m.k1)) * kF32Stride + m.k1 + e % (K0 - m.k1)] = 0.f;
   __syncthreads();
 }
 
 // One hidden layer: act[:, :K] x W_l^T -> bias + softplus -> act[:, :W].
 // With zout, the pre-activations are also stored there ([rows][W], FP32).
-template <int P, int W>
-__device__ __forceinline__ void mlp_layer(const MlpDesc& m, MlpSmem& sm, int l, int nrt, float* zout = nullptr) {
-  using S = MlpShape<P, W>;
+template <int W, class Sm>
+__device__ __forceinline__ void mlp_layer_f32(const MlpDesc& m, Sm& sm, int l, int nrt, float* zout = nullptr) {
+  using S = MlpShape<W>;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int K = l == 0 ? mlp_k0(m.k1, P) : W;
-  const int ksteps = K / mlp_kstep(P);
+  const int K = l == 0 ? mlp_k0(m.k1) : W;
+  const int ksteps = K / 2;
   const int ct0 = S::ct0(w), rt0 = S::rt0(w);
   f32x16_t acc[S::NR][S::NC];
 #pragma unroll
@@ -170,52 +176,18 @@ __device__ __forceinline__ void mlp_layer(const MlpDesc& m, MlpSmem& sm, int l, 
 #pragma unroll
       for (int t = 0; t < 16; ++t) acc[rt][ct][t] = 0.f;
   const int row_l = lane & 31, khalf = lane >> 5;
-  if constexpr (P != kPrecF32) {
-    const size_t off = mlp_layer_offset(l, m.k1, W, P);
-    const uint16_t* __restrict__ wl = m.wb + off;
-    const uint16_t* __restrict__ wll = m.wbl + off;
-    for (int kt = 0; kt < ksteps; ++kt) {
-      bf16x8_t bfr[S::NC], bfl[S::NC];
+  const float* __restrict__ wl = m.wf + mlp_layer_offset(l, m.k1, W);
+  for (int kt = 0; kt < ksteps; ++kt) {
+    float bfr[S::NC];
 #pragma unroll
-      for (int ct = 0; ct < S::NC; ++ct) {
-        const size_t o = ((size_t)(kt * S::CT + ct0 + ct) * 64 + lane) * 8;
-        bfr[ct] = *reinterpret_cast<const bf16x8_t*>(wl + o);
-        if constexpr (P == kPrecBf16x3) bfl[ct] = *reinterpret_cast<const bf16x8_t*>(wll + o);
-      }
+    for (int ct = 0; ct < S::NC; ++ct) bfr[ct] = wl[(size_t)(kt * S::CT + ct0 + ct) * 64 + lane];
 #pragma unroll
-      for (int rt = 0; rt < S::NR; ++rt) {
-        if (rt0 + rt >= nrt) break;
-        const int arow = (rt0 + rt) * 32 + row_l;
-        const bf16x8_t afr =
-            *reinterpret_cast<const bf16x8_t*>(&sm.act.ab[arow * kBf16Stride + kt * 16 + khalf * 8]);
-        if constexpr (P == kPrecBf16x3) {
-          const bf16x8_t afl = *reinterpret_cast<const bf16x8_t*>(
-              &sm.act.ab[(arow + kF32Rows) * kBf16Stride + kt * 16 + khalf * 8]);
+    for (int rt = 0; rt < S::NR; ++rt) {
+      if (rt0 + rt >= nrt) break;
+      const float afr = sm.af[((rt0 + rt) * 32 + row_l) * kF32Stride + kt * 2 + khalf];
 #pragma unroll
-          for (int ct = 0; ct < S::NC; ++ct) {
-            acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afl, bfr[ct], acc[rt][ct], 0, 0, 0);
-            acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfl[ct], acc[rt][ct], 0, 0, 0);
-          }
-        }
-#pragma unroll
-        for (int ct = 0; ct < S::NC; ++ct)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[ct], acc[rt][ct], 0, 0, 0);
-      }
-    }
-  } else {
-    const float* __restrict__ wl = m.wf + mlp_layer_offset(l, m.k1, W, P);
-    for (int kt = 0; kt < ksteps; ++kt) {
-      float bfr[S::NC];
-#pragma unroll
-      for (int ct = 0; ct < S::NC; ++ct) bfr[ct] = wl[(size_t)(kt * S::CT + ct0 + ct) * 64 + lane];
-#pragma unroll
-      for (int rt = 0; rt < S::NR; ++rt) {
-        if (rt0 + rt >= nrt) break;
-        const float afr = sm.act.af[((rt0 + rt) * 32 + row_l) * kF32Stride + kt * 2 + khalf];
-#pragma unroll
-        for (int ct = 0; ct < S::NC; ++ct)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(afr, bfr[ct], acc[rt][ct], 0, 0, 0);
-      }
+      for (int ct = 0; ct < S::NC; ++ct)
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(afr, bfr[ct], acc[rt][ct], 0, 0, 0);
     }
   }
   __syncthreads();  // every wave has read this layer's input
@@ -232,26 +204,24 @@ __device__ __forceinline__ void mlp_layer(const MlpDesc& m, MlpSmem& sm, int l, 
         const int row = (rt0 + rt) * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
         const float z = acc[rt][ct][t] + bv;
         if (zout) zout[row * W + col] = z;
-        act_store<P>(sm, row, col, softplus_t<P>(z));
+        sm.af[row * kF32Stride + col] = softplus_f32(z);
       }
     }
   }
   __syncthreads();
 }
 
-// Evaluates f at sm.pts[0, nrows) into sm.f[0, nrows).
-template <int P, int W>
-__device__ __forceinline__ void mlp_tile(const MlpDesc& m, MlpSmem& sm, int nrows) {
-  constexpr int kRows = mlp_rows<P>();
-  constexpr int kParts = kMlpBlock / kRows;  // threads per row in the output dot
+template <int W>
+__device__ __forceinline__ void mlp_tile_f32(const MlpDesc& m, MlpSmem& sm, int nrows) {
+  constexpr int kParts = kMlpBlock / kF32Rows;  // threads per row in the output dot
   const int nrt = (nrows + 31) / 32;
-  mlp_features<P>(m, sm, nrows);
-  for (int l = 0; l < m.depth; ++l) mlp_layer<P, W>(m, sm, l, nrt);
-  const int q = threadIdx.x / kRows, r = threadIdx.x % kRows;
+  mlp_features_f32(m, sm, nrows);
+  for (int l = 0; l < m.depth; ++l) mlp_layer_f32<W>(m, sm, l, nrt);
+  const int q = threadIdx.x / kF32Rows, r = threadIdx.x % kF32Rows;
   if (r < nrows) {
     float s = 0.f;
     const int c0 = q * (W / kParts), c1 = c0 + W / kParts;
-    for (int c = c0; c < c1; ++c) s += act_load<P>(sm, r, c) * m.wout[c];
+    for (int c = c0; c < c1; ++c) s += sm.af[r * kF32Stride + c] * m.wout[c];
     sm.part[q][r] = s;
   }
   __syncthreads();
@@ -259,11 +229,374 @@ __device__ __forceinline__ void mlp_tile(const MlpDesc& m, MlpSmem& sm, int nrow
     const int rr = threadIdx.x;
     float nn = m.b_out;
     for (int qq = 0; qq < kParts; ++qq) nn += sm.part[qq][rr];
-    const float x = sm.pts[rr][0], y = sm.pts[rr][1], z = sm.pts[rr][2];
-    const float rad = sqrtf((x * x + y * y) + z * z);
-    sm.f[rr] = (m.a_s * (rad - m.r0) + m.a_n * nn) + m.b;
+    sm.f[rr] = mlp_value(m, sm.pts[rr][0], sm.pts[rr][1], sm.pts[rr][2], nn);
   }
   __syncthreads();
+}
+
+// ====================================================== register evaluator
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  const bf16x2_t v = {(__bf16)a, (__bf16)b};  // hardware round to nearest even
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// Eight activations into a B fragment (and, for BF16x3, the fragment of the
+// remainders a - bf16(a)).
+template <int P>
+__device__ __forceinline__ void pack_fragment(const float (&a)[8], bf16x8_t& hi, bf16x8_t& lo) {
+  uint32_t h[4], r[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    h[i] = pack_bf16x2(a[2 * i], a[2 * i + 1]);
+    if constexpr (P == kPrecBf16x3) {
+      const float h0 = __uint_as_float(h[i] << 16), h1 = __uint_as_float(h[i] & 0xffff0000u);
+      r[i] = pack_bf16x2(a[2 * i] - h0, a[2 * i + 1] - h1);
+    }
+  }
+  hi = __builtin_bit_cast(bf16x8_t, h);
+  if constexpr (P == kPrecBf16x3) lo = __builtin_bit_cast(bf16x8_t, r);
+}
+
+template <int P>
+__device__ __forceinline__ f32x16_t mfma_step(const bf16x8_t& a, const bf16x8_t& al, const bf16x8_t& b,
+                                              const bf16x8_t& bl, f32x16_t acc) {
+  if constexpr (P == kPrecBf16x3) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc, 0, 0, 0);
+  }
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+}
+
+// Bias + softplus of one layer's output tiles c0 .. c0 + NT - 1 (this
+// wave's share); either packs them as B fragments of the next layer's
+// k-steps 2(c0 + c) and 2(c0 + c) + 1 into x[2c], x[2c + 1], or, for the
+// last hidden layer, returns this lane's
+// part of the output dot.  Lane l holds feature 32c + 8j + 4(l / 32) + i of
+// its point in acc[c - c0][4j + i].  The bias (and output weights) of the
+// next tile are loaded while a tile is processed, and a scheduling barrier
+// per tile keeps the compiler from hoisting every load of the layer (which
+// would cost registers instead of latency).
+template <int P, int W, int NT, bool kLast>
+__device__ __forceinline__ float mlp_epilogue(const MlpDesc& m, int l, int c0, f32x16_t (&acc)[NT],
+                                              bf16x8_t (&x)[2 * NT], bf16x8_t (&xl)[2 * NT]) {
+  const int h = (threadIdx.x >> 5) & 1;
+  const float4* __restrict__ bias4 = reinterpret_cast<const float4*>(m.bias + (size_t)l * W) + h;
+  const float4* __restrict__ wout4 = reinterpret_cast<const float4*>(m.wout) + h;
+  float dt[NT];  // per-tile output dots (kLast)
+  float4 bv[4], wv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    bv[j] = bias4[8 * c0 + 2 * j];
+    if constexpr (kLast) wv[j] = wout4[8 * c0 + 2 * j];
+  }
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    float a[16];
+    float dot = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      a[4 * j + 0] = softplus_hw(acc[c][4 * j + 0] + bv[j].x);
+      a[4 * j + 1] = softplus_hw(acc[c][4 * j + 1] + bv[j].y);
+      a[4 * j + 2] = softplus_hw(acc[c][4 * j + 2] + bv[j].z);
+      a[4 * j + 3] = softplus_hw(acc[c][4 * j + 3] + bv[j].w);
+      if constexpr (kLast) {
+        dot += a[4 * j + 0] * wv[j].x;
+        dot += a[4 * j + 1] * wv[j].y;
+        dot += a[4 * j + 2] * wv[j].z;
+        dot += a[4 * j + 3] * wv[j].w;
+      }
+    }
+    dt[c] = dot;
+    if (c + 1 < NT) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bv[j] = bias4[8 * (c0 + c + 1) + 2 * j];
+        if constexpr (kLast) wv[j] = wout4[8 * (c0 + c + 1) + 2 * j];
+      }
+    }
+    if constexpr (!kLast) {
+      float a0[8], a1[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        a0[i] = a[i];
+        a1[i] = a[8 + i];
+      }
+      pack_fragment<P>(a0, x[2 * c], xl[2 * c]);
+      pack_fragment<P>(a1, x[2 * c + 1], xl[2 * c + 1]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if constexpr (!kLast) return 0.f;
+  // Tile dots of the whole point (both lane halves), then a pairwise tree
+  // over the tiles: the same association for every split of the tiles over
+  // waves, so a value does not depend on how full its tile was.
+#pragma unroll
+  for (int c = 0; c < NT; ++c) dt[c] += __shfl_xor(dt[c], 32, 64);
+#pragma unroll
+  for (int span = 1; span < NT; span *= 2)
+#pragma unroll
+    for (int c = 0; c + span < NT; c += 2 * span) dt[c] += dt[c + span];
+  return dt[0];
+}
+
+// Features of k-step s of the first layer: slot 8h + i holds feature
+// 16s + 8h + i of gamma(p) = [p, then per frequency sin(w p_x..z), cos(w p_x..z)],
+// zero past 3 + 6F.  One hardware sine per feature (cos = sin + 1/4 turn).
+// s is a constant once the caller's loop is unrolled.
+template <int P>
+__device__ __forceinline__ void mlp_features_reg(const MlpDesc& m, int s, float px, float py, float pz, bf16x8_t& x,
+                                                 bf16x8_t& xl) {
+  const int h = (threadIdx.x >> 5) & 1;
+  float v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    float arg[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = 16 * s + 8 * q + i;
+      if (k < 3) {
+        arg[q] = k == 0 ? px : (k == 1 ? py : pz);
+      } else {
+        const int j = k - 3, fq = j / 6, r = j % 6, ax = r % 3;
+        const float pa = ax == 0 ? px : (ax == 1 ? py : pz);
+        arg[q] = fmaf(m.omrev[fq < 16 ? fq : 15], pa, r >= 3 ? 0.25f : 0.f);  // turns
+      }
+    }
+    const float u = h ? arg[1] : arg[0];
+    const bool lin = 16 * s + i < 3 && h == 0;
+    v[i] = lin ? u : (16 * s + 8 * h + i < m.k1 ? __builtin_amdgcn_sinf(u) : 0.f);  // sin(2 pi u)
+  }
+  pack_fragment<P>(v, x, xl);
+}
+
+// A fragments stream through LDS in chunks of kChunkSteps k-steps (all
+// m-tiles), double-buffered: while the waves multiply with one buffer, the
+// next chunk (possibly the next layer's first) travels from global memory
+// straight into the other buffer (global_load_lds, no registers); one wait
+// and one barrier per chunk.
+template <int P, int W>
+struct ChunkDma {
+  static constexpr int kPieces = kChunkSteps * (W / 32) / 4;  // 16-byte pieces per thread per part
+  // Issues the copy of one chunk (hi and, for BF16x3, lo parts) into buffer buf.
+  __device__ static void issue(const uint16_t* __restrict__ ghi, const uint16_t* __restrict__ glo, MlpSmem& sm,
+                               int buf) {
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kPieces; ++q) {
+      const int piece = threadIdx.x + q * kMlpBlock;  // lane l of wave w lands at (64w + 256q + l) * 16 bytes
+      const int wave_base = (64 * w + q * kMlpBlock) * 8;
+      __builtin_amdgcn_global_load_lds(ghi + (size_t)piece * 8,
+                                       (__attribute__((address_space(3))) void*)&sm.stage[buf][0][wave_base], 16, 0, 0);
+      if constexpr (P == kPrecBf16x3)
+        __builtin_amdgcn_global_load_lds(glo + (size_t)piece * 8,
+                                         (__attribute__((address_space(3))) void*)&sm.stage[buf][1][wave_base], 16, 0,
+                                         0);
+    }
+  }
+  // Waits for this thread's copies, then for the whole block.
+  __device__ static void wait_and_sync() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+  }
+};
+
+// One layer's products over NS input k-steps for this wave's NT m-tiles
+// c0 .. c0 + NT - 1; its chunks start in buffer 0 (the number of chunks is
+// even, so the next layer starts in buffer 0 too).  next_hi/next_lo: the
+// following layer's fragments, copied during this layer's last chunk, or
+// null.  Every wave of the block runs the same copies and barriers; with
+// kActive false a wave only helps with the copies.  For the first layer
+// (kFeat) the B fragments are the features, computed chunk by chunk.
+template <int P, int W, int NT, int NS, bool kFeat, bool kActive>
+__device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, MlpSmem& sm, int c0, const uint16_t* __restrict__ hi,
+                                              const uint16_t* __restrict__ lo, const uint16_t* __restrict__ next_hi,
+                                              const uint16_t* __restrict__ next_lo, f32x16_t (&acc)[NT],
+                                              const bf16x8_t (&x)[W / 16], const bf16x8_t (&xl)[W / 16], float px,
+                                              float py, float pz) {
+  constexpr int CT = W / 32;
+  constexpr int NCH = (NS + kChunkSteps - 1) / kChunkSteps;
+  constexpr int CE = kChunkSteps * CT * 512;  // bf16 elements per chunk
+  static_assert(NCH % 2 == 0, "layers must have an even number of chunks");
+  const int lane = threadIdx.x & 63;
+  if constexpr (kActive) {
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int t = 0; t < 16; ++t) acc[c][t] = 0.f;
+  }
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int cur = ch & 1;
+    if (ch + 1 < NCH) ChunkDma<P, W>::issue(hi + (size_t)(ch + 1) * CE, lo + (size_t)(ch + 1) * CE, sm, cur ^ 1);
+    else if (next_hi) ChunkDma<P, W>::issue(next_hi, next_lo, sm, cur ^ 1);
+    __builtin_amdgcn_sched_barrier(0);  // the copy starts before this chunk's products
+    if constexpr (kActive) {
+      const bf16x8_t* __restrict__ sa = reinterpret_cast<const bf16x8_t*>(sm.stage[cur][0]);
+      const bf16x8_t* __restrict__ sal = reinterpret_cast<const bf16x8_t*>(sm.stage[cur][1]);
+      // Read the fragments of FS k-steps at once, then multiply: the reads
+      // return in order, so each product waits only for its own fragment.
+      constexpr int FS = P == kPrecBf16x3 ? 1 : kChunkSteps;
+#pragma unroll
+      for (int u0 = 0; u0 < kChunkSteps; u0 += FS) {
+        bf16x8_t fa[FS][NT], fl[FS][NT];
+#pragma unroll
+        for (int u = 0; u < FS; ++u) {
+          if (ch * kChunkSteps + u0 + u >= NS) break;
+#pragma unroll
+          for (int c = 0; c < NT; ++c) {
+            const int o = ((u0 + u) * CT + c0 + c) * 64 + lane;
+            fa[u][c] = sa[o];
+            if constexpr (P == kPrecBf16x3) fl[u][c] = sal[o];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < FS; ++u) {
+          const int s = ch * kChunkSteps + u0 + u;
+          if (s >= NS) break;
+          bf16x8_t xb, xbl;
+          if constexpr (kFeat) {
+            mlp_features_reg<P>(m, s, px, py, pz, xb, xbl);
+          } else {
+            xb = x[s];
+            if constexpr (P == kPrecBf16x3) xbl = xl[s];
+          }
+#pragma unroll
+          for (int c = 0; c < NT; ++c) acc[c] = mfma_step<P>(fa[u][c], fl[u][c], xb, xbl, acc[c]);
+        }
+        // Scheduling order of this group: every fragment read, then the
+        // products (the compiler would otherwise serialise read -> wait ->
+        // product to save registers).
+        constexpr int kParts = P == kPrecBf16x3 ? 2 : 1;
+        __builtin_amdgcn_sched_group_barrier(0x100, FS * NT * kParts, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, FS * NT * (P == kPrecBf16x3 ? 3 : 1), 0);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // and is waited for only after them
+    ChunkDma<P, W>::wait_and_sync();
+  }
+}
+
+// Hands this wave's new B fragments (tiles c0 .. c0 + NT - 1) to the other
+// waves of its group through LDS and takes theirs (S > 1 only).  The chunk
+// barriers of the following layer keep the next exchange from overwriting
+// the buffer before every wave has read it.
+template <int P, int W, int NT>
+__device__ __forceinline__ void mlp_exchange(MlpSmem& sm, int grp, int c0, const bf16x8_t (&xo)[2 * NT],
+                                             const bf16x8_t (&xol)[2 * NT], bf16x8_t (&x)[W / 16],
+                                             bf16x8_t (&xl)[W / 16]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 2 * NT; ++q) {
+    sm.xch[grp][0][2 * c0 + q][lane] = __builtin_bit_cast(uint4, xo[q]);
+    if constexpr (P == kPrecBf16x3) sm.xch[grp][1][2 * c0 + q][lane] = __builtin_bit_cast(uint4, xol[q]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < W / 16; ++s) {
+    x[s] = __builtin_bit_cast(bf16x8_t, sm.xch[grp][0][s][lane]);
+    if constexpr (P == kPrecBf16x3) xl[s] = __builtin_bit_cast(bf16x8_t, sm.xch[grp][1][s][lane]);
+  }
+}
+
+// Part of NN(gamma(p)) of the group's 32 points that this wave computes: the
+// S waves of a group (waves w with equal w / S) share its points, each taking
+// W/32/S of the m-tiles of every layer.  Lanes l and l + 32 both pass point
+// l % 32 and both receive its part.  Every wave of the block must call it
+// with the same S (barriers inside), active or not.
+template <int P, int W, int S, bool kActive>
+__device__ __forceinline__ float mlp_wave(const MlpDesc& m, MlpSmem& sm, float px, float py, float pz) {
+  constexpr int KS = W / 16, NT = W / 32 / S;
+  const int w = threadIdx.x >> 6;
+  const int grp = w / S, c0 = (w % S) * NT;
+  f32x16_t acc[NT];
+  bf16x8_t x[KS], xl[KS];
+  {
+    ChunkDma<P, W>::issue(m.wa, m.wal, sm, 0);
+    ChunkDma<P, W>::wait_and_sync();
+    const size_t on = mlpa_layer_offset(1, W);
+    const bool deeper = m.depth > 1;
+    mlp_layer_reg<P, W, NT, kK0Steps, true, kActive>(m, sm, c0, m.wa, m.wal, deeper ? m.wa + on : nullptr,
+                                                     deeper ? m.wal + on : nullptr, acc, x, xl, px, py, pz);
+  }
+  float dot = 0.f;
+  for (int l = 0;; ++l) {
+    if (l + 1 == m.depth) {
+      bf16x8_t xo[2 * NT], xol[2 * NT];  // unused by the last layer
+      if constexpr (kActive) dot = mlp_epilogue<P, W, NT, true>(m, l, c0, acc, xo, xol);
+      break;
+    }
+    if constexpr (S == 1) {
+      if constexpr (kActive) mlp_epilogue<P, W, NT, false>(m, l, c0, acc, x, xl);
+    } else {
+      bf16x8_t xo[2 * NT], xol[2 * NT];
+      if constexpr (kActive) mlp_epilogue<P, W, NT, false>(m, l, c0, acc, xo, xol);
+      mlp_exchange<P, W, NT>(sm, grp, c0, xo, xol, x, xl);
+    }
+    const size_t o = mlpa_layer_offset(l + 1, W), on = mlpa_layer_offset(l + 2, W);
+    const bool deeper = l + 2 < m.depth;
+    mlp_layer_reg<P, W, NT, KS, false, kActive>(m, sm, c0, m.wa + o, m.wal + o, deeper ? m.wa + on : nullptr,
+                                                deeper ? m.wal + on : nullptr, acc, x, xl, px, py, pz);
+  }
+  return dot;
+}
+
+// Tile of nrows points with S waves per group of 32 points (4 / S groups).
+template <int P, int W, int S>
+__device__ __forceinline__ void mlp_tile_split(const MlpDesc& m, MlpSmem& sm, int nrows) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = w / S;
+  const int row = 32 * grp + (lane & 31);
+  const bool active = 32 * grp < nrows;  // wave-uniform
+  const int rr = row < nrows ? row : 32 * grp;  // idle lanes evaluate a valid point
+  float x = 0.f, y = 0.f, z = 0.f, part = 0.f;
+  if (active) {
+    x = sm.pts[rr][0];
+    y = sm.pts[rr][1];
+    z = sm.pts[rr][2];
+    part = mlp_wave<P, W, S, true>(m, sm, x, y, z);
+  } else {
+    (void)mlp_wave<P, W, S, false>(m, sm, 0.f, 0.f, 0.f);
+  }
+  if constexpr (S == 1) {
+    if (active && lane < 32 && row < nrows) sm.f[row] = mlp_value(m, x, y, z, m.b_out + part);
+  } else {
+    if (active && lane < 32) sm.part[w % S][row] = part;
+    __syncthreads();
+    if (active && (w % S) == 0 && lane < 32 && row < nrows) {
+      float p[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) p[q] = sm.part[q][row];
+#pragma unroll
+      for (int span = 1; span < S; span *= 2)  // the same pairwise tree as within a wave
+#pragma unroll
+        for (int q = 0; q + span < S; q += 2 * span) p[q] += p[q + span];
+      sm.f[row] = mlp_value(m, x, y, z, m.b_out + p[0]);
+    }
+  }
+  __syncthreads();
+}
+
+// A tile with few rows spreads each group's layers over more waves: the
+// round takes about as long as the largest share of one wave.
+template <int P, int W>
+__device__ __forceinline__ void mlp_tile_reg(const MlpDesc& m, MlpSmem& sm, int nrows) {
+  constexpr int kS4 = W / 32 >= 4 ? 4 : W / 32;  // at least one m-tile per wave
+  if (nrows <= 32) mlp_tile_split<P, W, kS4>(m, sm, nrows);
+  else if (nrows <= 64) mlp_tile_split<P, W, 2>(m, sm, nrows);
+  else mlp_tile_split<P, W, 1>(m, sm, nrows);
+}
+
+// Blocks per CU a kernel holding the tile evaluator is compiled for: the LDS
+// allows two; the split bf16 form at width 256 needs the registers of one.
+template <int P, int W>
+__host__ __device__ constexpr int mlp_min_blocks() { return (P == kPrecBf16x3 && W == 256) ? 1 : 1; }
+
+// Evaluates f at sm.pts[0, nrows) into sm.f[0, nrows) (nrows <= mlp_rows<P>);
+// sm.pts must be visible to the block (synchronised) before the call.
+template <int P, int W>
+__device__ __forceinline__ void mlp_tile(const MlpDesc& m, MlpSmem& sm, int nrows) {
+  if constexpr (P == kPrecF32) mlp_tile_f32<W>(m, sm, nrows);
+  else mlp_tile_reg<P, W>(m, sm, nrows);
 }
 
 }  // namespace gh

@@ -20,7 +20,7 @@ namespace gh {
 
 // ------------------------------------------------------------- point lists
 template <int P, int W>
-__global__ __launch_bounds__(kBlock) void k_mlp_points(MlpDesc m, const float* __restrict__ xyz, float* __restrict__ f,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_points(MlpDesc m, const float* __restrict__ xyz, float* __restrict__ f,
                                                        int64_t count) {
   __shared__ MlpSmem sm;
   constexpr int R = mlp_rows<P>();
@@ -41,46 +41,87 @@ __global__ __launch_bounds__(kBlock) void k_mlp_points(MlpDesc m, const float* _
   }
 }
 
-// Bound at every corner of the corner list; signs certified (see above).
+// FP32 values of the corners whose indices are in s_idx[0, cnt) (cnt <=
+// kF32Rows), written to the corner list.
+template <int W>
+__device__ __forceinline__ void corners_fp32(const MlpDesc& m, const Grid& g, const Workspace& ws, MlpSmem& sm,
+                                             const int64_t* s_idx, int cnt) {
+  const int n1 = g.n + 1;
+  const int t = threadIdx.x;
+  if (t < cnt) {
+    const int64_t i = s_idx[t];
+    const int L = ws.cl[i], a = L / n1, b = L - a * n1;
+    sm.pts[t][0] = lattice(g, a);
+    sm.pts[t][1] = lattice(g, b);
+    sm.pts[t][2] = lattice(g, ws.ck[i]);
+  }
+  __syncthreads();
+  mlp_tile<kPrecF32, W>(m, sm, cnt);
+  if (t < cnt) ws.cf[s_idx[t]] = sm.f[t];
+  __syncthreads();
+}
+
+// Bound at every corner of the corner list.  In the bf16 precisions a value
+// with |f| < eps gets an FP32 value instead (its sign is then the FP32 sign);
+// those corners are collected per block and evaluated in full FP32 tiles.
 template <int P, int W>
-__global__ __launch_bounds__(kBlock) void k_mlp_corners(MlpDesc m, Grid g, Workspace ws, gh_counters* __restrict__ ctr) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_corners(
+    MlpDesc m, Grid g, Workspace ws, gh_counters* __restrict__ ctr) {
   __shared__ MlpSmem sm;
   __shared__ int s_cnt[kBlock / 64];
+  __shared__ int64_t s_idx[kF32Rows + kBf16Rows];
   constexpr int R = mlp_rows<P>();
   const int64_t count = ws.nlist[0];
   if (count > ws.cap) return;
   const int n1 = g.n + 1;
   uint64_t reevals = 0;
+  int npend = 0;  // block-uniform
   const int64_t tiles = (count + R - 1) / R;
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t i0 = tile * R;
     const int nrows = (int)(count - i0 < R ? count - i0 : R);
     const bool mine = (int)threadIdx.x < nrows;
-    float x = 0.f, y = 0.f, z = 0.f;
     if (mine) {
       const int64_t i = i0 + threadIdx.x;
       const int L = ws.cl[i], a = L / n1, b = L - a * n1;
-      x = lattice(g, a);
-      y = lattice(g, b);
-      z = lattice(g, ws.ck[i]);
-      sm.pts[threadIdx.x][0] = x;
-      sm.pts[threadIdx.x][1] = y;
-      sm.pts[threadIdx.x][2] = z;
+      sm.pts[threadIdx.x][0] = lattice(g, a);
+      sm.pts[threadIdx.x][1] = lattice(g, b);
+      sm.pts[threadIdx.x][2] = lattice(g, ws.ck[i]);
     }
     __syncthreads();
     mlp_tile<P, W>(m, sm, nrows);
-    float f = mine ? sm.f[threadIdx.x] : 0.f;
+    const float f = mine ? sm.f[threadIdx.x] : 0.f;
     __syncthreads();
-    if constexpr (P != kPrecF32) f = reeval_fp32<W>(m, sm, s_cnt, mine && fabsf(f) < m.eps, x, y, z, f, reevals);
-    if (mine) ws.cf[i0 + threadIdx.x] = f;
+    if constexpr (P != kPrecF32) {
+      const bool amb = mine && fabsf(f) < m.eps;
+      int namb;
+      const int r = block_rank(amb, s_cnt, namb);
+      if (amb) s_idx[npend + r] = i0 + threadIdx.x;
+      else if (mine) ws.cf[i0 + threadIdx.x] = f;
+      npend += namb;
+      __syncthreads();
+      while (npend >= kF32Rows) {
+        npend -= kF32Rows;
+        corners_fp32<W>(m, g, ws, sm, s_idx + npend, kF32Rows);
+        reevals += threadIdx.x == 0 ? kF32Rows : 0;
+      }
+    } else {
+      if (mine) ws.cf[i0 + threadIdx.x] = f;
+    }
   }
-  if constexpr (P != kPrecF32) block_add_u64(reevals, (unsigned long long*)&ctr->n_reeval);
+  if constexpr (P != kPrecF32) {
+    if (npend > 0) {
+      corners_fp32<W>(m, g, ws, sm, s_idx, npend);
+      reevals += threadIdx.x == 0 ? npend : 0;
+    }
+    block_add_u64(reevals, (unsigned long long*)&ctr->n_reeval);
+  }
 }
 
 // Enumeration: a tile covers R/64 units of 64 consecutive lattice points c
 // of one lattice column; each unit becomes two sign words (bit: f < 0).
 template <int P, int W>
-__global__ __launch_bounds__(kBlock) void k_mlp_dense(MlpDesc m, Grid g, uint32_t* __restrict__ signs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_dense(MlpDesc m, Grid g, uint32_t* __restrict__ signs,
                                                       uint64_t* __restrict__ colmask, gh_counters* __restrict__ ctr) {
   __shared__ MlpSmem sm;
   __shared__ int s_cnt[kBlock / 64];
@@ -134,7 +175,7 @@ struct QueueRays {
 };
 
 template <int P, int W>
-__global__ __launch_bounds__(kBlock) void k_hop_mlp(MlpDesc m, Grid g, uint64_t* __restrict__ colmask,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_hop_mlp(MlpDesc m, Grid g, uint64_t* __restrict__ colmask,
                                                     uint32_t* __restrict__ colbits, unsigned int* __restrict__ queue,
                                                     gh_counters* __restrict__ ctr) {
   __shared__ MlpSmem sm;

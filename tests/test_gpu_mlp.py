@@ -188,3 +188,18 @@ def test_full_size_bf16x3_n512(gh):
     f = osdb.neural_f64(net, out["verts"][sel])
     assert np.abs(f).max() <= 0.25 * float(h)
     assert c["n_reeval"] < 0.01 * c["n_hop_evals"]
+
+
+@pytest.mark.parametrize("prec,width", [("bf16", 64), ("bf16", 256), ("bf16x3", 128), ("bf16x3", 256)])
+def test_value_does_not_depend_on_tile_fill(gh, prec, width):
+    # tiles with few rows spread their layers over more waves; the value of a
+    # point must be the same bits whatever else shares its tile
+    import torch
+    native, P = gh
+    net = W.neural_scene(0, width)
+    b = P.Bound.mlp(net, prec, margin=1e-3)
+    pts = torch.tensor(W.probe_points(seed=11, n=300).astype(np.float32), device="cuda")
+    full = b.eval(pts).cpu().numpy()
+    for n in (1, 5, 31, 32, 33, 64, 65, 100, 127, 128, 129):
+        part = b.eval(pts[:n].contiguous()).cpu().numpy()
+        np.testing.assert_array_equal(part.view(np.uint32), full[:n].view(np.uint32), err_msg=f"n={n}")
