@@ -111,7 +111,7 @@ def event_ms(stream, fn, reps):
     return sum(a.elapsed_time(b) for a, b in ev) / reps
 
 
-def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", dense=True):
+def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", dense=True, tune=True):
     import torch
 
     import workloads as W
@@ -121,6 +121,11 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", den
     margin = bf16_margin(net, W.probe_points(seed=3, n=65536), precision) if precision != "fp32" else 0.0
     poly = Polygonizer(Bound.mlp(net, precision, margin=margin, device=dev), n, lo, h, device=dev, keep_cells=False)
     c0 = dict(poly.run().counters)
+    tuning = None
+    if tune:
+        from paper_2111_05778_amd import autotune
+        tuning, _, _ = autotune.tune(poly, reps=2, store=False)
+        poly.tuning = tuning
     stream = torch.cuda.current_stream(dev)
     for _ in range(warmup):
         poly.enqueue_hop()
@@ -129,7 +134,7 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", den
     mc_ms = event_ms(stream, poly.enqueue_mc, steps)
     fpp = mlp_flop_per_point(width, 4, 16)
     flop = c0["n_hop_evals"] * fpp
-    out = {"workload": f"mlp_w{width}_d4_f16_seed0_n{n}", "precision": precision, "margin": margin,
+    out = {"workload": f"mlp_w{width}_d4_f16_seed0_n{n}", "precision": precision, "margin": margin, "tuning": tuning,
            "value": n ** 3 / ((hop_ms + mc_ms) * 1e-3), "unit": "cells/s", "hop_ms": hop_ms, "mc_ms": mc_ms,
            "counters": {k: c0[k] for k in ("n_hop_evals", "n_reeval", "n_corner", "n_vert", "n_tri")},
            "roofline": {"bound": "mfma", "kernel": "k_hop_mlp", "achieved": flop / (hop_ms * 1e-3) / 1e12,
@@ -179,7 +184,7 @@ def backward_section(dev, steps, warmup, n=256, width=256):
             "n_vert": int(V.shape[0]), "params": P, "grad_norm": float(grad.norm())}
 
 
-def batch_section(dev, steps, warmup, precision="bf16x3"):
+def batch_section(dev, steps, warmup, precision="bf16x3", tune=True):
     import torch
 
     import workloads as W
@@ -195,6 +200,12 @@ def batch_section(dev, steps, warmup, precision="bf16x3"):
             net = W.neural_scene(sc["seed"], sc["width"])
             b = Bound.mlp(net, precision, margin=bf16_margin(net, probe, precision), device=dev)
         shapes.append((b, n, lo, h))
+    tuning = None
+    if tune:
+        from paper_2111_05778_amd import autotune
+        tuning, _, _ = autotune.tune_batch(lambda: BatchPolygonizer(shapes, device=dev, keep_cells=False),
+                                           [(b, n) for (b, n, _, _) in shapes], reps=1, store=False)
+        autotune.apply(tuning)             # the item size is read when the batch is planned
     batch = BatchPolygonizer(shapes, device=dev, keep_cells=False)
     res = batch.run()
     ref = [dict(m.counters) for m in res]
@@ -211,7 +222,7 @@ def batch_section(dev, steps, warmup, precision="bf16x3"):
     for p, c in zip(batch.polys, ref):
         assert counters_dict(p.ctr)["n_tri"] == c["n_tri"]
     cells = sum(sc["n"] ** 3 for sc in scenes)
-    return {"workload": "batch64_seed2", "precision": precision, "shapes": len(scenes), "cells": cells,
+    return {"workload": "batch64_seed2", "precision": precision, "tuning": tuning, "shapes": len(scenes), "cells": cells,
             "work_items": batch.item_count(), "ms_per_step": ms, "value": cells / (ms * 1e-3), "unit": "cells/s",
             "n_tri": sum(c["n_tri"] for c in ref)}
 
@@ -228,6 +239,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes five times (the known-size kernel "
                          "that scales the HBM counters) and exit")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape autotuner (built-in shapes)")
     ap.add_argument("--sections", default="neural,backward,batch",
                     help="extra workloads to measure after the headline one (comma list, or none)")
     args = ap.parse_args()
@@ -257,6 +270,11 @@ def main():
     poly = Polygonizer(Bound.prims(recs, dev), n, lo, h, device=dev, keep_cells=False)
     ref = poly.run()                       # sizes the buffers; reference counters
     c0 = dict(ref.counters)
+    tuning = None
+    if not args.no_tune:                   # outside the timed region
+        from paper_2111_05778_amd import autotune
+        tuning, _, _ = autotune.tune(poly, reps=3, store=False)
+        poly.tuning = tuning
     stream = torch.cuda.current_stream(dev)
 
     def timed(enqueue_first, steps, warmup):
@@ -314,6 +332,7 @@ def main():
         "config": {"workload": f"csg12_seed{args.seed}_n{n}", "n": n, "domain": "[-1,1]^3",
                    "primitives": len(recs)},
         "counters": {k: c0[k] for k in ("n_hop_evals", "n_cand", "n_corner", "n_cells", "n_vert", "n_tri")},
+        "tuning": tuning,
         "dense": dense,
         "speedup_vs_dense": (dense["ms_per_step"] / ms_per_step) if dense else None,
         "roofline": roofline,
@@ -321,12 +340,12 @@ def main():
     }
     sw = max(1, args.warmup)
     if "neural" in sections:
-        out["neural"] = neural_section(dev, max(3, args.steps // 4), sw, dense=not args.no_dense)
+        out["neural"] = neural_section(dev, max(3, args.steps // 4), sw, dense=not args.no_dense, tune=not args.no_tune)
     if "backward" in sections:
         out["backward"] = backward_section(dev, max(3, args.steps // 4), sw)
         out["backward_ms"] = out["backward"]["backward_ms"]
     if "batch" in sections:
-        out["batch"] = batch_section(dev, max(3, args.steps // 4), sw)
+        out["batch"] = batch_section(dev, max(3, args.steps // 4), sw, tune=not args.no_tune)
     print(json.dumps(out), flush=True)
 
 

@@ -253,8 +253,15 @@ gh_status gh_batch_destroy(gh_batch* batch);
 /* Launch shapes of the kernels, process-wide (an autotuner sets them).
  * Fields left at 0 keep the built-in choice. */
 typedef struct {
-  int32_t hop_lanes_per_ray; /* lanes tracing one ray together: 1, 2, 4 or 8 */
-  int32_t reserved[7];
+  int32_t hop_lanes_per_ray;   /* analytic hop: lanes tracing one ray together: 1, 2, 4 or 8 (default 4) */
+  int32_t scan_blocks_per_cu;  /* marching-cubes look-back scans: resident blocks per CU, 1, 2, 4 or 8
+                                  (default 4; never more than the occupancy allows) */
+  int32_t batch_rays_per_item; /* batch: rays per network work item, a power of two in [256, 65536]
+                                  (default 4096); read by gh_batch_create */
+  int32_t mlp_split;           /* network tiles with few rows: 1 never split, 2 split tiles of <= 32 rows
+                                  over four waves, 3 also tiles of <= 64 rows over two (default 3);
+                                  values do not depend on it */
+  int32_t reserved[4];
 } gh_tuning;
 
 /* Replace the process-wide launch shapes; GH_EINVAL for unsupported values. */

@@ -18,7 +18,7 @@
 namespace {
 
 thread_local std::string g_last_error;
-std::atomic<int> g_hop_lanes{0};
+std::atomic<int> g_hop_lanes{0}, g_scan_blocks{0}, g_batch_rays{0}, g_mlp_split{0};
 
 gh_status fail(gh_status st, const char* fmt, ...) {
   char buf[512];
@@ -217,6 +217,7 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.b = sp->b;
   m.b_out = sp->biases_h[D][0];
   m.eps = sp->bf16_margin;
+  m.split = 3;
   memset(desc_h, 0, sizeof(*desc_h));
   memcpy(desc_h, &d, sizeof(d));
   return GH_OK;
@@ -224,16 +225,39 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
 
 }  // namespace
 
+namespace gh {
+Tuning current_tuning() {
+  Tuning t;
+  const int r = g_hop_lanes.load(std::memory_order_relaxed), sb = g_scan_blocks.load(std::memory_order_relaxed),
+            br = g_batch_rays.load(std::memory_order_relaxed), ms = g_mlp_split.load(std::memory_order_relaxed);
+  t.hop_lanes_per_ray = r ? r : 4;
+  t.scan_blocks_per_cu = sb ? sb : 4;
+  t.batch_rays_per_item = br ? br : 4096;
+  t.mlp_split = ms ? ms : 3;
+  return t;
+}
+}  // namespace gh
+
 extern "C" {
 
 const char* gh_last_error(void) { return g_last_error.c_str(); }
 
 gh_status gh_set_tuning(const gh_tuning* t) {
   if (!t) return fail(GH_EINVAL, "tuning is NULL");
-  const int r = t->hop_lanes_per_ray;
+  const int r = t->hop_lanes_per_ray, sb = t->scan_blocks_per_cu, br = t->batch_rays_per_item, ms = t->mlp_split;
   if (!(r == 0 || r == 1 || r == 2 || r == 4 || r == 8))
     return fail(GH_EINVAL, "hop_lanes_per_ray = %d must be 0, 1, 2, 4 or 8", r);
+  if (!(sb == 0 || sb == 1 || sb == 2 || sb == 4 || sb == 8))
+    return fail(GH_EINVAL, "scan_blocks_per_cu = %d must be 0, 1, 2, 4 or 8", sb);
+  if (!(br == 0 || (br >= 256 && br <= 65536 && (br & (br - 1)) == 0)))
+    return fail(GH_EINVAL, "batch_rays_per_item = %d must be 0 or a power of two in [256, 65536]", br);
+  if (!(ms >= 0 && ms <= 3)) return fail(GH_EINVAL, "mlp_split = %d must be 0, 1, 2 or 3", ms);
+  for (int q = 0; q < 4; ++q)
+    if (t->reserved[q] != 0) return fail(GH_EINVAL, "reserved tuning fields must be 0");
   g_hop_lanes.store(r, std::memory_order_relaxed);
+  g_scan_blocks.store(sb, std::memory_order_relaxed);
+  g_batch_rays.store(br, std::memory_order_relaxed);
+  g_mlp_split.store(ms, std::memory_order_relaxed);
   return GH_OK;
 }
 
@@ -241,6 +265,9 @@ gh_status gh_get_tuning(gh_tuning* t) {
   if (!t) return fail(GH_EINVAL, "tuning is NULL");
   memset(t, 0, sizeof(*t));
   t->hop_lanes_per_ray = g_hop_lanes.load(std::memory_order_relaxed);
+  t->scan_blocks_per_cu = g_scan_blocks.load(std::memory_order_relaxed);
+  t->batch_rays_per_item = g_batch_rays.load(std::memory_order_relaxed);
+  t->mlp_split = g_mlp_split.load(std::memory_order_relaxed);
   return GH_OK;
 }
 
@@ -338,7 +365,7 @@ gh_status gh_hop(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, siz
   if (!ctr) return fail(GH_EINVAL, "counters are NULL");
   hipStream_t s = (hipStream_t)stream;
   if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearAll, s), "clear")) != GH_OK) return st;
-  return hip_status(gh::launch_hop(d, g, w, ctr, g_hop_lanes.load(std::memory_order_relaxed), s), "hop");
+  return hip_status(gh::launch_hop(d, g, w, ctr, gh::current_tuning().hop_lanes_per_ray, s), "hop");
 }
 
 gh_status gh_dense(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,

@@ -314,10 +314,8 @@ size_t backward_layout(const MlpDesc& m, int64_t cap, void* base, BackwardWs* bw
 
 template <class K>
 static int grid_for(K kernel, int64_t tiles, int max_per_cu) {
-  int dev = 0, per_cu = 0;
-  (void)hipGetDevice(&dev);
-  hipDeviceProp_t prop;
-  const int cus = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 1;
+  int per_cu = 0;
+  const int cus = cu_count();
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
   const int64_t cap = (int64_t)cus * (per_cu < max_per_cu ? per_cu : max_per_cu);
   const int64_t gsz = tiles < cap ? tiles : cap;

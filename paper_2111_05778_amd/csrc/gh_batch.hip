@@ -2,7 +2,7 @@
 //
 // The plan holds a table of shapes (bound, grid, workspace, counters) and a
 // list of work items: a block tile of ray columns for an analytic bound, a
-// range of rays for a network bound.  Items are ordered by estimated cost,
+// range of rays for a network bound (gh_tuning.batch_rays_per_item).  Items are ordered by estimated cost,
 // longest first, and persistent blocks take them from one counter, so uneven
 // grids and widths keep the device busy until the end.  After the hop every
 // shape gets its own marching-cubes pass; the whole sequence can be captured
@@ -122,8 +122,6 @@ struct gh_batch {
 
 namespace {
 
-constexpr int64_t kRaysPerItem = 4096;
-
 size_t batch_layout(int n_shapes, int64_t n_items, void* base, gh_batch* b) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -154,9 +152,10 @@ void shape_items(int s, const gh::DevSdb& d, const gh::Grid& g, std::vector<std:
     for (int t = 0; t < nbh * nbw; ++t) out.push_back({cost, gh::WorkItem{s, 0, t, 0}});
   } else {
     const int64_t rays = (int64_t)g.n * g.n;
+    const int64_t per_item = gh::current_tuning().batch_rays_per_item;
     const double per_ray = steps * 2.0 * ((double)d.mlp.k1 * d.mlp.W + (double)(d.mlp.depth - 1) * d.mlp.W * d.mlp.W);
-    for (int64_t a = 0; a < rays; a += kRaysPerItem) {
-      const int64_t e = std::min(rays, a + kRaysPerItem);
+    for (int64_t a = 0; a < rays; a += per_item) {
+      const int64_t e = std::min(rays, a + per_item);
       out.push_back({per_ray * (double)(e - a), gh::WorkItem{s, 0, a, e}});
     }
   }
@@ -166,10 +165,8 @@ hipError_t enqueue_batch(gh_batch* b, hipStream_t s) {
   const int ns = (int)b->items.size();
   hipLaunchKernelGGL(gh::k_batch_clear, dim3(ns < 1024 ? ns : 1024), dim3(gh::kBlock), 0, s, b->d_shapes, ns,
                      b->d_head);
-  int dev = 0, per_cu = 0;
-  (void)hipGetDevice(&dev);
-  hipDeviceProp_t prop;
-  const int cus = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 1;
+  int per_cu = 0;
+  const int cus = gh::cu_count();
   auto hop = [&](auto kernel) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, gh::kBlock, 0) != hipSuccess || per_cu < 1)
       per_cu = 1;
@@ -256,7 +253,11 @@ gh_status gh_batch_create(int n_shapes, const gh_batch_item* items_h, void* dev_
   }
   batch_layout(n_shapes, b->n_items, dev_buf, b);
   std::vector<gh::BatchShape> shapes(n_shapes);
-  for (int i = 0; i < n_shapes; ++i) shapes[i] = gh::BatchShape{b->sdb[i], b->grids[i], b->ws[i], items_h[i].ctr};
+  const int split = gh::current_tuning().mlp_split;
+  for (int i = 0; i < n_shapes; ++i) {
+    shapes[i] = gh::BatchShape{b->sdb[i], b->grids[i], b->ws[i], items_h[i].ctr};
+    shapes[i].sdb.mlp.split = split;
+  }
   std::vector<gh::WorkItem> wi(b->n_items);
   for (int i = 0; i < b->n_items; ++i) wi[i] = work[i].second;
   hipStream_t s = (hipStream_t)stream;

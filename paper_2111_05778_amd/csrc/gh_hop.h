@@ -121,8 +121,8 @@ __device__ __forceinline__ int block_rank(bool pred, int* s_cnt, int& total) {
 
 // FP32 re-evaluation of the points (x, y, z) of the threads with amb set, in
 // tiles of kF32Rows; returns f updated for those threads.
-template <int W>
-__device__ __forceinline__ float reeval_fp32(const MlpDesc& m, MlpSmem& sm, int* s_cnt, bool amb, float x, float y,
+template <int W, class Sm>
+__device__ __forceinline__ float reeval_fp32(const MlpDesc& m, Sm& sm, int* s_cnt, bool amb, float x, float y,
                                              float z, float f, uint64_t& reevals) {
   int namb;
   const int arow = block_rank(amb, s_cnt, namb);
@@ -142,8 +142,8 @@ __device__ __forceinline__ float reeval_fp32(const MlpDesc& m, MlpSmem& sm, int*
   return f;
 }
 
-// A block keeps a pool of kBlock rays (one per thread), twice a tile of the
-// bf16 precisions.  Each round it refills finished slots from the ray source
+// A block keeps a pool of 2R rays (one per owner thread), twice a tile of R
+// rows.  Each round it refills finished slots from the ray source
 // (rays [first, end) of the column order, taken through src.take), then
 // evaluates one tile:
 //  * normally the current hop points of up to R live rays (R = tile rows),
@@ -157,14 +157,16 @@ __device__ __forceinline__ float reeval_fp32(const MlpDesc& m, MlpSmem& sm, int*
 // empty FP32 tile in every round that meets one ambiguous value.  The hop
 // rule (Section 3, eq. iter, cell-quantised) is applied to every value used,
 // so the schedule is the FP32 one.
-template <int P, int W, class Src>
+template <int P, int W, class Src, class Sm>
 __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, uint64_t* __restrict__ colmask,
                                              uint32_t* __restrict__ colbits, gh_counters* __restrict__ ctr,
-                                             MlpSmem& sm, int* s_cnt, unsigned int* s_base, Src src) {
+                                             Sm& sm, int* s_cnt, unsigned int* s_base, Src src) {
   constexpr int R = mlp_rows<P>();
   const int n = g.n;
   const size_t ncol = (size_t)n * n;
-  const bool owner = true;  // every thread owns one slot of the pool
+  // Two tiles' worth of slots: ready rays fill the tile while others wait for
+  // FP32 values, and the ray queue still balances the work between blocks.
+  const bool owner = (int)threadIdx.x < 2 * R;
   const float nf = (float)n;
   bool active = false, pend = false, bad = false;
   size_t col = 0;

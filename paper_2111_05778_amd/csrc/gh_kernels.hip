@@ -14,6 +14,8 @@
 
 #include <float.h>
 
+#include <atomic>
+
 #include "gh_device.h"
 #include "gh_launch.h"
 #include "gh_layout.h"
@@ -566,20 +568,26 @@ hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, uin
 // than the number of blocks the device holds at once: every tile a block
 // waits on then belongs to a resident block that only waits on earlier
 // tiles, so the scan always makes progress (no ticket counter needed).
-template <class K>
-static int resident_grid(K kernel, int64_t tiles) {
-  static thread_local int cache_dev = -1;
-  static thread_local int cus = 0;
+int cu_count() {
+  static std::atomic<int> cache[64];
   int dev = 0;
   (void)hipGetDevice(&dev);
-  if (dev != cache_dev) {
-    hipDeviceProp_t prop;
-    cus = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 1;
-    cache_dev = dev;
+  if (dev < 0 || dev >= 64) dev = 0;
+  int c = cache[dev].load(std::memory_order_relaxed);
+  if (c <= 0) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 1;
+    cache[dev].store(c, std::memory_order_relaxed);
   }
+  return c;
+}
+
+template <class K>
+static int resident_grid(K kernel, int64_t tiles) {
+  const int cus = cu_count();
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-  const int64_t cap = (int64_t)cus * (per_cu < 4 ? per_cu : 4);
+  const int want = current_tuning().scan_blocks_per_cu;
+  const int64_t cap = (int64_t)cus * (per_cu < want ? per_cu : want);
   const int64_t gsz = tiles < cap ? tiles : cap;
   return (int)(gsz < 1 ? 1 : gsz);
 }

@@ -10,6 +10,16 @@
 
 namespace gh {
 
+// Launch shapes in effect (gh_set_tuning); every field resolved to a value.
+struct Tuning {
+  int hop_lanes_per_ray, scan_blocks_per_cu, batch_rays_per_item, mlp_split;
+};
+Tuning current_tuning();
+
+// Compute units of the current device (cached per device).
+int cu_count();
+
+
 // What the kernels need to evaluate a bound; lives inside gh_sdb_desc.
 struct DevSdb {
   uint32_t magic;

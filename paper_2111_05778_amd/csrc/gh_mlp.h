@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace gh {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -57,6 +59,7 @@ struct MlpDesc {
   const float* omrev;   // [16] w_k / 2pi (turns per unit; zero past F), for the hardware sine
   int F, W, depth, k1;  // k1 = 3 + 6F features
   int precision;
+  int split;            // tiles with few rows: 1 never split, 2 split <= 32 rows, 3 also <= 64 rows
   float a_s, r0, a_n, b, b_out;
   float eps;            // |f_bf16 - f_fp32| bound used by the hop test
 };
@@ -177,17 +180,29 @@ __device__ __forceinline__ void mlp_layer_f32(const MlpDesc& m, Sm& sm, int l, i
       for (int t = 0; t < 16; ++t) acc[rt][ct][t] = 0.f;
   const int row_l = lane & 31, khalf = lane >> 5;
   const float* __restrict__ wl = m.wf + mlp_layer_offset(l, m.k1, W);
-  for (int kt = 0; kt < ksteps; ++kt) {
-    float bfr[S::NC];
+  // U k-steps per group: their weight loads are all in flight before the
+  // group's products, so the products wait for memory once per group.
+  constexpr int U = 8;
+  for (int kt0 = 0; kt0 < ksteps; kt0 += U) {
+    float bfr[U][S::NC];
 #pragma unroll
-    for (int ct = 0; ct < S::NC; ++ct) bfr[ct] = wl[(size_t)(kt * S::CT + ct0 + ct) * 64 + lane];
+    for (int u = 0; u < U; ++u) {
+      const int kt = kt0 + u < ksteps ? kt0 + u : ksteps - 1;  // in bounds; unused past the end
 #pragma unroll
-    for (int rt = 0; rt < S::NR; ++rt) {
-      if (rt0 + rt >= nrt) break;
-      const float afr = sm.af[((rt0 + rt) * 32 + row_l) * kF32Stride + kt * 2 + khalf];
+      for (int ct = 0; ct < S::NC; ++ct) bfr[u][ct] = wl[(size_t)(kt * S::CT + ct0 + ct) * 64 + lane];
+    }
 #pragma unroll
-      for (int ct = 0; ct < S::NC; ++ct)
-        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(afr, bfr[ct], acc[rt][ct], 0, 0, 0);
+    for (int u = 0; u < U; ++u) {
+      const int kt = kt0 + u;
+      if (kt >= ksteps) break;
+#pragma unroll
+      for (int rt = 0; rt < S::NR; ++rt) {
+        if (rt0 + rt >= nrt) break;
+        const float afr = sm.af[((rt0 + rt) * 32 + row_l) * kF32Stride + kt * 2 + khalf];
+#pragma unroll
+        for (int ct = 0; ct < S::NC; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(afr, bfr[u][ct], acc[rt][ct], 0, 0, 0);
+      }
     }
   }
   __syncthreads();  // every wave has read this layer's input
@@ -211,8 +226,8 @@ __device__ __forceinline__ void mlp_layer_f32(const MlpDesc& m, Sm& sm, int l, i
   __syncthreads();
 }
 
-template <int W>
-__device__ __forceinline__ void mlp_tile_f32(const MlpDesc& m, MlpSmem& sm, int nrows) {
+template <int W, class Sm>
+__device__ __forceinline__ void mlp_tile_f32(const MlpDesc& m, Sm& sm, int nrows) {
   constexpr int kParts = kMlpBlock / kF32Rows;  // threads per row in the output dot
   const int nrt = (nrows + 31) / 32;
   mlp_features_f32(m, sm, nrows);
@@ -581,8 +596,8 @@ __device__ __forceinline__ void mlp_tile_split(const MlpDesc& m, MlpSmem& sm, in
 template <int P, int W>
 __device__ __forceinline__ void mlp_tile_reg(const MlpDesc& m, MlpSmem& sm, int nrows) {
   constexpr int kS4 = W / 32 >= 4 ? 4 : W / 32;  // at least one m-tile per wave
-  if (nrows <= 32) mlp_tile_split<P, W, kS4>(m, sm, nrows);
-  else if (nrows <= 64) mlp_tile_split<P, W, 2>(m, sm, nrows);
+  if (m.split >= 2 && nrows <= 32) mlp_tile_split<P, W, kS4>(m, sm, nrows);
+  else if (m.split >= 3 && nrows <= 64) mlp_tile_split<P, W, 2>(m, sm, nrows);
   else mlp_tile_split<P, W, 1>(m, sm, nrows);
 }
 
@@ -593,10 +608,15 @@ __host__ __device__ constexpr int mlp_min_blocks() { return (P == kPrecBf16x3 &&
 
 // Evaluates f at sm.pts[0, nrows) into sm.f[0, nrows) (nrows <= mlp_rows<P>);
 // sm.pts must be visible to the block (synchronised) before the call.
-template <int P, int W>
-__device__ __forceinline__ void mlp_tile(const MlpDesc& m, MlpSmem& sm, int nrows) {
+template <int P, int W, class Sm>
+__device__ __forceinline__ void mlp_tile(const MlpDesc& m, Sm& sm, int nrows) {
   if constexpr (P == kPrecF32) mlp_tile_f32<W>(m, sm, nrows);
   else mlp_tile_reg<P, W>(m, sm, nrows);
 }
+
+// LDS of a kernel evaluating in precision P: the FP32-only layout when no
+// bf16 tile runs (it leaves room for two blocks per CU).
+template <int P>
+using MlpSmemFor = std::conditional_t<P == kPrecF32, MlpSmemF32, MlpSmem>;
 
 }  // namespace gh

@@ -22,7 +22,7 @@ namespace gh {
 template <int P, int W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_points(MlpDesc m, const float* __restrict__ xyz, float* __restrict__ f,
                                                        int64_t count) {
-  __shared__ MlpSmem sm;
+  __shared__ MlpSmemFor<P> sm;
   constexpr int R = mlp_rows<P>();
   const int64_t tiles = (count + R - 1) / R;
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -43,8 +43,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 
 // FP32 values of the corners whose indices are in s_idx[0, cnt) (cnt <=
 // kF32Rows), written to the corner list.
-template <int W>
-__device__ __forceinline__ void corners_fp32(const MlpDesc& m, const Grid& g, const Workspace& ws, MlpSmem& sm,
+template <int W, class Sm>
+__device__ __forceinline__ void corners_fp32(const MlpDesc& m, const Grid& g, const Workspace& ws, Sm& sm,
                                              const int64_t* s_idx, int cnt) {
   const int n1 = g.n + 1;
   const int t = threadIdx.x;
@@ -67,7 +67,7 @@ __device__ __forceinline__ void corners_fp32(const MlpDesc& m, const Grid& g, co
 template <int P, int W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_corners(
     MlpDesc m, Grid g, Workspace ws, gh_counters* __restrict__ ctr) {
-  __shared__ MlpSmem sm;
+  __shared__ MlpSmemFor<P> sm;
   __shared__ int s_cnt[kBlock / 64];
   __shared__ int64_t s_idx[kF32Rows + kBf16Rows];
   constexpr int R = mlp_rows<P>();
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 template <int P, int W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_dense(MlpDesc m, Grid g, uint32_t* __restrict__ signs,
                                                       uint64_t* __restrict__ colmask, gh_counters* __restrict__ ctr) {
-  __shared__ MlpSmem sm;
+  __shared__ MlpSmemFor<P> sm;
   __shared__ int s_cnt[kBlock / 64];
   constexpr int R = mlp_rows<P>();
   constexpr int kUnits = R / 64;
@@ -178,7 +178,7 @@ template <int P, int W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_hop_mlp(MlpDesc m, Grid g, uint64_t* __restrict__ colmask,
                                                     uint32_t* __restrict__ colbits, unsigned int* __restrict__ queue,
                                                     gh_counters* __restrict__ ctr) {
-  __shared__ MlpSmem sm;
+  __shared__ MlpSmemFor<P> sm;
   __shared__ int s_cnt[kBlock / 64];
   __shared__ unsigned int s_base;
   hop_mlp_pool<P, W>(m, g, colmask, colbits, ctr, sm, s_cnt, &s_base, QueueRays{queue, 0, (int64_t)g.n * g.n});
@@ -187,10 +187,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 // ================================================================ launchers
 template <class K>
 static int mlp_grid(K kernel, int64_t tiles) {
-  int dev = 0, per_cu = 0;
-  (void)hipGetDevice(&dev);
-  hipDeviceProp_t prop;
-  const int cus = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 1;
+  int per_cu = 0;
+  const int cus = cu_count();
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
   const int64_t cap = (int64_t)cus * per_cu;
   const int64_t gsz = tiles < cap ? tiles : cap;
@@ -242,9 +240,11 @@ static hipError_t launch_mlp_p(int what, const DevSdb& d, const Grid& g, const W
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mlp(int what, const DevSdb& d, const Grid& g, const Workspace* ws, uint32_t* signs,
+hipError_t launch_mlp(int what, const DevSdb& d0, const Grid& g, const Workspace* ws, uint32_t* signs,
                       const float* xyz, float* f, int64_t count, gh_counters* ctr, hipStream_t s) {
-  if (d.kind != GH_SDB_MLP) return hipErrorInvalidValue;
+  if (d0.kind != GH_SDB_MLP) return hipErrorInvalidValue;
+  DevSdb d = d0;
+  d.mlp.split = current_tuning().mlp_split;
   switch (d.mlp.precision) {
     case kPrecBf16: return launch_mlp_p<kPrecBf16>(what, d, g, ws, signs, xyz, f, count, ctr, s);
     case kPrecBf16x3: return launch_mlp_p<kPrecBf16x3>(what, d, g, ws, signs, xyz, f, count, ctr, s);

@@ -98,7 +98,11 @@ class Polygonizer:
     """Buffers and call sequence for one bound on one grid (n, lo, h)."""
 
     def __init__(self, bound, n, lo, h, corner_cap=0, vert_cap=0, tri_cap=0, cell_cap=0, device="cuda",
-                 keep_cells=True, keep_edges=True):
+                 keep_cells=True, keep_edges=True, tuning=None):
+        """tuning: launch shapes applied (process-wide) before each enqueue: a
+        dict of gh_tuning fields, "auto" for the autotuner's cached choice for
+        this workload (defaults when none is cached), or None to leave the
+        current setting alone."""
         self.bound = bound
         self.grid = N.make_grid(n, lo, h)
         self.n = int(n)
@@ -111,7 +115,28 @@ class Polygonizer:
         self.keep_cells, self.keep_edges = keep_cells, keep_edges
         self.ctr = torch.zeros(8, dtype=torch.int64, device=self.device)
         self.dense_buf = None
+        if tuning == "auto":
+            from . import autotune
+            tuning = autotune.lookup(autotune.signature(bound.spec, self.n), self.device) or {}
+        self.tuning = tuning
         self._alloc()
+
+    @property
+    def tuning(self):
+        return self._tuning
+
+    @tuning.setter
+    def tuning(self, t):
+        """Launch shapes (dict of gh_tuning fields; missing or zero fields keep
+        the built-in choice), applied before each enqueue; None leaves the
+        process-wide setting alone."""
+        self._tuning = None if t is None else dict(t)
+        self._tuning_struct = None
+        if t is not None:
+            st = N.gh_tuning()
+            for f in N.TUNING_FIELDS:
+                setattr(st, f, int(t.get(f, 0)))
+            self._tuning_struct = st
 
     def _alloc(self):
         dev = self.device
@@ -125,10 +150,16 @@ class Polygonizer:
         self.cases = torch.empty(self.cell_cap, dtype=torch.uint8, device=dev) if self.keep_cells else None
 
     # ---------------------------------------------------------- enqueue only
+    def _apply_tuning(self):
+        if self._tuning_struct is not None:  # one host call: the enqueue path stays lean
+            N.check(N.lib.gh_set_tuning(ctypes.byref(self._tuning_struct)), "gh_set_tuning")
+
     def enqueue_hop(self, stream=None):
+        self._apply_tuning()
         N.check(N.gh_hop(self.bound.desc, self.grid, self.ws, self.corner_cap, self.ctr, stream), "gh_hop")
 
     def enqueue_dense(self, stream=None):
+        self._apply_tuning()
         if self.dense_buf is None:
             nb = N.gh_dense_signs_size(self.grid)
             self.dense_buf = torch.empty(nb // 4, dtype=torch.int32, device=self.device)
@@ -136,6 +167,7 @@ class Polygonizer:
                 "gh_dense")
 
     def enqueue_mc(self, stream=None):
+        self._apply_tuning()
         N.check(N.gh_mc(self.bound.desc, self.grid, self.ws, self.corner_cap, self.verts, self.vert_edge,
                         self.vert_t, self.vert_cap, self.tris, self.tri_cap, self.cells, self.cases,
                         self.cell_cap if self.keep_cells else 0, self.ctr, stream), "gh_mc")
