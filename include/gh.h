@@ -253,7 +253,8 @@ gh_status gh_batch_destroy(gh_batch* batch);
 /* Launch shapes of the kernels, process-wide (an autotuner sets them).
  * Fields left at 0 keep the built-in choice. */
 typedef struct {
-  int32_t hop_lanes_per_ray;   /* analytic hop: lanes tracing one ray together: 1, 2, 4 or 8 (default 4) */
+  int32_t hop_lanes_per_ray;   /* analytic hop: lanes tracing one ray together: 1, 2, 3, 4 or 8 (default:
+                                  the largest number of primitives of one type, 8 above 4) */
   int32_t scan_blocks_per_cu;  /* marching-cubes look-back scans: resident blocks per CU, 1, 2, 4 or 8
                                   (default 4; never more than the occupancy allows) */
   int32_t batch_rays_per_item; /* batch: rays per network work item, a power of two in [256, 65536]

@@ -22,8 +22,9 @@ import torch
 
 from . import native as N
 
-DEFAULTS = {"hop_lanes_per_ray": 4, "scan_blocks_per_cu": 4, "mlp_split": 3, "batch_rays_per_item": 4096}
-SPACE_PRIMS = {"hop_lanes_per_ray": [1, 2, 4, 8], "scan_blocks_per_cu": [1, 2, 4, 8]}
+# hop_lanes_per_ray 0 lets the library choose from the bound's type groups.
+DEFAULTS = {"hop_lanes_per_ray": 0, "scan_blocks_per_cu": 4, "mlp_split": 3, "batch_rays_per_item": 4096}
+SPACE_PRIMS = {"hop_lanes_per_ray": [0, 1, 2, 3, 4, 8], "scan_blocks_per_cu": [1, 2, 4, 8]}
 SPACE_MLP = {"mlp_split": [1, 2, 3], "scan_blocks_per_cu": [1, 2, 4, 8]}
 SPACE_BATCH = {"batch_rays_per_item": [1024, 2048, 4096, 8192, 16384]}
 

@@ -230,7 +230,7 @@ Tuning current_tuning() {
   Tuning t;
   const int r = g_hop_lanes.load(std::memory_order_relaxed), sb = g_scan_blocks.load(std::memory_order_relaxed),
             br = g_batch_rays.load(std::memory_order_relaxed), ms = g_mlp_split.load(std::memory_order_relaxed);
-  t.hop_lanes_per_ray = r ? r : 4;
+  t.hop_lanes_per_ray = r;  // 0: chosen per bound by the launcher
   t.scan_blocks_per_cu = sb ? sb : 4;
   t.batch_rays_per_item = br ? br : 4096;
   t.mlp_split = ms ? ms : 3;
@@ -245,8 +245,8 @@ const char* gh_last_error(void) { return g_last_error.c_str(); }
 gh_status gh_set_tuning(const gh_tuning* t) {
   if (!t) return fail(GH_EINVAL, "tuning is NULL");
   const int r = t->hop_lanes_per_ray, sb = t->scan_blocks_per_cu, br = t->batch_rays_per_item, ms = t->mlp_split;
-  if (!(r == 0 || r == 1 || r == 2 || r == 4 || r == 8))
-    return fail(GH_EINVAL, "hop_lanes_per_ray = %d must be 0, 1, 2, 4 or 8", r);
+  if (!(r == 0 || r == 1 || r == 2 || r == 3 || r == 4 || r == 8))
+    return fail(GH_EINVAL, "hop_lanes_per_ray = %d must be 0, 1, 2, 3, 4 or 8", r);
   if (!(sb == 0 || sb == 1 || sb == 2 || sb == 4 || sb == 8))
     return fail(GH_EINVAL, "scan_blocks_per_cu = %d must be 0, 1, 2, 4 or 8", sb);
   if (!(br == 0 || (br >= 256 && br <= 65536 && (br & (br - 1)) == 0)))

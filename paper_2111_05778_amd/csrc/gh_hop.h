@@ -14,19 +14,39 @@ namespace gh {
 // --------------------------------------------------------------------- hop
 // R lanes trace one ray together: lane q of the group evaluates primitives
 // q, q + R, q + 2R, ... of each type group (records staged in LDS) and a
-// butterfly over the R lanes forms the union's minimum, which every lane of
+// reduction over the R lanes forms the union's minimum, which every lane of
 // the group then holds bit for bit.  This divides the latency of one hop
 // step by about R; it matters because the kernel lasts as long as its
 // longest column, and a ray grazing a flat face steps cell by cell (the
 // plane-parallel case of Section 4.1 costs N steps on such a column).
 // A wave covers a compact patch of columns whose step counts are similar.
+// R = 3 suits unions with three primitives of each type (21 rays per wave,
+// the last lane idle).
 template <int R>
 struct HopShape {
   static constexpr int kWaveRays = 64 / R;
-  static constexpr int kWaveW = R == 1 ? 8 : (R == 2 ? 8 : (R == 4 ? 4 : 4));
+  static constexpr int kWaveW = R == 1 ? 8 : (R == 2 ? 8 : (R == 3 ? 7 : 4));
   static constexpr int kWaveH = kWaveRays / kWaveW;
   static constexpr int kBlockH = 2 * kWaveH, kBlockW = 2 * kWaveW;
+  static_assert(kWaveH * kWaveW == kWaveRays, "wave patch must hold every ray of the wave");
 };
+
+// Minimum over the R lanes of each ray group, identical in every lane of the
+// group (fminf is exact, so any order gives the same value).
+template <int R>
+__device__ __forceinline__ float group_min(float f, int q) {
+  if constexpr ((R & (R - 1)) == 0) {
+#pragma unroll
+    for (int m = 1; m < R; m <<= 1) f = fminf(f, __shfl_xor(f, m, 64));
+    return f;
+  } else {
+    const int base = lane_id() - q;
+    float v = __shfl(f, base, 64);
+#pragma unroll
+    for (int t = 1; t < R; ++t) v = fminf(v, __shfl(f, base + t, 64));
+    return v;
+  }
+}
 
 // Hop rule (Section 3, eq. iter, cell-quantised): at the centroid of cell k,
 // s = floor(|f| * inv_h); s >= 1 skips s cells, s == 0 marks cell k as a
@@ -46,7 +66,7 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
   const int j = bj * S::kBlockW + (w & 1) * S::kWaveW + r % S::kWaveW;
   uint64_t evals = 0, cands = 0;
   bool bad = false;
-  if (i < n && j < n) {  // uniform over the R lanes of a ray
+  if (r < S::kWaveRays && i < n && j < n) {  // uniform over the R lanes of a ray
     const size_t ncol = (size_t)n * n, col = (size_t)i * n + j;
     const float x = centroid(g, i), y = centroid(g, j);
     const float nf = (float)n;
@@ -56,8 +76,7 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
     while (k < n) {
       float f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y,
                               centroid(g, k));
-#pragma unroll
-      for (int m = 1; m < R; m <<= 1) f = fminf(f, __shfl_xor(f, m, 64));
+      f = group_min<R>(f, q);
       ++evals;
       const float d = fabsf(f);
       if (!(d <= FLT_MAX)) {

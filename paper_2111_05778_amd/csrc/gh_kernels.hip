@@ -14,6 +14,7 @@
 
 #include <float.h>
 
+#include <algorithm>
 #include <atomic>
 
 #include "gh_device.h"
@@ -532,10 +533,17 @@ hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_co
                       hipStream_t s) {
   if (d.kind == GH_SDB_MLP) return launch_mlp(3, d, g, &ws, nullptr, nullptr, nullptr, 0, ctr, s);
   if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
-  if (lanes_per_ray <= 0) lanes_per_ray = 4;
+  if (lanes_per_ray <= 0) {
+    // Built-in choice: as many lanes as the largest type group has
+    // primitives, so every lane of a group evaluates one of each type.
+    int most = 1;
+    for (int t = 0; t < kPrimTypes; ++t) most = std::max(most, d.groups.start[t + 1] - d.groups.start[t]);
+    lanes_per_ray = most <= 4 ? most : 8;
+  }
   switch (lanes_per_ray) {
     case 1: launch_hop_r<1>(d, g, ws, ctr, s); break;
     case 2: launch_hop_r<2>(d, g, ws, ctr, s); break;
+    case 3: launch_hop_r<3>(d, g, ws, ctr, s); break;
     case 4: launch_hop_r<4>(d, g, ws, ctr, s); break;
     case 8: launch_hop_r<8>(d, g, ws, ctr, s); break;
     default: return hipErrorInvalidValue;

@@ -35,7 +35,7 @@ constexpr uint32_t kDescMagic = 0x67687364u;  // "ghsd"
 enum ClearMode { kClearAll = 0, kClearMc = 1, kClearCands = 2 };
 
 hipError_t launch_clear(const Workspace& ws, gh_counters* ctr, ClearMode mode, hipStream_t s);
-// lanes_per_ray: 1, 2, 4 or 8 lanes trace one ray together (0 = default).
+// lanes_per_ray: 1, 2, 3, 4 or 8 lanes trace one ray together (0 = chosen from the type groups).
 hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, int lanes_per_ray,
                       hipStream_t s);
 hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, uint32_t* signs, gh_counters* ctr,

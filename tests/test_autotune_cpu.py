@@ -21,6 +21,7 @@ def test_cache_round_trip(tmp_path):
 def test_full_resolves_zero_and_missing_to_defaults():
     t = A.full({"hop_lanes_per_ray": 0, "scan_blocks_per_cu": 8, "unknown": 3})
     assert t == dict(A.DEFAULTS, scan_blocks_per_cu=8)
+    assert A.full({"hop_lanes_per_ray": 3})["hop_lanes_per_ray"] == 3
 
 
 def test_coordinate_descent_finds_the_minimum_and_skips_wrong_results():
@@ -66,7 +67,7 @@ def test_set_tuning_validates_and_round_trips():
         N.gh_set_tuning(hop_lanes_per_ray=2, scan_blocks_per_cu=8, batch_rays_per_item=1024, mlp_split=1)
         assert N.gh_get_tuning() == {"hop_lanes_per_ray": 2, "scan_blocks_per_cu": 8,
                                      "batch_rays_per_item": 1024, "mlp_split": 1}
-        for bad in ({"hop_lanes_per_ray": 3}, {"scan_blocks_per_cu": 16}, {"batch_rays_per_item": 1000},
+        for bad in ({"hop_lanes_per_ray": 5}, {"scan_blocks_per_cu": 16}, {"batch_rays_per_item": 1000},
                     {"batch_rays_per_item": 128}, {"mlp_split": 4}, {"mlp_split": -1}):
             with pytest.raises(N.GhError):
                 N.gh_set_tuning(**bad)

@@ -227,7 +227,7 @@ def test_empty_scene(gh):
     assert out["ctr"]["n_cand"] == 0 and out["ctr"]["n_tri"] == 0 and out["ctr"]["n_corner"] == 0
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+@pytest.mark.parametrize("lanes", [0, 1, 2, 3, 4, 8])
 def test_every_hop_shape_matches_twin(gh, lanes):
     native, P = gh
     recs = W.csg_scene(1)
@@ -251,7 +251,7 @@ def test_counters_repeatable_full_size(gh):
     b = P.Bound.prims(recs)
     import torch
     try:
-        for lanes in (1, 2, 4, 8):
+        for lanes in (0, 1, 2, 3, 4, 8):
             native.gh_set_tuning(lanes)
             poly = P.Polygonizer(b, n, lo, h, keep_cells=False)
             for _ in range(3):
@@ -261,3 +261,19 @@ def test_counters_repeatable_full_size(gh):
                 assert c["n_hop_evals"] == total and c["n_cand"] == len(cells), (lanes, c)
     finally:
         native.gh_set_tuning(0)
+
+
+@pytest.mark.parametrize("n_prim,lanes", [(5, 0), (7, 0), (7, 3), (16, 0), (16, 3), (1, 0)])
+def test_uneven_type_groups_match_twin(gh, n_prim, lanes):
+    # type groups of unequal size (the built-in lane count follows the
+    # largest group; R = 3 leaves lanes idle in smaller groups)
+    native, P = gh
+    recs = W.csg_scene(7, n_prim)
+    g = W.grid(61)
+    native.gh_set_tuning(hop_lanes_per_ray=lanes)
+    try:
+        out = _run(gh, recs, *g)
+    finally:
+        native.gh_set_tuning(0)
+    ref = ohop.gridhop(osdb.SDB.prims(recs), *g, precision="f32")
+    _check_against_twin(out, ref, *[float(x) for x in g])
