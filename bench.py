@@ -58,24 +58,33 @@ def mlp_flop_per_point(width, depth, n_freq):
     return 2 * (k1 * width + (depth - 1) * width * width + width)
 
 
-def kernel_source_hash():
+# Sources each profiled kernel is built from; a committed traffic figure is
+# used only while these files are unchanged.
+KERNEL_SOURCES = {
+    "k_hop": ("gh_kernels.hip", "gh_device.h", "gh_hop.h"),
+    "k_hop_mlp": ("gh_mlp.hip", "gh_mlp.h", "gh_hop.h", "gh_device.h"),
+}
+
+
+def kernel_source_hash(kernel):
     h = hashlib.sha256()
-    for name in ("gh_kernels.hip", "gh_device.h", "gh_hop.h"):
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2111_05778_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel):
-    """HBM bytes per launch from the committed PMC summary, if it was taken on
-    the current kernel source; else None."""
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration) from the committed PMC summary, if it was taken on the
+    current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
     e = t.get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash(kernel):
         return None
     return e["bytes_per_launch"]
 
@@ -139,7 +148,7 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", den
            "counters": {k: c0[k] for k in ("n_hop_evals", "n_reeval", "n_corner", "n_vert", "n_tri")},
            "roofline": {"bound": "mfma", "kernel": "k_hop_mlp", "achieved": flop / (hop_ms * 1e-3) / 1e12,
                         "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
-                        "frac": flop / (hop_ms * 1e-3) / PEAK_BF16_MFMA, "traffic": None,
+                        "frac": flop / (hop_ms * 1e-3) / PEAK_BF16_MFMA, "traffic": load_traffic("k_hop_mlp"),
                         "flop_per_point": fpp, "per_launch_flop": flop}}
     if dense:
         poly.enqueue_dense()
