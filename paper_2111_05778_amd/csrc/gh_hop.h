@@ -52,7 +52,10 @@ __device__ __forceinline__ float group_min(float f, int q) {
 // s = floor(|f| * inv_h); s >= 1 skips s cells, s == 0 marks cell k as a
 // candidate and moves to k + 1; the ray ends when k >= n.  One block tile of
 // columns; srec holds the primitive records in LDS.
-template <int R>
+// kRegs: every type group has at most R primitives, so each lane holds at
+// most one record per type; those records then live in registers for the
+// whole ray instead of being read from LDS at every step.
+template <int R, bool kRegs = false>
 __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
                                                uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                gh_counters* __restrict__ ctr, int tile) {
@@ -73,9 +76,32 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
     int k = 0, wi = 0;
     uint32_t word = 0;
     uint64_t mask = 0;
+    float rec[kPrimTypes][GH_PRIM_FLOATS];
+    bool has[kPrimTypes];
+    if constexpr (kRegs) {
+#pragma unroll
+      for (int t = 0; t < kPrimTypes; ++t) {
+        const int p = groups.start[t] + q;
+        has[t] = p < groups.start[t + 1];
+        const float* src = srec + (has[t] ? p : 0) * GH_PRIM_FLOATS;
+#pragma unroll
+        for (int e = 0; e < GH_PRIM_FLOATS; ++e) rec[t][e] = src[e];
+      }
+    }
     while (k < n) {
-      float f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y,
-                              centroid(g, k));
+      float f;
+      if constexpr (kRegs) {
+        const float z = centroid(g, k);
+        f = __builtin_inff();
+        if (has[kPrimSphere]) f = fminf(f, prim_eval_t<kPrimSphere>(rec[kPrimSphere], x, y, z));
+        if (has[kPrimBox]) f = fminf(f, prim_eval_t<kPrimBox>(rec[kPrimBox], x, y, z));
+        if (has[kPrimTorus]) f = fminf(f, prim_eval_t<kPrimTorus>(rec[kPrimTorus], x, y, z));
+        if (has[kPrimCapsule]) f = fminf(f, prim_eval_t<kPrimCapsule>(rec[kPrimCapsule], x, y, z));
+        if (has[kPrimPlane]) f = fminf(f, prim_eval_t<kPrimPlane>(rec[kPrimPlane], x, y, z));
+        if (has[kPrimBoxBound]) f = fminf(f, prim_eval_t<kPrimBoxBound>(rec[kPrimBoxBound], x, y, z));
+      } else {
+        f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y, centroid(g, k));
+      }
       f = group_min<R>(f, q);
       ++evals;
       const float d = fabsf(f);

@@ -54,13 +54,13 @@ __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, u
 }
 
 // --------------------------------------------------------------------- hop
-template <int R>
+template <int R, bool kRegs>
 __global__ __launch_bounds__(kBlock) void k_hop_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                       uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                       gh_counters* __restrict__ ctr) {
   __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
   stage_prims(s_rec, prims, groups.start[kPrimTypes]);
-  hop_prims_tile<R>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, ctr, blockIdx.x);
+  hop_prims_tile<R, kRegs>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, ctr, blockIdx.x);
 }
 
 // ------------------------------------------------------------ enumeration
@@ -525,8 +525,14 @@ template <int R>
 static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, hipStream_t s) {
   using S = HopShape<R>;
   const int nbh = (g.n + S::kBlockH - 1) / S::kBlockH, nbw = (g.n + S::kBlockW - 1) / S::kBlockW;
-  hipLaunchKernelGGL(k_hop_prims<R>, dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
-                     ws.colbits, ctr);
+  int most = 0;
+  for (int t = 0; t < kPrimTypes; ++t) most = std::max(most, d.groups.start[t + 1] - d.groups.start[t]);
+  if (most <= R)
+    hipLaunchKernelGGL((k_hop_prims<R, true>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
+                       ws.colmask, ws.colbits, ctr);
+  else
+    hipLaunchKernelGGL((k_hop_prims<R, false>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
+                       ws.colmask, ws.colbits, ctr);
 }
 
 hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, int lanes_per_ray,
