@@ -262,7 +262,9 @@ typedef struct {
   int32_t mlp_split;           /* network tiles with few rows: 1 never split, 2 split tiles of <= 32 rows
                                   over four waves, 3 also tiles of <= 64 rows over two (default 3);
                                   values do not depend on it */
-  int32_t reserved[4];
+  int32_t mc_items_per_thread; /* marching cubes: list entries per thread of the vertex and triangle passes,
+                                  1, 2, 4 or 8 (default 4) */
+  int32_t reserved[3];
 } gh_tuning;
 
 /* Replace the process-wide launch shapes; GH_EINVAL for unsupported values. */

@@ -2,8 +2,9 @@
 
 The library's launch shapes are process-wide (`gh_set_tuning`): lanes per ray
 of the analytic hop, resident blocks per CU of the marching-cubes look-back
-scans, the split policy of network tiles with few rows, and the rays per
-network work item of a batch.  None of them changes a result, only the time.
+scans, list entries per thread of the vertex and triangle passes, the split
+policy of network tiles with few rows, and the rays per network work item of
+a batch.  None of them changes a result, only the time.
 
 `tune()` measures a workload on the device under a coordinate descent over
 these shapes: each parameter in turn sweeps its values with the others held
@@ -23,9 +24,11 @@ import torch
 from . import native as N
 
 # hop_lanes_per_ray 0 lets the library choose from the bound's type groups.
-DEFAULTS = {"hop_lanes_per_ray": 0, "scan_blocks_per_cu": 4, "mlp_split": 3, "batch_rays_per_item": 4096}
-SPACE_PRIMS = {"hop_lanes_per_ray": [0, 1, 2, 3, 4, 8], "scan_blocks_per_cu": [1, 2, 4, 8]}
-SPACE_MLP = {"mlp_split": [1, 2, 3], "scan_blocks_per_cu": [1, 2, 4, 8]}
+DEFAULTS = {"hop_lanes_per_ray": 0, "scan_blocks_per_cu": 4, "mlp_split": 3, "batch_rays_per_item": 4096,
+            "mc_items_per_thread": 4}
+SPACE_PRIMS = {"hop_lanes_per_ray": [0, 1, 2, 3, 4, 8], "scan_blocks_per_cu": [1, 2, 4, 8],
+               "mc_items_per_thread": [1, 2, 4, 8]}
+SPACE_MLP = {"mlp_split": [1, 2, 3], "scan_blocks_per_cu": [1, 2, 4, 8], "mc_items_per_thread": [1, 2, 4, 8]}
 SPACE_BATCH = {"batch_rays_per_item": [1024, 2048, 4096, 8192, 16384]}
 
 

@@ -18,7 +18,7 @@
 namespace {
 
 thread_local std::string g_last_error;
-std::atomic<int> g_hop_lanes{0}, g_scan_blocks{0}, g_batch_rays{0}, g_mlp_split{0};
+std::atomic<int> g_hop_lanes{0}, g_scan_blocks{0}, g_batch_rays{0}, g_mlp_split{0}, g_mc_items{0};
 
 gh_status fail(gh_status st, const char* fmt, ...) {
   char buf[512];
@@ -234,6 +234,8 @@ Tuning current_tuning() {
   t.scan_blocks_per_cu = sb ? sb : 4;
   t.batch_rays_per_item = br ? br : 4096;
   t.mlp_split = ms ? ms : 3;
+  const int mi = g_mc_items.load(std::memory_order_relaxed);
+  t.mc_items_per_thread = mi ? mi : 4;
   return t;
 }
 }  // namespace gh
@@ -252,12 +254,16 @@ gh_status gh_set_tuning(const gh_tuning* t) {
   if (!(br == 0 || (br >= 256 && br <= 65536 && (br & (br - 1)) == 0)))
     return fail(GH_EINVAL, "batch_rays_per_item = %d must be 0 or a power of two in [256, 65536]", br);
   if (!(ms >= 0 && ms <= 3)) return fail(GH_EINVAL, "mlp_split = %d must be 0, 1, 2 or 3", ms);
-  for (int q = 0; q < 4; ++q)
+  const int mi = t->mc_items_per_thread;
+  if (!(mi == 0 || mi == 1 || mi == 2 || mi == 4 || mi == 8))
+    return fail(GH_EINVAL, "mc_items_per_thread = %d must be 0, 1, 2, 4 or 8", mi);
+  for (int q = 0; q < 3; ++q)
     if (t->reserved[q] != 0) return fail(GH_EINVAL, "reserved tuning fields must be 0");
   g_hop_lanes.store(r, std::memory_order_relaxed);
   g_scan_blocks.store(sb, std::memory_order_relaxed);
   g_batch_rays.store(br, std::memory_order_relaxed);
   g_mlp_split.store(ms, std::memory_order_relaxed);
+  g_mc_items.store(mi, std::memory_order_relaxed);
   return GH_OK;
 }
 
@@ -268,6 +274,7 @@ gh_status gh_get_tuning(gh_tuning* t) {
   t->scan_blocks_per_cu = g_scan_blocks.load(std::memory_order_relaxed);
   t->batch_rays_per_item = g_batch_rays.load(std::memory_order_relaxed);
   t->mlp_split = g_mlp_split.load(std::memory_order_relaxed);
+  t->mc_items_per_thread = g_mc_items.load(std::memory_order_relaxed);
   return GH_OK;
 }
 

@@ -319,14 +319,15 @@ __device__ __forceinline__ unsigned cross_mask(const Workspace& ws, const Grid& 
   return msk;
 }
 
-// Each thread takes kItems consecutive list entries, so a tile covers
-// kBlock * kItems entries and the entries keep their order in the output.
-constexpr int kItems = 4;
-constexpr int kTileItems = kBlock * kItems;
+// Each thread takes kItems consecutive list entries (a launch shape: 1, 2, 4
+// or 8), so a tile covers kBlock * kItems entries and the entries keep their
+// order in the output.
 
+template <int kItems>
 __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* __restrict__ verts,
                                                   int64_t* __restrict__ vert_edge, float* __restrict__ vert_t,
                                                   int64_t vert_cap, gh_counters* __restrict__ ctr) {
+  constexpr int kTileItems = kBlock * kItems;
   const int64_t m = ws.nlist[0];
   if (m > ws.cap) return;  // uniform: the corners overflowed, nothing to do
   const int n1 = g.n + 1;
@@ -413,10 +414,12 @@ __device__ __forceinline__ bool cell_corners(const Workspace& ws, int n, size_t 
   return true;
 }
 
+template <int kItems>
 __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* __restrict__ tris, int64_t tri_cap,
                                                  int64_t* __restrict__ cells, uint8_t* __restrict__ cases,
                                                  int64_t cell_cap, int64_t vert_cap,
                                                  gh_counters* __restrict__ ctr) {
+  constexpr int kTileItems = kBlock * kItems;
   __shared__ McCase s_mc[256];
   s_mc[threadIdx.x] = g_mc.c[threadIdx.x];
   __syncthreads();
@@ -617,7 +620,8 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
                      float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap, int64_t* cells,
                      uint8_t* cases, int64_t cell_cap, gh_counters* ctr, hipStream_t s) {
   if (d.kind != GH_SDB_PRIMS && d.kind != GH_SDB_MLP) return hipErrorInvalidValue;
-  const int64_t list_tiles = (ws.cap + kTileItems - 1) / kTileItems;
+  const int items = current_tuning().mc_items_per_thread;
+  const int64_t list_tiles = (ws.cap + (int64_t)kBlock * items - 1) / ((int64_t)kBlock * items);
   hipLaunchKernelGGL(k_corners, dim3(resident_grid(k_corners, ws.tiles_lat)), dim3(kBlock), 0, s, g, ws, ctr);
   if (d.kind == GH_SDB_MLP) {
     const hipError_t e = launch_mlp(1, d, g, &ws, nullptr, nullptr, nullptr, 0, ctr, s);
@@ -626,10 +630,18 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
     hipLaunchKernelGGL(k_eval_corners<PrimsEval>, dim3(persistent_blocks(ws.cap)), dim3(kBlock), 0, s,
                        PrimsEval{d.prims, d.groups}, g, ws);
   }
-  hipLaunchKernelGGL(k_verts, dim3(resident_grid(k_verts, list_tiles)), dim3(kBlock), 0, s, g, ws, verts, vert_edge,
-                     vert_t, vert_cap, ctr);
-  hipLaunchKernelGGL(k_tris, dim3(resident_grid(k_tris, list_tiles)), dim3(kBlock), 0, s, g, ws, tris, tri_cap, cells,
-                     cases, cell_cap, vert_cap, ctr);
+  auto emit = [&](auto kv, auto kt) {
+    hipLaunchKernelGGL(kv, dim3(resident_grid(kv, list_tiles)), dim3(kBlock), 0, s, g, ws, verts, vert_edge, vert_t,
+                       vert_cap, ctr);
+    hipLaunchKernelGGL(kt, dim3(resident_grid(kt, list_tiles)), dim3(kBlock), 0, s, g, ws, tris, tri_cap, cells,
+                       cases, cell_cap, vert_cap, ctr);
+  };
+  switch (items) {
+    case 1: emit(k_verts<1>, k_tris<1>); break;
+    case 2: emit(k_verts<2>, k_tris<2>); break;
+    case 8: emit(k_verts<8>, k_tris<8>); break;
+    default: emit(k_verts<4>, k_tris<4>); break;
+  }
   return hipGetLastError();
 }
 
