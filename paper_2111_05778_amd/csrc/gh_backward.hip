@@ -158,14 +158,26 @@ __device__ __forceinline__ void vjp_dg(const MlpDesc& m, VjpSmem& sm, int l, con
   for (int q = 0; q < kPerWave; ++q)
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc[q][t] = 0.f;
-  for (int os = 0; os < W / 2; ++os) {
+  // U k-steps per group: the weight loads of a group are all in flight before
+  // its products (W / 2 is a multiple of U for every supported width).
+  constexpr int U = 8;
+  for (int os0 = 0; os0 < W / 2; os0 += U) {
+    float bv[U][kPerWave];
 #pragma unroll
-    for (int q = 0; q < kPerWave; ++q) {
-      const int tt = w * kPerWave + q, rt = tt / KT, kt = tt - rt * KT;
-      const float av = sm.g[(rt * 32 + (lane & 31)) * kF32Stride + 2 * os + (lane >> 5)];
-      const float bv = wt[(size_t)(os * KT + kt) * 64 + lane];
-      acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[q], 0, 0, 0);
-    }
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < kPerWave; ++q) {
+        const int tt = w * kPerWave + q, kt = tt % KT;
+        bv[u][q] = wt[(size_t)((os0 + u) * KT + kt) * 64 + lane];
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < kPerWave; ++q) {
+        const int tt = w * kPerWave + q, rt = tt / KT;
+        const float av = sm.g[(rt * 32 + (lane & 31)) * kF32Stride + 2 * (os0 + u) + (lane >> 5)];
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[u][q], acc[q], 0, 0, 0);
+      }
   }
   __syncthreads();  // every wave has read g
 #pragma unroll
