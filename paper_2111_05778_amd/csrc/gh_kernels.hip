@@ -236,11 +236,27 @@ __global__ __launch_bounds__(kBlock) void k_corners(Grid g, Workspace ws, gh_cou
   int a = 0, b = 0;
   uint64_t ncorner = 0, ncand = 0, own = 0;
   size_t own_col = 0;
+  // The first kCache corner words are kept for the write pass (most columns
+  // have fewer); the rest are recomputed there.
+  constexpr int kCache = 4;
+  int cw_w[kCache];
+  uint32_t cw_v[kCache];
+  int nw = 0;
   if (L < nl) {
     a = (int)(L / n1);
     b = (int)(L % n1);
     A = lat_adjacent(n, a, b, ws.colmask);
-    for_corner_words(A, [&](int w) { ncorner += __popc(corner_word(A, ws.colbits, ncol, w)); });
+    for_corner_words(A, [&](int w) {
+      const uint32_t cw = corner_word(A, ws.colbits, ncol, w);
+#pragma unroll
+      for (int i = 0; i < kCache; ++i)
+        if (i == nw) {
+          cw_w[i] = w;
+          cw_v[i] = cw;
+        }
+      ++nw;
+      ncorner += __popc(cw);
+    });
     if (a < n && b < n) {  // cell column (a, b) is slot 3 of the adjacency
       own = A.mask[3];
       own_col = A.col[3];
@@ -254,8 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_corners(Grid g, Workspace ws, gh_cou
     uint32_t hi = 0;
     if (c0 + ncorner <= (uint64_t)ws.cap) {
       int64_t o = (int64_t)c0;
-      for_corner_words(A, [&](int w) {
-        const uint32_t cw = corner_word(A, ws.colbits, ncol, w);
+      auto put = [&](int w, uint32_t cw) {
         if (!cw) return;
         if (w < 64) lm |= 1ull << w; else hi = 1u;
         ws.lbits[(size_t)w * nl + L] = cw;
@@ -265,7 +280,14 @@ __global__ __launch_bounds__(kBlock) void k_corners(Grid g, Workspace ws, gh_cou
           ws.cl[o] = (int32_t)L;
           ++o;
         }
-      });
+      };
+      if (nw <= kCache) {
+#pragma unroll
+        for (int i = 0; i < kCache; ++i)
+          if (i < nw) put(cw_w[i], cw_v[i]);
+      } else {
+        for_corner_words(A, [&](int w) { put(w, corner_word(A, ws.colbits, ncol, w)); });
+      }
       int64_t oc = (int64_t)k0;
       for (uint64_t r = own; r; r &= r - 1) {
         const int w = __builtin_ctzll(r);
@@ -304,18 +326,25 @@ __global__ __launch_bounds__(kBlock) void k_eval_corners(Eval ev, Grid g, Worksp
 // One thread per corner (a, b, k): the crossing edges it owns are the x edge
 // to (a+1, b, k), the y edge to (a, b+1, k) and the z edge to (a, b, k+1),
 // when the far end is a corner too and the signs differ.
+// Crossing edges of corner ci towards +x, +y, +z (bits 0..2); fe[axis] gets
+// the value at the far end of each crossing edge, so the vertex pass needs
+// no second round of loads.
 __device__ __forceinline__ unsigned cross_mask(const Workspace& ws, const Grid& g, size_t nl, int64_t ci, int64_t m,
-                                               int64_t& ix, int64_t& iy) {
+                                               float (&fe)[3]) {
   const int n = g.n, n1 = n + 1;
   const int L = ws.cl[ci], k = ws.ck[ci];
   const int a = L / n1, b = L - a * n1;
   const bool neg = ws.cf[ci] < 0.f;
   unsigned msk = 0;
-  ix = a < n ? corner_index(ws, nl, (size_t)L + n1, k) : -1;
-  iy = b < n ? corner_index(ws, nl, (size_t)L + 1, k) : -1;
-  if (ix >= 0 && ((ws.cf[ix] < 0.f) != neg)) msk |= 1u;
-  if (iy >= 0 && ((ws.cf[iy] < 0.f) != neg)) msk |= 2u;
-  if (ci + 1 < m && ws.cl[ci + 1] == L && ws.ck[ci + 1] == k + 1 && ((ws.cf[ci + 1] < 0.f) != neg)) msk |= 4u;
+  const int64_t ix = a < n ? corner_index(ws, nl, (size_t)L + n1, k) : -1;
+  const int64_t iy = b < n ? corner_index(ws, nl, (size_t)L + 1, k) : -1;
+  fe[0] = ix >= 0 ? ws.cf[ix] : 0.f;
+  fe[1] = iy >= 0 ? ws.cf[iy] : 0.f;
+  const bool zn = ci + 1 < m && ws.cl[ci + 1] == L && ws.ck[ci + 1] == k + 1;
+  fe[2] = zn ? ws.cf[ci + 1] : 0.f;
+  if (ix >= 0 && ((fe[0] < 0.f) != neg)) msk |= 1u;
+  if (iy >= 0 && ((fe[1] < 0.f) != neg)) msk |= 2u;
+  if (zn && ((fe[2] < 0.f) != neg)) msk |= 4u;
   return msk;
 }
 
@@ -338,13 +367,12 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
     __syncthreads();
     const int64_t c0 = (int64_t)tile * kTileItems + (int64_t)threadIdx.x * kItems;
     unsigned msk[kItems];
-    int64_t ix[kItems], iy[kItems];
+    float fe[kItems][3];
     unsigned cnt = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       msk[r] = 0;
-      ix[r] = iy[r] = -1;
-      if (c0 + r < m) msk[r] = cross_mask(ws, g, nl, c0 + r, m, ix[r], iy[r]);
+      if (c0 + r < m) msk[r] = cross_mask(ws, g, nl, c0 + r, m, fe[r]);
       cnt += __popc(msk[r]);
     }
     const ScanOut so = block_scan_lookback(cnt, scan_verts(ws), tile, &ctr->flags);
@@ -364,8 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
 #pragma unroll
         for (int axis = 0; axis < 3; ++axis) {
           if (!((msk[r] >> axis) & 1)) continue;
-          const int64_t far = axis == 0 ? ix[r] : (axis == 1 ? iy[r] : ci + 1);
-          const float fb = ws.cf[far];
+          const float fb = fe[r][axis];
           const float t = fa / (fa - fb);
           verts[3 * vv + 0] = axis == 0 ? xa + t * g.h : xa;
           verts[3 * vv + 1] = axis == 1 ? ya + t * g.h : ya;
@@ -603,6 +630,9 @@ static int resident_grid(K kernel, int64_t tiles) {
   const int cus = cu_count();
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  // One block per tile whenever every tile fits at once; otherwise the
+  // tuned number of resident blocks per CU walks the tiles.
+  if (tiles <= (int64_t)cus * per_cu) return (int)(tiles < 1 ? 1 : tiles);
   const int want = current_tuning().scan_blocks_per_cu;
   const int64_t cap = (int64_t)cus * (per_cu < want ? per_cu : want);
   const int64_t gsz = tiles < cap ? tiles : cap;
