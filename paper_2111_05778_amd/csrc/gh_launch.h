@@ -19,6 +19,30 @@ Tuning current_tuning();
 // Compute units of the current device (cached per device).
 int cu_count();
 
+// Grid of a grid-strided kernel over `work` items, one thread each.
+inline int persistent_blocks(int64_t work) {
+  const int64_t want = (work + kBlock - 1) / kBlock;
+  return (int)(want < 1 ? 1 : (want > 2048 ? 2048 : want));
+}
+
+// Look-back kernels run block-strided over their tiles with a grid no larger
+// than the number of blocks the device holds at once: every tile a block
+// waits on then belongs to a resident block that only waits on earlier
+// tiles, so the scan always makes progress (no ticket counter needed).
+// One block per tile whenever every tile fits at once; otherwise the tuned
+// number of resident blocks per CU walks the tiles.
+template <class K>
+inline int resident_grid(K kernel, int64_t tiles) {
+  const int cus = cu_count();
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (tiles <= (int64_t)cus * per_cu) return (int)(tiles < 1 ? 1 : tiles);
+  const int want = current_tuning().scan_blocks_per_cu;
+  const int64_t cap = (int64_t)cus * (per_cu < want ? per_cu : want);
+  const int64_t gsz = tiles < cap ? tiles : cap;
+  return (int)(gsz < 1 ? 1 : gsz);
+}
+
 
 // What the kernels need to evaluate a bound; lives inside gh_sdb_desc.
 struct DevSdb {
