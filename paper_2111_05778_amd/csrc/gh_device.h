@@ -159,6 +159,7 @@ constexpr uint64_t kScanValMask = (1ull << 62) - 1;
 
 struct ScanOut {
   uint64_t excl;   // exclusive prefix of this thread over the whole grid
+  uint64_t base;   // exclusive prefix of this tile (its first output)
   uint64_t total;  // inclusive prefix at the end of this tile
 };
 
@@ -256,6 +257,7 @@ __device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* fla
   __syncthreads();
   ScanOut o;
   o.excl = s_prev + wave_off + incl - v;
+  o.base = s_prev;
   o.total = s_prev + agg;
   return o;
 }

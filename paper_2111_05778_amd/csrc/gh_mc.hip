@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_candidates(Grid g, Workspace ws, int
 // (a, b); a missing or empty column has mask 0.  Fixed-size and unrolled so
 // that everything stays in registers.
 struct LatAdj {
-  size_t col[4];
+  uint32_t col[4];  // n * n < 2^32 for every supported n
   uint64_t mask[4];
   uint64_t uni;
 };
@@ -67,7 +67,7 @@ __device__ __forceinline__ LatAdj lat_adjacent(int n, int a, int b, const uint64
   for (int q = 0; q < 4; ++q) {
     const int i = a - 1 + (q >> 1), j = b - 1 + (q & 1);
     const bool ok = i >= 0 && i < n && j >= 0 && j < n;
-    const size_t c = ok ? (size_t)i * n + j : 0;
+    const uint32_t c = ok ? (uint32_t)(i * n + j) : 0u;
     const uint64_t m = ok ? colmask[c] : 0ull;
     A.col[q] = c;
     A.mask[q] = m;
@@ -76,107 +76,174 @@ __device__ __forceinline__ LatAdj lat_adjacent(int n, int a, int b, const uint64
   return A;
 }
 
-__device__ __forceinline__ uint32_t adj_cell_word(const LatAdj& A, const uint32_t* __restrict__ colbits,
-                                                  size_t ncol, int w) {
+// OR over the wave, returned in scalar registers: loops over its bits are
+// uniform, so every lane issues the load of word w in the same instruction
+// (adjacent lanes are adjacent columns: one coalesced access per word).
+__device__ __forceinline__ uint64_t wave_uniform_or(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Candidate word w of the four cell columns around a lattice column, OR-ed,
+// and slot 3's word (the cell column (a, b) itself) on its own.
+__device__ __forceinline__ uint32_t adj_cell_word_own(const LatAdj& A, const uint32_t* __restrict__ colbits,
+                                                      size_t ncol, int w, uint32_t& own) {
   uint32_t v = 0;
+  own = 0;
   if (w < 0 || w >= 64) return 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
-    if ((A.mask[q] >> w) & 1) v |= colbits[(size_t)w * ncol + A.col[q]];
+    if ((A.mask[q] >> w) & 1) {
+      const uint32_t x = colbits[(size_t)w * ncol + A.col[q]];
+      v |= x;
+      if (q == 3) own = x;
+    }
   return v;
 }
 
-// Lattice points k of column (a, b) that are corners of a candidate cell:
-// cell k of an adjacent column has corners k and k + 1.
-__device__ __forceinline__ uint32_t corner_word(const LatAdj& A, const uint32_t* __restrict__ colbits, size_t ncol,
-                                                int w) {
-  const uint32_t cur = adj_cell_word(A, colbits, ncol, w);
-  const uint32_t prev = adj_cell_word(A, colbits, ncol, w - 1);
-  return cur | (cur << 1) | (prev >> 31);
-}
+// Walks the corner words of the wave's columns in ascending order and calls
+// fn(w, corner word, own cell word) for each; a lane without word w sees 0.
+// Word w of a lattice column holds corners of cells w (bits k, k + 1) and
+// w - 1 (its top corner at bit 0).  Words go in groups of kWalk whose loads
+// are all issued before any is used (one memory round trip per group).  A
+// word the walk skips is 0 in every lane of the wave, so the carry from the
+// previous word needs no load.
+constexpr int kWalk = 4;
 
 template <class F>
-__device__ __forceinline__ void for_corner_words(const LatAdj& A, F&& fn) {
-  const uint64_t cw = A.uni | (A.uni << 1);
-  for (uint64_t r = cw; r; r &= r - 1) fn(__builtin_ctzll(r));
-  if ((A.uni >> 63) & 1) fn(64);
+__device__ __forceinline__ void walk_corner_words(const LatAdj& A, const uint32_t* __restrict__ colbits, size_t ncol,
+                                                  uint64_t wave_words, bool wave_hi, F&& fn) {
+  int pw = -2;
+  uint32_t pcur = 0;
+  for (uint64_t r = wave_words; r;) {
+    int wg[kWalk];
+    uint32_t cur[kWalk], own[kWalk];
+#pragma unroll
+    for (int g = 0; g < kWalk; ++g) {
+      wg[g] = r ? __builtin_ctzll(r) : -1;
+      r &= r - 1;
+      own[g] = 0;
+      cur[g] = wg[g] >= 0 ? adj_cell_word_own(A, colbits, ncol, wg[g], own[g]) : 0u;
+    }
+#pragma unroll
+    for (int g = 0; g < kWalk; ++g) {
+      if (wg[g] < 0) break;
+      const int w = wg[g];
+      const uint32_t prv = pw == w - 1 ? pcur : 0u;
+      pw = w;
+      pcur = cur[g];
+      fn(w, cur[g] | (cur[g] << 1) | (prv >> 31), own[g]);
+    }
+  }
+  if (wave_hi) fn(64, pw == 63 ? pcur >> 31 : 0u, 0u);  // word 64: top corners of cell word 63 (n = 2048)
 }
+
+// Outputs a tile stages in LDS before writing them out with coalesced stores
+// (a tile's outputs are one contiguous range of each list); a tile with more
+// writes its entries directly.
+constexpr int kStageCorners = 2048;
+constexpr int kStageCands = 1024;
 
 // One thread per lattice column (a, b): its corner words, their starting
 // list indices, its corners, and, when (a, b) is also a cell column, its
 // candidate cells.  One packed scan: (candidates << 31) | corners.
-__global__ __launch_bounds__(kBlock) void k_corners(Grid g, Workspace ws, gh_counters* __restrict__ ctr) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_corners(Grid g, Workspace ws,
+                                                                                        gh_counters* __restrict__ ctr) {
+  __shared__ int32_t s_ck[kStageCorners];
+  __shared__ int32_t s_cl[kStageCorners];
+  __shared__ int64_t s_cand[kStageCands];
   const int n = g.n, n1 = n + 1;
   const size_t ncol = (size_t)n * n, nl = (size_t)n1 * n1;
   for (int tile = blockIdx.x; tile < (int)ws.tiles_lat; tile += gridDim.x) {
   __syncthreads();
   const size_t L = (size_t)tile * kBlock + threadIdx.x;
   LatAdj A{{0, 0, 0, 0}, {0, 0, 0, 0}, 0};
-  int a = 0, b = 0;
-  uint64_t ncorner = 0, ncand = 0, own = 0;
-  size_t own_col = 0;
-  // The first kCache corner words are kept for the write pass (most columns
-  // have fewer); the rest are recomputed there.
-  constexpr int kCache = 4;
-  int cw_w[kCache];
-  uint32_t cw_v[kCache];
-  int nw = 0;
-  if (L < nl) {
-    a = (int)(L / n1);
-    b = (int)(L % n1);
-    A = lat_adjacent(n, a, b, ws.colmask);
-    for_corner_words(A, [&](int w) {
-      const uint32_t cw = corner_word(A, ws.colbits, ncol, w);
-#pragma unroll
-      for (int i = 0; i < kCache; ++i)
-        if (i == nw) {
-          cw_w[i] = w;
-          cw_v[i] = cw;
-        }
-      ++nw;
-      ncorner += __popc(cw);
-    });
-    if (a < n && b < n) {  // cell column (a, b) is slot 3 of the adjacency
-      own = A.mask[3];
-      own_col = A.col[3];
-      for (uint64_t r = own; r; r &= r - 1) ncand += __popc(ws.colbits[(size_t)__builtin_ctzll(r) * ncol + own_col]);
-    }
-  }
+  if (L < nl) A = lat_adjacent(n, (int)(L / n1), (int)(L % n1), ws.colmask);
+  // Slot 3 is the cell column (a, b); its mask is 0 on the lattice's far faces.
+  const uint64_t own = A.mask[3];
+  const size_t own_col = A.col[3];  // valid where own != 0
+  const uint64_t wave_words = wave_uniform_or(A.uni | (A.uni << 1));
+  const bool wave_hi = wave_uniform_or(A.uni >> 63) != 0;
+  uint64_t ncorner = 0, ncand = 0;
+  // Corner words go to lbits as they are found (they do not depend on the
+  // scan); the write pass reads them back.
+  uint64_t lm = 0;
+  uint32_t hi = 0;
+  walk_corner_words(A, ws.colbits, ncol, wave_words, wave_hi, [&](int w, uint32_t cw, uint32_t ow) {
+    ncand += __popc(ow);
+    if (!cw) return;
+    if (w < 64) lm |= 1ull << w; else hi = 1u;
+    ws.lbits[(size_t)w * nl + L] = cw;
+    ncorner += __popc(cw);
+  });
   const ScanOut so = block_scan_lookback((ncand << 31) | ncorner, scan_corners(ws), tile, &ctr->flags);
   const uint64_t c0 = so.excl & 0x7fffffffull, k0 = so.excl >> 31;
-  if (L < nl) {
-    uint64_t lm = 0;
-    uint32_t hi = 0;
-    if (c0 + ncorner <= (uint64_t)ws.cap) {
-      int64_t o = (int64_t)c0;
-      auto put = [&](int w, uint32_t cw) {
-        if (!cw) return;
-        if (w < 64) lm |= 1ull << w; else hi = 1u;
-        ws.lbits[(size_t)w * nl + L] = cw;
-        ws.lwst[(size_t)w * nl + L] = (int32_t)o;
-        for (uint32_t bb = cw; bb; bb &= bb - 1) {
-          ws.ck[o] = 32 * w + __builtin_ctz(bb);
-          ws.cl[o] = (int32_t)L;
-          ++o;
-        }
-      };
-      if (nw <= kCache) {
-#pragma unroll
-        for (int i = 0; i < kCache; ++i)
-          if (i < nw) put(cw_w[i], cw_v[i]);
+  const uint64_t cbase = so.base & 0x7fffffffull, kbase = so.base >> 31;
+  const uint64_t tile_c = (so.total & 0x7fffffffull) - cbase, tile_k = (so.total >> 31) - kbase;
+  const bool stage_c = tile_c <= (uint64_t)kStageCorners, stage_k = tile_k <= (uint64_t)kStageCands;
+  const bool fits = L < nl && c0 + ncorner <= (uint64_t)ws.cap;
+  int64_t o = (int64_t)c0, oc = (int64_t)k0;
+  auto put = [&](int w, uint32_t cw, uint32_t ow) {
+    if (cw) ws.lwst[(size_t)w * nl + L] = (int32_t)o;
+    for (uint32_t bb = cw; bb; bb &= bb - 1) {
+      const int32_t kk = 32 * w + __builtin_ctz(bb);
+      if (stage_c) {
+        s_ck[o - (int64_t)cbase] = kk;
+        s_cl[o - (int64_t)cbase] = (int32_t)L;
       } else {
-        for_corner_words(A, [&](int w) { put(w, corner_word(A, ws.colbits, ncol, w)); });
+        ws.ck[o] = kk;
+        ws.cl[o] = (int32_t)L;
       }
-      int64_t oc = (int64_t)k0;
-      for (uint64_t r = own; r; r &= r - 1) {
-        const int w = __builtin_ctzll(r);
-        for (uint32_t bb = ws.colbits[(size_t)w * ncol + own_col]; bb; bb &= bb - 1)
-          ws.cand[oc++] = (int64_t)own_col * n + 32 * w + __builtin_ctz(bb);
+      ++o;
+    }
+    for (uint32_t bb = ow; bb; bb &= bb - 1) {
+      const int64_t id = (int64_t)own_col * n + 32 * w + __builtin_ctz(bb);
+      if (stage_k) s_cand[oc - (int64_t)kbase] = id;
+      else ws.cand[oc] = id;
+      ++oc;
+    }
+  };
+  // Write pass over the wave's corner words, loads grouped as in the walk;
+  // every own cell word w has corner word w.
+  const uint64_t wave_lm = wave_uniform_or(fits ? lm : 0ull);
+  for (uint64_t r = wave_lm; r;) {
+    int wg[kWalk];
+    uint32_t cw[kWalk], ow[kWalk];
+#pragma unroll
+    for (int g = 0; g < kWalk; ++g) {
+      const int w = r ? __builtin_ctzll(r) : -1;
+      r &= r - 1;
+      wg[g] = w;
+      const bool mine = fits && w >= 0 && ((lm >> w) & 1);
+      const bool owns = fits && w >= 0 && ((own >> w) & 1);
+      cw[g] = mine ? ws.lbits[(size_t)w * nl + L] : 0u;
+      ow[g] = owns ? ws.colbits[(size_t)w * ncol + own_col] : 0u;
+    }
+#pragma unroll
+    for (int g = 0; g < kWalk; ++g)
+      if (wg[g] >= 0) put(wg[g], cw[g], ow[g]);
+  }
+  if (fits && hi) put(64, ws.lbits[(size_t)64 * nl + L], 0u);
+  if (L < nl) {
+    ws.lmask[L] = fits ? lm : 0ull;
+    ws.lmhi[L] = fits ? hi : 0u;
+  }
+  __syncthreads();
+  if (stage_c)
+    for (int64_t i = threadIdx.x; i < (int64_t)tile_c; i += kBlock) {
+      const int64_t gi = (int64_t)cbase + i;
+      if (gi < ws.cap) {
+        ws.ck[gi] = s_ck[i];
+        ws.cl[gi] = s_cl[i];
       }
     }
-    ws.lmask[L] = lm;
-    ws.lmhi[L] = hi;
-  }
+  if (stage_k)
+    for (int64_t i = threadIdx.x; i < (int64_t)tile_k; i += kBlock) {
+      const int64_t gi = (int64_t)kbase + i;
+      if (gi < ws.cap) ws.cand[gi] = s_cand[i];
+    }
   if (threadIdx.x == 0 && tile == (int)ws.tiles_lat - 1) {
     const int64_t tc = (int64_t)(so.total & 0x7fffffffull), tk = (int64_t)(so.total >> 31);
     ws.nlist[0] = tc;
@@ -205,66 +272,111 @@ __global__ __launch_bounds__(kBlock) void k_eval_corners(Eval ev, Grid g, Worksp
 // One thread per corner (a, b, k): the crossing edges it owns are the x edge
 // to (a+1, b, k), the y edge to (a, b+1, k) and the z edge to (a, b, k+1),
 // when the far end is a corner too and the signs differ.
-// Crossing edges of corner ci towards +x, +y, +z (bits 0..2); fe[axis] gets
-// the value at the far end of each crossing edge, so the vertex pass needs
-// no second round of loads.
-__device__ __forceinline__ unsigned cross_mask(const Workspace& ws, const Grid& g, size_t nl, int64_t ci, int64_t m,
-                                               float (&fe)[3]) {
-  const int n = g.n, n1 = n + 1;
-  const int L = ws.cl[ci], k = ws.ck[ci];
-  const int a = L / n1, b = L - a * n1;
-  const bool neg = ws.cf[ci] < 0.f;
-  unsigned msk = 0;
-  const int64_t ix = a < n ? corner_index(ws, nl, (size_t)L + n1, k) : -1;
-  const int64_t iy = b < n ? corner_index(ws, nl, (size_t)L + 1, k) : -1;
-  fe[0] = ix >= 0 ? ws.cf[ix] : 0.f;
-  fe[1] = iy >= 0 ? ws.cf[iy] : 0.f;
-  const bool zn = ci + 1 < m && ws.cl[ci + 1] == L && ws.ck[ci + 1] == k + 1;
-  fe[2] = zn ? ws.cf[ci + 1] : 0.f;
-  if (ix >= 0 && ((fe[0] < 0.f) != neg)) msk |= 1u;
-  if (iy >= 0 && ((fe[1] < 0.f) != neg)) msk |= 2u;
-  if (zn && ((fe[2] < 0.f) != neg)) msk |= 4u;
-  return msk;
-}
 
 // Each thread takes kItems consecutive list entries (a launch shape: 1, 2, 4
 // or 8), so a tile covers kBlock * kItems entries and the entries keep their
-// order in the output.
+// order in the output.  The thread's run of a 4-byte list is read with the
+// widest aligned vector loads (the lists are 256-byte aligned and c0 is a
+// multiple of kItems); entries past the list end are read but never used.
+template <int kItems, class T>
+__device__ __forceinline__ void load_run(const T* __restrict__ p, int64_t c0, int64_t cap, T (&out)[kItems]) {
+  static_assert(sizeof(T) == 4, "4-byte lists");
+  if (c0 + kItems <= cap) {
+    if constexpr (kItems >= 4) {
+#pragma unroll
+      for (int r = 0; r < kItems; r += 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(p + c0 + r);
+        out[r] = __builtin_bit_cast(T, v.x);
+        out[r + 1] = __builtin_bit_cast(T, v.y);
+        out[r + 2] = __builtin_bit_cast(T, v.z);
+        out[r + 3] = __builtin_bit_cast(T, v.w);
+      }
+    } else if constexpr (kItems == 2) {
+      const uint2 v = *reinterpret_cast<const uint2*>(p + c0);
+      out[0] = __builtin_bit_cast(T, v.x);
+      out[1] = __builtin_bit_cast(T, v.y);
+    } else {
+      out[0] = p[c0];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) out[r] = c0 + r < cap ? p[c0 + r] : T{};
+  }
+}
 
 template <int kItems>
 __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* __restrict__ verts,
                                                   int64_t* __restrict__ vert_edge, float* __restrict__ vert_t,
                                                   int64_t vert_cap, gh_counters* __restrict__ ctr) {
   constexpr int kTileItems = kBlock * kItems;
+  // A tile stages up to one vertex per corner (0.4 on average).
+  constexpr int kStageV = kTileItems;
+  __shared__ float s_v[3 * kStageV];
+  __shared__ int64_t s_e[kStageV];
+  __shared__ float s_t[kStageV];
   const int64_t m = ws.nlist[0];
   if (m > ws.cap) return;  // uniform: the corners overflowed, nothing to do
-  const int n1 = g.n + 1;
+  const int n = g.n, n1 = n + 1;
   const size_t nl = (size_t)n1 * n1;
   const int ntiles = (int)((m + kTileItems - 1) / kTileItems);
   if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) ctr->n_vert = 0;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     __syncthreads();
     const int64_t c0 = (int64_t)tile * kTileItems + (int64_t)threadIdx.x * kItems;
+    int32_t Ls[kItems], ks[kItems];
+    float fs[kItems];
+    load_run<kItems>(ws.cl, c0, ws.cap, Ls);
+    load_run<kItems>(ws.ck, c0, ws.cap, ks);
+    load_run<kItems>(ws.cf, c0, ws.cap, fs);
+    // The entry after the run is the next lane's first (one wave covers
+    // consecutive runs); the last lane reads it.
+    int32_t Lz = __shfl_down(Ls[0], 1, 64), kz = __shfl_down(ks[0], 1, 64);
+    float fz = __shfl_down(fs[0], 1, 64);
+    const int64_t cz = c0 + kItems;
+    if (lane_id() == 63 && cz < m) {
+      Lz = ws.cl[cz];
+      kz = ws.ck[cz];
+      fz = ws.cf[cz];
+    }
     unsigned msk[kItems];
     float fe[kItems][3];
     unsigned cnt = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       msk[r] = 0;
-      if (c0 + r < m) msk[r] = cross_mask(ws, g, nl, c0 + r, m, fe[r]);
+      fe[r][0] = fe[r][1] = fe[r][2] = 0.f;
+      const int64_t ci = c0 + r;
+      if (ci < m) {
+        const int L = Ls[r], k = ks[r];
+        const int a = L / n1, b = L - a * n1;
+        const bool neg = fs[r] < 0.f;
+        const int64_t ix = a < n ? corner_index(ws, nl, (size_t)L + n1, k) : -1;
+        const int64_t iy = b < n ? corner_index(ws, nl, (size_t)L + 1, k) : -1;
+        if (ix >= 0) fe[r][0] = ws.cf[ix];
+        if (iy >= 0) fe[r][1] = ws.cf[iy];
+        const int Ln = r + 1 < kItems ? Ls[r + 1 < kItems ? r + 1 : 0] : Lz;
+        const int kn = r + 1 < kItems ? ks[r + 1 < kItems ? r + 1 : 0] : kz;
+        const bool zn = ci + 1 < m && Ln == L && kn == k + 1;
+        if (zn) fe[r][2] = r + 1 < kItems ? fs[r + 1 < kItems ? r + 1 : 0] : fz;
+        if (ix >= 0 && ((fe[r][0] < 0.f) != neg)) msk[r] |= 1u;
+        if (iy >= 0 && ((fe[r][1] < 0.f) != neg)) msk[r] |= 2u;
+        if (zn && ((fe[r][2] < 0.f) != neg)) msk[r] |= 4u;
+      }
       cnt += __popc(msk[r]);
     }
     const ScanOut so = block_scan_lookback(cnt, scan_verts(ws), tile, &ctr->flags);
+    const int64_t vbase = (int64_t)so.base, tile_v = (int64_t)(so.total - so.base);
+    const bool stage = tile_v <= kStageV;
     int64_t v = (int64_t)so.excl;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const int64_t ci = c0 + r;
       if (ci >= m) break;
       ws.cinfo[ci] = (v << 3) | (int64_t)msk[r];
-      if (msk[r] && v + __popc(msk[r]) <= vert_cap) {
-        const int L = ws.cl[ci], k = ws.ck[ci];
+      if (msk[r] && (stage || v + __popc(msk[r]) <= vert_cap)) {
+        const int L = Ls[r], k = ks[r];
         const int a = L / n1, b = L - a * n1;
-        const float fa = ws.cf[ci];
+        const float fa = fs[r];
         const float xa = lattice(g, a), ya = lattice(g, b), za = lattice(g, k);
         const int64_t pid = ((int64_t)L * n1 + k) * 3;
         int64_t vv = v;
@@ -273,15 +385,36 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
           if (!((msk[r] >> axis) & 1)) continue;
           const float fb = fe[r][axis];
           const float t = fa / (fa - fb);
-          verts[3 * vv + 0] = axis == 0 ? xa + t * g.h : xa;
-          verts[3 * vv + 1] = axis == 1 ? ya + t * g.h : ya;
-          verts[3 * vv + 2] = axis == 2 ? za + t * g.h : za;
-          if (vert_edge) vert_edge[vv] = pid + axis;
-          if (vert_t) vert_t[vv] = t;
+          const float px = axis == 0 ? xa + t * g.h : xa;
+          const float py = axis == 1 ? ya + t * g.h : ya;
+          const float pz = axis == 2 ? za + t * g.h : za;
+          if (stage) {
+            const int64_t lv = vv - vbase;
+            s_v[3 * lv + 0] = px;
+            s_v[3 * lv + 1] = py;
+            s_v[3 * lv + 2] = pz;
+            s_e[lv] = pid + axis;
+            s_t[lv] = t;
+          } else {
+            verts[3 * vv + 0] = px;
+            verts[3 * vv + 1] = py;
+            verts[3 * vv + 2] = pz;
+            if (vert_edge) vert_edge[vv] = pid + axis;
+            if (vert_t) vert_t[vv] = t;
+          }
           ++vv;
         }
       }
       v += __popc(msk[r]);
+    }
+    __syncthreads();
+    if (stage) {
+      const int64_t nv = vbase + tile_v <= vert_cap ? tile_v : (vbase < vert_cap ? vert_cap - vbase : 0);
+      for (int64_t i = threadIdx.x; i < 3 * nv; i += kBlock) verts[3 * vbase + i] = s_v[i];
+      if (vert_edge)
+        for (int64_t i = threadIdx.x; i < nv; i += kBlock) vert_edge[vbase + i] = s_e[i];
+      if (vert_t)
+        for (int64_t i = threadIdx.x; i < nv; i += kBlock) vert_t[vbase + i] = s_t[i];
     }
     if (threadIdx.x == 0 && tile == ntiles - 1) {
       ctr->n_vert = (int64_t)so.total;
@@ -295,6 +428,14 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
 // the four lattice columns (i+dx, j+dy) (the corner at k+1 follows the one
 // at k in the list), the case byte, and the table's triangles; each triangle
 // vertex is the welded vertex of the cell edge, found at its lower corner.
+// Lower corner of each of the 12 cell edges, 3 bits per edge.
+constexpr uint64_t edge_lower_pack() {
+  uint64_t v = 0;
+  for (int e = 0; e < 12; ++e) v |= (uint64_t)mc_edge_lower(e) << (3 * e);
+  return v;
+}
+constexpr uint64_t kEdgeLower = edge_lower_pack();
+
 struct CellCorners {
   int64_t p[4];  // list index of corner (i+dx, j+dy, k), slot dx + 2 dy
 };
@@ -326,7 +467,13 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
                                                  int64_t cell_cap, int64_t vert_cap,
                                                  gh_counters* __restrict__ ctr) {
   constexpr int kTileItems = kBlock * kItems;
+  // A tile stages up to 1.5 triangles per candidate (about 1.5 on average
+  // for closed surfaces; a larger tile writes directly) and every cell.
+  constexpr int kStageT = 3 * kTileItems / 2;
   __shared__ McCase s_mc[256];
+  __shared__ int32_t s_tri[3 * kStageT];
+  __shared__ int64_t s_cell[kTileItems];
+  __shared__ uint8_t s_case[kTileItems];
   s_mc[threadIdx.x] = g_mc.c[threadIdx.x];
   __syncthreads();
   if (ws.nlist[0] > ws.cap) return;
@@ -347,48 +494,89 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
     unsigned cs[kItems], nt[kItems];
     int64_t cell[kItems];
     uint64_t pack = 0;
+    bool vec = false;
+    if constexpr (kItems >= 2) {
+      // 16-byte loads of the thread's run of cell ids (as in load_run)
+      vec = q0 + kItems <= ws.cap;
+      if (vec)
+#pragma unroll
+        for (int r = 0; r < kItems; r += 2) {
+          const uint4 v = *reinterpret_cast<const uint4*>(ws.cand + q0 + r);
+          cell[r] = (int64_t)(((uint64_t)v.y << 32) | v.x);
+          cell[r + 1] = (int64_t)(((uint64_t)v.w << 32) | v.z);
+        }
+    }
+    if (!vec)
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) cell[r] = q0 + r < m ? ws.cand[q0 + r] : 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       cs[r] = nt[r] = 0;
-      cell[r] = 0;
       C[r] = CellCorners{{0, 0, 0, 0}};
       if (q0 + r < m) {
         int k;
-        cell[r] = ws.cand[q0 + r];
         if (cell_corners(ws, n, nl, cell[r], C[r], cs[r], k)) nt[r] = s_mc[cs[r]].ntri;
         else broken = true;
+      } else {
+        cell[r] = 0;
       }
       // (cells << 31) | triangles: both stay below 2^31 for any mesh the outputs can index
       pack += ((uint64_t)(nt[r] ? 1 : 0) << 31) | nt[r];
     }
     const ScanOut so = block_scan_lookback(pack, scan_tris(ws), tile, &ctr->flags);
     int64_t t0 = (int64_t)(so.excl & 0x7fffffffull), c = (int64_t)(so.excl >> 31);
+    const int64_t tbase = (int64_t)(so.base & 0x7fffffffull), cbase = (int64_t)(so.base >> 31);
+    const int64_t tile_t = (int64_t)(so.total & 0x7fffffffull) - tbase;
+    const int64_t tile_c = (int64_t)(so.total >> 31) - cbase;
+    const bool stage = tile_t <= kStageT;  // the cells always fit: at most one per candidate
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       if (!nt[r]) continue;
       if (verts_ok) {
-        if (c < cell_cap) {
-          if (cells) cells[c] = cell[r];
-          if (cases) cases[c] = (uint8_t)cs[r];
-        }
-        if (t0 + (int64_t)nt[r] <= tri_cap) {
+        s_cell[c - cbase] = cell[r];
+        s_case[c - cbase] = (uint8_t)cs[r];
+        if (stage || t0 + (int64_t)nt[r] <= tri_cap) {
           const McCase mcc = s_mc[cs[r]];
-          for (unsigned tq = 0; tq < nt[r]; ++tq) {
+          // The vertex records of the lower corners of the crossing edges
+          // (corner 7 is no edge's lower corner), all loaded up front.
+          unsigned need = 0;
+#pragma unroll
+          for (int e = 0; e < 12; ++e)
+            if ((mcc.edges >> e) & 1) need |= 1u << mc_edge_lower(e);
+          int64_t info[7];
+#pragma unroll
+          for (int lc = 0; lc < 7; ++lc) info[lc] = (need >> lc) & 1 ? ws.cinfo[C[r].p[lc & 3] + (lc >> 2)] : 0;
+#pragma unroll
+          for (unsigned tq = 0; tq < 5; ++tq) {
+            if (tq >= nt[r]) break;
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
               const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
-              const int lc = mc_edge_lower(e), axis = e >> 2;
-              const int slot = (lc & 1) + 2 * ((lc >> 1) & 1);
-              const int64_t base =
-                  slot == 0 ? C[r].p[0] : (slot == 1 ? C[r].p[1] : (slot == 2 ? C[r].p[2] : C[r].p[3]));
-              const int64_t info = ws.cinfo[base + (lc >> 2)];
-              tris[3 * (t0 + tq) + v] = (int32_t)((info >> 3) + __popc((unsigned)(info & 7) & ((1u << axis) - 1u)));
+              const int lc = (int)((kEdgeLower >> (3 * e)) & 7), axis = e >> 2;
+              int64_t in = info[0];
+#pragma unroll
+              for (int q = 1; q < 7; ++q) in = lc == q ? info[q] : in;
+              const int32_t vid = (int32_t)((in >> 3) + __popc((unsigned)(in & 7) & ((1u << axis) - 1u)));
+              if (stage) s_tri[3 * (t0 - tbase + tq) + v] = vid;
+              else tris[3 * (t0 + tq) + v] = vid;
             }
           }
         }
       }
       t0 += nt[r];
       ++c;
+    }
+    __syncthreads();
+    if (verts_ok) {
+      if (stage) {
+        const int64_t nt3 = 3 * (tbase + tile_t <= tri_cap ? tile_t : (tbase < tri_cap ? tri_cap - tbase : 0));
+        for (int64_t i = threadIdx.x; i < nt3; i += kBlock) tris[3 * tbase + i] = s_tri[i];
+      }
+      const int64_t nc = cbase + tile_c <= cell_cap ? tile_c : (cbase < cell_cap ? cell_cap - cbase : 0);
+      if (cells)
+        for (int64_t i = threadIdx.x; i < nc; i += kBlock) cells[cbase + i] = s_cell[i];
+      if (cases)
+        for (int64_t i = threadIdx.x; i < nc; i += kBlock) cases[cbase + i] = s_case[i];
     }
     if (threadIdx.x == 0 && tile == ntiles - 1) {
       const int64_t tt = (int64_t)(so.total & 0x7fffffffull), tc = (int64_t)(so.total >> 31);
@@ -400,7 +588,6 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
   if (broken) atomicOr(&ctr->flags, GH_FLAG_INTERNAL);
 }
 
-// Bound at arbitrary points.
 hipError_t launch_candidates(const Grid& g, const Workspace& ws, int64_t* out, int64_t cap, gh_counters* ctr,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_candidates, dim3(resident_grid(k_candidates, ws.tiles_col)), dim3(kBlock), 0, s, g, ws, out,
