@@ -104,17 +104,18 @@ __host__ __device__ inline uint64_t* scan_cands(const Workspace& w) {
 }
 inline size_t scan_words(const Workspace& w) { return (size_t)(w.tiles_lat + 2 * w.tiles_cap + w.tiles_col); }
 
-// List index of corner (L, k), or -1 when (L, k) is not a corner.  The mask,
-// word and start are loaded together (one memory round trip): a word that
-// was not written this run is read but never used.  k <= n, so the word
-// index stays inside the W1 rows.
+// List index of corner (L, k), or -1 when (L, k) is not a corner.  All four
+// loads are unconditional and issued together (one memory round trip); a
+// word that was not written this run is read but never used.  k <= n, so
+// the word index stays inside the W1 rows; L < (n+1)^2.
 __device__ __forceinline__ int64_t corner_index(const Workspace& ws, size_t nl, size_t L, int k) {
   const int w = k >> 5;
   const size_t o = (size_t)w * nl + L;
   const uint64_t lm = ws.lmask[L];
+  const uint32_t lh = ws.lmhi[L];
   const uint32_t word = ws.lbits[o];
   const int32_t start = ws.lwst[o];
-  const bool present = w < 64 ? ((lm >> w) & 1) : (ws.lmhi[L] & 1);
+  const bool present = w < 64 ? ((lm >> (w & 63)) & 1) : (lh & 1);
   const uint32_t bit = 1u << (k & 31);
   const int64_t idx = (int64_t)start + __popc(word & (bit - 1u));
   return present && (word & bit) ? idx : -1;

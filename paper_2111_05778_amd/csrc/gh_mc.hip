@@ -87,34 +87,34 @@ __device__ __forceinline__ uint64_t wave_uniform_or(uint64_t v) {
 }
 
 // Candidate word w of the four cell columns around a lattice column, OR-ed,
-// and slot 3's word (the cell column (a, b) itself) on its own.
+// and slot 3's word (the cell column (a, b) itself) on its own.  The four
+// loads are unconditional (a missing column reads column 0 of the same word
+// and is masked off), so no branch separates a load from its use and a group
+// of words issues all its loads before the first wait.  0 <= w < words.
 __device__ __forceinline__ uint32_t adj_cell_word_own(const LatAdj& A, const uint32_t* __restrict__ colbits,
                                                       size_t ncol, int w, uint32_t& own) {
   uint32_t v = 0;
-  own = 0;
-  if (w < 0 || w >= 64) return 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if ((A.mask[q] >> w) & 1) {
-      const uint32_t x = colbits[(size_t)w * ncol + A.col[q]];
-      v |= x;
-      if (q == 3) own = x;
-    }
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t x = colbits[(size_t)w * ncol + A.col[q]] & (0u - (uint32_t)((A.mask[q] >> w) & 1));
+    v |= x;
+    if (q == 3) own = x;
+  }
   return v;
 }
 
 // Walks the corner words of the wave's columns in ascending order and calls
 // fn(w, corner word, own cell word) for each; a lane without word w sees 0.
 // Word w of a lattice column holds corners of cells w (bits k, k + 1) and
-// w - 1 (its top corner at bit 0).  Words go in groups of kWalk whose loads
-// are all issued before any is used (one memory round trip per group).  A
-// word the walk skips is 0 in every lane of the wave, so the carry from the
-// previous word needs no load.
+// w - 1 (its top corner at bit 0); cell words exist for w < words.  Words go
+// in groups of kWalk whose loads are all issued before any is used (one
+// memory round trip per group).  A word the walk skips is 0 in every lane of
+// the wave, so the carry from the previous word needs no load.
 constexpr int kWalk = 4;
 
 template <class F>
 __device__ __forceinline__ void walk_corner_words(const LatAdj& A, const uint32_t* __restrict__ colbits, size_t ncol,
-                                                  uint64_t wave_words, bool wave_hi, F&& fn) {
+                                                  int words, uint64_t wave_words, bool wave_hi, F&& fn) {
   int pw = -2;
   uint32_t pcur = 0;
   for (uint64_t r = wave_words; r;) {
@@ -122,10 +122,14 @@ __device__ __forceinline__ void walk_corner_words(const LatAdj& A, const uint32_
     uint32_t cur[kWalk], own[kWalk];
 #pragma unroll
     for (int g = 0; g < kWalk; ++g) {
-      wg[g] = r ? __builtin_ctzll(r) : -1;
+      const int w = r ? __builtin_ctzll(r) : -1;
       r &= r - 1;
-      own[g] = 0;
-      cur[g] = wg[g] >= 0 ? adj_cell_word_own(A, colbits, ncol, wg[g], own[g]) : 0u;
+      wg[g] = w;
+      const bool cell = w >= 0 && w < words;  // uniform
+      uint32_t o;
+      const uint32_t c = adj_cell_word_own(A, colbits, ncol, cell ? w : 0, o);
+      cur[g] = cell ? c : 0u;
+      own[g] = cell ? o : 0u;
     }
 #pragma unroll
     for (int g = 0; g < kWalk; ++g) {
@@ -140,6 +144,9 @@ __device__ __forceinline__ void walk_corner_words(const LatAdj& A, const uint32_
   if (wave_hi) fn(64, pw == 63 ? pcur >> 31 : 0u, 0u);  // word 64: top corners of cell word 63 (n = 2048)
 }
 
+// Outputs a tile stages in LDS before writing them out with coalesced stores
+// (a tile's outputs are one contiguous range of each list); a tile with more
+// writes its entries directly.
 // Outputs a tile stages in LDS before writing them out with coalesced stores
 // (a tile's outputs are one contiguous range of each list); a tile with more
 // writes its entries directly.
@@ -171,7 +178,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   // scan); the write pass reads them back.
   uint64_t lm = 0;
   uint32_t hi = 0;
-  walk_corner_words(A, ws.colbits, ncol, wave_words, wave_hi, [&](int w, uint32_t cw, uint32_t ow) {
+  const int words = (n + 31) >> 5, words1 = (n + 32) >> 5;
+  walk_corner_words(A, ws.colbits, ncol, words, wave_words, wave_hi, [&](int w, uint32_t cw, uint32_t ow) {
     ncand += __popc(ow);
     if (!cw) return;
     if (w < 64) lm |= 1ull << w; else hi = 1u;
@@ -208,6 +216,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   // Write pass over the wave's corner words, loads grouped as in the walk;
   // every own cell word w has corner word w.
   const uint64_t wave_lm = wave_uniform_or(fits ? lm : 0ull);
+  const size_t Lq = L < nl ? L : 0;
   for (uint64_t r = wave_lm; r;) {
     int wg[kWalk];
     uint32_t cw[kWalk], ow[kWalk];
@@ -216,20 +225,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
       const int w = r ? __builtin_ctzll(r) : -1;
       r &= r - 1;
       wg[g] = w;
-      const bool mine = fits && w >= 0 && ((lm >> w) & 1);
-      const bool owns = fits && w >= 0 && ((own >> w) & 1);
-      cw[g] = mine ? ws.lbits[(size_t)w * nl + L] : 0u;
-      ow[g] = owns ? ws.colbits[(size_t)w * ncol + own_col] : 0u;
+      // unconditional loads at clamped in-bounds addresses, masked after
+      const int wl = w >= 0 && w < words1 ? w : 0, wc = w >= 0 && w < words ? w : 0;
+      const uint32_t lw = ws.lbits[(size_t)wl * nl + Lq];
+      const uint32_t cwd = ws.colbits[(size_t)wc * ncol + own_col];
+      cw[g] = fits && w >= 0 && ((lm >> w) & 1) ? lw : 0u;
+      ow[g] = fits && w >= 0 && ((own >> w) & 1) ? cwd : 0u;
     }
 #pragma unroll
     for (int g = 0; g < kWalk; ++g)
       if (wg[g] >= 0) put(wg[g], cw[g], ow[g]);
   }
   if (fits && hi) put(64, ws.lbits[(size_t)64 * nl + L], 0u);
-  if (L < nl) {
-    ws.lmask[L] = fits ? lm : 0ull;
-    ws.lmhi[L] = fits ? hi : 0u;
-  }
   __syncthreads();
   if (stage_c)
     for (int64_t i = threadIdx.x; i < (int64_t)tile_c; i += kBlock) {
@@ -244,6 +251,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
       const int64_t gi = (int64_t)kbase + i;
       if (gi < ws.cap) ws.cand[gi] = s_cand[i];
     }
+  if (L < nl) {
+    ws.lmask[L] = fits ? lm : 0ull;
+    ws.lmhi[L] = fits ? hi : 0u;
+  }
   if (threadIdx.x == 0 && tile == (int)ws.tiles_lat - 1) {
     const int64_t tc = (int64_t)(so.total & 0x7fffffffull), tk = (int64_t)(so.total >> 31);
     ws.nlist[0] = tc;
@@ -338,30 +349,42 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
       kz = ws.ck[cz];
       fz = ws.cf[cz];
     }
+    // Straight-line and unconditional (entries past the list end use
+    // lattice column 0 and are masked): the index loads of all items go out
+    // together, then the value loads.
     unsigned msk[kItems];
     float fe[kItems][3];
+    int64_t ix[kItems], iy[kItems];
+    bool xo[kItems], yo[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const bool valid = c0 + r < m;
+      const int L = valid ? Ls[r] : 0, k = valid ? ks[r] : 0;
+      const int a = L / n1, b = L - a * n1;
+      xo[r] = valid && a < n;
+      yo[r] = valid && b < n;
+      ix[r] = corner_index(ws, nl, (size_t)(xo[r] ? L + n1 : L), k);
+      iy[r] = corner_index(ws, nl, (size_t)(yo[r] ? L + 1 : L), k);
+      xo[r] = xo[r] && ix[r] >= 0;
+      yo[r] = yo[r] && iy[r] >= 0;
+    }
     unsigned cnt = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-      msk[r] = 0;
-      fe[r][0] = fe[r][1] = fe[r][2] = 0.f;
       const int64_t ci = c0 + r;
-      if (ci < m) {
-        const int L = Ls[r], k = ks[r];
-        const int a = L / n1, b = L - a * n1;
-        const bool neg = fs[r] < 0.f;
-        const int64_t ix = a < n ? corner_index(ws, nl, (size_t)L + n1, k) : -1;
-        const int64_t iy = b < n ? corner_index(ws, nl, (size_t)L + 1, k) : -1;
-        if (ix >= 0) fe[r][0] = ws.cf[ix];
-        if (iy >= 0) fe[r][1] = ws.cf[iy];
-        const int Ln = r + 1 < kItems ? Ls[r + 1 < kItems ? r + 1 : 0] : Lz;
-        const int kn = r + 1 < kItems ? ks[r + 1 < kItems ? r + 1 : 0] : kz;
-        const bool zn = ci + 1 < m && Ln == L && kn == k + 1;
-        if (zn) fe[r][2] = r + 1 < kItems ? fs[r + 1 < kItems ? r + 1 : 0] : fz;
-        if (ix >= 0 && ((fe[r][0] < 0.f) != neg)) msk[r] |= 1u;
-        if (iy >= 0 && ((fe[r][1] < 0.f) != neg)) msk[r] |= 2u;
-        if (zn && ((fe[r][2] < 0.f) != neg)) msk[r] |= 4u;
-      }
+      const float fx = ws.cf[xo[r] ? ix[r] : 0], fy = ws.cf[yo[r] ? iy[r] : 0];
+      const bool neg = fs[r] < 0.f;
+      const int Ln = r + 1 < kItems ? Ls[r + 1 < kItems ? r + 1 : 0] : Lz;
+      const int kn = r + 1 < kItems ? ks[r + 1 < kItems ? r + 1 : 0] : kz;
+      const float fn = r + 1 < kItems ? fs[r + 1 < kItems ? r + 1 : 0] : fz;
+      const bool zn = ci + 1 < m && Ln == Ls[r] && kn == ks[r] + 1;
+      fe[r][0] = xo[r] ? fx : 0.f;
+      fe[r][1] = yo[r] ? fy : 0.f;
+      fe[r][2] = zn ? fn : 0.f;
+      msk[r] = 0;
+      if (xo[r] && ((fx < 0.f) != neg)) msk[r] |= 1u;
+      if (yo[r] && ((fy < 0.f) != neg)) msk[r] |= 2u;
+      if (zn && ((fn < 0.f) != neg)) msk[r] |= 4u;
       cnt += __popc(msk[r]);
     }
     const ScanOut so = block_scan_lookback(cnt, scan_verts(ws), tile, &ctr->flags);
@@ -441,24 +464,29 @@ struct CellCorners {
 };
 
 __device__ __forceinline__ bool cell_corners(const Workspace& ws, int n, size_t nl, int64_t cell, CellCorners& C,
-                                             unsigned& cs, int& k) {
+                                             unsigned& cs) {
   const int n1 = n + 1;
   const int64_t col = cell / n;
-  k = (int)(cell - col * n);
+  const int k = (int)(cell - col * n);
   const int i = (int)(col / n), j = (int)(col - (int64_t)i * n);
   const size_t L = (size_t)i * n1 + j;
+  // Unconditional loads (a missing corner reads entry 0 and is ignored):
+  // the four index lookups, then the eight values, each one round trip.
   C.p[0] = corner_index(ws, nl, L, k);
   C.p[1] = corner_index(ws, nl, L + n1, k);
   C.p[2] = corner_index(ws, nl, L + 1, k);
   C.p[3] = corner_index(ws, nl, L + n1 + 1, k);
+  bool ok = true;
   cs = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    if (C.p[q] < 0) return false;
-    cs |= (unsigned)(ws.cf[C.p[q]] < 0.f) << q;
-    cs |= (unsigned)(ws.cf[C.p[q] + 1] < 0.f) << (q + 4);
+    ok = ok && C.p[q] >= 0;
+    const int64_t p0 = C.p[q] >= 0 ? C.p[q] : 0;
+    const int64_t p1 = p0 + 1 < ws.cap ? p0 + 1 : p0;
+    cs |= (unsigned)(ws.cf[p0] < 0.f) << q;
+    cs |= (unsigned)(ws.cf[p1] < 0.f) << (q + 4);
   }
-  return true;
+  return ok;
 }
 
 template <int kItems>
@@ -511,15 +539,11 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
       for (int r = 0; r < kItems; ++r) cell[r] = q0 + r < m ? ws.cand[q0 + r] : 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-      cs[r] = nt[r] = 0;
-      C[r] = CellCorners{{0, 0, 0, 0}};
-      if (q0 + r < m) {
-        int k;
-        if (cell_corners(ws, n, nl, cell[r], C[r], cs[r], k)) nt[r] = s_mc[cs[r]].ntri;
-        else broken = true;
-      } else {
-        cell[r] = 0;
-      }
+      const bool valid = q0 + r < m;
+      if (!valid) cell[r] = 0;  // cell 0 keeps every address in bounds; masked below
+      const bool ok = cell_corners(ws, n, nl, cell[r], C[r], cs[r]);
+      nt[r] = valid && ok ? s_mc[cs[r]].ntri : 0u;
+      broken = broken || (valid && !ok);
       // (cells << 31) | triangles: both stay below 2^31 for any mesh the outputs can index
       pack += ((uint64_t)(nt[r] ? 1 : 0) << 31) | nt[r];
     }
