@@ -264,7 +264,11 @@ typedef struct {
                                   values do not depend on it */
   int32_t mc_items_per_thread; /* marching cubes: list entries per thread of the vertex and triangle passes,
                                   1, 2, 4 or 8 (default 4) */
-  int32_t reserved[3];
+  int32_t hop_step_budget;     /* analytic hop: 0 one pass (default); 1..4096 steps a ray takes in the
+                                  first pass, after which a ray still running continues in a second pass
+                                  at 16 lanes per ray (shorter steps for the few long rays).  Results do
+                                  not depend on it */
+  int32_t reserved[2];
 } gh_tuning;
 
 /* Replace the process-wide launch shapes; GH_EINVAL for unsupported values. */

@@ -1,7 +1,8 @@
 """Launch-shape autotuner.
 
 The library's launch shapes are process-wide (`gh_set_tuning`): lanes per ray
-of the analytic hop, resident blocks per CU of the marching-cubes look-back
+of the analytic hop and the step budget after which its long rays move to a
+16-lane pass, resident blocks per CU of the marching-cubes look-back
 scans, list entries per thread of the vertex and triangle passes, the split
 policy of network tiles with few rows, and the rays per network work item of
 a batch.  None of them changes a result, only the time.
@@ -25,9 +26,9 @@ from . import native as N
 
 # hop_lanes_per_ray 0 lets the library choose from the bound's type groups.
 DEFAULTS = {"hop_lanes_per_ray": 0, "scan_blocks_per_cu": 4, "mlp_split": 3, "batch_rays_per_item": 4096,
-            "mc_items_per_thread": 4}
-SPACE_PRIMS = {"hop_lanes_per_ray": [0, 1, 2, 3, 4, 8], "scan_blocks_per_cu": [1, 2, 4, 8],
-               "mc_items_per_thread": [1, 2, 4, 8]}
+            "mc_items_per_thread": 4, "hop_step_budget": 0}
+SPACE_PRIMS = {"hop_lanes_per_ray": [0, 1, 2, 3, 4, 8], "hop_step_budget": [0, 32, 64, 128],
+               "scan_blocks_per_cu": [1, 2, 4, 8], "mc_items_per_thread": [1, 2, 4, 8]}
 SPACE_MLP = {"mlp_split": [1, 2, 3], "scan_blocks_per_cu": [1, 2, 4, 8], "mc_items_per_thread": [1, 2, 4, 8]}
 SPACE_BATCH = {"batch_rays_per_item": [1024, 2048, 4096, 8192, 16384]}
 

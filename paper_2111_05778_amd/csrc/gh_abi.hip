@@ -18,7 +18,7 @@
 namespace {
 
 thread_local std::string g_last_error;
-std::atomic<int> g_hop_lanes{0}, g_scan_blocks{0}, g_batch_rays{0}, g_mlp_split{0}, g_mc_items{0};
+std::atomic<int> g_hop_lanes{0}, g_scan_blocks{0}, g_batch_rays{0}, g_mlp_split{0}, g_mc_items{0}, g_hop_budget{0};
 
 gh_status fail(gh_status st, const char* fmt, ...) {
   char buf[512];
@@ -236,6 +236,8 @@ Tuning current_tuning() {
   t.mlp_split = ms ? ms : 3;
   const int mi = g_mc_items.load(std::memory_order_relaxed);
   t.mc_items_per_thread = mi ? mi : 4;
+  const int hb = g_hop_budget.load(std::memory_order_relaxed);
+  t.hop_step_budget = hb;  // 0: one pass
   return t;
 }
 }  // namespace gh
@@ -257,13 +259,16 @@ gh_status gh_set_tuning(const gh_tuning* t) {
   const int mi = t->mc_items_per_thread;
   if (!(mi == 0 || mi == 1 || mi == 2 || mi == 4 || mi == 8))
     return fail(GH_EINVAL, "mc_items_per_thread = %d must be 0, 1, 2, 4 or 8", mi);
-  for (int q = 0; q < 3; ++q)
+  const int hb = t->hop_step_budget;
+  if (!(hb >= 0 && hb <= 4096)) return fail(GH_EINVAL, "hop_step_budget = %d must be 0 or 1..4096", hb);
+  for (int q = 0; q < 2; ++q)
     if (t->reserved[q] != 0) return fail(GH_EINVAL, "reserved tuning fields must be 0");
   g_hop_lanes.store(r, std::memory_order_relaxed);
   g_scan_blocks.store(sb, std::memory_order_relaxed);
   g_batch_rays.store(br, std::memory_order_relaxed);
   g_mlp_split.store(ms, std::memory_order_relaxed);
   g_mc_items.store(mi, std::memory_order_relaxed);
+  g_hop_budget.store(hb, std::memory_order_relaxed);
   return GH_OK;
 }
 
@@ -275,6 +280,7 @@ gh_status gh_get_tuning(gh_tuning* t) {
   t->batch_rays_per_item = g_batch_rays.load(std::memory_order_relaxed);
   t->mlp_split = g_mlp_split.load(std::memory_order_relaxed);
   t->mc_items_per_thread = g_mc_items.load(std::memory_order_relaxed);
+  t->hop_step_budget = g_hop_budget.load(std::memory_order_relaxed);
   return GH_OK;
 }
 

@@ -55,10 +55,16 @@ __device__ __forceinline__ float group_min(float f, int q) {
 // kRegs: every type group has at most R primitives, so each lane holds at
 // most one record per type; those records then live in registers for the
 // whole ray instead of being read from LDS at every step.
+// budget > 0: a ray still running after that many steps is handed over with
+// its state (column, k, the candidate word in progress and the word mask)
+// to park[*park_count++]; the long-ray pass finishes it exactly as this loop
+// would have (the hop is a function of the state alone).
 template <int R, bool kRegs = false>
 __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
                                                uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
-                                               gh_counters* __restrict__ ctr, int tile) {
+                                               gh_counters* __restrict__ ctr, int tile, int budget = 0,
+                                               uint32_t* __restrict__ park = nullptr,
+                                               unsigned int* __restrict__ park_count = nullptr) {
   using S = HopShape<R>;
   const int n = g.n;
   const int nbw = (n + S::kBlockW - 1) / S::kBlockW;
@@ -68,14 +74,14 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
   const int i = bi * S::kBlockH + (w >> 1) * S::kWaveH + r / S::kWaveW;
   const int j = bj * S::kBlockW + (w & 1) * S::kWaveW + r % S::kWaveW;
   uint64_t evals = 0, cands = 0;
-  bool bad = false;
+  bool bad = false, parked = false;
+  const size_t ncol = (size_t)n * n, col = (size_t)i * n + j;
+  int k = 0, wi = 0;
+  uint32_t word = 0;
+  uint64_t mask = 0;
   if (r < S::kWaveRays && i < n && j < n) {  // uniform over the R lanes of a ray
-    const size_t ncol = (size_t)n * n, col = (size_t)i * n + j;
     const float x = centroid(g, i), y = centroid(g, j);
     const float nf = (float)n;
-    int k = 0, wi = 0;
-    uint32_t word = 0;
-    uint64_t mask = 0;
     float rec[kPrimTypes][GH_PRIM_FLOATS];
     bool has[kPrimTypes];
     if constexpr (kRegs) {
@@ -89,6 +95,10 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
       }
     }
     while (k < n) {
+      if (budget > 0 && (int)evals >= budget) {
+        parked = true;
+        break;
+      }
       float f;
       if constexpr (kRegs) {
         const float z = centroid(g, k);
@@ -125,6 +135,123 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
         k += (int)fminf(s, nf);
       }
     }
+    if (q == 0 && !parked) {
+      if (word) {
+        colbits[(size_t)wi * ncol + col] = word;
+        mask |= 1ull << wi;
+      }
+      colmask[col] = mask;
+    }
+  }
+  if (budget > 0) {  // hand-over: one atomic per wave
+    const bool give = parked && q == 0;
+    const uint64_t gb = __ballot(give);
+    if (gb) {
+      const int first = __builtin_ctzll(gb);
+      unsigned base = 0;
+      if (l == first) base = atomicAdd(park_count, (unsigned)__popcll(gb));
+      base = __shfl(base, first, 64);
+      if (give) {
+        uint32_t* o = park + 6 * (size_t)(base + __popcll(gb & ((1ull << l) - 1ull)));
+        o[0] = (uint32_t)col;
+        o[1] = (uint32_t)k;
+        o[2] = (uint32_t)wi;
+        o[3] = word;
+        o[4] = (uint32_t)mask;
+        o[5] = (uint32_t)(mask >> 32);
+      }
+    }
+  }
+  if (q != 0) evals = cands = 0;
+  if (bad && q == 0) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
+  block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
+}
+
+// Minimum over the 16 lanes of a row (lanes 16 m .. 16 m + 15) with DPP
+// moves inside the row: pairs (xor 1, xor 2 in a quad), then each half-row
+// with its mirror image, then the row with its mirror image.
+__device__ __forceinline__ float row16_min(float f) {
+  f = fminf(f, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(f), 0xB1, 0xF, 0xF, false)));
+  f = fminf(f, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(f), 0x4E, 0xF, 0xF, false)));
+  f = fminf(f, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(f), 0x141, 0xF, 0xF, false)));
+  f = fminf(f, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(f), 0x140, 0xF, 0xF, false)));
+  return f;
+}
+
+// Long-ray pass: each handed-over ray continues from its saved state with a
+// row of 16 lanes, lane q evaluating primitives q, q + 16, ... through
+// prim_eval_any (one instruction stream for every type), so a step costs
+// about one primitive instead of one of each type.  kOne: at most 16
+// primitives, each lane's record and type stay in registers.
+template <bool kOne>
+__device__ __forceinline__ void hop_long_rays(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
+                                              uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
+                                              const uint32_t* __restrict__ park, unsigned npark,
+                                              gh_counters* __restrict__ ctr) {
+  const int n = g.n, np = groups.start[kPrimTypes];
+  const size_t ncol = (size_t)n * n;
+  const int l = lane_id(), q = l & 15;
+  const float nf = (float)n;
+  auto type_of = [&](int p) {
+    int t = 0;
+#pragma unroll
+    for (int u = 1; u < kPrimTypes; ++u) t += p >= groups.start[u] ? 1 : 0;
+    return t;
+  };
+  float rec[GH_PRIM_FLOATS];
+  int ty = 0;
+  const bool own = q < np;
+  if constexpr (kOne) {
+    const float* src = srec + (own ? q : 0) * GH_PRIM_FLOATS;
+#pragma unroll
+    for (int e = 0; e < GH_PRIM_FLOATS; ++e) rec[e] = src[e];
+    ty = type_of(own ? q : 0);
+  }
+  uint64_t evals = 0, cands = 0;
+  bool bad = false;
+  const unsigned stride = gridDim.x * (kBlock / 16);
+  for (unsigned ray = (blockIdx.x * kBlock + threadIdx.x) / 16; ray < npark; ray += stride) {  // uniform per row
+    const uint32_t* st = park + 6 * (size_t)ray;
+    const size_t col = st[0];
+    int k = (int)st[1], wi = (int)st[2];
+    uint32_t word = st[3];
+    uint64_t mask = (uint64_t)st[4] | ((uint64_t)st[5] << 32);
+    const int i = (int)(col / n), j = (int)(col - (size_t)i * n);
+    const float x = centroid(g, i), y = centroid(g, j);
+    bool rbad = false;
+    while (k < n) {
+      const float z = centroid(g, k);
+      float f = __builtin_inff();
+      if constexpr (kOne) {
+        const float v = prim_eval_any(rec, ty, x, y, z);
+        f = own ? v : f;
+      } else {
+        for (int p = q; p < np; p += 16) f = fminf(f, prim_eval_any(srec + p * GH_PRIM_FLOATS, type_of(p), x, y, z));
+      }
+      f = row16_min(f);
+      ++evals;
+      const float d = fabsf(f);
+      if (!(d <= FLT_MAX)) {
+        rbad = true;
+        break;
+      }
+      const float s = floorf(d * g.inv_h);
+      if (s == 0.f) {
+        const int kw = k >> 5;
+        if (kw != wi) {
+          if (word && q == 0) colbits[(size_t)wi * ncol + col] = word;
+          if (word) mask |= 1ull << wi;
+          word = 0;
+          wi = kw;
+        }
+        word |= 1u << (k & 31);
+        ++cands;
+        ++k;
+      } else {
+        k += (int)fminf(s, nf);
+      }
+    }
     if (q == 0) {
       if (word) {
         colbits[(size_t)wi * ncol + col] = word;
@@ -132,6 +259,7 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
       }
       colmask[col] = mask;
     }
+    bad = bad || rbad;
   }
   if (q != 0) evals = cands = 0;
   if (bad && q == 0) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);

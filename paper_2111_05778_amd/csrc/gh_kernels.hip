@@ -50,10 +50,25 @@ __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, u
 template <int R, bool kRegs>
 __global__ __launch_bounds__(kBlock) void k_hop_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                       uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
-                                                      gh_counters* __restrict__ ctr) {
+                                                      gh_counters* __restrict__ ctr, int budget,
+                                                      uint32_t* __restrict__ park, unsigned int* __restrict__ npark) {
   __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
   stage_prims(s_rec, prims, groups.start[kPrimTypes]);
-  hop_prims_tile<R, kRegs>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, ctr, blockIdx.x);
+  hop_prims_tile<R, kRegs>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, ctr, blockIdx.x, budget,
+                           park, npark);
+}
+
+// Second pass of a hop with a step budget: the rays the first pass handed
+// over, 16 lanes each (see hop_long_rays).
+template <bool kOne>
+__global__ __launch_bounds__(kBlock) void k_hop_long(const float* __restrict__ prims, PrimGroups groups, Grid g,
+                                                     uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
+                                                     const uint32_t* __restrict__ park,
+                                                     const unsigned int* __restrict__ npark,
+                                                     gh_counters* __restrict__ ctr) {
+  __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
+  stage_prims(s_rec, prims, groups.start[kPrimTypes]);
+  hop_long_rays<kOne>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, park, *npark, ctr);
 }
 
 // ------------------------------------------------------------ enumeration
@@ -166,12 +181,25 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
   const int nbh = (g.n + S::kBlockH - 1) / S::kBlockH, nbw = (g.n + S::kBlockW - 1) / S::kBlockW;
   int most = 0;
   for (int t = 0; t < kPrimTypes; ++t) most = std::max(most, d.groups.start[t + 1] - d.groups.start[t]);
+  const int budget = current_tuning().hop_step_budget;
+  unsigned int* npark = &ws.ticket[kTicketPark];  // zeroed by the clear before every hop
   if (most <= R)
     hipLaunchKernelGGL((k_hop_prims<R, true>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
-                       ws.colmask, ws.colbits, ctr);
+                       ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
   else
     hipLaunchKernelGGL((k_hop_prims<R, false>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
-                       ws.colmask, ws.colbits, ctr);
+                       ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
+  if (budget > 0) {
+    // The count of handed-over rays is read on the device; the grid covers
+    // the device once and strides over them.
+    const int blocks = cu_count() * 4;
+    if (d.groups.start[kPrimTypes] <= 16)
+      hipLaunchKernelGGL(k_hop_long<true>, dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
+                         ws.colbits, ws.park, npark, ctr);
+    else
+      hipLaunchKernelGGL(k_hop_long<false>, dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
+                         ws.colbits, ws.park, npark, ctr);
+  }
 }
 
 hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, int lanes_per_ray,

@@ -13,6 +13,7 @@ namespace gh {
 // Launch shapes in effect (gh_set_tuning); every field resolved to a value.
 struct Tuning {
   int hop_lanes_per_ray, scan_blocks_per_cu, batch_rays_per_item, mlp_split, mc_items_per_thread;
+  int hop_step_budget;  // 0: no hand-over to the long-ray pass
 };
 Tuning current_tuning();
 

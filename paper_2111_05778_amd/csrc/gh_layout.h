@@ -31,6 +31,7 @@ struct Workspace {
   int64_t* cinfo;      // [cap] (first vertex index << 3) | crossing mask (x=1, y=2, z=4)
   int64_t* cand;       // [cap] candidate cell ids in ascending order (never more than the corners)
   int64_t* nlist;      // [2] corners, candidates in the lists
+  uint32_t* park;      // [n*n][6] rays handed to the long-ray pass: column, k, word index, word, mask lo/hi
   uint64_t* scan;      // look-back words: corners, vertices, triangles, candidates export
   unsigned int* ticket;// [8] tile tickets (one per scan) and spare
   int64_t cap;         // corner capacity
@@ -67,6 +68,7 @@ inline size_t workspace_layout(int n, int64_t cap, void* base, Workspace* ws) {
   const size_t o_ci = take((size_t)cap * 8);
   const size_t o_cand = take((size_t)cap * 8);
   const size_t o_nlist = take(2 * 8);
+  const size_t o_park = take(n2 * 6 * 4);
   const size_t scan_words = (size_t)(tiles_lat + 2 * tiles_cap + tiles_col);
   const size_t o_scan = take(scan_words * 8);
   const size_t o_ticket = take(8 * sizeof(unsigned int));
@@ -84,6 +86,7 @@ inline size_t workspace_layout(int n, int64_t cap, void* base, Workspace* ws) {
     ws->cinfo = (int64_t*)(b + o_ci);
     ws->cand = (int64_t*)(b + o_cand);
     ws->nlist = (int64_t*)(b + o_nlist);
+    ws->park = (uint32_t*)(b + o_park);
     ws->scan = (uint64_t*)(b + o_scan);
     ws->ticket = (unsigned int*)(b + o_ticket);
     ws->cap = cap;
@@ -121,6 +124,6 @@ __device__ __forceinline__ int64_t corner_index(const Workspace& ws, size_t nl, 
   return present && (word & bit) ? idx : -1;
 }
 
-enum { kTicketCorners = 0, kTicketVerts = 1, kTicketTris = 2, kTicketCands = 3, kTicketRays = 4 };
+enum { kTicketCorners = 0, kTicketVerts = 1, kTicketTris = 2, kTicketCands = 3, kTicketRays = 4, kTicketPark = 5 };
 
 }  // namespace gh

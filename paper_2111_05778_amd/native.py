@@ -53,10 +53,12 @@ class gh_sdb_spec(ctypes.Structure):
 class gh_tuning(ctypes.Structure):
     _fields_ = [("hop_lanes_per_ray", ctypes.c_int32), ("scan_blocks_per_cu", ctypes.c_int32),
                 ("batch_rays_per_item", ctypes.c_int32), ("mlp_split", ctypes.c_int32),
-                ("mc_items_per_thread", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("mc_items_per_thread", ctypes.c_int32), ("hop_step_budget", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
-TUNING_FIELDS = ("hop_lanes_per_ray", "scan_blocks_per_cu", "batch_rays_per_item", "mlp_split", "mc_items_per_thread")
+TUNING_FIELDS = ("hop_lanes_per_ray", "scan_blocks_per_cu", "batch_rays_per_item", "mlp_split", "mc_items_per_thread",
+                 "hop_step_budget")
 
 
 class gh_sdb_desc(ctypes.Structure):
@@ -173,7 +175,7 @@ def gh_eval_points(desc, xyz, f, m, stream=None):
 
 
 def gh_set_tuning(hop_lanes_per_ray=0, scan_blocks_per_cu=0, batch_rays_per_item=0, mlp_split=0,
-                  mc_items_per_thread=0):
+                  mc_items_per_thread=0, hop_step_budget=0):
     """Process-wide launch shapes; 0 keeps the built-in choice (see include/gh.h)."""
     t = gh_tuning()
     t.hop_lanes_per_ray = int(hop_lanes_per_ray)
@@ -181,6 +183,7 @@ def gh_set_tuning(hop_lanes_per_ray=0, scan_blocks_per_cu=0, batch_rays_per_item
     t.batch_rays_per_item = int(batch_rays_per_item)
     t.mlp_split = int(mlp_split)
     t.mc_items_per_thread = int(mc_items_per_thread)
+    t.hop_step_budget = int(hop_step_budget)
     check(lib.gh_set_tuning(ctypes.byref(t)), "gh_set_tuning")
 
 

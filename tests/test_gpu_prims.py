@@ -179,6 +179,30 @@ def test_eval_points_bit_exact(gh):
     np.testing.assert_array_equal(f, ref)
 
 
+def test_sqrt_correctly_rounded_over_wide_range(gh):
+    """The kernels' square root (hardware estimate + rounding test, library
+    path for tiny inputs) against numpy's correctly rounded float32 sqrt:
+    a sphere of radius 0 at the origin evaluates sqrt((x x + y y) + z z).
+    Magnitudes are log-uniform over [2^-63, 2^60] (sums of squares from the
+    smallest normal up, so the tiny-input path is covered), signs random,
+    plus exact zeros."""
+    import torch
+    native, P = gh
+    recs = W.sphere_scene(0.0)
+    b = P.Bound.prims(recs)
+    rng = np.random.default_rng(5)
+    m = 1 << 22
+    mag = np.exp2(rng.uniform(-63, 60, (m, 3)))
+    pts = (mag * rng.choice([-1.0, 1.0], (m, 3))).astype(np.float32)
+    pts[:1000] = 0.0
+    pts[1000:2000, 1:] = 0.0  # one non-zero component: sqrt of a rounded square
+    f = b.eval(torch.from_numpy(pts).cuda()).cpu().numpy()
+    ref = osdb.union_f32(recs, pts[:, 0], pts[:, 1], pts[:, 2])
+    s = (pts[:, 0] * pts[:, 0] + pts[:, 1] * pts[:, 1]) + pts[:, 2] * pts[:, 2]
+    assert (s < np.float32(2.0 ** -96)).sum() > 1000  # the tiny-input path ran
+    np.testing.assert_array_equal(f, ref)
+
+
 def test_capacity_overflow_reports_required_sizes(gh):
     import torch
     native, P = gh
@@ -277,3 +301,44 @@ def test_uneven_type_groups_match_twin(gh, n_prim, lanes):
         native.gh_set_tuning(0)
     ref = ohop.gridhop(osdb.SDB.prims(recs), *g, precision="f32")
     _check_against_twin(out, ref, *[float(x) for x in g])
+
+
+@pytest.mark.parametrize("budget,lanes,scene,n_prim,n", [
+    (1, 0, 1, 12, 100), (4, 3, 1, 12, 100), (16, 1, 1, 12, 100), (2, 8, 1, 12, 100), (0, 0, 1, 12, 100),
+    (3, 0, 7, 24, 61), (1, 4, 7, 5, 61), (2, 0, 7, 1, 61)])
+def test_long_ray_pass_matches_twin(gh, budget, lanes, scene, n_prim, n):
+    # a small step budget hands nearly every ray to the 16-lane pass, which
+    # must continue it bit for bit (more than 16 primitives take its loop
+    # over records; fewer leave lanes without one)
+    native, P = gh
+    recs = W.csg_scene(scene, n_prim)
+    g = W.grid(n)
+    native.gh_set_tuning(hop_lanes_per_ray=lanes, hop_step_budget=budget)
+    try:
+        out = _run(gh, recs, *g)
+    finally:
+        native.gh_set_tuning(0)
+    ref = ohop.gridhop(osdb.SDB.prims(recs), *g, precision="f32")
+    _check_against_twin(out, ref, *[float(x) for x in g])
+
+
+def test_long_ray_pass_counters_full_size(gh):
+    # every budget gives the oracle's exact evaluation and candidate counts
+    # at N = 512, repeated runs included
+    native, P = gh
+    n, lo, h = W.grid(512)
+    recs = W.csg_scene(0)
+    cells, total, _ = ohop.hop(osdb.SDB.prims(recs), n, lo, h, precision="f32")
+    b = P.Bound.prims(recs)
+    import torch
+    try:
+        for budget in (0, 1, 8, 32, 100):
+            native.gh_set_tuning(hop_step_budget=budget)
+            poly = P.Polygonizer(b, n, lo, h, keep_cells=False)
+            for _ in range(2):
+                poly.enqueue_hop()
+                torch.cuda.synchronize()
+                c = P.counters_dict(poly.ctr)
+                assert c["n_hop_evals"] == total and c["n_cand"] == len(cells), (budget, c)
+    finally:
+        native.gh_set_tuning(0)
