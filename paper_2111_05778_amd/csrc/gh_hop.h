@@ -103,12 +103,21 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
       if constexpr (kRegs) {
         const float z = centroid(g, k);
         f = __builtin_inff();
-        if (has[kPrimSphere]) f = fminf(f, prim_eval_t<kPrimSphere>(rec[kPrimSphere], x, y, z));
-        if (has[kPrimBox]) f = fminf(f, prim_eval_t<kPrimBox>(rec[kPrimBox], x, y, z));
-        if (has[kPrimTorus]) f = fminf(f, prim_eval_t<kPrimTorus>(rec[kPrimTorus], x, y, z));
-        if (has[kPrimCapsule]) f = fminf(f, prim_eval_t<kPrimCapsule>(rec[kPrimCapsule], x, y, z));
-        if (has[kPrimPlane]) f = fminf(f, prim_eval_t<kPrimPlane>(rec[kPrimPlane], x, y, z));
-        if (has[kPrimBoxBound]) f = fminf(f, prim_eval_t<kPrimBoxBound>(rec[kPrimBoxBound], x, y, z));
+        // Every type is evaluated (a lane without one holds another record
+        // and discards the value): no branch splits the step, so the
+        // independent chains of the six formulas interleave.
+        const float v0 = prim_eval_t<kPrimSphere>(rec[kPrimSphere], x, y, z);
+        const float v1 = prim_eval_t<kPrimBox>(rec[kPrimBox], x, y, z);
+        const float v2 = prim_eval_t<kPrimTorus>(rec[kPrimTorus], x, y, z);
+        const float v3 = prim_eval_t<kPrimCapsule>(rec[kPrimCapsule], x, y, z);
+        const float v4 = prim_eval_t<kPrimPlane>(rec[kPrimPlane], x, y, z);
+        const float v5 = prim_eval_t<kPrimBoxBound>(rec[kPrimBoxBound], x, y, z);
+        f = has[kPrimSphere] ? fminf(f, v0) : f;
+        f = has[kPrimBox] ? fminf(f, v1) : f;
+        f = has[kPrimTorus] ? fminf(f, v2) : f;
+        f = has[kPrimCapsule] ? fminf(f, v3) : f;
+        f = has[kPrimPlane] ? fminf(f, v4) : f;
+        f = has[kPrimBoxBound] ? fminf(f, v5) : f;
       } else {
         f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y, centroid(g, k));
       }

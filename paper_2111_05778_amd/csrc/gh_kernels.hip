@@ -48,7 +48,7 @@ __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, u
 
 // --------------------------------------------------------------------- hop
 template <int R, bool kRegs>
-__global__ __launch_bounds__(kBlock) void k_hop_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_hop_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                       uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                       gh_counters* __restrict__ ctr, int budget,
                                                       uint32_t* __restrict__ park, unsigned int* __restrict__ npark) {
