@@ -172,6 +172,23 @@ class Polygonizer:
                         self.vert_t, self.vert_cap, self.tris, self.tri_cap, self.cells, self.cases,
                         self.cell_cap if self.keep_cells else 0, self.ctr, stream), "gh_mc")
 
+    # ------------------------------------------------------------ graphs
+    def capture(self, dense=False):
+        """Records one hop (or enumeration) and marching cubes into a graph;
+        replay() launches it again with no per-kernel host work.  The buffers
+        must already be large enough (run() once first): a replay does not
+        grow them, and the counters report any shortfall as after run()."""
+        self._graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.graph(self._graph, stream=side):
+            (self.enqueue_dense if dense else self.enqueue_hop)()
+            self.enqueue_mc()
+        torch.cuda.current_stream(self.device).wait_stream(side)
+
+    def replay(self):
+        self._graph.replay()
+
     # ------------------------------------------------------------ blocking
     def run(self, dense=False, stream=None, max_retries=3):
         for _ in range(max_retries + 1):

@@ -342,3 +342,30 @@ def test_long_ray_pass_counters_full_size(gh):
                 assert c["n_hop_evals"] == total and c["n_cand"] == len(cells), (budget, c)
     finally:
         native.gh_set_tuning(0)
+
+
+def test_graph_replay_matches_eager(gh):
+    # one captured step (hop or enumeration, then marching cubes), replayed
+    # several times with eager work and synchronisations in between: every
+    # replay gives that step's eager counters, vertices and triangles bit for
+    # bit
+    import torch
+    native, P = gh
+    n, lo, h = W.grid(96)
+    poly = P.Polygonizer(P.Bound.prims(W.csg_scene(2)), n, lo, h)
+    other = P.Polygonizer(P.Bound.prims(W.csg_scene(4)), *W.grid(40))
+    for dense in (False, True):
+        ref = poly.run(dense=dense)
+        c_ref = dict(ref.counters)
+        v_ref, t_ref = ref.verts.clone(), ref.tris.clone()
+        poly.capture(dense=dense)
+        for rep in range(3):
+            poly.verts.zero_()
+            poly.tris.zero_()
+            poly.replay()
+            torch.cuda.synchronize()
+            c = P.counters_dict(poly.ctr)
+            for k in ("n_hop_evals", "n_cand", "n_corner", "n_cells", "n_vert", "n_tri", "flags"):
+                assert c[k] == c_ref[k], (dense, rep, k)
+            assert torch.equal(poly.verts[:c["n_vert"]], v_ref) and torch.equal(poly.tris[:c["n_tri"]], t_ref)
+            other.run()  # eager work between replays
