@@ -553,42 +553,56 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
     const int64_t tile_t = (int64_t)(so.total & 0x7fffffffull) - tbase;
     const int64_t tile_c = (int64_t)(so.total >> 31) - cbase;
     const bool stage = tile_t <= kStageT;  // the cells always fit: at most one per candidate
+    // The vertex records of the lower corners of each item's crossing edges
+    // (corner 7 is no edge's lower corner), loaded for a batch of items at
+    // once and unconditionally (a record an item does not need reads entry
+    // 0), so the batch costs one memory round trip.
+    constexpr int kB = kItems < 4 ? kItems : 4;
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      if (!nt[r]) continue;
-      if (verts_ok) {
-        s_cell[c - cbase] = cell[r];
-        s_case[c - cbase] = (uint8_t)cs[r];
-        if (stage || t0 + (int64_t)nt[r] <= tri_cap) {
-          const McCase mcc = s_mc[cs[r]];
-          // The vertex records of the lower corners of the crossing edges
-          // (corner 7 is no edge's lower corner), all loaded up front.
-          unsigned need = 0;
+    for (int r0 = 0; r0 < kItems; r0 += kB) {
+      int64_t info[kB][7];
 #pragma unroll
-          for (int e = 0; e < 12; ++e)
-            if ((mcc.edges >> e) & 1) need |= 1u << mc_edge_lower(e);
-          int64_t info[7];
+      for (int rb = 0; rb < kB; ++rb) {
+        const int r = r0 + rb;
+        const unsigned edges = s_mc[cs[r]].edges;
+        unsigned need = 0;
 #pragma unroll
-          for (int lc = 0; lc < 7; ++lc) info[lc] = (need >> lc) & 1 ? ws.cinfo[C[r].p[lc & 3] + (lc >> 2)] : 0;
+        for (int e = 0; e < 12; ++e)
+          if ((edges >> e) & 1) need |= 1u << mc_edge_lower(e);
+        if (!nt[r] || !verts_ok) need = 0;
 #pragma unroll
-          for (unsigned tq = 0; tq < 5; ++tq) {
-            if (tq >= nt[r]) break;
+        for (int lc = 0; lc < 7; ++lc)
+          info[rb][lc] = ws.cinfo[(need >> lc) & 1 ? C[r].p[lc & 3] + (lc >> 2) : 0];
+      }
 #pragma unroll
-            for (int v = 0; v < 3; ++v) {
-              const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
-              const int lc = (int)((kEdgeLower >> (3 * e)) & 7), axis = e >> 2;
-              int64_t in = info[0];
+      for (int rb = 0; rb < kB; ++rb) {
+        const int r = r0 + rb;
+        if (!nt[r]) continue;
+        if (verts_ok) {
+          s_cell[c - cbase] = cell[r];
+          s_case[c - cbase] = (uint8_t)cs[r];
+          if (stage || t0 + (int64_t)nt[r] <= tri_cap) {
+            const McCase mcc = s_mc[cs[r]];
 #pragma unroll
-              for (int q = 1; q < 7; ++q) in = lc == q ? info[q] : in;
-              const int32_t vid = (int32_t)((in >> 3) + __popc((unsigned)(in & 7) & ((1u << axis) - 1u)));
-              if (stage) s_tri[3 * (t0 - tbase + tq) + v] = vid;
-              else tris[3 * (t0 + tq) + v] = vid;
+            for (unsigned tq = 0; tq < 5; ++tq) {
+              if (tq >= nt[r]) break;
+#pragma unroll
+              for (int v = 0; v < 3; ++v) {
+                const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
+                const int lc = (int)((kEdgeLower >> (3 * e)) & 7), axis = e >> 2;
+                int64_t in = info[rb][0];
+#pragma unroll
+                for (int q = 1; q < 7; ++q) in = lc == q ? info[rb][q] : in;
+                const int32_t vid = (int32_t)((in >> 3) + __popc((unsigned)(in & 7) & ((1u << axis) - 1u)));
+                if (stage) s_tri[3 * (t0 - tbase + tq) + v] = vid;
+                else tris[3 * (t0 + tq) + v] = vid;
+              }
             }
           }
         }
+        t0 += nt[r];
+        ++c;
       }
-      t0 += nt[r];
-      ++c;
     }
     __syncthreads();
     if (verts_ok) {
