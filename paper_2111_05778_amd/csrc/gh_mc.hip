@@ -158,8 +158,8 @@ constexpr int kStageCands = 1024;
 // candidate cells.  One packed scan: (candidates << 31) | corners.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_corners(Grid g, Workspace ws,
                                                                                         gh_counters* __restrict__ ctr) {
-  __shared__ int32_t s_ck[kStageCorners];
-  __shared__ int32_t s_cl[kStageCorners];
+  __shared__ __align__(16) int32_t s_ck[kStageCorners];
+  __shared__ __align__(16) int32_t s_cl[kStageCorners];
   __shared__ int64_t s_cand[kStageCands];
   const int n = g.n, n1 = n + 1;
   const size_t ncol = (size_t)n * n, nl = (size_t)n1 * n1;
@@ -193,19 +193,39 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   const bool stage_c = tile_c <= (uint64_t)kStageCorners, stage_k = tile_k <= (uint64_t)kStageCands;
   const bool fits = L < nl && c0 + ncorner <= (uint64_t)ws.cap;
   int64_t o = (int64_t)c0, oc = (int64_t)k0;
+  // A full word (32 consecutive corners, the columns along a wall parallel
+  // to them) goes out as 16-byte stores once its position is 4-aligned.
+  // dk, dl: the list (off 0) or the tile's LDS stage (off the tile's base).
+  auto emit_word = [&](int32_t* __restrict__ dk, int32_t* __restrict__ dl, int64_t off, int w, uint32_t cw) {
+    const int32_t Li = (int32_t)L;
+    int64_t i = o - off;
+    if (cw == 0xffffffffu) {
+      const int32_t k0 = 32 * w;
+      int j = 0;
+      for (; j < 32 && (i & 3); ++j, ++i) {
+        dk[i] = k0 + j;
+        dl[i] = Li;
+      }
+      for (; j + 4 <= 32; j += 4, i += 4) {
+        *reinterpret_cast<int4*>(dk + i) = make_int4(k0 + j, k0 + j + 1, k0 + j + 2, k0 + j + 3);
+        *reinterpret_cast<int4*>(dl + i) = make_int4(Li, Li, Li, Li);
+      }
+      for (; j < 32; ++j, ++i) {
+        dk[i] = k0 + j;
+        dl[i] = Li;
+      }
+    } else {
+      for (uint32_t bb = cw; bb; bb &= bb - 1, ++i) {
+        dk[i] = 32 * w + __builtin_ctz(bb);
+        dl[i] = Li;
+      }
+    }
+    o = i + off;
+  };
   auto put = [&](int w, uint32_t cw, uint32_t ow) {
     if (cw) ws.lwst[(size_t)w * nl + L] = (int32_t)o;
-    for (uint32_t bb = cw; bb; bb &= bb - 1) {
-      const int32_t kk = 32 * w + __builtin_ctz(bb);
-      if (stage_c) {
-        s_ck[o - (int64_t)cbase] = kk;
-        s_cl[o - (int64_t)cbase] = (int32_t)L;
-      } else {
-        ws.ck[o] = kk;
-        ws.cl[o] = (int32_t)L;
-      }
-      ++o;
-    }
+    if (stage_c) emit_word(s_ck, s_cl, (int64_t)cbase, w, cw);
+    else emit_word(ws.ck, ws.cl, 0, w, cw);
     for (uint32_t bb = ow; bb; bb &= bb - 1) {
       const int64_t id = (int64_t)own_col * n + 32 * w + __builtin_ctz(bb);
       if (stage_k) s_cand[oc - (int64_t)kbase] = id;
