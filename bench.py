@@ -259,7 +259,7 @@ def main():
     sections = [x for x in args.sections.split(",") if x and x != "none"]
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (each ray column is "
-              f"independent, the multi-GPU split is described in DESIGN.md)", file=sys.stderr)
+              f"independent: several GPUs would each take a band of columns)", file=sys.stderr)
         sys.exit(2)
 
     import torch

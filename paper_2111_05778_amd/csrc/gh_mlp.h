@@ -601,11 +601,6 @@ __device__ __forceinline__ void mlp_tile_reg(const MlpDesc& m, MlpSmem& sm, int 
   else mlp_tile_split<P, W, 1>(m, sm, nrows);
 }
 
-// Blocks per CU a kernel holding the tile evaluator is compiled for: the LDS
-// allows two; the split bf16 form at width 256 needs the registers of one.
-template <int P, int W>
-__host__ __device__ constexpr int mlp_min_blocks() { return (P == kPrecBf16x3 && W == 256) ? 1 : 1; }
-
 // Evaluates f at sm.pts[0, nrows) into sm.f[0, nrows) (nrows <= mlp_rows<P>);
 // sm.pts must be visible to the block (synchronised) before the call.
 template <int P, int W, class Sm>
