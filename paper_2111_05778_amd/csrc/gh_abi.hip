@@ -289,7 +289,7 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
   if (!spec_h) return fail(GH_EINVAL, "spec is NULL");
   if (spec_h->kind == GH_SDB_MLP) return describe_mlp(spec_h, dev_blob, blob_bytes, blob_needed_h, desc_h, stream);
   if (spec_h->kind != GH_SDB_PRIMS)
-    return fail(GH_EUNSUPPORTED, "bound kind %d is not supported by this build", spec_h->kind);
+    return fail(GH_EUNSUPPORTED, "bound kind %d is not supported by this library", spec_h->kind);
   const int np = spec_h->n_prim;
   if (np < 1 || np > gh::kMaxPrims) return fail(GH_EINVAL, "n_prim = %d must be in [1, %d]", np, gh::kMaxPrims);
   if (!spec_h->prims_h) return fail(GH_EINVAL, "prims_h is NULL");
