@@ -59,7 +59,9 @@ __device__ __forceinline__ float group_min(float f, int q) {
 // its state (column, k, the candidate word in progress and the word mask)
 // to park[*park_count++]; the long-ray pass finishes it exactly as this loop
 // would have (the hop is a function of the state alone).
-template <int R, bool kRegs = false>
+// kTypes (kRegs only): bit t set when type t may be present; a type whose
+// bit is clear is neither loaded nor evaluated.
+template <int R, bool kRegs = false, int kTypes = 63>
 __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
                                                uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                gh_counters* __restrict__ ctr, int tile, int budget = 0,
@@ -89,6 +91,7 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
       for (int t = 0; t < kPrimTypes; ++t) {
         const int p = groups.start[t] + q;
         has[t] = p < groups.start[t + 1];
+        if (!((kTypes >> t) & 1)) continue;
         const float* src = srec + (has[t] ? p : 0) * GH_PRIM_FLOATS;
 #pragma unroll
         for (int e = 0; e < GH_PRIM_FLOATS; ++e) rec[t][e] = src[e];
@@ -106,18 +109,18 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
         // Every type is evaluated (a lane without one holds another record
         // and discards the value): no branch splits the step, so the
         // independent chains of the six formulas interleave.
-        const float v0 = prim_eval_t<kPrimSphere>(rec[kPrimSphere], x, y, z);
-        const float v1 = prim_eval_t<kPrimBox>(rec[kPrimBox], x, y, z);
-        const float v2 = prim_eval_t<kPrimTorus>(rec[kPrimTorus], x, y, z);
-        const float v3 = prim_eval_t<kPrimCapsule>(rec[kPrimCapsule], x, y, z);
-        const float v4 = prim_eval_t<kPrimPlane>(rec[kPrimPlane], x, y, z);
-        const float v5 = prim_eval_t<kPrimBoxBound>(rec[kPrimBoxBound], x, y, z);
-        f = has[kPrimSphere] ? fminf(f, v0) : f;
-        f = has[kPrimBox] ? fminf(f, v1) : f;
-        f = has[kPrimTorus] ? fminf(f, v2) : f;
-        f = has[kPrimCapsule] ? fminf(f, v3) : f;
-        f = has[kPrimPlane] ? fminf(f, v4) : f;
-        f = has[kPrimBoxBound] ? fminf(f, v5) : f;
+        float v[kPrimTypes];
+        if constexpr (kTypes & (1 << kPrimSphere)) v[kPrimSphere] = prim_eval_t<kPrimSphere>(rec[kPrimSphere], x, y, z);
+        if constexpr (kTypes & (1 << kPrimBox)) v[kPrimBox] = prim_eval_t<kPrimBox>(rec[kPrimBox], x, y, z);
+        if constexpr (kTypes & (1 << kPrimTorus)) v[kPrimTorus] = prim_eval_t<kPrimTorus>(rec[kPrimTorus], x, y, z);
+        if constexpr (kTypes & (1 << kPrimCapsule))
+          v[kPrimCapsule] = prim_eval_t<kPrimCapsule>(rec[kPrimCapsule], x, y, z);
+        if constexpr (kTypes & (1 << kPrimPlane)) v[kPrimPlane] = prim_eval_t<kPrimPlane>(rec[kPrimPlane], x, y, z);
+        if constexpr (kTypes & (1 << kPrimBoxBound))
+          v[kPrimBoxBound] = prim_eval_t<kPrimBoxBound>(rec[kPrimBoxBound], x, y, z);
+#pragma unroll
+        for (int t = 0; t < kPrimTypes; ++t)
+          if ((kTypes >> t) & 1) f = has[t] ? fminf(f, v[t]) : f;
       } else {
         f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y, centroid(g, k));
       }

@@ -47,14 +47,15 @@ __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, u
 }
 
 // --------------------------------------------------------------------- hop
-template <int R, bool kRegs>
+template <int R, bool kRegs, int kTypes = 63>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_hop_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                       uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                       gh_counters* __restrict__ ctr, int budget,
                                                       uint32_t* __restrict__ park, unsigned int* __restrict__ npark) {
   __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
   stage_prims(s_rec, prims, groups.start[kPrimTypes]);
-  hop_prims_tile<R, kRegs>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, ctr, blockIdx.x, budget,
+  hop_prims_tile<R, kRegs, kTypes>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, ctr, blockIdx.x,
+                                   budget,
                            park, npark);
 }
 
@@ -183,7 +184,15 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
   for (int t = 0; t < kPrimTypes; ++t) most = std::max(most, d.groups.start[t + 1] - d.groups.start[t]);
   const int budget = current_tuning().hop_step_budget;
   unsigned int* npark = &ws.ticket[kTicketPark];  // zeroed by the clear before every hop
-  if (most <= R)
+  int present = 0;
+  for (int t = 0; t < kPrimTypes; ++t) present |= (d.groups.start[t + 1] > d.groups.start[t] ? 1 : 0) << t;
+  // Unions of spheres, boxes, tori and capsules (at most) get a kernel that
+  // skips the other two types; any other mix takes the general one.
+  constexpr int kSolids = (1 << kPrimSphere) | (1 << kPrimBox) | (1 << kPrimTorus) | (1 << kPrimCapsule);
+  if (most <= R && (present & ~kSolids) == 0)
+    hipLaunchKernelGGL((k_hop_prims<R, true, kSolids>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
+                       ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
+  else if (most <= R)
     hipLaunchKernelGGL((k_hop_prims<R, true>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
                        ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
   else
