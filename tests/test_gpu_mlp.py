@@ -95,7 +95,7 @@ def test_bf16_values_close_to_fp64(gh, width):
     assert errs["bf16x3"] < 1e-4 and m3 < 0.05 * 0.134 * (2.0 / 512)
 
 
-@pytest.mark.parametrize("width,n", [(64, 64), (256, 48)])
+@pytest.mark.parametrize("width,n", [(64, 64), (256, 48), (64, 37)])
 def test_fp32_mesh_matches_fp64_oracle(gh, width, n):
     import torch
     native, P = gh
@@ -130,7 +130,7 @@ def test_fp32_mesh_matches_fp64_oracle(gh, width, n):
 
 
 @pytest.mark.parametrize("prec,width,n", [("bf16", 256, 64), ("bf16", 64, 128), ("bf16x3", 128, 96),
-                                          ("bf16x3", 256, 128)])
+                                          ("bf16x3", 256, 128), ("bf16x3", 64, 77)])
 def test_bf16_takes_the_fp32_schedule_and_signs(gh, prec, width, n):
     native, P = gh
     net = W.neural_scene(0, width)
