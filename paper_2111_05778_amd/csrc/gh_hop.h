@@ -342,6 +342,10 @@ __device__ __forceinline__ float reeval_fp32(const MlpDesc& m, Sm& sm, int* s_cn
 // empty FP32 tile in every round that meets one ambiguous value.  The hop
 // rule (Section 3, eq. iter, cell-quantised) is applied to every value used,
 // so the schedule is the FP32 one.
+// Speculative rows of a draining pool: at most kSpecMax cells ahead per ray,
+// within a tile of kSpecRows rows.
+constexpr int kSpecRows = 32, kSpecMax = 8;
+
 template <int P, int W, class Src, class Sm>
 __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, uint64_t* __restrict__ colmask,
                                              uint32_t* __restrict__ colbits, gh_counters* __restrict__ ctr,
@@ -445,22 +449,38 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
       }
       continue;
     }
+    // Few ready rays (the pool draining): each also gets rows for its next
+    // cells k + 1, k + 2, ..., filling a 32-row tile, which takes as long as
+    // a tile of one row per ray.  A ray that steps a single cell (a
+    // candidate) takes the next row's value at once; a value is used only
+    // at the cell the ray reaches, so the steps and counts are unchanged.
+    const int D = nrun <= kSpecRows ? (kSpecRows / nrun < kSpecMax ? kSpecRows / nrun : kSpecMax) : 1;
     if (run) {
-      sm.pts[row][0] = x;
-      sm.pts[row][1] = y;
-      sm.pts[row][2] = z;
+#pragma unroll 1
+      for (int t = 0; t < D; ++t) {
+        sm.pts[row * D + t][0] = x;
+        sm.pts[row * D + t][1] = y;
+        sm.pts[row * D + t][2] = k + t < n ? centroid(g, k + t) : z;
+      }
     }
     __syncthreads();
-    mlp_tile<P, W>(m, sm, nrun);
-    const float d = run ? fabsf(sm.f[row]) : 0.f;
-    __syncthreads();
+    mlp_tile<P, W>(m, sm, nrun * D);
     if (run) {
-      bool amb = false;
-      if constexpr (P != kPrecF32)
-        amb = d <= FLT_MAX && floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
-      if (amb) pend = true;
-      else advance(d);
+      const int k0 = k;
+#pragma unroll 1
+      for (int t = 0; t < D && active && k == k0 + t; ++t) {
+        const float d = fabsf(sm.f[row * D + t]);
+        bool amb = false;
+        if constexpr (P != kPrecF32)
+          amb = d <= FLT_MAX && floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
+        if (amb) {
+          pend = true;
+          break;
+        }
+        advance(d);
+      }
     }
+    __syncthreads();
   }
   if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
   block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
