@@ -342,9 +342,9 @@ __device__ __forceinline__ float reeval_fp32(const MlpDesc& m, Sm& sm, int* s_cn
 // empty FP32 tile in every round that meets one ambiguous value.  The hop
 // rule (Section 3, eq. iter, cell-quantised) is applied to every value used,
 // so the schedule is the FP32 one.
-// Speculative rows of a draining pool: at most kSpecMax cells ahead per ray,
-// within a tile of kSpecRows rows.
-constexpr int kSpecRows = 32, kSpecMax = 8;
+// Rows of a draining pool's tile, shared out as windows of cells ahead of
+// each ready ray.
+constexpr int kSpecRows = 32;
 
 template <int P, int W, class Src, class Sm>
 __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, uint64_t* __restrict__ colmask,
@@ -450,11 +450,12 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
       continue;
     }
     // Few ready rays (the pool draining): each also gets rows for its next
-    // cells k + 1, k + 2, ..., filling a 32-row tile, which takes as long as
-    // a tile of one row per ray.  A ray that steps a single cell (a
-    // candidate) takes the next row's value at once; a value is used only
-    // at the cell the ray reaches, so the steps and counts are unchanged.
-    const int D = nrun <= kSpecRows ? (kSpecRows / nrun < kSpecMax ? kSpecRows / nrun : kSpecMax) : 1;
+    // cells k + 1, ..., k + D - 1, filling a 32-row tile, which takes as long
+    // as a tile of one row per ray.  A ray whose step (one cell as a
+    // candidate, or a hop) lands inside that window takes the landing cell's
+    // value at once; a value is used only at a cell the ray reaches, so the
+    // steps and counts are unchanged.
+    const int D = nrun <= kSpecRows ? kSpecRows / nrun : 1;
     if (run) {
 #pragma unroll 1
       for (int t = 0; t < D; ++t) {
@@ -468,8 +469,8 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
     if (run) {
       const int k0 = k;
 #pragma unroll 1
-      for (int t = 0; t < D && active && k == k0 + t; ++t) {
-        const float d = fabsf(sm.f[row * D + t]);
+      while (active && k - k0 < D) {  // k grows with every step: at most D rounds
+        const float d = fabsf(sm.f[row * D + (k - k0)]);
         bool amb = false;
         if constexpr (P != kPrecF32)
           amb = d <= FLT_MAX && floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
