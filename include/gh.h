@@ -266,8 +266,8 @@ typedef struct {
                                   1, 2, 4 or 8 (default 4) */
   int32_t hop_step_budget;     /* analytic hop: 0 one pass (default); 1..4096 steps a ray takes in the
                                   first pass, after which a ray still running continues in a second pass
-                                  at 16 lanes per ray (shorter steps for the few long rays).  Results do
-                                  not depend on it */
+                                  with one wave per ray, which evaluates a window of 64 / lanes cells at
+                                  once and steps through it.  Results do not depend on it */
   int32_t reserved[2];
 } gh_tuning;
 

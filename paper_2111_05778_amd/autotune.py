@@ -2,10 +2,10 @@
 
 The library's launch shapes are process-wide (`gh_set_tuning`): lanes per ray
 of the analytic hop and the step budget after which its long rays move to a
-16-lane pass, resident blocks per CU of the marching-cubes look-back
-scans, list entries per thread of the vertex and triangle passes, the split
-policy of network tiles with few rows, and the rays per network work item of
-a batch.  None of them changes a result, only the time.
+pass of one wave and one window of cells per ray, resident blocks per CU of
+the marching-cubes look-back scans, list entries per thread of the vertex and
+triangle passes, the split policy of network tiles with few rows, and the
+rays per network work item of a batch.  None of them changes a result, only the time.
 
 `tune()` measures a workload on the device under a coordinate descent over
 these shapes: each parameter in turn sweeps its values with the others held

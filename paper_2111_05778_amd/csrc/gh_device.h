@@ -75,32 +75,6 @@ __device__ __forceinline__ float prim_eval_t(const float* __restrict__ r, float 
 
 constexpr int kPrimTypes = 6;
 
-// Any primitive type t in one instruction stream, so that lanes holding
-// different types evaluate together.  Value for value it is prim_eval_t<t>:
-// the selected path performs the same rounded operations in the same order
-// (a plane reads p - 0 = p; the sums that a type lacks add an exact +0 and
-// the subtraction it lacks subtracts 0), and the other paths are discarded.
-// Only the sign of a zero result may differ, which |f| ignores.
-__device__ __forceinline__ float prim_eval_any(const float* __restrict__ r, int t, float x, float y, float z) {
-  const bool plane = t == kPrimPlane;
-  const float dx = x - (plane ? 0.f : r[1]), dy = y - (plane ? 0.f : r[2]), dz = z - (plane ? 0.f : r[3]);
-  const float qx = (r[4] * dx + r[5] * dy) + r[6] * dz;
-  const float qy = (r[7] * dx + r[8] * dy) + r[9] * dz;
-  const float qz = (r[10] * dx + r[11] * dy) + r[12] * dz;
-  const float ts = sqrtf(qx * qx + qz * qz) - r[13];          // torus: distance to the ring
-  const float w = qz - fminf(fmaxf(qz, -r[13]), r[13]);       // capsule: axial excess
-  const float ux = fabsf(qx) - r[13], uy = fabsf(qy) - r[14], uz = fabsf(qz) - r[15];
-  const float inner = fmaxf(ux, fmaxf(uy, uz));               // box: largest face distance
-  const bool box = t == kPrimBox, torus = t == kPrimTorus, capsule = t == kPrimCapsule;
-  const float a = box ? fmaxf(ux, 0.f) : (torus ? ts : qx);
-  const float b = box ? fmaxf(uy, 0.f) : qy;
-  const float c = box ? fmaxf(uz, 0.f) : (torus ? 0.f : (capsule ? w : qz));
-  const float rr = box ? 0.f : ((torus || capsule) ? r[14] : r[13]);
-  const float e = box ? fminf(inner, 0.f) : 0.f;
-  const float v = (sqrtf((a * a + b * b) + c * c) - rr) + e;
-  return plane ? qx - r[13] : (t == kPrimBoxBound ? inner : v);
-}
-
 // Primitives sorted by type: group t occupies records [start[t], start[t+1]).
 // The minimum is exact and commutative, so the order of the union does not
 // change a single bit of the result (parameters are validated on the host so

@@ -48,19 +48,63 @@ __device__ __forceinline__ float group_min(float f, int q) {
   }
 }
 
+// One lane's share of a cell's union value when R lanes evaluate a cell:
+// lane q takes primitives q, q + R, q + 2R, ... of each type group.
+// kRegs: every type group has at most R primitives, so the lane holds at
+// most one record per type, loaded once by lane_records into registers.
+// kTypes (kRegs only): bit t set when type t may be present; a type whose bit
+// is clear is neither loaded nor evaluated.
+template <int R, int kTypes>
+__device__ __forceinline__ void lane_records(const float* __restrict__ srec, const PrimGroups& groups, int q,
+                                             float (&rec)[kPrimTypes][GH_PRIM_FLOATS], bool (&has)[kPrimTypes]) {
+#pragma unroll
+  for (int t = 0; t < kPrimTypes; ++t) {
+    const int p = groups.start[t] + q;
+    has[t] = p < groups.start[t + 1];
+    if (!((kTypes >> t) & 1)) continue;
+    const float* src = srec + (has[t] ? p : 0) * GH_PRIM_FLOATS;
+#pragma unroll
+    for (int e = 0; e < GH_PRIM_FLOATS; ++e) rec[t][e] = src[e];
+  }
+}
+
+template <int R, bool kRegs, int kTypes>
+__device__ __forceinline__ float lane_union(const float* __restrict__ srec, const PrimGroups& groups, int q,
+                                            const float (&rec)[kPrimTypes][GH_PRIM_FLOATS],
+                                            const bool (&has)[kPrimTypes], float x, float y, float z) {
+  if constexpr (kRegs) {
+    float f = __builtin_inff();
+    // Every type is evaluated (a lane without one holds another record and
+    // discards the value): no branch splits the step, so the independent
+    // chains of the six formulas interleave.
+    float v[kPrimTypes];
+    if constexpr (kTypes & (1 << kPrimSphere)) v[kPrimSphere] = prim_eval_t<kPrimSphere>(rec[kPrimSphere], x, y, z);
+    if constexpr (kTypes & (1 << kPrimBox)) v[kPrimBox] = prim_eval_t<kPrimBox>(rec[kPrimBox], x, y, z);
+    if constexpr (kTypes & (1 << kPrimTorus)) v[kPrimTorus] = prim_eval_t<kPrimTorus>(rec[kPrimTorus], x, y, z);
+    if constexpr (kTypes & (1 << kPrimCapsule))
+      v[kPrimCapsule] = prim_eval_t<kPrimCapsule>(rec[kPrimCapsule], x, y, z);
+    if constexpr (kTypes & (1 << kPrimPlane)) v[kPrimPlane] = prim_eval_t<kPrimPlane>(rec[kPrimPlane], x, y, z);
+    if constexpr (kTypes & (1 << kPrimBoxBound))
+      v[kPrimBoxBound] = prim_eval_t<kPrimBoxBound>(rec[kPrimBoxBound], x, y, z);
+#pragma unroll
+    for (int t = 0; t < kPrimTypes; ++t)
+      if ((kTypes >> t) & 1) f = has[t] ? fminf(f, v[t]) : f;
+    return f;
+  } else {
+    return union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y, z);
+  }
+}
+
 // Hop rule (Section 3, eq. iter, cell-quantised): at the centroid of cell k,
 // s = floor(|f| * inv_h); s >= 1 skips s cells, s == 0 marks cell k as a
 // candidate and moves to k + 1; the ray ends when k >= n.  One block tile of
 // columns; srec holds the primitive records in LDS.
-// kRegs: every type group has at most R primitives, so each lane holds at
-// most one record per type; those records then live in registers for the
-// whole ray instead of being read from LDS at every step.
+// kRegs and kTypes as for lane_union: with kRegs the records live in
+// registers for the whole ray instead of being read from LDS at every step.
 // budget > 0: a ray still running after that many steps is handed over with
 // its state (column, k, the candidate word in progress and the word mask)
 // to park[*park_count++]; the long-ray pass finishes it exactly as this loop
 // would have (the hop is a function of the state alone).
-// kTypes (kRegs only): bit t set when type t may be present; a type whose
-// bit is clear is neither loaded nor evaluated.
 template <int R, bool kRegs = false, int kTypes = 63>
 __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
                                                uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
@@ -86,44 +130,13 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
     const float nf = (float)n;
     float rec[kPrimTypes][GH_PRIM_FLOATS];
     bool has[kPrimTypes];
-    if constexpr (kRegs) {
-#pragma unroll
-      for (int t = 0; t < kPrimTypes; ++t) {
-        const int p = groups.start[t] + q;
-        has[t] = p < groups.start[t + 1];
-        if (!((kTypes >> t) & 1)) continue;
-        const float* src = srec + (has[t] ? p : 0) * GH_PRIM_FLOATS;
-#pragma unroll
-        for (int e = 0; e < GH_PRIM_FLOATS; ++e) rec[t][e] = src[e];
-      }
-    }
+    if constexpr (kRegs) lane_records<R, kTypes>(srec, groups, q, rec, has);
     while (k < n) {
       if (budget > 0 && (int)evals >= budget) {
         parked = true;
         break;
       }
-      float f;
-      if constexpr (kRegs) {
-        const float z = centroid(g, k);
-        f = __builtin_inff();
-        // Every type is evaluated (a lane without one holds another record
-        // and discards the value): no branch splits the step, so the
-        // independent chains of the six formulas interleave.
-        float v[kPrimTypes];
-        if constexpr (kTypes & (1 << kPrimSphere)) v[kPrimSphere] = prim_eval_t<kPrimSphere>(rec[kPrimSphere], x, y, z);
-        if constexpr (kTypes & (1 << kPrimBox)) v[kPrimBox] = prim_eval_t<kPrimBox>(rec[kPrimBox], x, y, z);
-        if constexpr (kTypes & (1 << kPrimTorus)) v[kPrimTorus] = prim_eval_t<kPrimTorus>(rec[kPrimTorus], x, y, z);
-        if constexpr (kTypes & (1 << kPrimCapsule))
-          v[kPrimCapsule] = prim_eval_t<kPrimCapsule>(rec[kPrimCapsule], x, y, z);
-        if constexpr (kTypes & (1 << kPrimPlane)) v[kPrimPlane] = prim_eval_t<kPrimPlane>(rec[kPrimPlane], x, y, z);
-        if constexpr (kTypes & (1 << kPrimBoxBound))
-          v[kPrimBoxBound] = prim_eval_t<kPrimBoxBound>(rec[kPrimBoxBound], x, y, z);
-#pragma unroll
-        for (int t = 0; t < kPrimTypes; ++t)
-          if ((kTypes >> t) & 1) f = has[t] ? fminf(f, v[t]) : f;
-      } else {
-        f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y, centroid(g, k));
-      }
+      float f = lane_union<R, kRegs, kTypes>(srec, groups, q, rec, has, x, y, centroid(g, k));
       f = group_min<R>(f, q);
       ++evals;
       const float d = fabsf(f);
@@ -180,91 +193,74 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
   block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
 }
 
-// Minimum over the 16 lanes of a row (lanes 16 m .. 16 m + 15) with DPP
-// moves inside the row: pairs (xor 1, xor 2 in a quad), then each half-row
-// with its mirror image, then the row with its mirror image.
-__device__ __forceinline__ float row16_min(float f) {
-  f = fminf(f, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(f), 0xB1, 0xF, 0xF, false)));
-  f = fminf(f, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(f), 0x4E, 0xF, 0xF, false)));
-  f = fminf(f, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(f), 0x141, 0xF, 0xF, false)));
-  f = fminf(f, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(f), 0x140, 0xF, 0xF, false)));
-  return f;
-}
-
-// Long-ray pass: each handed-over ray continues from its saved state with a
-// row of 16 lanes, lane q evaluating primitives q, q + 16, ... through
-// prim_eval_any (one instruction stream for every type), so a step costs
-// about one primitive instead of one of each type.  kOne: at most 16
-// primitives, each lane's record and type stay in registers.
-template <bool kOne>
-__device__ __forceinline__ void hop_long_rays(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
-                                              uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
-                                              const uint32_t* __restrict__ park, unsigned npark,
-                                              gh_counters* __restrict__ ctr) {
-  const int n = g.n, np = groups.start[kPrimTypes];
+// Long-ray pass over cell windows: each handed-over ray continues from its
+// saved state with a whole wave.  The R lanes of group t evaluate cell
+// k0 + t exactly as the first pass evaluates a cell, for the W = 64 / R cells
+// k0 .. k0 + W - 1 of the window at once; the wave then applies the hop rule
+// at each cell it lands on with that cell's value, until a step leaves the
+// window, which starts the next round there.  Only the values at cells the
+// ray reaches are used, so the steps, candidates and counts are those of the
+// one-pass hop; a ray stepping one cell at a time along a surface advances W
+// cells per round instead of one.  Wave v of the grid takes rays v, v + V,
+// ... for V waves (a ticket shared by every wave costs more than the
+// imbalance: its atomics serialise across the chip).
+template <int R, bool kRegs, int kTypes>
+__device__ __forceinline__ void hop_window_rays(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
+                                                uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
+                                                const uint32_t* __restrict__ park, unsigned npark,
+                                                gh_counters* __restrict__ ctr) {
+  constexpr int W = 64 / R;
+  const int n = g.n;
   const size_t ncol = (size_t)n * n;
-  const int l = lane_id(), q = l & 15;
+  const int l = lane_id(), t = l / R, q = l % R;  // lanes past W * R evaluate a spare cell
   const float nf = (float)n;
-  auto type_of = [&](int p) {
-    int t = 0;
-#pragma unroll
-    for (int u = 1; u < kPrimTypes; ++u) t += p >= groups.start[u] ? 1 : 0;
-    return t;
-  };
-  float rec[GH_PRIM_FLOATS];
-  int ty = 0;
-  const bool own = q < np;
-  if constexpr (kOne) {
-    const float* src = srec + (own ? q : 0) * GH_PRIM_FLOATS;
-#pragma unroll
-    for (int e = 0; e < GH_PRIM_FLOATS; ++e) rec[e] = src[e];
-    ty = type_of(own ? q : 0);
-  }
+  float rec[kPrimTypes][GH_PRIM_FLOATS];
+  bool has[kPrimTypes];
+  if constexpr (kRegs) lane_records<R, kTypes>(srec, groups, q, rec, has);
   uint64_t evals = 0, cands = 0;
   bool bad = false;
-  const unsigned stride = gridDim.x * (kBlock / 16);
-  for (unsigned ray = (blockIdx.x * kBlock + threadIdx.x) / 16; ray < npark; ray += stride) {  // uniform per row
+  const unsigned nwaves = gridDim.x * (kBlock / 64);
+  for (unsigned ray = (unsigned)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / 64) + wave_id()));
+       ray < npark; ray += nwaves) {  // uniform
     const uint32_t* st = park + 6 * (size_t)ray;
-    const size_t col = st[0];
-    int k = (int)st[1], wi = (int)st[2];
-    uint32_t word = st[3];
-    uint64_t mask = (uint64_t)st[4] | ((uint64_t)st[5] << 32);
+    const size_t col = (uint32_t)__builtin_amdgcn_readfirstlane((int)st[0]);
+    int k = __builtin_amdgcn_readfirstlane((int)st[1]), wi = __builtin_amdgcn_readfirstlane((int)st[2]);
+    uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)st[3]);
+    uint64_t mask = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)st[4]) |
+                    ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)st[5]) << 32);
     const int i = (int)(col / n), j = (int)(col - (size_t)i * n);
     const float x = centroid(g, i), y = centroid(g, j);
     bool rbad = false;
-    while (k < n) {
-      const float z = centroid(g, k);
-      float f = __builtin_inff();
-      if constexpr (kOne) {
-        const float v = prim_eval_any(rec, ty, x, y, z);
-        f = own ? v : f;
-      } else {
-        for (int p = q; p < np; p += 16) f = fminf(f, prim_eval_any(srec + p * GH_PRIM_FLOATS, type_of(p), x, y, z));
-      }
-      f = row16_min(f);
-      ++evals;
+    while (k < n && !rbad) {
+      const int k0 = k, kt = k0 + t;
+      float f = lane_union<R, kRegs, kTypes>(srec, groups, q, rec, has, x, y, centroid(g, kt < n ? kt : n - 1));
+      f = group_min<R>(f, q);
       const float d = fabsf(f);
-      if (!(d <= FLT_MAX)) {
-        rbad = true;
-        break;
-      }
-      const float s = floorf(d * g.inv_h);
-      if (s == 0.f) {
-        const int kw = k >> 5;
-        if (kw != wi) {
-          if (word && q == 0) colbits[(size_t)wi * ncol + col] = word;
-          if (word) mask |= 1ull << wi;
-          word = 0;
-          wi = kw;
+      while (k < n && k - k0 < W) {  // k grows at every step: at most W steps
+        const float dk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), (k - k0) * R));
+        ++evals;
+        if (!(dk <= FLT_MAX)) {
+          rbad = true;
+          break;
         }
-        word |= 1u << (k & 31);
-        ++cands;
-        ++k;
-      } else {
-        k += (int)fminf(s, nf);
+        const float s = floorf(dk * g.inv_h);
+        if (s == 0.f) {
+          const int kw = k >> 5;
+          if (kw != wi) {
+            if (word && l == 0) colbits[(size_t)wi * ncol + col] = word;
+            if (word) mask |= 1ull << wi;
+            word = 0;
+            wi = kw;
+          }
+          word |= 1u << (k & 31);
+          ++cands;
+          ++k;
+        } else {
+          k += (int)fminf(s, nf);
+        }
       }
     }
-    if (q == 0) {
+    if (l == 0) {
       if (word) {
         colbits[(size_t)wi * ncol + col] = word;
         mask |= 1ull << wi;
@@ -273,8 +269,8 @@ __device__ __forceinline__ void hop_long_rays(const float* __restrict__ srec, co
     }
     bad = bad || rbad;
   }
-  if (q != 0) evals = cands = 0;
-  if (bad && q == 0) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  if (l != 0) evals = cands = 0;
+  if (bad && l == 0) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
   block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
   block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
 }

@@ -60,8 +60,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 }
 
 // Second pass of a hop with a step budget: the rays the first pass handed
-// over, 16 lanes each (see hop_long_rays).
-template <bool kOne>
+// over, one wave and one window of cells each (see hop_window_rays).
+template <int R, bool kRegs, int kTypes = 63>
 __global__ __launch_bounds__(kBlock) void k_hop_long(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                      uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                      const uint32_t* __restrict__ park,
@@ -69,7 +69,8 @@ __global__ __launch_bounds__(kBlock) void k_hop_long(const float* __restrict__ p
                                                      gh_counters* __restrict__ ctr) {
   __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
   stage_prims(s_rec, prims, groups.start[kPrimTypes]);
-  hop_long_rays<kOne>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, park, *npark, ctr);
+  hop_window_rays<R, kRegs, kTypes>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, park, *npark,
+                                    ctr);
 }
 
 // ------------------------------------------------------------ enumeration
@@ -189,24 +190,26 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
   // Unions of spheres, boxes, tori and capsules (at most) get a kernel that
   // skips the other two types; any other mix takes the general one.
   constexpr int kSolids = (1 << kPrimSphere) | (1 << kPrimBox) | (1 << kPrimTorus) | (1 << kPrimCapsule);
-  if (most <= R && (present & ~kSolids) == 0)
+  // The second pass (budget > 0) reads the count of handed-over rays on the
+  // device; its grid fills the device once and strides over them.
+  const int blocks = cu_count() * 8;
+  if (most <= R && (present & ~kSolids) == 0) {
     hipLaunchKernelGGL((k_hop_prims<R, true, kSolids>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
                        ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
-  else if (most <= R)
+    if (budget > 0)
+      hipLaunchKernelGGL((k_hop_long<R, true, kSolids>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
+                         ws.colmask, ws.colbits, ws.park, npark, ctr);
+  } else if (most <= R) {
     hipLaunchKernelGGL((k_hop_prims<R, true>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
                        ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
-  else
+    if (budget > 0)
+      hipLaunchKernelGGL((k_hop_long<R, true>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
+                         ws.colbits, ws.park, npark, ctr);
+  } else {
     hipLaunchKernelGGL((k_hop_prims<R, false>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
                        ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
-  if (budget > 0) {
-    // The count of handed-over rays is read on the device; the grid covers
-    // the device once and strides over them.
-    const int blocks = cu_count() * 4;
-    if (d.groups.start[kPrimTypes] <= 16)
-      hipLaunchKernelGGL(k_hop_long<true>, dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
-                         ws.colbits, ws.park, npark, ctr);
-    else
-      hipLaunchKernelGGL(k_hop_long<false>, dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
+    if (budget > 0)
+      hipLaunchKernelGGL((k_hop_long<R, false>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
                          ws.colbits, ws.park, npark, ctr);
   }
 }

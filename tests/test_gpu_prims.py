@@ -307,9 +307,10 @@ def test_uneven_type_groups_match_twin(gh, n_prim, lanes):
     (1, 0, 1, 12, 100), (4, 3, 1, 12, 100), (16, 1, 1, 12, 100), (2, 8, 1, 12, 100), (0, 0, 1, 12, 100),
     (3, 0, 7, 24, 61), (1, 4, 7, 5, 61), (2, 0, 7, 1, 61)])
 def test_long_ray_pass_matches_twin(gh, budget, lanes, scene, n_prim, n):
-    # a small step budget hands nearly every ray to the 16-lane pass, which
-    # must continue it bit for bit (more than 16 primitives take its loop
-    # over records; fewer leave lanes without one)
+    # a small step budget hands nearly every ray to the window pass, which
+    # must continue it bit for bit, for every lanes-per-cell split (8 to 64
+    # cells per window) and with records in registers or read from LDS (a
+    # type group larger than the split)
     native, P = gh
     recs = W.csg_scene(scene, n_prim)
     g = W.grid(n)
