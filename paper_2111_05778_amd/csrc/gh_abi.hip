@@ -338,6 +338,9 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
   d.magic = gh::kDescMagic;
   d.kind = GH_SDB_PRIMS;
   d.n_prim = np;
+  d.flags = gh::kSdbRingsNormal;
+  for (int p = groups.start[gh::kPrimTorus]; p < groups.start[gh::kPrimTorus + 1]; ++p)
+    if (!(fabsf(sorted[(size_t)p * GH_PRIM_FLOATS + 13]) >= 0x1p-23f)) d.flags &= ~gh::kSdbRingsNormal;
   d.prims = (const float*)dev_blob;
   d.groups = groups;
   memset(desc_h, 0, sizeof(*desc_h));

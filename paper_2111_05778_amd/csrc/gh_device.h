@@ -32,6 +32,29 @@ __device__ __forceinline__ float centroid(const Grid& g, int idx) {
 __device__ __forceinline__ float lattice(const Grid& g, int idx) { return g.lo + (float)idx * g.h; }
 
 // ------------------------------------------------------------ analytic bound
+// Square root for hop decisions.  For a >= 2^-96 it is the correctly
+// rounded root: the hardware estimate (within one ulp) or its neighbour on
+// either side, chosen by the sign of the residual a - t s for each neighbour t
+// (one fma, whose sign is exact); this range needs no scaling of the
+// argument.  Below 2^-96 it returns the root of 2^-96 (2^-48).  A hop
+// decision only needs floor(|f| / h), and in every formula a root below 2^-47
+// either disappears when a term of magnitude >= 2^-23 is added (a radius or a
+// face distance: the sum rounds to that term, as it does with the exact root)
+// or leaves |f| < 2^-22, below h whenever h >= 2^-20, where both give s = 0.
+// The torus's inner root feeds a second root instead, hence the condition
+// |R| >= 2^-23 on its ring radius.  Kernels that use it run only when the
+// grid and the union meet both conditions.
+__device__ __forceinline__ float sqrt_hop(float a) {
+  a = fmaxf(a, 0x1p-96f);
+  const float s = __builtin_amdgcn_sqrtf(a);
+  const float lo = __int_as_float(__float_as_int(s) - 1), hi = __int_as_float(__float_as_int(s) + 1);
+  const float r = fmaf(-lo, s, a) <= 0.f ? lo : s;
+  return fmaf(-hi, s, a) > 0.f ? hi : r;
+}
+
+// Smallest cell size for which sqrt_hop gives the decisions of the exact root.
+constexpr float kHopRootMinH = 0x1p-20f;
+
 // One primitive record (16 floats) at p, float32, one rounding per operation
 // in exactly this order (the oracle's twin follows the same order):
 //   d = p - c;  q_r = (M_r0 d_x + M_r1 d_y) + M_r2 d_z
@@ -42,9 +65,12 @@ __device__ __forceinline__ float lattice(const Grid& g, int idx) { return g.lo +
 //   capsule  w = qz - min(max(qz, -a), a);  sqrt((qx qx + qy qy) + w w) - r
 //   plane    ((n_x x + n_y y) + n_z z) - d                 (Section 4.1, eq. plane)
 // The type is a template argument: callers loop over primitives grouped by
-// type, so no branch on the type sits inside the loop.
-template <int T>
+// type, so no branch on the type sits inside the loop.  kHopRoot: the roots
+// are taken by sqrt_hop (hop decisions only; the values themselves may differ
+// from the exact ones below 2^-47).
+template <int T, bool kHopRoot = false>
 __device__ __forceinline__ float prim_eval_t(const float* __restrict__ r, float x, float y, float z) {
+  auto root = [](float v) { return kHopRoot ? sqrt_hop(v) : sqrtf(v); };
   if constexpr (T == kPrimPlane) {
     return ((r[4] * x + r[5] * y) + r[6] * z) - r[13];
   } else {
@@ -53,13 +79,13 @@ __device__ __forceinline__ float prim_eval_t(const float* __restrict__ r, float 
     const float qy = (r[7] * dx + r[8] * dy) + r[9] * dz;
     const float qz = (r[10] * dx + r[11] * dy) + r[12] * dz;
     if constexpr (T == kPrimSphere) {
-      return sqrtf((qx * qx + qy * qy) + qz * qz) - r[13];
+      return root((qx * qx + qy * qy) + qz * qz) - r[13];
     } else if constexpr (T == kPrimTorus) {
-      const float s = sqrtf(qx * qx + qz * qz) - r[13];
-      return sqrtf(s * s + qy * qy) - r[14];
+      const float s = root(qx * qx + qz * qz) - r[13];
+      return root(s * s + qy * qy) - r[14];
     } else if constexpr (T == kPrimCapsule) {
       const float w = qz - fminf(fmaxf(qz, -r[13]), r[13]);
-      return sqrtf((qx * qx + qy * qy) + w * w) - r[14];
+      return root((qx * qx + qy * qy) + w * w) - r[14];
     } else {
       const float ux = fabsf(qx) - r[13], uy = fabsf(qy) - r[14], uz = fabsf(qz) - r[15];
       const float inner = fmaxf(ux, fmaxf(uy, uz));
@@ -67,7 +93,7 @@ __device__ __forceinline__ float prim_eval_t(const float* __restrict__ r, float 
         return inner;
       } else {
         const float mx = fmaxf(ux, 0.f), my = fmaxf(uy, 0.f), mz = fmaxf(uz, 0.f);
-        return sqrtf((mx * mx + my * my) + mz * mz) + fminf(inner, 0.f);
+        return root((mx * mx + my * my) + mz * mz) + fminf(inner, 0.f);
       }
     }
   }

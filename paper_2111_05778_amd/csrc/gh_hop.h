@@ -51,7 +51,10 @@ __device__ __forceinline__ float group_min(float f, int q) {
 // One lane's share of a cell's union value when R lanes evaluate a cell:
 // lane q takes primitives q, q + R, q + 2R, ... of each type group.
 // kRegs: every type group has at most R primitives, so the lane holds at
-// most one record per type, loaded once by lane_records into registers.
+// most one record per type, loaded once by lane_records into registers; its
+// roots are taken by sqrt_hop, so kRegs kernels run only on grids and unions
+// that meet that root's conditions (the others take the LDS-record kernel,
+// with exact roots).
 // kTypes (kRegs only): bit t set when type t may be present; a type whose bit
 // is clear is neither loaded nor evaluated.
 template <int R, int kTypes>
@@ -78,14 +81,14 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
     // discards the value): no branch splits the step, so the independent
     // chains of the six formulas interleave.
     float v[kPrimTypes];
-    if constexpr (kTypes & (1 << kPrimSphere)) v[kPrimSphere] = prim_eval_t<kPrimSphere>(rec[kPrimSphere], x, y, z);
-    if constexpr (kTypes & (1 << kPrimBox)) v[kPrimBox] = prim_eval_t<kPrimBox>(rec[kPrimBox], x, y, z);
-    if constexpr (kTypes & (1 << kPrimTorus)) v[kPrimTorus] = prim_eval_t<kPrimTorus>(rec[kPrimTorus], x, y, z);
+    if constexpr (kTypes & (1 << kPrimSphere)) v[kPrimSphere] = prim_eval_t<kPrimSphere, true>(rec[kPrimSphere], x, y, z);
+    if constexpr (kTypes & (1 << kPrimBox)) v[kPrimBox] = prim_eval_t<kPrimBox, true>(rec[kPrimBox], x, y, z);
+    if constexpr (kTypes & (1 << kPrimTorus)) v[kPrimTorus] = prim_eval_t<kPrimTorus, true>(rec[kPrimTorus], x, y, z);
     if constexpr (kTypes & (1 << kPrimCapsule))
-      v[kPrimCapsule] = prim_eval_t<kPrimCapsule>(rec[kPrimCapsule], x, y, z);
-    if constexpr (kTypes & (1 << kPrimPlane)) v[kPrimPlane] = prim_eval_t<kPrimPlane>(rec[kPrimPlane], x, y, z);
+      v[kPrimCapsule] = prim_eval_t<kPrimCapsule, true>(rec[kPrimCapsule], x, y, z);
+    if constexpr (kTypes & (1 << kPrimPlane)) v[kPrimPlane] = prim_eval_t<kPrimPlane, true>(rec[kPrimPlane], x, y, z);
     if constexpr (kTypes & (1 << kPrimBoxBound))
-      v[kPrimBoxBound] = prim_eval_t<kPrimBoxBound>(rec[kPrimBoxBound], x, y, z);
+      v[kPrimBoxBound] = prim_eval_t<kPrimBoxBound, true>(rec[kPrimBoxBound], x, y, z);
 #pragma unroll
     for (int t = 0; t < kPrimTypes; ++t)
       if ((kTypes >> t) & 1) f = has[t] ? fminf(f, v[t]) : f;

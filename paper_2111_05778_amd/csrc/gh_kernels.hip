@@ -193,13 +193,16 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
   // The second pass (budget > 0) reads the count of handed-over rays on the
   // device; its grid fills the device once and strides over them.
   const int blocks = cu_count() * 8;
-  if (most <= R && (present & ~kSolids) == 0) {
+  // Register-record kernels take the hop square root: only where it gives
+  // the exact root's decisions.
+  const bool regs = most <= R && (d.flags & kSdbRingsNormal) && g.h >= kHopRootMinH;
+  if (regs && (present & ~kSolids) == 0) {
     hipLaunchKernelGGL((k_hop_prims<R, true, kSolids>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
                        ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, true, kSolids>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
                          ws.colmask, ws.colbits, ws.park, npark, ctr);
-  } else if (most <= R) {
+  } else if (regs) {
     hipLaunchKernelGGL((k_hop_prims<R, true>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
                        ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
     if (budget > 0)

@@ -96,6 +96,41 @@ def test_matches_fp32_twin(gh, scene, n):
     _check_against_twin(out, ref, *[float(x) for x in g])
 
 
+def _prim(ptype, centre, params):
+    return W._record(ptype, centre, np.eye(3), params)[None, :]
+
+
+@pytest.mark.parametrize("case", ["zero_radius_at_centroids", "thin_ring", "fine_grid"])
+def test_hop_root_conditions(gh, case):
+    # The register-record hop takes square roots that are exact from 2^-96 up
+    # and clamp below; that gives the exact root's decisions only for cells
+    # of at least 2^-20 and torus ring radii of at least 2^-23, and a grid or
+    # union outside those takes the kernel with exact roots.  Either way the
+    # result is the twin's.
+    if case == "fine_grid":
+        h = 2.0 ** -22
+        n, lo, h = W.grid(48, lo=-24 * h, extent=48 * h)
+        recs = np.concatenate([_prim(W.PRIM_SPHERE, (0.0, 0.0, 0.0), (15 * h,)),
+                               _prim(W.PRIM_BOX, (5 * h, 3 * h, -4 * h), (9 * h, 6 * h, 11 * h)),
+                               _prim(W.PRIM_TORUS, (-6 * h, 2 * h, 1 * h), (12 * h, 3 * h))])
+    else:
+        n, lo, h = W.grid(40)
+        if case == "thin_ring":  # ring radius below 2^-23: a sphere-like torus
+            recs = np.concatenate([_prim(W.PRIM_TORUS, (0.1, -0.05, 0.0), (1e-9, 0.45)),
+                                   _prim(W.PRIM_CAPSULE, (-0.3, 0.2, 0.1), (0.3, 0.15))])
+        else:  # radius-0 spheres and a radius-0 torus tube whose roots see exact zeros at centroids
+            c = lambda i, j, k: tuple(float(v) for v in ohop.centroid_f32(lo, h, np.array([i, j, k])))
+            recs = np.concatenate([_prim(W.PRIM_SPHERE, c(10, 20, 30), (0.0,)),
+                                   _prim(W.PRIM_SPHERE, c(25, 5, 17), (2.0 ** -30,)),
+                                   _prim(W.PRIM_TORUS, c(32, 30, 8), (0.25, 0.0)),
+                                   _prim(W.PRIM_BOX, (0.1, 0.0, -0.1), (0.3, 0.25, 0.2))])
+    out = _run(gh, recs, n, lo, h)
+    ref = ohop.gridhop(osdb.SDB.prims(recs), n, lo, h, precision="f32")
+    print(f"{case}: evals={ref.hop_evals} cand={len(ref.candidates)} cells={len(ref.mesh.cells)}", flush=True)
+    assert ref.hop_evals > n * n
+    _check_against_twin(out, ref, float(n), float(lo), float(h))
+
+
 def test_sphere_n64_against_fp64_oracle(gh):
     n, lo, h = W.grid(64)
     recs = W.sphere_scene()
