@@ -68,8 +68,8 @@ constexpr float kHopRootMinH = 0x1p-20f;
 // type, so no branch on the type sits inside the loop.  kHopRoot: the roots
 // are taken by sqrt_hop (hop decisions only; the values themselves may differ
 // from the exact ones below 2^-47).
-template <int T, bool kHopRoot = false>
-__device__ __forceinline__ float prim_eval_t(const float* __restrict__ r, float x, float y, float z) {
+template <int T, bool kHopRoot = false, class Ptr = const float*>
+__device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
   auto root = [](float v) { return kHopRoot ? sqrt_hop(v) : sqrtf(v); };
   if constexpr (T == kPrimPlane) {
     return ((r[4] * x + r[5] * y) + r[6] * z) - r[13];
@@ -130,13 +130,18 @@ __device__ __forceinline__ float union_strided(const PrimGroups& g, Rec rec, int
   return f;
 }
 
-// Min-union evaluated by one lane, parameters read through the scalar cache
-// (the record pointer is uniform across the wave).
+// Read-only global memory seen through the constant address space: a load
+// at a wave-uniform address then becomes a scalar load into SGPRs instead of
+// a vector load per lane.  Valid for data no kernel writes while it runs.
+using ConstFloatPtr = const __attribute__((address_space(4))) float*;
+
+// Min-union evaluated by one lane; every lane reads the same record at the
+// same time, so the records come in by scalar loads.
 struct PrimsEval {
   const float* __restrict__ prims;
   PrimGroups groups;
   __device__ __forceinline__ float operator()(float x, float y, float z) const {
-    const float* __restrict__ base = prims;
+    const ConstFloatPtr base = (ConstFloatPtr)prims;
     return union_strided(groups, [base](int p) { return base + p * GH_PRIM_FLOATS; }, 0, 1, x, y, z);
   }
 };
