@@ -10,6 +10,8 @@ Modules
           GPU path's float32 formula operation by operation
   mc      per-cell polygon construction (no lookup table) and enumeration
   hop     grid hopping over the N^2 ray columns, with evaluation counters
+  traced  the paper's per-column procedure taken literally: continuous
+          sphere tracing to the polygonization distance (Algorithm 1)
   mesh    mesh checks: manifoldness, Euler characteristic, area, volume,
           Hausdorff distance
   adjoint analytic FP64 gradient of a vertex loss w.r.t. network parameters,
