@@ -147,7 +147,22 @@ gh_status gh_workspace_size(const gh_grid* grid_h, int64_t corner_cap, size_t* b
 gh_status gh_hop(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
                  int64_t corner_cap, gh_counters* ctr, void* stream);
 
-/* Marching cubes on the cells recorded in ws by gh_hop or gh_dense
+/* The paper's per-column procedure taken literally (Section 3: eq. iter,
+ * eq. polydist and Algorithm 1), for comparison with gh_hop.  From the
+ * centroid of cell k each ray is sphere-traced in +z until |f| <= sqrt(6)/2 h
+ * or its travel reaches 1.05 x the distance to the top face; the cell of the
+ * last centroid at or below the stopping point (never below k) is a
+ * candidate unless it lies past the last cell or the stopping point is above
+ * the overrun height lo + N h/2 + 1.05 N h/2; the ray resumes at the next
+ * cell.  Unlike gh_hop this rule can miss cells that the surface crosses.
+ * Same arguments, workspace contents and counters as gh_hop (n_hop_evals
+ * counts every evaluation of the traces), so gh_mc can follow it.  Analytic
+ * bounds only (GH_EUNSUPPORTED for a network).  GH_FLAG_INTERNAL if a ray
+ * took (N+2)^2 + 64 evaluations, which the rule cannot need. */
+gh_status gh_hop_traced(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
+                        int64_t corner_cap, gh_counters* ctr, void* stream);
+
+/* Marching cubes on the cells recorded in ws by gh_hop, gh_hop_traced or gh_dense
  * (Section 5: every reached cell is polygonized by marching cubes).
  * Evaluates the bound once per distinct corner point, welds one vertex per
  * crossing lattice edge and writes:

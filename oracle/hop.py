@@ -122,6 +122,13 @@ def gridhop(sdb, n, lo, h, precision="f64"):
     candidates; their count is the corner evaluation count.
     """
     cells, hop_evals, col_evals = hop(sdb, n, lo, h, precision)
+    return polygonize_cells(sdb, n, lo, h, cells, hop_evals, col_evals, precision)
+
+
+def polygonize_cells(sdb, n, lo, h, cells, hop_evals, col_evals, precision="f64"):
+    """Marching cubes on the given candidate cells (bound evaluated once per
+    distinct corner point), packaged with the counts of the step that found
+    the cells."""
     pid = corner_points(n, cells)
     n1 = n + 1
     a, b, c = pid // (n1 * n1), (pid // n1) % n1, pid % n1

@@ -40,7 +40,7 @@ uses float32(1 / h) as the hop does.
 """
 import numpy as np
 
-from .hop import centroid_f32, centroid_f64
+from .hop import centroid_f32, centroid_f64, polygonize_cells
 
 
 def _constants(n, lo, h, precision):
@@ -124,3 +124,10 @@ def hop_traced(sdb, n, lo, h, precision="f64", columns=None):
             live = np.setdiff1d(live, finished, assume_unique=True)
     cells = np.sort(np.concatenate(cand)) if cand else np.zeros(0, np.int64)
     return cells, int(evals.sum()), evals
+
+
+def gridhop_traced(sdb, n, lo, h, precision="f64"):
+    """The literal procedure followed by marching cubes on its candidates
+    (the same result form as `hop.gridhop`)."""
+    cells, evals, col_evals = hop_traced(sdb, n, lo, h, precision)
+    return polygonize_cells(sdb, n, lo, h, cells, evals, col_evals, precision)

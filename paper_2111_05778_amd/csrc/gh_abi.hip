@@ -384,6 +384,22 @@ gh_status gh_hop(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, siz
   return hip_status(gh::launch_hop(d, g, w, ctr, gh::current_tuning().hop_lanes_per_ray, s), "hop");
 }
 
+gh_status gh_hop_traced(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
+                        int64_t corner_cap, gh_counters* ctr, void* stream) {
+  gh::DevSdb d;
+  gh::Grid g;
+  gh::Workspace w;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if (d.kind != GH_SDB_PRIMS) return fail(GH_EUNSUPPORTED, "gh_hop_traced takes analytic bounds only");
+  if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
+  if ((st = carve(g, ws, ws_bytes, corner_cap, &w)) != GH_OK) return st;
+  if (!ctr) return fail(GH_EINVAL, "counters are NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearAll, s), "clear")) != GH_OK) return st;
+  return hip_status(gh::launch_hop_traced(d, g, w, ctr, gh::current_tuning().hop_lanes_per_ray, s), "traced hop");
+}
+
 gh_status gh_dense(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
                    uint32_t* signs, gh_counters* ctr, void* stream) {
   gh::DevSdb d;

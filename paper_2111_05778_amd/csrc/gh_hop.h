@@ -278,6 +278,101 @@ __device__ __forceinline__ void hop_window_rays(const float* __restrict__ srec, 
   block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
 }
 
+// ------------------------------------------------------------ traced hop
+// Constants of the paper's per-column procedure taken literally, each
+// computed on the host in double from the float32 grid and rounded once:
+// tau = sqrt(6)/2 h (eq. polydist), the top face z_top = lo + N h, and the
+// overrun height lo + N h / 2 + 1.05 N h / 2 (Algorithm 1's exit test, the
+// unit cube's 1.05/2 generalised).  max_steps bounds one ray's evaluations.
+struct TraceConsts {
+  float tau, z_top, z_exit;
+  int64_t max_steps;
+};
+
+// Algorithm 1 as printed, over one block tile of columns (the same tiles and
+// R-lane groups as hop_prims_tile, records in LDS, exact roots): from the
+// centroid of cell k the ray is sphere-traced (eq. iter) until |f| <= tau or
+// the travel t reaches 1.05 (z_top - z_s); the cell of the last centroid at
+// or below z_s + t (never below k) is a candidate unless it lies past the
+// last cell or z_s + t is above the overrun height, and the ray resumes at
+// the next cell.  Candidates rise strictly along a column, so they go to the
+// same candidate words as the hop's.  The float32 operations are those of
+// the oracle's FP32 twin, one rounding each, in the same order.
+template <int R>
+__device__ __forceinline__ void trace_prims_tile(const float* __restrict__ srec, const PrimGroups& groups,
+                                                 const Grid& g, const TraceConsts tc, uint64_t* __restrict__ colmask,
+                                                 uint32_t* __restrict__ colbits, gh_counters* __restrict__ ctr,
+                                                 int tile) {
+  using S = HopShape<R>;
+  const int n = g.n;
+  const int nbw = (n + S::kBlockW - 1) / S::kBlockW;
+  const int bi = tile / nbw, bj = tile - bi * nbw;
+  const int w = wave_id(), l = lane_id();
+  const int r = l / R, q = l % R;
+  const int i = bi * S::kBlockH + (w >> 1) * S::kWaveH + r / S::kWaveW;
+  const int j = bj * S::kBlockW + (w & 1) * S::kWaveW + r % S::kWaveW;
+  uint64_t evals = 0, cands = 0;
+  bool bad = false, stuck = false;
+  if (r < S::kWaveRays && i < n && j < n) {  // uniform over the R lanes of a ray
+    const size_t ncol = (size_t)n * n, col = (size_t)i * n + j;
+    const float x = centroid(g, i), y = centroid(g, j), z0 = centroid(g, 0);
+    const float nf = (float)n;
+    int k = 0, wi = 0;
+    uint32_t word = 0;
+    uint64_t mask = 0;
+    float zs = z0, t = 0.f, tmax = 1.05f * (tc.z_top - zs);
+    for (int64_t steps = 0;; ++steps) {
+      if (steps >= tc.max_steps) {
+        stuck = true;
+        break;
+      }
+      float f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y, zs + t);
+      f = group_min<R>(f, q);
+      ++evals;
+      const float d = fabsf(f);
+      if (!(d <= FLT_MAX)) {
+        bad = true;
+        break;
+      }
+      const bool near = d <= tc.tau;
+      const float tn = t + d;
+      if (!near) t = tn;
+      if (near || tn >= tmax) {
+        const float z = zs + t;
+        const float kf = floorf((z - z0) * g.inv_h);
+        // max(k, kf), held below n + 1 so that it fits an int
+        const int kk = kf > (float)k ? (kf < nf ? (int)kf : n) : k;
+        if (kk > n - 1 || z > tc.z_exit) break;
+        const int kw = kk >> 5;
+        if (kw != wi) {
+          if (word && q == 0) colbits[(size_t)wi * ncol + col] = word;
+          if (word) mask |= 1ull << wi;
+          word = 0;
+          wi = kw;
+        }
+        word |= 1u << (kk & 31);
+        ++cands;
+        k = kk + 1;
+        zs = centroid(g, k);
+        t = 0.f;
+        tmax = 1.05f * (tc.z_top - zs);
+      }
+    }
+    if (q == 0) {
+      if (word) {
+        colbits[(size_t)wi * ncol + col] = word;
+        mask |= 1ull << wi;
+      }
+      colmask[col] = mask;
+    }
+  }
+  if (q != 0) evals = cands = 0;
+  if (bad && q == 0) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  if (stuck && q == 0) atomicOr(&ctr->flags, GH_FLAG_INTERNAL);
+  block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
+  block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
+}
+
 // Copies the primitive records into LDS (then one barrier).
 __device__ __forceinline__ void stage_prims(float4* s_rec, const float* __restrict__ prims, int np) {
   for (int t = threadIdx.x; t < np * (GH_PRIM_FLOATS / 4); t += kBlock) s_rec[t] = reinterpret_cast<const float4*>(prims)[t];

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 
 #include "gh_device.h"
 #include "gh_launch.h"
@@ -71,6 +72,17 @@ __global__ __launch_bounds__(kBlock) void k_hop_long(const float* __restrict__ p
   stage_prims(s_rec, prims, groups.start[kPrimTypes]);
   hop_window_rays<R, kRegs, kTypes>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, park, *npark,
                                     ctr);
+}
+
+// Algorithm 1 taken literally (see trace_prims_tile).
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_trace_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
+                                                        TraceConsts tc, uint64_t* __restrict__ colmask,
+                                                        uint32_t* __restrict__ colbits,
+                                                        gh_counters* __restrict__ ctr) {
+  __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
+  stage_prims(s_rec, prims, groups.start[kPrimTypes]);
+  trace_prims_tile<R>(reinterpret_cast<const float*>(s_rec), groups, g, tc, colmask, colbits, ctr, blockIdx.x);
 }
 
 // ------------------------------------------------------------ enumeration
@@ -234,6 +246,42 @@ hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_co
     case 3: launch_hop_r<3>(d, g, ws, ctr, s); break;
     case 4: launch_hop_r<4>(d, g, ws, ctr, s); break;
     case 8: launch_hop_r<8>(d, g, ws, ctr, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int R>
+static void launch_trace_r(const DevSdb& d, const Grid& g, const TraceConsts& tc, const Workspace& ws,
+                           gh_counters* ctr, hipStream_t s) {
+  using S = HopShape<R>;
+  const int nbh = (g.n + S::kBlockH - 1) / S::kBlockH, nbw = (g.n + S::kBlockW - 1) / S::kBlockW;
+  hipLaunchKernelGGL(k_trace_prims<R>, dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g, tc, ws.colmask,
+                     ws.colbits, ctr);
+}
+
+hipError_t launch_hop_traced(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr,
+                             int lanes_per_ray, hipStream_t s) {
+  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
+  const double h = g.h, side = (double)g.n * h;
+  TraceConsts tc;
+  tc.tau = (float)(std::sqrt(6.0) / 2.0 * h);
+  tc.z_top = (float)((double)g.lo + side);
+  tc.z_exit = (float)((double)g.lo + side / 2.0 + 1.05 * (side / 2.0));
+  // Every trace advances by more than tau per evaluation and travels at
+  // most 1.05 (N + 1/2) h, so a ray needs fewer than (N + 2)^2 evaluations.
+  tc.max_steps = ((int64_t)g.n + 2) * ((int64_t)g.n + 2) + 64;
+  if (lanes_per_ray <= 0) {
+    int most = 1;
+    for (int t = 0; t < kPrimTypes; ++t) most = std::max(most, d.groups.start[t + 1] - d.groups.start[t]);
+    lanes_per_ray = most <= 4 ? most : 8;
+  }
+  switch (lanes_per_ray) {
+    case 1: launch_trace_r<1>(d, g, tc, ws, ctr, s); break;
+    case 2: launch_trace_r<2>(d, g, tc, ws, ctr, s); break;
+    case 3: launch_trace_r<3>(d, g, tc, ws, ctr, s); break;
+    case 4: launch_trace_r<4>(d, g, tc, ws, ctr, s); break;
+    case 8: launch_trace_r<8>(d, g, tc, ws, ctr, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

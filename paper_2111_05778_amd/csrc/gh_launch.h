@@ -66,6 +66,10 @@ hipError_t launch_clear(const Workspace& ws, gh_counters* ctr, ClearMode mode, h
 // lanes_per_ray: 1, 2, 3, 4 or 8 lanes trace one ray together (0 = chosen from the type groups).
 hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, int lanes_per_ray,
                       hipStream_t s);
+// Algorithm 1 taken literally (analytic bounds): candidates into the same
+// workspace words as launch_hop.
+hipError_t launch_hop_traced(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr,
+                             int lanes_per_ray, hipStream_t s);
 hipError_t launch_dense(const DevSdb& d, const Grid& g, const Workspace& ws, uint32_t* signs, gh_counters* ctr,
                         hipStream_t s);
 hipError_t launch_candidates(const Grid& g, const Workspace& ws, int64_t* out, int64_t cap, gh_counters* ctr,

@@ -21,7 +21,7 @@ GH_SDB_PRIMS, GH_SDB_MLP = 1, 2
 GH_PREC_FP32, GH_PREC_BF16, GH_PREC_BF16X3 = 0, 1, 2
 GH_PRIM_FLOATS = 16
 
-EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
+EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_hop_traced", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
            "gh_eval_points", "gh_set_tuning", "gh_get_tuning", "gh_param_count", "gh_backward_workspace_size",
            "gh_backward", "gh_batch_buffer_size", "gh_batch_create", "gh_batch_run", "gh_batch_capture",
            "gh_batch_replay", "gh_batch_item_count", "gh_batch_destroy", "gh_last_error"]
@@ -79,6 +79,7 @@ _P = ctypes.POINTER
 lib.sdb_describe.argtypes = [_P(gh_sdb_spec), _vp, _sz, _P(_sz), _P(gh_sdb_desc), _vp]
 lib.gh_workspace_size.argtypes = [_P(gh_grid), _i64, _P(_sz)]
 lib.gh_hop.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp]
+lib.gh_hop_traced.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp]
 lib.gh_mc.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64,
                       _vp, _vp]
 lib.gh_dense.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp]
@@ -145,6 +146,11 @@ def gh_workspace_size(grid, corner_cap=0):
 def gh_hop(desc, grid, ws, corner_cap, ctr, stream=None):
     return lib.gh_hop(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
                       int(corner_cap), ptr(ctr), stream_handle(stream))
+
+
+def gh_hop_traced(desc, grid, ws, corner_cap, ctr, stream=None):
+    return lib.gh_hop_traced(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
+                             int(corner_cap), ptr(ctr), stream_handle(stream))
 
 
 def gh_dense(desc, grid, ws, corner_cap, signs, ctr, stream=None):

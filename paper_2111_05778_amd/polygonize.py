@@ -158,6 +158,13 @@ class Polygonizer:
         self._apply_tuning()
         N.check(N.gh_hop(self.bound.desc, self.grid, self.ws, self.corner_cap, self.ctr, stream), "gh_hop")
 
+    def enqueue_hop_traced(self, stream=None):
+        """The paper's per-column procedure taken literally (gh_hop_traced);
+        analytic bounds only."""
+        self._apply_tuning()
+        N.check(N.gh_hop_traced(self.bound.desc, self.grid, self.ws, self.corner_cap, self.ctr, stream),
+                "gh_hop_traced")
+
     def enqueue_dense(self, stream=None):
         self._apply_tuning()
         if self.dense_buf is None:
@@ -190,14 +197,17 @@ class Polygonizer:
         self._graph.replay()
 
     # ------------------------------------------------------------ blocking
-    def run(self, dense=False, stream=None, max_retries=3):
+    def run(self, dense=False, stream=None, max_retries=3, traced=False):
+        """Cells by grid hopping (or enumeration with dense, or the literal
+        traced procedure with traced), then marching cubes; blocks."""
+        first = self.enqueue_dense if dense else (self.enqueue_hop_traced if traced else self.enqueue_hop)
         for _ in range(max_retries + 1):
-            (self.enqueue_dense if dense else self.enqueue_hop)(stream)
+            first(stream)
             self.enqueue_mc(stream)
             torch.cuda.synchronize(self.device)
             c = counters_dict(self.ctr)
             if c["flags"] & N.GH_FLAG_INTERNAL:
-                raise RuntimeError("gh_mc found inconsistent workspace contents")
+                raise RuntimeError("inconsistent workspace contents or an unbounded trace (library bug)")
             if c["flags"] & N.GH_FLAG_NONFINITE:
                 raise FloatingPointError("the bound returned a non-finite value")
             if not c["flags"] & N.GH_FLAG_CAPACITY:
