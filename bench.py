@@ -20,6 +20,10 @@ Prints one JSON line.  Extra objects:
                 same network at N = 256, FP32 forward (milliseconds)
   batch         64 bounds on grids of 64..512, one persistent hop launch plus
                 marching cubes per shape, replayed from a hipGraph
+  traced        the paper's per-column procedure taken literally
+                (gh_hop_traced: sphere tracing to sqrt(6)/2 h) on the headline
+                workload, with marching cubes on its candidates, its counts,
+                and the number of sign-change cells it leaves out
 """
 import argparse
 import hashlib
@@ -239,6 +243,30 @@ def batch_section(dev, steps, warmup, precision="bf16x3", tune=True):
             "n_tri": sum(c["n_tri"] for c in ref)}
 
 
+def traced_section(dev, steps, warmup, recs, n, lo, h, seed):
+    """The paper's per-column procedure taken literally (gh_hop_traced) on
+    the headline workload: its times and counts beside grid hopping's, and
+    the audit of sign-change cells it leaves out."""
+    import torch
+    from paper_2111_05778_amd.polygonize import Bound, Polygonizer, counters_dict
+    poly = Polygonizer(Bound.prims(recs, dev), n, lo, h, device=dev, keep_cells=True)
+    sign_cells = poly.run().cells.clone()          # grid hopping finds every sign-change cell
+    poly.run(traced=True)                          # sizes the buffers for the traced candidates
+    for _ in range(warmup):
+        poly.enqueue_hop_traced()
+        poly.enqueue_mc()
+    stream = torch.cuda.current_stream(dev)
+    hop_ms = event_ms(stream, poly.enqueue_hop_traced, steps)
+    mc_ms = event_ms(stream, poly.enqueue_mc, steps)
+    c = counters_dict(poly.ctr)
+    assert c["flags"] == 0
+    cand = poly.candidates()
+    missed = int((~torch.isin(sign_cells, cand)).sum().item())
+    return {"workload": f"csg12_seed{seed}_n{n}", "hop_ms": hop_ms, "mc_ms": mc_ms, "ms_per_step": hop_ms + mc_ms,
+            "counters": {k: c[k] for k in ("n_hop_evals", "n_cand", "n_corner", "n_cells", "n_vert", "n_tri")},
+            "sign_change_cells": int(sign_cells.numel()), "missed_sign_change_cells": missed}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,7 +281,7 @@ def main():
                          "that scales the HBM counters) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (built-in shapes)")
-    ap.add_argument("--sections", default="neural,backward,batch",
+    ap.add_argument("--sections", default="neural,backward,batch,traced",
                     help="extra workloads to measure after the headline one (comma list, or none)")
     args = ap.parse_args()
     sections = [x for x in args.sections.split(",") if x and x != "none"]
@@ -379,6 +407,8 @@ def main():
         out["backward_ms"] = out["backward"]["backward_ms"]
     if "batch" in sections:
         out["batch"] = batch_section(dev, max(3, args.steps // 4), sw, tune=not args.no_tune)
+    if "traced" in sections:
+        out["traced"] = traced_section(dev, max(3, args.steps // 4), sw, recs, n, lo, h, args.seed)
     print(json.dumps(out), flush=True)
 
 
