@@ -94,6 +94,10 @@ enum { GH_SDB_PRIMS = 1, GH_SDB_MLP = 2 };
  * lattice signs) is re-evaluated in FP32 when it lies within bf16_margin of
  * changing, so schedules and signs are the FP32 ones (n_reeval counts). */
 enum { GH_PREC_FP32 = 0, GH_PREC_BF16 = 1, GH_PREC_BF16X3 = 2 };
+/* Activation of the hidden layers: softplus (the default, smooth) or ReLU
+ * max(z, 0), the paper's choice (Section 5.2; batch normalisation folds into
+ * the weights and biases at inference). */
+enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
 
 /* Primitive record: 16 float32 values.
  *  [0] type: 0 sphere, 1 box (exact), 2 torus, 3 capsule, 4 plane,
@@ -111,7 +115,7 @@ typedef struct {
   const float* prims_h;          /* n_prim * GH_PRIM_FLOATS, host */
   /* GH_SDB_MLP (eq. nnsdb): f = a_s (||p|| - r0) + a_n NN(gamma(p)) + b,
    * gamma(p) = [p, for each k: sin(w_k p_x,y,z), cos(w_k p_x,y,z)],
-   * NN = W_D ... softplus(W_1 gamma + b_1) ... + b_D, D = depth + 1 layers. */
+   * NN = W_D ... act(W_1 gamma + b_1) ... + b_D, D = depth + 1 layers. */
   int32_t n_freq;                /* 0 .. 16 */
   int32_t width;                 /* 64, 128 or 256 */
   int32_t depth;                 /* hidden layers, 1 .. 8 */
@@ -121,6 +125,7 @@ typedef struct {
   const float* const* biases_h;  /* depth+1 host arrays of fan_out */
   float a_s, r0, a_n, b;
   float bf16_margin;             /* eps >= max |f_bf16 - f_fp32| (bf16 modes) */
+  int32_t activation;            /* GH_ACT_SOFTPLUS (0) or GH_ACT_RELU; gh_backward takes softplus only */
 } gh_sdb_spec;
 
 /* Opaque, caller-owned, plain-old-data handle filled by sdb_describe.  It

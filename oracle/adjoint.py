@@ -81,7 +81,7 @@ def mlp_vjp(net, P, gout):
         grads[2 * l] = g.T @ acts[l]                          # dW_l = g^T a_l
         grads[2 * l + 1] = g.sum(axis=0)
         if l > 0:
-            g = (g @ Ws[l]) * sdb.sigmoid(pres[l - 1])        # through softplus
+            g = (g @ Ws[l]) * sdb.activation_grad_f64(net, pres[l - 1])  # through the activation
     return np.concatenate([x.ravel() for x in grads])
 
 

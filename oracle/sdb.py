@@ -132,6 +132,16 @@ def sigmoid(x):
     return 0.5 * (1.0 + np.tanh(0.5 * x))
 
 
+def activation_f64(net, z):
+    """The hidden layers' activation: softplus (default) or ReLU max(z, 0)."""
+    return np.maximum(z, 0.0) if net.get("activation", "softplus") == "relu" else softplus(z)
+
+
+def activation_grad_f64(net, z):
+    """Its derivative: sigmoid for softplus, the step [z > 0] for ReLU."""
+    return (z > 0).astype(np.float64) if net.get("activation", "softplus") == "relu" else sigmoid(z)
+
+
 def mlp_forward_f64(net, P, keep=False):
     """Raw network output NN(gamma(p)) in FP64 (eq. nnsdb); optionally the
     pre-activations and activations of every layer."""
@@ -141,7 +151,7 @@ def mlp_forward_f64(net, P, keep=False):
     for l in range(len(Ws)):
         z = a @ np.asarray(Ws[l], dtype=np.float64).T + np.asarray(bs[l], dtype=np.float64)
         pres.append(z)
-        a = softplus(z) if l < len(Ws) - 1 else z
+        a = activation_f64(net, z) if l < len(Ws) - 1 else z
         acts.append(a)
     out = a[:, 0]
     return (out, pres, acts) if keep else out
@@ -156,7 +166,7 @@ def mlp_input_grad_f64(net, P):
     for l in range(len(Ws) - 1, -1, -1):
         g = g @ Ws[l]                      # d out / d a_{l}
         if l > 0:
-            g = g * sigmoid(pres[l - 1])   # softplus' = sigmoid
+            g = g * activation_grad_f64(net, pres[l - 1])
     # g = d out / d gamma; chain into p
     grad = g[:, 0:3].copy()
     for kk, w in enumerate(np.asarray(net["omegas"], dtype=np.float64)):

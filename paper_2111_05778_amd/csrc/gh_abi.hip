@@ -98,6 +98,8 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   for (float v : scal)
     if (!finite_bounded(v, 1e6f)) return fail(GH_EINVAL, "network scalar not finite or above 1e6");
   if (sp->bf16_margin < 0.f) return fail(GH_EINVAL, "bf16_margin must be >= 0");
+  if (!(sp->activation == GH_ACT_SOFTPLUS || sp->activation == GH_ACT_RELU))
+    return fail(GH_EINVAL, "activation %d unknown", sp->activation);
   const int k1 = 3 + 6 * F;
   for (int l = 0; l <= D; ++l) {
     const int fi = l == 0 ? k1 : W, fo = l == D ? 1 : W;
@@ -217,6 +219,7 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.b = sp->b;
   m.b_out = sp->biases_h[D][0];
   m.eps = sp->bf16_margin;
+  m.relu = sp->activation == GH_ACT_RELU ? 1 : 0;
   m.split = 3;
   memset(desc_h, 0, sizeof(*desc_h));
   memcpy(desc_h, &d, sizeof(d));
@@ -494,6 +497,7 @@ gh_status gh_backward(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws
   gh_status st;
   if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
   if (d.kind != GH_SDB_MLP) return fail(GH_EUNSUPPORTED, "the adjoint exists for network bounds only");
+  if (d.mlp.relu) return fail(GH_EUNSUPPORTED, "the adjoint takes softplus networks only");
   if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
   if ((st = carve(g, ws, ws_bytes, corner_cap, &w)) != GH_OK) return st;
   if (!dL_dverts || !dL_dtheta || !ctr || !bws) return fail(GH_EINVAL, "NULL buffer");

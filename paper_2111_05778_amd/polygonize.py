@@ -42,7 +42,8 @@ class Bound:
         """Neural bound f = a_s (||p|| - r0) + a_n NN(gamma(p)) + b.
 
         net: dict with "omegas" (F), "weights" (depth+1 arrays, fan_out x
-        fan_in), "biases", and the scalars "a_s", "r0", "a_n", "b".
+        fan_in), "biases", the scalars "a_s", "r0", "a_n", "b", and
+        optionally "activation" ("softplus", the default, or "relu").
         margin: eps >= |f_bf16 - f_fp32| for the bf16 hop test."""
         ws = [np.ascontiguousarray(np.asarray(w, dtype=np.float32)) for w in net["weights"]]
         bs = [np.ascontiguousarray(np.asarray(b, dtype=np.float32)) for b in net["biases"]]
@@ -56,6 +57,7 @@ class Bound:
         spec.width = ws[0].shape[0]
         spec.depth = len(ws) - 1
         spec.precision = {"fp32": N.GH_PREC_FP32, "bf16": N.GH_PREC_BF16, "bf16x3": N.GH_PREC_BF16X3}[precision]
+        spec.activation = {"softplus": N.GH_ACT_SOFTPLUS, "relu": N.GH_ACT_RELU}[net.get("activation", "softplus")]
         spec.omegas_h = om.ctypes.data_as(fp)
         spec.weights_h = wptr
         spec.biases_h = bptr

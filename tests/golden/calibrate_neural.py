@@ -15,22 +15,23 @@ from oracle.sdb import calibrate_network  # noqa: E402
 
 
 def networks():
-    """(seed, width, depth, n_freq) of every network the workloads use."""
-    nets = [(0, 256, 4, 16), (0, 64, 4, 16), (0, 128, 4, 16)]
+    """(seed, width, depth, n_freq, activation) of every network the workloads use."""
+    nets = [(0, 256, 4, 16, "softplus"), (0, 64, 4, 16, "softplus"), (0, 128, 4, 16, "softplus"),
+            (0, 64, 8, 0, "relu")]
     for s in W.batch_scenes():
         if s["kind"] == "mlp":
-            nets.append((s["seed"], s["width"], 4, 16))
+            nets.append((s["seed"], s["width"], 4, 16, "softplus"))
     return sorted(set(nets))
 
 
 def main():
     probe = W.probe_points()
     out = {}
-    for (seed, width, depth, nf) in networks():
-        net = W.mlp_net(seed, width, depth, nf)
+    for (seed, width, depth, nf, act) in networks():
+        net = W.mlp_net(seed, width, depth, nf, act)
         c = calibrate_network(net, probe, W.NEURAL_AMPLITUDE, W.NEURAL_R0)
-        out[f"seed{seed}_w{width}_d{depth}_f{nf}"] = c
-        print(seed, width, c, flush=True)
+        out[W.calibration_key(seed, width, depth, nf, act)] = c
+        print(seed, width, depth, nf, act, c, flush=True)
     with open(W.neural_calibration_path(), "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
 

@@ -1,0 +1,94 @@
+"""The paper's network shape on the GPU (Section 5.2: eight ReLU layers of
+width 64 on the raw coordinates; random weights under the sphere prior and
+calibration of the other neural workloads), through the C ABI, against the
+FP64 oracle: FP32 values, the bf16 certification taking exactly the FP32
+schedule and signs, and meshes against the oracle's."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hop as ohop
+from oracle import mesh as omesh
+from oracle import sdb as osdb
+
+from test_gpu_mlp import _closed_oriented, _points, _run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gh():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_05778_amd import native, polygonize
+    return native, polygonize
+
+
+@pytest.fixture(scope="module")
+def net():
+    return W.paper_net_scene()
+
+
+def test_fp32_and_bf16_values(gh, net):
+    import torch
+    native, P = gh
+    pts = _points()
+    ref = osdb.neural_f64(net, pts.astype(np.float64))
+    errs = {}
+    for prec in ("fp32", "bf16", "bf16x3"):
+        f = P.Bound.mlp(net, prec).eval(torch.from_numpy(pts).cuda()).cpu().numpy().astype(np.float64)
+        errs[prec] = np.abs(f - ref).max()
+    print("max |f - f64|: " + ", ".join(f"{k} {v:.3e}" for k, v in errs.items()), flush=True)
+    assert errs["fp32"] < 2e-5 and errs["bf16x3"] < 1e-4 and errs["bf16"] < 2e-2
+
+
+@pytest.mark.parametrize("prec,n", [("bf16", 64), ("bf16x3", 77), ("bf16x3", 128)])
+def test_bf16_takes_the_fp32_schedule_and_signs(gh, net, prec, n):
+    native, P = gh
+    margin = P.bf16_margin(net, W.probe_points(seed=3, n=65536), prec)
+    g = W.grid(n)
+    a = _run(gh, P.Bound.mlp(net, "fp32"), *g)
+    b = _run(gh, P.Bound.mlp(net, prec, margin=margin), *g)
+    print(f"{prec} n {n}: margin {margin:.2e}, evals {b['ctr']['n_hop_evals']}, re-evaluated {b['ctr']['n_reeval']}",
+          flush=True)
+    np.testing.assert_array_equal(a["cand"], b["cand"])
+    assert a["ctr"]["n_hop_evals"] == b["ctr"]["n_hop_evals"]
+    for key in ("cells", "cases", "edge", "tri_e"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_fp32_mesh_matches_fp64_oracle(gh, net):
+    native, P = gh
+    n, lo, h = W.grid(64)
+    out = _run(gh, P.Bound.mlp(net, "fp32"), n, lo, h)
+    ref = ohop.gridhop(osdb.SDB.neural(net), n, lo, h)
+    diff = np.setxor1d(out["cells"], ref.mesh.cells)
+    print(f"cells gpu {len(out['cells'])} oracle {len(ref.mesh.cells)}, differing {len(diff)}", flush=True)
+    assert len(diff) <= max(2, len(ref.mesh.cells) // 1000)
+    assert abs(out["ctr"]["n_hop_evals"] - ref.hop_evals) <= 1e-3 * ref.hop_evals
+
+
+def test_bf16x3_mesh_within_half_cell_of_fp64(gh, net):
+    native, P = gh
+    n, lo, h = W.grid(64)
+    margin = P.bf16_margin(net, W.probe_points(seed=3, n=65536), "bf16x3")
+    out = _run(gh, P.Bound.mlp(net, "bf16x3", margin=margin), n, lo, h)
+    ref = ohop.gridhop(osdb.SDB.neural(net), n, lo, h).mesh
+    T = np.searchsorted(out["edge"], out["tri_e"])
+    hd = omesh.hausdorff(out["verts"], T, ref.positions(), ref.tri_vertex_index())
+    print(f"Hausdorff {hd:.3e} = {hd / float(h):.4f} h", flush=True)
+    assert hd <= 0.5 * float(h)
+    assert _closed_oriented(T)
+
+
+def test_adjoint_refuses_relu(gh, net):
+    import torch
+    native, P = gh
+    from paper_2111_05778_amd.autograd import GridHopMesh, flatten
+    n, lo, h = W.grid(16)
+    theta = torch.tensor(flatten(net), device="cuda", requires_grad=True)
+    with pytest.raises(native.GhError) as e:
+        V = GridHopMesh.apply(theta, net, n, float(lo), float(h), "fp32", 0.0)
+        V.sum().backward()
+    assert e.value.status == native.GH_EUNSUPPORTED

@@ -177,3 +177,30 @@ def test_literal_reading_has_no_surface():
     P = np.random.default_rng(0).uniform(-1, 1, (4000, 3))
     f = sdb.mlp_forward_f64(net, P) / S - 0.2
     assert f.max() < 0
+
+
+def test_relu_network_closed_form():
+    # A ReLU layer whose units are +-p_x, +-p_y, +-p_z summed by the output
+    # layer is the L1 norm |x| + |y| + |z|, with gradient sign(p) (the
+    # activation of the paper's networks, Section 5.2).
+    W1 = np.zeros((8, 3), np.float32)
+    for u, (axis, sign) in enumerate([(0, 1), (0, -1), (1, 1), (1, -1), (2, 1), (2, -1)]):
+        W1[u, axis] = sign
+    W2 = np.array([[1, 1, 1, 1, 1, 1, 0, 0]], np.float32)
+    net = {"omegas": np.zeros(0, np.float32), "weights": [W1, W2],
+           "biases": [np.zeros(8, np.float32), np.zeros(1, np.float32)], "activation": "relu"}
+    P = np.random.default_rng(4).uniform(-1, 1, (1000, 3))
+    np.testing.assert_allclose(sdb.mlp_forward_f64(net, P), np.abs(P).sum(axis=1), rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(sdb.mlp_input_grad_f64(net, P), np.sign(P))
+    # the same weights under softplus are not piecewise linear
+    soft = dict(net, activation="softplus")
+    assert np.abs(sdb.mlp_forward_f64(soft, P) - np.abs(P).sum(axis=1)).min() > 1.0
+
+
+def test_paper_network_shape():
+    # eight ReLU layers of width 64 on the raw coordinates: about 30,000
+    # weights (Section 5.2)
+    net = W.paper_net_scene()
+    assert net["activation"] == "relu" and len(net["omegas"]) == 0
+    assert [w.shape for w in net["weights"]] == [(64, 3)] + [(64, 64)] * 7 + [(1, 64)]
+    assert sum(w.size for w in net["weights"]) == 28928

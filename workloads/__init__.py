@@ -121,22 +121,33 @@ def fourier_omegas(n_freq=16):
     return (2.0 ** (np.arange(n_freq) / 4.0)).astype(np.float32)
 
 
-def mlp_net(seed=0, width=256, depth=4, n_freq=16):
-    """Random-weight MLP  gamma(p) -> depth x [width, softplus] -> 1.
+def mlp_net(seed=0, width=256, depth=4, n_freq=16, activation="softplus"):
+    """Random-weight MLP  gamma(p) -> depth x [width, activation] -> 1.
 
     gamma(p) = [p_x, p_y, p_z, then for each k: sin(w_k p_x), sin(w_k p_y),
     sin(w_k p_z), cos(w_k p_x), cos(w_k p_y), cos(w_k p_z)], 3 + 6 n_freq
-    features.  Weights W_l (fan_out x fan_in) ~ N(0, 1/fan_in), drawn in layer
-    order from default_rng(seed); biases zero.  All float32.
+    features.  softplus: weights W_l (fan_out x fan_in) ~ N(0, 1/fan_in),
+    drawn in layer order from default_rng(seed); biases zero.  relu (the
+    paper's architecture, Section 5.2: ReLU layers with batch normalisation,
+    which folds into each layer's weights and bias at inference): weights
+    ~ N(0, 2/fan_in) drawn in layer order, then the hidden layers' biases
+    ~ N(0, 0.1^2) in layer order; the output bias is zero.  All float32.
     """
+    if activation not in ("softplus", "relu"):
+        raise ValueError(f"unknown activation {activation!r}")
     rng = np.random.default_rng(seed)
     dims = [3 + 6 * n_freq] + [width] * depth + [1]
     weights, biases = [], []
     for l in range(len(dims) - 1):
         fan_in, fan_out = dims[l], dims[l + 1]
-        weights.append((rng.standard_normal((fan_out, fan_in)) / np.sqrt(fan_in)).astype(np.float32))
+        z = rng.standard_normal((fan_out, fan_in))
+        w = z * np.sqrt(2.0 / fan_in) if activation == "relu" else z / np.sqrt(fan_in)
+        weights.append(w.astype(np.float32))
         biases.append(np.zeros(fan_out, dtype=np.float32))
-    return {"omegas": fourier_omegas(n_freq), "weights": weights, "biases": biases}
+    if activation == "relu":
+        for l in range(len(dims) - 2):
+            biases[l] = (0.1 * rng.standard_normal(dims[l + 1])).astype(np.float32)
+    return {"omegas": fourier_omegas(n_freq), "weights": weights, "biases": biases, "activation": activation}
 
 
 def probe_points(seed=3, n=65536):
@@ -159,7 +170,11 @@ def neural_calibration_path():
     return os.path.join(_HERE, "neural_calibration.json")
 
 
-def neural_scene(seed=0, width=256, depth=4, n_freq=16):
+def calibration_key(seed, width, depth, n_freq, activation="softplus"):
+    return f"seed{seed}_w{width}_d{depth}_f{n_freq}" + ("" if activation == "softplus" else f"_{activation}")
+
+
+def neural_scene(seed=0, width=256, depth=4, n_freq=16, activation="softplus"):
     """Neural bound  f(p) = a_s (||p|| - r0) + a_n NN(gamma(p)) + b.
 
     The coefficients come from a stored calibration of this exact network
@@ -169,8 +184,8 @@ def neural_scene(seed=0, width=256, depth=4, n_freq=16):
     over probe_points() and L the largest |grad g| there.  Hence
     a_s = 1/(lambda L), a_n = A/(sigma_u S lambda L), b = -A mu_u/(sigma_u lambda L).
     """
-    net = mlp_net(seed, width, depth, n_freq)
-    key = f"seed{seed}_w{width}_d{depth}_f{n_freq}"
+    net = mlp_net(seed, width, depth, n_freq, activation)
+    key = calibration_key(seed, width, depth, n_freq, activation)
     with open(neural_calibration_path()) as fh:
         cal = json.load(fh)
     if key not in cal:
@@ -183,6 +198,13 @@ def neural_scene(seed=0, width=256, depth=4, n_freq=16):
     net["b"] = np.float32(-NEURAL_AMPLITUDE * c["mu_u"] / (c["sigma_u"] * lam_l))
     net["calibration"] = c
     return net
+
+
+def paper_net_scene(seed=0):
+    """The paper's network shape (Section 5.2): eight ReLU layers of width 64
+    on the raw coordinates (no Fourier features), random weights, under the
+    same sphere prior and calibration as neural_scene: 28,928 weights."""
+    return neural_scene(seed, 64, 8, 0, "relu")
 
 
 # -------------------------------------------------------------------------- batch
