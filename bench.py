@@ -16,6 +16,9 @@ Prints one JSON line.  Extra objects:
   neural        the network bound (width 256, depth 4, 16 frequencies) at
                 N = 512 in split bf16 on MFMA, with its own MFMA roofline
                 and the enumeration path beside it
+  paper_net     the same for the paper's network shape (eight ReLU layers of
+                width 64 on raw coordinates, random weights): the
+                small-width MFMA regime
   backward      the adjoint of the mean squared vertex-to-target loss for the
                 same network at N = 256, FP32 forward (milliseconds)
   batch         64 bounds on grids of 64..512, one persistent hop launch plus
@@ -127,12 +130,20 @@ def event_ms(stream, fn, reps):
     return sum(a.elapsed_time(b) for a, b in ev) / reps
 
 
-def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", dense=True, tune=True):
+def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", dense=True, tune=True, paper=False):
+    """The network bound at N = 512: the calibrated random network of width
+    256 (softplus, 16 frequencies), or with paper=True the paper's shape
+    (eight ReLU layers of width 64 on raw coordinates)."""
     import torch
 
     import workloads as W
     from paper_2111_05778_amd.polygonize import Bound, Polygonizer, bf16_margin
-    net = W.neural_scene(0, width)
+    if paper:
+        net, width, depth, n_freq = W.paper_net_scene(), 64, 8, 0
+        workload = f"mlp_w64_d8_f0_relu_seed0_n{n}"
+    else:
+        net, depth, n_freq = W.neural_scene(0, width), 4, 16
+        workload = f"mlp_w{width}_d4_f16_seed0_n{n}"
     n, lo, h = W.grid(n)
     margin = bf16_margin(net, W.probe_points(seed=3, n=65536), precision) if precision != "fp32" else 0.0
     poly = Polygonizer(Bound.mlp(net, precision, margin=margin, device=dev), n, lo, h, device=dev, keep_cells=False)
@@ -148,14 +159,15 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", den
         poly.enqueue_mc()
     hop_ms = event_ms(stream, poly.enqueue_hop, steps)
     mc_ms = event_ms(stream, poly.enqueue_mc, steps)
-    fpp = mlp_flop_per_point(width, 4, 16)
+    fpp = mlp_flop_per_point(width, depth, n_freq)
     flop = c0["n_hop_evals"] * fpp
-    out = {"workload": f"mlp_w{width}_d4_f16_seed0_n{n}", "precision": precision, "margin": margin, "tuning": tuning,
+    out = {"workload": workload, "precision": precision, "margin": margin, "tuning": tuning,
            "value": n ** 3 / ((hop_ms + mc_ms) * 1e-3), "unit": "cells/s", "hop_ms": hop_ms, "mc_ms": mc_ms,
            "counters": {k: c0[k] for k in ("n_hop_evals", "n_reeval", "n_corner", "n_vert", "n_tri")},
            "roofline": {"bound": "mfma", "kernel": "k_hop_mlp", "achieved": flop / (hop_ms * 1e-3) / 1e12,
                         "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
-                        "frac": flop / (hop_ms * 1e-3) / PEAK_BF16_MFMA, "traffic": load_traffic("k_hop_mlp"),
+                        "frac": flop / (hop_ms * 1e-3) / PEAK_BF16_MFMA,
+                        "traffic": None if paper else load_traffic("k_hop_mlp"),
                         "flop_per_point": fpp, "per_launch_flop": flop}}
     if dense:
         poly.enqueue_dense()
@@ -281,7 +293,7 @@ def main():
                          "that scales the HBM counters) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (built-in shapes)")
-    ap.add_argument("--sections", default="neural,backward,batch,traced",
+    ap.add_argument("--sections", default="neural,paper_net,backward,batch,traced",
                     help="extra workloads to measure after the headline one (comma list, or none)")
     args = ap.parse_args()
     sections = [x for x in args.sections.split(",") if x and x != "none"]
@@ -402,6 +414,9 @@ def main():
     sw = max(1, args.warmup)
     if "neural" in sections:
         out["neural"] = neural_section(dev, max(3, args.steps // 4), sw, dense=not args.no_dense, tune=not args.no_tune)
+    if "paper_net" in sections:
+        out["paper_net"] = neural_section(dev, max(3, args.steps // 4), sw, dense=not args.no_dense,
+                                          tune=not args.no_tune, paper=True)
     if "backward" in sections:
         out["backward"] = backward_section(dev, max(3, args.steps // 4), sw)
         out["backward_ms"] = out["backward"]["backward_ms"]
