@@ -220,6 +220,8 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.b_out = sp->biases_h[D][0];
   m.eps = sp->bf16_margin;
   m.relu = sp->activation == GH_ACT_RELU ? 1 : 0;
+  m.act_ln2 = m.relu ? 0.f : 0.693147180559945309f;
+  m.act_one = m.relu ? 0.f : 1.f;
   m.split = 3;
   memset(desc_h, 0, sizeof(*desc_h));
   memcpy(desc_h, &d, sizeof(d));

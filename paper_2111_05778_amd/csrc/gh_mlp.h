@@ -60,6 +60,7 @@ struct MlpDesc {
   int F, W, depth, k1;  // k1 = 3 + 6F features
   int precision;
   int relu;             // hidden activation: 0 softplus, 1 ReLU max(z, 0)
+  float act_ln2, act_one;  // ln 2 and 1 for softplus, 0 and 0 for ReLU (act_hw, act_f32)
   int split;            // tiles with few rows: 1 never split, 2 split <= 32 rows, 3 also <= 64 rows
   float a_s, r0, a_n, b, b_out;
   float eps;            // |f_bf16 - f_fp32| bound used by the hop test
@@ -115,20 +116,20 @@ struct MlpSmemF32 {
 // functions (FP32 evaluator).
 __device__ __forceinline__ float softplus_f32(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
 
-// The same with the hardware base-2 exponential and logarithm (about 1 ulp
-// each): absolute error near 2e-7, far below the bf16 roundings that follow.
-__device__ __forceinline__ float softplus_hw(float z) {
+// Hidden-layer activation of the bf16 evaluators, max(z, 0) + c log2(1 +
+// 2^(-|z| log2 e)) with the hardware base-2 exponential and logarithm (about
+// 1 ulp each: absolute error near 2e-7, far below the bf16 roundings that
+// follow): softplus for c = ln 2, ReLU for c = 0 (the log term is finite, so
+// c = 0 leaves max(z, 0) exactly).  One instruction stream for both: a
+// branch on the activation here measurably slowed the softplus networks.
+__device__ __forceinline__ float act_hw(float z, float c) {
   const float e = __builtin_amdgcn_exp2f(-fabsf(z) * 1.44269504088896341f);
-  return fmaf(__builtin_amdgcn_logf(1.f + e), 0.693147180559945309f, fmaxf(z, 0.f));
+  return fmaf(__builtin_amdgcn_logf(1.f + e), c, fmaxf(z, 0.f));
 }
 
-// Hidden-layer activation of the bf16 evaluators: ReLU max(z, 0) or the
-// hardware softplus.
-template <bool kRelu>
-__device__ __forceinline__ float act_hw(float z) {
-  if constexpr (kRelu) return fmaxf(z, 0.f);
-  else return softplus_hw(z);
-}
+// The same for the FP32 evaluator: max(z, 0) + c log(1 + e^-|z|), softplus
+// for c = 1 (1 x is exact), ReLU for c = 0.
+__device__ __forceinline__ float act_f32(float z, float c) { return fmaxf(z, 0.f) + c * log1pf(expf(-fabsf(z))); }
 
 // Final value from NN (both evaluators).
 __device__ __forceinline__ float mlp_value(const MlpDesc& m, float x, float y, float z, float nn) {
@@ -228,7 +229,7 @@ __device__ __forceinline__ void mlp_layer_f32(const MlpDesc& m, Sm& sm, int l, i
         const int row = (rt0 + rt) * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
         const float z = acc[rt][ct][t] + bv;
         if (zout) zout[row * W + col] = z;
-        sm.af[row * kF32Stride + col] = m.relu ? fmaxf(z, 0.f) : softplus_f32(z);
+        sm.af[row * kF32Stride + col] = act_f32(z, m.act_one);
       }
     }
   }
@@ -300,9 +301,9 @@ __device__ __forceinline__ f32x16_t mfma_step(const bf16x8_t& a, const bf16x8_t&
 // next tile are loaded while a tile is processed, and a scheduling barrier
 // per tile keeps the compiler from hoisting every load of the layer (which
 // would cost registers instead of latency).
-template <int P, int W, int NT, bool kLast, bool kRelu>
-__device__ __forceinline__ float mlp_epilogue_act(const MlpDesc& m, int l, int c0, f32x16_t (&acc)[NT],
-                                                  bf16x8_t (&x)[2 * NT], bf16x8_t (&xl)[2 * NT]) {
+template <int P, int W, int NT, bool kLast>
+__device__ __forceinline__ float mlp_epilogue(const MlpDesc& m, int l, int c0, f32x16_t (&acc)[NT],
+                                              bf16x8_t (&x)[2 * NT], bf16x8_t (&xl)[2 * NT]) {
   const int h = (threadIdx.x >> 5) & 1;
   const float4* __restrict__ bias4 = reinterpret_cast<const float4*>(m.bias + (size_t)l * W) + h;
   const float4* __restrict__ wout4 = reinterpret_cast<const float4*>(m.wout) + h;
@@ -319,10 +320,10 @@ __device__ __forceinline__ float mlp_epilogue_act(const MlpDesc& m, int l, int c
     float dot = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      a[4 * j + 0] = act_hw<kRelu>(acc[c][4 * j + 0] + bv[j].x);
-      a[4 * j + 1] = act_hw<kRelu>(acc[c][4 * j + 1] + bv[j].y);
-      a[4 * j + 2] = act_hw<kRelu>(acc[c][4 * j + 2] + bv[j].z);
-      a[4 * j + 3] = act_hw<kRelu>(acc[c][4 * j + 3] + bv[j].w);
+      a[4 * j + 0] = act_hw(acc[c][4 * j + 0] + bv[j].x, m.act_ln2);
+      a[4 * j + 1] = act_hw(acc[c][4 * j + 1] + bv[j].y, m.act_ln2);
+      a[4 * j + 2] = act_hw(acc[c][4 * j + 2] + bv[j].z, m.act_ln2);
+      a[4 * j + 3] = act_hw(acc[c][4 * j + 3] + bv[j].w, m.act_ln2);
       if constexpr (kLast) {
         dot += a[4 * j + 0] * wv[j].x;
         dot += a[4 * j + 1] * wv[j].y;
@@ -361,15 +362,6 @@ __device__ __forceinline__ float mlp_epilogue_act(const MlpDesc& m, int l, int c
 #pragma unroll
     for (int c = 0; c + span < NT; c += 2 * span) dt[c] += dt[c + span];
   return dt[0];
-}
-
-// The activation is uniform over the launch: one branch per call picks the
-// epilogue built for it.
-template <int P, int W, int NT, bool kLast>
-__device__ __forceinline__ float mlp_epilogue(const MlpDesc& m, int l, int c0, f32x16_t (&acc)[NT],
-                                              bf16x8_t (&x)[2 * NT], bf16x8_t (&xl)[2 * NT]) {
-  if (m.relu) return mlp_epilogue_act<P, W, NT, kLast, true>(m, l, c0, acc, x, xl);
-  return mlp_epilogue_act<P, W, NT, kLast, false>(m, l, c0, acc, x, xl);
 }
 
 // Features of k-step s of the first layer: slot 8h + i holds feature
