@@ -23,6 +23,9 @@ Prints one JSON line.  Extra objects:
                 same network at N = 256, FP32 forward (milliseconds)
   batch         64 bounds on grids of 64..512, one persistent hop launch plus
                 marching cubes per shape, replayed from a hipGraph
+  primitives    the paper's first scene's seven primitive types (sphere,
+                cube, cone, cylinder, torus, hexagonal prism, capsule) at
+                N = 512, with the enumeration path beside it
   traced        the paper's per-column procedure taken literally
                 (gh_hop_traced: sphere tracing to sqrt(6)/2 h) on the headline
                 workload, with marching cubes on its candidates, its counts,
@@ -54,7 +57,12 @@ PEAK_BF16_MFMA = 2.5e15   # dense, no sparsity
 #   capsule neg + max + min + sub + 3 mul + 2 add + sqrt + sub = 11
 #   plane   3 mul + 2 add + sub (no translate/rotate)          = 6 total
 #   boxbound 3 abs + 3 sub + 2 max                              = 8
-OPS = {0: 18 + 7, 1: 18 + 19, 2: 18 + 10, 3: 18 + 11, 4: 6, 5: 18 + 8}
+#   cylinder 2 mul + add + sqrt, sub, abs + sub, 2 max, 2 mul + add + sqrt,
+#            max + min + add                                    = 16
+#   cone     2 mul + add + sqrt, mul + sub + mul + sub, abs + sub + max = 11
+#   hexprism 2 mul, abs + sub, add + abs + sub, sub + abs + sub, abs + sub,
+#            3 max                                              = 15
+OPS = {0: 18 + 7, 1: 18 + 19, 2: 18 + 10, 3: 18 + 11, 4: 6, 5: 18 + 8, 6: 18 + 16, 7: 18 + 11, 8: 18 + 15}
 
 
 def ops_per_eval(records):
@@ -255,6 +263,33 @@ def batch_section(dev, steps, warmup, precision="bf16x3", tune=True):
             "n_tri": sum(c["n_tri"] for c in ref)}
 
 
+def primitives_section(dev, steps, warmup, n=512, seed=0):
+    """The paper's first scene's seven primitives (sphere, cube, cone,
+    cylinder, torus, hexagonal prism, capsule) at N = 512: grid hopping and
+    enumeration, each followed by marching cubes."""
+    import torch
+
+    import workloads as W
+    from paper_2111_05778_amd.polygonize import Bound, Polygonizer, counters_dict
+    recs = W.primitives_scene(seed)
+    n, lo, h = W.grid(n)
+    poly = Polygonizer(Bound.prims(recs, dev), n, lo, h, device=dev, keep_cells=False)
+    poly.run()
+    for _ in range(warmup):
+        poly.enqueue_hop()
+        poly.enqueue_mc()
+    stream = torch.cuda.current_stream(dev)
+    hop_ms = event_ms(stream, poly.enqueue_hop, steps)
+    mc_ms = event_ms(stream, poly.enqueue_mc, steps)
+    c = counters_dict(poly.ctr)
+    dense_ms = event_ms(stream, lambda: (poly.enqueue_dense(), poly.enqueue_mc()), max(1, steps // 2))
+    return {"workload": f"primitives7_seed{seed}_n{n}", "hop_ms": hop_ms, "mc_ms": mc_ms,
+            "ms_per_step": hop_ms + mc_ms, "value": n ** 3 / ((hop_ms + mc_ms) * 1e-3), "unit": "cells/s",
+            "dense_ms": dense_ms, "speedup_vs_dense": dense_ms / (hop_ms + mc_ms),
+            "counters": {k: c[k] for k in ("n_hop_evals", "n_cand", "n_corner", "n_vert", "n_tri")},
+            "ops_per_eval": ops_per_eval(recs)}
+
+
 def traced_section(dev, steps, warmup, recs, n, lo, h, seed):
     """The paper's per-column procedure taken literally (gh_hop_traced) on
     the headline workload: its times and counts beside grid hopping's, and
@@ -293,7 +328,7 @@ def main():
                          "that scales the HBM counters) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (built-in shapes)")
-    ap.add_argument("--sections", default="neural,paper_net,backward,batch,traced",
+    ap.add_argument("--sections", default="neural,paper_net,backward,batch,traced,primitives",
                     help="extra workloads to measure after the headline one (comma list, or none)")
     args = ap.parse_args()
     sections = [x for x in args.sections.split(",") if x and x != "none"]
@@ -422,6 +457,8 @@ def main():
         out["backward_ms"] = out["backward"]["backward_ms"]
     if "batch" in sections:
         out["batch"] = batch_section(dev, max(3, args.steps // 4), sw, tune=not args.no_tune)
+    if "primitives" in sections:
+        out["primitives"] = primitives_section(dev, max(3, args.steps // 4), sw)
     if "traced" in sections:
         out["traced"] = traced_section(dev, max(3, args.steps // 4), sw, recs, n, lo, h, args.seed)
     print(json.dumps(out), flush=True)

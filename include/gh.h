@@ -101,10 +101,16 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
 
 /* Primitive record: 16 float32 values.
  *  [0] type: 0 sphere, 1 box (exact), 2 torus, 3 capsule, 4 plane,
- *            5 box bound (max of six face planes, Section 4.2 eq. boxdist)
+ *            5 box bound (max of six face planes, Section 4.2 eq. boxdist),
+ *            6 cylinder, 7 cone, 8 hexagonal prism (Section 6.1's primitives)
  *  [1..3] centre c;  [4..12] 3x3 matrix M row-major, local q = M (p - c)
  *  [13..15] sphere (r), box/box bound (bx, by, bz), torus (R, r) about local y,
- *           capsule (a, r) on local z in [-a, a], plane (d) with f = M_row0 . p - d.
+ *           capsule (a, r) on local z in [-a, a], plane (d) with f = M_row0 . p - d,
+ *           cylinder (r, a) capped at local z = -a, a (exact distance),
+ *           cone (a, s, c): apex at local z = a, axis -z, half-angle of sine s and
+ *           cosine c (s^2 + c^2 <= 1), cut at z = -a (max of side and cap: a bound),
+ *           hexagonal prism (r, a): apothem r with one pair of faces normal to local
+ *           x, capped at z = -a, a (max of the face planes: a bound).
  * The bound is the minimum over the records (union, Section 4.3). */
 #define GH_PRIM_FLOATS 16
 

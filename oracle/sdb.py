@@ -10,7 +10,17 @@ Primitive distances are written from geometry:
   torus    sqrt((sqrt(q_x^2 + q_z^2) - R)^2 + q_y^2) - r
   capsule  ||q - (0, 0, clamp(q_z, -a, a))|| - r
   plane    n . p - d       (Section 4.1, eq. plane)
+  cylinder d = (rho - r, |q_z| - a), rho = ||(q_x, q_y)||:  ||max(d, 0)|| + min(max_i d_i, 0)
+           (exact distance to the capped cylinder)
+  cone     max(rho cos - (a - q_z) sin, |q_z| - a): the distance to the
+           cone's side line through the apex (a bound, since it reaches
+           the other nappe too) and to the slab of the caps, intersected
+  hexprism max(|q . n_k| - r over the three face normals n_k = (1, 0),
+           (1/2, sqrt3/2), (-1/2, sqrt3/2) in the local xy plane, |q_z| - a):
+           the max of the eight face planes, like the box bound
 and combined by the minimum, which is the union of the shapes (Section 4.3).
+The paper's first scene holds sphere, cube, cone, cylinder, torus,
+hexagonal prism and capsule, each with a simple distance bound (Section 6.1).
 
 The FP32 twin evaluates the same expressions in numpy float32 in a fixed
 order, one rounding per operation and no fused multiply-add; numpy's float32
@@ -20,6 +30,7 @@ op order is documented beside each twin function.
 import numpy as np
 
 PRIM_SPHERE, PRIM_BOX, PRIM_TORUS, PRIM_CAPSULE, PRIM_PLANE, PRIM_BOXBOUND = 0, 1, 2, 3, 4, 5
+PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM = 6, 7, 8
 
 
 # ------------------------------------------------------------------------- FP64
@@ -48,6 +59,16 @@ def prim_f64(rec, P):
         w = q.copy()
         w[:, 2] = q[:, 2] - np.clip(q[:, 2], -a0, a0)
         return np.linalg.norm(w, axis=1) - a1
+    if t == PRIM_CYLINDER:
+        d = np.stack([np.hypot(q[:, 0], q[:, 1]) - a0, np.abs(q[:, 2]) - a1], axis=1)
+        return np.linalg.norm(np.maximum(d, 0.0), axis=1) + np.minimum(d.max(axis=1), 0.0)
+    if t == PRIM_CONE:
+        side = np.hypot(q[:, 0], q[:, 1]) * a2 - (a0 - q[:, 2]) * a1
+        return np.maximum(side, np.abs(q[:, 2]) - a0)
+    if t == PRIM_HEXPRISM:
+        s3 = np.sqrt(3.0) / 2.0
+        faces = [np.abs(q[:, 0]), np.abs(0.5 * q[:, 0] + s3 * q[:, 1]), np.abs(s3 * q[:, 1] - 0.5 * q[:, 0])]
+        return np.maximum(np.max(np.stack(faces), axis=0) - a0, np.abs(q[:, 2]) - a1)
     raise ValueError(f"unknown primitive type {t}")
 
 
@@ -72,6 +93,11 @@ def prim_f32(rec, x, y, z):
     torus:   s = sqrt(q_x*q_x + q_z*q_z) - R;  sqrt(s*s + q_y*q_y) - r
     capsule: w = q_z - min(max(q_z, -a), a);  sqrt((q_x*q_x + q_y*q_y) + w*w) - r
     plane:   ((n_x*x + n_y*y) + n_z*z) - d
+    cylinder: rho = sqrt(q_x*q_x + q_y*q_y);  d_x = rho - r, d_z = |q_z| - a;
+             m_i = max(d_i, 0);  sqrt(m_x*m_x + m_z*m_z) + min(max(d_x, d_z), 0)
+    cone:    rho = sqrt(q_x*q_x + q_y*q_y);  max(rho*c - (a - q_z)*s, |q_z| - a)
+    hexprism: h_x = 0.5*q_x, h_y = S*q_y with S = float32(sqrt(3)/2);
+             max(|q_x| - r, max(|h_x + h_y| - r, max(|h_y - h_x| - r, |q_z| - a)))
     """
     rec = np.asarray(rec, dtype=np.float32)
     t = int(rec[0])
@@ -98,6 +124,18 @@ def prim_f32(rec, x, y, z):
     if t == PRIM_CAPSULE:
         w = qz - np.minimum(np.maximum(qz, -a0), a0)
         return np.sqrt((qx * qx + qy * qy) + w * w) - a1
+    if t == PRIM_CYLINDER:
+        rho = np.sqrt(qx * qx + qy * qy)
+        dx, dz = rho - a0, np.abs(qz) - a1
+        mx, mz = np.maximum(dx, np.float32(0)), np.maximum(dz, np.float32(0))
+        return np.sqrt(mx * mx + mz * mz) + np.minimum(np.maximum(dx, dz), np.float32(0))
+    if t == PRIM_CONE:
+        rho = np.sqrt(qx * qx + qy * qy)
+        return np.maximum(rho * a2 - (a0 - qz) * a1, np.abs(qz) - a0)
+    if t == PRIM_HEXPRISM:
+        hx, hy = np.float32(0.5) * qx, np.float32(np.sqrt(3.0) / 2.0) * qy
+        u1, u2, u3 = np.abs(qx) - a0, np.abs(hx + hy) - a0, np.abs(hy - hx) - a0
+        return np.maximum(u1, np.maximum(u2, np.maximum(u3, np.abs(qz) - a1)))
     raise ValueError(f"unknown primitive type {t}")
 
 

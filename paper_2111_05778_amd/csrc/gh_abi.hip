@@ -301,7 +301,7 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
   for (int p = 0; p < np; ++p) {
     const float* r = spec_h->prims_h + (size_t)p * GH_PRIM_FLOATS;
     const float t = r[0];
-    if (!(t == 0.f || t == 1.f || t == 2.f || t == 3.f || t == 4.f || t == 5.f))
+    if (!(t >= 0.f && t <= 8.f && t == floorf(t)))
       return fail(GH_EINVAL, "primitive %d has unknown type %g", p, (double)t);
     // Bounded magnitudes keep every intermediate finite or +inf, never NaN:
     // |M q| <= 3e33 and sums of squares can only overflow towards +inf.
@@ -311,6 +311,11 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
         return fail(GH_EINVAL, "primitive %d parameter %d = %g is not finite or exceeds %g", p, q, (double)r[q],
                     (double)lim);
     }
+    // A cone's (sine, cosine) must not be longer than a unit vector: the
+    // side term is then 1-Lipschitz and the record a distance bound.
+    if (t == 7.f && !((double)r[14] * r[14] + (double)r[15] * r[15] <= 1.0 + 1e-6))
+      return fail(GH_EINVAL, "cone %d: (sin, cos) = (%g, %g) is longer than a unit vector", p, (double)r[14],
+                  (double)r[15]);
   }
   const size_t need = (size_t)np * GH_PRIM_FLOATS * sizeof(float);
   if (blob_needed_h) *blob_needed_h = need;
@@ -343,9 +348,10 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
   d.magic = gh::kDescMagic;
   d.kind = GH_SDB_PRIMS;
   d.n_prim = np;
-  d.flags = gh::kSdbRingsNormal;
-  for (int p = groups.start[gh::kPrimTorus]; p < groups.start[gh::kPrimTorus + 1]; ++p)
-    if (!(fabsf(sorted[(size_t)p * GH_PRIM_FLOATS + 13]) >= 0x1p-23f)) d.flags &= ~gh::kSdbRingsNormal;
+  d.flags = gh::kSdbRadiiNormal;
+  for (int t : {(int)gh::kPrimTorus, (int)gh::kPrimCylinder})
+    for (int p = groups.start[t]; p < groups.start[t + 1]; ++p)
+      if (!(fabsf(sorted[(size_t)p * GH_PRIM_FLOATS + 13]) >= 0x1p-23f)) d.flags &= ~gh::kSdbRadiiNormal;
   d.prims = (const float*)dev_blob;
   d.groups = groups;
   memset(desc_h, 0, sizeof(*desc_h));

@@ -14,7 +14,17 @@ constexpr int kBlock = 256;  // threads per block in every tiled kernel (4 waves
 constexpr int kMaxN = 2048;
 constexpr int kMaxPrims = 64;
 
-enum : int { kPrimSphere = 0, kPrimBox = 1, kPrimTorus = 2, kPrimCapsule = 3, kPrimPlane = 4, kPrimBoxBound = 5 };
+enum : int {
+  kPrimSphere = 0,
+  kPrimBox = 1,
+  kPrimTorus = 2,
+  kPrimCapsule = 3,
+  kPrimPlane = 4,
+  kPrimBoxBound = 5,
+  kPrimCylinder = 6,
+  kPrimCone = 7,
+  kPrimHexPrism = 8
+};
 
 struct Grid {
   int n;        // cells per axis
@@ -41,9 +51,13 @@ __device__ __forceinline__ float lattice(const Grid& g, int idx) { return g.lo +
 // either disappears when a term of magnitude >= 2^-23 is added (a radius or a
 // face distance: the sum rounds to that term, as it does with the exact root)
 // or leaves |f| < 2^-22, below h whenever h >= 2^-20, where both give s = 0.
-// The torus's inner root feeds a second root instead, hence the condition
-// |R| >= 2^-23 on its ring radius.  Kernels that use it run only when the
-// grid and the union meet both conditions.
+// The torus's and the cylinder's first roots feed a second root instead,
+// hence the condition |R| >= 2^-23 on the torus's ring radius and the
+// cylinder's radius.  The cone's root is multiplied by c and followed by the
+// subtraction of (a - qz) s, which either absorbs it or leaves a value below
+// 2^-22 on both sides, so the maximum with the cap term gives s = 0 either
+// way or the same cap value.  Kernels that use it run only when the grid and
+// the union meet these conditions.
 __device__ __forceinline__ float sqrt_hop(float a) {
   a = fmaxf(a, 0x1p-96f);
   const float s = __builtin_amdgcn_sqrtf(a);
@@ -64,6 +78,12 @@ constexpr float kHopRootMinH = 0x1p-20f;
 //   torus    s = sqrt(qx qx + qz qz) - R;  sqrt(s s + qy qy) - r
 //   capsule  w = qz - min(max(qz, -a), a);  sqrt((qx qx + qy qy) + w w) - r
 //   plane    ((n_x x + n_y y) + n_z z) - d                 (Section 4.1, eq. plane)
+//   cylinder rho = sqrt(qx qx + qy qy);  dx = rho - r, dz = |qz| - a, m = max(d, 0):
+//            sqrt(mx mx + mz mz) + min(max(dx, dz), 0)     (capped, axis local z)
+//   cone     rho = sqrt(qx qx + qy qy);  max(rho c - (a - qz) s, |qz| - a)
+//            (apex at local z = a, half-angle with sine s and cosine c, cut at z = -a)
+//   hexprism hx = qx/2, hy = (sqrt 3/2) qy;  max(|qx| - r, max(|hx + hy| - r,
+//            max(|hy - hx| - r, |qz| - a)))                 (apothem r, axis local z)
 // The type is a template argument: callers loop over primitives grouped by
 // type, so no branch on the type sits inside the loop.  kHopRoot: the roots
 // are taken by sqrt_hop (hop decisions only; the values themselves may differ
@@ -86,6 +106,18 @@ __device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
     } else if constexpr (T == kPrimCapsule) {
       const float w = qz - fminf(fmaxf(qz, -r[13]), r[13]);
       return root((qx * qx + qy * qy) + w * w) - r[14];
+    } else if constexpr (T == kPrimCylinder) {
+      const float rho = root(qx * qx + qy * qy);
+      const float dx = rho - r[13], dz = fabsf(qz) - r[14];
+      const float mx = fmaxf(dx, 0.f), mz = fmaxf(dz, 0.f);
+      return root(mx * mx + mz * mz) + fminf(fmaxf(dx, dz), 0.f);
+    } else if constexpr (T == kPrimCone) {
+      const float rho = root(qx * qx + qy * qy);
+      return fmaxf(rho * r[15] - (r[13] - qz) * r[14], fabsf(qz) - r[13]);
+    } else if constexpr (T == kPrimHexPrism) {
+      const float hx = 0.5f * qx, hy = 0.866025403784438646f * qy;
+      const float u1 = fabsf(qx) - r[13], u2 = fabsf(hx + hy) - r[13], u3 = fabsf(hy - hx) - r[13];
+      return fmaxf(u1, fmaxf(u2, fmaxf(u3, fabsf(qz) - r[14])));
     } else {
       const float ux = fabsf(qx) - r[13], uy = fabsf(qy) - r[14], uz = fabsf(qz) - r[15];
       const float inner = fmaxf(ux, fmaxf(uy, uz));
@@ -99,7 +131,8 @@ __device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
   }
 }
 
-constexpr int kPrimTypes = 6;
+constexpr int kPrimTypes = 9;
+constexpr int kAllTypes = (1 << kPrimTypes) - 1;  // type mask with every type
 
 // Primitives sorted by type: group t occupies records [start[t], start[t+1]).
 // The minimum is exact and commutative, so the order of the union does not
@@ -127,6 +160,11 @@ __device__ __forceinline__ float union_strided(const PrimGroups& g, Rec rec, int
   for_prims_of_type<kPrimPlane>(g, first, step, [&](int p) { f = fminf(f, prim_eval_t<kPrimPlane>(rec(p), x, y, z)); });
   for_prims_of_type<kPrimBoxBound>(g, first, step,
                                    [&](int p) { f = fminf(f, prim_eval_t<kPrimBoxBound>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimCylinder>(g, first, step,
+                                   [&](int p) { f = fminf(f, prim_eval_t<kPrimCylinder>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimCone>(g, first, step, [&](int p) { f = fminf(f, prim_eval_t<kPrimCone>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimHexPrism>(g, first, step,
+                                   [&](int p) { f = fminf(f, prim_eval_t<kPrimHexPrism>(rec(p), x, y, z)); });
   return f;
 }
 

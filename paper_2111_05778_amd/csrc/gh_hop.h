@@ -79,7 +79,7 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
     float f = __builtin_inff();
     // Every type is evaluated (a lane without one holds another record and
     // discards the value): no branch splits the step, so the independent
-    // chains of the six formulas interleave.
+    // chains of the formulas interleave.
     float v[kPrimTypes];
     if constexpr (kTypes & (1 << kPrimSphere)) v[kPrimSphere] = prim_eval_t<kPrimSphere, true>(rec[kPrimSphere], x, y, z);
     if constexpr (kTypes & (1 << kPrimBox)) v[kPrimBox] = prim_eval_t<kPrimBox, true>(rec[kPrimBox], x, y, z);
@@ -89,6 +89,11 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
     if constexpr (kTypes & (1 << kPrimPlane)) v[kPrimPlane] = prim_eval_t<kPrimPlane, true>(rec[kPrimPlane], x, y, z);
     if constexpr (kTypes & (1 << kPrimBoxBound))
       v[kPrimBoxBound] = prim_eval_t<kPrimBoxBound, true>(rec[kPrimBoxBound], x, y, z);
+    if constexpr (kTypes & (1 << kPrimCylinder))
+      v[kPrimCylinder] = prim_eval_t<kPrimCylinder, true>(rec[kPrimCylinder], x, y, z);
+    if constexpr (kTypes & (1 << kPrimCone)) v[kPrimCone] = prim_eval_t<kPrimCone, true>(rec[kPrimCone], x, y, z);
+    if constexpr (kTypes & (1 << kPrimHexPrism))
+      v[kPrimHexPrism] = prim_eval_t<kPrimHexPrism, true>(rec[kPrimHexPrism], x, y, z);
 #pragma unroll
     for (int t = 0; t < kPrimTypes; ++t)
       if ((kTypes >> t) & 1) f = has[t] ? fminf(f, v[t]) : f;
@@ -108,7 +113,7 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
 // its state (column, k, the candidate word in progress and the word mask)
 // to park[*park_count++]; the long-ray pass finishes it exactly as this loop
 // would have (the hop is a function of the state alone).
-template <int R, bool kRegs = false, int kTypes = 63>
+template <int R, bool kRegs = false, int kTypes = kAllTypes>
 __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
                                                uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                gh_counters* __restrict__ ctr, int tile, int budget = 0,

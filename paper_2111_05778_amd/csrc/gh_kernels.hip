@@ -48,7 +48,7 @@ __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, u
 }
 
 // --------------------------------------------------------------------- hop
-template <int R, bool kRegs, int kTypes = 63>
+template <int R, bool kRegs, int kTypes = kAllTypes>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_hop_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                       uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                       gh_counters* __restrict__ ctr, int budget,
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 
 // Second pass of a hop with a step budget: the rays the first pass handed
 // over, one wave and one window of cells each (see hop_window_rays).
-template <int R, bool kRegs, int kTypes = 63>
+template <int R, bool kRegs, int kTypes = kAllTypes>
 __global__ __launch_bounds__(kBlock) void k_hop_long(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                      uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                      const uint32_t* __restrict__ park,
@@ -207,12 +207,21 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
   const int blocks = cu_count() * 8;
   // Register-record kernels take the hop square root: only where it gives
   // the exact root's decisions.
-  const bool regs = most <= R && (d.flags & kSdbRingsNormal) && g.h >= kHopRootMinH;
+  const bool regs = most <= R && (d.flags & kSdbRadiiNormal) && g.h >= kHopRootMinH;
+  // Unions without planes and box bounds (the solids plus cylinders, cones
+  // and hexagonal prisms) get a kernel that skips those two.
+  constexpr int kNoPlanes = kAllTypes & ~((1 << kPrimPlane) | (1 << kPrimBoxBound));
   if (regs && (present & ~kSolids) == 0) {
     hipLaunchKernelGGL((k_hop_prims<R, true, kSolids>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
                        ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, true, kSolids>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
+                         ws.colmask, ws.colbits, ws.park, npark, ctr);
+  } else if (regs && (present & ~kNoPlanes) == 0) {
+    hipLaunchKernelGGL((k_hop_prims<R, true, kNoPlanes>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups,
+                       g, ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
+    if (budget > 0)
+      hipLaunchKernelGGL((k_hop_long<R, true, kNoPlanes>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
                          ws.colmask, ws.colbits, ws.park, npark, ctr);
   } else if (regs) {
     hipLaunchKernelGGL((k_hop_prims<R, true>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,

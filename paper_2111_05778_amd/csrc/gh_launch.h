@@ -50,15 +50,15 @@ struct DevSdb {
   uint32_t magic;
   int32_t kind;
   int32_t n_prim;
-  int32_t flags;       // kSdbRingsNormal
+  int32_t flags;       // kSdbRadiiNormal
   const float* prims;  // device, n_prim * GH_PRIM_FLOATS, sorted by type
   PrimGroups groups;   // type t occupies records [start[t], start[t+1])
   MlpDesc mlp;         // GH_SDB_MLP: packed network in the blob
 };
 constexpr uint32_t kDescMagic = 0x67687364u;  // "ghsd"
-// Every torus of the union has a ring radius of magnitude >= 2^-23 (one of
-// the conditions for the hop square root, sqrt_hop).
-constexpr int32_t kSdbRingsNormal = 1;
+// Every torus ring radius and cylinder radius of the union has magnitude
+// >= 2^-23 (one of the conditions for the hop square root, sqrt_hop).
+constexpr int32_t kSdbRadiiNormal = 1;
 
 enum ClearMode { kClearAll = 0, kClearMc = 1, kClearCands = 2 };
 

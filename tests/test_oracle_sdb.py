@@ -204,3 +204,68 @@ def test_paper_network_shape():
     assert net["activation"] == "relu" and len(net["omegas"]) == 0
     assert [w.shape for w in net["weights"]] == [(64, 3)] + [(64, 64)] * 7 + [(1, 64)]
     assert sum(w.size for w in net["weights"]) == 28928
+
+
+def _both(recs, P):
+    """The oracle's FP64 value and its FP32 twin at the points P."""
+    P = np.asarray(P, dtype=np.float64)
+    f64 = sdb.union_f64(recs, P)
+    f32 = sdb.union_f32(recs, *[P[:, i].astype(np.float32) for i in range(3)]).astype(np.float64)
+    return f64, f32
+
+
+def test_cylinder_closed_forms():
+    # capped cylinder r = 0.3, a = 0.2 about z: radial, axial and rim
+    # distances outside, the nearer of side and cap inside
+    recs = W.cylinder_scene(0.3, 0.2)
+    P = [(0.5, 0, 0), (0, 0, 0.5), (0.5, 0, 0.5), (0, 0, 0), (0.1, 0, 0.1), (0, -0.7, -0.05)]
+    exp = [0.2, 0.3, np.hypot(0.2, 0.3), -0.2, -0.1, 0.4]
+    for f in _both(recs, P):
+        np.testing.assert_allclose(f, exp, atol=1e-6)
+
+
+def test_cone_closed_forms():
+    # apex at z = 0.2, half-angle 30 degrees, cut at z = -0.2
+    recs = W.cone_scene(0.2, np.pi / 6)
+    s, c = 0.5, np.sqrt(3) / 2
+    P = [(0, 0, 0), (0, 0, 0.3), (0.5, 0, 0), (0, 0, -0.5), (0.05, 0, -0.1)]
+    exp = [-0.2 * s,                 # on the axis: distance to the side line
+           0.1,                      # above the apex: distance to the apex
+           0.5 * c - 0.2 * s,        # beside it: perpendicular to the side
+           0.3,                      # below the base: distance to the base plane
+           max(0.05 * c - 0.3 * s, -0.1)]
+    for f in _both(recs, P):
+        np.testing.assert_allclose(f, exp, atol=1e-6)
+
+
+def test_hexprism_closed_forms():
+    # apothem 0.2, half-length 0.3: along a face normal the bound is the exact
+    # distance |p| - r; towards a vertex (the local y axis) it is
+    # |p| cos 30 - r, below the exact |p| - r / cos 30
+    recs = W.hexprism_scene(0.2, 0.3)
+    P = [(0.5, 0, 0), (0.25, 0.25 * np.sqrt(3), 0), (0, 0.5, 0), (0, 0, 0.4), (0, 0, 0)]
+    exp = [0.3, 0.3, 0.5 * np.sqrt(3) / 2 - 0.2, 0.1, -0.2]
+    for f in _both(recs, P):
+        np.testing.assert_allclose(f, exp, atol=1e-6)
+    assert exp[2] < 0.5 - 0.2 / (np.sqrt(3) / 2)
+
+
+def test_new_primitives_are_distance_bounds():
+    # |f| <= distance to the zero set, sampled: the zero set is located on
+    # segments from each inside point to far outside points by bisection, and
+    # every outside sample's |f| must not exceed its distance to those points
+    rng = np.random.default_rng(7)
+    for recs in (W.cylinder_scene(0.3, 0.2), W.cone_scene(0.25, 0.5), W.hexprism_scene(0.2, 0.3)):
+        inside = np.zeros((1, 3))
+        dirs = rng.standard_normal((4000, 3))
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        lo_t, hi_t = np.zeros(len(dirs)), np.full(len(dirs), 2.0)
+        for _ in range(60):
+            mid = 0.5 * (lo_t + hi_t)
+            neg = sdb.union_f64(recs, inside + mid[:, None] * dirs) < 0
+            lo_t, hi_t = np.where(neg, mid, lo_t), np.where(neg, hi_t, mid)
+        surf = inside + lo_t[:, None] * dirs
+        Q = rng.uniform(-1, 1, (3000, 3))
+        f = sdb.union_f64(recs, Q)
+        dist = np.min(np.linalg.norm(Q[:, None, :] - surf[None, :, :], axis=2), axis=1)
+        assert np.all(np.abs(f) <= dist + 2e-3), np.max(np.abs(f) - dist)

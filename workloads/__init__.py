@@ -20,6 +20,11 @@ Primitive record layout (float32, PRIM_STRIDE = 16 per primitive):
           capsule   (a, r, 0)   segment [-a, a] on the local z axis
           plane     (d, 0, 0)   f = n . p - d with n = first row of M, c = 0
           boxbound  (bx, by, bz) max of the six face-plane distances
+          cylinder  (r, a, 0)   capped at local z = -a, a
+          cone      (a, s, c)   apex at local z = a opening toward -z with
+                                half-angle sin s, cos c; cut at z = -a
+          hexprism  (r, a, 0)   apothem r, faces normal to local x and at
+                                +-60 degrees from it; capped at z = -a, a
 """
 import json
 import os
@@ -27,6 +32,7 @@ import os
 import numpy as np
 
 PRIM_SPHERE, PRIM_BOX, PRIM_TORUS, PRIM_CAPSULE, PRIM_PLANE, PRIM_BOXBOUND = 0, 1, 2, 3, 4, 5
+PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM = 6, 7, 8
 PRIM_STRIDE = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -83,6 +89,60 @@ def plane_scene(normal, offset):
 def box_scene(half, centre=(0.0, 0.0, 0.0), bound=False):
     """Axis-aligned box: exact distance, or the max-of-planes bound of eq. boxdist."""
     return _record(PRIM_BOXBOUND if bound else PRIM_BOX, centre, np.eye(3), half)[None, :]
+
+
+def cylinder_scene(r, a, centre=(0.0, 0.0, 0.0)):
+    """Capped cylinder about the z axis (exact distance)."""
+    return _record(PRIM_CYLINDER, centre, np.eye(3), (r, a))[None, :]
+
+
+def cone_scene(a, half_angle, centre=(0.0, 0.0, 0.0)):
+    """Cone with apex at centre + (0, 0, a), opening toward -z, cut at -a."""
+    return _record(PRIM_CONE, centre, np.eye(3), (a, np.sin(half_angle), np.cos(half_angle)))[None, :]
+
+
+def hexprism_scene(r, a, centre=(0.0, 0.0, 0.0)):
+    """Hexagonal prism of apothem r about the z axis, capped at +-a."""
+    return _record(PRIM_HEXPRISM, centre, np.eye(3), (r, a))[None, :]
+
+
+def primitives_scene(seed=0):
+    """The paper's first scene's seven primitives (Section 6.1: sphere,
+    cube, cone, cylinder, torus, hexagonal prism, capsule), each seeded in
+    its own slot of a 3 x 3 layout in the z = 0 plane (the centre slot and
+    one corner stay empty), with a rotation from a normalised N(0, I_4)
+    quaternion and these sizes, drawn in this order per primitive:
+      sphere r ~ U[0.15, 0.25]; cube half side ~ U[0.12, 0.2];
+      cone a ~ U[0.15, 0.22], half-angle ~ U[0.3, 0.6] rad;
+      cylinder r ~ U[0.08, 0.16], a ~ U[0.12, 0.2];
+      torus R ~ U[0.12, 0.18], r ~ U[0.03, 0.06];
+      hexagonal prism apothem ~ U[0.08, 0.16], a ~ U[0.1, 0.2];
+      capsule a ~ U[0.08, 0.15], r ~ U[0.05, 0.09]."""
+    rng = np.random.default_rng(seed)
+    slots = [(-0.6, -0.6), (0.0, -0.6), (0.6, -0.6), (-0.6, 0.0), (0.6, 0.0), (-0.6, 0.6), (0.0, 0.6)]
+    recs = []
+    for t, (sx, sy) in zip((PRIM_SPHERE, PRIM_BOX, PRIM_CONE, PRIM_CYLINDER, PRIM_TORUS, PRIM_HEXPRISM, PRIM_CAPSULE),
+                           slots):
+        qv = rng.standard_normal(4)
+        M = _quat_to_local(qv / np.linalg.norm(qv))
+        c = (sx, sy, 0.0)
+        if t == PRIM_SPHERE:
+            params = (rng.uniform(0.15, 0.25),)
+        elif t == PRIM_BOX:
+            params = (rng.uniform(0.12, 0.2),) * 3
+        elif t == PRIM_CONE:
+            a, ang = rng.uniform(0.15, 0.22), rng.uniform(0.3, 0.6)
+            params = (a, np.sin(ang), np.cos(ang))
+        elif t == PRIM_CYLINDER:
+            params = (rng.uniform(0.08, 0.16), rng.uniform(0.12, 0.2))
+        elif t == PRIM_TORUS:
+            params = (rng.uniform(0.12, 0.18), rng.uniform(0.03, 0.06))
+        elif t == PRIM_HEXPRISM:
+            params = (rng.uniform(0.08, 0.16), rng.uniform(0.1, 0.2))
+        else:
+            params = (rng.uniform(0.08, 0.15), rng.uniform(0.05, 0.09))
+        recs.append(_record(t, c, M, params))
+    return np.stack(recs)
 
 
 def csg_scene(seed=0, n_prim=12):
