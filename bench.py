@@ -62,7 +62,10 @@ PEAK_BF16_MFMA = 2.5e15   # dense, no sparsity
 #   cone     2 mul + add + sqrt, mul + sub + mul + sub, abs + sub + max = 11
 #   hexprism 2 mul, abs + sub, add + abs + sub, sub + abs + sub, abs + sub,
 #            3 max                                              = 15
-OPS = {0: 18 + 7, 1: 18 + 19, 2: 18 + 10, 3: 18 + 11, 4: 6, 5: 18 + 8, 6: 18 + 16, 7: 18 + 11, 8: 18 + 15}
+#   genus2   3 mul (squares), sub, add, mul + mul + sub + mul + mul, mul + add,
+#            mul + sub + mul + sub, mul (k)                        = 18
+OPS = {0: 18 + 7, 1: 18 + 19, 2: 18 + 10, 3: 18 + 11, 4: 6, 5: 18 + 8, 6: 18 + 16, 7: 18 + 11, 8: 18 + 15,
+       9: 18 + 18}
 
 
 def ops_per_eval(records):

@@ -102,7 +102,8 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
 /* Primitive record: 16 float32 values.
  *  [0] type: 0 sphere, 1 box (exact), 2 torus, 3 capsule, 4 plane,
  *            5 box bound (max of six face planes, Section 4.2 eq. boxdist),
- *            6 cylinder, 7 cone, 8 hexagonal prism (Section 6.1's primitives)
+ *            6 cylinder, 7 cone, 8 hexagonal prism (Section 6.1's primitives),
+ *            9 the implicit surface of genus 2 of Section 6.1, scaled
  *  [1..3] centre c;  [4..12] 3x3 matrix M row-major, local q = M (p - c)
  *  [13..15] sphere (r), box/box bound (bx, by, bz), torus (R, r) about local y,
  *           capsule (a, r) on local z in [-a, a], plane (d) with f = M_row0 . p - d,
@@ -110,7 +111,9 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
  *           cone (a, s, c): apex at local z = a, axis -z, half-angle of sine s and
  *           cosine c (s^2 + c^2 <= 1), cut at z = -a (max of side and cap: a bound),
  *           hexagonal prism (r, a): apothem r with one pair of faces normal to local
- *           x, capped at z = -a, a (max of the face planes: a bound).
+ *           x, capped at z = -a, a (max of the face planes: a bound),
+ *           genus 2 (k): k F(q) with F = 2y(y^2-3x^2)(1-z^2) + (x^2+y^2)^2 - (9z^2-1)(1-z^2);
+ *           the caller picks k so that |grad| <= 1 wherever it is evaluated.
  * The bound is the minimum over the records (union, Section 4.3). */
 #define GH_PRIM_FLOATS 16
 
@@ -137,7 +140,7 @@ typedef struct {
 /* Opaque, caller-owned, plain-old-data handle filled by sdb_describe.  It
  * refers to the device blob, which must outlive every call that uses it. */
 typedef struct {
-  uint64_t opaque[24];
+  uint64_t opaque[32];
 } gh_sdb_desc;
 
 /* Validate a bound and pack it into the caller's device blob.

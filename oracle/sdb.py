@@ -18,6 +18,9 @@ Primitive distances are written from geometry:
   hexprism max(|q . n_k| - r over the three face normals n_k = (1, 0),
            (1/2, sqrt3/2), (-1/2, sqrt3/2) in the local xy plane, |q_z| - a):
            the max of the eight face planes, like the box bound
+  genus2   k F(q), F = 2y(y^2 - 3x^2)(1 - z^2) + (x^2 + y^2)^2 - (9z^2 - 1)(1 - z^2),
+           the paper's implicit surface of genus 2; a bound once k makes the
+           gradient at most 1 over the region evaluated (Lipschitz normalisation)
 and combined by the minimum, which is the union of the shapes (Section 4.3).
 The paper's first scene holds sphere, cube, cone, cylinder, torus,
 hexagonal prism and capsule, each with a simple distance bound (Section 6.1).
@@ -30,7 +33,7 @@ op order is documented beside each twin function.
 import numpy as np
 
 PRIM_SPHERE, PRIM_BOX, PRIM_TORUS, PRIM_CAPSULE, PRIM_PLANE, PRIM_BOXBOUND = 0, 1, 2, 3, 4, 5
-PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM = 6, 7, 8
+PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM, PRIM_GENUS2 = 6, 7, 8, 9
 
 
 # ------------------------------------------------------------------------- FP64
@@ -69,7 +72,27 @@ def prim_f64(rec, P):
         s3 = np.sqrt(3.0) / 2.0
         faces = [np.abs(q[:, 0]), np.abs(0.5 * q[:, 0] + s3 * q[:, 1]), np.abs(s3 * q[:, 1] - 0.5 * q[:, 0])]
         return np.maximum(np.max(np.stack(faces), axis=0) - a0, np.abs(q[:, 2]) - a1)
+    if t == PRIM_GENUS2:
+        return a0 * genus2_f64(q[:, 0], q[:, 1], q[:, 2])
     raise ValueError(f"unknown primitive type {t}")
+
+
+def genus2_f64(x, y, z):
+    """The implicit function of the paper's genus-2 surface (Section 6.1)."""
+    return 2 * y * (y * y - 3 * x * x) * (1 - z * z) + (x * x + y * y) ** 2 - (9 * z * z - 1) * (1 - z * z)
+
+
+def genus2_gradient_bound(B):
+    """An upper bound of |grad F| for the genus-2 function over the cube
+    |x|, |y|, |z| <= B: each partial derivative, expanded into monomials,
+    is at most the sum of its coefficients' magnitudes times B^degree,
+      F_x = -12xy + 12xyz^2 + 4x^3 + 4xy^2              <= 12B^2 + 8B^3 + 12B^4
+      F_y = 6y^2 - 6y^2z^2 - 6x^2 + 6x^2z^2 + 4x^2y + 4y^3 <= 12B^2 + 8B^3 + 12B^4
+      F_z = -4y^3z + 12x^2yz - 20z + 36z^3               <= 20B + 36B^3 + 16B^4
+    and |grad F| <= the norm of the three."""
+    fx = 12 * B ** 2 + 8 * B ** 3 + 12 * B ** 4
+    fz = 20 * B + 36 * B ** 3 + 16 * B ** 4
+    return float(np.sqrt(2 * fx * fx + fz * fz))
 
 
 def union_f64(recs, P):
@@ -98,6 +121,8 @@ def prim_f32(rec, x, y, z):
     cone:    rho = sqrt(q_x*q_x + q_y*q_y);  max(rho*c - (a - q_z)*s, |q_z| - a)
     hexprism: h_x = 0.5*q_x, h_y = S*q_y with S = float32(sqrt(3)/2);
              max(|q_x| - r, max(|h_x + h_y| - r, max(|h_y - h_x| - r, |q_z| - a)))
+    genus2:  x2 = q_x*q_x (y2, z2 alike), w = 1 - z2, r2 = x2 + y2;
+             ((((2*q_y)*(y2 - 3*x2))*w + r2*r2) - (9*z2 - 1)*w) * k
     """
     rec = np.asarray(rec, dtype=np.float32)
     t = int(rec[0])
@@ -136,6 +161,12 @@ def prim_f32(rec, x, y, z):
         hx, hy = np.float32(0.5) * qx, np.float32(np.sqrt(3.0) / 2.0) * qy
         u1, u2, u3 = np.abs(qx) - a0, np.abs(hx + hy) - a0, np.abs(hy - hx) - a0
         return np.maximum(u1, np.maximum(u2, np.maximum(u3, np.abs(qz) - a1)))
+    if t == PRIM_GENUS2:
+        x2, y2, z2 = qx * qx, qy * qy, qz * qz
+        w = np.float32(1) - z2
+        r2 = x2 + y2
+        f = (((np.float32(2) * qy) * (y2 - np.float32(3) * x2)) * w + r2 * r2) - (np.float32(9) * z2 - np.float32(1)) * w
+        return f * a0
     raise ValueError(f"unknown primitive type {t}")
 
 

@@ -301,7 +301,7 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
   for (int p = 0; p < np; ++p) {
     const float* r = spec_h->prims_h + (size_t)p * GH_PRIM_FLOATS;
     const float t = r[0];
-    if (!(t >= 0.f && t <= 8.f && t == floorf(t)))
+    if (!(t >= 0.f && t <= 9.f && t == floorf(t)))
       return fail(GH_EINVAL, "primitive %d has unknown type %g", p, (double)t);
     // Bounded magnitudes keep every intermediate finite or +inf, never NaN:
     // |M q| <= 3e33 and sums of squares can only overflow towards +inf.

@@ -23,7 +23,8 @@ enum : int {
   kPrimBoxBound = 5,
   kPrimCylinder = 6,
   kPrimCone = 7,
-  kPrimHexPrism = 8
+  kPrimHexPrism = 8,
+  kPrimGenus2 = 9
 };
 
 struct Grid {
@@ -84,6 +85,11 @@ constexpr float kHopRootMinH = 0x1p-20f;
 //            (apex at local z = a, half-angle with sine s and cosine c, cut at z = -a)
 //   hexprism hx = qx/2, hy = (sqrt 3/2) qy;  max(|qx| - r, max(|hx + hy| - r,
 //            max(|hy - hx| - r, |qz| - a)))                 (apothem r, axis local z)
+//   genus2   k F(q), F = 2y(y^2 - 3x^2)(1 - z^2) + (x^2 + y^2)^2 - (9z^2 - 1)(1 - z^2)
+//            (Section 6.1's implicit surface of genus 2; k normalises the
+//            gradient over the grid to at most 1):  x2 = qx qx, y2, z2 alike,
+//            w = 1 - z2;  ((((2 qy) (y2 - 3 x2)) w + (x2 + y2)(x2 + y2))
+//            - (9 z2 - 1) w) k
 // The type is a template argument: callers loop over primitives grouped by
 // type, so no branch on the type sits inside the loop.  kHopRoot: the roots
 // are taken by sqrt_hop (hop decisions only; the values themselves may differ
@@ -114,6 +120,11 @@ __device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
     } else if constexpr (T == kPrimCone) {
       const float rho = root(qx * qx + qy * qy);
       return fmaxf(rho * r[15] - (r[13] - qz) * r[14], fabsf(qz) - r[13]);
+    } else if constexpr (T == kPrimGenus2) {
+      const float x2 = qx * qx, y2 = qy * qy, z2 = qz * qz, w = 1.f - z2;
+      const float r2 = x2 + y2;
+      const float f = (((2.f * qy) * (y2 - 3.f * x2)) * w + r2 * r2) - (9.f * z2 - 1.f) * w;
+      return f * r[13];
     } else if constexpr (T == kPrimHexPrism) {
       const float hx = 0.5f * qx, hy = 0.866025403784438646f * qy;
       const float u1 = fabsf(qx) - r[13], u2 = fabsf(hx + hy) - r[13], u3 = fabsf(hy - hx) - r[13];
@@ -131,7 +142,7 @@ __device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
   }
 }
 
-constexpr int kPrimTypes = 9;
+constexpr int kPrimTypes = 10;
 constexpr int kAllTypes = (1 << kPrimTypes) - 1;  // type mask with every type
 
 // Primitives sorted by type: group t occupies records [start[t], start[t+1]).
@@ -165,6 +176,8 @@ __device__ __forceinline__ float union_strided(const PrimGroups& g, Rec rec, int
   for_prims_of_type<kPrimCone>(g, first, step, [&](int p) { f = fminf(f, prim_eval_t<kPrimCone>(rec(p), x, y, z)); });
   for_prims_of_type<kPrimHexPrism>(g, first, step,
                                    [&](int p) { f = fminf(f, prim_eval_t<kPrimHexPrism>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimGenus2>(g, first, step,
+                                 [&](int p) { f = fminf(f, prim_eval_t<kPrimGenus2>(rec(p), x, y, z)); });
   return f;
 }
 

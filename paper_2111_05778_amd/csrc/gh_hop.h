@@ -94,6 +94,8 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
     if constexpr (kTypes & (1 << kPrimCone)) v[kPrimCone] = prim_eval_t<kPrimCone, true>(rec[kPrimCone], x, y, z);
     if constexpr (kTypes & (1 << kPrimHexPrism))
       v[kPrimHexPrism] = prim_eval_t<kPrimHexPrism, true>(rec[kPrimHexPrism], x, y, z);
+    if constexpr (kTypes & (1 << kPrimGenus2))
+      v[kPrimGenus2] = prim_eval_t<kPrimGenus2, true>(rec[kPrimGenus2], x, y, z);
 #pragma unroll
     for (int t = 0; t < kPrimTypes; ++t)
       if ((kTypes >> t) & 1) f = has[t] ? fminf(f, v[t]) : f;

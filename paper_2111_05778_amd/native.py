@@ -63,7 +63,7 @@ TUNING_FIELDS = ("hop_lanes_per_ray", "scan_blocks_per_cu", "batch_rays_per_item
 
 
 class gh_sdb_desc(ctypes.Structure):
-    _fields_ = [("opaque", ctypes.c_uint64 * 24)]
+    _fields_ = [("opaque", ctypes.c_uint64 * 32)]
 
 
 class gh_batch_item(ctypes.Structure):

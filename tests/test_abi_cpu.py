@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(N.gh_counters) == 64
     assert ctypes.sizeof(N.gh_grid) == 12
-    assert ctypes.sizeof(N.gh_sdb_desc) == 192
+    assert ctypes.sizeof(N.gh_sdb_desc) == 256
 
 
 def test_workspace_size_grows_with_grid_and_cap():
@@ -73,7 +73,12 @@ def test_describe_size_query_and_validation():
     assert N.lib.sdb_describe(ctypes.byref(s), None, 0, ctypes.byref(need), None, None) == N.GH_OK
     assert need.value == 12 * 16 * 4
     bad = keep.copy()
-    bad[3, 0] = 9.0                       # unknown primitive type
+    for t in (10.0, 2.5, -1.0):            # unknown primitive types
+        bad[3, 0] = t
+        s2, keep2 = _spec(bad)
+        assert N.lib.sdb_describe(ctypes.byref(s2), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
+    bad = W.cone_scene(0.2, 0.4).copy()
+    bad[0, 14:16] = (0.8, 0.8)            # a cone whose (sin, cos) is longer than a unit vector
     s2, keep2 = _spec(bad)
     assert N.lib.sdb_describe(ctypes.byref(s2), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
     bad = keep.copy()

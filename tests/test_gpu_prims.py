@@ -87,7 +87,8 @@ def _named_scene(scene):
             "boxbound": W.box_scene((0.31, 0.2, 0.45), (0.05, -0.1, 0.02), bound=True),
             "cylinder": W.cylinder_scene(0.37, 0.29, (0.03, -0.05, 0.01)),
             "cone": W.cone_scene(0.41, 0.45, (-0.02, 0.04, 0.0)),
-            "hexprism": W.hexprism_scene(0.33, 0.27, (0.02, 0.01, -0.03))}.get(scene)
+            "hexprism": W.hexprism_scene(0.33, 0.27, (0.02, 0.01, -0.03)),
+            "genus2": W.genus2_scene()}.get(scene)
     if recs is None and scene.startswith("prims"):
         recs = W.primitives_scene(int(scene[5:]))
     if recs is None:
@@ -97,7 +98,8 @@ def _named_scene(scene):
 
 @pytest.mark.parametrize("scene,n", [("sphere", 64), ("csg0", 64), ("csg1", 100), ("csg2", 37), ("csg0", 128),
                                      ("box", 50), ("boxbound", 33), ("csg3", 1), ("csg4", 2), ("cylinder", 64),
-                                     ("cone", 57), ("hexprism", 64), ("prims0", 128), ("prims1", 75)])
+                                     ("cone", 57), ("hexprism", 64), ("prims0", 128), ("prims1", 75),
+                                     ("genus2", 48), ("genus2", 64)])
 def test_matches_fp32_twin(gh, scene, n):
     recs = _named_scene(scene)
     g = W.grid(n)
@@ -171,7 +173,7 @@ def test_sphere_n64_against_fp64_oracle(gh):
     assert abs(area - math.pi) < 5e-3
 
 
-@pytest.mark.parametrize("scene,n", [("sphere", 48), ("csg0", 64), ("csg1", 77), ("prims0", 96)])
+@pytest.mark.parametrize("scene,n", [("sphere", 48), ("csg0", 64), ("csg1", 77), ("prims0", 96), ("genus2", 40)])
 def test_dense_equals_hop(gh, scene, n):
     recs = _named_scene(scene)
     g = W.grid(n)

@@ -269,3 +269,39 @@ def test_new_primitives_are_distance_bounds():
         f = sdb.union_f64(recs, Q)
         dist = np.min(np.linalg.norm(Q[:, None, :] - surf[None, :, :], axis=2), axis=1)
         assert np.all(np.abs(f) <= dist + 2e-3), np.max(np.abs(f) - dist)
+
+
+def test_genus2_function_and_bound():
+    # the polynomial of the paper's genus-2 surface (Section 6.1) at points
+    # worked by hand: F(0,0,0) = 1, F(1,0,0) = 2, zeros at (0,-1,0) (z = 0
+    # leaves y^4 + 2y^3 + 1, zero at y = -1) and at the poles (0,0,+-1)
+    x = np.array([0.0, 1.0, 0.0, 0.0, 0.0])
+    y = np.array([0.0, 0.0, -1.0, 0.0, 0.0])
+    z = np.array([0.0, 0.0, 0.0, 1.0, -1.0])
+    np.testing.assert_array_equal(sdb.genus2_f64(x, y, z), [1.0, 2.0, 0.0, 0.0, 0.0])
+    # the gradient bound holds over the cube (central differences at random
+    # points and at the corners, where the quartic terms peak)
+    B = 2.2
+    rng = np.random.default_rng(11)
+    P = np.concatenate([rng.uniform(-B, B, (200000, 3)),
+                        np.array(np.meshgrid(*3 * [[-B, B]], indexing="ij")).reshape(3, -1).T])
+    e = 1e-6
+    g = np.stack([(sdb.genus2_f64(*(P + e * np.eye(3)[i]).T) - sdb.genus2_f64(*(P - e * np.eye(3)[i]).T)) / (2 * e)
+                  for i in range(3)], axis=1)
+    L = sdb.genus2_gradient_bound(B)
+    assert np.linalg.norm(g, axis=1).max() <= L
+    # the scene's factor is 1 / (s L) over the cube holding the grid's local points
+    rec = W.genus2_scene()[0]
+    s = W.GENUS2_SCALE
+    Bg = s * (1.0 + W.GENUS2_CENTRE[1])
+    assert np.isclose(float(rec[13]), 1.0 / (s * sdb.genus2_gradient_bound(Bg)), rtol=1e-6)
+    # which makes it 1-Lipschitz on the grid: |f(q)| <= |f(z)| + |q - z| for
+    # sampled points z where f nearly vanishes
+    S = sdb.SDB.prims(W.genus2_scene())
+    Q = rng.uniform(-1, 1, (20000, 3))
+    f = S.f64(Q)
+    near = np.abs(f) < 2e-5
+    zeros, fz = Q[near], np.abs(f[near])
+    assert len(zeros) > 10
+    for q, v in zip(Q[:500], f[:500]):
+        assert abs(v) <= (np.linalg.norm(zeros - q, axis=1) + fz).min() + 1e-12

@@ -25,6 +25,8 @@ Primitive record layout (float32, PRIM_STRIDE = 16 per primitive):
                                 half-angle sin s, cos c; cut at z = -a
           hexprism  (r, a, 0)   apothem r, faces normal to local x and at
                                 +-60 degrees from it; capped at z = -a, a
+          genus2    (k, 0, 0)   k F(q) with the genus-2 polynomial F of the
+                                paper's Section 6.1; M = s I scales it
 """
 import json
 import os
@@ -32,7 +34,7 @@ import os
 import numpy as np
 
 PRIM_SPHERE, PRIM_BOX, PRIM_TORUS, PRIM_CAPSULE, PRIM_PLANE, PRIM_BOXBOUND = 0, 1, 2, 3, 4, 5
-PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM = 6, 7, 8
+PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM, PRIM_GENUS2 = 6, 7, 8, 9
 PRIM_STRIDE = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -104,6 +106,28 @@ def cone_scene(a, half_angle, centre=(0.0, 0.0, 0.0)):
 def hexprism_scene(r, a, centre=(0.0, 0.0, 0.0)):
     """Hexagonal prism of apothem r about the z axis, capped at +-a."""
     return _record(PRIM_HEXPRISM, centre, np.eye(3), (r, a))[None, :]
+
+
+GENUS2_SCALE = 1.8              # local q = s (p - c): the shape spans x in [-1.6, 1.6], y in [-1.82, 0.98]
+GENUS2_CENTRE = (0.0, 0.42 / 1.8, 0.0)
+
+
+def genus2_scene(lo=-1.0, extent=2.0):
+    """The paper's implicit surface of genus 2 (Section 6.1) in the grid
+    [lo, lo + extent]^3: q = s (p - c) with s = 1.8 and c = (0, 0.42/s, 0)
+    centre the shape, and the factor k = 1 / (s L) makes the bound
+    1-Lipschitz in p, L = sqrt(2 Fx^2 + Fz^2) with Fx = 12B^2 + 8B^3 + 12B^4
+    and Fz = 20B + 36B^3 + 16B^4 bounding |grad F| (sums of the
+    monomials' magnitudes) over the cube |q_i| <= B that holds every local
+    point of the grid."""
+    s = GENUS2_SCALE
+    c = np.asarray(GENUS2_CENTRE, dtype=np.float64)
+    far = np.maximum(np.abs(lo - c), np.abs(lo + extent - c)).max()
+    B = s * far
+    fx = 12 * B ** 2 + 8 * B ** 3 + 12 * B ** 4
+    fz = 20 * B + 36 * B ** 3 + 16 * B ** 4
+    k = 1.0 / (s * np.sqrt(2 * fx * fx + fz * fz))
+    return _record(PRIM_GENUS2, c, s * np.eye(3), (k,))[None, :]
 
 
 def primitives_scene(seed=0):
