@@ -102,8 +102,8 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
 /* Primitive record: 16 float32 values.
  *  [0] type: 0 sphere, 1 box (exact), 2 torus, 3 capsule, 4 plane,
  *            5 box bound (max of six face planes, Section 4.2 eq. boxdist),
- *            6 cylinder, 7 cone, 8 hexagonal prism (Section 6.1's primitives),
- *            9 the implicit surface of genus 2 of Section 6.1, scaled
+ *            6 cylinder, 7 cone, 8 hexagonal prism (Section 5.1's primitives),
+ *            9 the implicit surface of genus 2 of Section 5.1, scaled
  *  [1..3] centre c;  [4..12] 3x3 matrix M row-major, local q = M (p - c)
  *  [13..15] sphere (r), box/box bound (bx, by, bz), torus (R, r) about local y,
  *           capsule (a, r) on local z in [-a, a], plane (d) with f = M_row0 . p - d,

@@ -23,7 +23,7 @@ Primitive distances are written from geometry:
            gradient at most 1 over the region evaluated (Lipschitz normalisation)
 and combined by the minimum, which is the union of the shapes (Section 4.3).
 The paper's first scene holds sphere, cube, cone, cylinder, torus,
-hexagonal prism and capsule, each with a simple distance bound (Section 6.1).
+hexagonal prism and capsule, each with a simple distance bound (Section 5.1).
 
 The FP32 twin evaluates the same expressions in numpy float32 in a fixed
 order, one rounding per operation and no fused multiply-add; numpy's float32
@@ -78,7 +78,7 @@ def prim_f64(rec, P):
 
 
 def genus2_f64(x, y, z):
-    """The implicit function of the paper's genus-2 surface (Section 6.1)."""
+    """The implicit function of the paper's genus-2 surface (Section 5.1)."""
     return 2 * y * (y * y - 3 * x * x) * (1 - z * z) + (x * x + y * y) ** 2 - (9 * z * z - 1) * (1 - z * z)
 
 

@@ -86,7 +86,7 @@ constexpr float kHopRootMinH = 0x1p-20f;
 //   hexprism hx = qx/2, hy = (sqrt 3/2) qy;  max(|qx| - r, max(|hx + hy| - r,
 //            max(|hy - hx| - r, |qz| - a)))                 (apothem r, axis local z)
 //   genus2   k F(q), F = 2y(y^2 - 3x^2)(1 - z^2) + (x^2 + y^2)^2 - (9z^2 - 1)(1 - z^2)
-//            (Section 6.1's implicit surface of genus 2; k normalises the
+//            (Section 5.1's implicit surface of genus 2; k normalises the
 //            gradient over the grid to at most 1):  x2 = qx qx, y2, z2 alike,
 //            w = 1 - z2;  ((((2 qy) (y2 - 3 x2)) w + (x2 + y2)(x2 + y2))
 //            - (9 z2 - 1) w) k

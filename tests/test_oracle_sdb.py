@@ -272,7 +272,7 @@ def test_new_primitives_are_distance_bounds():
 
 
 def test_genus2_function_and_bound():
-    # the polynomial of the paper's genus-2 surface (Section 6.1) at points
+    # the polynomial of the paper's genus-2 surface (Section 5.1) at points
     # worked by hand: F(0,0,0) = 1, F(1,0,0) = 2, zeros at (0,-1,0) (z = 0
     # leaves y^4 + 2y^3 + 1, zero at y = -1) and at the poles (0,0,+-1)
     x = np.array([0.0, 1.0, 0.0, 0.0, 0.0])

@@ -26,7 +26,7 @@ Primitive record layout (float32, PRIM_STRIDE = 16 per primitive):
           hexprism  (r, a, 0)   apothem r, faces normal to local x and at
                                 +-60 degrees from it; capped at z = -a, a
           genus2    (k, 0, 0)   k F(q) with the genus-2 polynomial F of the
-                                paper's Section 6.1; M = s I scales it
+                                paper's Section 5.1; M = s I scales it
 """
 import json
 import os
@@ -113,7 +113,7 @@ GENUS2_CENTRE = (0.0, 0.42 / 1.8, 0.0)
 
 
 def genus2_scene(lo=-1.0, extent=2.0):
-    """The paper's implicit surface of genus 2 (Section 6.1) in the grid
+    """The paper's implicit surface of genus 2 (Section 5.1) in the grid
     [lo, lo + extent]^3: q = s (p - c) with s = 1.8 and c = (0, 0.42/s, 0)
     centre the shape, and the factor k = 1 / (s L) makes the bound
     1-Lipschitz in p, L = sqrt(2 Fx^2 + Fz^2) with Fx = 12B^2 + 8B^3 + 12B^4
@@ -131,7 +131,7 @@ def genus2_scene(lo=-1.0, extent=2.0):
 
 
 def primitives_scene(seed=0):
-    """The paper's first scene's seven primitives (Section 6.1: sphere,
+    """The paper's first scene's seven primitives (Section 5.1: sphere,
     cube, cone, cylinder, torus, hexagonal prism, capsule), each seeded in
     its own slot of a 3 x 3 layout in the z = 0 plane (the centre slot and
     one corner stay empty), with a rotation from a normalised N(0, I_4)
