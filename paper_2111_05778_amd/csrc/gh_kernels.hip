@@ -208,9 +208,9 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
   // Register-record kernels take the hop square root: only where it gives
   // the exact root's decisions.
   const bool regs = most <= R && (d.flags & kSdbRadiiNormal) && g.h >= kHopRootMinH;
-  // Unions without planes and box bounds (the solids plus cylinders, cones
-  // and hexagonal prisms) get a kernel that skips those two.
-  constexpr int kNoPlanes = kAllTypes & ~((1 << kPrimPlane) | (1 << kPrimBoxBound));
+  // Unions of the solids, cylinders, cones and hexagonal prisms (the paper's
+  // primitives) get a kernel that skips the other types.
+  constexpr int kNoPlanes = kSolids | (1 << kPrimCylinder) | (1 << kPrimCone) | (1 << kPrimHexPrism);
   if (regs && (present & ~kSolids) == 0) {
     hipLaunchKernelGGL((k_hop_prims<R, true, kSolids>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
                        ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
