@@ -12,6 +12,8 @@ Modules
   hop     grid hopping over the N^2 ray columns, with evaluation counters
   traced  the paper's per-column procedure taken literally: continuous
           sphere tracing to the polygonization distance (Algorithm 1)
+  cont    continuation, the paper's surface-following comparator: from seed
+          cells to face neighbours across faces the surface crosses
   mesh    mesh checks: manifoldness, Euler characteristic, area, volume,
           Hausdorff distance
   adjoint analytic FP64 gradient of a vertex loss w.r.t. network parameters,
