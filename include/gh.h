@@ -176,7 +176,28 @@ gh_status gh_hop(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, siz
 gh_status gh_hop_traced(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
                         int64_t corner_cap, gh_counters* ctr, void* stream);
 
-/* Marching cubes on the cells recorded in ws by gh_hop, gh_hop_traced or gh_dense
+/* Bytes of the continuation workspace for this grid with room for
+ * frontier_cap cells per level (frontier_cap <= 0 selects 16*(n+1)^2). */
+gh_status gh_cont_workspace_size(const gh_grid* grid_h, int64_t frontier_cap, size_t* bytes_h);
+
+/* Continuation, the paper's surface-following comparator (Section 2): from
+ * the seed cells (device list of n_seeds cell ids (i*n + j)*n + k; ids outside
+ * the grid are ignored) the search moves to every face neighbour behind a
+ * face whose four corners do not share one sign, until no new cell appears.
+ * It reaches every sign-change cell of each surface component holding a
+ * seed, and only sign-change cells besides the seeds.  The cells reached go
+ * to ws as candidates (gh_mc can follow); n_hop_evals counts the distinct
+ * lattice points evaluated and n_cand the cells.  cws: device, 256-byte
+ * aligned, cws_bytes >= gh_cont_workspace_size.  GH_FLAG_CAPACITY when a
+ * level held more than frontier_cap cells (the search then stops).  Runs one
+ * kernel per level and waits for each on `stream`: the call returns when the
+ * search is done; *levels_h (may be NULL) receives the number of levels.
+ * Analytic bounds only (GH_EUNSUPPORTED for a network). */
+gh_status gh_cont(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
+                  void* cws, size_t cws_bytes, int64_t frontier_cap, const int64_t* seeds, int64_t n_seeds,
+                  gh_counters* ctr, int64_t* levels_h, void* stream);
+
+/* Marching cubes on the cells recorded in ws by gh_hop, gh_hop_traced, gh_cont or gh_dense
  * (Section 5: every reached cell is polygonized by marching cubes).
  * Evaluates the bound once per distinct corner point, welds one vertex per
  * crossing lattice edge and writes:

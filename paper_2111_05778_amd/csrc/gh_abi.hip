@@ -449,6 +449,41 @@ gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size
                     "mc");
 }
 
+gh_status gh_cont_workspace_size(const gh_grid* grid_h, int64_t frontier_cap, size_t* bytes_h) {
+  gh::Grid g;
+  gh_status st = read_grid(grid_h, &g);
+  if (st != GH_OK) return st;
+  if (!bytes_h) return fail(GH_EINVAL, "bytes_h is NULL");
+  if (frontier_cap <= 0) frontier_cap = default_cap(g.n);
+  *bytes_h = gh::cont_layout(g.n, frontier_cap, nullptr, nullptr);
+  return GH_OK;
+}
+
+gh_status gh_cont(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
+                  void* cws, size_t cws_bytes, int64_t frontier_cap, const int64_t* seeds, int64_t n_seeds,
+                  gh_counters* ctr, int64_t* levels_h, void* stream) {
+  gh::DevSdb d;
+  gh::Grid g;
+  gh::Workspace w;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if (d.kind != GH_SDB_PRIMS) return fail(GH_EUNSUPPORTED, "gh_cont takes analytic bounds only");
+  if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
+  if ((st = carve(g, ws, ws_bytes, corner_cap, &w)) != GH_OK) return st;
+  if (!ctr || !cws) return fail(GH_EINVAL, "counters or continuation workspace are NULL");
+  if (((uintptr_t)cws) & 255) return fail(GH_EINVAL, "continuation workspace must be 256-byte aligned");
+  if (frontier_cap <= 0) frontier_cap = default_cap(g.n);
+  gh::ContWorkspace cw;
+  const size_t need = gh::cont_layout(g.n, frontier_cap, &cw, cws);
+  if (cws_bytes < need) return fail(GH_ECAPACITY, "continuation workspace of %zu bytes, %zu needed", cws_bytes, need);
+  if (n_seeds < 0 || n_seeds > frontier_cap) return fail(GH_EINVAL, "n_seeds = %lld must be in [0, frontier_cap]",
+                                                         (long long)n_seeds);
+  if (n_seeds > 0 && !seeds) return fail(GH_EINVAL, "seeds are NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearAll, s), "clear")) != GH_OK) return st;
+  return hip_status(gh::run_cont(d, g, w, cw, seeds, n_seeds, ctr, levels_h, s), "continuation");
+}
+
 gh_status gh_candidates(const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap, int64_t* out,
                         int64_t cap, gh_counters* ctr, void* stream) {
   gh::Grid g;

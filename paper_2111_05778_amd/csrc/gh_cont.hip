@@ -1,0 +1,191 @@
+// Continuation: the paper's surface-following comparator (Section 2,
+// "cont").  From seed cells the search moves to the face neighbours of each
+// cell it holds whose shared face has a sign change among its four corners,
+// level by level, until no new cell appears.  Every cell reached is a
+// sign-change cell; the set reached does not depend on the order.
+//
+// State in the caller's continuation workspace: a bitmap of reached cells
+// (N^3 bits), a bitmap of evaluated lattice points ((N+1)^3 bits, so that each
+// distinct corner counts as one evaluation) and two frontier lists.  The
+// host drives the levels: one kernel per level, then the next frontier's
+// length comes back to the host, which ends the loop when it is zero.  The
+// reached cells end as the candidate words of the hop workspace, so gh_mc
+// follows as after gh_hop.
+#include <hip/hip_runtime.h>
+
+#include <float.h>
+
+#include <algorithm>
+
+#include "gh_device.h"
+#include "gh_launch.h"
+#include "gh_layout.h"
+
+namespace gh {
+
+namespace {
+
+// Claims bit b of a bitmap; true for the one thread that set it.
+__device__ __forceinline__ bool claim(uint32_t* __restrict__ bits, int64_t b) {
+  const uint32_t m = 1u << (b & 31);
+  return (atomicOr(&bits[b >> 5], m) & m) == 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cont_seed(const int64_t* __restrict__ seeds, int64_t n_seeds, int n,
+                                                      uint32_t* __restrict__ reached, int64_t* __restrict__ front,
+                                                      unsigned long long* __restrict__ count) {
+  const int64_t ncell = (int64_t)n * n * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_seeds; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t id = seeds[t];
+    if (id < 0 || id >= ncell) continue;  // not a cell of the grid
+    if (claim(reached, id)) front[atomicAdd(count, 1ull)] = id;  // at most n_seeds <= capacity entries
+  }
+}
+
+// One level: every frontier cell evaluates its eight corners, counts those
+// evaluated for the first time, and adds each face neighbour behind a face
+// with a sign change that no one has reached yet to the next frontier.
+template <class Eval>
+__global__ __launch_bounds__(kBlock) void k_cont_level(Eval ev, Grid g, const int64_t* __restrict__ front,
+                                                       int64_t nfront, int64_t* __restrict__ next,
+                                                       unsigned long long* __restrict__ nnext, int64_t cap,
+                                                       uint32_t* __restrict__ reached, uint32_t* __restrict__ known,
+                                                       gh_counters* __restrict__ ctr) {
+  const int n = g.n;
+  const int64_t n1 = n + 1;
+  uint64_t evals = 0;
+  bool bad = false, full = false;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nfront; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t id = front[t];
+    const int i = (int)(id / ((int64_t)n * n)), j = (int)((id / n) % n), k = (int)(id % n);
+    unsigned neg = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int a = i + (c & 1), b = j + ((c >> 1) & 1), z = k + ((c >> 2) & 1);
+      const float f = ev(lattice(g, a), lattice(g, b), lattice(g, z));
+      bad = bad || !(fabsf(f) <= FLT_MAX);
+      neg |= (f < 0.f ? 1u : 0u) << c;
+      if (claim(known, ((int64_t)a * n1 + b) * n1 + z)) ++evals;
+    }
+    // faces: corners with bit d clear (lower side) or set (upper side) of axis d
+    constexpr unsigned kSide[3] = {0x55u, 0x33u, 0x0Fu};  // corners with bit 0, 1, 2 clear
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+      for (int up = 0; up < 2; ++up) {
+        const unsigned face = up ? (~kSide[d] & 0xFFu) : kSide[d];
+        const unsigned s = neg & face;
+        if (s == 0 || s == face) continue;  // no sign change on this face
+        const int ni = i + (d == 0 ? (up ? 1 : -1) : 0), nj = j + (d == 1 ? (up ? 1 : -1) : 0),
+                  nk = k + (d == 2 ? (up ? 1 : -1) : 0);
+        if (ni < 0 || ni >= n || nj < 0 || nj >= n || nk < 0 || nk >= n) continue;
+        const int64_t nb = ((int64_t)ni * n + nj) * n + nk;
+        if (claim(reached, nb)) {
+          const unsigned long long pos = atomicAdd(nnext, 1ull);
+          if ((int64_t)pos < cap) next[pos] = nb;
+          else full = true;
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(&ctr->flags, GH_FLAG_NONFINITE);
+  if (full) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+  block_add_u64(evals, (unsigned long long*)&ctr->n_hop_evals);
+}
+
+// The reached cells as the hop's candidate words: word w of column col holds
+// cells k = 32 w .. 32 w + 31, i.e. bits col n + 32 w .. of the cell bitmap.
+__global__ __launch_bounds__(kBlock) void k_cont_columns(int n, const uint32_t* __restrict__ reached,
+                                                         uint64_t* __restrict__ colmask,
+                                                         uint32_t* __restrict__ colbits,
+                                                         gh_counters* __restrict__ ctr) {
+  const int64_t ncol = (int64_t)n * n;
+  const int W = (n + 31) / 32;
+  uint64_t cands = 0;
+  for (int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; col < ncol; col += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t mask = 0;
+    for (int w = 0; w < W; ++w) {
+      const int64_t b0 = col * n + 32 * w;       // first bit of the word
+      const int len = std::min(32, n - 32 * w);  // cells of this column in the word
+      const int64_t q = b0 >> 5;
+      const int sh = (int)(b0 & 31);
+      uint64_t two = reached[q];
+      if (sh + len > 32) two |= (uint64_t)reached[q + 1] << 32;  // in bounds: the word holds a cell of this column
+      uint32_t word = (uint32_t)(two >> sh);
+      if (len < 32) word &= (1u << len) - 1u;
+      if (word) {
+        colbits[(size_t)w * ncol + col] = word;
+        mask |= 1ull << w;
+        cands += __popc(word);
+      }
+    }
+    colmask[col] = mask;
+  }
+  block_add_u64(cands, (unsigned long long*)&ctr->n_cand);
+}
+
+}  // namespace
+
+size_t cont_layout(int n, int64_t cap, ContWorkspace* cw, void* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const int64_t cells = (int64_t)n * n * n, pts = (int64_t)(n + 1) * (n + 1) * (n + 1);
+  const size_t o_reached = take((size_t)(cells / 32 + 1) * 4), o_known = take((size_t)(pts / 32 + 1) * 4),
+               o_a = take((size_t)cap * 8), o_b = take((size_t)cap * 8), o_count = take(2 * 8);
+  if (cw && base) {
+    char* b = (char*)base;
+    cw->reached = (uint32_t*)(b + o_reached);
+    cw->known = (uint32_t*)(b + o_known);
+    cw->front[0] = (int64_t*)(b + o_a);
+    cw->front[1] = (int64_t*)(b + o_b);
+    cw->count = (unsigned long long*)(b + o_count);
+    cw->reached_bytes = (size_t)(cells / 32 + 1) * 4;
+    cw->known_bytes = (size_t)(pts / 32 + 1) * 4;
+    cw->cap = cap;
+  }
+  return off;
+}
+
+hipError_t run_cont(const DevSdb& d, const Grid& g, const Workspace& ws, const ContWorkspace& cw,
+                    const int64_t* seeds, int64_t n_seeds, gh_counters* ctr, int64_t* levels, hipStream_t s) {
+  if (d.kind != GH_SDB_PRIMS) return hipErrorInvalidValue;
+  hipError_t e;
+  if ((e = hipMemsetAsync(cw.reached, 0, cw.reached_bytes, s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(cw.known, 0, cw.known_bytes, s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(cw.count, 0, 2 * sizeof(unsigned long long), s)) != hipSuccess) return e;
+  const int blocks = cu_count() * 8;
+  hipLaunchKernelGGL(k_cont_seed, dim3(blocks), dim3(kBlock), 0, s, seeds, n_seeds, g.n, cw.reached, cw.front[0],
+                     &cw.count[0]);
+  unsigned long long nfront = 0;
+  if ((e = hipMemcpyAsync(&nfront, &cw.count[0], sizeof(nfront), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  // Each level adds cells never reached before, so there are at most N^3 levels.
+  const int64_t max_levels = (int64_t)g.n * g.n * g.n + 1;
+  int cur = 0;
+  int64_t level = 0;
+  const PrimsEval ev{d.prims, d.groups};
+  while (nfront > 0 && level < max_levels) {
+    if ((e = hipMemsetAsync(&cw.count[1 - cur], 0, sizeof(unsigned long long), s)) != hipSuccess) return e;
+    const int64_t units = (int64_t)nfront;
+    const int grid = (int)std::min<int64_t>((units + kBlock - 1) / kBlock, (int64_t)blocks);
+    hipLaunchKernelGGL(k_cont_level<PrimsEval>, dim3(grid), dim3(kBlock), 0, s, ev, g, cw.front[cur], units,
+                       cw.front[1 - cur], &cw.count[1 - cur], cw.cap, cw.reached, cw.known, ctr);
+    if ((e = hipMemcpyAsync(&nfront, &cw.count[1 - cur], sizeof(nfront), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    ++level;
+    if ((int64_t)nfront > cw.cap) break;  // flagged by the kernel: the search stops incomplete
+    cur = 1 - cur;
+  }
+  if (levels) *levels = level;
+  const int64_t ncol = (int64_t)g.n * g.n;
+  hipLaunchKernelGGL(k_cont_columns, dim3((int)std::min<int64_t>((ncol + kBlock - 1) / kBlock, (int64_t)blocks)),
+                     dim3(kBlock), 0, s, g.n, cw.reached, ws.colmask, ws.colbits, ctr);
+  return hipGetLastError();
+}
+
+}  // namespace gh

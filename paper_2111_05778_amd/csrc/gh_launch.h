@@ -62,6 +62,24 @@ constexpr int32_t kSdbRadiiNormal = 1;
 
 enum ClearMode { kClearAll = 0, kClearMc = 1, kClearCands = 2 };
 
+// Continuation workspace (gh_cont): reached-cell and evaluated-point
+// bitmaps, two frontier lists of cap cell ids, two frontier counters.
+struct ContWorkspace {
+  uint32_t* reached;
+  uint32_t* known;
+  int64_t* front[2];
+  unsigned long long* count;
+  size_t reached_bytes, known_bytes;
+  int64_t cap;
+};
+// Layout of the continuation workspace for grid size n and frontier
+// capacity cap; fills cw when base is given.  Returns the bytes needed.
+size_t cont_layout(int n, int64_t cap, ContWorkspace* cw, void* base);
+// Continuation from the seed cells (device list) to the candidate words of
+// ws; host-driven levels, returns after the last one.  levels: out, may be null.
+hipError_t run_cont(const DevSdb& d, const Grid& g, const Workspace& ws, const ContWorkspace& cw,
+                    const int64_t* seeds, int64_t n_seeds, gh_counters* ctr, int64_t* levels, hipStream_t s);
+
 hipError_t launch_clear(const Workspace& ws, gh_counters* ctr, ClearMode mode, hipStream_t s);
 // lanes_per_ray: 1, 2, 3, 4 or 8 lanes trace one ray together (0 = chosen from the type groups).
 hipError_t launch_hop(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr, int lanes_per_ray,

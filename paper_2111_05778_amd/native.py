@@ -22,7 +22,7 @@ GH_PREC_FP32, GH_PREC_BF16, GH_PREC_BF16X3 = 0, 1, 2
 GH_ACT_SOFTPLUS, GH_ACT_RELU = 0, 1
 GH_PRIM_FLOATS = 16
 
-EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_hop_traced", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
+EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_hop_traced", "gh_cont_workspace_size", "gh_cont", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
            "gh_eval_points", "gh_set_tuning", "gh_get_tuning", "gh_param_count", "gh_backward_workspace_size",
            "gh_backward", "gh_batch_buffer_size", "gh_batch_create", "gh_batch_run", "gh_batch_capture",
            "gh_batch_replay", "gh_batch_item_count", "gh_batch_destroy", "gh_last_error"]
@@ -81,6 +81,8 @@ lib.sdb_describe.argtypes = [_P(gh_sdb_spec), _vp, _sz, _P(_sz), _P(gh_sdb_desc)
 lib.gh_workspace_size.argtypes = [_P(gh_grid), _i64, _P(_sz)]
 lib.gh_hop.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp]
 lib.gh_hop_traced.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp]
+lib.gh_cont_workspace_size.argtypes = [_P(gh_grid), _i64, _P(_sz)]
+lib.gh_cont.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _sz, _i64, _vp, _i64, _vp, _P(_i64), _vp]
 lib.gh_mc.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64,
                       _vp, _vp]
 lib.gh_dense.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp]
@@ -152,6 +154,21 @@ def gh_hop(desc, grid, ws, corner_cap, ctr, stream=None):
 def gh_hop_traced(desc, grid, ws, corner_cap, ctr, stream=None):
     return lib.gh_hop_traced(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
                              int(corner_cap), ptr(ctr), stream_handle(stream))
+
+
+def gh_cont_workspace_size(grid, frontier_cap=0):
+    out = _sz(0)
+    check(lib.gh_cont_workspace_size(ctypes.byref(grid), int(frontier_cap), ctypes.byref(out)), "gh_cont_workspace_size")
+    return out.value
+
+
+def gh_cont(desc, grid, ws, corner_cap, cws, frontier_cap, seeds, ctr, stream=None):
+    """Returns the number of levels."""
+    levels = _i64(0)
+    check(lib.gh_cont(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(), int(corner_cap),
+                      ptr(cws), cws.numel() * cws.element_size(), int(frontier_cap), ptr(seeds), seeds.numel(), ptr(ctr),
+                      ctypes.byref(levels), stream_handle(stream)), "gh_cont")
+    return levels.value
 
 
 def gh_dense(desc, grid, ws, corner_cap, signs, ctr, stream=None):

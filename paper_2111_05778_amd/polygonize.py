@@ -117,6 +117,7 @@ class Polygonizer:
         self.keep_cells, self.keep_edges = keep_cells, keep_edges
         self.ctr = torch.zeros(8, dtype=torch.int64, device=self.device)
         self.dense_buf = None
+        self._cws = None
         if tuning == "auto":
             from . import autotune
             tuning = autotune.lookup(autotune.signature(bound.spec, self.n), self.device) or {}
@@ -167,6 +168,17 @@ class Polygonizer:
         N.check(N.gh_hop_traced(self.bound.desc, self.grid, self.ws, self.corner_cap, self.ctr, stream),
                 "gh_hop_traced")
 
+    def enqueue_cont(self, seeds, frontier_cap=0, stream=None):
+        """Continuation (gh_cont) from seed cells, an int64 device tensor of
+        cell ids; analytic bounds only.  Blocks until the search is done and
+        returns its number of levels."""
+        self._apply_tuning()
+        nb = N.gh_cont_workspace_size(self.grid, frontier_cap)
+        if self._cws is None or self._cws.numel() < nb:
+            self._cws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        return N.gh_cont(self.bound.desc, self.grid, self.ws, self.corner_cap, self._cws, frontier_cap, seeds,
+                         self.ctr, stream)
+
     def enqueue_dense(self, stream=None):
         self._apply_tuning()
         if self.dense_buf is None:
@@ -199,10 +211,13 @@ class Polygonizer:
         self._graph.replay()
 
     # ------------------------------------------------------------ blocking
-    def run(self, dense=False, stream=None, max_retries=3, traced=False):
-        """Cells by grid hopping (or enumeration with dense, or the literal
-        traced procedure with traced), then marching cubes; blocks."""
+    def run(self, dense=False, stream=None, max_retries=3, traced=False, seeds=None):
+        """Cells by grid hopping (or enumeration with dense, the literal
+        traced procedure with traced, or continuation from the given seed
+        cells), then marching cubes; blocks."""
         first = self.enqueue_dense if dense else (self.enqueue_hop_traced if traced else self.enqueue_hop)
+        if seeds is not None:
+            first = lambda st: self.enqueue_cont(seeds, stream=st)  # noqa: E731
         for _ in range(max_retries + 1):
             first(stream)
             self.enqueue_mc(stream)
