@@ -23,6 +23,9 @@ Prints one JSON line.  Extra objects:
                 same network at N = 256, FP32 forward (milliseconds)
   batch         64 bounds on grids of 64..512, one persistent hop launch plus
                 marching cubes per shape, replayed from a hipGraph
+  cont          continuation (gh_cont, the paper's surface-following
+                comparator) on the headline workload from one seed per
+                surface component, with marching cubes
   primitives    the paper's first scene's seven primitive types (sphere,
                 cube, cone, cylinder, torus, hexagonal prism, capsule) at
                 N = 512, with the enumeration path beside it
@@ -293,6 +296,42 @@ def primitives_section(dev, steps, warmup, n=512, seed=0):
             "ops_per_eval": ops_per_eval(recs)}
 
 
+def cont_section(dev, steps, warmup, recs, n, lo, h, seed):
+    """Continuation (gh_cont, the paper's surface-following comparator) on
+    the headline workload, seeded with one cell per surface component (found
+    from the grid-hopping mesh before timing, as the paper assumes seeds are
+    given), followed by marching cubes.  gh_cont waits for each level, so it
+    is timed by the host clock."""
+    import numpy as np
+    import torch
+    from scipy import ndimage
+
+    from paper_2111_05778_amd.polygonize import Bound, Polygonizer, counters_dict
+    poly = Polygonizer(Bound.prims(recs, dev), n, lo, h, device=dev, keep_cells=True)
+    cells = poly.run().cells.cpu().numpy()
+    grid = np.zeros(n ** 3, dtype=bool)
+    grid[cells] = True
+    lab, k = ndimage.label(grid.reshape(n, n, n))
+    flat = lab.reshape(-1)
+    seeds = torch.tensor([int(np.flatnonzero(flat == c)[0]) for c in range(1, k + 1)], dtype=torch.int64, device=dev)
+    poly.run(seeds=seeds)
+    for _ in range(warmup):
+        poly.enqueue_cont(seeds)
+        poly.enqueue_mc()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        levels = poly.enqueue_cont(seeds)
+    torch.cuda.synchronize(dev)
+    cont_ms = (time.perf_counter() - t0) / steps * 1e3
+    mc_ms = event_ms(torch.cuda.current_stream(dev), poly.enqueue_mc, steps)
+    c = counters_dict(poly.ctr)
+    assert c["flags"] == 0
+    return {"workload": f"csg12_seed{seed}_n{n}", "components": int(k), "levels": levels, "cont_ms": cont_ms,
+            "mc_ms": mc_ms, "ms_per_step": cont_ms + mc_ms,
+            "counters": {kk: c[kk] for kk in ("n_hop_evals", "n_cand", "n_corner", "n_cells", "n_vert", "n_tri")}}
+
+
 def traced_section(dev, steps, warmup, recs, n, lo, h, seed):
     """The paper's per-column procedure taken literally (gh_hop_traced) on
     the headline workload: its times and counts beside grid hopping's, and
@@ -331,7 +370,7 @@ def main():
                          "that scales the HBM counters) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (built-in shapes)")
-    ap.add_argument("--sections", default="neural,paper_net,backward,batch,traced,primitives",
+    ap.add_argument("--sections", default="neural,paper_net,backward,batch,traced,cont,primitives",
                     help="extra workloads to measure after the headline one (comma list, or none)")
     args = ap.parse_args()
     sections = [x for x in args.sections.split(",") if x and x != "none"]
@@ -460,6 +499,8 @@ def main():
         out["backward_ms"] = out["backward"]["backward_ms"]
     if "batch" in sections:
         out["batch"] = batch_section(dev, max(3, args.steps // 4), sw, tune=not args.no_tune)
+    if "cont" in sections:
+        out["cont"] = cont_section(dev, max(3, args.steps // 4), sw, recs, n, lo, h, args.seed)
     if "primitives" in sections:
         out["primitives"] = primitives_section(dev, max(3, args.steps // 4), sw)
     if "traced" in sections:
