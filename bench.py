@@ -300,8 +300,8 @@ def cont_section(dev, steps, warmup, recs, n, lo, h, seed):
     """Continuation (gh_cont, the paper's surface-following comparator) on
     the headline workload, seeded with one cell per surface component (found
     from the grid-hopping mesh before timing, as the paper assumes seeds are
-    given), followed by marching cubes.  gh_cont waits for each level, so it
-    is timed by the host clock."""
+    given), followed by marching cubes.  gh_cont waits for each batch of
+    levels, so it is timed by the host clock."""
     import numpy as np
     import torch
     from scipy import ndimage

@@ -189,9 +189,11 @@ gh_status gh_cont_workspace_size(const gh_grid* grid_h, int64_t frontier_cap, si
  * to ws as candidates (gh_mc can follow); n_hop_evals counts the distinct
  * lattice points evaluated and n_cand the cells.  cws: device, 256-byte
  * aligned, cws_bytes >= gh_cont_workspace_size.  GH_FLAG_CAPACITY when a
- * level held more than frontier_cap cells (the search then stops).  Runs one
- * kernel per level and waits for each on `stream`: the call returns when the
- * search is done; *levels_h (may be NULL) receives the number of levels.
+ * level held more than frontier_cap cells (the search then goes on with the
+ * first frontier_cap of them and its result is incomplete).  Runs one kernel
+ * per level in batches and waits for each batch on `stream`: the call returns
+ * when the search is done; *levels_h (may be NULL) receives the number of
+ * levels.
  * Analytic bounds only (GH_EUNSUPPORTED for a network). */
 gh_status gh_cont(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes, int64_t corner_cap,
                   void* cws, size_t cws_bytes, int64_t frontier_cap, const int64_t* seeds, int64_t n_seeds,

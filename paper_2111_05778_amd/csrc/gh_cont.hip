@@ -7,8 +7,9 @@
 // State in the caller's continuation workspace: a bitmap of reached cells
 // (N^3 bits), a bitmap of evaluated lattice points ((N+1)^3 bits, so that each
 // distinct corner counts as one evaluation) and two frontier lists.  The
-// host drives the levels: one kernel per level, then the next frontier's
-// length comes back to the host, which ends the loop when it is zero.  The
+// host drives the levels: one kernel per level, enqueued in batches, each
+// reading its frontier's length on the device; after a batch the length
+// comes back to the host, which ends the loop when it is zero.  The
 // reached cells end as the candidate words of the hop workspace, so gh_mc
 // follows as after gh_hop.
 #include <hip/hip_runtime.h>
@@ -47,12 +48,21 @@ __global__ __launch_bounds__(kBlock) void k_cont_seed(const int64_t* __restrict_
 // with a sign change that no one has reached yet to the next frontier.
 template <class Eval>
 __global__ __launch_bounds__(kBlock) void k_cont_level(Eval ev, Grid g, const int64_t* __restrict__ front,
-                                                       int64_t nfront, int64_t* __restrict__ next,
+                                                       const unsigned long long* __restrict__ nfront_d,
+                                                       int64_t* __restrict__ next,
                                                        unsigned long long* __restrict__ nnext, int64_t cap,
                                                        uint32_t* __restrict__ reached, uint32_t* __restrict__ known,
+                                                       unsigned long long* __restrict__ levels,
+                                                       unsigned long long* __restrict__ clear,
                                                        gh_counters* __restrict__ ctr) {
   const int n = g.n;
   const int64_t n1 = n + 1;
+  // the frontier's length, as the previous level left it (held to the list's capacity)
+  const int64_t nfront = (int64_t)*nfront_d < cap ? (int64_t)*nfront_d : cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (nfront > 0) atomicAdd(levels, 1ull);
+    *clear = 0;  // the counter the next level fills (read by the previous one, which has finished)
+  }
   uint64_t evals = 0;
   bool bad = false, full = false;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nfront; t += (int64_t)gridDim.x * blockDim.x) {
@@ -135,7 +145,7 @@ size_t cont_layout(int n, int64_t cap, ContWorkspace* cw, void* base) {
   };
   const int64_t cells = (int64_t)n * n * n, pts = (int64_t)(n + 1) * (n + 1) * (n + 1);
   const size_t o_reached = take((size_t)(cells / 32 + 1) * 4), o_known = take((size_t)(pts / 32 + 1) * 4),
-               o_a = take((size_t)cap * 8), o_b = take((size_t)cap * 8), o_count = take(2 * 8);
+               o_a = take((size_t)cap * 8), o_b = take((size_t)cap * 8), o_count = take(4 * 8);
   if (cw && base) {
     char* b = (char*)base;
     cw->reached = (uint32_t*)(b + o_reached);
@@ -156,32 +166,41 @@ hipError_t run_cont(const DevSdb& d, const Grid& g, const Workspace& ws, const C
   hipError_t e;
   if ((e = hipMemsetAsync(cw.reached, 0, cw.reached_bytes, s)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(cw.known, 0, cw.known_bytes, s)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(cw.count, 0, 2 * sizeof(unsigned long long), s)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(cw.count, 0, 4 * sizeof(unsigned long long), s)) != hipSuccess) return e;
   const int blocks = cu_count() * 8;
   hipLaunchKernelGGL(k_cont_seed, dim3(blocks), dim3(kBlock), 0, s, seeds, n_seeds, g.n, cw.reached, cw.front[0],
                      &cw.count[0]);
-  unsigned long long nfront = 0;
-  if ((e = hipMemcpyAsync(&nfront, &cw.count[0], sizeof(nfront), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  // Each level adds cells never reached before, so there are at most N^3 levels.
-  const int64_t max_levels = (int64_t)g.n * g.n * g.n + 1;
-  int cur = 0;
-  int64_t level = 0;
+  // Levels are enqueued in batches: each level reads its frontier's length
+  // on the device (a level past the end finds it zero and does nothing), so
+  // the host waits once per batch instead of once per level.  Level l reads
+  // counter l mod 3, fills counter (l + 1) mod 3 and clears (l + 2) mod 3 for
+  // the level after it.  Every level with a frontier holds cells no earlier
+  // level held, so N^3 levels bound the loop.
+  constexpr int kBatch = 16;
+  const int64_t max_levels = (int64_t)g.n * g.n * g.n + kBatch;
   const PrimsEval ev{d.prims, d.groups};
-  while (nfront > 0 && level < max_levels) {
-    if ((e = hipMemsetAsync(&cw.count[1 - cur], 0, sizeof(unsigned long long), s)) != hipSuccess) return e;
-    const int64_t units = (int64_t)nfront;
-    const int grid = (int)std::min<int64_t>((units + kBlock - 1) / kBlock, (int64_t)blocks);
-    hipLaunchKernelGGL(k_cont_level<PrimsEval>, dim3(grid), dim3(kBlock), 0, s, ev, g, cw.front[cur], units,
-                       cw.front[1 - cur], &cw.count[1 - cur], cw.cap, cw.reached, cw.known, ctr);
-    if ((e = hipMemcpyAsync(&nfront, &cw.count[1 - cur], sizeof(nfront), hipMemcpyDeviceToHost, s)) != hipSuccess)
+  const int lgrid = cu_count();
+  for (int64_t level = 0; level < max_levels; level += kBatch) {
+    for (int b = 0; b < kBatch; ++b) {
+      const int64_t l = level + b;
+      const int c0 = (int)(l % 3), c1 = (int)((l + 1) % 3), c2 = (int)((l + 2) % 3);
+      hipLaunchKernelGGL(k_cont_level<PrimsEval>, dim3(lgrid), dim3(kBlock), 0, s, ev, g, cw.front[l & 1],
+                         &cw.count[c0], cw.front[(l + 1) & 1], &cw.count[c1], cw.cap, cw.reached, cw.known,
+                         &cw.count[3], &cw.count[c2], ctr);
+    }
+    unsigned long long nfront = 0;
+    const int last = (int)((level + kBatch) % 3);  // the counter the next level would read
+    if ((e = hipMemcpyAsync(&nfront, &cw.count[last], sizeof(nfront), hipMemcpyDeviceToHost, s)) != hipSuccess)
       return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    ++level;
-    if ((int64_t)nfront > cw.cap) break;  // flagged by the kernel: the search stops incomplete
-    cur = 1 - cur;
+    if (nfront == 0) break;
   }
-  if (levels) *levels = level;
+  if (levels) {
+    unsigned long long nl = 0;
+    if ((e = hipMemcpyAsync(&nl, &cw.count[3], sizeof(nl), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    *levels = (int64_t)nl;
+  }
   const int64_t ncol = (int64_t)g.n * g.n;
   hipLaunchKernelGGL(k_cont_columns, dim3((int)std::min<int64_t>((ncol + kBlock - 1) / kBlock, (int64_t)blocks)),
                      dim3(kBlock), 0, s, g.n, cw.reached, ws.colmask, ws.colbits, ctr);

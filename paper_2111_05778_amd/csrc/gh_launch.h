@@ -63,7 +63,8 @@ constexpr int32_t kSdbRadiiNormal = 1;
 enum ClearMode { kClearAll = 0, kClearMc = 1, kClearCands = 2 };
 
 // Continuation workspace (gh_cont): reached-cell and evaluated-point
-// bitmaps, two frontier lists of cap cell ids, two frontier counters.
+// bitmaps, two frontier lists of cap cell ids, three rotating frontier
+// counters and a level counter.
 struct ContWorkspace {
   uint32_t* reached;
   uint32_t* known;
