@@ -43,9 +43,12 @@ __global__ __launch_bounds__(kBlock) void k_cont_seed(const int64_t* __restrict_
   }
 }
 
-// One level: every frontier cell evaluates its eight corners, counts those
-// evaluated for the first time, and adds each face neighbour behind a face
-// with a sign change that no one has reached yet to the next frontier.
+// One level.  Eight lanes take each frontier cell: lane c evaluates corner
+// c = dx + 2 dy + 4 dz (counted when it is the first to claim that lattice
+// point), the group's signs come from one ballot, and lanes 0..5 take the
+// faces (axis c / 2, upper side when c is odd): a face whose four corners do
+// not share one sign leads to the neighbour behind it, which joins the next
+// frontier if no one has reached it yet.
 template <class Eval>
 __global__ __launch_bounds__(kBlock) void k_cont_level(Eval ev, Grid g, const int64_t* __restrict__ front,
                                                        const unsigned long long* __restrict__ nfront_d,
@@ -63,32 +66,28 @@ __global__ __launch_bounds__(kBlock) void k_cont_level(Eval ev, Grid g, const in
     if (nfront > 0) atomicAdd(levels, 1ull);
     *clear = 0;  // the counter the next level fills (read by the previous one, which has finished)
   }
+  const int lane = lane_id(), c = lane & 7;
   uint64_t evals = 0;
   bool bad = false, full = false;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nfront; t += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / 8);
+  // uniform over the eight lanes of a group; waves run the loop the same
+  // number of times except for the last round
+  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 8; t < nfront; t += groups) {
     const int64_t id = front[t];
     const int i = (int)(id / ((int64_t)n * n)), j = (int)((id / n) % n), k = (int)(id % n);
-    unsigned neg = 0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int a = i + (c & 1), b = j + ((c >> 1) & 1), z = k + ((c >> 2) & 1);
-      const float f = ev(lattice(g, a), lattice(g, b), lattice(g, z));
-      bad = bad || !(fabsf(f) <= FLT_MAX);
-      neg |= (f < 0.f ? 1u : 0u) << c;
-      if (claim(known, ((int64_t)a * n1 + b) * n1 + z)) ++evals;
-    }
-    // faces: corners with bit d clear (lower side) or set (upper side) of axis d
-    constexpr unsigned kSide[3] = {0x55u, 0x33u, 0x0Fu};  // corners with bit 0, 1, 2 clear
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-#pragma unroll
-      for (int up = 0; up < 2; ++up) {
-        const unsigned face = up ? (~kSide[d] & 0xFFu) : kSide[d];
-        const unsigned s = neg & face;
-        if (s == 0 || s == face) continue;  // no sign change on this face
-        const int ni = i + (d == 0 ? (up ? 1 : -1) : 0), nj = j + (d == 1 ? (up ? 1 : -1) : 0),
-                  nk = k + (d == 2 ? (up ? 1 : -1) : 0);
-        if (ni < 0 || ni >= n || nj < 0 || nj >= n || nk < 0 || nk >= n) continue;
+    const int a = i + (c & 1), b = j + ((c >> 1) & 1), z = k + ((c >> 2) & 1);
+    const float f = ev(lattice(g, a), lattice(g, b), lattice(g, z));
+    bad = bad || !(fabsf(f) <= FLT_MAX);
+    if (claim(known, ((int64_t)a * n1 + b) * n1 + z)) ++evals;
+    const unsigned neg = (unsigned)(__ballot(f < 0.f) >> (lane & ~7)) & 0xFFu;
+    if (c < 6) {
+      const int d = c >> 1, up = c & 1;
+      constexpr unsigned kLow[3] = {0x55u, 0x33u, 0x0Fu};  // corners with bit 0, 1, 2 clear
+      const unsigned face = up ? (~kLow[d] & 0xFFu) : kLow[d];
+      const unsigned sgn = neg & face;
+      const int ni = i + (d == 0 ? 2 * up - 1 : 0), nj = j + (d == 1 ? 2 * up - 1 : 0),
+                nk = k + (d == 2 ? 2 * up - 1 : 0);
+      if (sgn != 0 && sgn != face && ni >= 0 && ni < n && nj >= 0 && nj < n && nk >= 0 && nk < n) {
         const int64_t nb = ((int64_t)ni * n + nj) * n + nk;
         if (claim(reached, nb)) {
           const unsigned long long pos = atomicAdd(nnext, 1ull);
