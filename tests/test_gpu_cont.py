@@ -118,3 +118,18 @@ def test_full_size_cont_n512(gh):
     assert c["flags"] == 0
     np.testing.assert_array_equal(got, sign_cells)
     assert c["n_hop_evals"] == len(ohop.corner_points(n, got))
+
+
+def test_no_seeds_and_networks(gh):
+    # no seed reaches nothing; a network bound is refused
+    import torch
+    native, P = gh
+    n, lo, h = W.grid(32)
+    poly = P.Polygonizer(P.Bound.prims(W.sphere_scene()), n, lo, h)
+    levels = poly.enqueue_cont(torch.zeros(0, dtype=torch.int64, device="cuda"))
+    c = P.counters_dict(poly.ctr)
+    assert levels == 0 and c["n_cand"] == 0 and c["n_hop_evals"] == 0 and c["flags"] == 0
+    poly = P.Polygonizer(P.Bound.mlp(W.neural_scene(0, 64), "fp32"), n, lo, h)
+    with pytest.raises(native.GhError) as e:
+        poly.enqueue_cont(torch.zeros(1, dtype=torch.int64, device="cuda"))
+    assert e.value.status == native.GH_EUNSUPPORTED
