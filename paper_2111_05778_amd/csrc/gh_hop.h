@@ -1,6 +1,8 @@
 // Hop kernels' device functions, shared by the single-bound and the batched
-// launches: the analytic hop over one block tile of ray columns, and the
-// network hop over a pool of rays fed by a ray source.
+// launches: the analytic hop over one block tile of ray columns (and its
+// optional long-ray pass over cell windows), the paper's per-column
+// procedure taken literally over the same tiles, and the network hop over a
+// pool of rays fed by a ray source.
 #pragma once
 
 #include <float.h>
