@@ -113,11 +113,13 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
 // columns; srec holds the primitive records in LDS.
 // kRegs and kTypes as for lane_union: with kRegs the records live in
 // registers for the whole ray instead of being read from LDS at every step.
-// budget > 0: a ray still running after that many steps is handed over with
-// its state (column, k, the candidate word in progress and the word mask)
-// to park[*park_count++]; the long-ray pass finishes it exactly as this loop
-// would have (the hop is a function of the state alone).
-template <int R, bool kRegs = false, int kTypes = kAllTypes>
+// kBudget and budget > 0: a ray still running after that many steps is
+// handed over with its state (column, k, the candidate word in progress and
+// the word mask) to park[*park_count++]; the long-ray pass finishes it
+// exactly as this loop would have (the hop is a function of the state
+// alone).  Without kBudget the loop carries no budget test (about 18 scalar
+// instructions per step).
+template <int R, bool kRegs = false, int kTypes = kAllTypes, bool kBudget = false>
 __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, const PrimGroups& groups, const Grid& g,
                                                uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                gh_counters* __restrict__ ctr, int tile, int budget = 0,
@@ -144,9 +146,11 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
     bool has[kPrimTypes];
     if constexpr (kRegs) lane_records<R, kTypes>(srec, groups, q, rec, has);
     while (k < n) {
-      if (budget > 0 && (int)evals >= budget) {
-        parked = true;
-        break;
+      if constexpr (kBudget) {
+        if (budget > 0 && (int)evals >= budget) {
+          parked = true;
+          break;
+        }
       }
       float f = lane_union<R, kRegs, kTypes>(srec, groups, q, rec, has, x, y, centroid(g, k));
       f = group_min<R>(f, q);
@@ -180,7 +184,7 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
       colmask[col] = mask;
     }
   }
-  if (budget > 0) {  // hand-over: one atomic per wave
+  if constexpr (kBudget) {  // hand-over: one atomic per wave
     const bool give = parked && q == 0;
     const uint64_t gb = __ballot(give);
     if (gb) {

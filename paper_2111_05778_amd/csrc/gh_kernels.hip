@@ -48,14 +48,15 @@ __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, u
 }
 
 // --------------------------------------------------------------------- hop
-template <int R, bool kRegs, int kTypes = kAllTypes>
+template <int R, bool kRegs, int kTypes = kAllTypes, bool kBudget = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_hop_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                       uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits,
                                                       gh_counters* __restrict__ ctr, int budget,
                                                       uint32_t* __restrict__ park, unsigned int* __restrict__ npark) {
   __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
   stage_prims(s_rec, prims, groups.start[kPrimTypes]);
-  hop_prims_tile<R, kRegs, kTypes>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, ctr, blockIdx.x,
+  hop_prims_tile<R, kRegs, kTypes, kBudget>(reinterpret_cast<const float*>(s_rec), groups, g, colmask, colbits, ctr,
+                                            blockIdx.x,
                                    budget,
                            park, npark);
 }
@@ -200,7 +201,8 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
   int present = 0;
   for (int t = 0; t < kPrimTypes; ++t) present |= (d.groups.start[t + 1] > d.groups.start[t] ? 1 : 0) << t;
   // Unions of spheres, boxes, tori and capsules (at most) get a kernel that
-  // skips the other two types; any other mix takes the general one.
+  // skips the other types; mixes covered by no special kernel take the
+  // general one.
   constexpr int kSolids = (1 << kPrimSphere) | (1 << kPrimBox) | (1 << kPrimTorus) | (1 << kPrimCapsule);
   // The second pass (budget > 0) reads the count of handed-over rays on the
   // device; its grid fills the device once and strides over them.
@@ -211,27 +213,32 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
   // Unions of the solids, cylinders, cones and hexagonal prisms (the paper's
   // primitives) get a kernel that skips the other types.
   constexpr int kNoPlanes = kSolids | (1 << kPrimCylinder) | (1 << kPrimCone) | (1 << kPrimHexPrism);
+  // The first pass without a budget carries no budget test.
+  auto first = [&](auto kernel_nb, auto kernel_b) {
+    if (budget > 0)
+      hipLaunchKernelGGL(kernel_b, dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask, ws.colbits,
+                         ctr, budget, ws.park, npark);
+    else
+      hipLaunchKernelGGL(kernel_nb, dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
+                         ws.colbits, ctr, budget, ws.park, npark);
+  };
   if (regs && (present & ~kSolids) == 0) {
-    hipLaunchKernelGGL((k_hop_prims<R, true, kSolids>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
-                       ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
+    first(k_hop_prims<R, true, kSolids, false>, k_hop_prims<R, true, kSolids, true>);
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, true, kSolids>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
                          ws.colmask, ws.colbits, ws.park, npark, ctr);
   } else if (regs && (present & ~kNoPlanes) == 0) {
-    hipLaunchKernelGGL((k_hop_prims<R, true, kNoPlanes>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups,
-                       g, ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
+    first(k_hop_prims<R, true, kNoPlanes, false>, k_hop_prims<R, true, kNoPlanes, true>);
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, true, kNoPlanes>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
                          ws.colmask, ws.colbits, ws.park, npark, ctr);
   } else if (regs) {
-    hipLaunchKernelGGL((k_hop_prims<R, true>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
-                       ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
+    first(k_hop_prims<R, true, kAllTypes, false>, k_hop_prims<R, true, kAllTypes, true>);
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, true>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
                          ws.colbits, ws.park, npark, ctr);
   } else {
-    hipLaunchKernelGGL((k_hop_prims<R, false>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
-                       ws.colmask, ws.colbits, ctr, budget, ws.park, npark);
+    first(k_hop_prims<R, false, kAllTypes, false>, k_hop_prims<R, false, kAllTypes, true>);
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, false>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
                          ws.colbits, ws.park, npark, ctr);
