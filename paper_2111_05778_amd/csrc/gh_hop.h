@@ -156,10 +156,9 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
       f = group_min<R>(f, q);
       ++evals;
       const float d = fabsf(f);
-      if (!(d <= FLT_MAX)) {
-        bad = true;
-        break;
-      }
+      // A non-finite value ends the ray without a branch out of the loop:
+      // floor(inf) is inf and fminf(NaN, n) is n, so the step below is n.
+      bad = bad || !(d <= FLT_MAX);
       const float s = floorf(d * g.inv_h);
       if (s == 0.f) {
         const int kw = k >> 5;
