@@ -418,3 +418,18 @@ def test_graph_replay_matches_eager(gh):
                 assert c[k] == c_ref[k], (dense, rep, k)
             assert torch.equal(poly.verts[:c["n_vert"]], v_ref) and torch.equal(poly.tris[:c["n_tri"]], t_ref)
             other.run()  # eager work between replays
+
+
+def test_csg_n1024_candidates_and_counts(gh):
+    # twice the headline size: the candidate cells and every counter of the
+    # hop equal the twin's, and the mesh is closed and oriented
+    n, lo, h = W.grid(1024)
+    recs = W.csg_scene(0)
+    out = _run(gh, recs, n, lo, h)
+    cells, total, _ = ohop.hop(osdb.SDB.prims(recs), n, lo, h, precision="f32")
+    print(f"N=1024 csg0: evals={total} cand={len(cells)} tris={len(out['tris'])}", flush=True)
+    assert out["ctr"]["n_hop_evals"] == total and out["ctr"]["n_cand"] == len(cells)
+    np.testing.assert_array_equal(out["cand"], cells)
+    assert out["ctr"]["n_corner"] == len(ohop.corner_points(n, cells))
+    T = np.searchsorted(out["edge"], out["tri_e"])
+    assert _closed_oriented(T)
