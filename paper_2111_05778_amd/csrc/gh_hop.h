@@ -53,10 +53,10 @@ __device__ __forceinline__ float group_min(float f, int q) {
 // One lane's share of a cell's union value when R lanes evaluate a cell:
 // lane q takes primitives q, q + R, q + 2R, ... of each type group.
 // kRegs: every type group has at most R primitives, so the lane holds at
-// most one record per type, loaded once by lane_records into registers; its
-// roots are taken by sqrt_hop, so kRegs kernels run only on grids and unions
-// that meet that root's conditions (the others take the LDS-record kernel,
-// with exact roots).
+// most one record per type, loaded once by lane_records into registers.
+// kHopRoot: the roots of the register path are taken by sqrt_hop, so such
+// kernels run only on grids and unions that meet that root's conditions (the
+// others take the LDS-record kernel, with exact roots).
 // kTypes (kRegs only): bit t set when type t may be present; a type whose bit
 // is clear is neither loaded nor evaluated.
 template <int R, int kTypes>
@@ -73,7 +73,7 @@ __device__ __forceinline__ void lane_records(const float* __restrict__ srec, con
   }
 }
 
-template <int R, bool kRegs, int kTypes>
+template <int R, bool kRegs, int kTypes, bool kHopRoot = true>
 __device__ __forceinline__ float lane_union(const float* __restrict__ srec, const PrimGroups& groups, int q,
                                             const float (&rec)[kPrimTypes][GH_PRIM_FLOATS],
                                             const bool (&has)[kPrimTypes], float x, float y, float z) {
@@ -83,21 +83,21 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
     // discards the value): no branch splits the step, so the independent
     // chains of the formulas interleave.
     float v[kPrimTypes];
-    if constexpr (kTypes & (1 << kPrimSphere)) v[kPrimSphere] = prim_eval_t<kPrimSphere, true>(rec[kPrimSphere], x, y, z);
-    if constexpr (kTypes & (1 << kPrimBox)) v[kPrimBox] = prim_eval_t<kPrimBox, true>(rec[kPrimBox], x, y, z);
-    if constexpr (kTypes & (1 << kPrimTorus)) v[kPrimTorus] = prim_eval_t<kPrimTorus, true>(rec[kPrimTorus], x, y, z);
+    if constexpr (kTypes & (1 << kPrimSphere)) v[kPrimSphere] = prim_eval_t<kPrimSphere, kHopRoot>(rec[kPrimSphere], x, y, z);
+    if constexpr (kTypes & (1 << kPrimBox)) v[kPrimBox] = prim_eval_t<kPrimBox, kHopRoot>(rec[kPrimBox], x, y, z);
+    if constexpr (kTypes & (1 << kPrimTorus)) v[kPrimTorus] = prim_eval_t<kPrimTorus, kHopRoot>(rec[kPrimTorus], x, y, z);
     if constexpr (kTypes & (1 << kPrimCapsule))
-      v[kPrimCapsule] = prim_eval_t<kPrimCapsule, true>(rec[kPrimCapsule], x, y, z);
-    if constexpr (kTypes & (1 << kPrimPlane)) v[kPrimPlane] = prim_eval_t<kPrimPlane, true>(rec[kPrimPlane], x, y, z);
+      v[kPrimCapsule] = prim_eval_t<kPrimCapsule, kHopRoot>(rec[kPrimCapsule], x, y, z);
+    if constexpr (kTypes & (1 << kPrimPlane)) v[kPrimPlane] = prim_eval_t<kPrimPlane, kHopRoot>(rec[kPrimPlane], x, y, z);
     if constexpr (kTypes & (1 << kPrimBoxBound))
-      v[kPrimBoxBound] = prim_eval_t<kPrimBoxBound, true>(rec[kPrimBoxBound], x, y, z);
+      v[kPrimBoxBound] = prim_eval_t<kPrimBoxBound, kHopRoot>(rec[kPrimBoxBound], x, y, z);
     if constexpr (kTypes & (1 << kPrimCylinder))
-      v[kPrimCylinder] = prim_eval_t<kPrimCylinder, true>(rec[kPrimCylinder], x, y, z);
-    if constexpr (kTypes & (1 << kPrimCone)) v[kPrimCone] = prim_eval_t<kPrimCone, true>(rec[kPrimCone], x, y, z);
+      v[kPrimCylinder] = prim_eval_t<kPrimCylinder, kHopRoot>(rec[kPrimCylinder], x, y, z);
+    if constexpr (kTypes & (1 << kPrimCone)) v[kPrimCone] = prim_eval_t<kPrimCone, kHopRoot>(rec[kPrimCone], x, y, z);
     if constexpr (kTypes & (1 << kPrimHexPrism))
-      v[kPrimHexPrism] = prim_eval_t<kPrimHexPrism, true>(rec[kPrimHexPrism], x, y, z);
+      v[kPrimHexPrism] = prim_eval_t<kPrimHexPrism, kHopRoot>(rec[kPrimHexPrism], x, y, z);
     if constexpr (kTypes & (1 << kPrimGenus2))
-      v[kPrimGenus2] = prim_eval_t<kPrimGenus2, true>(rec[kPrimGenus2], x, y, z);
+      v[kPrimGenus2] = prim_eval_t<kPrimGenus2, kHopRoot>(rec[kPrimGenus2], x, y, z);
 #pragma unroll
     for (int t = 0; t < kPrimTypes; ++t)
       if ((kTypes >> t) & 1) f = has[t] ? fminf(f, v[t]) : f;
@@ -301,8 +301,9 @@ struct TraceConsts {
   int64_t max_steps;
 };
 
-// Algorithm 1 as printed, over one block tile of columns (the same tiles and
-// R-lane groups as hop_prims_tile, records in LDS, exact roots): from the
+// Algorithm 1 as printed, over one block tile of columns (the same tiles,
+// R-lane groups and record placement as hop_prims_tile, but exact roots,
+// since the stopping test compares |f| itself): from the
 // centroid of cell k the ray is sphere-traced (eq. iter) until |f| <= tau or
 // the travel t reaches 1.05 (z_top - z_s); the cell of the last centroid at
 // or below z_s + t (never below k) is a candidate unless it lies past the
@@ -310,7 +311,7 @@ struct TraceConsts {
 // the next cell.  Candidates rise strictly along a column, so they go to the
 // same candidate words as the hop's.  The float32 operations are those of
 // the oracle's FP32 twin, one rounding each, in the same order.
-template <int R>
+template <int R, bool kRegs = false, int kTypes = kAllTypes>
 __device__ __forceinline__ void trace_prims_tile(const float* __restrict__ srec, const PrimGroups& groups,
                                                  const Grid& g, const TraceConsts tc, uint64_t* __restrict__ colmask,
                                                  uint32_t* __restrict__ colbits, gh_counters* __restrict__ ctr,
@@ -332,13 +333,16 @@ __device__ __forceinline__ void trace_prims_tile(const float* __restrict__ srec,
     int k = 0, wi = 0;
     uint32_t word = 0;
     uint64_t mask = 0;
+    float rec[kPrimTypes][GH_PRIM_FLOATS];
+    bool has[kPrimTypes];
+    if constexpr (kRegs) lane_records<R, kTypes>(srec, groups, q, rec, has);
     float zs = z0, t = 0.f, tmax = 1.05f * (tc.z_top - zs);
     for (int64_t steps = 0;; ++steps) {
       if (steps >= tc.max_steps) {
         stuck = true;
         break;
       }
-      float f = union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y, zs + t);
+      float f = lane_union<R, kRegs, kTypes, false>(srec, groups, q, rec, has, x, y, zs + t);  // exact roots
       f = group_min<R>(f, q);
       ++evals;
       const float d = fabsf(f);

@@ -76,14 +76,15 @@ __global__ __launch_bounds__(kBlock) void k_hop_long(const float* __restrict__ p
 }
 
 // Algorithm 1 taken literally (see trace_prims_tile).
-template <int R>
+template <int R, bool kRegs = false, int kTypes = kAllTypes>
 __global__ __launch_bounds__(kBlock) void k_trace_prims(const float* __restrict__ prims, PrimGroups groups, Grid g,
                                                         TraceConsts tc, uint64_t* __restrict__ colmask,
                                                         uint32_t* __restrict__ colbits,
                                                         gh_counters* __restrict__ ctr) {
   __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
   stage_prims(s_rec, prims, groups.start[kPrimTypes]);
-  trace_prims_tile<R>(reinterpret_cast<const float*>(s_rec), groups, g, tc, colmask, colbits, ctr, blockIdx.x);
+  trace_prims_tile<R, kRegs, kTypes>(reinterpret_cast<const float*>(s_rec), groups, g, tc, colmask, colbits, ctr,
+                                     blockIdx.x);
 }
 
 // ------------------------------------------------------------ enumeration
@@ -272,8 +273,21 @@ static void launch_trace_r(const DevSdb& d, const Grid& g, const TraceConsts& tc
                            gh_counters* ctr, hipStream_t s) {
   using S = HopShape<R>;
   const int nbh = (g.n + S::kBlockH - 1) / S::kBlockH, nbw = (g.n + S::kBlockW - 1) / S::kBlockW;
-  hipLaunchKernelGGL(k_trace_prims<R>, dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g, tc, ws.colmask,
-                     ws.colbits, ctr);
+  int most = 0, present = 0;
+  for (int t = 0; t < kPrimTypes; ++t) {
+    most = std::max(most, d.groups.start[t + 1] - d.groups.start[t]);
+    present |= (d.groups.start[t + 1] > d.groups.start[t] ? 1 : 0) << t;
+  }
+  constexpr int kSolids = (1 << kPrimSphere) | (1 << kPrimBox) | (1 << kPrimTorus) | (1 << kPrimCapsule);
+  if (most <= R && (present & ~kSolids) == 0)  // records in registers, solids only
+    hipLaunchKernelGGL((k_trace_prims<R, true, kSolids>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
+                       tc, ws.colmask, ws.colbits, ctr);
+  else if (most <= R)
+    hipLaunchKernelGGL((k_trace_prims<R, true, kAllTypes>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups,
+                       g, tc, ws.colmask, ws.colbits, ctr);
+  else
+    hipLaunchKernelGGL((k_trace_prims<R, false>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g, tc,
+                       ws.colmask, ws.colbits, ctr);
 }
 
 hipError_t launch_hop_traced(const DevSdb& d, const Grid& g, const Workspace& ws, gh_counters* ctr,
