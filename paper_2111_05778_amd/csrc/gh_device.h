@@ -144,6 +144,7 @@ __device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
 
 constexpr int kPrimTypes = 10;
 constexpr int kAllTypes = (1 << kPrimTypes) - 1;  // type mask with every type
+constexpr int kFullTypes = 1 << 16;                 // flag beside a type mask: every lane holds every type
 
 // Primitives sorted by type: group t occupies records [start[t], start[t+1]).
 // The minimum is exact and commutative, so the order of the union does not

@@ -58,7 +58,9 @@ __device__ __forceinline__ float group_min(float f, int q) {
 // kernels run only on grids and unions that meet that root's conditions (the
 // others take the LDS-record kernel, with exact roots).
 // kTypes (kRegs only): bit t set when type t may be present; a type whose bit
-// is clear is neither loaded nor evaluated.
+// is clear is neither loaded nor evaluated.  With kFullTypes also set, every
+// type of the mask is present with exactly R primitives, so every lane holds
+// one record of each and no presence select is needed.
 template <int R, int kTypes>
 __device__ __forceinline__ void lane_records(const float* __restrict__ srec, const PrimGroups& groups, int q,
                                              float (&rec)[kPrimTypes][GH_PRIM_FLOATS], bool (&has)[kPrimTypes]) {
@@ -100,7 +102,7 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
       v[kPrimGenus2] = prim_eval_t<kPrimGenus2, kHopRoot>(rec[kPrimGenus2], x, y, z);
 #pragma unroll
     for (int t = 0; t < kPrimTypes; ++t)
-      if ((kTypes >> t) & 1) f = has[t] ? fminf(f, v[t]) : f;
+      if ((kTypes >> t) & 1) f = (kTypes & kFullTypes) || has[t] ? fminf(f, v[t]) : f;
     return f;
   } else {
     return union_strided(groups, [srec](int p) { return srec + p * GH_PRIM_FLOATS; }, q, R, x, y, z);

@@ -223,7 +223,17 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
       hipLaunchKernelGGL(kernel_nb, dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
                          ws.colbits, ctr, budget, ws.park, npark);
   };
-  if (regs && (present & ~kSolids) == 0) {
+  // all four solid types present, each with exactly R primitives: every lane
+  // holds one record of each, and the kernel needs no presence select
+  bool full = present == kSolids;
+  for (int t = 0; t < kPrimTypes; ++t)
+    if ((present >> t) & 1) full = full && d.groups.start[t + 1] - d.groups.start[t] == R;
+  if (regs && full) {
+    first(k_hop_prims<R, true, kSolids | kFullTypes, false>, k_hop_prims<R, true, kSolids | kFullTypes, true>);
+    if (budget > 0)
+      hipLaunchKernelGGL((k_hop_long<R, true, kSolids>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
+                         ws.colmask, ws.colbits, ws.park, npark, ctr);
+  } else if (regs && (present & ~kSolids) == 0) {
     first(k_hop_prims<R, true, kSolids, false>, k_hop_prims<R, true, kSolids, true>);
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, true, kSolids>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
