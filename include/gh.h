@@ -106,7 +106,7 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
  *            9 the implicit surface of genus 2 of Section 5.1, scaled
  *  [1..3] centre c;  [4..12] 3x3 matrix M row-major, local q = M (p - c)
  *  [13..15] sphere (r), box/box bound (bx, by, bz), torus (R, r) about local y,
- *           capsule (a, r) on local z in [-a, a], plane (d) with f = M_row0 . p - d,
+ *           capsule (a, r) on local z in [-a, a] (a >= 0), plane (d) with f = M_row0 . p - d,
  *           cylinder (r, a) capped at local z = -a, a (exact distance),
  *           cone (a, s, c): apex at local z = a, axis -z, half-angle of sine s and
  *           cosine c (s^2 + c^2 <= 1), cut at z = -a (max of side and cap: a bound),

@@ -311,6 +311,8 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
         return fail(GH_EINVAL, "primitive %d parameter %d = %g is not finite or exceeds %g", p, q, (double)r[q],
                     (double)lim);
     }
+    if (t == 3.f && !(r[13] >= 0.f))
+      return fail(GH_EINVAL, "capsule %d: half-length %g must be >= 0", p, (double)r[13]);
     // A cone's (sine, cosine) must not be longer than a unit vector: the
     // side term is then 1-Lipschitz and the record a distance bound.
     if (t == 7.f && !((double)r[14] * r[14] + (double)r[15] * r[15] <= 1.0 + 1e-6))

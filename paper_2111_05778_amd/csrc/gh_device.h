@@ -77,7 +77,7 @@ constexpr float kHopRootMinH = 0x1p-20f;
 //   box      u = |q| - b;  sqrt((mx mx + my my) + mz mz) + min(max(ux, max(uy, uz)), 0), m = max(u, 0)
 //   boxbound max(ux, max(uy, uz))                         (Section 4.2, eq. boxdist)
 //   torus    s = sqrt(qx qx + qz qz) - R;  sqrt(s s + qy qy) - r
-//   capsule  w = qz - min(max(qz, -a), a);  sqrt((qx qx + qy qy) + w w) - r
+//   capsule  w = qz - min(max(qz, -a), a);  sqrt((qx qx + qy qy) + w w) - r   (a >= 0)
 //   plane    ((n_x x + n_y y) + n_z z) - d                 (Section 4.1, eq. plane)
 //   cylinder rho = sqrt(qx qx + qy qy);  dx = rho - r, dz = |qz| - a, m = max(d, 0):
 //            sqrt(mx mx + mz mz) + min(max(dx, dz), 0)     (capped, axis local z)
@@ -110,7 +110,9 @@ __device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
       const float s = root(qx * qx + qz * qz) - r[13];
       return root(s * s + qy * qy) - r[14];
     } else if constexpr (T == kPrimCapsule) {
-      const float w = qz - fminf(fmaxf(qz, -r[13]), r[13]);
+      // clamp(qz, -a, a) as one median of three (a >= 0 is validated on the
+      // host; the result is the same input min(max(qz, -a), a) selects)
+      const float w = qz - __builtin_amdgcn_fmed3f(qz, -r[13], r[13]);
       return root((qx * qx + qy * qy) + w * w) - r[14];
     } else if constexpr (T == kPrimCylinder) {
       const float rho = root(qx * qx + qy * qy);

@@ -77,6 +77,11 @@ def test_describe_size_query_and_validation():
         bad[3, 0] = t
         s2, keep2 = _spec(bad)
         assert N.lib.sdb_describe(ctypes.byref(s2), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
+    bad = keep.copy()
+    bad[3, 13] = -0.1                     # csg primitive 3 is a capsule: negative half-length
+    assert int(bad[3, 0]) == W.PRIM_CAPSULE
+    s2, keep2 = _spec(bad)
+    assert N.lib.sdb_describe(ctypes.byref(s2), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
     bad = W.cone_scene(0.2, 0.4).copy()
     bad[0, 14:16] = (0.8, 0.8)            # a cone whose (sin, cos) is longer than a unit vector
     s2, keep2 = _spec(bad)
