@@ -67,13 +67,20 @@ PEAK_BF16_MFMA = 2.5e15   # dense, no sparsity
 #            3 max                                              = 15
 #   genus2   3 mul (squares), sub, add, mul + mul + sub + mul + mul, mul + add,
 #            mul + sub + mul + sub, mul (k)                        = 18
+#   sierpinski per level: add + sub (u, w), 4 add/sub (e), 3 compares, 4
+#            selects, 3 mul + 3 sub (q = 2q - v), mul (v_z) = 20; at the end
+#            6 for e, 3 max, sub, mul, ldexp, mul (k) = 13: 13 + 20 d
 OPS = {0: 18 + 7, 1: 18 + 19, 2: 18 + 10, 3: 18 + 11, 4: 6, 5: 18 + 8, 6: 18 + 16, 7: 18 + 11, 8: 18 + 15,
        9: 18 + 18}
 
 
+def prim_ops(r):
+    t = int(r[0])
+    return 18 + 13 + 20 * int(r[14]) if t == 10 else OPS[t]
+
+
 def ops_per_eval(records):
-    types = [int(r[0]) for r in records]
-    return sum(OPS[t] for t in types) + (len(types) - 1)   # plus the union minima
+    return sum(prim_ops(r) for r in records) + (len(records) - 1)   # plus the union minima
 
 
 def mlp_flop_per_point(width, depth, n_freq):
@@ -296,6 +303,33 @@ def primitives_section(dev, steps, warmup, n=512, seed=0):
             "ops_per_eval": ops_per_eval(recs)}
 
 
+def sierpinski_section(dev, steps, warmup, n=512, depth=8):
+    """The Sierpinski tetrahedron (Section 5.1's fractal scene) at N = 512,
+    depth 8 (65,536 tetrahedra of about 2.4 cells per edge): grid hopping
+    and enumeration, each followed by marching cubes."""
+    import torch
+
+    import workloads as W
+    from paper_2111_05778_amd.polygonize import Bound, Polygonizer, counters_dict
+    recs = W.sierpinski_scene(depth)
+    n, lo, h = W.grid(n)
+    poly = Polygonizer(Bound.prims(recs, dev), n, lo, h, device=dev, keep_cells=False)
+    poly.run()
+    for _ in range(warmup):
+        poly.enqueue_hop()
+        poly.enqueue_mc()
+    stream = torch.cuda.current_stream(dev)
+    hop_ms = event_ms(stream, poly.enqueue_hop, steps)
+    mc_ms = event_ms(stream, poly.enqueue_mc, steps)
+    c = counters_dict(poly.ctr)
+    dense_ms = event_ms(stream, lambda: (poly.enqueue_dense(), poly.enqueue_mc()), max(1, steps // 2))
+    return {"workload": f"sierpinski_d{depth}_n{n}", "hop_ms": hop_ms, "mc_ms": mc_ms,
+            "ms_per_step": hop_ms + mc_ms, "value": n ** 3 / ((hop_ms + mc_ms) * 1e-3), "unit": "cells/s",
+            "dense_ms": dense_ms, "speedup_vs_dense": dense_ms / (hop_ms + mc_ms),
+            "counters": {k: c[k] for k in ("n_hop_evals", "n_cand", "n_corner", "n_vert", "n_tri")},
+            "evals_per_column": c["n_hop_evals"] / n ** 2, "ops_per_eval": ops_per_eval(recs)}
+
+
 def cont_section(dev, steps, warmup, recs, n, lo, h, seed):
     """Continuation (gh_cont, the paper's surface-following comparator) on
     the headline workload, seeded with one cell per surface component (found
@@ -370,7 +404,7 @@ def main():
                          "that scales the HBM counters) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (built-in shapes)")
-    ap.add_argument("--sections", default="neural,paper_net,backward,batch,traced,cont,primitives",
+    ap.add_argument("--sections", default="neural,paper_net,backward,batch,traced,cont,primitives,sierpinski",
                     help="extra workloads to measure after the headline one (comma list, or none)")
     args = ap.parse_args()
     sections = [x for x in args.sections.split(",") if x and x != "none"]
@@ -503,6 +537,8 @@ def main():
         out["cont"] = cont_section(dev, max(3, args.steps // 4), sw, recs, n, lo, h, args.seed)
     if "primitives" in sections:
         out["primitives"] = primitives_section(dev, max(3, args.steps // 4), sw)
+    if "sierpinski" in sections:
+        out["sierpinski"] = sierpinski_section(dev, max(3, args.steps // 4), sw)
     if "traced" in sections:
         out["traced"] = traced_section(dev, max(3, args.steps // 4), sw, recs, n, lo, h, args.seed)
     print(json.dumps(out), flush=True)

@@ -103,7 +103,8 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
  *  [0] type: 0 sphere, 1 box (exact), 2 torus, 3 capsule, 4 plane,
  *            5 box bound (max of six face planes, Section 4.2 eq. boxdist),
  *            6 cylinder, 7 cone, 8 hexagonal prism (Section 5.1's primitives),
- *            9 the implicit surface of genus 2 of Section 5.1, scaled
+ *            9 the implicit surface of genus 2 of Section 5.1, scaled,
+ *            10 the Sierpinski tetrahedron of Section 5.1's fractal scene
  *  [1..3] centre c;  [4..12] 3x3 matrix M row-major, local q = M (p - c)
  *  [13..15] sphere (r), box/box bound (bx, by, bz), torus (R, r) about local y,
  *           capsule (a, r) on local z in [-a, a] (a >= 0), plane (d) with f = M_row0 . p - d,
@@ -113,7 +114,13 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
  *           hexagonal prism (r, a): apothem r with one pair of faces normal to local
  *           x, capped at z = -a, a (max of the face planes: a bound),
  *           genus 2 (k): k F(q) with F = 2y(y^2-3x^2)(1-z^2) + (x^2+y^2)^2 - (9z^2-1)(1-z^2);
- *           the caller picks k so that |grad| <= 1 wherever it is evaluated.
+ *           the caller picks k so that |grad| <= 1 wherever it is evaluated,
+ *           Sierpinski (k, d): the tetrahedron of depth d (an integer in [0, 16])
+ *           on the regular tetrahedron with vertices (1,1,1), (1,-1,-1), (-1,1,-1),
+ *           (-1,-1,1) in local q; d times q = 2q - v_b with v_b the nearest vertex
+ *           (largest v . q, lowest index on ties), then k 2^-d times the maximum of
+ *           the four face-plane distances at the last q.  With M = s R (R a
+ *           rotation) k = 1/s makes it a bound in world units; k > 0.
  * The bound is the minimum over the records (union, Section 4.3). */
 #define GH_PRIM_FLOATS 16
 

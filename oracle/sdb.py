@@ -21,6 +21,8 @@ Primitive distances are written from geometry:
   genus2   k F(q), F = 2y(y^2 - 3x^2)(1 - z^2) + (x^2 + y^2)^2 - (9z^2 - 1)(1 - z^2),
            the paper's implicit surface of genus 2; a bound once k makes the
            gradient at most 1 over the region evaluated (Lipschitz normalisation)
+  sierpinski k S_d(q): a bound of the Sierpinski tetrahedron of depth d
+           (Section 5.1's fractal scene); see `sierpinski_f64`
 and combined by the minimum, which is the union of the shapes (Section 4.3).
 The paper's first scene holds sphere, cube, cone, cylinder, torus,
 hexagonal prism and capsule, each with a simple distance bound (Section 5.1).
@@ -33,7 +35,12 @@ op order is documented beside each twin function.
 import numpy as np
 
 PRIM_SPHERE, PRIM_BOX, PRIM_TORUS, PRIM_CAPSULE, PRIM_PLANE, PRIM_BOXBOUND = 0, 1, 2, 3, 4, 5
-PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM, PRIM_GENUS2 = 6, 7, 8, 9
+PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM, PRIM_GENUS2, PRIM_SIERPINSKI = 6, 7, 8, 9, 10
+SIERPINSKI_MAX_DEPTH = 16
+
+# Vertices of the regular tetrahedron T of the Sierpinski record, in local
+# coordinates (centroid at the origin, circumradius sqrt 3).
+TETRA_V = np.array([[1.0, 1.0, 1.0], [1.0, -1.0, -1.0], [-1.0, 1.0, -1.0], [-1.0, -1.0, 1.0]])
 
 
 # ------------------------------------------------------------------------- FP64
@@ -74,12 +81,49 @@ def prim_f64(rec, P):
         return np.maximum(np.max(np.stack(faces), axis=0) - a0, np.abs(q[:, 2]) - a1)
     if t == PRIM_GENUS2:
         return a0 * genus2_f64(q[:, 0], q[:, 1], q[:, 2])
+    if t == PRIM_SIERPINSKI:
+        return a0 * sierpinski_f64(q, int(a1))
     raise ValueError(f"unknown primitive type {t}")
 
 
 def genus2_f64(x, y, z):
     """The implicit function of the paper's genus-2 surface (Section 5.1)."""
     return 2 * y * (y * y - 3 * x * x) * (1 - z * z) + (x * x + y * y) ** 2 - (9 * z * z - 1) * (1 - z * z)
+
+
+def tetra_bound_f64(q):
+    """The maximum of the signed distances to the four face planes of T: the
+    face opposite v_i has outward unit normal -v_i / sqrt 3 and lies at
+    distance 1 / sqrt 3 from the centroid.  Exact inside T (the distance to
+    the nearest face) and below the distance outside, like the box bound of
+    Section 4.2."""
+    return ((-q @ TETRA_V.T) - 1.0).max(axis=1) / np.sqrt(3.0)
+
+
+def sierpinski_f64(q, depth):
+    """A signed distance bound of the Sierpinski tetrahedron of depth d
+    (Section 5.1, fourth scene; the paper gives no formula, this one is
+    written from the geometry).  S_0 = T and S_d is the union of the four
+    copies (S_{d-1} + v_i) / 2.  With b the vertex nearest to q (largest
+    v_i . q, lowest i on ties):
+        f_0(q) = tetra_bound(q)
+        f_d(q) = f_{d-1}(2q - v_b) / 2
+    i.e. the bound of the copy at v_b, scaled back.  That copy is the nearest
+    of the four: the reflection in the bisector plane of v_b and v_j is a
+    symmetry of S_{d-1} and of T that swaps the copies at v_b and v_j, and q
+    lies on v_b's side, so every point of copy j has its mirror image in copy
+    b at most as far from q.  Each copy lies on its own vertex's side of every
+    bisector and meets it at one point, and the copies meet only at points,
+    so a point inside S_d is inside copy b and the distance to the boundary
+    of S_d is the distance to copy b's.  By induction f_d is negative exactly
+    inside S_d and |f_d| is at most the distance to its boundary."""
+    q = np.asarray(q, dtype=np.float64)
+    scale = 1.0
+    for _ in range(depth):
+        b = np.argmax(q @ TETRA_V.T, axis=1)
+        q = 2.0 * q - TETRA_V[b]
+        scale *= 0.5
+    return scale * tetra_bound_f64(q)
 
 
 def genus2_gradient_bound(B):
@@ -123,6 +167,7 @@ def prim_f32(rec, x, y, z):
              max(|q_x| - r, max(|h_x + h_y| - r, max(|h_y - h_x| - r, |q_z| - a)))
     genus2:  x2 = q_x*q_x (y2, z2 alike), w = 1 - z2, r2 = x2 + y2;
              ((((2*q_y)*(y2 - 3*x2))*w + r2*r2) - (9*z2 - 1)*w) * k
+    sierpinski: see `sierpinski_f32`
     """
     rec = np.asarray(rec, dtype=np.float32)
     t = int(rec[0])
@@ -167,7 +212,33 @@ def prim_f32(rec, x, y, z):
         r2 = x2 + y2
         f = (((np.float32(2) * qy) * (y2 - np.float32(3) * x2)) * w + r2 * r2) - (np.float32(9) * z2 - np.float32(1)) * w
         return f * a0
+    if t == PRIM_SIERPINSKI:
+        return sierpinski_f32(qx, qy, qz, int(a1)) * a0
     raise ValueError(f"unknown primitive type {t}")
+
+
+def sierpinski_f32(x, y, z, depth):
+    """`sierpinski_f64` in float32 at local coordinates, GPU op order.  With
+    u = x + y, w = x - y the four values e_i = -v_i . q are
+    e_0 = -(u + z), e_1 = z - w, e_2 = w + z, e_3 = u - z; the nearest
+    vertex is the least e_i (lowest i on ties).  Per level q = 2q - v_b (2q
+    exact, one rounding per component); at the end
+    ((max_i e_i - 1) * float32(1/sqrt 3)) * 2^-d, applied before the
+    caller's k (the power of two is exact)."""
+    x = np.asarray(x, dtype=np.float32).copy()
+    y = np.asarray(y, dtype=np.float32).copy()
+    z = np.asarray(z, dtype=np.float32).copy()
+    V = TETRA_V.astype(np.float32)
+
+    def es(x, y, z):
+        u, w = x + y, x - y
+        return np.stack([-(u + z), z - w, w + z, u - z])
+
+    for _ in range(depth):
+        b = np.argmin(es(x, y, z), axis=0)       # lowest index on ties
+        x, y, z = np.float32(2) * x - V[b, 0], np.float32(2) * y - V[b, 1], np.float32(2) * z - V[b, 2]
+    t = (es(x, y, z).max(axis=0) - np.float32(1)) * np.float32(1.0 / np.sqrt(3.0))
+    return t * np.float32(2.0 ** -depth)
 
 
 def union_f32(recs, x, y, z):

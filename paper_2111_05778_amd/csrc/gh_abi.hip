@@ -301,7 +301,7 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
   for (int p = 0; p < np; ++p) {
     const float* r = spec_h->prims_h + (size_t)p * GH_PRIM_FLOATS;
     const float t = r[0];
-    if (!(t >= 0.f && t <= 9.f && t == floorf(t)))
+    if (!(t >= 0.f && t <= (float)(gh::kPrimTypes - 1) && t == floorf(t)))
       return fail(GH_EINVAL, "primitive %d has unknown type %g", p, (double)t);
     // Bounded magnitudes keep every intermediate finite or +inf, never NaN:
     // |M q| <= 3e33 and sums of squares can only overflow towards +inf.
@@ -311,6 +311,9 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
         return fail(GH_EINVAL, "primitive %d parameter %d = %g is not finite or exceeds %g", p, q, (double)r[q],
                     (double)lim);
     }
+    if (t == 10.f && !(r[13] > 0.f && r[14] >= 0.f && r[14] <= (float)gh::kSierpinskiMaxDepth && r[14] == floorf(r[14])))
+      return fail(GH_EINVAL, "sierpinski %d: needs k > 0 and an integer depth in [0, %d] (k = %g, depth = %g)", p,
+                  gh::kSierpinskiMaxDepth, (double)r[13], (double)r[14]);
     if (t == 3.f && !(r[13] >= 0.f))
       return fail(GH_EINVAL, "capsule %d: half-length %g must be >= 0", p, (double)r[13]);
     // A cone's (sine, cosine) must not be longer than a unit vector: the

@@ -24,8 +24,12 @@ enum : int {
   kPrimCylinder = 6,
   kPrimCone = 7,
   kPrimHexPrism = 8,
-  kPrimGenus2 = 9
+  kPrimGenus2 = 9,
+  kPrimSierpinski = 10
 };
+
+// Deepest Sierpinski record sdb_describe accepts.
+constexpr int kSierpinskiMaxDepth = 16;
 
 struct Grid {
   int n;        // cells per axis
@@ -90,6 +94,16 @@ constexpr float kHopRootMinH = 0x1p-20f;
 //            gradient over the grid to at most 1):  x2 = qx qx, y2, z2 alike,
 //            w = 1 - z2;  ((((2 qy) (y2 - 3 x2)) w + (x2 + y2)(x2 + y2))
 //            - (9 z2 - 1) w) k
+//   sierpinski k S_d(q), the Sierpinski tetrahedron of depth d (Section 5.1's
+//            fractal scene) on the tetrahedron T with vertices v_0 = (1,1,1),
+//            v_1 = (1,-1,-1), v_2 = (-1,1,-1), v_3 = (-1,-1,1): d times
+//            u = x + y, w = x - y, e = (-(u + z), z - w, w + z, u - z)
+//            (e_i = -v_i . q), b = the least e_i (lowest i on ties), q = 2q - v_b;
+//            then ldexp((max_i e_i - 1) float32(1/sqrt 3), -d) k.  The copy at
+//            the nearest vertex is the nearest of the four (the reflection
+//            swapping two vertices is a symmetry of the set), so the
+//            tetrahedron's face-plane bound of the last q, scaled back, bounds
+//            the distance to the set
 // The type is a template argument: callers loop over primitives grouped by
 // type, so no branch on the type sits inside the loop.  kHopRoot: the roots
 // are taken by sqrt_hop (hop decisions only; the values themselves may differ
@@ -127,6 +141,23 @@ __device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
       const float r2 = x2 + y2;
       const float f = (((2.f * qy) * (y2 - 3.f * x2)) * w + r2 * r2) - (9.f * z2 - 1.f) * w;
       return f * r[13];
+    } else if constexpr (T == kPrimSierpinski) {
+      const int depth = (int)r[14];  // an integer in [0, kSierpinskiMaxDepth], validated on the host
+      float x = qx, y = qy, z = qz;
+      for (int l = 0; l < depth; ++l) {
+        const float u = x + y, w = x - y;
+        const float e0 = -(u + z), e1 = z - w, e2 = w + z, e3 = u - z;
+        const bool odd01 = e1 < e0, odd23 = e3 < e2;  // the lesser of each pair, the lower index on a tie
+        const float m01 = odd01 ? e1 : e0, m23 = odd23 ? e3 : e2;
+        const bool low = !(m23 < m01);              // b in {0, 1}
+        const float vx = low ? 1.f : -1.f, vy = (low ? odd01 : odd23) ? -1.f : 1.f;
+        x = 2.f * x - vx;
+        y = 2.f * y - vy;
+        z = 2.f * z - vx * vy;                      // v_z = v_x v_y for the four vertices
+      }
+      const float u = x + y, w = x - y;
+      const float e = fmaxf(fmaxf(-(u + z), z - w), fmaxf(w + z, u - z));
+      return __builtin_amdgcn_ldexpf((e - 1.f) * 0.577350269189625764f, -depth) * r[13];
     } else if constexpr (T == kPrimHexPrism) {
       const float hx = 0.5f * qx, hy = 0.866025403784438646f * qy;
       const float u1 = fabsf(qx) - r[13], u2 = fabsf(hx + hy) - r[13], u3 = fabsf(hy - hx) - r[13];
@@ -144,7 +175,7 @@ __device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
   }
 }
 
-constexpr int kPrimTypes = 10;
+constexpr int kPrimTypes = 11;
 constexpr int kAllTypes = (1 << kPrimTypes) - 1;  // type mask with every type
 constexpr int kFullTypes = 1 << 16;                 // flag beside a type mask: every lane holds every type
 
@@ -181,6 +212,8 @@ __device__ __forceinline__ float union_strided(const PrimGroups& g, Rec rec, int
                                    [&](int p) { f = fminf(f, prim_eval_t<kPrimHexPrism>(rec(p), x, y, z)); });
   for_prims_of_type<kPrimGenus2>(g, first, step,
                                  [&](int p) { f = fminf(f, prim_eval_t<kPrimGenus2>(rec(p), x, y, z)); });
+  for_prims_of_type<kPrimSierpinski>(g, first, step,
+                                     [&](int p) { f = fminf(f, prim_eval_t<kPrimSierpinski>(rec(p), x, y, z)); });
   return f;
 }
 

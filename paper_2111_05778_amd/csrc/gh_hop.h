@@ -100,6 +100,8 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
       v[kPrimHexPrism] = prim_eval_t<kPrimHexPrism, kHopRoot>(rec[kPrimHexPrism], x, y, z);
     if constexpr (kTypes & (1 << kPrimGenus2))
       v[kPrimGenus2] = prim_eval_t<kPrimGenus2, kHopRoot>(rec[kPrimGenus2], x, y, z);
+    if constexpr (kTypes & (1 << kPrimSierpinski))
+      v[kPrimSierpinski] = prim_eval_t<kPrimSierpinski, kHopRoot>(rec[kPrimSierpinski], x, y, z);
 #pragma unroll
     for (int t = 0; t < kPrimTypes; ++t)
       if ((kTypes >> t) & 1) f = (kTypes & kFullTypes) || has[t] ? fminf(f, v[t]) : f;

@@ -73,7 +73,7 @@ def test_describe_size_query_and_validation():
     assert N.lib.sdb_describe(ctypes.byref(s), None, 0, ctypes.byref(need), None, None) == N.GH_OK
     assert need.value == 12 * 16 * 4
     bad = keep.copy()
-    for t in (10.0, 2.5, -1.0):            # unknown primitive types
+    for t in (11.0, 2.5, -1.0):            # unknown primitive types
         bad[3, 0] = t
         s2, keep2 = _spec(bad)
         assert N.lib.sdb_describe(ctypes.byref(s2), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
@@ -86,6 +86,13 @@ def test_describe_size_query_and_validation():
     bad[0, 14:16] = (0.8, 0.8)            # a cone whose (sin, cos) is longer than a unit vector
     s2, keep2 = _spec(bad)
     assert N.lib.sdb_describe(ctypes.byref(s2), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
+    for k, depth in ((0.8, 17.0), (0.8, 2.5), (0.8, -1.0), (0.0, 3.0), (-0.8, 3.0)):
+        bad = W.sierpinski_scene(3).copy()  # depth beyond 16 or not an integer, k <= 0
+        bad[0, 13:15] = (k, depth)
+        s2, keep2 = _spec(bad)
+        assert N.lib.sdb_describe(ctypes.byref(s2), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
+    s2, keep2 = _spec(W.sierpinski_scene(16))
+    assert N.lib.sdb_describe(ctypes.byref(s2), None, 0, ctypes.byref(need), None, None) == N.GH_OK
     bad = keep.copy()
     bad[1, 5] = np.inf
     s3, keep3 = _spec(bad)

@@ -89,6 +89,8 @@ def _named_scene(scene):
             "cone": W.cone_scene(0.41, 0.45, (-0.02, 0.04, 0.0)),
             "hexprism": W.hexprism_scene(0.33, 0.27, (0.02, 0.01, -0.03)),
             "genus2": W.genus2_scene()}.get(scene)
+    if recs is None and scene.startswith("sierpinski"):
+        recs = W.sierpinski_scene(int(scene[10:]))
     if recs is None and scene.startswith("prims"):
         recs = W.primitives_scene(int(scene[5:]))
     if recs is None:
@@ -99,7 +101,8 @@ def _named_scene(scene):
 @pytest.mark.parametrize("scene,n", [("sphere", 64), ("csg0", 64), ("csg1", 100), ("csg2", 37), ("csg0", 128),
                                      ("box", 50), ("boxbound", 33), ("csg3", 1), ("csg4", 2), ("cylinder", 64),
                                      ("cone", 57), ("hexprism", 64), ("prims0", 128), ("prims1", 75),
-                                     ("genus2", 48), ("genus2", 64)])
+                                     ("genus2", 48), ("genus2", 64), ("sierpinski0", 40), ("sierpinski3", 64),
+                                     ("sierpinski6", 128), ("sierpinski16", 33)])
 def test_matches_fp32_twin(gh, scene, n):
     recs = _named_scene(scene)
     g = W.grid(n)
@@ -173,7 +176,8 @@ def test_sphere_n64_against_fp64_oracle(gh):
     assert abs(area - math.pi) < 5e-3
 
 
-@pytest.mark.parametrize("scene,n", [("sphere", 48), ("csg0", 64), ("csg1", 77), ("prims0", 96), ("genus2", 40)])
+@pytest.mark.parametrize("scene,n", [("sphere", 48), ("csg0", 64), ("csg1", 77), ("prims0", 96), ("genus2", 40),
+                                     ("sierpinski5", 96)])
 def test_dense_equals_hop(gh, scene, n):
     recs = _named_scene(scene)
     g = W.grid(n)
@@ -342,6 +346,22 @@ def test_uneven_type_groups_match_twin(gh, n_prim, lanes):
     native, P = gh
     recs = W.csg_scene(7, n_prim)
     g = W.grid(61)
+    native.gh_set_tuning(hop_lanes_per_ray=lanes)
+    try:
+        out = _run(gh, recs, *g)
+    finally:
+        native.gh_set_tuning(0)
+    ref = ohop.gridhop(osdb.SDB.prims(recs), *g, precision="f32")
+    _check_against_twin(out, ref, *[float(x) for x in g])
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 3])
+def test_sierpinski_in_a_union_matches_twin(gh, lanes):
+    # the fractal beside the other types: records in registers (one per lane
+    # at R = 1, a group of three at R = 3) and read from LDS (lanes = 0)
+    native, P = gh
+    recs = np.concatenate([W.csg_scene(0), W.sierpinski_scene(5, scale=2.0, centre=(0.31, -0.27, 0.22))])
+    g = W.grid(80)
     native.gh_set_tuning(hop_lanes_per_ray=lanes)
     try:
         out = _run(gh, recs, *g)

@@ -27,6 +27,8 @@ Primitive record layout (float32, PRIM_STRIDE = 16 per primitive):
                                 +-60 degrees from it; capped at z = -a, a
           genus2    (k, 0, 0)   k F(q) with the genus-2 polynomial F of the
                                 paper's Section 5.1; M = s I scales it
+          sierpinski (k, d, 0)  the Sierpinski tetrahedron of depth d on the
+                                tetrahedron (+-1, +-1, +-1); M = s I, k = 1/s
 """
 import json
 import os
@@ -34,7 +36,7 @@ import os
 import numpy as np
 
 PRIM_SPHERE, PRIM_BOX, PRIM_TORUS, PRIM_CAPSULE, PRIM_PLANE, PRIM_BOXBOUND = 0, 1, 2, 3, 4, 5
-PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM, PRIM_GENUS2 = 6, 7, 8, 9
+PRIM_CYLINDER, PRIM_CONE, PRIM_HEXPRISM, PRIM_GENUS2, PRIM_SIERPINSKI = 6, 7, 8, 9, 10
 PRIM_STRIDE = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -128,6 +130,16 @@ def genus2_scene(lo=-1.0, extent=2.0):
     fz = 20 * B + 36 * B ** 3 + 16 * B ** 4
     k = 1.0 / (s * np.sqrt(2 * fx * fx + fz * fz))
     return _record(PRIM_GENUS2, c, s * np.eye(3), (k,))[None, :]
+
+
+def sierpinski_scene(depth=6, scale=1.2, centre=(0.013, -0.021, 0.008)):
+    """The Sierpinski tetrahedron of the given depth (Section 5.1's fractal
+    scene): the regular tetrahedron with vertices (+-1, +-1, +-1) (an even
+    number of minus signs) in local q = scale (p - centre), so its vertices
+    sit at distance sqrt(3)/scale from the centre, k = 1/scale.  The centre
+    is off the lattice so that no vertex falls on a lattice point."""
+    s = float(scale)
+    return _record(PRIM_SIERPINSKI, centre, s * np.eye(3), (1.0 / s, depth))[None, :]
 
 
 def primitives_scene(seed=0):
