@@ -69,14 +69,16 @@ PEAK_BF16_MFMA = 2.5e15   # dense, no sparsity
 #            mul + sub + mul + sub, mul (k)                        = 18
 #   sierpinski per level: add + sub (u, w), 4 add/sub (e), 3 compares, 4
 #            selects, 3 mul + 3 sub (q = 2q - v), mul (v_z) = 20; at the end
-#            6 for e, 3 max, sub, mul, ldexp, mul (k) = 13: 13 + 20 d
+#            20 as per level (e, nearest vertex), 7 min/max, 2 sub, 5 for the
+#            two region tests, the three distances (mul; 6 + sqrt; 5 + sqrt),
+#            2 selects, ldexp, mul (k) = 52: 52 + 20 d
 OPS = {0: 18 + 7, 1: 18 + 19, 2: 18 + 10, 3: 18 + 11, 4: 6, 5: 18 + 8, 6: 18 + 16, 7: 18 + 11, 8: 18 + 15,
        9: 18 + 18}
 
 
 def prim_ops(r):
     t = int(r[0])
-    return 18 + 13 + 20 * int(r[14]) if t == 10 else OPS[t]
+    return 18 + 52 + 20 * int(r[14]) if t == 10 else OPS[t]
 
 
 def ops_per_eval(records):

@@ -118,9 +118,10 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
  *           Sierpinski (k, d): the tetrahedron of depth d (an integer in [0, 16])
  *           on the regular tetrahedron with vertices (1,1,1), (1,-1,-1), (-1,1,-1),
  *           (-1,-1,1) in local q; d times q = 2q - v_b with v_b the nearest vertex
- *           (largest v . q, lowest index on ties), then k 2^-d times the maximum of
- *           the four face-plane distances at the last q.  With M = s R (R a
- *           rotation) k = 1/s makes it a bound in world units; k > 0.
+ *           (largest v . q, lowest index on ties), then k 2^-d times the signed
+ *           distance to the tetrahedron at the last q: the exact signed distance to
+ *           the set in local units.  With M = s R (R a rotation) k = 1/s makes it
+ *           the distance in world units; k > 0.
  * The bound is the minimum over the records (union, Section 4.3). */
 #define GH_PRIM_FLOATS 16
 

@@ -100,30 +100,64 @@ def tetra_bound_f64(q):
     return ((-q @ TETRA_V.T) - 1.0).max(axis=1) / np.sqrt(3.0)
 
 
+def _segment_distance_f64(P, A, B):
+    d = B - A
+    t = np.clip((P - A) @ d / (d @ d), 0.0, 1.0)
+    return np.linalg.norm(P - (A + t[:, None] * d), axis=1)
+
+
+def _triangle_distance_f64(P, A, B, C):
+    """Distance from the points P to the triangle ABC: to its plane where the
+    foot of the perpendicular falls inside it, else to the nearest edge."""
+    n = np.cross(B - A, C - A)
+    n = n / np.linalg.norm(n)
+    height = (P - A) @ n
+    F = P - height[:, None] * n
+    u, v, w = B - A, C - A, F - A
+    uu, uv, vv, wu, wv = u @ u, u @ v, v @ v, w @ u, w @ v
+    den = uu * vv - uv * uv
+    beta = (vv * wu - uv * wv) / den
+    gamma = (uu * wv - uv * wu) / den
+    inside = (beta >= 0) & (gamma >= 0) & (beta + gamma <= 1)
+    edges = np.minimum(np.minimum(_segment_distance_f64(P, A, B), _segment_distance_f64(P, B, C)),
+                       _segment_distance_f64(P, C, A))
+    return np.where(inside, np.abs(height), edges)
+
+
+def tetra_distance_f64(q):
+    """The signed distance to T: inside, minus the distance to the nearest
+    face plane (the face-plane bound is exact there); outside, the distance
+    to the nearest of the four faces."""
+    q = np.asarray(q, dtype=np.float64)
+    plane = tetra_bound_f64(q)
+    faces = [_triangle_distance_f64(q, *[TETRA_V[k] for k in range(4) if k != f]) for f in range(4)]
+    return np.where(plane <= 0.0, plane, np.min(np.stack(faces), axis=0))
+
+
 def sierpinski_f64(q, depth):
-    """A signed distance bound of the Sierpinski tetrahedron of depth d
+    """The signed distance to the Sierpinski tetrahedron of depth d
     (Section 5.1, fourth scene; the paper gives no formula, this one is
     written from the geometry).  S_0 = T and S_d is the union of the four
     copies (S_{d-1} + v_i) / 2.  With b the vertex nearest to q (largest
     v_i . q, lowest i on ties):
-        f_0(q) = tetra_bound(q)
+        f_0(q) = the signed distance to T
         f_d(q) = f_{d-1}(2q - v_b) / 2
-    i.e. the bound of the copy at v_b, scaled back.  That copy is the nearest
-    of the four: the reflection in the bisector plane of v_b and v_j is a
-    symmetry of S_{d-1} and of T that swaps the copies at v_b and v_j, and q
-    lies on v_b's side, so every point of copy j has its mirror image in copy
-    b at most as far from q.  Each copy lies on its own vertex's side of every
-    bisector and meets it at one point, and the copies meet only at points,
-    so a point inside S_d is inside copy b and the distance to the boundary
-    of S_d is the distance to copy b's.  By induction f_d is negative exactly
-    inside S_d and |f_d| is at most the distance to its boundary."""
+    i.e. the distance to the copy at v_b, scaled back.  That copy is the
+    nearest of the four: the reflection in the bisector plane of v_b and v_j
+    is a symmetry of S_{d-1} and of T that swaps the copies at v_b and v_j,
+    and q lies on v_b's side, so every point of copy j has its mirror image
+    in copy b at most as far from q.  Each copy lies on its own vertex's side
+    of every bisector and meets it at one point, and the copies meet only at
+    points, so a point inside S_d is inside copy b and the distance to the
+    boundary of S_d is the distance to copy b's.  By induction f_d is the
+    signed distance to S_d (a bound with equality)."""
     q = np.asarray(q, dtype=np.float64)
     scale = 1.0
     for _ in range(depth):
         b = np.argmax(q @ TETRA_V.T, axis=1)
         q = 2.0 * q - TETRA_V[b]
         scale *= 0.5
-    return scale * tetra_bound_f64(q)
+    return scale * tetra_distance_f64(q)
 
 
 def genus2_gradient_bound(B):
@@ -222,13 +256,24 @@ def sierpinski_f32(x, y, z, depth):
     u = x + y, w = x - y the four values e_i = -v_i . q are
     e_0 = -(u + z), e_1 = z - w, e_2 = w + z, e_3 = u - z; the nearest
     vertex is the least e_i (lowest i on ties).  Per level q = 2q - v_b (2q
-    exact, one rounding per component); at the end
-    ((max_i e_i - 1) * float32(1/sqrt 3)) * 2^-d, applied before the
-    caller's k (the power of two is exact)."""
+    exact, one rounding per component).  At the last q, with the e_i sorted
+    E1 >= E2 >= E3 >= E4, a = E1 - 1, c = E2 - 1 (a / sqrt 3 and c / sqrt 3
+    are the two largest face-plane distances) and the nearest vertex v_b,
+    the distance to T is
+        a * float32(1/sqrt 3)                  if E1 + 3 E2 <= 4  (inside, or beyond one face)
+        sqrt(0.375 (a a + c c) + 0.25 (a c))   if (E1 + E2) + 2 E3 <= 4  (beyond an edge)
+        sqrt((d_x d_x + d_y d_y) + d_z d_z), d = q - v_b   otherwise (beyond a vertex)
+    (the foot of the perpendicular on the nearest face plane lies in the
+    face when every other face-plane distance is at most minus a third of
+    it, the foot on the nearest edge's line lies on the edge when the third
+    is at most minus half the sum of the first two; the faces' normals meet
+    at cos = -1/3).  The result times 2^-d (exact) is returned for the
+    caller's k."""
     x = np.asarray(x, dtype=np.float32).copy()
     y = np.asarray(y, dtype=np.float32).copy()
     z = np.asarray(z, dtype=np.float32).copy()
     V = TETRA_V.astype(np.float32)
+    f = np.float32
 
     def es(x, y, z):
         u, w = x + y, x - y
@@ -236,9 +281,19 @@ def sierpinski_f32(x, y, z, depth):
 
     for _ in range(depth):
         b = np.argmin(es(x, y, z), axis=0)       # lowest index on ties
-        x, y, z = np.float32(2) * x - V[b, 0], np.float32(2) * y - V[b, 1], np.float32(2) * z - V[b, 2]
-    t = (es(x, y, z).max(axis=0) - np.float32(1)) * np.float32(1.0 / np.sqrt(3.0))
-    return t * np.float32(2.0 ** -depth)
+        x, y, z = f(2) * x - V[b, 0], f(2) * y - V[b, 1], f(2) * z - V[b, 2]
+    e = es(x, y, z)
+    E = np.sort(e, axis=0)
+    E1, E2, E3 = E[3], E[2], E[1]
+    b = np.argmin(e, axis=0)
+    a, c = E1 - f(1), E2 - f(1)
+    face = a * f(1.0 / np.sqrt(3.0))
+    with np.errstate(invalid="ignore"):
+        edge = np.sqrt(f(0.375) * (a * a + c * c) + f(0.25) * (a * c))
+    dx, dy, dz = x - V[b, 0], y - V[b, 1], z - V[b, 2]
+    vert = np.sqrt((dx * dx + dy * dy) + dz * dz)
+    t = np.where(E1 + f(3) * E2 <= f(4), face, np.where((E1 + E2) + f(2) * E3 <= f(4), edge, vert))
+    return t.astype(np.float32) * f(2.0 ** -depth)
 
 
 def union_f32(recs, x, y, z):

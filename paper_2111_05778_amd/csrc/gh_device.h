@@ -99,11 +99,14 @@ constexpr float kHopRootMinH = 0x1p-20f;
 //            v_1 = (1,-1,-1), v_2 = (-1,1,-1), v_3 = (-1,-1,1): d times
 //            u = x + y, w = x - y, e = (-(u + z), z - w, w + z, u - z)
 //            (e_i = -v_i . q), b = the least e_i (lowest i on ties), q = 2q - v_b;
-//            then ldexp((max_i e_i - 1) float32(1/sqrt 3), -d) k.  The copy at
-//            the nearest vertex is the nearest of the four (the reflection
-//            swapping two vertices is a symmetry of the set), so the
-//            tetrahedron's face-plane bound of the last q, scaled back, bounds
-//            the distance to the set
+//            then ldexp(t, -d) k with t the signed distance to T at the last q:
+//            with the e_i sorted E1 >= E2 >= E3, a = E1 - 1, c = E2 - 1,
+//              a float32(1/sqrt 3)                  if E1 + 3 E2 <= 4 (inside or beyond a face)
+//              sqrt(0.375 (a a + c c) + 0.25 (a c))  if (E1 + E2) + 2 E3 <= 4 (beyond an edge)
+//              |q - v_b| = sqrt((dx dx + dy dy) + dz dz)  otherwise (beyond the nearest vertex).
+//            The copy at the nearest vertex is the nearest of the four (the
+//            reflection swapping two vertices is a symmetry of the set), so
+//            this is the signed distance to the set itself
 // The type is a template argument: callers loop over primitives grouped by
 // type, so no branch on the type sits inside the loop.  kHopRoot: the roots
 // are taken by sqrt_hop (hop decisions only; the values themselves may differ
@@ -155,9 +158,27 @@ __device__ __forceinline__ float prim_eval_t(Ptr r, float x, float y, float z) {
         y = 2.f * y - vy;
         z = 2.f * z - vx * vy;                      // v_z = v_x v_y for the four vertices
       }
+      // the distance to T at the last q: beyond one face (or inside), beyond
+      // an edge, or beyond a vertex (the nearest one, picked as in the loop)
       const float u = x + y, w = x - y;
-      const float e = fmaxf(fmaxf(-(u + z), z - w), fmaxf(w + z, u - z));
-      return __builtin_amdgcn_ldexpf((e - 1.f) * 0.577350269189625764f, -depth) * r[13];
+      const float e0 = -(u + z), e1 = z - w, e2 = w + z, e3 = u - z;
+      const bool odd01 = e1 < e0, odd23 = e3 < e2;
+      const bool low = !((odd23 ? e3 : e2) < (odd01 ? e1 : e0));
+      const float vx = low ? 1.f : -1.f, vy = (low ? odd01 : odd23) ? -1.f : 1.f;
+      const float h01 = fmaxf(e0, e1), l01 = fminf(e0, e1), h23 = fmaxf(e2, e3), l23 = fminf(e2, e3);
+      const float mh = fminf(h01, h23), ml = fmaxf(l01, l23);
+      const float E1 = fmaxf(h01, h23), E2 = fmaxf(mh, ml), E3 = fminf(mh, ml);  // the three largest e_i
+      const float a = E1 - 1.f, c = E2 - 1.f;
+      float t;
+      if (E1 + 3.f * E2 <= 4.f) {
+        t = a * 0.577350269189625764f;
+      } else if ((E1 + E2) + 2.f * E3 <= 4.f) {
+        t = root(0.375f * (a * a + c * c) + 0.25f * (a * c));
+      } else {
+        const float dx = x - vx, dy = y - vy, dz = z - vx * vy;
+        t = root((dx * dx + dy * dy) + dz * dz);
+      }
+      return __builtin_amdgcn_ldexpf(t, -depth) * r[13];
     } else if constexpr (T == kPrimHexPrism) {
       const float hx = 0.5f * qx, hy = 0.866025403784438646f * qy;
       const float u1 = fabsf(qx) - r[13], u2 = fabsf(hx + hy) - r[13], u3 = fabsf(hy - hx) - r[13];

@@ -1,12 +1,14 @@
 """Pins of the oracle's Sierpinski tetrahedron bound (Section 5.1's fractal
 scene; the paper gives no formula, so the pins come from the geometry).
 
-S_d is the union of 4^d tetrahedra, listed here by brute force.  The bound
-must be negative exactly inside them, and its magnitude must not exceed the
-exact distance to the boundary of the union, computed from point-triangle
-distances.  The closed forms: at the centroid, depth 0 gives minus the
-inradius of T (1/sqrt 3), depth 1 the inradius of the octahedral hole
-|x| + |y| + |z| <= 1 (1/sqrt 3 again, with the opposite sign)."""
+S_d is the union of 4^d tetrahedra, listed here by brute force.  The
+function must be negative exactly inside them, and its magnitude must equal
+the distance to the boundary of the union, the least point-triangle distance
+over all their faces (it is the exact signed distance, not only a bound).
+The closed forms: at the centroid, depth 0 gives minus the inradius of T
+(1/sqrt 3), depth 1 the inradius of the octahedral hole |x| + |y| + |z| <= 1
+(1/sqrt 3 again, with the opposite sign); beyond a vertex on its axis the
+distance is to that vertex at every depth."""
 import numpy as np
 import pytest
 
@@ -88,17 +90,14 @@ def points(depth, rng, n=1500):
 
 
 @pytest.mark.parametrize("depth", [0, 1, 2, 3])
-def test_sign_is_membership_and_magnitude_below_distance(depth):
+def test_sign_is_membership_and_magnitude_is_distance(depth):
     rng = np.random.default_rng(depth)
     P = points(depth, rng)
     inside, dist, margin = exact(P, depth)
     f = S.sierpinski_f64(P, depth)
     ok = margin > 1e-9                        # not on a face of a tetrahedron
     assert np.array_equal(f[ok] < 0, inside[ok])
-    assert np.all(np.abs(f) <= dist + 1e-12)
-    # not a vacuous bound: it reaches the distance near the faces
-    near = dist < 0.05
-    assert np.median(np.abs(f[near]) / dist[near]) > 0.5
+    np.testing.assert_allclose(np.abs(f), dist, rtol=0, atol=1e-12)
 
 
 def test_tighter_than_hull_bounds():
@@ -119,6 +118,14 @@ def test_closed_forms_at_the_centroid():
     # the octahedral hole's inradius is the exact distance at depth 1
     inside, dist, _ = exact(o, 1)
     assert not inside[0] and dist[0] == pytest.approx(1 / np.sqrt(3), abs=1e-12)
+
+
+def test_distance_beyond_a_vertex():
+    for d in range(6):
+        for i in range(4):
+            t = 2.0 / 3.0 + np.arange(1, 4)[:, None]      # points v_i (1 + k/3 ...), off T on the axis
+            f = S.sierpinski_f64(t * V[i], d)
+            np.testing.assert_allclose(f, (t[:, 0] - 1) * np.sqrt(3.0), rtol=1e-13)
 
 
 def test_vertices_are_fixed_points():
