@@ -214,6 +214,9 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
   // Unions of the solids, cylinders, cones and hexagonal prisms (the paper's
   // primitives) get a kernel that skips the other types.
   constexpr int kNoPlanes = kSolids | (1 << kPrimCylinder) | (1 << kPrimCone) | (1 << kPrimHexPrism);
+  // Unions of Sierpinski records alone get a kernel that evaluates no other
+  // type (the general kernel evaluates every type at every step).
+  constexpr int kFractal = 1 << kPrimSierpinski;
   // The first pass without a budget carries no budget test.
   auto first = [&](auto kernel_nb, auto kernel_b) {
     if (budget > 0)
@@ -242,6 +245,11 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
     first(k_hop_prims<R, true, kNoPlanes, false>, k_hop_prims<R, true, kNoPlanes, true>);
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, true, kNoPlanes>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
+                         ws.colmask, ws.colbits, ws.park, npark, ctr);
+  } else if (regs && present == kFractal) {
+    first(k_hop_prims<R, true, kFractal, false>, k_hop_prims<R, true, kFractal, true>);
+    if (budget > 0)
+      hipLaunchKernelGGL((k_hop_long<R, true, kFractal>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
                          ws.colmask, ws.colbits, ws.park, npark, ctr);
   } else if (regs) {
     first(k_hop_prims<R, true, kAllTypes, false>, k_hop_prims<R, true, kAllTypes, true>);

@@ -373,14 +373,15 @@ def test_sierpinski_in_a_union_matches_twin(gh, lanes):
 
 @pytest.mark.parametrize("budget,lanes,scene,n_prim,n", [
     (1, 0, 1, 12, 100), (4, 3, 1, 12, 100), (16, 1, 1, 12, 100), (2, 8, 1, 12, 100), (0, 0, 1, 12, 100),
-    (3, 0, 7, 24, 61), (1, 4, 7, 5, 61), (2, 0, 7, 1, 61), (2, 0, "prims0", 0, 72), (5, 2, "prims1", 0, 50)])
+    (3, 0, 7, 24, 61), (1, 4, 7, 5, 61), (2, 0, 7, 1, 61), (2, 0, "prims0", 0, 72), (5, 2, "prims1", 0, 50),
+    (2, 0, "sierpinski6", 0, 90), (3, 2, "sierpinski4", 0, 64)])
 def test_long_ray_pass_matches_twin(gh, budget, lanes, scene, n_prim, n):
     # a small step budget hands nearly every ray to the window pass, which
     # must continue it bit for bit, for every lanes-per-cell split (8 to 64
     # cells per window) and with records in registers or read from LDS (a
     # type group larger than the split)
     native, P = gh
-    recs = W.primitives_scene(int(scene[5:])) if isinstance(scene, str) else W.csg_scene(scene, n_prim)
+    recs = _named_scene(scene) if isinstance(scene, str) else W.csg_scene(scene, n_prim)
     g = W.grid(n)
     native.gh_set_tuning(hop_lanes_per_ray=lanes, hop_step_budget=budget)
     try:
