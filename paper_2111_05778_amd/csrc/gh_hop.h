@@ -75,33 +75,43 @@ __device__ __forceinline__ void lane_records(const float* __restrict__ srec, con
   }
 }
 
+// One type's value in the register path: +inf for a type outside the mask.
+// The general mask (every type) skips a type the union does not hold by a
+// branch on the group table, which is the same for the whole wave; the
+// narrower masks evaluate their types without a branch.
+template <int T, int kTypes, bool kHopRoot>
+__device__ __forceinline__ float lane_type(const PrimGroups& groups, const float (&rec)[kPrimTypes][GH_PRIM_FLOATS],
+                                           float x, float y, float z) {
+  if constexpr (!(kTypes & (1 << T))) {
+    return __builtin_inff();
+  } else {
+    if constexpr ((kTypes & kAllTypes) == kAllTypes)
+      if (!(groups.start[T + 1] > groups.start[T])) return __builtin_inff();
+    return prim_eval_t<T, kHopRoot>(rec[T], x, y, z);
+  }
+}
+
 template <int R, bool kRegs, int kTypes, bool kHopRoot = true>
 __device__ __forceinline__ float lane_union(const float* __restrict__ srec, const PrimGroups& groups, int q,
                                             const float (&rec)[kPrimTypes][GH_PRIM_FLOATS],
                                             const bool (&has)[kPrimTypes], float x, float y, float z) {
   if constexpr (kRegs) {
     float f = __builtin_inff();
-    // Every type is evaluated (a lane without one holds another record and
-    // discards the value): no branch splits the step, so the independent
-    // chains of the formulas interleave.
+    // Every type of the mask is evaluated (a lane without one holds another
+    // record and discards the value): no lane-dependent branch splits the
+    // step, so the independent chains of the formulas interleave.
     float v[kPrimTypes];
-    if constexpr (kTypes & (1 << kPrimSphere)) v[kPrimSphere] = prim_eval_t<kPrimSphere, kHopRoot>(rec[kPrimSphere], x, y, z);
-    if constexpr (kTypes & (1 << kPrimBox)) v[kPrimBox] = prim_eval_t<kPrimBox, kHopRoot>(rec[kPrimBox], x, y, z);
-    if constexpr (kTypes & (1 << kPrimTorus)) v[kPrimTorus] = prim_eval_t<kPrimTorus, kHopRoot>(rec[kPrimTorus], x, y, z);
-    if constexpr (kTypes & (1 << kPrimCapsule))
-      v[kPrimCapsule] = prim_eval_t<kPrimCapsule, kHopRoot>(rec[kPrimCapsule], x, y, z);
-    if constexpr (kTypes & (1 << kPrimPlane)) v[kPrimPlane] = prim_eval_t<kPrimPlane, kHopRoot>(rec[kPrimPlane], x, y, z);
-    if constexpr (kTypes & (1 << kPrimBoxBound))
-      v[kPrimBoxBound] = prim_eval_t<kPrimBoxBound, kHopRoot>(rec[kPrimBoxBound], x, y, z);
-    if constexpr (kTypes & (1 << kPrimCylinder))
-      v[kPrimCylinder] = prim_eval_t<kPrimCylinder, kHopRoot>(rec[kPrimCylinder], x, y, z);
-    if constexpr (kTypes & (1 << kPrimCone)) v[kPrimCone] = prim_eval_t<kPrimCone, kHopRoot>(rec[kPrimCone], x, y, z);
-    if constexpr (kTypes & (1 << kPrimHexPrism))
-      v[kPrimHexPrism] = prim_eval_t<kPrimHexPrism, kHopRoot>(rec[kPrimHexPrism], x, y, z);
-    if constexpr (kTypes & (1 << kPrimGenus2))
-      v[kPrimGenus2] = prim_eval_t<kPrimGenus2, kHopRoot>(rec[kPrimGenus2], x, y, z);
-    if constexpr (kTypes & (1 << kPrimSierpinski))
-      v[kPrimSierpinski] = prim_eval_t<kPrimSierpinski, kHopRoot>(rec[kPrimSierpinski], x, y, z);
+    v[kPrimSphere] = lane_type<kPrimSphere, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimBox] = lane_type<kPrimBox, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimTorus] = lane_type<kPrimTorus, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimCapsule] = lane_type<kPrimCapsule, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimPlane] = lane_type<kPrimPlane, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimBoxBound] = lane_type<kPrimBoxBound, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimCylinder] = lane_type<kPrimCylinder, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimCone] = lane_type<kPrimCone, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimHexPrism] = lane_type<kPrimHexPrism, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimGenus2] = lane_type<kPrimGenus2, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimSierpinski] = lane_type<kPrimSierpinski, kTypes, kHopRoot>(groups, rec, x, y, z);
 #pragma unroll
     for (int t = 0; t < kPrimTypes; ++t)
       if ((kTypes >> t) & 1) f = (kTypes & kFullTypes) || has[t] ? fminf(f, v[t]) : f;
