@@ -76,19 +76,13 @@ __device__ __forceinline__ void lane_records(const float* __restrict__ srec, con
 }
 
 // One type's value in the register path: +inf for a type outside the mask.
-// The general mask (every type) skips a type the union does not hold by a
-// branch on the group table, which is the same for the whole wave; the
-// narrower masks evaluate their types without a branch.
 template <int T, int kTypes, bool kHopRoot>
-__device__ __forceinline__ float lane_type(const PrimGroups& groups, const float (&rec)[kPrimTypes][GH_PRIM_FLOATS],
-                                           float x, float y, float z) {
-  if constexpr (!(kTypes & (1 << T))) {
+__device__ __forceinline__ float lane_type(const float (&rec)[kPrimTypes][GH_PRIM_FLOATS], float x, float y,
+                                           float z) {
+  if constexpr (!(kTypes & (1 << T)))
     return __builtin_inff();
-  } else {
-    if constexpr ((kTypes & kAllTypes) == kAllTypes)
-      if (!(groups.start[T + 1] > groups.start[T])) return __builtin_inff();
+  else
     return prim_eval_t<T, kHopRoot>(rec[T], x, y, z);
-  }
 }
 
 template <int R, bool kRegs, int kTypes, bool kHopRoot = true>
@@ -101,17 +95,17 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
     // record and discards the value): no lane-dependent branch splits the
     // step, so the independent chains of the formulas interleave.
     float v[kPrimTypes];
-    v[kPrimSphere] = lane_type<kPrimSphere, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimBox] = lane_type<kPrimBox, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimTorus] = lane_type<kPrimTorus, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimCapsule] = lane_type<kPrimCapsule, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimPlane] = lane_type<kPrimPlane, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimBoxBound] = lane_type<kPrimBoxBound, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimCylinder] = lane_type<kPrimCylinder, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimCone] = lane_type<kPrimCone, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimHexPrism] = lane_type<kPrimHexPrism, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimGenus2] = lane_type<kPrimGenus2, kTypes, kHopRoot>(groups, rec, x, y, z);
-    v[kPrimSierpinski] = lane_type<kPrimSierpinski, kTypes, kHopRoot>(groups, rec, x, y, z);
+    v[kPrimSphere] = lane_type<kPrimSphere, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimBox] = lane_type<kPrimBox, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimTorus] = lane_type<kPrimTorus, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimCapsule] = lane_type<kPrimCapsule, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimPlane] = lane_type<kPrimPlane, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimBoxBound] = lane_type<kPrimBoxBound, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimCylinder] = lane_type<kPrimCylinder, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimCone] = lane_type<kPrimCone, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimHexPrism] = lane_type<kPrimHexPrism, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimGenus2] = lane_type<kPrimGenus2, kTypes, kHopRoot>(rec, x, y, z);
+    v[kPrimSierpinski] = lane_type<kPrimSierpinski, kTypes, kHopRoot>(rec, x, y, z);
 #pragma unroll
     for (int t = 0; t < kPrimTypes; ++t)
       if ((kTypes >> t) & 1) f = (kTypes & kFullTypes) || has[t] ? fminf(f, v[t]) : f;

@@ -251,12 +251,11 @@ static void launch_hop_r(const DevSdb& d, const Grid& g, const Workspace& ws, gh
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, true, kFractal>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g,
                          ws.colmask, ws.colbits, ws.park, npark, ctr);
-  } else if (regs) {
-    first(k_hop_prims<R, true, kAllTypes, false>, k_hop_prims<R, true, kAllTypes, true>);
-    if (budget > 0)
-      hipLaunchKernelGGL((k_hop_long<R, true>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
-                         ws.colbits, ws.park, npark, ctr);
   } else {
+    // Other unions read their records from LDS at every step, which only
+    // touches the types present: holding a record of every type in
+    // registers cost more (CSG-12 with a plane at N = 512, 0.43 against
+    // 0.20 ms).
     first(k_hop_prims<R, false, kAllTypes, false>, k_hop_prims<R, false, kAllTypes, true>);
     if (budget > 0)
       hipLaunchKernelGGL((k_hop_long<R, false>), dim3(blocks), dim3(kBlock), 0, s, d.prims, d.groups, g, ws.colmask,
@@ -300,10 +299,7 @@ static void launch_trace_r(const DevSdb& d, const Grid& g, const TraceConsts& tc
   if (most <= R && (present & ~kSolids) == 0)  // records in registers, solids only
     hipLaunchKernelGGL((k_trace_prims<R, true, kSolids>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g,
                        tc, ws.colmask, ws.colbits, ctr);
-  else if (most <= R)
-    hipLaunchKernelGGL((k_trace_prims<R, true, kAllTypes>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups,
-                       g, tc, ws.colmask, ws.colbits, ctr);
-  else
+  else  // records read from LDS, as for the hop's other unions
     hipLaunchKernelGGL((k_trace_prims<R, false>), dim3(nbh * nbw), dim3(kBlock), 0, s, d.prims, d.groups, g, tc,
                        ws.colmask, ws.colbits, ctr);
 }

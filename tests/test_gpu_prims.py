@@ -357,8 +357,8 @@ def test_uneven_type_groups_match_twin(gh, n_prim, lanes):
 
 @pytest.mark.parametrize("lanes", [0, 1, 3])
 def test_sierpinski_in_a_union_matches_twin(gh, lanes):
-    # the fractal beside the other types: records in registers (one per lane
-    # at R = 1, a group of three at R = 3) and read from LDS (lanes = 0)
+    # the fractal beside the other types (records read from LDS, one or
+    # three lanes per ray, and the default)
     native, P = gh
     recs = np.concatenate([W.csg_scene(0), W.sierpinski_scene(5, scale=2.0, centre=(0.31, -0.27, 0.22))])
     g = W.grid(80)
