@@ -121,7 +121,8 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
  *           (largest v . q, lowest index on ties), then k 2^-d times the signed
  *           distance to the tetrahedron at the last q: the exact signed distance to
  *           the set in local units.  With M = s R (R a rotation) k = 1/s makes it
- *           the distance in world units; k > 0.
+ *           the distance in world units; k > 0 (with k >= 2^27 the hop takes the
+ *           LDS-record kernel with exact roots).
  * The bound is the minimum over the records (union, Section 4.3). */
 #define GH_PRIM_FLOATS 16
 

@@ -357,6 +357,10 @@ gh_status sdb_describe(const gh_sdb_spec* spec_h, void* dev_blob, size_t blob_by
   for (int t : {(int)gh::kPrimTorus, (int)gh::kPrimCylinder})
     for (int p = groups.start[t]; p < groups.start[t + 1]; ++p)
       if (!(fabsf(sorted[(size_t)p * GH_PRIM_FLOATS + 13]) >= 0x1p-23f)) d.flags &= ~gh::kSdbRadiiNormal;
+  // A Sierpinski record's edge and vertex roots are scaled by 2^-d k: the
+  // hop root's 2^-48 floor stays below 2^-21 <= h only for k < 2^27.
+  for (int p = groups.start[gh::kPrimSierpinski]; p < groups.start[gh::kPrimSierpinski + 1]; ++p)
+    if (!(sorted[(size_t)p * GH_PRIM_FLOATS + 13] < 0x1p27f)) d.flags &= ~gh::kSdbRadiiNormal;
   d.prims = (const float*)dev_blob;
   d.groups = groups;
   memset(desc_h, 0, sizeof(*desc_h));

@@ -61,8 +61,10 @@ __device__ __forceinline__ float lattice(const Grid& g, int idx) { return g.lo +
 // cylinder's radius.  The cone's root is multiplied by c and followed by the
 // subtraction of (a - qz) s, which either absorbs it or leaves a value below
 // 2^-22 on both sides, so the maximum with the cap term gives s = 0 either
-// way or the same cap value.  Kernels that use it run only when the grid and
-// the union meet these conditions.
+// way or the same cap value.  A Sierpinski record's edge and vertex roots are
+// the value itself times 2^-d k, below 2^-48 k there, hence k < 2^27 for
+// those records.  Kernels that use it run only when the grid and the union
+// meet these conditions.
 __device__ __forceinline__ float sqrt_hop(float a) {
   a = fmaxf(a, 0x1p-96f);
   const float s = __builtin_amdgcn_sqrtf(a);
