@@ -98,7 +98,21 @@ def test_analytic_batch_matches_twin(gh):
     recs = [W.csg_scene(sc["seed"], sc["n_prim"]) for sc in scenes]
     grids = [W.grid(n) for n in sizes]
     batch = P.BatchPolygonizer([(P.Bound.prims(r), *g) for r, g in zip(recs, grids)])
-    res = batch.run()
+    _check_batch_twin(recs, grids, batch.run())
+
+
+def test_batch_of_other_families_matches_twin(gh):
+    # the paper's seven primitives, the genus-2 surface, Sierpinski
+    # tetrahedra and a union of CSG-12 with one, in one launch
+    torch, N, P = gh
+    recs = [W.primitives_scene(0), W.genus2_scene(), W.sierpinski_scene(4), W.sierpinski_scene(7),
+            np.concatenate([W.csg_scene(0), W.sierpinski_scene(5, scale=2.0, centre=(0.31, -0.27, 0.22))])]
+    grids = [W.grid(n) for n in (48, 40, 64, 80, 56)]
+    batch = P.BatchPolygonizer([(P.Bound.prims(r), *g) for r, g in zip(recs, grids)])
+    _check_batch_twin(recs, grids, batch.run())
+
+
+def _check_batch_twin(recs, grids, res):
     for r, g, m in zip(recs, grids, res):
         n, lo, h = g
         ref = ohop.gridhop(osdb.SDB.prims(r), n, lo, h, precision="f32")
