@@ -57,13 +57,15 @@ def _scene(name):
         return W.genus2_scene()
     if name.startswith("prims"):
         return W.primitives_scene(int(name[5:]))
+    if name.startswith("sierpinski"):
+        return W.sierpinski_scene(int(name[10:]))
     return W.csg_scene(int(name[3:]))
 
 
 @pytest.mark.parametrize("scene,n,lanes", [
     ("sphere", 64, 0), ("csg0", 64, 0), ("csg1", 100, 0), ("csg2", 37, 0), ("csg3", 128, 1), ("csg4", 48, 8),
     ("box", 50, 0), ("xplane", 16, 0), ("zplane_top", 16, 0), ("csg0", 1, 0), ("csg0", 2, 0), ("csg7", 61, 4),
-    ("prims0", 80, 0), ("genus2", 32, 0)])
+    ("prims0", 80, 0), ("genus2", 32, 0), ("sierpinski5", 72, 0), ("sierpinski3", 40, 2)])
 def test_traced_matches_fp32_twin(gh, scene, n, lanes):
     recs = _scene(scene)
     g = W.grid(n)
