@@ -125,6 +125,8 @@ enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
  *           LDS-record kernel with exact roots).
  * The bound is the minimum over the records (union, Section 4.3). */
 #define GH_PRIM_FLOATS 16
+/* Number of record types: the type field is an integer in [0, GH_PRIM_TYPES). */
+#define GH_PRIM_TYPES 11
 
 typedef struct {
   int32_t kind;                  /* GH_SDB_PRIMS or GH_SDB_MLP */
@@ -142,7 +144,7 @@ typedef struct {
   const float* const* weights_h; /* depth+1 host arrays, row-major fan_out x fan_in */
   const float* const* biases_h;  /* depth+1 host arrays of fan_out */
   float a_s, r0, a_n, b;
-  float bf16_margin;             /* eps >= max |f_bf16 - f_fp32| (bf16 modes) */
+  float bf16_margin;             /* eps >= max |f_bf16 - f_fp32|, > 0 in the bf16 modes (gh_bf16_margin) */
   int32_t activation;            /* GH_ACT_SOFTPLUS (0) or GH_ACT_RELU; gh_backward takes softplus only */
 } gh_sdb_spec;
 
@@ -266,6 +268,21 @@ gh_status gh_backward_workspace_size(const gh_sdb_desc* desc_h, int64_t corner_c
 gh_status gh_backward(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
                       int64_t corner_cap, const float* dL_dverts, float* dL_dtheta, void* bws, size_t bws_bytes,
                       gh_counters* ctr, void* stream);
+
+/* Margin of the bf16 decisions of a network bound.  The paper keeps a learned
+ * bound safe by shrinking it (Section 5.2, the factor lambda); evaluating it
+ * in bf16 adds an error that the hop test and the corner signs must also
+ * absorb, and this measures it: the bound at m points xyz [m][3] in FP32 into
+ * f32 [m] and in `precision` (GH_PREC_BF16 or GH_PREC_BF16X3) into flp [m],
+ * both with the library's own evaluators, then
+ *   *margin = factor * max_i |flp[i] - f32[i]|      (one float, device)
+ * with a fixed reduction order (the same bits every run), or NaN when a value
+ * or difference is not finite.  The descriptor may hold any precision (it
+ * carries both weight forms).  factor in [1, 1000]; m = 0 gives 0.  Pass the
+ * result as gh_sdb_spec.bf16_margin: it is a measured bound over the points
+ * given, not a proof, so the points should cover the grid's cube. */
+gh_status gh_bf16_margin(const gh_sdb_desc* desc_h, int32_t precision, const float* xyz, int64_t m, float factor,
+                         float* f32, float* flp, float* margin, void* stream);
 
 /* Evaluate the bound at m points xyz [m][3] (device) into f [m] (device). */
 gh_status gh_eval_points(const gh_sdb_desc* desc_h, const float* xyz, float* f, int64_t m, void* stream);

@@ -68,9 +68,12 @@ def device_key(device=None):
 def signature(spec, n):
     """Workload key: the bound's kind and shape (not its values) and the grid size."""
     if spec.kind == N.GH_SDB_PRIMS:
-        types = [0] * 6
+        types = [0] * N.GH_PRIM_TYPES
         for q in range(spec.n_prim):
-            types[int(spec.prims_h[q * N.GH_PRIM_FLOATS])] += 1
+            t = spec.prims_h[q * N.GH_PRIM_FLOATS]
+            if not (t == int(t) and 0 <= int(t) < N.GH_PRIM_TYPES):
+                raise ValueError(f"record {q} has type {t}, not an integer in [0, {N.GH_PRIM_TYPES})")
+            types[int(t)] += 1
         return f"prims:{'-'.join(map(str, types))}:n{int(n)}"
     return f"mlp:w{spec.width}:d{spec.depth}:f{spec.n_freq}:p{spec.precision}:n{int(n)}"
 

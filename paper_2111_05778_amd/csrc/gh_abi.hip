@@ -15,6 +15,8 @@
 #include "gh_launch.h"
 #include "gh_layout.h"
 
+static_assert(GH_PRIM_TYPES == gh::kPrimTypes, "record type count of the header and the evaluators");
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -98,6 +100,10 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   for (float v : scal)
     if (!finite_bounded(v, 1e6f)) return fail(GH_EINVAL, "network scalar not finite or above 1e6");
   if (sp->bf16_margin < 0.f) return fail(GH_EINVAL, "bf16_margin must be >= 0");
+  // The bf16 modes take a hop or a sign only when it holds for every value
+  // within bf16_margin, so their decisions are uncertified without one.
+  if (sp->precision != GH_PREC_FP32 && !(sp->bf16_margin > 0.f))
+    return fail(GH_EINVAL, "bf16 precisions need bf16_margin > 0 (>= max |f_bf16 - f_fp32|, see gh_bf16_margin)");
   if (!(sp->activation == GH_ACT_SOFTPLUS || sp->activation == GH_ACT_RELU))
     return fail(GH_EINVAL, "activation %d unknown", sp->activation);
   const int k1 = 3 + 6 * F;
@@ -559,6 +565,22 @@ gh_status gh_backward(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws
   gh::BackwardWs bw;
   gh::backward_layout(d.mlp, w.cap, bws, &bw);
   return hip_status(gh::launch_backward(d, g, w, bw, dL_dverts, dL_dtheta, ctr, (hipStream_t)stream), "backward");
+}
+
+gh_status gh_bf16_margin(const gh_sdb_desc* desc_h, int32_t precision, const float* xyz, int64_t m, float factor,
+                         float* f32, float* flp, float* margin, void* stream) {
+  gh::DevSdb d;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if (d.kind != GH_SDB_MLP) return fail(GH_EINVAL, "gh_bf16_margin takes a network bound");
+  if (!(precision == GH_PREC_BF16 || precision == GH_PREC_BF16X3))
+    return fail(GH_EINVAL, "precision %d: GH_PREC_BF16 or GH_PREC_BF16X3", precision);
+  if (m < 0) return fail(GH_EINVAL, "negative point count");
+  if (!(factor >= 1.f && factor <= 1e3f)) return fail(GH_EINVAL, "factor must be in [1, 1000]");
+  if (!margin || (m > 0 && (!xyz || !f32 || !flp))) return fail(GH_EINVAL, "NULL buffer");
+  const int prec = precision == GH_PREC_BF16 ? gh::kPrecBf16 : gh::kPrecBf16x3;
+  return hip_status(gh::launch_bf16_margin(d, prec, xyz, m, factor, f32, flp, margin, (hipStream_t)stream),
+                    "bf16 margin");
 }
 
 gh_status gh_eval_points(const gh_sdb_desc* desc_h, const float* xyz, float* f, int64_t m, void* stream) {

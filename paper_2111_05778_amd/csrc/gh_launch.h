@@ -97,6 +97,10 @@ hipError_t launch_mc(const DevSdb& d, const Grid& g, const Workspace& ws, float*
                      float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap, int64_t* cells,
                      uint8_t* cases, int64_t cell_cap, gh_counters* ctr, hipStream_t s);
 hipError_t launch_eval_points(const DevSdb& d, const float* xyz, float* f, int64_t m, hipStream_t s);
+// Network values at m points in FP32 (f32) and in bf16 precision prec (flp),
+// then factor * max |flp - f32| into *out (NaN if any value is not finite).
+hipError_t launch_bf16_margin(const DevSdb& d, int prec, const float* xyz, int64_t m, float factor, float* f32,
+                              float* flp, float* out, hipStream_t s);
 // Workspace of the adjoint (gh_backward).
 constexpr int kVjpBlocks = 256;  // blocks of the network VJP, each with its own partial gradient
 struct BackwardWs {

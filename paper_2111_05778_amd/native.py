@@ -21,9 +21,10 @@ GH_SDB_PRIMS, GH_SDB_MLP = 1, 2
 GH_PREC_FP32, GH_PREC_BF16, GH_PREC_BF16X3 = 0, 1, 2
 GH_ACT_SOFTPLUS, GH_ACT_RELU = 0, 1
 GH_PRIM_FLOATS = 16
+GH_PRIM_TYPES = 11
 
 EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_hop_traced", "gh_cont_workspace_size", "gh_cont", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
-           "gh_eval_points", "gh_set_tuning", "gh_get_tuning", "gh_param_count", "gh_backward_workspace_size",
+           "gh_eval_points", "gh_bf16_margin", "gh_set_tuning", "gh_get_tuning", "gh_param_count", "gh_backward_workspace_size",
            "gh_backward", "gh_batch_buffer_size", "gh_batch_create", "gh_batch_run", "gh_batch_capture",
            "gh_batch_replay", "gh_batch_item_count", "gh_batch_destroy", "gh_last_error"]
 
@@ -89,6 +90,7 @@ lib.gh_dense.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp,
 lib.gh_dense_signs_size.argtypes = [_P(gh_grid), _P(_sz)]
 lib.gh_candidates.argtypes = [_P(gh_grid), _vp, _sz, _i64, _vp, _i64, _vp, _vp]
 lib.gh_eval_points.argtypes = [_P(gh_sdb_desc), _vp, _vp, _i64, _vp]
+lib.gh_bf16_margin.argtypes = [_P(gh_sdb_desc), ctypes.c_int32, _vp, _i64, ctypes.c_float, _vp, _vp, _vp, _vp]
 lib.gh_param_count.argtypes = [_P(gh_sdb_desc), _P(_i64)]
 lib.gh_backward_workspace_size.argtypes = [_P(gh_sdb_desc), _i64, _P(_sz)]
 lib.gh_backward.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp, _sz, _vp, _vp]
@@ -196,6 +198,11 @@ def gh_candidates(grid, ws, corner_cap, out, cap, ctr, stream=None):
 
 def gh_eval_points(desc, xyz, f, m, stream=None):
     return lib.gh_eval_points(ctypes.byref(desc), ptr(xyz), ptr(f), int(m), stream_handle(stream))
+
+
+def gh_bf16_margin(desc, precision, xyz, m, factor, f32, flp, margin, stream=None):
+    return lib.gh_bf16_margin(ctypes.byref(desc), int(precision), ptr(xyz), int(m), float(factor), ptr(f32), ptr(flp),
+                              ptr(margin), stream_handle(stream))
 
 
 def gh_set_tuning(hop_lanes_per_ray=0, scan_blocks_per_cu=0, batch_rays_per_item=0, mlp_split=0,

@@ -38,13 +38,19 @@ class Bound:
         return Bound(spec, [rec], device)
 
     @staticmethod
-    def mlp(net, precision="bf16", margin=0.0, device="cuda"):
+    def mlp(net, precision="fp32", margin=None, device="cuda"):
         """Neural bound f = a_s (||p|| - r0) + a_n NN(gamma(p)) + b.
 
         net: dict with "omegas" (F), "weights" (depth+1 arrays, fan_out x
         fan_in), "biases", the scalars "a_s", "r0", "a_n", "b", and
         optionally "activation" ("softplus", the default, or "relu").
-        margin: eps >= |f_bf16 - f_fp32| for the bf16 hop test."""
+        precision: "fp32", "bf16" or "bf16x3".
+        margin: eps >= |f_bf16 - f_fp32|, required (> 0) for the bf16
+        precisions, whose hop tests and signs it certifies: measure it with
+        bf16_margin() over points covering the grid's cube."""
+        if precision != "fp32" and margin is None:
+            raise ValueError(f"precision {precision!r} needs a margin: pass margin=bf16_margin(net, points, "
+                             f"{precision!r}) with points covering the grid's cube")
         ws = [np.ascontiguousarray(np.asarray(w, dtype=np.float32)) for w in net["weights"]]
         bs = [np.ascontiguousarray(np.asarray(b, dtype=np.float32)) for b in net["biases"]]
         om = np.ascontiguousarray(np.asarray(net["omegas"], dtype=np.float32))
@@ -62,7 +68,7 @@ class Bound:
         spec.weights_h = wptr
         spec.biases_h = bptr
         spec.a_s, spec.r0, spec.a_n, spec.b = (float(net[k]) for k in ("a_s", "r0", "a_n", "b"))
-        spec.bf16_margin = float(margin)
+        spec.bf16_margin = float(margin or 0.0)
         return Bound(spec, [ws, bs, om, wptr, bptr], device)
 
     def eval(self, xyz):
@@ -75,11 +81,17 @@ class Bound:
 
 def bf16_margin(net, points, precision="bf16", factor=2.0, device="cuda"):
     """Margin of the bf16 decisions: factor * max |f_bf16 - f_fp32| over the
-    given points, both values from the library's own evaluators."""
-    pts = torch.as_tensor(np.asarray(points, dtype=np.float32), device=device)
-    f32 = Bound.mlp(net, "fp32", device=device).eval(pts)
-    fb = Bound.mlp(net, precision, device=device).eval(pts)
-    return float(factor * (fb - f32).abs().max().item())
+    given points, computed by gh_bf16_margin with the library's own
+    evaluators (one call; the result is read back)."""
+    pts = torch.as_tensor(np.asarray(points, dtype=np.float32), device=device).reshape(-1, 3).contiguous()
+    m = pts.shape[0]
+    bound = Bound.mlp(net, "fp32", device=device)
+    f32 = torch.empty(max(m, 1), dtype=torch.float32, device=device)
+    flp = torch.empty(max(m, 1), dtype=torch.float32, device=device)
+    out = torch.empty(1, dtype=torch.float32, device=device)
+    prec = {"bf16": N.GH_PREC_BF16, "bf16x3": N.GH_PREC_BF16X3}[precision]
+    N.check(N.gh_bf16_margin(bound.desc, prec, pts, m, factor, f32, flp, out), "gh_bf16_margin")
+    return float(out.item())
 
 
 def counters_dict(ctr):

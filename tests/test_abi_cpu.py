@@ -118,3 +118,42 @@ def test_workspace_too_small_is_capacity_error():
                              ctypes.c_void_p(1024), None)
     assert st == N.GH_ECAPACITY
     del desc
+
+
+def _mlp_spec(net, precision, margin):
+    ws = [np.ascontiguousarray(w, dtype=np.float32) for w in net["weights"]]
+    bs = [np.ascontiguousarray(b, dtype=np.float32) for b in net["biases"]]
+    om = np.ascontiguousarray(net["omegas"], dtype=np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    wptr = (fp * len(ws))(*[w.ctypes.data_as(fp) for w in ws])
+    bptr = (fp * len(bs))(*[b.ctypes.data_as(fp) for b in bs])
+    s = N.gh_sdb_spec()
+    s.kind = N.GH_SDB_MLP
+    s.n_freq, s.width, s.depth = len(om), ws[0].shape[0], len(ws) - 1
+    s.precision = precision
+    s.omegas_h, s.weights_h, s.biases_h = om.ctypes.data_as(fp), wptr, bptr
+    s.a_s, s.r0, s.a_n, s.b = (float(net[k]) for k in ("a_s", "r0", "a_n", "b"))
+    s.bf16_margin = margin
+    return s, (ws, bs, om, wptr, bptr)
+
+
+def test_bf16_network_needs_a_positive_margin():
+    """A bf16 network takes its hop steps and corner signs only where they hold
+    for every value within the margin; without one they would be uncertified."""
+    net = W.mlp_net(seed=0, width=64, depth=2, n_freq=2)
+    net.update(a_s=1.0, r0=0.5, a_n=0.01, b=0.0)
+    need = ctypes.c_size_t(0)
+    for prec in (N.GH_PREC_BF16, N.GH_PREC_BF16X3):
+        for margin in (0.0, -1e-3, float("nan")):
+            s, keep = _mlp_spec(net, prec, margin)
+            assert N.lib.sdb_describe(ctypes.byref(s), None, 0, ctypes.byref(need), None, None) == N.GH_EINVAL
+        s, keep = _mlp_spec(net, prec, 1e-3)
+        assert N.lib.sdb_describe(ctypes.byref(s), None, 0, ctypes.byref(need), None, None) == N.GH_OK
+    s, keep = _mlp_spec(net, N.GH_PREC_FP32, 0.0)
+    assert N.lib.sdb_describe(ctypes.byref(s), None, 0, ctypes.byref(need), None, None) == N.GH_OK
+
+
+def test_bf16_margin_validates_before_enqueuing():
+    desc = N.gh_sdb_desc()
+    st = N.lib.gh_bf16_margin(ctypes.byref(desc), N.GH_PREC_BF16, None, 0, 2.0, None, None, ctypes.c_void_p(256), None)
+    assert st == N.GH_EINVAL and b"sdb_describe" in N.lib.gh_last_error()

@@ -57,8 +57,33 @@ def test_signature_depends_on_shape_not_values():
     a, ka = spec_of(W.csg_scene(0, 12))
     b, kb = spec_of(W.csg_scene(1, 12))
     c, kc = spec_of(W.csg_scene(0, 8))
-    assert A.signature(a, 256) == A.signature(b, 256) == "prims:3-3-3-3-0-0:n256"
+    assert A.signature(a, 256) == A.signature(b, 256) == "prims:3-3-3-3-0-0-0-0-0-0-0:n256"
     assert A.signature(a, 256) != A.signature(c, 256) and A.signature(a, 256) != A.signature(a, 512)
+
+
+def _spec_of(recs):
+    rec = np.ascontiguousarray(np.asarray(recs, dtype=np.float32).reshape(-1, N.GH_PRIM_FLOATS))
+    sp = N.gh_sdb_spec()
+    sp.kind = N.GH_SDB_PRIMS
+    sp.n_prim = rec.shape[0]
+    sp.prims_h = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    return sp, rec
+
+
+def test_signature_counts_every_record_type():
+    """One record of each of the library's types, as in the seven-primitive,
+    genus-2 and fractal scenes; an unknown type is refused."""
+    recs = np.zeros((N.GH_PRIM_TYPES, N.GH_PRIM_FLOATS), np.float32)
+    recs[:, 0] = np.arange(N.GH_PRIM_TYPES)
+    sp, keep = _spec_of(recs)
+    assert A.signature(sp, 64) == "prims:" + "-".join(["1"] * N.GH_PRIM_TYPES) + ":n64"
+    for scene in (W.primitives_scene(0), W.genus2_scene(), W.sierpinski_scene(4)):
+        sp, keep = _spec_of(scene)
+        assert A.signature(sp, 128).startswith("prims:")
+    recs[3, 0] = N.GH_PRIM_TYPES
+    sp, keep = _spec_of(recs)
+    with pytest.raises(ValueError):
+        A.signature(sp, 64)
 
 
 def test_set_tuning_validates_and_round_trips():
