@@ -11,8 +11,10 @@ per-call launches are timed too (ms_per_step_eager) and give the per-phase
 split (roofline.hop_ms, mc_ms).
 
 Prints one JSON line.  Extra objects:
-  roofline      the hop kernel against the FP32 VALU peak of the chip
-  cpu_baseline  the oracle (FP64 numpy, one thread) on the same workload
+  roofline      the hop kernel against the FP32 peak of the chip (157.3 TFLOP/s),
+                and against the issue ceiling of its unfused FP32 operations
+  cpu_baseline  the oracle (FP64 numpy) on the same workload on all host cores
+                (at most 16), with the one-thread time beside it
   neural        the network bound (width 256, depth 4, 16 frequencies) at
                 N = 512 in split bf16 on MFMA, with its own MFMA roofline
                 and the enumeration path beside it
@@ -44,15 +46,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 FP32 lanes per clock x 2.4 GHz = 39.3e12 FP32 operations/s
-# without FMA and without packed dual-FP32 (the published 157.3 TFLOP/s counts
-# an FMA as two operations and packed math as two more).
-PEAK_FP32_OPS = 256 * 64 * 2.4e9
+# MI355X published peaks (dense, no sparsity).
+PEAK_FP32 = 157.3e12        # FP32 vector: an FMA counts two FLOP, packed dual-FP32 two more
+PEAK_FP32_MFMA = 157.3e12   # FP32 on the matrix cores
+PEAK_BF16_MFMA = 2.5e15
 HBM_PEAK = 8.0e12
-PEAK_BF16_MFMA = 2.5e15   # dense, no sparsity
+# Issue ceiling of the analytic bounds' arithmetic: 256 CUs x 64 lanes x 2.4 GHz
+# = 39.3e12 FP32 operations/s, one operation per lane per clock.  Their
+# formulas can use neither the FMA (contraction is off: each operation is
+# rounded on its own) nor packed dual-FP32 (disabled on this target), so
+# this is the most they can reach; it is reported beside the published peak.
+PEAK_FP32_ISSUE = 256 * 64 * 2.4e9
 
 # FP32 operations per evaluation of each primitive type, counted from the
-# formula in include/gh.h (add, sub, mul, min, max, abs, neg, sqrt each 1):
+# formula in include/gh.h.  Counting rule: every add, sub, mul, min, max, abs,
+# neg, compare, select and square root of the formula is one operation (the
+# square root one, though the hardware takes several instructions for a
+# correctly rounded one); loads, the loop and the hop's own control are not
+# counted.  These are the FLOP of the analytic rooflines:
 # translate 3 + rotate 15 = 18 shared, then
 #   sphere  3 mul + 2 add + sqrt + sub                          = 7
 #   box     3 abs + 3 sub + 2 max + 3 max + 3 mul + 2 add + sqrt + min + add = 19
@@ -91,6 +102,13 @@ def mlp_flop_per_point(width, depth, n_freq):
     return 2 * (k1 * width + (depth - 1) * width * width + width)
 
 
+def vjp_flop_per_corner(width, depth, n_freq):
+    """Multiply-adds x 2 of the adjoint at one corner: the forward products
+    again, the weight-gradient products of every layer (the same count), and
+    the products that carry dL/dz back through the hidden layers."""
+    return 2 * mlp_flop_per_point(width, depth, n_freq) + 2 * (depth - 1) * width * width
+
+
 # Sources each profiled kernel is built from; a committed traffic figure is
 # used only while these files are unchanged.
 KERNEL_SOURCES = {
@@ -122,8 +140,28 @@ def load_traffic(kernel):
     return e["bytes_per_launch"]
 
 
+def _oracle_hop_band(args):
+    """One worker of the all-cores leg: the oracle's hop over a band of columns."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hop as ohop
+    from oracle import sdb as osdb
+    recs, n, lo, h, columns = args
+    with threadpool_limits(1):
+        cells, evals, col_evals = ohop.hop(osdb.SDB.prims(recs), n, lo, h, columns=columns)
+    return cells, evals, col_evals
+
+
 def cpu_baseline(recs, n, lo, h):
-    """The oracle as it stands: FP64 grid hopping + marching cubes, one thread."""
+    """The oracle as it stands (FP64 grid hopping + marching cubes) on the
+    host, timed twice: one thread, and all the host cores this process may
+    use (at most 16), where a pool of forked workers runs the oracle's hop on
+    bands of columns (columns are independent) and marching cubes follow on
+    the union of their cells.  Runs before anything touches the GPU (the
+    workers are forked)."""
+    import multiprocessing as mp
+
+    import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import hop as ohop
@@ -135,9 +173,27 @@ def cpu_baseline(recs, n, lo, h):
             t0 = time.perf_counter()
             ohop.gridhop(S, n, lo, h)
             times.append(time.perf_counter() - t0)
-    t = min(times)
-    return {"value": n ** 3 / t, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full workload (N={n}, all {n * n} columns), best of 2 runs, {t:.2f} s"}
+    t1 = min(times)
+    host = len(os.sched_getaffinity(0))
+    cores = max(1, min(16, host))
+    bands = np.array_split(np.arange(n * n, dtype=np.int64), cores * 4)
+    times = []
+    with mp.get_context("fork").Pool(cores) as pool:
+        for _ in range(2):
+            t0 = time.perf_counter()
+            parts = pool.map(_oracle_hop_band, [(recs, n, lo, h, b) for b in bands])
+            cells = np.sort(np.concatenate([p[0] for p in parts]))
+            with threadpool_limits(1):
+                ohop.polygonize_cells(S, n, lo, h, cells, sum(p[1] for p in parts),
+                                      np.concatenate([p[2] for p in parts]))
+            times.append(time.perf_counter() - t0)
+    tc = min(times)
+    return {"value": n ** 3 / tc, "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": f"the full workload (N={n}, all {n * n} columns), best of 2 runs, {tc:.2f} s: the hop on "
+                      f"{len(bands)} column bands over {cores} forked workers (host affinity {host} CPUs), "
+                      f"marching cubes on one",
+            "one_thread": {"value": n ** 3 / t1, "unit": "cells/s", "cores": 1,
+                           "sample": f"the full workload, best of 2 runs, {t1:.2f} s"}}
 
 
 def event_ms(stream, fn, reps):
@@ -231,8 +287,20 @@ def backward_section(dev, steps, warmup, n=256, width=256):
     fwd_ms = event_ms(stream, lambda: (poly.enqueue_hop(), poly.enqueue_mc()), steps)
     bwd()
     bwd_ms = event_ms(stream, bwd, steps)
+    # corners the loss depends on: the distinct ends of the crossing edges
+    e = mesh.vert_edge
+    axis, lower = e % 3, e // 3
+    n1 = n + 1
+    upper = lower + torch.where(axis == 0, n1 * n1, torch.where(axis == 1, n1, 1))
+    corners = int(torch.unique(torch.cat([lower, upper])).numel())
+    fpc = vjp_flop_per_corner(width, 4, 16)
+    flop = corners * fpc
     return {"workload": f"mlp_w{width}_d4_f16_seed0_n{n}_fp32", "backward_ms": bwd_ms, "forward_ms": fwd_ms,
-            "n_vert": int(V.shape[0]), "params": P, "grad_norm": float(grad.norm())}
+            "n_vert": int(V.shape[0]), "params": P, "grad_norm": float(grad.norm()),
+            "roofline": {"bound": "mfma", "kernel": "k_mlp_vjp (whole gh_backward call timed)",
+                         "achieved": flop / (bwd_ms * 1e-3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                         "unit": "TFLOP/s", "frac": flop / (bwd_ms * 1e-3) / PEAK_FP32_MFMA, "traffic": None,
+                         "corners": corners, "flop_per_corner": fpc, "per_launch_flop": flop}}
 
 
 def batch_section(dev, steps, warmup, precision="bf16x3", tune=True):
@@ -415,6 +483,12 @@ def main():
               f"independent: several GPUs would each take a band of columns)", file=sys.stderr)
         sys.exit(2)
 
+    import workloads as W
+    n, lo, h = W.grid(args.n)
+    recs = W.csg_scene(args.seed)
+    # the oracle's legs fork worker processes: before anything touches the GPU
+    cpu = None if (args.no_cpu_baseline or args.copy_calibration) else cpu_baseline(recs, n, lo, h)
+
     import torch
 
     dev = torch.device("cuda:0")
@@ -427,11 +501,8 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_calibration, "launches": 5}), flush=True)
         return
 
-    import workloads as W
     from paper_2111_05778_amd.polygonize import Bound, Polygonizer
 
-    n, lo, h = W.grid(args.n)
-    recs = W.csg_scene(args.seed)
     poly = Polygonizer(Bound.prims(recs, dev), n, lo, h, device=dev, keep_cells=False)
     ref = poly.run()                       # sizes the buffers; reference counters
     c0 = dict(ref.counters)
@@ -504,9 +575,10 @@ def main():
     flops = c0["n_hop_evals"] * ops_per_eval(recs)
     achieved = flops / hop_s
     traffic = load_traffic("k_hop")
-    roofline = {"bound": "alu", "kernel": "k_hop", "achieved": achieved / 1e12, "peak": PEAK_FP32_OPS / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_OPS, "traffic": traffic,
-                "per_launch_ops": flops, "ops_per_eval": ops_per_eval(recs), "hop_ms": hop_s * 1e3,
+    roofline = {"bound": "alu", "kernel": "k_hop", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
+                "peak_issue": PEAK_FP32_ISSUE / 1e12, "frac_issue": achieved / PEAK_FP32_ISSUE,
+                "per_launch_flop": flops, "flop_per_eval": ops_per_eval(recs), "hop_ms": hop_s * 1e3,
                 "mc_ms": 1e3 * sum(t_mc) / len(t_mc)}
 
     out = {
@@ -522,7 +594,7 @@ def main():
         "dense": dense,
         "speedup_vs_dense": (dense["ms_per_step"] / ms_per_step) if dense else None,
         "roofline": roofline,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(recs, n, lo, h),
+        "cpu_baseline": cpu,
     }
     sw = max(1, args.warmup)
     if "neural" in sections:

@@ -85,7 +85,8 @@ def test_bf16_values_close_to_fp64(gh, width):
     ref = osdb.neural_f64(net, pts.astype(np.float64))
     errs = {}
     for prec in ("bf16", "bf16x3"):
-        f = P.Bound.mlp(net, prec).eval(torch.from_numpy(pts).cuda()).cpu().numpy().astype(np.float64)
+        # point values take no decision, so the margin is not used here
+        f = P.Bound.mlp(net, prec, margin=1.0).eval(torch.from_numpy(pts).cuda()).cpu().numpy().astype(np.float64)
         errs[prec] = np.abs(f - ref).max()
     m3 = P.bf16_margin(net, W.probe_points(seed=3, n=65536), "bf16x3")
     print(f"width {width}: max |f - f64| bf16 {errs['bf16']:.3e}, bf16x3 {errs['bf16x3']:.3e}; "
