@@ -229,6 +229,27 @@ gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size
                 int32_t* tris, int64_t tri_cap, int64_t* cells, uint8_t* cases, int64_t cell_cap,
                 gh_counters* ctr, void* stream);
 
+/* Bytes of the fixed workspace of gh_polygonize_noalloc (128 MiB per device). */
+#define GH_NOALLOC_WORKSPACE_BYTES ((size_t)128 << 20)
+
+/* gh_hop followed by gh_mc with no workspace argument and no allocation, for
+ * callers that cannot allocate device memory (code under hipGraph capture,
+ * serving loops, hosts that forbid hipMalloc).  The workspace is a
+ * GH_NOALLOC_WORKSPACE_BYTES array in the library's device code, one per
+ * device, taken on the current device (the stream must belong to it) and
+ * held until the process ends; this call allocates and frees nothing.
+ * Outputs, capacities and counters are those of gh_mc; corner_cap <= 0
+ * selects the default of gh_workspace_size or the largest capacity that
+ * fits, whichever is smaller.  GH_ECAPACITY (synchronous, nothing enqueued)
+ * when the grid with that corner capacity needs a larger workspace: the
+ * array holds any n <= 512 with the default capacity up to n = 256 and about
+ * 2.5e6 corners at n = 512.  Every call on one device shares the array, and
+ * it keeps the last call's contents: calls that overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller. */
+gh_status gh_polygonize_noalloc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, int64_t corner_cap, float* verts,
+                                int64_t* vert_edge, float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap,
+                                int64_t* cells, uint8_t* cases, int64_t cell_cap, gh_counters* ctr, void* stream);
+
 /* Enumeration baseline (Section 2): evaluates f at every lattice point,
  * keeps only the signs in `signs` (device, gh_dense_signs_size bytes,
  * layout [w][a*(n+1) + b], bit c%32 of word w = c/32 set when

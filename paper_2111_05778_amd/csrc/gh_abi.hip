@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -253,6 +254,51 @@ Tuning current_tuning() {
 }
 }  // namespace gh
 
+namespace {
+
+// ------------------------------------------------- fixed workspace (no allocation)
+// gh_polygonize_noalloc's workspace: one array per device, loaded with the
+// code object and held until the process ends.  In host code `scratch` names
+// a host-side stand-in, never the device memory: kernels and copies get the
+// address that hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) static unsigned char scratch[GH_NOALLOC_WORKSPACE_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device, set on first use
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+gh_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(GH_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_status(e, "hipGetSymbolAddress(scratch)");
+    if (!p || ((uintptr_t)p & 255)) return fail(GH_EHIP, "fixed workspace address %p unusable", p);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GH_OK;
+}
+
+// Largest corner capacity whose workspace fits in `bytes` on this grid (0 if none).
+int64_t largest_cap(int n, size_t bytes) {
+  int64_t lo = 0, hi = ((int64_t)1 << 31) - 1;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (gh::workspace_layout(n, mid, nullptr, nullptr) <= bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* gh_last_error(void) { return g_last_error.c_str(); }
@@ -458,6 +504,41 @@ gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size
     return fail(GH_EUNSUPPORTED, "capacities must stay below 2^31");
   if (!cells && !cases) cell_cap = 0;
   hipStream_t s = (hipStream_t)stream;
+  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearMc, s), "clear")) != GH_OK) return st;
+  return hip_status(gh::launch_mc(d, g, w, verts, vert_edge, vert_t, vert_cap, tris, tri_cap, cells, cases, cell_cap,
+                                  ctr, s),
+                    "mc");
+}
+
+gh_status gh_polygonize_noalloc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, int64_t corner_cap, float* verts,
+                                int64_t* vert_edge, float* vert_t, int64_t vert_cap, int32_t* tris, int64_t tri_cap,
+                                int64_t* cells, uint8_t* cases, int64_t cell_cap, gh_counters* ctr, void* stream) {
+  gh::DevSdb d;
+  gh::Grid g;
+  gh::Workspace w;
+  gh_status st;
+  if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
+  if ((st = read_grid(grid_h, &g)) != GH_OK) return st;
+  if (!ctr) return fail(GH_EINVAL, "counters are NULL");
+  if (vert_cap < 0 || tri_cap < 0 || cell_cap < 0) return fail(GH_EINVAL, "negative capacity");
+  if ((vert_cap > 0 && !verts) || (tri_cap > 0 && !tris)) return fail(GH_EINVAL, "output buffer is NULL");
+  if (tri_cap >= ((int64_t)1 << 31) || vert_cap >= ((int64_t)1 << 31))
+    return fail(GH_EUNSUPPORTED, "capacities must stay below 2^31");
+  if (!cells && !cases) cell_cap = 0;
+  const size_t bytes = GH_NOALLOC_WORKSPACE_BYTES;
+  if (corner_cap <= 0) corner_cap = std::min(default_cap(g.n), largest_cap(g.n, bytes));
+  if (corner_cap <= 0 || corner_cap >= ((int64_t)1 << 31) ||
+      gh::workspace_layout(g.n, corner_cap, nullptr, nullptr) > bytes)
+    return fail(GH_ECAPACITY,
+                "the fixed workspace of %zu bytes holds n=%d with at most %lld corners (corner_cap %lld asked)",
+                bytes, g.n, (long long)largest_cap(g.n, bytes), (long long)corner_cap);
+  void* ws = nullptr;
+  if ((st = scratch_of_current_device(&ws)) != GH_OK) return st;
+  if ((st = carve(g, ws, bytes, corner_cap, &w)) != GH_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int lanes = gh::current_tuning().hop_lanes_per_ray;
+  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearAll, s), "clear")) != GH_OK) return st;
+  if ((st = hip_status(gh::launch_hop(d, g, w, ctr, lanes, s), "hop")) != GH_OK) return st;
   if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearMc, s), "clear")) != GH_OK) return st;
   return hip_status(gh::launch_mc(d, g, w, verts, vert_edge, vert_t, vert_cap, tris, tri_cap, cells, cases, cell_cap,
                                   ctr, s),

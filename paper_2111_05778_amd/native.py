@@ -22,8 +22,9 @@ GH_PREC_FP32, GH_PREC_BF16, GH_PREC_BF16X3 = 0, 1, 2
 GH_ACT_SOFTPLUS, GH_ACT_RELU = 0, 1
 GH_PRIM_FLOATS = 16
 GH_PRIM_TYPES = 11
+GH_NOALLOC_WORKSPACE_BYTES = 128 << 20
 
-EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_hop_traced", "gh_cont_workspace_size", "gh_cont", "gh_mc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
+EXPORTS = ["sdb_describe", "gh_workspace_size", "gh_hop", "gh_hop_traced", "gh_cont_workspace_size", "gh_cont", "gh_mc", "gh_polygonize_noalloc", "gh_dense", "gh_dense_signs_size", "gh_candidates",
            "gh_eval_points", "gh_bf16_margin", "gh_set_tuning", "gh_get_tuning", "gh_param_count", "gh_backward_workspace_size",
            "gh_backward", "gh_batch_buffer_size", "gh_batch_create", "gh_batch_run", "gh_batch_capture",
            "gh_batch_replay", "gh_batch_item_count", "gh_batch_destroy", "gh_last_error"]
@@ -86,6 +87,8 @@ lib.gh_cont_workspace_size.argtypes = [_P(gh_grid), _i64, _P(_sz)]
 lib.gh_cont.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _sz, _i64, _vp, _i64, _vp, _P(_i64), _vp]
 lib.gh_mc.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64,
                       _vp, _vp]
+lib.gh_polygonize_noalloc.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp,
+                                      _i64, _vp, _vp]
 lib.gh_dense.argtypes = [_P(gh_sdb_desc), _P(gh_grid), _vp, _sz, _i64, _vp, _vp, _vp]
 lib.gh_dense_signs_size.argtypes = [_P(gh_grid), _P(_sz)]
 lib.gh_candidates.argtypes = [_P(gh_grid), _vp, _sz, _i64, _vp, _i64, _vp, _vp]
@@ -189,6 +192,13 @@ def gh_mc(desc, grid, ws, corner_cap, verts, vert_edge, vert_t, vert_cap, tris, 
     return lib.gh_mc(ctypes.byref(desc), ctypes.byref(grid), ptr(ws), ws.numel() * ws.element_size(),
                      int(corner_cap), ptr(verts), ptr(vert_edge), ptr(vert_t), int(vert_cap), ptr(tris),
                      int(tri_cap), ptr(cells), ptr(cases), int(cell_cap), ptr(ctr), stream_handle(stream))
+
+
+def gh_polygonize_noalloc(desc, grid, corner_cap, verts, vert_edge, vert_t, vert_cap, tris, tri_cap, cells, cases,
+                          cell_cap, ctr, stream=None):
+    return lib.gh_polygonize_noalloc(ctypes.byref(desc), ctypes.byref(grid), int(corner_cap), ptr(verts),
+                                     ptr(vert_edge), ptr(vert_t), int(vert_cap), ptr(tris), int(tri_cap), ptr(cells),
+                                     ptr(cases), int(cell_cap), ptr(ctr), stream_handle(stream))
 
 
 def gh_candidates(grid, ws, corner_cap, out, cap, ctr, stream=None):
