@@ -11,10 +11,12 @@ several times with eager work and synchronisations between the replays, and
 every replay is checked against the eager result.
 """
 import numpy as np
+import parity_util as U
 import pytest
 
 import workloads as W
 from oracle import hop as ohop
+from oracle import mesh as omesh
 from oracle import sdb as osdb
 
 pytestmark = pytest.mark.gpu
@@ -167,6 +169,26 @@ def test_full_batch_64_shapes(gh):
         _assert_same(torch, a, b, f"shape {s} {scenes[s]['kind']} n={grids[s][0]}")
     tot = sum(a["ctr"]["n_tri"] for a in res)
     print(f"64 shapes, {batch.item_count()} items, {tot} triangles", flush=True)
+    # the network shapes of the batch at N = 64 (widths 64, 128, 256) against
+    # the FP64 oracle: cells under the exclusion rule, mesh within 0.5 h
+    for s in (1, 9, 57):
+        sc = scenes[s]
+        assert sc["kind"] == "mlp" and sc["n"] == 64
+        net = W.neural_scene(sc["seed"], sc["width"])
+        n, lo, h = grids[s]
+        ref = ohop.gridhop(osdb.SDB.neural(net), n, lo, h).mesh
+        m = res[s]
+        cells, cases = m["cells"].cpu().numpy(), m["cases"].cpu().numpy()
+        f64 = lambda X: osdb.neural_f64(net, X)  # noqa: E731
+        # bf16x3 takes the FP32 signs (certified), so the FP32 error sets the threshold
+        thr = U.fp32_threshold(P, net, n, lo, h, np.union1d(cells, ref.cells))
+        U.assert_cells_match_excluding_near_zero(cells, cases, ref.cells, ref.cases, f64, n, lo, h, thr,
+                                                 f"batch shape {s} width {sc['width']}")
+        V = m["verts"].cpu().numpy().astype(np.float64)
+        T = m["tris"].cpu().numpy().astype(np.int64)
+        hd = omesh.hausdorff(V, T, ref.positions(), ref.tri_vertex_index())
+        print(f"batch shape {s}: Hausdorff to FP64 {hd / float(h):.4f} h", flush=True)
+        assert hd <= 0.5 * float(h)
 
 
 def test_batch_rejects_mixed_network_precisions(gh):
