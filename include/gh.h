@@ -223,7 +223,8 @@ gh_status gh_cont(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, si
  *   cases     [cell_cap] uint8 inside-corner mask of those cells, corner
  *             dx + 2 dy + 4 dz inside when f < 0 (may be NULL)
  * Sets n_corner, n_cells, n_vert, n_tri; GH_FLAG_CAPACITY if any capacity
- * (including the workspace corner_cap) was too small. */
+ * (including the workspace corner_cap) was too small.  Capacities must stay
+ * below 2^28 vertices and 2^31 triangles (GH_EUNSUPPORTED). */
 gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size_t ws_bytes,
                 int64_t corner_cap, float* verts, int64_t* vert_edge, float* vert_t, int64_t vert_cap,
                 int32_t* tris, int64_t tri_cap, int64_t* cells, uint8_t* cases, int64_t cell_cap,

@@ -500,8 +500,8 @@ gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size
   if (!ctr) return fail(GH_EINVAL, "counters are NULL");
   if (vert_cap < 0 || tri_cap < 0 || cell_cap < 0) return fail(GH_EINVAL, "negative capacity");
   if ((vert_cap > 0 && !verts) || (tri_cap > 0 && !tris)) return fail(GH_EINVAL, "output buffer is NULL");
-  if (tri_cap >= ((int64_t)1 << 31) || vert_cap >= ((int64_t)1 << 31))
-    return fail(GH_EUNSUPPORTED, "capacities must stay below 2^31");
+  if (tri_cap >= ((int64_t)1 << 31) || vert_cap >= gh::kMaxVerts)
+    return fail(GH_EUNSUPPORTED, "capacities must stay below 2^31 triangles and 2^28 vertices");
   if (!cells && !cases) cell_cap = 0;
   hipStream_t s = (hipStream_t)stream;
   if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearMc, s), "clear")) != GH_OK) return st;
@@ -522,8 +522,8 @@ gh_status gh_polygonize_noalloc(const gh_sdb_desc* desc_h, const gh_grid* grid_h
   if (!ctr) return fail(GH_EINVAL, "counters are NULL");
   if (vert_cap < 0 || tri_cap < 0 || cell_cap < 0) return fail(GH_EINVAL, "negative capacity");
   if ((vert_cap > 0 && !verts) || (tri_cap > 0 && !tris)) return fail(GH_EINVAL, "output buffer is NULL");
-  if (tri_cap >= ((int64_t)1 << 31) || vert_cap >= ((int64_t)1 << 31))
-    return fail(GH_EUNSUPPORTED, "capacities must stay below 2^31");
+  if (tri_cap >= ((int64_t)1 << 31) || vert_cap >= gh::kMaxVerts)
+    return fail(GH_EUNSUPPORTED, "capacities must stay below 2^31 triangles and 2^28 vertices");
   if (!cells && !cases) cell_cap = 0;
   const size_t bytes = GH_NOALLOC_WORKSPACE_BYTES;
   if (corner_cap <= 0) corner_cap = std::min(default_cap(g.n), largest_cap(g.n, bytes));
@@ -603,6 +603,8 @@ gh_status gh_batch_validate_item(const gh_batch_item* it, int index, gh::DevSdb*
   if (it->vert_cap < 0 || it->tri_cap < 0 || it->cell_cap < 0) return fail(GH_EINVAL, "negative capacity");
   if ((it->vert_cap > 0 && !it->verts) || (it->tri_cap > 0 && !it->tris))
     return fail(GH_EINVAL, "batch item %d output buffer is NULL", index);
+  if (it->tri_cap >= ((int64_t)1 << 31) || it->vert_cap >= gh::kMaxVerts)
+    return fail(GH_EUNSUPPORTED, "batch item %d: capacities must stay below 2^31 triangles and 2^28 vertices", index);
   return GH_OK;
 }
 

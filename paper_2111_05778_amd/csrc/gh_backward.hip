@@ -26,9 +26,9 @@ __device__ __forceinline__ float corner_cotangent(const Workspace& ws, const Gri
   const int L = ws.cl[ci], k = ws.ck[ci];
   const int a = L / n1, b = L - a * n1;
   const float fc = ws.cf[ci];
-  const int64_t info = ws.cinfo[ci];
-  const unsigned msk = (unsigned)(info & 7);
-  const int64_t vb = info >> 3;
+  const uint32_t info = ws.cinfo[ci];
+  const unsigned msk = cinfo_mask(info);
+  const int64_t vb = cinfo_vbase(info);
   float s = 0.f;
   // c is the lower end a of its own crossing edges: dt/df_a = -f_b/(f_a - f_b)^2
   if (msk & 1u) {
@@ -49,23 +49,23 @@ __device__ __forceinline__ float corner_cotangent(const Workspace& ws, const Gri
   // c is the upper end b of the edges from (a-1, b, k), (a, b-1, k), (a, b, k-1)
   if (a > 0) {
     const int64_t c2 = corner_index(ws, nl, (size_t)L - n1, k);
-    if (c2 >= 0 && (ws.cinfo[c2] & 1)) {
+    if (c2 >= 0 && (cinfo_mask(ws.cinfo[c2]) & 1u)) {
       const float fa = ws.cf[c2], d = fa - fc;
-      s += dldv[3 * (ws.cinfo[c2] >> 3) + 0] * g.h * (fa / (d * d));
+      s += dldv[3 * cinfo_vbase(ws.cinfo[c2]) + 0] * g.h * (fa / (d * d));
     }
   }
   if (b > 0) {
     const int64_t c2 = corner_index(ws, nl, (size_t)L - 1, k);
-    if (c2 >= 0 && (ws.cinfo[c2] & 2)) {
-      const int64_t inf = ws.cinfo[c2];
+    if (c2 >= 0 && (cinfo_mask(ws.cinfo[c2]) & 2u)) {
+      const uint32_t inf = ws.cinfo[c2];
       const float fa = ws.cf[c2], d = fa - fc;
-      s += dldv[3 * ((inf >> 3) + (inf & 1)) + 1] * g.h * (fa / (d * d));
+      s += dldv[3 * (cinfo_vbase(inf) + (cinfo_mask(inf) & 1u)) + 1] * g.h * (fa / (d * d));
     }
   }
-  if (ci > 0 && ws.cl[ci - 1] == L && ws.ck[ci - 1] == k - 1 && (ws.cinfo[ci - 1] & 4)) {
-    const int64_t inf = ws.cinfo[ci - 1];
+  if (ci > 0 && ws.cl[ci - 1] == L && ws.ck[ci - 1] == k - 1 && (cinfo_mask(ws.cinfo[ci - 1]) & 4u)) {
+    const uint32_t inf = ws.cinfo[ci - 1];
     const float fa = ws.cf[ci - 1], d = fa - fc;
-    s += dldv[3 * ((inf >> 3) + __popc((unsigned)(inf & 3))) + 2] * g.h * (fa / (d * d));
+    s += dldv[3 * (cinfo_vbase(inf) + __popc(cinfo_mask(inf) & 3u)) + 2] * g.h * (fa / (d * d));
   }
   (void)m;
   return s;

@@ -4,9 +4,10 @@
 // only the non-zero 32-bit words and a 64-bit mask saying which words exist),
 // so nothing has to be cleared between runs.  Corner points are listed by
 // lattice column (a, b), then k; per lattice column a word bitmap over k with
-// the list index of each word's first corner gives any corner's list index
-// in O(1).  Each corner carries its bound value and the index of its first
-// welded vertex.
+// the list index of each word's first corner (one 8-byte record per word)
+// gives any corner's list index in O(1).  Each corner carries its bound
+// value and one 32-bit word with its sign, the crossing edges it owns and
+// the index of its first welded vertex.
 #pragma once
 
 #include <stddef.h>
@@ -23,12 +24,12 @@ struct Workspace {
   uint32_t* colbits;   // [W][n*n] candidate bitmap words, word-major (W = ceil(n/32))
   uint64_t* lmask;     // [(n+1)^2] bit w set when corner word w of lattice column L exists (w < 64)
   uint32_t* lmhi;      // [(n+1)^2] bit 0: corner word 64 exists (n = 2048 only)
-  uint32_t* lbits;     // [W1][(n+1)^2] corner words (k bits), written where non-zero (W1 = ceil((n+1)/32))
-  int32_t* lwst;       // [W1][(n+1)^2] index of the first corner of that word in the corner list
+  uint64_t* lrec;      // [W1][(n+1)^2] corner word w of a lattice column (k bits, low half) and the list
+                       // index of its first corner (high half), written where non-zero (W1 = ceil((n+1)/32))
   int32_t* ck;         // [cap] k of each corner (list ordered by lattice column, then k)
   int32_t* cl;         // [cap] lattice column a*(n+1) + b of each corner
   float* cf;           // [cap] bound value at the corner
-  int64_t* cinfo;      // [cap] (first vertex index << 3) | crossing mask (x=1, y=2, z=4)
+  uint32_t* cinfo;     // [cap] (first vertex index << 4) | (crossing mask << 1) | (f < 0); mask x=1, y=2, z=4
   int64_t* cand;       // [cap] candidate cell ids in ascending order (never more than the corners)
   int64_t* nlist;      // [2] corners, candidates in the lists
   uint32_t* park;      // [n*n][6] rays handed to the long-ray pass: column, k, word index, word, mask lo/hi
@@ -60,12 +61,11 @@ inline size_t workspace_layout(int n, int64_t cap, void* base, Workspace* ws) {
   const size_t o_bits = take(words * n2 * 4);
   const size_t o_lmask = take(nl * 8);
   const size_t o_lmhi = take(nl * 4);
-  const size_t o_lbits = take(words1 * nl * 4);
-  const size_t o_lwst = take(words1 * nl * 4);
+  const size_t o_lrec = take(words1 * nl * 8);
   const size_t o_ck = take((size_t)cap * 4);
   const size_t o_cl = take((size_t)cap * 4);
   const size_t o_cf = take((size_t)cap * 4);
-  const size_t o_ci = take((size_t)cap * 8);
+  const size_t o_ci = take((size_t)cap * 4);
   const size_t o_cand = take((size_t)cap * 8);
   const size_t o_nlist = take(2 * 8);
   const size_t o_park = take(n2 * 6 * 4);
@@ -78,12 +78,11 @@ inline size_t workspace_layout(int n, int64_t cap, void* base, Workspace* ws) {
     ws->colbits = (uint32_t*)(b + o_bits);
     ws->lmask = (uint64_t*)(b + o_lmask);
     ws->lmhi = (uint32_t*)(b + o_lmhi);
-    ws->lbits = (uint32_t*)(b + o_lbits);
-    ws->lwst = (int32_t*)(b + o_lwst);
+    ws->lrec = (uint64_t*)(b + o_lrec);
     ws->ck = (int32_t*)(b + o_ck);
     ws->cl = (int32_t*)(b + o_cl);
     ws->cf = (float*)(b + o_cf);
-    ws->cinfo = (int64_t*)(b + o_ci);
+    ws->cinfo = (uint32_t*)(b + o_ci);
     ws->cand = (int64_t*)(b + o_cand);
     ws->nlist = (int64_t*)(b + o_nlist);
     ws->park = (uint32_t*)(b + o_park);
@@ -107,22 +106,43 @@ __host__ __device__ inline uint64_t* scan_cands(const Workspace& w) {
 }
 inline size_t scan_words(const Workspace& w) { return (size_t)(w.tiles_lat + 2 * w.tiles_cap + w.tiles_col); }
 
-// List index of corner (L, k), or -1 when (L, k) is not a corner.  All four
-// loads are unconditional and issued together (one memory round trip); a
-// word that was not written this run is read but never used.  k <= n, so
-// the word index stays inside the W1 rows; L < (n+1)^2.
+// List index of corner (L, k), or -1 when (L, k) is not a corner.  The mask
+// and record loads are unconditional and issued together (one memory round
+// trip); a record that was not written this run is read but never used.
+// k <= n, so the word index stays inside the W1 rows; L < (n+1)^2.  Word 64
+// exists only for n >= 2016, where its presence bit lives in lmhi.
 __device__ __forceinline__ int64_t corner_index(const Workspace& ws, size_t nl, size_t L, int k) {
   const int w = k >> 5;
-  const size_t o = (size_t)w * nl + L;
   const uint64_t lm = ws.lmask[L];
-  const uint32_t lh = ws.lmhi[L];
-  const uint32_t word = ws.lbits[o];
-  const int32_t start = ws.lwst[o];
-  const bool present = w < 64 ? ((lm >> (w & 63)) & 1) : (lh & 1);
+  const uint64_t rec = ws.lrec[(size_t)w * nl + L];
+  bool present;
+  if (ws.words1 > 64) present = w < 64 ? ((lm >> (w & 63)) & 1) : (ws.lmhi[L] & 1);
+  else present = (lm >> w) & 1;
+  const uint32_t word = (uint32_t)rec;
   const uint32_t bit = 1u << (k & 31);
-  const int64_t idx = (int64_t)start + __popc(word & (bit - 1u));
+  const int64_t idx = (int64_t)(int32_t)(rec >> 32) + __popc(word & (bit - 1u));
   return present && (word & bit) ? idx : -1;
 }
+
+// List index of a lattice point known to be a corner (a corner of a
+// candidate cell): one record load, no presence test.  *ok is cleared when
+// the record's word lacks the point (inconsistent workspace contents).
+__device__ __forceinline__ int64_t corner_index_known(const Workspace& ws, size_t nl, size_t L, int k, bool* ok) {
+  const uint64_t rec = ws.lrec[(size_t)(k >> 5) * nl + L];
+  const uint32_t word = (uint32_t)rec;
+  const uint32_t bit = 1u << (k & 31);
+  *ok = *ok && (word & bit);
+  return (int64_t)(int32_t)(rec >> 32) + __popc(word & (bit - 1u));
+}
+
+// The 32-bit corner word: sign, owned crossing edges, first vertex index.
+constexpr int64_t kMaxVerts = (int64_t)1 << 28;  // vertex indices fit in 28 bits (vertex capacities stay below)
+__host__ __device__ inline uint32_t cinfo_pack(int64_t vbase, unsigned mask, bool neg) {
+  return ((uint32_t)vbase << 4) | (mask << 1) | (neg ? 1u : 0u);
+}
+__host__ __device__ inline int64_t cinfo_vbase(uint32_t c) { return (int64_t)(c >> 4); }
+__host__ __device__ inline unsigned cinfo_mask(uint32_t c) { return (c >> 1) & 7u; }
+__host__ __device__ inline bool cinfo_neg(uint32_t c) { return c & 1u; }
 
 enum { kTicketCorners = 0, kTicketVerts = 1, kTicketTris = 2, kTicketCands = 3, kTicketRays = 4, kTicketPark = 5 };
 

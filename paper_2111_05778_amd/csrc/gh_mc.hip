@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     ncand += __popc(ow);
     if (!cw) return;
     if (w < 64) lm |= 1ull << w; else hi = 1u;
-    ws.lbits[(size_t)w * nl + L] = cw;
+    ws.lrec[(size_t)w * nl + L] = cw;  // the word now, its first index in the write pass
     ncorner += __popc(cw);
   });
   const ScanOut so = block_scan_lookback((ncand << 31) | ncorner, scan_corners(ws), tile, &ctr->flags);
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     o = i + off;
   };
   auto put = [&](int w, uint32_t cw, uint32_t ow) {
-    if (cw) ws.lwst[(size_t)w * nl + L] = (int32_t)o;
+    if (cw) ws.lrec[(size_t)w * nl + L] = ((uint64_t)(uint32_t)o << 32) | cw;
     if (stage_c) emit_word(s_ck, s_cl, (int64_t)cbase, w, cw);
     else emit_word(ws.ck, ws.cl, 0, w, cw);
     for (uint32_t bb = ow; bb; bb &= bb - 1) {
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
       wg[g] = w;
       // unconditional loads at clamped in-bounds addresses, masked after
       const int wl = w >= 0 && w < words1 ? w : 0, wc = w >= 0 && w < words ? w : 0;
-      const uint32_t lw = ws.lbits[(size_t)wl * nl + Lq];
+      const uint32_t lw = (uint32_t)ws.lrec[(size_t)wl * nl + Lq];
       const uint32_t cwd = ws.colbits[(size_t)wc * ncol + own_col];
       cw[g] = fits && w >= 0 && ((lm >> w) & 1) ? lw : 0u;
       ow[g] = fits && w >= 0 && ((own >> w) & 1) ? cwd : 0u;
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     for (int g = 0; g < kWalk; ++g)
       if (wg[g] >= 0) put(wg[g], cw[g], ow[g]);
   }
-  if (fits && hi) put(64, ws.lbits[(size_t)64 * nl + L], 0u);
+  if (fits && hi) put(64, (uint32_t)ws.lrec[(size_t)64 * nl + L], 0u);
   __syncthreads();
   if (stage_c)
     for (int64_t i = threadIdx.x; i < (int64_t)tile_c; i += kBlock) {
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
     for (int r = 0; r < kItems; ++r) {
       const int64_t ci = c0 + r;
       if (ci >= m) break;
-      ws.cinfo[ci] = (v << 3) | (int64_t)msk[r];
+      ws.cinfo[ci] = cinfo_pack(v, msk[r], fs[r] < 0.f);
       if (msk[r] && (stage || v + __popc(msk[r]) <= vert_cap)) {
         const int L = Ls[r], k = ks[r];
         const int a = L / n1, b = L - a * n1;
@@ -469,8 +469,9 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
 // ----------------------------------------------------------------- triangles
 // One thread per candidate cell (i, j, k): list indices of its corners in
 // the four lattice columns (i+dx, j+dy) (the corner at k+1 follows the one
-// at k in the list), the case byte, and the table's triangles; each triangle
-// vertex is the welded vertex of the cell edge, found at its lower corner.
+// at k in the list), their corner words (sign, owned crossing edges, first
+// vertex), the case byte, and the table's triangles; each triangle vertex is
+// the welded vertex of the cell edge, found in the word of its lower corner.
 // Lower corner of each of the 12 cell edges, 3 bits per edge.
 constexpr uint64_t edge_lower_pack() {
   uint64_t v = 0;
@@ -480,9 +481,13 @@ constexpr uint64_t edge_lower_pack() {
 constexpr uint64_t kEdgeLower = edge_lower_pack();
 
 struct CellCorners {
-  int64_t p[4];  // list index of corner (i+dx, j+dy, k), slot dx + 2 dy
+  uint32_t info[8];  // corner word of corner dx + 2 dy + 4 dz
 };
 
+// The corners of a candidate are corners by construction, so their list
+// indices need only the word records (one load each, issued together), then
+// the eight corner words (a second round trip).  Returns false when a record
+// lacks its corner (inconsistent workspace contents).
 __device__ __forceinline__ bool cell_corners(const Workspace& ws, int n, size_t nl, int64_t cell, CellCorners& C,
                                              unsigned& cs) {
   const int n1 = n + 1;
@@ -490,21 +495,22 @@ __device__ __forceinline__ bool cell_corners(const Workspace& ws, int n, size_t 
   const int k = (int)(cell - col * n);
   const int i = (int)(col / n), j = (int)(col - (int64_t)i * n);
   const size_t L = (size_t)i * n1 + j;
-  // Unconditional loads (a missing corner reads entry 0 and is ignored):
-  // the four index lookups, then the eight values, each one round trip.
-  C.p[0] = corner_index(ws, nl, L, k);
-  C.p[1] = corner_index(ws, nl, L + n1, k);
-  C.p[2] = corner_index(ws, nl, L + 1, k);
-  C.p[3] = corner_index(ws, nl, L + n1 + 1, k);
   bool ok = true;
+  int64_t p[4];
+  p[0] = corner_index_known(ws, nl, L, k, &ok);
+  p[1] = corner_index_known(ws, nl, L + n1, k, &ok);
+  p[2] = corner_index_known(ws, nl, L + 1, k, &ok);
+  p[3] = corner_index_known(ws, nl, L + n1 + 1, k, &ok);
   cs = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    ok = ok && C.p[q] >= 0;
-    const int64_t p0 = C.p[q] >= 0 ? C.p[q] : 0;
+    // clamped into the list, so that even a corrupt record reads in bounds
+    const int64_t p0 = p[q] < 0 ? 0 : (p[q] < ws.cap ? p[q] : ws.cap - 1);
     const int64_t p1 = p0 + 1 < ws.cap ? p0 + 1 : p0;
-    cs |= (unsigned)(ws.cf[p0] < 0.f) << q;
-    cs |= (unsigned)(ws.cf[p1] < 0.f) << (q + 4);
+    C.info[q] = ws.cinfo[p0];
+    C.info[q + 4] = ws.cinfo[p1];
+    cs |= (C.info[q] & 1u) << q;
+    cs |= (C.info[q + 4] & 1u) << (q + 4);
   }
   return ok;
 }
@@ -573,56 +579,33 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
     const int64_t tile_t = (int64_t)(so.total & 0x7fffffffull) - tbase;
     const int64_t tile_c = (int64_t)(so.total >> 31) - cbase;
     const bool stage = tile_t <= kStageT;  // the cells always fit: at most one per candidate
-    // The vertex records of the lower corners of each item's crossing edges
-    // (corner 7 is no edge's lower corner), loaded for a batch of items at
-    // once and unconditionally (a record an item does not need reads entry
-    // 0), so the batch costs one memory round trip.
-    constexpr int kB = kItems < 4 ? kItems : 4;
 #pragma unroll
-    for (int r0 = 0; r0 < kItems; r0 += kB) {
-      int64_t info[kB][7];
+    for (int r = 0; r < kItems; ++r) {
+      if (!nt[r]) continue;
+      if (verts_ok) {
+        s_cell[c - cbase] = cell[r];
+        s_case[c - cbase] = (uint8_t)cs[r];
+        if (stage || t0 + (int64_t)nt[r] <= tri_cap) {
+          const McCase mcc = s_mc[cs[r]];
 #pragma unroll
-      for (int rb = 0; rb < kB; ++rb) {
-        const int r = r0 + rb;
-        const unsigned edges = s_mc[cs[r]].edges;
-        unsigned need = 0;
+          for (unsigned tq = 0; tq < 5; ++tq) {
+            if (tq >= nt[r]) break;
 #pragma unroll
-        for (int e = 0; e < 12; ++e)
-          if ((edges >> e) & 1) need |= 1u << mc_edge_lower(e);
-        if (!nt[r] || !verts_ok) need = 0;
+            for (int v = 0; v < 3; ++v) {
+              const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
+              const int lc = (int)((kEdgeLower >> (3 * e)) & 7), axis = e >> 2;
+              uint32_t in = C[r].info[0];
 #pragma unroll
-        for (int lc = 0; lc < 7; ++lc)
-          info[rb][lc] = ws.cinfo[(need >> lc) & 1 ? C[r].p[lc & 3] + (lc >> 2) : 0];
-      }
-#pragma unroll
-      for (int rb = 0; rb < kB; ++rb) {
-        const int r = r0 + rb;
-        if (!nt[r]) continue;
-        if (verts_ok) {
-          s_cell[c - cbase] = cell[r];
-          s_case[c - cbase] = (uint8_t)cs[r];
-          if (stage || t0 + (int64_t)nt[r] <= tri_cap) {
-            const McCase mcc = s_mc[cs[r]];
-#pragma unroll
-            for (unsigned tq = 0; tq < 5; ++tq) {
-              if (tq >= nt[r]) break;
-#pragma unroll
-              for (int v = 0; v < 3; ++v) {
-                const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
-                const int lc = (int)((kEdgeLower >> (3 * e)) & 7), axis = e >> 2;
-                int64_t in = info[rb][0];
-#pragma unroll
-                for (int q = 1; q < 7; ++q) in = lc == q ? info[rb][q] : in;
-                const int32_t vid = (int32_t)((in >> 3) + __popc((unsigned)(in & 7) & ((1u << axis) - 1u)));
-                if (stage) s_tri[3 * (t0 - tbase + tq) + v] = vid;
-                else tris[3 * (t0 + tq) + v] = vid;
-              }
+              for (int q = 1; q < 7; ++q) in = lc == q ? C[r].info[q] : in;
+              const int32_t vid = (int32_t)(cinfo_vbase(in) + __popc(cinfo_mask(in) & ((1u << axis) - 1u)));
+              if (stage) s_tri[3 * (t0 - tbase + tq) + v] = vid;
+              else tris[3 * (t0 + tq) + v] = vid;
             }
           }
         }
-        t0 += nt[r];
-        ++c;
       }
+      t0 += nt[r];
+      ++c;
     }
     __syncthreads();
     if (verts_ok) {

@@ -39,9 +39,10 @@ def test_workspace_size_grows_with_grid_and_cap():
     b = N.gh_workspace_size(N.make_grid(128, -1, 2 / 128), 1000)
     c = N.gh_workspace_size(N.make_grid(128, -1, 2 / 128), 100000)
     assert 0 < a < b < c
-    # 28 bytes per corner plus two look-back words per 256-item tile, up to alignment
+    # 24 bytes per corner (k, column, value, corner word, candidate id) plus two look-back words per
+    # 256-item tile, up to alignment
     tiles = lambda cap: -(-cap // 256)
-    assert abs((c - b) - 99000 * 28 - 2 * 8 * (tiles(100000) - tiles(1000))) < 8 * 256
+    assert abs((c - b) - 99000 * 24 - 2 * 8 * (tiles(100000) - tiles(1000))) < 8 * 256
 
 
 @pytest.mark.parametrize("n,h", [(0, 0.1), (-3, 0.1), (16, 0.0), (16, float("nan")), (16, -1.0)])
