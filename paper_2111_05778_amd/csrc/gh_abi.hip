@@ -503,10 +503,8 @@ gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size
   if (tri_cap >= ((int64_t)1 << 31) || vert_cap >= gh::kMaxVerts)
     return fail(GH_EUNSUPPORTED, "capacities must stay below 2^31 triangles and 2^28 vertices");
   if (!cells && !cases) cell_cap = 0;
-  hipStream_t s = (hipStream_t)stream;
-  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearMc, s), "clear")) != GH_OK) return st;
   return hip_status(gh::launch_mc(d, g, w, verts, vert_edge, vert_t, vert_cap, tris, tri_cap, cells, cases, cell_cap,
-                                  ctr, s),
+                                  ctr, (hipStream_t)stream),
                     "mc");
 }
 
@@ -539,7 +537,6 @@ gh_status gh_polygonize_noalloc(const gh_sdb_desc* desc_h, const gh_grid* grid_h
   const int lanes = gh::current_tuning().hop_lanes_per_ray;
   if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearAll, s), "clear")) != GH_OK) return st;
   if ((st = hip_status(gh::launch_hop(d, g, w, ctr, lanes, s), "hop")) != GH_OK) return st;
-  if ((st = hip_status(gh::launch_clear(w, ctr, gh::kClearMc, s), "clear")) != GH_OK) return st;
   return hip_status(gh::launch_mc(d, g, w, verts, vert_edge, vert_t, vert_cap, tris, tri_cap, cells, cases, cell_cap,
                                   ctr, s),
                     "mc");

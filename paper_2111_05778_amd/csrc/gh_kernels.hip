@@ -22,8 +22,8 @@
 namespace gh {
 
 // ------------------------------------------------------------------ clear
-// Zeroes scan[begin, end), the given tickets and, per mode, the counters:
-// all of them before a hop, the marching-cubes ones before gh_mc.
+// Zeroes scan[begin, end), the given tickets and, before a hop, the
+// counters.  (Marching cubes leave their own scans clean for the next pass.)
 __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, unsigned int* __restrict__ ticket,
                         unsigned ticket_mask, gh_counters* __restrict__ ctr, int mode) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -36,13 +36,10 @@ __global__ void k_clear(uint64_t* __restrict__ scan, size_t begin, size_t end, u
       ctr->n_reeval = 0;
       ctr->flags = 0;
       ctr->reserved = 0;
-    }
-    if (mode == kClearAll || mode == kClearMc) {
       ctr->n_corner = 0;
       ctr->n_cells = 0;
       ctr->n_vert = 0;
       ctr->n_tri = 0;
-      ctr->flags &= ~GH_FLAG_CAPACITY;
     }
   }
 }
@@ -179,10 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_points(Eval ev, const float* __
 hipError_t launch_clear(const Workspace& ws, gh_counters* ctr, ClearMode mode, hipStream_t s) {
   size_t begin = 0, end = scan_words(ws);
   unsigned tmask = 0xffu;
-  if (mode == kClearMc) {
-    end = (size_t)(scan_cands(ws) - ws.scan);
-    tmask = (1u << kTicketCorners) | (1u << kTicketVerts) | (1u << kTicketTris);
-  } else if (mode == kClearCands) {
+  if (mode == kClearCands) {
     begin = (size_t)(scan_cands(ws) - ws.scan);
     tmask = 1u << kTicketCands;
   }

@@ -60,7 +60,7 @@ constexpr uint32_t kDescMagic = 0x67687364u;  // "ghsd"
 // >= 2^-23 (one of the conditions for the hop square root, sqrt_hop).
 constexpr int32_t kSdbRadiiNormal = 1;
 
-enum ClearMode { kClearAll = 0, kClearMc = 1, kClearCands = 2 };
+enum ClearMode { kClearAll = 0, kClearCands = 2 };
 
 // Continuation workspace (gh_cont): reached-cell and evaluated-point
 // bitmaps, two frontier lists of cap cell ids, three rotating frontier

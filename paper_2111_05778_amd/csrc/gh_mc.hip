@@ -50,6 +50,12 @@ __global__ __launch_bounds__(kBlock) void k_candidates(Grid g, Workspace ws, int
   }
 }
 
+// Zeroes p[0, count) with the whole grid.
+__device__ __forceinline__ void zero_words(uint64_t* __restrict__ p, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 // ------------------------------------------------------------------ corners
 // Candidate words of the (up to four) cell columns around lattice column
 // (a, b); a missing or empty column has mask 0.  Fixed-size and unrolled so
@@ -163,6 +169,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   __shared__ int64_t s_cand[kStageCands];
   const int n = g.n, n1 = n + 1;
   const size_t ncol = (size_t)n * n, nl = (size_t)n1 * n1;
+  // A new pass: the capacity flag of an earlier one goes.  Every tile that
+  // can set it does so after its look-back has seen tile 0 (block 0), so the
+  // clear comes first.
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAnd(&ctr->flags, ~GH_FLAG_CAPACITY);
   for (int tile = blockIdx.x; tile < (int)ws.tiles_lat; tile += gridDim.x) {
   __syncthreads();
   const size_t L = (size_t)tile * kBlock + threadIdx.x;
@@ -345,8 +355,16 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
   __shared__ float s_v[3 * kStageV];
   __shared__ int64_t s_e[kStageV];
   __shared__ float s_t[kStageV];
+  // The scans keep themselves clean for the next pass, so that a pass needs
+  // no clearing launch: the corner scan is done, the triangle scan is next.
+  // (After any pass the corner and vertex scans are zero; a hop clears all.)
+  zero_words(scan_corners(ws), (size_t)ws.tiles_lat);
+  zero_words(scan_tris(ws), (size_t)ws.tiles_cap);
   const int64_t m = ws.nlist[0];
-  if (m > ws.cap) return;  // uniform: the corners overflowed, nothing to do
+  if (m > ws.cap) {  // uniform: the corners overflowed, nothing to do
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->n_vert = 0;
+    return;
+  }
   const int n = g.n, n1 = n + 1;
   const size_t nl = (size_t)n1 * n1;
   const int ntiles = (int)((m + kTileItems - 1) / kTileItems);
@@ -530,7 +548,14 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
   __shared__ uint8_t s_case[kTileItems];
   s_mc[threadIdx.x] = g_mc.c[threadIdx.x];
   __syncthreads();
-  if (ws.nlist[0] > ws.cap) return;
+  zero_words(scan_verts(ws), (size_t)ws.tiles_cap);  // done with; zero for the next pass
+  if (ws.nlist[0] > ws.cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctr->n_tri = 0;
+      ctr->n_cells = 0;
+    }
+    return;
+  }
   const int64_t m = ws.nlist[1];
   const int n = g.n;
   const size_t nl = (size_t)(n + 1) * (n + 1);

@@ -454,3 +454,36 @@ def test_csg_n1024_candidates_and_counts(gh):
     assert out["ctr"]["n_corner"] == len(ohop.corner_points(n, cells))
     T = np.searchsorted(out["edge"], out["tri_e"])
     assert _closed_oriented(T)
+
+
+def test_marching_cubes_repeat_after_one_hop(gh):
+    """gh_mc keeps its scans clean for the next pass (no clearing launch):
+    marching cubes run three times after one hop, the middle time with too
+    small a vertex capacity, reproduce the first run exactly, and the
+    overflowing run reports the required size."""
+    import torch
+    native, P = gh
+    n, lo, h = W.grid(96)
+    poly = P.Polygonizer(P.Bound.prims(W.csg_scene(1)), n, lo, h)
+    ref = poly.run()
+    keep = {k: getattr(ref, k).clone() for k in ("verts", "vert_edge", "vert_t", "tris", "cells", "cases")}
+    c0 = dict(ref.counters)
+    for rep in range(3):
+        for k in keep:
+            getattr(poly, k).fill_(-3 if getattr(poly, k).dtype != torch.float32 else float("nan"))
+        small = rep == 1
+        st = native.gh_mc(poly.bound.desc, poly.grid, poly.ws, poly.corner_cap, poly.verts, poly.vert_edge,
+                          poly.vert_t, 10 if small else poly.vert_cap, poly.tris, poly.tri_cap, poly.cells,
+                          poly.cases, poly.cell_cap, poly.ctr)
+        native.check(st, "gh_mc")
+        torch.cuda.synchronize()
+        c = P.counters_dict(poly.ctr)
+        print(f"pass {rep}: {c}", flush=True)
+        assert c["n_vert"] == c0["n_vert"] and c["n_corner"] == c0["n_corner"]
+        if small:
+            assert c["flags"] & native.GH_FLAG_CAPACITY
+            continue
+        assert c == c0
+        m = poly.result(c)
+        for k, v in keep.items():
+            assert torch.equal(getattr(m, k), v), (rep, k)
