@@ -18,6 +18,8 @@ Prints one JSON line.  Extra objects:
   neural        the network bound (width 256, depth 4, 16 frequencies) at
                 N = 512 in split bf16 on MFMA, with its own MFMA roofline
                 and the enumeration path beside it
+  neural_bf16   the same network in plain bf16 with the shrunk hop rule (no
+                FP32 in the hop), with its own roofline and counts
   paper_net     the same for the paper's network shape (eight ReLU layers of
                 width 64 on raw coordinates, random weights): the
                 small-width MFMA regime
@@ -209,10 +211,13 @@ def event_ms(stream, fn, reps):
     return sum(a.elapsed_time(b) for a, b in ev) / reps
 
 
-def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", dense=True, tune=True, paper=False):
+def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", dense=True, tune=True, paper=False,
+                   hop="fp32"):
     """The network bound at N = 512: the calibrated random network of width
     256 (softplus, 16 frequencies), or with paper=True the paper's shape
-    (eight ReLU layers of width 64 on raw coordinates)."""
+    (eight ReLU layers of width 64 on raw coordinates).  hop: the bf16 hop
+    rule, "fp32" (ambiguous steps re-evaluated in FP32) or "shrink" (steps
+    shortened by the margin, no FP32 in the hop)."""
     import torch
 
     import workloads as W
@@ -225,7 +230,8 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", den
         workload = f"mlp_w{width}_d4_f16_seed0_n{n}"
     n, lo, h = W.grid(n)
     margin = bf16_margin(net, W.probe_points(seed=3, n=65536), precision) if precision != "fp32" else 0.0
-    poly = Polygonizer(Bound.mlp(net, precision, margin=margin, device=dev), n, lo, h, device=dev, keep_cells=False)
+    poly = Polygonizer(Bound.mlp(net, precision, margin=margin if precision != "fp32" else None, device=dev, hop=hop),
+                       n, lo, h, device=dev, keep_cells=False)
     c0 = dict(poly.run().counters)
     tuning = None
     if tune:
@@ -240,13 +246,14 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", den
     mc_ms = event_ms(stream, poly.enqueue_mc, steps)
     fpp = mlp_flop_per_point(width, depth, n_freq)
     flop = c0["n_hop_evals"] * fpp
-    out = {"workload": workload, "precision": precision, "margin": margin, "tuning": tuning,
+    out = {"workload": workload, "precision": precision, "hop_rule": hop, "margin": margin, "tuning": tuning,
            "value": n ** 3 / ((hop_ms + mc_ms) * 1e-3), "unit": "cells/s", "hop_ms": hop_ms, "mc_ms": mc_ms,
-           "counters": {k: c0[k] for k in ("n_hop_evals", "n_reeval", "n_corner", "n_vert", "n_tri")},
+           "counters": {k: c0[k] for k in ("n_hop_evals", "n_cand", "n_reeval", "n_corner", "n_vert", "n_tri")},
            "roofline": {"bound": "mfma", "kernel": "k_hop_mlp", "achieved": flop / (hop_ms * 1e-3) / 1e12,
                         "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
                         "frac": flop / (hop_ms * 1e-3) / PEAK_BF16_MFMA,
-                        "traffic": None if paper else load_traffic("k_hop_mlp"),
+                        "traffic": load_traffic("k_hop_mlp") if (not paper and precision == "bf16x3"
+                                                                 and hop == "fp32") else None,
                         "flop_per_point": fpp, "per_launch_flop": flop}}
     if dense:
         poly.enqueue_dense()
@@ -474,7 +481,8 @@ def main():
                          "that scales the HBM counters) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (built-in shapes)")
-    ap.add_argument("--sections", default="neural,paper_net,backward,batch,traced,cont,primitives,sierpinski",
+    ap.add_argument("--sections", default="neural,neural_bf16,paper_net,backward,batch,traced,cont,primitives,"
+                                          "sierpinski",
                     help="extra workloads to measure after the headline one (comma list, or none)")
     args = ap.parse_args()
     sections = [x for x in args.sections.split(",") if x and x != "none"]
@@ -599,6 +607,9 @@ def main():
     sw = max(1, args.warmup)
     if "neural" in sections:
         out["neural"] = neural_section(dev, max(3, args.steps // 4), sw, dense=not args.no_dense, tune=not args.no_tune)
+    if "neural_bf16" in sections:
+        out["neural_bf16"] = neural_section(dev, max(3, args.steps // 4), sw, precision="bf16", hop="shrink",
+                                            dense=False, tune=not args.no_tune)
     if "paper_net" in sections:
         out["paper_net"] = neural_section(dev, max(3, args.steps // 4), sw, dense=not args.no_dense,
                                           tune=not args.no_tune, paper=True)

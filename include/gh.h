@@ -98,6 +98,17 @@ enum { GH_PREC_FP32 = 0, GH_PREC_BF16 = 1, GH_PREC_BF16X3 = 2 };
  * max(z, 0), the paper's choice (Section 5.2; batch normalisation folds into
  * the weights and biases at inference). */
 enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
+/* Hop rule of the bf16 modes (the corner and lattice signs are certified in
+ * either, so the mesh is the FP32 one):
+ *   GH_BF16_HOP_FP32    a value whose step floor(|f|/h) could change within
+ *                       bf16_margin is re-evaluated in FP32 first: the hop
+ *                       schedule, candidates and counts are the FP32 ones
+ *   GH_BF16_HOP_SHRINK  the step is floor(max(|f| - bf16_margin, 0)/h) from
+ *                       the bf16 value alone (|f| - bf16_margin bounds the
+ *                       FP32 value's magnitude from below, so no cell the
+ *                       surface crosses is skipped): no FP32 in the hop, at
+ *                       the price of shorter steps and more candidates */
+enum { GH_BF16_HOP_FP32 = 0, GH_BF16_HOP_SHRINK = 1 };
 
 /* Primitive record: 16 float32 values.
  *  [0] type: 0 sphere, 1 box (exact), 2 torus, 3 capsule, 4 plane,
@@ -146,6 +157,7 @@ typedef struct {
   float a_s, r0, a_n, b;
   float bf16_margin;             /* eps >= max |f_bf16 - f_fp32|, > 0 in the bf16 modes (gh_bf16_margin) */
   int32_t activation;            /* GH_ACT_SOFTPLUS (0) or GH_ACT_RELU; gh_backward takes softplus only */
+  int32_t bf16_hop;              /* GH_BF16_HOP_FP32 (0) or GH_BF16_HOP_SHRINK (bf16 modes) */
 } gh_sdb_spec;
 
 /* Opaque, caller-owned, plain-old-data handle filled by sdb_describe.  It

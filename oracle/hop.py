@@ -35,14 +35,19 @@ def centroid_f32(lo, h, idx):
     return np.float32(lo) + t * np.float32(h)
 
 
-def hop(sdb, n, lo, h, precision="f64", columns=None):
+def hop(sdb, n, lo, h, precision="f64", columns=None, shrink=0.0):
     """Run the hop rule over every column (or the given column ids i*N + j).
 
     Returns (candidate cell ids sorted, number of bound evaluations, per-column
     evaluation counts).  precision "f32" is the twin of the GPU float32
     formula: float32 coordinates, float32 f, s = floor(d * inv_h) in float32
     with inv_h = float32(1/h), and the step capped at N.
+    shrink (FP64 only): the step is floor(max(|f| - shrink, 0) / h), the rule
+    for a value known only to within shrink of f; since |f| - shrink is still
+    at most the distance to the surface, no sign-change cell is skipped.
     """
+    if shrink and precision != "f64":
+        raise ValueError("shrink applies to the FP64 hop")
     if columns is None:
         columns = np.arange(n * n, dtype=np.int64)
     columns = np.asarray(columns, dtype=np.int64)
@@ -60,7 +65,7 @@ def hop(sdb, n, lo, h, precision="f64", columns=None):
         kk = k[live]
         if precision == "f64":
             f = sdb.f64(np.stack([x[live], y[live], centroid_f64(lo, h, kk)], axis=1))
-            s = np.floor(np.abs(f) / np.float64(h))
+            s = np.floor(np.maximum(np.abs(f) - shrink, 0.0) / np.float64(h))
         else:
             f = sdb.f32(x[live], y[live], centroid_f32(lo, h, kk))
             s = np.floor(np.abs(f) * inv_h)
@@ -115,13 +120,13 @@ class HopResult:
         return self.hop_evals + self.corner_evals
 
 
-def gridhop(sdb, n, lo, h, precision="f64"):
+def gridhop(sdb, n, lo, h, precision="f64", shrink=0.0):
     """Grid hopping followed by marching cubes on the candidate cells.
 
     Corner values are evaluated once per distinct lattice point of the
     candidates; their count is the corner evaluation count.
     """
-    cells, hop_evals, col_evals = hop(sdb, n, lo, h, precision)
+    cells, hop_evals, col_evals = hop(sdb, n, lo, h, precision, shrink=shrink)
     return polygonize_cells(sdb, n, lo, h, cells, hop_evals, col_evals, precision)
 
 

@@ -107,6 +107,8 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
     return fail(GH_EINVAL, "bf16 precisions need bf16_margin > 0 (>= max |f_bf16 - f_fp32|, see gh_bf16_margin)");
   if (!(sp->activation == GH_ACT_SOFTPLUS || sp->activation == GH_ACT_RELU))
     return fail(GH_EINVAL, "activation %d unknown", sp->activation);
+  if (!(sp->bf16_hop == GH_BF16_HOP_FP32 || sp->bf16_hop == GH_BF16_HOP_SHRINK))
+    return fail(GH_EINVAL, "bf16_hop %d unknown", sp->bf16_hop);
   const int k1 = 3 + 6 * F;
   for (int l = 0; l <= D; ++l) {
     const int fi = l == 0 ? k1 : W, fo = l == D ? 1 : W;
@@ -226,6 +228,7 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.b = sp->b;
   m.b_out = sp->biases_h[D][0];
   m.eps = sp->bf16_margin;
+  m.hop_shrink = sp->precision != GH_PREC_FP32 && sp->bf16_hop == GH_BF16_HOP_SHRINK ? 1 : 0;
   m.relu = sp->activation == GH_ACT_RELU ? 1 : 0;
   m.act_ln2 = m.relu ? 0.f : 0.693147180559945309f;
   m.act_one = m.relu ? 0.f : 1.f;

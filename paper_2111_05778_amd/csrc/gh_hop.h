@@ -588,10 +588,17 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
       const int k0 = k;
 #pragma unroll 1
       while (active && k - k0 < D) {  // k grows with every step: at most D rounds
-        const float d = fabsf(sm.f[row * D + (k - k0)]);
+        float d = fabsf(sm.f[row * D + (k - k0)]);
         bool amb = false;
-        if constexpr (P != kPrecF32)
-          amb = d <= FLT_MAX && floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
+        if constexpr (P != kPrecF32) {
+          if (m.hop_shrink) {
+            // |f| - eps bounds |f_fp32| from below: the step is safe as it is
+            // (a non-finite value stays non-finite)
+            d = d <= FLT_MAX ? fmaxf(d - m.eps, 0.f) : d;
+          } else {
+            amb = d <= FLT_MAX && floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
+          }
+        }
         if (amb) {
           pend = true;
           break;

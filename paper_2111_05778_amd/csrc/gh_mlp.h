@@ -64,6 +64,7 @@ struct MlpDesc {
   int split;            // tiles with few rows: 1 never split, 2 split <= 32 rows, 3 also <= 64 rows
   float a_s, r0, a_n, b, b_out;
   float eps;            // |f_bf16 - f_fp32| bound used by the hop test
+  int hop_shrink;       // bf16 hop: 0 FP32 values for ambiguous steps, 1 steps of floor(max(|f| - eps, 0)/h)
 };
 
 // Input feature of a hidden layer (l >= 1) that sits in slot q (0..15) of a

@@ -20,6 +20,7 @@ GH_FLAG_CAPACITY, GH_FLAG_NONFINITE, GH_FLAG_INTERNAL = 1, 2, 4
 GH_SDB_PRIMS, GH_SDB_MLP = 1, 2
 GH_PREC_FP32, GH_PREC_BF16, GH_PREC_BF16X3 = 0, 1, 2
 GH_ACT_SOFTPLUS, GH_ACT_RELU = 0, 1
+GH_BF16_HOP_FP32, GH_BF16_HOP_SHRINK = 0, 1
 GH_PRIM_FLOATS = 16
 GH_PRIM_TYPES = 11
 GH_NOALLOC_WORKSPACE_BYTES = 128 << 20
@@ -50,7 +51,7 @@ class gh_sdb_spec(ctypes.Structure):
                 ("weights_h", ctypes.POINTER(ctypes.POINTER(ctypes.c_float))),
                 ("biases_h", ctypes.POINTER(ctypes.POINTER(ctypes.c_float))),
                 ("a_s", ctypes.c_float), ("r0", ctypes.c_float), ("a_n", ctypes.c_float), ("b", ctypes.c_float),
-                ("bf16_margin", ctypes.c_float), ("activation", ctypes.c_int32)]
+                ("bf16_margin", ctypes.c_float), ("activation", ctypes.c_int32), ("bf16_hop", ctypes.c_int32)]
 
 
 class gh_tuning(ctypes.Structure):

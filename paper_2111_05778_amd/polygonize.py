@@ -38,7 +38,7 @@ class Bound:
         return Bound(spec, [rec], device)
 
     @staticmethod
-    def mlp(net, precision="fp32", margin=None, device="cuda"):
+    def mlp(net, precision="fp32", margin=None, device="cuda", hop="fp32"):
         """Neural bound f = a_s (||p|| - r0) + a_n NN(gamma(p)) + b.
 
         net: dict with "omegas" (F), "weights" (depth+1 arrays, fan_out x
@@ -47,7 +47,10 @@ class Bound:
         precision: "fp32", "bf16" or "bf16x3".
         margin: eps >= |f_bf16 - f_fp32|, required (> 0) for the bf16
         precisions, whose hop tests and signs it certifies: measure it with
-        bf16_margin() over points covering the grid's cube."""
+        bf16_margin() over points covering the grid's cube.
+        hop: rule of the bf16 hop, "fp32" (ambiguous steps re-evaluated in
+        FP32: the FP32 schedule) or "shrink" (steps of
+        floor(max(|f| - margin, 0)/h) from the bf16 value alone)."""
         if precision != "fp32" and margin is None:
             raise ValueError(f"precision {precision!r} needs a margin: pass margin=bf16_margin(net, points, "
                              f"{precision!r}) with points covering the grid's cube")
@@ -69,6 +72,7 @@ class Bound:
         spec.biases_h = bptr
         spec.a_s, spec.r0, spec.a_n, spec.b = (float(net[k]) for k in ("a_s", "r0", "a_n", "b"))
         spec.bf16_margin = float(margin or 0.0)
+        spec.bf16_hop = {"fp32": N.GH_BF16_HOP_FP32, "shrink": N.GH_BF16_HOP_SHRINK}[hop]
         return Bound(spec, [ws, bs, om, wptr, bptr], device)
 
     def eval(self, xyz):

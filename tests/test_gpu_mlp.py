@@ -253,3 +253,27 @@ def test_value_does_not_depend_on_tile_fill(gh, prec, width):
     for n in (1, 5, 31, 32, 33, 64, 65, 100, 127, 128, 129):
         part = b.eval(pts[:n].contiguous()).cpu().numpy()
         np.testing.assert_array_equal(part.view(np.uint32), full[:n].view(np.uint32), err_msg=f"n={n}")
+
+
+@pytest.mark.parametrize("prec,width,n", [("bf16", 64, 77), ("bf16", 256, 128), ("bf16", 256, 512),
+                                          ("bf16x3", 256, 512)])
+def test_shrunk_bf16_hop_gives_the_fp32_mesh(gh, prec, width, n):
+    """The bf16 hop without FP32 re-evaluation (steps of
+    floor(max(|f| - eps, 0)/h)): every sign-change cell of the FP32 path is a
+    candidate, and since corner signs stay certified the cells, cases, edges
+    and triangles are the FP32 path's; only the counts differ."""
+    native, P = gh
+    net = W.neural_scene(0, width)
+    margin = P.bf16_margin(net, W.probe_points(seed=3, n=65536), prec)
+    g = W.grid(n)
+    a = _run(gh, P.Bound.mlp(net, "fp32"), *g)
+    b = _run(gh, P.Bound.mlp(net, prec, margin=margin, hop="shrink"), *g)
+    ca, cb = a["ctr"], b["ctr"]
+    print(f"{prec} w{width} N={n} margin {margin:.2e} = {margin / float(g[2]):.3f} h: hop evals fp32 "
+          f"{ca['n_hop_evals']} shrink {cb['n_hop_evals']}, candidates {ca['n_cand']} / {cb['n_cand']}, "
+          f"re-evaluated {cb['n_reeval']}", flush=True)
+    assert cb["flags"] == 0
+    assert np.all(np.isin(a["cells"], b["cand"]))
+    for key in ("cells", "cases", "edge", "tri_e"):
+        np.testing.assert_array_equal(a[key], b[key])
+    assert cb["n_hop_evals"] >= 0.9 * ca["n_hop_evals"]

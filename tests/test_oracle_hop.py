@@ -261,3 +261,25 @@ def test_fp32_twin_matches_fp64_at_full_size(n):
     print(f"N={n}: {len(common)} vertices, max |t32 - t64| {dt.max():.2e}, "
           f"max |t32 - t64| |f_a - f_b| {(dt * gap).max():.2e}", flush=True)
     assert np.all(dt * gap <= 2e-6 * 1.01)
+
+
+@pytest.mark.parametrize("scene", ["sphere", "csg"])
+def test_shrunk_hop_rule_keeps_every_cell(scene):
+    """The bf16 hop rule: a value known only to within eps of f steps
+    floor(max(|f| - eps, 0)/h).  It still reaches every cell the surface
+    crosses (the mesh equals enumeration's), with at least as many
+    evaluations and candidates as the exact rule; a planted sign mistake
+    (|f| + eps) skips cells."""
+    recs = W.sphere_scene(0.5) if scene == "sphere" else W.csg_scene(2)
+    S = sdb.SDB.prims(recs)
+    n, lo, h = W.grid(48)
+    dense, _ = mc.enumerate_mesh(S, n, lo, h)
+    exact = hop.gridhop(S, n, lo, h)
+    for eps in (0.3 * h, 1.7 * h):
+        r = hop.gridhop(S, n, lo, h, shrink=eps)
+        assert _mesh_equal(r.mesh, dense)
+        assert np.all(np.isin(dense.cells, r.candidates))
+        assert r.hop_evals >= exact.hop_evals and len(r.candidates) >= len(exact.candidates)
+    # planted: the margin added instead of subtracted
+    cells, _, _ = hop.hop(S, n, lo, h, shrink=-1.7 * h)
+    assert not np.all(np.isin(dense.cells, cells))
