@@ -347,10 +347,36 @@ def batch_section(dev, steps, warmup, precision="bf16x3", tune=True):
     from paper_2111_05778_amd.polygonize import counters_dict
     for p, c in zip(batch.polys, ref):
         assert counters_dict(p.ctr)["n_tri"] == c["n_tri"]
+    # the same shapes one by one, each replaying its own captured graph (hop +
+    # marching cubes), back to back on one stream
+    for p in batch.polys:
+        p.capture()
+    for _ in range(warmup):
+        for p in batch.polys:
+            p.replay()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for p in batch.polys:
+            p.replay()
+    torch.cuda.synchronize(dev)
+    singles_ms = (time.perf_counter() - t0) / steps * 1e3
+    for p, c in zip(batch.polys, ref):
+        assert counters_dict(p.ctr)["n_tri"] == c["n_tri"]
     cells = sum(sc["n"] ** 3 for sc in scenes)
+    # algorithmic work of the batch's hops, per kind
+    net_flop = sum(c["n_hop_evals"] * mlp_flop_per_point(sc["width"], 4, 16)
+                   for sc, c in zip(scenes, ref) if sc["kind"] == "mlp")
+    prim_ops = sum(c["n_hop_evals"] * ops_per_eval(W.csg_scene(sc["seed"], sc["n_prim"]))
+                   for sc, c in zip(scenes, ref) if sc["kind"] == "csg")
     return {"workload": "batch64_seed2", "precision": precision, "tuning": tuning, "shapes": len(scenes), "cells": cells,
             "work_items": batch.item_count(), "ms_per_step": ms, "value": cells / (ms * 1e-3), "unit": "cells/s",
-            "n_tri": sum(c["n_tri"] for c in ref)}
+            "n_tri": sum(c["n_tri"] for c in ref),
+            "singles_ms": singles_ms, "batch_over_singles": ms / singles_ms,
+            "hop_evals": {"network": sum(c["n_hop_evals"] for sc, c in zip(scenes, ref) if sc["kind"] == "mlp"),
+                          "analytic": sum(c["n_hop_evals"] for sc, c in zip(scenes, ref) if sc["kind"] == "csg")},
+            "network_flop": net_flop, "analytic_flop": prim_ops,
+            "network_tflops_over_step": net_flop / (ms * 1e-3) / 1e12}
 
 
 def primitives_section(dev, steps, warmup, n=512, seed=0):

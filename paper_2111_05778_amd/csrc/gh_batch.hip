@@ -1,12 +1,17 @@
-// Many bounds on uneven grids in one persistent hop launch.
+// Many bounds on uneven grids in two persistent hop launches.
 //
-// The plan holds a table of shapes (bound, grid, workspace, counters) and a
-// list of work items: a block tile of ray columns for an analytic bound, a
-// range of rays for a network bound (gh_tuning.batch_rays_per_item).  Items are ordered by estimated cost,
-// longest first, and persistent blocks take them from one counter, so uneven
-// grids and widths keep the device busy until the end.  After the hop every
-// shape gets its own marching-cubes pass; the whole sequence can be captured
-// once into a hipGraph and replayed.
+// The plan holds a table of shapes (bound, grid, workspace, counters) and two
+// lists of work items: block tiles of ray columns of the analytic bounds, and
+// ranges of rays of the network bounds (gh_tuning.batch_rays_per_item).  Each
+// list is ordered by estimated cost, longest first, and its persistent kernel
+// takes items from its own counter, so uneven grids and widths keep the
+// device busy until the end.  The analytic items run at the occupancy of the
+// single-shape hop, the network items at one wave per SIMD (their activations
+// fill the register file).  After the hops every shape gets its own
+// marching-cubes pass; the whole sequence can be captured once into a
+// hipGraph and replayed.  (The marching-cubes passes of different shapes stay
+// in order on one stream: their look-back scans need every block of a kernel
+// resident at once, which kernels running side by side would not ensure.)
 
 #include <math.h>
 #include <string.h>
@@ -47,9 +52,9 @@ struct RangeRays {
   }
 };
 
-// Zeroes every shape's counters, look-back words and tickets, and the item counter.
+// Zeroes every shape's counters, look-back words and tickets, and the two item counters.
 __global__ void k_batch_clear(const BatchShape* __restrict__ shapes, int n_shapes, unsigned int* __restrict__ head) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *head = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 2) head[threadIdx.x] = 0;
   for (int s = blockIdx.x; s < n_shapes; s += gridDim.x) {
     const BatchShape& sh = shapes[s];
     const size_t nw = (size_t)(sh.ws.tiles_lat + 2 * sh.ws.tiles_cap + sh.ws.tiles_col);
@@ -64,12 +69,32 @@ __global__ void k_batch_clear(const BatchShape* __restrict__ shapes, int n_shape
   }
 }
 
+// Analytic items: a block tile of ray columns of one shape each.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_hop_batched_prims(
+    const BatchShape* __restrict__ shapes, const WorkItem* __restrict__ items, int n_items,
+    unsigned int* __restrict__ head) {
+  __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= n_items) break;  // uniform: every block leaves once the list is exhausted
+    const WorkItem wi = items[it];
+    const BatchShape& sh = shapes[wi.shape];
+    stage_prims(s_rec, sh.sdb.prims, sh.sdb.groups.start[kPrimTypes]);
+    hop_prims_tile<4>(reinterpret_cast<const float*>(s_rec), sh.sdb.groups, sh.grid, sh.ws.colmask, sh.ws.colbits,
+                      sh.ctr, (int)wi.a);
+  }
+}
+
+// Network items: a range of rays of one shape each, through the ray pool.
 template <int P>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_hop_batched(const BatchShape* __restrict__ shapes,
                                                         const WorkItem* __restrict__ items, int n_items,
                                                         unsigned int* __restrict__ head) {
   __shared__ MlpSmem sm;
-  __shared__ float4 s_rec[kMaxPrims * GH_PRIM_FLOATS / 4];
   __shared__ int s_cnt[kBlock / 64];
   __shared__ unsigned int s_base, s_next;
   __shared__ int s_item;
@@ -81,11 +106,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     if (it >= n_items) break;  // uniform: every block leaves once the list is exhausted
     const WorkItem wi = items[it];
     const BatchShape& sh = shapes[wi.shape];
-    if (sh.sdb.kind == GH_SDB_PRIMS) {
-      stage_prims(s_rec, sh.sdb.prims, sh.sdb.groups.start[kPrimTypes]);
-      hop_prims_tile<4>(reinterpret_cast<const float*>(s_rec), sh.sdb.groups, sh.grid, sh.ws.colmask, sh.ws.colbits,
-                        sh.ctr, (int)wi.a);
-    } else {
+    {
       if (threadIdx.x == 0) s_next = 0;
       __syncthreads();
       const RangeRays src{&s_next, wi.a, wi.b};
@@ -114,8 +135,9 @@ struct gh_batch {
   std::vector<gh::Workspace> ws;
   gh::BatchShape* d_shapes = nullptr;  // in the caller's device buffer
   gh::WorkItem* d_items = nullptr;
-  unsigned int* d_head = nullptr;
+  unsigned int* d_head = nullptr;      // [0] network item counter, [1] analytic item counter
   int n_items = 0;
+  int n_prim_items = 0;                // the analytic items come first in d_items
   int precision = gh::kPrecF32;
   hipGraphExec_t exec = nullptr;
 };
@@ -165,18 +187,22 @@ hipError_t enqueue_batch(gh_batch* b, hipStream_t s) {
   const int ns = (int)b->items.size();
   hipLaunchKernelGGL(gh::k_batch_clear, dim3(ns < 1024 ? ns : 1024), dim3(gh::kBlock), 0, s, b->d_shapes, ns,
                      b->d_head);
-  int per_cu = 0;
   const int cus = gh::cu_count();
-  auto hop = [&](auto kernel) {
+  auto hop = [&](auto kernel, const gh::WorkItem* items, int n, unsigned int* head) {
+    if (n == 0) return;
+    int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, gh::kBlock, 0) != hipSuccess || per_cu < 1)
       per_cu = 1;
-    const int blocks = std::max(1, std::min(b->n_items, cus * per_cu));
-    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(gh::kBlock), 0, s, b->d_shapes, b->d_items, b->n_items, b->d_head);
+    const int blocks = std::max(1, std::min(n, cus * per_cu));
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(gh::kBlock), 0, s, b->d_shapes, items, n, head);
   };
+  const int n_net = b->n_items - b->n_prim_items;
+  hop(gh::k_hop_batched_prims, b->d_items, b->n_prim_items, b->d_head + 1);
+  const gh::WorkItem* net_items = b->d_items + b->n_prim_items;
   switch (b->precision) {
-    case gh::kPrecBf16: hop(gh::k_hop_batched<gh::kPrecBf16>); break;
-    case gh::kPrecBf16x3: hop(gh::k_hop_batched<gh::kPrecBf16x3>); break;
-    default: hop(gh::k_hop_batched<gh::kPrecF32>); break;
+    case gh::kPrecBf16: hop(gh::k_hop_batched<gh::kPrecBf16>, net_items, n_net, b->d_head); break;
+    case gh::kPrecBf16x3: hop(gh::k_hop_batched<gh::kPrecBf16x3>, net_items, n_net, b->d_head); break;
+    default: hop(gh::k_hop_batched<gh::kPrecF32>, net_items, n_net, b->d_head); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -244,8 +270,14 @@ gh_status gh_batch_create(int n_shapes, const gh_batch_item* items_h, void* dev_
     shape_items(i, d, g, work);
   }
   b->precision = mlp_prec < 0 ? gh::kPrecF32 : mlp_prec;
-  std::stable_sort(work.begin(), work.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  // analytic items first, then network items, each by cost, longest first
+  std::stable_sort(work.begin(), work.end(), [&](const auto& x, const auto& y) {
+    const bool px = b->sdb[x.second.shape].kind == GH_SDB_PRIMS, py = b->sdb[y.second.shape].kind == GH_SDB_PRIMS;
+    return px != py ? px : x.first > y.first;
+  });
   b->n_items = (int)work.size();
+  b->n_prim_items = 0;
+  for (const auto& w : work) b->n_prim_items += b->sdb[w.second.shape].kind == GH_SDB_PRIMS ? 1 : 0;
   const size_t need = batch_layout(n_shapes, b->n_items, nullptr, nullptr);
   if (dev_bytes < need) {
     delete b;
