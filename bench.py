@@ -229,9 +229,12 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", den
         net, depth, n_freq = W.neural_scene(0, width), 4, 16
         workload = f"mlp_w{width}_d4_f16_seed0_n{n}"
     n, lo, h = W.grid(n)
-    margin = bf16_margin(net, W.probe_points(seed=3, n=65536), precision) if precision != "fp32" else 0.0
-    poly = Polygonizer(Bound.mlp(net, precision, margin=margin if precision != "fp32" else None, device=dev, hop=hop),
-                       n, lo, h, device=dev, keep_cells=False)
+    probe = W.probe_points(seed=3, n=65536)
+    margin = bf16_margin(net, probe, precision) if precision != "fp32" else 0.0
+    # plain bf16: corner values near zero are certified by the split form first
+    margin3 = bf16_margin(net, probe, "bf16x3") if precision == "bf16" else 0.0
+    poly = Polygonizer(Bound.mlp(net, precision, margin=margin if precision != "fp32" else None, device=dev, hop=hop,
+                                 margin3=margin3), n, lo, h, device=dev, keep_cells=False)
     c0 = dict(poly.run().counters)
     tuning = None
     if tune:
@@ -246,7 +249,8 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", den
     mc_ms = event_ms(stream, poly.enqueue_mc, steps)
     fpp = mlp_flop_per_point(width, depth, n_freq)
     flop = c0["n_hop_evals"] * fpp
-    out = {"workload": workload, "precision": precision, "hop_rule": hop, "margin": margin, "tuning": tuning,
+    out = {"workload": workload, "precision": precision, "hop_rule": hop, "margin": margin, "margin3": margin3,
+           "tuning": tuning,
            "value": n ** 3 / ((hop_ms + mc_ms) * 1e-3), "unit": "cells/s", "hop_ms": hop_ms, "mc_ms": mc_ms,
            "counters": {k: c0[k] for k in ("n_hop_evals", "n_cand", "n_reeval", "n_corner", "n_vert", "n_tri")},
            "roofline": {"bound": "mfma", "kernel": "k_hop_mlp", "achieved": flop / (hop_ms * 1e-3) / 1e12,

@@ -158,6 +158,9 @@ typedef struct {
   float bf16_margin;             /* eps >= max |f_bf16 - f_fp32|, > 0 in the bf16 modes (gh_bf16_margin) */
   int32_t activation;            /* GH_ACT_SOFTPLUS (0) or GH_ACT_RELU; gh_backward takes softplus only */
   int32_t bf16_hop;              /* GH_BF16_HOP_FP32 (0) or GH_BF16_HOP_SHRINK (bf16 modes) */
+  float bf16x3_margin;           /* GH_PREC_BF16 only: eps3 >= max |f_bf16x3 - f_fp32| > 0 certifies the corner
+                                    values within bf16_margin of zero in two steps, bf16x3 first and FP32 only
+                                    within eps3 of zero; 0: those corners go to FP32 directly */
 } gh_sdb_spec;
 
 /* Opaque, caller-owned, plain-old-data handle filled by sdb_describe.  It

@@ -109,6 +109,9 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
     return fail(GH_EINVAL, "activation %d unknown", sp->activation);
   if (!(sp->bf16_hop == GH_BF16_HOP_FP32 || sp->bf16_hop == GH_BF16_HOP_SHRINK))
     return fail(GH_EINVAL, "bf16_hop %d unknown", sp->bf16_hop);
+  if (!(sp->bf16x3_margin >= 0.f && sp->bf16x3_margin <= 1e6f)) return fail(GH_EINVAL, "bf16x3_margin must be >= 0");
+  if (sp->bf16x3_margin > 0.f && sp->precision != GH_PREC_BF16)
+    return fail(GH_EINVAL, "bf16x3_margin applies to GH_PREC_BF16 only");
   const int k1 = 3 + 6 * F;
   for (int l = 0; l <= D; ++l) {
     const int fi = l == 0 ? k1 : W, fo = l == D ? 1 : W;
@@ -229,6 +232,7 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.b_out = sp->biases_h[D][0];
   m.eps = sp->bf16_margin;
   m.hop_shrink = sp->precision != GH_PREC_FP32 && sp->bf16_hop == GH_BF16_HOP_SHRINK ? 1 : 0;
+  m.eps3 = sp->bf16x3_margin;
   m.relu = sp->activation == GH_ACT_RELU ? 1 : 0;
   m.act_ln2 = m.relu ? 0.f : 0.693147180559945309f;
   m.act_one = m.relu ? 0.f : 1.f;

@@ -65,6 +65,7 @@ struct MlpDesc {
   float a_s, r0, a_n, b, b_out;
   float eps;            // |f_bf16 - f_fp32| bound used by the hop test
   int hop_shrink;       // bf16 hop: 0 FP32 values for ambiguous steps, 1 steps of floor(max(|f| - eps, 0)/h)
+  float eps3;           // plain bf16: |f_bf16x3 - f_fp32| bound for two-step corner certification (0: none)
 };
 
 // Input feature of a hidden layer (l >= 1) that sits in slot q (0..15) of a

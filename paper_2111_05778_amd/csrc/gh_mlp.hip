@@ -61,21 +61,55 @@ __device__ __forceinline__ void corners_fp32(const MlpDesc& m, const Grid& g, co
   __syncthreads();
 }
 
+// Split-bf16 values of the corners whose indices are in s_idx3[0, cnt) (cnt <=
+// kBf16Rows): a value with |f| >= eps3 is certain of its sign and goes to
+// the corner list, the others join the FP32 queue s_idx at *npend.
+template <int W, class Sm>
+__device__ __forceinline__ void corners_split(const MlpDesc& m, const Grid& g, const Workspace& ws, Sm& sm,
+                                              int* s_cnt, const int64_t* s_idx3, int cnt, int64_t* s_idx,
+                                              int& npend) {
+  const int n1 = g.n + 1;
+  const int t = threadIdx.x;
+  if (t < cnt) {
+    const int64_t i = s_idx3[t];
+    const int L = ws.cl[i], a = L / n1, b = L - a * n1;
+    sm.pts[t][0] = lattice(g, a);
+    sm.pts[t][1] = lattice(g, b);
+    sm.pts[t][2] = lattice(g, ws.ck[i]);
+  }
+  __syncthreads();
+  mlp_tile<kPrecBf16x3, W>(m, sm, cnt);
+  const float f = t < cnt ? sm.f[t] : 0.f;
+  __syncthreads();
+  const bool amb = t < cnt && fabsf(f) < m.eps3;
+  int namb;
+  const int r = block_rank(amb, s_cnt, namb);
+  if (amb) s_idx[npend + r] = s_idx3[t];
+  else if (t < cnt) ws.cf[s_idx3[t]] = f;
+  npend += namb;
+  __syncthreads();
+}
+
 // Bound at every corner of the corner list.  In the bf16 precisions a value
 // with |f| < eps gets an FP32 value instead (its sign is then the FP32 sign);
 // those corners are collected per block and evaluated in full FP32 tiles.
+// Plain bf16 with eps3 > 0 certifies in two steps: such a corner first gets
+// a split-bf16 value (full tiles of kBf16Rows), and only one within eps3 of
+// zero goes on to FP32.
 template <int P, int W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_corners(
     MlpDesc m, Grid g, Workspace ws, gh_counters* __restrict__ ctr) {
   __shared__ MlpSmemFor<P> sm;
   __shared__ int s_cnt[kBlock / 64];
-  __shared__ int64_t s_idx[kF32Rows + kBf16Rows];
+  __shared__ int64_t s_idx[kF32Rows + kBf16Rows];  // waiting for FP32: < kF32Rows + one tile's worth
+  __shared__ int64_t s_idx3[P == kPrecBf16 ? 2 * kBf16Rows : 1];  // waiting for split bf16
   constexpr int R = mlp_rows<P>();
   const int64_t count = ws.nlist[0];
   if (count > ws.cap) return;
   const int n1 = g.n + 1;
   uint64_t reevals = 0;
-  int npend = 0;  // block-uniform
+  int npend = 0, npend3 = 0;  // block-uniform
+  const bool two_step = P == kPrecBf16 && m.eps3 > 0.f;
   const int64_t tiles = (count + R - 1) / R;
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t i0 = tile * R;
@@ -96,10 +130,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
       const bool amb = mine && fabsf(f) < m.eps;
       int namb;
       const int r = block_rank(amb, s_cnt, namb);
-      if (amb) s_idx[npend + r] = i0 + threadIdx.x;
-      else if (mine) ws.cf[i0 + threadIdx.x] = f;
-      npend += namb;
+      if constexpr (P == kPrecBf16) {
+        if (two_step) {
+          if (amb) s_idx3[npend3 + r] = i0 + threadIdx.x;
+          npend3 += namb;
+        } else {
+          if (amb) s_idx[npend + r] = i0 + threadIdx.x;
+          npend += namb;
+        }
+      } else {
+        if (amb) s_idx[npend + r] = i0 + threadIdx.x;
+        npend += namb;
+      }
+      if (!amb && mine) ws.cf[i0 + threadIdx.x] = f;
       __syncthreads();
+      if constexpr (P == kPrecBf16) {
+        while (npend3 >= kBf16Rows) {  // each split tile adds at most kBf16Rows to a queue below kF32Rows
+          npend3 -= kBf16Rows;
+          corners_split<W>(m, g, ws, sm, s_cnt, s_idx3 + npend3, kBf16Rows, s_idx, npend);
+          while (npend >= kF32Rows) {
+            npend -= kF32Rows;
+            corners_fp32<W>(m, g, ws, sm, s_idx + npend, kF32Rows);
+            reevals += threadIdx.x == 0 ? kF32Rows : 0;
+          }
+        }
+      }
       while (npend >= kF32Rows) {
         npend -= kF32Rows;
         corners_fp32<W>(m, g, ws, sm, s_idx + npend, kF32Rows);
@@ -110,9 +165,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     }
   }
   if constexpr (P != kPrecF32) {
-    if (npend > 0) {
-      corners_fp32<W>(m, g, ws, sm, s_idx, npend);
-      reevals += threadIdx.x == 0 ? npend : 0;
+    if constexpr (P == kPrecBf16) {
+      if (npend3 > 0) corners_split<W>(m, g, ws, sm, s_cnt, s_idx3, npend3, s_idx, npend);
+    }
+    while (npend > 0) {
+      const int c = npend < kF32Rows ? npend : kF32Rows;
+      npend -= c;
+      corners_fp32<W>(m, g, ws, sm, s_idx + npend, c);
+      reevals += threadIdx.x == 0 ? c : 0;
     }
     block_add_u64(reevals, (unsigned long long*)&ctr->n_reeval);
   }

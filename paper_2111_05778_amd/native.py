@@ -51,7 +51,8 @@ class gh_sdb_spec(ctypes.Structure):
                 ("weights_h", ctypes.POINTER(ctypes.POINTER(ctypes.c_float))),
                 ("biases_h", ctypes.POINTER(ctypes.POINTER(ctypes.c_float))),
                 ("a_s", ctypes.c_float), ("r0", ctypes.c_float), ("a_n", ctypes.c_float), ("b", ctypes.c_float),
-                ("bf16_margin", ctypes.c_float), ("activation", ctypes.c_int32), ("bf16_hop", ctypes.c_int32)]
+                ("bf16_margin", ctypes.c_float), ("activation", ctypes.c_int32), ("bf16_hop", ctypes.c_int32),
+                ("bf16x3_margin", ctypes.c_float)]
 
 
 class gh_tuning(ctypes.Structure):

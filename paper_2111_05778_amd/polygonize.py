@@ -38,7 +38,7 @@ class Bound:
         return Bound(spec, [rec], device)
 
     @staticmethod
-    def mlp(net, precision="fp32", margin=None, device="cuda", hop="fp32"):
+    def mlp(net, precision="fp32", margin=None, device="cuda", hop="fp32", margin3=0.0):
         """Neural bound f = a_s (||p|| - r0) + a_n NN(gamma(p)) + b.
 
         net: dict with "omegas" (F), "weights" (depth+1 arrays, fan_out x
@@ -50,7 +50,10 @@ class Bound:
         bf16_margin() over points covering the grid's cube.
         hop: rule of the bf16 hop, "fp32" (ambiguous steps re-evaluated in
         FP32: the FP32 schedule) or "shrink" (steps of
-        floor(max(|f| - margin, 0)/h) from the bf16 value alone)."""
+        floor(max(|f| - margin, 0)/h) from the bf16 value alone).
+        margin3 (plain bf16 only): eps3 >= |f_bf16x3 - f_fp32|; corner values
+        within margin of zero are then certified by a split-bf16 value first
+        and go to FP32 only within margin3 of zero (0: FP32 directly)."""
         if precision != "fp32" and margin is None:
             raise ValueError(f"precision {precision!r} needs a margin: pass margin=bf16_margin(net, points, "
                              f"{precision!r}) with points covering the grid's cube")
@@ -73,6 +76,7 @@ class Bound:
         spec.a_s, spec.r0, spec.a_n, spec.b = (float(net[k]) for k in ("a_s", "r0", "a_n", "b"))
         spec.bf16_margin = float(margin or 0.0)
         spec.bf16_hop = {"fp32": N.GH_BF16_HOP_FP32, "shrink": N.GH_BF16_HOP_SHRINK}[hop]
+        spec.bf16x3_margin = float(margin3)
         return Bound(spec, [ws, bs, om, wptr, bptr], device)
 
     def eval(self, xyz):

@@ -277,3 +277,33 @@ def test_shrunk_bf16_hop_gives_the_fp32_mesh(gh, prec, width, n):
     for key in ("cells", "cases", "edge", "tri_e"):
         np.testing.assert_array_equal(a[key], b[key])
     assert cb["n_hop_evals"] >= 0.9 * ca["n_hop_evals"]
+
+
+@pytest.mark.parametrize("n", [128, 512])
+def test_two_step_corner_certification(gh, n):
+    """Plain bf16 with the split form's margin eps3: corner values within eps
+    of zero are certified by a split-bf16 value first and go to FP32 only
+    within eps3 of zero.  The cells, cases, edges and triangles stay the FP32
+    path's, the mesh stays within 0.5 h of it (surface Hausdorff on the band
+    of rows through the shape), and far fewer values need FP32."""
+    import torch
+    native, P = gh
+    net = W.neural_scene(0, 256)
+    probe = W.probe_points(seed=3, n=65536)
+    eps, eps3 = P.bf16_margin(net, probe, "bf16"), P.bf16_margin(net, probe, "bf16x3")
+    g = W.grid(n)
+    a = _run(gh, P.Bound.mlp(net, "fp32"), *g)
+    one = _run(gh, P.Bound.mlp(net, "bf16", margin=eps, hop="shrink"), *g)
+    two = _run(gh, P.Bound.mlp(net, "bf16", margin=eps, hop="shrink", margin3=eps3), *g)
+    print(f"N={n}: eps {eps:.2e} eps3 {eps3:.2e}; FP32 re-evaluations one step {one['ctr']['n_reeval']}, "
+          f"two steps {two['ctr']['n_reeval']}", flush=True)
+    for key in ("cells", "cases", "edge", "tri_e"):
+        np.testing.assert_array_equal(a[key], two[key])
+    i0, i1 = n // 2 - 8, n // 2 + 8
+    _, _, VA, TA = U.gpu_band(a["cells"], a["cases"], a["verts"], a["tris"], n, i0, i1)
+    _, _, VB, TB = U.gpu_band(two["cells"], two["cases"], two["verts"], two["tris"], n, i0, i1)
+    hd = omesh.hausdorff(VB, TB, VA, TA)
+    print(f"N={n}: Hausdorff to the FP32 mesh on rows {i0}..{i1}: {hd / float(g[2]):.4f} h", flush=True)
+    assert hd <= 0.5 * float(g[2])
+    assert two["ctr"]["n_reeval"] < 0.1 * one["ctr"]["n_reeval"]
+    assert two["ctr"]["n_hop_evals"] == one["ctr"]["n_hop_evals"]
