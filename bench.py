@@ -16,10 +16,12 @@ Prints one JSON line.  Extra objects:
   cpu_baseline  the oracle (FP64 numpy) on the same workload on all host cores
                 (at most 16), with the one-thread time beside it
   neural        the network bound (width 256, depth 4, 16 frequencies) at
-                N = 512 in split bf16 on MFMA, with its own MFMA roofline
-                and the enumeration path beside it
-  neural_bf16   the same network in plain bf16 with the shrunk hop rule (no
-                FP32 in the hop), with its own roofline and counts
+                N = 512 in bf16 on MFMA with FP32 accumulation: the hop steps
+                shortened by the bf16 margin (no FP32 in the hop), corner
+                signs certified by split bf16 and FP32; its MFMA roofline and
+                the enumeration path (same certification) beside it
+  neural_bf16x3 the same network in split bf16 (hi*hi + hi*lo + lo*hi) with
+                the FP32 hop schedule, its roofline and its enumeration
   paper_net     the same for the paper's network shape (eight ReLU layers of
                 width 64 on raw coordinates, random weights): the
                 small-width MFMA regime
@@ -211,8 +213,8 @@ def event_ms(stream, fn, reps):
     return sum(a.elapsed_time(b) for a, b in ev) / reps
 
 
-def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16x3", dense=True, tune=True, paper=False,
-                   hop="fp32"):
+def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16", dense=True, tune=True, paper=False,
+                   hop="shrink"):
     """The network bound at N = 512: the calibrated random network of width
     256 (softplus, 16 frequencies), or with paper=True the paper's shape
     (eight ReLU layers of width 64 on raw coordinates).  hop: the bf16 hop
@@ -314,7 +316,7 @@ def backward_section(dev, steps, warmup, n=256, width=256):
                          "corners": corners, "flop_per_corner": fpc, "per_launch_flop": flop}}
 
 
-def batch_section(dev, steps, warmup, precision="bf16x3", tune=True):
+def batch_section(dev, steps, warmup, precision="bf16", tune=True):
     import torch
 
     import workloads as W
@@ -328,7 +330,10 @@ def batch_section(dev, steps, warmup, precision="bf16x3", tune=True):
             b = Bound.prims(W.csg_scene(sc["seed"], sc["n_prim"]), dev)
         else:
             net = W.neural_scene(sc["seed"], sc["width"])
-            b = Bound.mlp(net, precision, margin=bf16_margin(net, probe, precision), device=dev)
+            plain = precision == "bf16"   # shrunk hop, two-step corner certification
+            b = Bound.mlp(net, precision, margin=bf16_margin(net, probe, precision), device=dev,
+                          hop="shrink" if plain else "fp32",
+                          margin3=bf16_margin(net, probe, "bf16x3") if plain else 0.0)
         shapes.append((b, n, lo, h))
     tuning = None
     if tune:
@@ -511,7 +516,7 @@ def main():
                          "that scales the HBM counters) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (built-in shapes)")
-    ap.add_argument("--sections", default="neural,neural_bf16,paper_net,backward,batch,traced,cont,primitives,"
+    ap.add_argument("--sections", default="neural,neural_bf16x3,paper_net,backward,batch,traced,cont,primitives,"
                                           "sierpinski",
                     help="extra workloads to measure after the headline one (comma list, or none)")
     args = ap.parse_args()
@@ -637,9 +642,9 @@ def main():
     sw = max(1, args.warmup)
     if "neural" in sections:
         out["neural"] = neural_section(dev, max(3, args.steps // 4), sw, dense=not args.no_dense, tune=not args.no_tune)
-    if "neural_bf16" in sections:
-        out["neural_bf16"] = neural_section(dev, max(3, args.steps // 4), sw, precision="bf16", hop="shrink",
-                                            dense=False, tune=not args.no_tune)
+    if "neural_bf16x3" in sections:
+        out["neural_bf16x3"] = neural_section(dev, max(3, args.steps // 4), sw, precision="bf16x3", hop="fp32",
+                                              dense=not args.no_dense, tune=not args.no_tune)
     if "paper_net" in sections:
         out["paper_net"] = neural_section(dev, max(3, args.steps // 4), sw, dense=not args.no_dense,
                                           tune=not args.no_tune, paper=True)

@@ -422,6 +422,29 @@ __device__ __forceinline__ int block_rank(bool pred, int* s_cnt, int& total) {
   return before + __popcll(bal & ((1ull << lane) - 1ull));
 }
 
+// Split-bf16 re-evaluation of the points (x, y, z) of the threads with amb
+// set, in tiles of kBf16Rows; returns f updated for those threads (the first
+// step of the plain-bf16 sign certification).
+template <int W, class Sm>
+__device__ __forceinline__ float reeval_split(const MlpDesc& m, Sm& sm, int* s_cnt, bool amb, float x, float y,
+                                              float z, float f) {
+  int namb;
+  const int arow = block_rank(amb, s_cnt, namb);
+  for (int base = 0; base < namb; base += kBf16Rows) {
+    const bool mine = amb && arow >= base && arow < base + kBf16Rows;
+    if (mine) {
+      sm.pts[arow - base][0] = x;
+      sm.pts[arow - base][1] = y;
+      sm.pts[arow - base][2] = z;
+    }
+    __syncthreads();
+    mlp_tile<kPrecBf16x3, W>(m, sm, namb - base < kBf16Rows ? namb - base : kBf16Rows);
+    if (mine) f = sm.f[arow - base];
+    __syncthreads();
+  }
+  return f;
+}
+
 // FP32 re-evaluation of the points (x, y, z) of the threads with amb set, in
 // tiles of kF32Rows; returns f updated for those threads.
 template <int W, class Sm>

@@ -213,7 +213,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     mlp_tile<P, W>(m, sm, R);
     float f = r < R ? sm.f[r] : 0.f;
     __syncthreads();
-    if constexpr (P != kPrecF32) f = reeval_fp32<W>(m, sm, s_cnt, valid && fabsf(f) < m.eps, x, y, z, f, reevals);
+    if constexpr (P != kPrecF32) {
+      bool amb = valid && fabsf(f) < m.eps;
+      if constexpr (P == kPrecBf16) {
+        if (m.eps3 > 0.f) {  // two steps: split bf16 first, FP32 only within eps3 of zero
+          f = reeval_split<W>(m, sm, s_cnt, amb, x, y, z, f);
+          amb = amb && fabsf(f) < m.eps3;
+        }
+      }
+      f = reeval_fp32<W>(m, sm, s_cnt, amb, x, y, z, f, reevals);
+    }
     bad |= valid && !(fabsf(f) <= FLT_MAX);
     const uint64_t msk = __ballot(valid && f < 0.f);
     if (r < R && (r & 63) == 0 && u < units) {

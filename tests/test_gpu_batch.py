@@ -38,12 +38,18 @@ def _bound(P, sc, precision, margin_cache):
     if sc["kind"] == "csg":
         return P.Bound.prims(W.csg_scene(sc["seed"], sc["n_prim"]))
     net = W.neural_scene(sc["seed"], sc["width"])
-    margin = 0.0
-    if precision != "fp32":
-        key = (sc["seed"], sc["width"], precision)
+    margin = None
+
+    def measured(prec):
+        key = (sc["seed"], sc["width"], prec)
         if key not in margin_cache:
-            margin_cache[key] = P.bf16_margin(net, W.probe_points(seed=3, n=65536), precision)
-        margin = margin_cache[key]
+            margin_cache[key] = P.bf16_margin(net, W.probe_points(seed=3, n=65536), prec)
+        return margin_cache[key]
+
+    if precision == "bf16":  # plain bf16: shrunk hop, two-step corner certification
+        return P.Bound.mlp(net, precision, margin=measured("bf16"), hop="shrink", margin3=measured("bf16x3"))
+    if precision != "fp32":
+        margin = measured(precision)
     return P.Bound.mlp(net, precision, margin=margin)
 
 
@@ -80,7 +86,7 @@ def _mixed(P, precision, margins, sizes):
 SIZES = [37, 50, 61, 64, 75, 83, 29, 96]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16"])
 def test_mixed_batch_equals_single_runs(gh, precision):
     torch, N, P = gh
     margins = {}
@@ -156,11 +162,11 @@ def test_graph_replays_equal_eager(gh):
 
 def test_full_batch_64_shapes(gh):
     # the batched workload: 64 shapes, N in {64, 128, 256, 512}, half CSG
-    # unions of 4..16 primitives, half networks of width 64/128/256 (split bf16)
+    # unions of 4..16 primitives, half networks of width 64/128/256 (bf16)
     torch, N, P = gh
     margins = {}
     scenes = W.batch_scenes()
-    bounds = [_bound(P, sc, "bf16x3", margins) for sc in scenes]
+    bounds = [_bound(P, sc, "bf16", margins) for sc in scenes]
     grids = [W.grid(sc["n"]) for sc in scenes]
     batch = P.BatchPolygonizer([(b, *g) for b, g in zip(bounds, grids)], keep_cells=True)
     res = [_snap(r) for r in batch.run()]
