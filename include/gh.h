@@ -383,6 +383,11 @@ typedef struct {
                                   first pass, after which a ray still running continues in a second pass
                                   with one wave per ray, which evaluates a window of 64 / lanes cells at
                                   once and steps through it.  Results do not depend on it */
+  int32_t mlp_pool_tiles;      /* network hop: rays a block keeps in its pool, in tiles of rows: 1 or 2
+                                  (default 2; the second tile's rays wait while others are evaluated) */
+  int32_t mlp_spec_rows;       /* network hop: rows of a draining pool's tile shared out as windows of cells
+                                  ahead of each ray: 1 (no windows), 8, 16 or 32 (default 32); values and
+                                  steps do not depend on it */
   int32_t reserved[2];
 } gh_tuning;
 

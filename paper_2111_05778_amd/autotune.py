@@ -4,8 +4,10 @@ The library's launch shapes are process-wide (`gh_set_tuning`): lanes per ray
 of the analytic hop and the step budget after which its long rays move to a
 pass of one wave and one window of cells per ray, resident blocks per CU of
 the marching-cubes look-back scans, list entries per thread of the vertex and
-triangle passes, the split policy of network tiles with few rows, and the
-rays per network work item of a batch.  None of them changes a result, only the time.
+triangle passes, and for the network hop the split policy of tiles with few
+rows (waves per group of 32 points), the ray pool of a block (one or two
+tiles of rows) and the rows of a draining tile given out as windows of cells
+ahead of each ray, and the rays per network work item of a batch.  None of them changes a result, only the time.
 
 `tune()` measures a workload on the device under a coordinate descent over
 these shapes: each parameter in turn sweeps its values with the others held
@@ -26,11 +28,13 @@ from . import native as N
 
 # hop_lanes_per_ray 0 lets the library choose from the bound's type groups.
 DEFAULTS = {"hop_lanes_per_ray": 0, "scan_blocks_per_cu": 4, "mlp_split": 3, "batch_rays_per_item": 4096,
-            "mc_items_per_thread": 4, "hop_step_budget": 0}
+            "mc_items_per_thread": 4, "hop_step_budget": 0, "mlp_pool_tiles": 2, "mlp_spec_rows": 32}
 SPACE_PRIMS = {"hop_lanes_per_ray": [0, 1, 2, 3, 4, 8], "hop_step_budget": [0, 32, 64, 128],
                "scan_blocks_per_cu": [1, 2, 4, 8], "mc_items_per_thread": [1, 2, 4, 8]}
-SPACE_MLP = {"mlp_split": [1, 2, 3], "scan_blocks_per_cu": [1, 2, 4, 8], "mc_items_per_thread": [1, 2, 4, 8]}
-SPACE_BATCH = {"batch_rays_per_item": [1024, 2048, 4096, 8192, 16384]}
+SPACE_MLP = {"mlp_split": [1, 2, 3], "mlp_pool_tiles": [1, 2], "mlp_spec_rows": [1, 8, 16, 32],
+             "scan_blocks_per_cu": [1, 2, 4, 8], "mc_items_per_thread": [1, 2, 4, 8]}
+SPACE_BATCH = {"batch_rays_per_item": [1024, 2048, 4096, 8192, 16384], "mlp_pool_tiles": [1, 2],
+               "mlp_spec_rows": [1, 8, 32]}
 
 
 def cache_path():

@@ -21,7 +21,8 @@ static_assert(GH_PRIM_TYPES == gh::kPrimTypes, "record type count of the header 
 namespace {
 
 thread_local std::string g_last_error;
-std::atomic<int> g_hop_lanes{0}, g_scan_blocks{0}, g_batch_rays{0}, g_mlp_split{0}, g_mc_items{0}, g_hop_budget{0};
+std::atomic<int> g_hop_lanes{0}, g_scan_blocks{0}, g_batch_rays{0}, g_mlp_split{0}, g_mc_items{0}, g_hop_budget{0},
+    g_mlp_pool{0}, g_mlp_spec{0};
 
 gh_status fail(gh_status st, const char* fmt, ...) {
   char buf[512];
@@ -237,6 +238,8 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.act_ln2 = m.relu ? 0.f : 0.693147180559945309f;
   m.act_one = m.relu ? 0.f : 1.f;
   m.split = 3;
+  m.pool_tiles = 2;
+  m.spec_rows = gh::kSpecRowsDefault;
   memset(desc_h, 0, sizeof(*desc_h));
   memcpy(desc_h, &d, sizeof(d));
   return GH_OK;
@@ -257,6 +260,9 @@ Tuning current_tuning() {
   t.mc_items_per_thread = mi ? mi : 4;
   const int hb = g_hop_budget.load(std::memory_order_relaxed);
   t.hop_step_budget = hb;  // 0: one pass
+  const int mp = g_mlp_pool.load(std::memory_order_relaxed), msr = g_mlp_spec.load(std::memory_order_relaxed);
+  t.mlp_pool_tiles = mp ? mp : 2;
+  t.mlp_spec_rows = msr ? msr : 32;
   return t;
 }
 }  // namespace gh
@@ -325,6 +331,10 @@ gh_status gh_set_tuning(const gh_tuning* t) {
     return fail(GH_EINVAL, "mc_items_per_thread = %d must be 0, 1, 2, 4 or 8", mi);
   const int hb = t->hop_step_budget;
   if (!(hb >= 0 && hb <= 4096)) return fail(GH_EINVAL, "hop_step_budget = %d must be 0 or 1..4096", hb);
+  const int mp = t->mlp_pool_tiles, msr = t->mlp_spec_rows;
+  if (!(mp >= 0 && mp <= 2)) return fail(GH_EINVAL, "mlp_pool_tiles = %d must be 0, 1 or 2", mp);
+  if (!(msr == 0 || msr == 1 || msr == 8 || msr == 16 || msr == 32))
+    return fail(GH_EINVAL, "mlp_spec_rows = %d must be 0, 1, 8, 16 or 32", msr);
   for (int q = 0; q < 2; ++q)
     if (t->reserved[q] != 0) return fail(GH_EINVAL, "reserved tuning fields must be 0");
   g_hop_lanes.store(r, std::memory_order_relaxed);
@@ -333,6 +343,8 @@ gh_status gh_set_tuning(const gh_tuning* t) {
   g_mlp_split.store(ms, std::memory_order_relaxed);
   g_mc_items.store(mi, std::memory_order_relaxed);
   g_hop_budget.store(hb, std::memory_order_relaxed);
+  g_mlp_pool.store(mp, std::memory_order_relaxed);
+  g_mlp_spec.store(msr, std::memory_order_relaxed);
   return GH_OK;
 }
 
@@ -345,6 +357,8 @@ gh_status gh_get_tuning(gh_tuning* t) {
   t->mlp_split = g_mlp_split.load(std::memory_order_relaxed);
   t->mc_items_per_thread = g_mc_items.load(std::memory_order_relaxed);
   t->hop_step_budget = g_hop_budget.load(std::memory_order_relaxed);
+  t->mlp_pool_tiles = g_mlp_pool.load(std::memory_order_relaxed);
+  t->mlp_spec_rows = g_mlp_spec.load(std::memory_order_relaxed);
   return GH_OK;
 }
 

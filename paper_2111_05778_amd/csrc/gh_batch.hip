@@ -285,10 +285,12 @@ gh_status gh_batch_create(int n_shapes, const gh_batch_item* items_h, void* dev_
   }
   batch_layout(n_shapes, b->n_items, dev_buf, b);
   std::vector<gh::BatchShape> shapes(n_shapes);
-  const int split = gh::current_tuning().mlp_split;
+  const gh::Tuning tu = gh::current_tuning();
   for (int i = 0; i < n_shapes; ++i) {
     shapes[i] = gh::BatchShape{b->sdb[i], b->grids[i], b->ws[i], items_h[i].ctr};
-    shapes[i].sdb.mlp.split = split;
+    shapes[i].sdb.mlp.split = tu.mlp_split;
+    shapes[i].sdb.mlp.pool_tiles = tu.mlp_pool_tiles;
+    shapes[i].sdb.mlp.spec_rows = tu.mlp_spec_rows;
   }
   std::vector<gh::WorkItem> wi(b->n_items);
   for (int i = 0; i < b->n_items; ++i) wi[i] = work[i].second;

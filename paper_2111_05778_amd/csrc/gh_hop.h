@@ -468,8 +468,8 @@ __device__ __forceinline__ float reeval_fp32(const MlpDesc& m, Sm& sm, int* s_cn
   return f;
 }
 
-// A block keeps a pool of 2R rays (one per owner thread), twice a tile of R
-// rows.  Each round it refills finished slots from the ray source
+// A block keeps a pool of up to 2R rays (one per owner thread; the launch
+// shape mlp_pool_tiles picks one or two tiles of R rows).  Each round it refills finished slots from the ray source
 // (rays [first, end) of the column order, taken through src.take), then
 // evaluates one tile:
 //  * normally the current hop points of up to R live rays (R = tile rows),
@@ -483,9 +483,6 @@ __device__ __forceinline__ float reeval_fp32(const MlpDesc& m, Sm& sm, int* s_cn
 // empty FP32 tile in every round that meets one ambiguous value.  The hop
 // rule (Section 3, eq. iter, cell-quantised) is applied to every value used,
 // so the schedule is the FP32 one.
-// Rows of a draining pool's tile, shared out as windows of cells ahead of
-// each ready ray.
-constexpr int kSpecRows = 32;
 
 template <int P, int W, class Src, class Sm>
 __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, uint64_t* __restrict__ colmask,
@@ -494,9 +491,10 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
   constexpr int R = mlp_rows<P>();
   const int n = g.n;
   const size_t ncol = (size_t)n * n;
-  // Two tiles' worth of slots: ready rays fill the tile while others wait for
-  // FP32 values, and the ray queue still balances the work between blocks.
-  const bool owner = (int)threadIdx.x < 2 * R;
+  // Up to two tiles' worth of slots (a launch shape): ready rays fill the
+  // tile while others wait for FP32 values, and the ray queue still balances
+  // the work between blocks.
+  const bool owner = (int)threadIdx.x < (m.pool_tiles == 1 ? 1 : 2) * R;
   const float nf = (float)n;
   bool active = false, pend = false, bad = false;
   size_t col = 0;
@@ -596,7 +594,8 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
     // candidate, or a hop) lands inside that window takes the landing cell's
     // value at once; a value is used only at a cell the ray reaches, so the
     // steps and counts are unchanged.
-    const int D = nrun <= kSpecRows ? kSpecRows / nrun : 1;
+    const int spec = m.spec_rows < R ? m.spec_rows : R;  // rows given out as windows (a launch shape)
+    const int D = nrun <= spec ? spec / nrun : 1;
     if (run) {
 #pragma unroll 1
       for (int t = 0; t < D; ++t) {

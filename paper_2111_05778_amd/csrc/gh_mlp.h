@@ -44,6 +44,7 @@ constexpr int kK0Steps = 7;                // bf16 first layer: 7 k-steps of 16 
 constexpr int kK0Mfma = 16 * kK0Steps;     // (3 + 6F <= 99 features, zero padded)
 constexpr int kK0Store = 8;                // k-steps stored for the first layer (the 8th is zero)
 constexpr int kChunkSteps = 2;             // k-steps per LDS chunk of A fragments
+constexpr int kSpecRowsDefault = 32;       // network hop: rows of a draining tile given out as windows
 constexpr int kStageElems = kChunkSteps * (kMlpMaxK / 32) * 512;  // bf16 per chunk buffer (W = 256)
 
 enum : int { kPrecF32 = 0, kPrecBf16 = 1, kPrecBf16x3 = 2 };
@@ -66,6 +67,8 @@ struct MlpDesc {
   float eps;            // |f_bf16 - f_fp32| bound used by the hop test
   int hop_shrink;       // bf16 hop: 0 FP32 values for ambiguous steps, 1 steps of floor(max(|f| - eps, 0)/h)
   float eps3;           // plain bf16: |f_bf16x3 - f_fp32| bound for two-step corner certification (0: none)
+  int pool_tiles;       // network hop: ray slots of a block, in tiles (launch shape)
+  int spec_rows;        // network hop: rows of a draining tile given out as windows ahead of the rays
 };
 
 // Input feature of a hidden layer (l >= 1) that sits in slot q (0..15) of a

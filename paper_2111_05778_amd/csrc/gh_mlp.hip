@@ -313,7 +313,10 @@ hipError_t launch_mlp(int what, const DevSdb& d0, const Grid& g, const Workspace
                       const float* xyz, float* f, int64_t count, gh_counters* ctr, hipStream_t s) {
   if (d0.kind != GH_SDB_MLP) return hipErrorInvalidValue;
   DevSdb d = d0;
-  d.mlp.split = current_tuning().mlp_split;
+  const Tuning tu = current_tuning();
+  d.mlp.split = tu.mlp_split;
+  d.mlp.pool_tiles = tu.mlp_pool_tiles;
+  d.mlp.spec_rows = tu.mlp_spec_rows;
   switch (d.mlp.precision) {
     case kPrecBf16: return launch_mlp_p<kPrecBf16>(what, d, g, ws, signs, xyz, f, count, ctr, s);
     case kPrecBf16x3: return launch_mlp_p<kPrecBf16x3>(what, d, g, ws, signs, xyz, f, count, ctr, s);

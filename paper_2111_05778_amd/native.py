@@ -59,11 +59,12 @@ class gh_tuning(ctypes.Structure):
     _fields_ = [("hop_lanes_per_ray", ctypes.c_int32), ("scan_blocks_per_cu", ctypes.c_int32),
                 ("batch_rays_per_item", ctypes.c_int32), ("mlp_split", ctypes.c_int32),
                 ("mc_items_per_thread", ctypes.c_int32), ("hop_step_budget", ctypes.c_int32),
+                ("mlp_pool_tiles", ctypes.c_int32), ("mlp_spec_rows", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
 
 
 TUNING_FIELDS = ("hop_lanes_per_ray", "scan_blocks_per_cu", "batch_rays_per_item", "mlp_split", "mc_items_per_thread",
-                 "hop_step_budget")
+                 "hop_step_budget", "mlp_pool_tiles", "mlp_spec_rows")
 
 
 class gh_sdb_desc(ctypes.Structure):
@@ -218,7 +219,7 @@ def gh_bf16_margin(desc, precision, xyz, m, factor, f32, flp, margin, stream=Non
 
 
 def gh_set_tuning(hop_lanes_per_ray=0, scan_blocks_per_cu=0, batch_rays_per_item=0, mlp_split=0,
-                  mc_items_per_thread=0, hop_step_budget=0):
+                  mc_items_per_thread=0, hop_step_budget=0, mlp_pool_tiles=0, mlp_spec_rows=0):
     """Process-wide launch shapes; 0 keeps the built-in choice (see include/gh.h)."""
     t = gh_tuning()
     t.hop_lanes_per_ray = int(hop_lanes_per_ray)
@@ -227,6 +228,8 @@ def gh_set_tuning(hop_lanes_per_ray=0, scan_blocks_per_cu=0, batch_rays_per_item
     t.mlp_split = int(mlp_split)
     t.mc_items_per_thread = int(mc_items_per_thread)
     t.hop_step_budget = int(hop_step_budget)
+    t.mlp_pool_tiles = int(mlp_pool_tiles)
+    t.mlp_spec_rows = int(mlp_spec_rows)
     check(lib.gh_set_tuning(ctypes.byref(t)), "gh_set_tuning")
 
 

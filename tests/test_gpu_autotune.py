@@ -38,11 +38,16 @@ def test_tune_analytic_and_reuse(gh, tmp_path, monkeypatch):
     N.gh_set_tuning()
 
 
-def test_tune_network(gh, tmp_path):
+@pytest.mark.parametrize("prec,hop", [("bf16x3", "fp32"), ("bf16", "shrink")])
+def test_tune_network(gh, tmp_path, prec, hop):
+    # every candidate, the ray pool and tail windows included, must reproduce
+    # the reference counters and triangles bit for bit
     torch, N, P, A = gh
     net = W.neural_scene(0, 64)
-    margin = P.bf16_margin(net, W.probe_points(seed=3, n=65536), "bf16x3")
-    poly = P.Polygonizer(P.Bound.mlp(net, "bf16x3", margin=margin), *W.grid(48))
+    probe = W.probe_points(seed=3, n=65536)
+    margin = P.bf16_margin(net, probe, prec)
+    margin3 = P.bf16_margin(net, probe, "bf16x3") if prec == "bf16" else 0.0
+    poly = P.Polygonizer(P.Bound.mlp(net, prec, margin=margin, hop=hop, margin3=margin3), *W.grid(48))
     poly.run()
     best, ms, trials = A.tune(poly, reps=1, path=str(tmp_path / "t.json"))
     print("network:", best, [(t, m) for t, m in trials], flush=True)
