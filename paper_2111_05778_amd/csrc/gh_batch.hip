@@ -57,7 +57,7 @@ __global__ void k_batch_clear(const BatchShape* __restrict__ shapes, int n_shape
   if (blockIdx.x == 0 && threadIdx.x < 2) head[threadIdx.x] = 0;
   for (int s = blockIdx.x; s < n_shapes; s += gridDim.x) {
     const BatchShape& sh = shapes[s];
-    const size_t nw = (size_t)(sh.ws.tiles_lat + 2 * sh.ws.tiles_cap + sh.ws.tiles_col);
+    const size_t nw = scan_words(sh.ws);
     for (size_t i = threadIdx.x; i < nw; i += blockDim.x) sh.ws.scan[i] = 0;
     if (threadIdx.x < 8) sh.ws.ticket[threadIdx.x] = 0;
     if (threadIdx.x == 0) {

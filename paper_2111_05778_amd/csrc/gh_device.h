@@ -317,7 +317,14 @@ struct ScanOut {
 constexpr int kSpinLimit = 1 << 22;
 constexpr int kLookWindow = kBlock * 4;
 
-__device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* flags, int tile, unsigned int* err) {
+struct NoAggHook {
+  __device__ void operator()(uint64_t) const {}
+};
+
+// on_agg(tile aggregate) runs in thread 0 before the tile publishes it.
+template <class OnAgg = NoAggHook>
+__device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* flags, int tile, unsigned int* err,
+                                                       OnAgg on_agg = OnAgg{}) {
   __shared__ uint64_t s_wave[kBlock / 64];
   __shared__ uint64_t s_sum[kBlock / 64];
   __shared__ int s_first, s_empty;
@@ -333,6 +340,7 @@ __device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* fla
     if (w < wave_id()) wave_off += s;
     agg += s;
   }
+  if (threadIdx.x == 0) on_agg(agg);
   if (tile == 0) {
     if (threadIdx.x == 0)
       __hip_atomic_store(&flags[0], kScanPrefix | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

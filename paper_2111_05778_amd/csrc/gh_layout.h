@@ -44,6 +44,8 @@ struct Workspace {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+constexpr int kPackCounts = 4;  // 64-bit words after the look-back words (see pack_counts)
+
 // Computes the layout; with base == nullptr only the size is produced.
 inline size_t workspace_layout(int n, int64_t cap, void* base, Workspace* ws) {
   const size_t n2 = (size_t)n * n, n1 = (size_t)n + 1, nl = n1 * n1;
@@ -69,7 +71,7 @@ inline size_t workspace_layout(int n, int64_t cap, void* base, Workspace* ws) {
   const size_t o_cand = take((size_t)cap * 8);
   const size_t o_nlist = take(2 * 8);
   const size_t o_park = take(n2 * 6 * 4);
-  const size_t scan_words = (size_t)(tiles_lat + 2 * tiles_cap + tiles_col);
+  const size_t scan_words = (size_t)(tiles_lat + 2 * tiles_cap + tiles_col) + kPackCounts;
   const size_t o_scan = take(scan_words * 8);
   const size_t o_ticket = take(8 * sizeof(unsigned int));
   if (base && ws) {
@@ -104,7 +106,15 @@ __host__ __device__ inline uint64_t* scan_tris(const Workspace& w) { return w.sc
 __host__ __device__ inline uint64_t* scan_cands(const Workspace& w) {
   return w.scan + w.tiles_lat + 2 * w.tiles_cap;
 }
-inline size_t scan_words(const Workspace& w) { return (size_t)(w.tiles_lat + 2 * w.tiles_cap + w.tiles_col); }
+__host__ __device__ inline size_t scan_words(const Workspace& w) {
+  return (size_t)(w.tiles_lat + 2 * w.tiles_cap + w.tiles_col) + kPackCounts;
+}
+// Exact 64-bit totals behind the two packed scans (two 31-bit fields in one
+// word, which a total of 2^31 would carry over): corners, candidates,
+// triangles, cells.  Zero between passes.
+__host__ __device__ inline unsigned long long* pack_counts(const Workspace& w) {
+  return (unsigned long long*)(w.scan + w.tiles_lat + 2 * w.tiles_cap + w.tiles_col);
+}
 
 // List index of corner (L, k), or -1 when (L, k) is not a corner.  The mask
 // and record loads are unconditional and issued together (one memory round

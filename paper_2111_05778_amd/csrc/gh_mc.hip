@@ -50,6 +50,13 @@ __global__ __launch_bounds__(kBlock) void k_candidates(Grid g, Workspace ws, int
   }
 }
 
+// Waits until this thread's device-scope atomic adds are performed, so that
+// the tile's scan word, stored next, is seen only after them (a device-scope
+// fence would also write back the whole L2 at every tile).
+__device__ __forceinline__ void counts_done() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+}
+
 // Zeroes p[0, count) with the whole grid.
 __device__ __forceinline__ void zero_words(uint64_t* __restrict__ p, size_t count) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
@@ -196,12 +203,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     ws.lrec[(size_t)w * nl + L] = cw;  // the word now, its first index in the write pass
     ncorner += __popc(cw);
   });
-  const ScanOut so = block_scan_lookback((ncand << 31) | ncorner, scan_corners(ws), tile, &ctr->flags);
+  // Two 31-bit fields share the scan word.  On grids whose totals can reach
+  // 2^31 ((n + 1)^3 corners), where a carry would spill into the other field,
+  // each tile's own counts (far below 2^31) also go, exact, into 64-bit
+  // totals, which the last tile compares with the scan's.
+  unsigned long long* const pc = pack_counts(ws);
+  const bool exact = (int64_t)n1 * n1 * n1 >= ((int64_t)1 << 31);
+  const ScanOut so = block_scan_lookback((ncand << 31) | ncorner, scan_corners(ws), tile, &ctr->flags,
+                                         [pc, exact](uint64_t agg) {
+                                           if (!exact) return;
+                                           atomicAdd(&pc[0], (unsigned long long)(agg & 0x7fffffffull));
+                                           atomicAdd(&pc[1], (unsigned long long)(agg >> 31));
+                                           counts_done();
+                                         });
   const uint64_t c0 = so.excl & 0x7fffffffull, k0 = so.excl >> 31;
   const uint64_t cbase = so.base & 0x7fffffffull, kbase = so.base >> 31;
+  // a field that wrapped inside this tile: the pass is void (flagged by the
+  // last tile), and this tile writes nothing
+  const bool wrapped = (so.total & 0x7fffffffull) < cbase || (so.total >> 31) < kbase;
   const uint64_t tile_c = (so.total & 0x7fffffffull) - cbase, tile_k = (so.total >> 31) - kbase;
-  const bool stage_c = tile_c <= (uint64_t)kStageCorners, stage_k = tile_k <= (uint64_t)kStageCands;
-  const bool fits = L < nl && c0 + ncorner <= (uint64_t)ws.cap;
+  const bool stage_c = !wrapped && tile_c <= (uint64_t)kStageCorners;
+  const bool stage_k = !wrapped && tile_k <= (uint64_t)kStageCands;
+  const bool fits = !wrapped && L < nl && c0 + ncorner <= (uint64_t)ws.cap;
   int64_t o = (int64_t)c0, oc = (int64_t)k0;
   // A full word (32 consecutive corners, the columns along a wall parallel
   // to them) goes out as 16-byte stores once its position is 4-aligned.
@@ -286,7 +309,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     ws.lmhi[L] = fits ? hi : 0u;
   }
   if (threadIdx.x == 0 && tile == (int)ws.tiles_lat - 1) {
-    const int64_t tc = (int64_t)(so.total & 0x7fffffffull), tk = (int64_t)(so.total >> 31);
+    // every tile added its counts before publishing them, so they are all in
+    int64_t tc = (int64_t)(so.total & 0x7fffffffull), tk = (int64_t)(so.total >> 31);
+    if (exact) {
+      const unsigned long long ec = __hip_atomic_load(&pc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long ek = __hip_atomic_load(&pc[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ec != (unsigned long long)tc || ek != (unsigned long long)tk) {  // carried: at least 2^31 > cap
+        tc = (int64_t)ec;
+        tk = (int64_t)ek;
+        atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+      }
+      __hip_atomic_store(&pc[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // zero for the next pass
+      __hip_atomic_store(&pc[1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     ws.nlist[0] = tc;
     ws.nlist[1] = tk;
     ctr->n_corner = tc;
@@ -598,16 +633,26 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
       // (cells << 31) | triangles: both stay below 2^31 for any mesh the outputs can index
       pack += ((uint64_t)(nt[r] ? 1 : 0) << 31) | nt[r];
     }
-    const ScanOut so = block_scan_lookback(pack, scan_tris(ws), tile, &ctr->flags);
+    // exact 64-bit totals beside the packed scan where the triangles (at
+    // most 5 n^3) can reach 2^31, as in the corner pass
+    unsigned long long* const pc = pack_counts(ws);
+    const bool exact = (int64_t)5 * n * n * n >= ((int64_t)1 << 31);
+    const ScanOut so = block_scan_lookback(pack, scan_tris(ws), tile, &ctr->flags, [pc, exact](uint64_t agg) {
+      if (!exact) return;
+      atomicAdd(&pc[2], (unsigned long long)(agg & 0x7fffffffull));
+      atomicAdd(&pc[3], (unsigned long long)(agg >> 31));
+      counts_done();
+    });
     int64_t t0 = (int64_t)(so.excl & 0x7fffffffull), c = (int64_t)(so.excl >> 31);
     const int64_t tbase = (int64_t)(so.base & 0x7fffffffull), cbase = (int64_t)(so.base >> 31);
     const int64_t tile_t = (int64_t)(so.total & 0x7fffffffull) - tbase;
     const int64_t tile_c = (int64_t)(so.total >> 31) - cbase;
+    const bool wrapped = tile_t < 0 || tile_c < 0;  // a field wrapped here: the pass is void, write nothing
     const bool stage = tile_t <= kStageT;  // the cells always fit: at most one per candidate
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       if (!nt[r]) continue;
-      if (verts_ok) {
+      if (verts_ok && !wrapped) {
         s_cell[c - cbase] = cell[r];
         s_case[c - cbase] = (uint8_t)cs[r];
         if (stage || t0 + (int64_t)nt[r] <= tri_cap) {
@@ -633,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
       ++c;
     }
     __syncthreads();
-    if (verts_ok) {
+    if (verts_ok && !wrapped) {
       if (stage) {
         const int64_t nt3 = 3 * (tbase + tile_t <= tri_cap ? tile_t : (tbase < tri_cap ? tri_cap - tbase : 0));
         for (int64_t i = threadIdx.x; i < nt3; i += kBlock) tris[3 * tbase + i] = s_tri[i];
@@ -645,7 +690,18 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
         for (int64_t i = threadIdx.x; i < nc; i += kBlock) cases[cbase + i] = s_case[i];
     }
     if (threadIdx.x == 0 && tile == ntiles - 1) {
-      const int64_t tt = (int64_t)(so.total & 0x7fffffffull), tc = (int64_t)(so.total >> 31);
+      int64_t tt = (int64_t)(so.total & 0x7fffffffull), tc = (int64_t)(so.total >> 31);
+      if (exact) {
+        const unsigned long long et = __hip_atomic_load(&pc[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long ec = __hip_atomic_load(&pc[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (et != (unsigned long long)tt || ec != (unsigned long long)tc) {  // carried: at least 2^31 > tri_cap
+          tt = (int64_t)et;
+          tc = (int64_t)ec;
+          atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+        }
+        __hip_atomic_store(&pc[2], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // zero for the next pass
+        __hip_atomic_store(&pc[3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       ctr->n_tri = tt;
       ctr->n_cells = tc;
       if (tt > tri_cap || ((cells || cases) && tc > cell_cap)) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
