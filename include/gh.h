@@ -388,7 +388,12 @@ typedef struct {
   int32_t mlp_spec_rows;       /* network hop: rows of a draining pool's tile shared out as windows of cells
                                   ahead of each ray: 1 (no windows), 8, 16 or 32 (default 32); values and
                                   steps do not depend on it */
-  int32_t reserved[2];
+  int32_t mlp_lean_hop;        /* network hop under the shrunk plain bf16 rule (GH_BF16_HOP_SHRINK, which
+                                  never waits for FP32 values): 1 on a lean LDS layout with two blocks per
+                                  CU (default; at width 256 every tile is then split over two waves per
+                                  group, 64 rows), 2 on the full layout with one block per CU; values and
+                                  steps do not depend on it */
+  int32_t reserved;
 } gh_tuning;
 
 /* Replace the process-wide launch shapes; GH_EINVAL for unsupported values. */

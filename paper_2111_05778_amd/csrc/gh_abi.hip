@@ -22,7 +22,7 @@ namespace {
 
 thread_local std::string g_last_error;
 std::atomic<int> g_hop_lanes{0}, g_scan_blocks{0}, g_batch_rays{0}, g_mlp_split{0}, g_mc_items{0}, g_hop_budget{0},
-    g_mlp_pool{0}, g_mlp_spec{0};
+    g_mlp_pool{0}, g_mlp_spec{0}, g_mlp_lean{0};
 
 gh_status fail(gh_status st, const char* fmt, ...) {
   char buf[512];
@@ -263,6 +263,8 @@ Tuning current_tuning() {
   const int mp = g_mlp_pool.load(std::memory_order_relaxed), msr = g_mlp_spec.load(std::memory_order_relaxed);
   t.mlp_pool_tiles = mp ? mp : 2;
   t.mlp_spec_rows = msr ? msr : 32;
+  const int ml = g_mlp_lean.load(std::memory_order_relaxed);
+  t.mlp_lean_hop = ml ? ml : 1;
   return t;
 }
 }  // namespace gh
@@ -335,8 +337,9 @@ gh_status gh_set_tuning(const gh_tuning* t) {
   if (!(mp >= 0 && mp <= 2)) return fail(GH_EINVAL, "mlp_pool_tiles = %d must be 0, 1 or 2", mp);
   if (!(msr == 0 || msr == 1 || msr == 8 || msr == 16 || msr == 32))
     return fail(GH_EINVAL, "mlp_spec_rows = %d must be 0, 1, 8, 16 or 32", msr);
-  for (int q = 0; q < 2; ++q)
-    if (t->reserved[q] != 0) return fail(GH_EINVAL, "reserved tuning fields must be 0");
+  const int ml = t->mlp_lean_hop;
+  if (!(ml >= 0 && ml <= 2)) return fail(GH_EINVAL, "mlp_lean_hop = %d must be 0, 1 or 2", ml);
+  if (t->reserved != 0) return fail(GH_EINVAL, "the reserved tuning field must be 0");
   g_hop_lanes.store(r, std::memory_order_relaxed);
   g_scan_blocks.store(sb, std::memory_order_relaxed);
   g_batch_rays.store(br, std::memory_order_relaxed);
@@ -345,6 +348,7 @@ gh_status gh_set_tuning(const gh_tuning* t) {
   g_hop_budget.store(hb, std::memory_order_relaxed);
   g_mlp_pool.store(mp, std::memory_order_relaxed);
   g_mlp_spec.store(msr, std::memory_order_relaxed);
+  g_mlp_lean.store(ml, std::memory_order_relaxed);
   return GH_OK;
 }
 
@@ -359,6 +363,7 @@ gh_status gh_get_tuning(gh_tuning* t) {
   t->hop_step_budget = g_hop_budget.load(std::memory_order_relaxed);
   t->mlp_pool_tiles = g_mlp_pool.load(std::memory_order_relaxed);
   t->mlp_spec_rows = g_mlp_spec.load(std::memory_order_relaxed);
+  t->mlp_lean_hop = g_mlp_lean.load(std::memory_order_relaxed);
   return GH_OK;
 }
 

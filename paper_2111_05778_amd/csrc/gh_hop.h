@@ -488,7 +488,11 @@ template <int P, int W, class Src, class Sm>
 __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, uint64_t* __restrict__ colmask,
                                              uint32_t* __restrict__ colbits, gh_counters* __restrict__ ctr,
                                              Sm& sm, int* s_cnt, unsigned int* s_base, Src src) {
-  constexpr int R = mlp_rows<P>();
+  constexpr int R = mlp_tile_rows<P, W, Sm>();
+  // The lean layout holds no FP32 activations: it serves the shrunk bf16 hop,
+  // which never waits for an FP32 value.
+  constexpr bool kLean = std::is_same_v<Sm, MlpSmemBf16>;
+  static_assert(!kLean || P == kPrecBf16, "the lean layout runs the plain bf16 evaluator only");
   const int n = g.n;
   const size_t ncol = (size_t)n * n;
   // Up to two tiles' worth of slots (a launch shape): ready rays fill the
@@ -566,27 +570,29 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
     const bool run = ready && row < R;  // the first R ready rays form this round's tile
     nrun = nrun < R ? nrun : R;
     int prow = 0;
-    if constexpr (P != kPrecF32) prow = block_rank(owner && active && pend, s_cnt, npend);
+    if constexpr (P != kPrecF32 && !kLean) prow = block_rank(owner && active && pend, s_cnt, npend);
     if (nrun == 0 && npend == 0) break;  // uniform: the queue is empty and every slot is idle
     const float z = centroid(g, k);
-    if (npend >= kF32Rows || nrun == 0) {
-      // FP32 values for up to kF32Rows waiting rays
-      const bool mine = owner && active && pend && prow < kF32Rows;
-      if (mine) {
-        sm.pts[prow][0] = x;
-        sm.pts[prow][1] = y;
-        sm.pts[prow][2] = z;
+    if constexpr (!kLean) {
+      if (npend >= kF32Rows || nrun == 0) {
+        // FP32 values for up to kF32Rows waiting rays
+        const bool mine = owner && active && pend && prow < kF32Rows;
+        if (mine) {
+          sm.pts[prow][0] = x;
+          sm.pts[prow][1] = y;
+          sm.pts[prow][2] = z;
+        }
+        __syncthreads();
+        mlp_tile<kPrecF32, W>(m, sm, npend < kF32Rows ? npend : kF32Rows);
+        const float d = mine ? fabsf(sm.f[prow]) : 0.f;
+        __syncthreads();
+        if (mine) {
+          ++reevals;
+          pend = false;
+          advance(d);
+        }
+        continue;
       }
-      __syncthreads();
-      mlp_tile<kPrecF32, W>(m, sm, npend < kF32Rows ? npend : kF32Rows);
-      const float d = mine ? fabsf(sm.f[prow]) : 0.f;
-      __syncthreads();
-      if (mine) {
-        ++reevals;
-        pend = false;
-        advance(d);
-      }
-      continue;
     }
     // Few ready rays (the pool draining): each also gets rows for its next
     // cells k + 1, ..., k + D - 1, filling a 32-row tile, which takes as long
@@ -613,7 +619,7 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
         float d = fabsf(sm.f[row * D + (k - k0)]);
         bool amb = false;
         if constexpr (P != kPrecF32) {
-          if (m.hop_shrink) {
+          if (kLean || m.hop_shrink) {
             // |f| - eps bounds |f_fp32| from below: the step is safe as it is
             // (a non-finite value stays non-finite)
             d = d <= FLT_MAX ? fmaxf(d - m.eps, 0.f) : d;

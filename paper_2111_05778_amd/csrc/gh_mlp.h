@@ -108,6 +108,29 @@ struct MlpSmem {
   float part[4][kBf16Rows];
 };
 
+// The plain bf16 register evaluator's part alone (hi fragments only, no FP32
+// activations): about half of MlpSmem, so that two blocks fit one CU, for
+// kernels that never run the FP32 or the split evaluator.
+struct MlpSmemBf16 {
+  uint16_t stage[2][1][kStageElems];
+  uint4 xch[2][1][kMlpMaxK / 16][64];
+  float pts[kBf16Rows][3];
+  float f[kBf16Rows];
+  float part[4][kBf16Rows];
+};
+
+// On the lean layout the widest network runs every tile split over two or
+// more waves per group (at most 64 rows), so that a wave holds half of a
+// layer's accumulators and two waves fit one SIMD.
+template <int W, class Sm>
+__host__ __device__ constexpr bool mlp_split_only() {
+  return std::is_same_v<Sm, MlpSmemBf16> && W == kMlpMaxK;
+}
+template <int P, int W, class Sm>
+__host__ __device__ constexpr int mlp_tile_rows() {
+  return mlp_split_only<W, Sm>() ? 64 : (P == kPrecF32 ? kF32Rows : kBf16Rows);
+}
+
 // The FP32 evaluator's part alone (for kernels that never run the register
 // evaluator).
 struct MlpSmemF32 {
@@ -408,7 +431,8 @@ template <int P, int W>
 struct ChunkDma {
   static constexpr int kPieces = kChunkSteps * (W / 32) / 4;  // 16-byte pieces per thread per part
   // Issues the copy of one chunk (hi and, for BF16x3, lo parts) into buffer buf.
-  __device__ static void issue(const uint16_t* __restrict__ ghi, const uint16_t* __restrict__ glo, MlpSmem& sm,
+  template <class Sm>
+  __device__ static void issue(const uint16_t* __restrict__ ghi, const uint16_t* __restrict__ glo, Sm& sm,
                                int buf) {
     const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -437,8 +461,8 @@ struct ChunkDma {
 // null.  Every wave of the block runs the same copies and barriers; with
 // kActive false a wave only helps with the copies.  For the first layer
 // (kFeat) the B fragments are the features, computed chunk by chunk.
-template <int P, int W, int NT, int NS, bool kFeat, bool kActive>
-__device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, MlpSmem& sm, int c0, const uint16_t* __restrict__ hi,
+template <int P, int W, int NT, int NS, bool kFeat, bool kActive, class Sm>
+__device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, Sm& sm, int c0, const uint16_t* __restrict__ hi,
                                               const uint16_t* __restrict__ lo, const uint16_t* __restrict__ next_hi,
                                               const uint16_t* __restrict__ next_lo, f32x16_t (&acc)[NT],
                                               const bf16x8_t (&x)[W / 16], const bf16x8_t (&xl)[W / 16], float px,
@@ -462,10 +486,11 @@ __device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, MlpSmem& sm, int
     __builtin_amdgcn_sched_barrier(0);  // the copy starts before this chunk's products
     if constexpr (kActive) {
       const bf16x8_t* __restrict__ sa = reinterpret_cast<const bf16x8_t*>(sm.stage[cur][0]);
-      const bf16x8_t* __restrict__ sal = reinterpret_cast<const bf16x8_t*>(sm.stage[cur][1]);
+      const bf16x8_t* __restrict__ sal = sa;  // the lo parts (BF16x3 only)
+      if constexpr (P == kPrecBf16x3) sal = reinterpret_cast<const bf16x8_t*>(sm.stage[cur][1]);
       // Read the fragments of FS k-steps at once, then multiply: the reads
       // return in order, so each product waits only for its own fragment.
-      constexpr int FS = P == kPrecBf16x3 ? 1 : kChunkSteps;
+      constexpr int FS = P == kPrecBf16x3 || mlp_split_only<W, Sm>() ? 1 : kChunkSteps;
 #pragma unroll
       for (int u0 = 0; u0 < kChunkSteps; u0 += FS) {
         bf16x8_t fa[FS][NT], fl[FS][NT];
@@ -510,8 +535,8 @@ __device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, MlpSmem& sm, int
 // waves of its group through LDS and takes theirs (S > 1 only).  The chunk
 // barriers of the following layer keep the next exchange from overwriting
 // the buffer before every wave has read it.
-template <int P, int W, int NT>
-__device__ __forceinline__ void mlp_exchange(MlpSmem& sm, int grp, int c0, const bf16x8_t (&xo)[2 * NT],
+template <int P, int W, int NT, class Sm>
+__device__ __forceinline__ void mlp_exchange(Sm& sm, int grp, int c0, const bf16x8_t (&xo)[2 * NT],
                                              const bf16x8_t (&xol)[2 * NT], bf16x8_t (&x)[W / 16],
                                              bf16x8_t (&xl)[W / 16]) {
   const int lane = threadIdx.x & 63;
@@ -533,8 +558,8 @@ __device__ __forceinline__ void mlp_exchange(MlpSmem& sm, int grp, int c0, const
 // W/32/S of the m-tiles of every layer.  Lanes l and l + 32 both pass point
 // l % 32 and both receive its part.  Every wave of the block must call it
 // with the same S (barriers inside), active or not.
-template <int P, int W, int S, bool kActive>
-__device__ __forceinline__ float mlp_wave(const MlpDesc& m, MlpSmem& sm, float px, float py, float pz) {
+template <int P, int W, int S, bool kActive, class Sm>
+__device__ __forceinline__ float mlp_wave(const MlpDesc& m, Sm& sm, float px, float py, float pz) {
   constexpr int KS = W / 16, NT = W / 32 / S;
   const int w = threadIdx.x >> 6;
   const int grp = w / S, c0 = (w % S) * NT;
@@ -571,8 +596,8 @@ __device__ __forceinline__ float mlp_wave(const MlpDesc& m, MlpSmem& sm, float p
 }
 
 // Tile of nrows points with S waves per group of 32 points (4 / S groups).
-template <int P, int W, int S>
-__device__ __forceinline__ void mlp_tile_split(const MlpDesc& m, MlpSmem& sm, int nrows) {
+template <int P, int W, int S, class Sm>
+__device__ __forceinline__ void mlp_tile_split(const MlpDesc& m, Sm& sm, int nrows) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = w / S;
   const int row = 32 * grp + (lane & 31);
@@ -608,12 +633,18 @@ __device__ __forceinline__ void mlp_tile_split(const MlpDesc& m, MlpSmem& sm, in
 
 // A tile with few rows spreads each group's layers over more waves: the
 // round takes about as long as the largest share of one wave.
-template <int P, int W>
-__device__ __forceinline__ void mlp_tile_reg(const MlpDesc& m, MlpSmem& sm, int nrows) {
+template <int P, int W, class Sm>
+__device__ __forceinline__ void mlp_tile_reg(const MlpDesc& m, Sm& sm, int nrows) {
   constexpr int kS4 = W / 32 >= 4 ? 4 : W / 32;  // at least one m-tile per wave
-  if (m.split >= 2 && nrows <= 32) mlp_tile_split<P, W, kS4>(m, sm, nrows);
-  else if (m.split >= 3 && nrows <= 64) mlp_tile_split<P, W, 2>(m, sm, nrows);
-  else mlp_tile_split<P, W, 1>(m, sm, nrows);
+  if constexpr (mlp_split_only<W, Sm>()) {
+    // nrows <= 64: every layer is split over two or four waves per group
+    if (m.split >= 2 && nrows <= 32) mlp_tile_split<P, W, kS4>(m, sm, nrows);
+    else mlp_tile_split<P, W, 2>(m, sm, nrows);
+  } else {
+    if (m.split >= 2 && nrows <= 32) mlp_tile_split<P, W, kS4>(m, sm, nrows);
+    else if (m.split >= 3 && nrows <= 64) mlp_tile_split<P, W, 2>(m, sm, nrows);
+    else mlp_tile_split<P, W, 1>(m, sm, nrows);
+  }
 }
 
 // Evaluates f at sm.pts[0, nrows) into sm.f[0, nrows) (nrows <= mlp_rows<P>);

@@ -253,6 +253,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
   hop_mlp_pool<P, W>(m, g, colmask, colbits, ctr, sm, s_cnt, &s_base, QueueRays{queue, 0, (int64_t)g.n * g.n});
 }
 
+// The shrunk plain bf16 hop on the lean LDS layout (no FP32 activations, no
+// lo fragments): two blocks share a CU, so one wave's epilogue can issue
+// while the other wave of its SIMD runs products.  At W = 256 a wave with
+// all eight m-tiles of its 32 points would need more registers than two
+// waves per SIMD leave, so there every tile is split over two waves per
+// group (64 rows per tile; mlp_split_only).
+template <int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hop_mlp_lean(
+    MlpDesc m, Grid g, uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits, unsigned int* __restrict__ queue,
+    gh_counters* __restrict__ ctr) {
+  __shared__ MlpSmemBf16 sm;
+  __shared__ int s_cnt[kBlock / 64];
+  __shared__ unsigned int s_base;
+  hop_mlp_pool<kPrecBf16, W>(m, g, colmask, colbits, ctr, sm, s_cnt, &s_base, QueueRays{queue, 0, (int64_t)g.n * g.n});
+}
+
 // ================================================================ launchers
 template <class K>
 static int mlp_grid(K kernel, int64_t tiles) {
@@ -289,6 +305,10 @@ static hipError_t launch_mlp_w(int what, const DevSdb& d, const Grid& g, const W
     }
     case 3: {  // hop
       auto k = k_hop_mlp<P, W>;
+      // the shrunk plain bf16 hop never waits for FP32 values: by default it
+      // runs on the lean layout, two blocks per CU
+      if constexpr (P == kPrecBf16)
+        if (d.mlp.hop_shrink && current_tuning().mlp_lean_hop == 1) k = k_hop_mlp_lean<W>;
       const int64_t rays = (int64_t)g.n * g.n;
       hipLaunchKernelGGL(k, dim3(mlp_grid(k, (rays + R - 1) / R)), dim3(kBlock), 0, s, d.mlp, g, ws->colmask,
                          ws->colbits, &ws->ticket[kTicketRays], ctr);

@@ -90,18 +90,21 @@ def test_set_tuning_validates_and_round_trips():
     old = N.gh_get_tuning()
     try:
         N.gh_set_tuning(hop_lanes_per_ray=2, scan_blocks_per_cu=8, batch_rays_per_item=1024, mlp_split=1,
-                        mc_items_per_thread=2, hop_step_budget=48, mlp_pool_tiles=1, mlp_spec_rows=8)
+                        mc_items_per_thread=2, hop_step_budget=48, mlp_pool_tiles=1, mlp_spec_rows=8,
+                        mlp_lean_hop=2)
         assert N.gh_get_tuning() == {"hop_lanes_per_ray": 2, "scan_blocks_per_cu": 8,
                                      "batch_rays_per_item": 1024, "mlp_split": 1, "mc_items_per_thread": 2,
-                                     "hop_step_budget": 48, "mlp_pool_tiles": 1, "mlp_spec_rows": 8}
+                                     "hop_step_budget": 48, "mlp_pool_tiles": 1, "mlp_spec_rows": 8,
+                                     "mlp_lean_hop": 2}
         for bad in ({"hop_lanes_per_ray": 5}, {"scan_blocks_per_cu": 16}, {"batch_rays_per_item": 1000},
                     {"batch_rays_per_item": 128}, {"mlp_split": 4}, {"mlp_split": -1},
                     {"mc_items_per_thread": 3}, {"hop_step_budget": -1}, {"hop_step_budget": 4097},
-                    {"mlp_pool_tiles": 3}, {"mlp_spec_rows": 4}, {"mlp_spec_rows": 64}):
+                    {"mlp_pool_tiles": 3}, {"mlp_spec_rows": 4}, {"mlp_spec_rows": 64},
+                    {"mlp_lean_hop": 3}, {"mlp_lean_hop": -1}):
             with pytest.raises(N.GhError):
                 N.gh_set_tuning(**bad)
         t = N.gh_tuning()
-        t.reserved[0] = 1
+        t.reserved = 1
         assert N.lib.gh_set_tuning(ctypes.byref(t)) == N.GH_EINVAL
     finally:
         N.gh_set_tuning(**old)

@@ -255,8 +255,8 @@ def test_value_does_not_depend_on_tile_fill(gh, prec, width):
         np.testing.assert_array_equal(part.view(np.uint32), full[:n].view(np.uint32), err_msg=f"n={n}")
 
 
-@pytest.mark.parametrize("prec,width,n", [("bf16", 64, 77), ("bf16", 256, 128), ("bf16", 256, 512),
-                                          ("bf16x3", 256, 512)])
+@pytest.mark.parametrize("prec,width,n", [("bf16", 64, 77), ("bf16", 128, 100), ("bf16", 256, 128),
+                                          ("bf16", 256, 512), ("bf16x3", 256, 512)])
 def test_shrunk_bf16_hop_gives_the_fp32_mesh(gh, prec, width, n):
     """The bf16 hop without FP32 re-evaluation (steps of
     floor(max(|f| - eps, 0)/h)): every sign-change cell of the FP32 path is a
@@ -277,6 +277,31 @@ def test_shrunk_bf16_hop_gives_the_fp32_mesh(gh, prec, width, n):
     for key in ("cells", "cases", "edge", "tri_e"):
         np.testing.assert_array_equal(a[key], b[key])
     assert cb["n_hop_evals"] >= 0.9 * ca["n_hop_evals"]
+
+
+@pytest.mark.parametrize("width,n", [(64, 77), (128, 100), (256, 128), (256, 512)])
+def test_lean_hop_layout_changes_nothing(gh, width, n):
+    # the shrunk plain bf16 hop on the lean layout (two blocks per CU, at
+    # width 256 every tile split over two waves per group) and on the full
+    # layout: the same counters, candidates, vertices and triangles
+    native, P = gh
+    net = W.neural_scene(0, width)
+    probe = W.probe_points(seed=3, n=65536)
+    b = P.Bound.mlp(net, "bf16", margin=P.bf16_margin(net, probe, "bf16"), hop="shrink",
+                    margin3=P.bf16_margin(net, probe, "bf16x3"))
+    g = W.grid(n)
+    old = native.gh_get_tuning()
+    try:
+        native.gh_set_tuning(**{**old, "mlp_lean_hop": 1})
+        lean = _run(gh, b, *g)
+        native.gh_set_tuning(**{**old, "mlp_lean_hop": 2})
+        full = _run(gh, b, *g)
+    finally:
+        native.gh_set_tuning(**old)
+    assert lean["ctr"] == full["ctr"] and lean["ctr"]["flags"] == 0
+    for key in ("cand", "cells", "cases", "edge", "tris"):
+        np.testing.assert_array_equal(lean[key], full[key])
+    np.testing.assert_array_equal(lean["verts"].view(np.uint64), full["verts"].view(np.uint64))
 
 
 @pytest.mark.parametrize("n", [128, 512])

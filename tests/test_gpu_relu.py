@@ -61,6 +61,25 @@ def test_bf16_takes_the_fp32_schedule_and_signs(gh, net, prec, n):
         np.testing.assert_array_equal(a[key], b[key])
 
 
+@pytest.mark.parametrize("n", [64, 128, 256])
+def test_shrunk_bf16_hop_gives_the_fp32_mesh(gh, net, n):
+    # plain bf16 with steps of floor(max(|f| - eps, 0)/h) and two-step corner
+    # certification: the FP32 path's sign-change cells are all candidates,
+    # and cells, cases, edges and triangles are the FP32 path's
+    native, P = gh
+    probe = W.probe_points(seed=3, n=65536)
+    eps, eps3 = P.bf16_margin(net, probe, "bf16"), P.bf16_margin(net, probe, "bf16x3")
+    g = W.grid(n)
+    a = _run(gh, P.Bound.mlp(net, "fp32"), *g)
+    b = _run(gh, P.Bound.mlp(net, "bf16", margin=eps, hop="shrink", margin3=eps3), *g)
+    print(f"n {n}: eps {eps:.2e}, hop evals fp32 {a['ctr']['n_hop_evals']} shrink {b['ctr']['n_hop_evals']}, "
+          f"candidates {a['ctr']['n_cand']} / {b['ctr']['n_cand']}", flush=True)
+    assert b["ctr"]["flags"] == 0
+    assert np.all(np.isin(a["cells"], b["cand"]))
+    for key in ("cells", "cases", "edge", "tri_e"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
 @pytest.mark.parametrize("n", [64, 128])
 def test_fp32_mesh_matches_fp64_oracle(gh, net, n):
     """The FP32 cells equal the FP64 oracle's once cells with a corner closer
