@@ -388,11 +388,12 @@ typedef struct {
   int32_t mlp_spec_rows;       /* network hop: rows of a draining pool's tile shared out as windows of cells
                                   ahead of each ray: 1 (no windows), 8, 16 or 32 (default 32); values and
                                   steps do not depend on it */
-  int32_t mlp_lean_hop;        /* network hop under the shrunk plain bf16 rule (GH_BF16_HOP_SHRINK, which
-                                  never waits for FP32 values): 1 on a lean LDS layout with two blocks per
-                                  CU (default; at width 256 every tile is then split over two waves per
-                                  group, 64 rows), 2 on the full layout with one block per CU; values and
-                                  steps do not depend on it */
+  int32_t mlp_lean;            /* plain bf16 networks: 1 (default) runs the shrunk hop (GH_BF16_HOP_SHRINK,
+                                  which never waits for FP32 values) and the corner values on a lean LDS
+                                  layout with two blocks per CU (at width 256 every tile is then split
+                                  over two waves per group, 64 rows), the corner certification as a pass
+                                  of its own; 2 runs both on the full layout, one block per CU; values,
+                                  steps and signs do not depend on it */
   int32_t reserved;
 } gh_tuning;
 

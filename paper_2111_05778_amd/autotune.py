@@ -29,10 +29,11 @@ from . import native as N
 # hop_lanes_per_ray 0 lets the library choose from the bound's type groups.
 DEFAULTS = {"hop_lanes_per_ray": 0, "scan_blocks_per_cu": 4, "mlp_split": 3, "batch_rays_per_item": 4096,
             "mc_items_per_thread": 4, "hop_step_budget": 0, "mlp_pool_tiles": 2, "mlp_spec_rows": 32,
-            "mlp_lean_hop": 1}
+            "mlp_lean": 1}
 SPACE_PRIMS = {"hop_lanes_per_ray": [0, 1, 2, 3, 4, 8], "hop_step_budget": [0, 32, 64, 128],
                "scan_blocks_per_cu": [1, 2, 4, 8], "mc_items_per_thread": [1, 2, 4, 8]}
-SPACE_MLP = {"mlp_split": [1, 2, 3], "mlp_pool_tiles": [1, 2], "mlp_spec_rows": [1, 8, 16, 32], "mlp_lean_hop": [1, 2],
+SPACE_MLP = {"mlp_split": [1, 2, 3], "mlp_pool_tiles": [1, 2], "mlp_spec_rows": [1, 8, 16, 32],
+             "mlp_lean": [1, 2],
              "scan_blocks_per_cu": [1, 2, 4, 8], "mc_items_per_thread": [1, 2, 4, 8]}
 SPACE_BATCH = {"batch_rays_per_item": [1024, 2048, 4096, 8192, 16384], "mlp_pool_tiles": [1, 2],
                "mlp_spec_rows": [1, 8, 32]}

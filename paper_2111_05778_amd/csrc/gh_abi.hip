@@ -264,7 +264,7 @@ Tuning current_tuning() {
   t.mlp_pool_tiles = mp ? mp : 2;
   t.mlp_spec_rows = msr ? msr : 32;
   const int ml = g_mlp_lean.load(std::memory_order_relaxed);
-  t.mlp_lean_hop = ml ? ml : 1;
+  t.mlp_lean = ml ? ml : 1;
   return t;
 }
 }  // namespace gh
@@ -337,8 +337,8 @@ gh_status gh_set_tuning(const gh_tuning* t) {
   if (!(mp >= 0 && mp <= 2)) return fail(GH_EINVAL, "mlp_pool_tiles = %d must be 0, 1 or 2", mp);
   if (!(msr == 0 || msr == 1 || msr == 8 || msr == 16 || msr == 32))
     return fail(GH_EINVAL, "mlp_spec_rows = %d must be 0, 1, 8, 16 or 32", msr);
-  const int ml = t->mlp_lean_hop;
-  if (!(ml >= 0 && ml <= 2)) return fail(GH_EINVAL, "mlp_lean_hop = %d must be 0, 1 or 2", ml);
+  const int ml = t->mlp_lean;
+  if (!(ml >= 0 && ml <= 2)) return fail(GH_EINVAL, "mlp_lean = %d must be 0, 1 or 2", ml);
   if (t->reserved != 0) return fail(GH_EINVAL, "the reserved tuning field must be 0");
   g_hop_lanes.store(r, std::memory_order_relaxed);
   g_scan_blocks.store(sb, std::memory_order_relaxed);
@@ -363,7 +363,7 @@ gh_status gh_get_tuning(gh_tuning* t) {
   t->hop_step_budget = g_hop_budget.load(std::memory_order_relaxed);
   t->mlp_pool_tiles = g_mlp_pool.load(std::memory_order_relaxed);
   t->mlp_spec_rows = g_mlp_spec.load(std::memory_order_relaxed);
-  t->mlp_lean_hop = g_mlp_lean.load(std::memory_order_relaxed);
+  t->mlp_lean = g_mlp_lean.load(std::memory_order_relaxed);
   return GH_OK;
 }
 

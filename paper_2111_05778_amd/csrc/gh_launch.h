@@ -15,7 +15,7 @@ struct Tuning {
   int hop_lanes_per_ray, scan_blocks_per_cu, batch_rays_per_item, mlp_split, mc_items_per_thread;
   int hop_step_budget;  // 0: no hand-over to the long-ray pass
   int mlp_pool_tiles, mlp_spec_rows;
-  int mlp_lean_hop;  // 1 lean layout for the shrunk plain bf16 hop, 2 full layout
+  int mlp_lean;  // plain bf16 shrunk hop and corner values: 1 lean layout, 2 full layout
 };
 Tuning current_tuning();
 

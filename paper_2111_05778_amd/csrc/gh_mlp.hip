@@ -95,10 +95,12 @@ __device__ __forceinline__ void corners_split(const MlpDesc& m, const Grid& g, c
 // those corners are collected per block and evaluated in full FP32 tiles.
 // Plain bf16 with eps3 > 0 certifies in two steps: such a corner first gets
 // a split-bf16 value (full tiles of kBf16Rows), and only one within eps3 of
-// zero goes on to FP32.
-template <int P, int W>
+// zero goes on to FP32.  With kStored the bf16 values are already in the
+// corner list (k_mlp_corners_lean) and this pass only certifies.
+template <int P, int W, bool kStored = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_mlp_corners(
     MlpDesc m, Grid g, Workspace ws, gh_counters* __restrict__ ctr) {
+  static_assert(!kStored || P == kPrecBf16, "stored values are plain bf16 ones");
   __shared__ MlpSmemFor<P> sm;
   __shared__ int s_cnt[kBlock / 64];
   __shared__ int64_t s_idx[kF32Rows + kBf16Rows];  // waiting for FP32: < kF32Rows + one tile's worth
@@ -115,17 +117,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     const int64_t i0 = tile * R;
     const int nrows = (int)(count - i0 < R ? count - i0 : R);
     const bool mine = (int)threadIdx.x < nrows;
-    if (mine) {
-      const int64_t i = i0 + threadIdx.x;
-      const int L = ws.cl[i], a = L / n1, b = L - a * n1;
-      sm.pts[threadIdx.x][0] = lattice(g, a);
-      sm.pts[threadIdx.x][1] = lattice(g, b);
-      sm.pts[threadIdx.x][2] = lattice(g, ws.ck[i]);
+    float f = 0.f;
+    if constexpr (kStored) {
+      if (mine) f = ws.cf[i0 + threadIdx.x];
+    } else {
+      if (mine) {
+        const int64_t i = i0 + threadIdx.x;
+        const int L = ws.cl[i], a = L / n1, b = L - a * n1;
+        sm.pts[threadIdx.x][0] = lattice(g, a);
+        sm.pts[threadIdx.x][1] = lattice(g, b);
+        sm.pts[threadIdx.x][2] = lattice(g, ws.ck[i]);
+      }
+      __syncthreads();
+      mlp_tile<P, W>(m, sm, nrows);
+      f = mine ? sm.f[threadIdx.x] : 0.f;
+      __syncthreads();
     }
-    __syncthreads();
-    mlp_tile<P, W>(m, sm, nrows);
-    const float f = mine ? sm.f[threadIdx.x] : 0.f;
-    __syncthreads();
     if constexpr (P != kPrecF32) {
       const bool amb = mine && fabsf(f) < m.eps;
       int namb;
@@ -142,7 +149,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         if (amb) s_idx[npend + r] = i0 + threadIdx.x;
         npend += namb;
       }
-      if (!amb && mine) ws.cf[i0 + threadIdx.x] = f;
+      if (!kStored && !amb && mine) ws.cf[i0 + threadIdx.x] = f;
       __syncthreads();
       if constexpr (P == kPrecBf16) {
         while (npend3 >= kBf16Rows) {  // each split tile adds at most kBf16Rows to a queue below kF32Rows
@@ -175,6 +182,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
       reevals += threadIdx.x == 0 ? c : 0;
     }
     block_add_u64(reevals, (unsigned long long*)&ctr->n_reeval);
+  }
+}
+
+// Plain bf16 values of every corner of the list on the lean layout (two
+// blocks per CU); k_mlp_corners<kPrecBf16, W, true> then certifies the
+// signs of those within eps of zero.
+template <int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_corners_lean(
+    MlpDesc m, Grid g, Workspace ws) {
+  __shared__ MlpSmemBf16 sm;
+  constexpr int R = mlp_tile_rows<kPrecBf16, W, MlpSmemBf16>();
+  const int64_t count = ws.nlist[0];
+  if (count > ws.cap) return;
+  const int n1 = g.n + 1;
+  const int64_t tiles = (count + R - 1) / R;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t i0 = tile * R;
+    const int nrows = (int)(count - i0 < R ? count - i0 : R);
+    const bool mine = (int)threadIdx.x < nrows;
+    if (mine) {
+      const int64_t i = i0 + threadIdx.x;
+      const int L = ws.cl[i], a = L / n1, b = L - a * n1;
+      sm.pts[threadIdx.x][0] = lattice(g, a);
+      sm.pts[threadIdx.x][1] = lattice(g, b);
+      sm.pts[threadIdx.x][2] = lattice(g, ws.ck[i]);
+    }
+    __syncthreads();
+    mlp_tile<kPrecBf16, W>(m, sm, nrows);
+    if (mine) ws.cf[i0 + threadIdx.x] = sm.f[threadIdx.x];
+    __syncthreads();
   }
 }
 
@@ -291,6 +328,16 @@ static hipError_t launch_mlp_w(int what, const DevSdb& d, const Grid& g, const W
       break;
     }
     case 1: {  // corners
+      if constexpr (P == kPrecBf16) {
+        if (current_tuning().mlp_lean == 1) {  // all values on the lean layout, then the certification
+          constexpr int RL = mlp_tile_rows<kPrecBf16, W, MlpSmemBf16>();
+          auto ka = k_mlp_corners_lean<W>;
+          hipLaunchKernelGGL(ka, dim3(mlp_grid(ka, (ws->cap + RL - 1) / RL)), dim3(kBlock), 0, s, d.mlp, g, *ws);
+          auto kb = k_mlp_corners<P, W, true>;
+          hipLaunchKernelGGL(kb, dim3(mlp_grid(kb, (ws->cap + R - 1) / R)), dim3(kBlock), 0, s, d.mlp, g, *ws, ctr);
+          break;
+        }
+      }
       auto k = k_mlp_corners<P, W>;
       hipLaunchKernelGGL(k, dim3(mlp_grid(k, (ws->cap + R - 1) / R)), dim3(kBlock), 0, s, d.mlp, g, *ws, ctr);
       break;
@@ -308,7 +355,7 @@ static hipError_t launch_mlp_w(int what, const DevSdb& d, const Grid& g, const W
       // the shrunk plain bf16 hop never waits for FP32 values: by default it
       // runs on the lean layout, two blocks per CU
       if constexpr (P == kPrecBf16)
-        if (d.mlp.hop_shrink && current_tuning().mlp_lean_hop == 1) k = k_hop_mlp_lean<W>;
+        if (d.mlp.hop_shrink && current_tuning().mlp_lean == 1) k = k_hop_mlp_lean<W>;
       const int64_t rays = (int64_t)g.n * g.n;
       hipLaunchKernelGGL(k, dim3(mlp_grid(k, (rays + R - 1) / R)), dim3(kBlock), 0, s, d.mlp, g, ws->colmask,
                          ws->colbits, &ws->ticket[kTicketRays], ctr);

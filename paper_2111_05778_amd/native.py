@@ -60,11 +60,11 @@ class gh_tuning(ctypes.Structure):
                 ("batch_rays_per_item", ctypes.c_int32), ("mlp_split", ctypes.c_int32),
                 ("mc_items_per_thread", ctypes.c_int32), ("hop_step_budget", ctypes.c_int32),
                 ("mlp_pool_tiles", ctypes.c_int32), ("mlp_spec_rows", ctypes.c_int32),
-                ("mlp_lean_hop", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("mlp_lean", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 TUNING_FIELDS = ("hop_lanes_per_ray", "scan_blocks_per_cu", "batch_rays_per_item", "mlp_split", "mc_items_per_thread",
-                 "hop_step_budget", "mlp_pool_tiles", "mlp_spec_rows", "mlp_lean_hop")
+                 "hop_step_budget", "mlp_pool_tiles", "mlp_spec_rows", "mlp_lean")
 
 
 class gh_sdb_desc(ctypes.Structure):
@@ -220,7 +220,7 @@ def gh_bf16_margin(desc, precision, xyz, m, factor, f32, flp, margin, stream=Non
 
 def gh_set_tuning(hop_lanes_per_ray=0, scan_blocks_per_cu=0, batch_rays_per_item=0, mlp_split=0,
                   mc_items_per_thread=0, hop_step_budget=0, mlp_pool_tiles=0, mlp_spec_rows=0,
-                  mlp_lean_hop=0):
+                  mlp_lean=0):
     """Process-wide launch shapes; 0 keeps the built-in choice (see include/gh.h)."""
     t = gh_tuning()
     t.hop_lanes_per_ray = int(hop_lanes_per_ray)
@@ -231,7 +231,7 @@ def gh_set_tuning(hop_lanes_per_ray=0, scan_blocks_per_cu=0, batch_rays_per_item
     t.hop_step_budget = int(hop_step_budget)
     t.mlp_pool_tiles = int(mlp_pool_tiles)
     t.mlp_spec_rows = int(mlp_spec_rows)
-    t.mlp_lean_hop = int(mlp_lean_hop)
+    t.mlp_lean = int(mlp_lean)
     check(lib.gh_set_tuning(ctypes.byref(t)), "gh_set_tuning")
 
 

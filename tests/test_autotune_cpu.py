@@ -91,16 +91,16 @@ def test_set_tuning_validates_and_round_trips():
     try:
         N.gh_set_tuning(hop_lanes_per_ray=2, scan_blocks_per_cu=8, batch_rays_per_item=1024, mlp_split=1,
                         mc_items_per_thread=2, hop_step_budget=48, mlp_pool_tiles=1, mlp_spec_rows=8,
-                        mlp_lean_hop=2)
+                        mlp_lean=2)
         assert N.gh_get_tuning() == {"hop_lanes_per_ray": 2, "scan_blocks_per_cu": 8,
                                      "batch_rays_per_item": 1024, "mlp_split": 1, "mc_items_per_thread": 2,
                                      "hop_step_budget": 48, "mlp_pool_tiles": 1, "mlp_spec_rows": 8,
-                                     "mlp_lean_hop": 2}
+                                     "mlp_lean": 2}
         for bad in ({"hop_lanes_per_ray": 5}, {"scan_blocks_per_cu": 16}, {"batch_rays_per_item": 1000},
                     {"batch_rays_per_item": 128}, {"mlp_split": 4}, {"mlp_split": -1},
                     {"mc_items_per_thread": 3}, {"hop_step_budget": -1}, {"hop_step_budget": 4097},
                     {"mlp_pool_tiles": 3}, {"mlp_spec_rows": 4}, {"mlp_spec_rows": 64},
-                    {"mlp_lean_hop": 3}, {"mlp_lean_hop": -1}):
+                    {"mlp_lean": 3}, {"mlp_lean": -1}):
             with pytest.raises(N.GhError):
                 N.gh_set_tuning(**bad)
         t = N.gh_tuning()

@@ -280,10 +280,11 @@ def test_shrunk_bf16_hop_gives_the_fp32_mesh(gh, prec, width, n):
 
 
 @pytest.mark.parametrize("width,n", [(64, 77), (128, 100), (256, 128), (256, 512)])
-def test_lean_hop_layout_changes_nothing(gh, width, n):
-    # the shrunk plain bf16 hop on the lean layout (two blocks per CU, at
-    # width 256 every tile split over two waves per group) and on the full
-    # layout: the same counters, candidates, vertices and triangles
+def test_lean_layout_changes_nothing(gh, width, n):
+    # the shrunk plain bf16 hop and the corner values on the lean layout (two
+    # blocks per CU, at width 256 every tile split over two waves per group,
+    # corner signs certified in a pass of their own) and on the full layout:
+    # the same counters, candidates, vertices and triangles
     native, P = gh
     net = W.neural_scene(0, width)
     probe = W.probe_points(seed=3, n=65536)
@@ -292,9 +293,9 @@ def test_lean_hop_layout_changes_nothing(gh, width, n):
     g = W.grid(n)
     old = native.gh_get_tuning()
     try:
-        native.gh_set_tuning(**{**old, "mlp_lean_hop": 1})
+        native.gh_set_tuning(**{**old, "mlp_lean": 1})
         lean = _run(gh, b, *g)
-        native.gh_set_tuning(**{**old, "mlp_lean_hop": 2})
+        native.gh_set_tuning(**{**old, "mlp_lean": 2})
         full = _run(gh, b, *g)
     finally:
         native.gh_set_tuning(**old)
