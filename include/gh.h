@@ -392,8 +392,9 @@ typedef struct {
                                   which never waits for FP32 values) and the corner values on a lean LDS
                                   layout with two blocks per CU (at width 256 every tile is then split
                                   over two waves per group, 64 rows), the corner certification as a pass
-                                  of its own; 2 runs both on the full layout, one block per CU; values,
-                                  steps and signs do not depend on it */
+                                  of its own; 2 runs both on the full layout, one block per CU (a batch
+                                  reads it in gh_batch_create); values, steps and signs do not depend
+                                  on it */
   int32_t reserved;
 } gh_tuning;
 

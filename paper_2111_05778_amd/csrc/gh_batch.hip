@@ -89,12 +89,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   }
 }
 
-// Network items: a range of rays of one shape each, through the ray pool.
-template <int P>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_hop_batched(const BatchShape* __restrict__ shapes,
-                                                        const WorkItem* __restrict__ items, int n_items,
-                                                        unsigned int* __restrict__ head) {
-  __shared__ MlpSmem sm;
+// Network items: a range of rays of one shape each, through the ray pool,
+// with the evaluator's LDS in sm.
+template <int P, class Sm>
+__device__ __forceinline__ void hop_batched_net(Sm& sm, const BatchShape* __restrict__ shapes,
+                                                const WorkItem* __restrict__ items, int n_items,
+                                                unsigned int* __restrict__ head) {
   __shared__ int s_cnt[kBlock / 64];
   __shared__ unsigned int s_base, s_next;
   __shared__ int s_item;
@@ -125,6 +125,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
   }
 }
 
+template <int P>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_hop_batched(
+    const BatchShape* __restrict__ shapes, const WorkItem* __restrict__ items, int n_items,
+    unsigned int* __restrict__ head) {
+  __shared__ MlpSmem sm;
+  hop_batched_net<P>(sm, shapes, items, n_items, head);
+}
+
+// Network items when every network shape takes the shrunk plain bf16 hop:
+// the lean layout, two blocks per CU (as k_hop_mlp_lean).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hop_batched_lean(
+    const BatchShape* __restrict__ shapes, const WorkItem* __restrict__ items, int n_items,
+    unsigned int* __restrict__ head) {
+  __shared__ MlpSmemBf16 sm;
+  hop_batched_net<kPrecBf16>(sm, shapes, items, n_items, head);
+}
+
 }  // namespace gh
 
 // ==================================================================== host
@@ -139,6 +156,7 @@ struct gh_batch {
   int n_items = 0;
   int n_prim_items = 0;                // the analytic items come first in d_items
   int precision = gh::kPrecF32;
+  bool lean = false;                   // network items on the lean layout (every one shrunk plain bf16)
   hipGraphExec_t exec = nullptr;
 };
 
@@ -200,7 +218,10 @@ hipError_t enqueue_batch(gh_batch* b, hipStream_t s) {
   hop(gh::k_hop_batched_prims, b->d_items, b->n_prim_items, b->d_head + 1);
   const gh::WorkItem* net_items = b->d_items + b->n_prim_items;
   switch (b->precision) {
-    case gh::kPrecBf16: hop(gh::k_hop_batched<gh::kPrecBf16>, net_items, n_net, b->d_head); break;
+    case gh::kPrecBf16:
+      if (b->lean) hop(gh::k_hop_batched_lean, net_items, n_net, b->d_head);
+      else hop(gh::k_hop_batched<gh::kPrecBf16>, net_items, n_net, b->d_head);
+      break;
     case gh::kPrecBf16x3: hop(gh::k_hop_batched<gh::kPrecBf16x3>, net_items, n_net, b->d_head); break;
     default: hop(gh::k_hop_batched<gh::kPrecF32>, net_items, n_net, b->d_head); break;
   }
@@ -270,6 +291,9 @@ gh_status gh_batch_create(int n_shapes, const gh_batch_item* items_h, void* dev_
     shape_items(i, d, g, work);
   }
   b->precision = mlp_prec < 0 ? gh::kPrecF32 : mlp_prec;
+  b->lean = b->precision == gh::kPrecBf16 && gh::current_tuning().mlp_lean == 1;
+  for (int i = 0; i < n_shapes; ++i)
+    if (b->sdb[i].kind == GH_SDB_MLP && !b->sdb[i].mlp.hop_shrink) b->lean = false;
   // analytic items first, then network items, each by cost, longest first
   std::stable_sort(work.begin(), work.end(), [&](const auto& x, const auto& y) {
     const bool px = b->sdb[x.second.shape].kind == GH_SDB_PRIMS, py = b->sdb[y.second.shape].kind == GH_SDB_PRIMS;

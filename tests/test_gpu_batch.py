@@ -99,6 +99,25 @@ def test_mixed_batch_equals_single_runs(gh, precision):
         _assert_same(torch, _snap(r), ref, f"shape {s} {sc['kind']} n={grids[s][0]}")
 
 
+def test_lean_batch_equals_full_layout(gh):
+    # plain bf16 network items on the lean layout (two blocks per CU) and on
+    # the full one, read when the batch is created: every output the same
+    torch, N, P = gh
+    margins = {}
+    scenes, bounds, grids = _mixed(P, "bf16", margins, SIZES)
+    old = N.gh_get_tuning()
+    res = {}
+    try:
+        for lean in (1, 2):
+            N.gh_set_tuning(**{**old, "mlp_lean": lean})
+            batch = P.BatchPolygonizer([(b, *g) for b, g in zip(bounds, grids)])
+            res[lean] = [_snap(r) for r in batch.run()]
+    finally:
+        N.gh_set_tuning(**old)
+    for s, (a, b) in enumerate(zip(res[1], res[2])):
+        _assert_same(torch, a, b, f"shape {s} {scenes[s]['kind']} n={grids[s][0]}")
+
+
 def test_analytic_batch_matches_twin(gh):
     torch, N, P = gh
     scenes = [sc for sc in W.batch_scenes() if sc["kind"] == "csg"][:6]
