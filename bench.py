@@ -258,8 +258,8 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16", dense
            "roofline": {"bound": "mfma", "kernel": "k_hop_mlp", "achieved": flop / (hop_ms * 1e-3) / 1e12,
                         "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
                         "frac": flop / (hop_ms * 1e-3) / PEAK_BF16_MFMA,
-                        "traffic": load_traffic("k_hop_mlp") if (not paper and precision == "bf16x3"
-                                                                 and hop == "fp32") else None,
+                        "traffic": load_traffic("k_hop_mlp") if (not paper and precision == "bf16"
+                                                                 and hop == "shrink") else None,
                         "flop_per_point": fpp, "per_launch_flop": flop}}
     if dense:
         poly.enqueue_dense()
