@@ -259,7 +259,7 @@ gh_status gh_mc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws, size
  * fits, whichever is smaller.  GH_ECAPACITY (synchronous, nothing enqueued)
  * when the grid with that corner capacity needs a larger workspace: the
  * array holds any n <= 512 with the default capacity up to n = 256 and about
- * 2.5e6 corners at n = 512.  Every call on one device shares the array, and
+ * 2.9e6 corners at n = 512.  Every call on one device shares the array, and
  * it keeps the last call's contents: calls that overlap on one device (other
  * streams, other threads) race and must be ordered by the caller. */
 gh_status gh_polygonize_noalloc(const gh_sdb_desc* desc_h, const gh_grid* grid_h, int64_t corner_cap, float* verts,

@@ -205,7 +205,7 @@ def test_full_batch_64_shapes(gh):
         m = res[s]
         cells, cases = m["cells"].cpu().numpy(), m["cases"].cpu().numpy()
         f64 = lambda X: osdb.neural_f64(net, X)  # noqa: E731
-        # bf16x3 takes the FP32 signs (certified), so the FP32 error sets the threshold
+        # corner signs are certified FP32 signs, so the FP32 error sets the threshold
         thr = U.fp32_threshold(P, net, n, lo, h, np.union1d(cells, ref.cells))
         U.assert_cells_match_excluding_near_zero(cells, cases, ref.cells, ref.cases, f64, n, lo, h, thr,
                                                  f"batch shape {s} width {sc['width']}")
