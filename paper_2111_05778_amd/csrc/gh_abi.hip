@@ -136,7 +136,7 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   const size_t nft = (size_t)(D - 1) * W * W;
   const size_t o_wa = take(nb * 2), o_wal = take(nb * 2), o_wf = take(nf * 4), o_wft = take(nft * 4 + 4),
                o_bias = take((size_t)D * W * 4), o_wout = take((size_t)W * 4), o_om = take(16 * 4),
-               o_omrev = take(16 * 4);
+               o_omrev = take(16 * 4), o_bias2 = take((size_t)D * W * 4), o_wout2 = take((size_t)W * 4);
   const size_t need = off;
   if (blob_needed_h) *blob_needed_h = need;
   if (!dev_blob) return desc_h ? fail(GH_EINVAL, "dev_blob is NULL") : GH_OK;
@@ -151,6 +151,14 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
     float* om = (float*)(host.data() + o_omrev);
     for (int q = 0; q < F; ++q) om[q] = (float)((double)sp->omegas_h[q] / (2.0 * M_PI));
   }
+  // The register evaluator works on pre-activations in base-2 units,
+  // z' = z log2 e, so that its activation needs no multiply: the first
+  // layer's weights and every bias are scaled by log2 e here, the hidden
+  // layers' weights are not (a = ln 2 u with u = max(z', 0) + c log2(1 +
+  // 2^-|z'|) is ln 2 times the activation, which the next layer's log2 e
+  // cancels; ReLU is homogeneous, so c = 0 gives the same), and the output
+  // weights are scaled by ln 2.
+  const double kLog2e = 1.4426950408889634074, kLn2 = 0.6931471805599453094;
   for (int l = 0; l < D; ++l) {
     const float* Wl = sp->weights_h[l];  // W x fan_in, row-major
     const int fi = l == 0 ? k1 : W;
@@ -169,7 +177,9 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
               const int q = 8 * (lane / 32) + i;
               const int k = 16 * ks + (l == 0 ? q : gh::mlpa_slot_feature(q));
               const int row = c * 32 + lane % 32;
-              const float v = k < fi ? Wl[(size_t)row * fi + k] : 0.f;
+              const float v = k < fi ? (l == 0 ? (float)(Wl[(size_t)row * fi + k] * kLog2e)
+                                                : Wl[(size_t)row * fi + k])
+                                     : 0.f;
               const uint16_t hi = to_bf16(v);
               uint32_t hb = (uint32_t)hi << 16;
               float hv;
@@ -199,8 +209,14 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
             dst[(size_t)(ks * CT + kt) * 64 + lane] = Wl[(size_t)(2 * ks + lane / 32) * W + kt * 32 + lane % 32];
     }
     memcpy(host.data() + o_bias + (size_t)l * W * 4, sp->biases_h[l], (size_t)W * 4);
+    float* b2 = (float*)(host.data() + o_bias2) + (size_t)l * W;
+    for (int q = 0; q < W; ++q) b2[q] = (float)(sp->biases_h[l][q] * kLog2e);
   }
   memcpy(host.data() + o_wout, sp->weights_h[D], (size_t)W * 4);
+  {
+    float* w2 = (float*)(host.data() + o_wout2);
+    for (int q = 0; q < W; ++q) w2[q] = (float)(sp->weights_h[D][q] * kLn2);
+  }
   if (F > 0) memcpy(host.data() + o_om, sp->omegas_h, (size_t)F * 4);
   hipStream_t s = (hipStream_t)stream;
   gh_status st = hip_status(hipMemcpyAsync(dev_blob, host.data(), need, hipMemcpyHostToDevice, s), "upload");
@@ -219,6 +235,8 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.wft = (const float*)(b + o_wft);
   m.bias = (const float*)(b + o_bias);
   m.wout = (const float*)(b + o_wout);
+  m.bias2 = (const float*)(b + o_bias2);
+  m.wout2 = (const float*)(b + o_wout2);
   m.omegas = (const float*)(b + o_om);
   m.F = F;
   m.W = W;
@@ -235,7 +253,6 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.hop_shrink = sp->precision != GH_PREC_FP32 && sp->bf16_hop == GH_BF16_HOP_SHRINK ? 1 : 0;
   m.eps3 = sp->bf16x3_margin;
   m.relu = sp->activation == GH_ACT_RELU ? 1 : 0;
-  m.act_ln2 = m.relu ? 0.f : 0.693147180559945309f;
   m.act_one = m.relu ? 0.f : 1.f;
   m.split = 3;
   m.pool_tiles = 2;

@@ -13,9 +13,11 @@
 // tile leaves lane l with 16 features of point l % 32; those registers are
 // exactly the next layer's B fragments once the input features of that layer
 // are permuted inside each group of 16 (swap of index bits 3 and 2), and
-// sdb_describe packs the weights in that permuted order.  The epilogue adds
-// the bias, applies softplus with the hardware exp2/log2, and converts with
-// the hardware bf16 rounding.
+// sdb_describe packs the weights in that permuted order.  The layers work in
+// base-2 units (first-layer weights and biases scaled by log2 e, output
+// weights by ln 2), so the epilogue adds the bias, applies softplus with the
+// hardware exp2/log2 and no multiply, and converts with the hardware bf16
+// rounding.
 //   BF16:   one product per fragment pair, activations and weights bf16
 //   BF16x3: hi/lo bf16 splits of both, hi*hi + hi*lo + lo*hi with FP32
 //           accumulation: about 2^-16 relative error
@@ -56,12 +58,14 @@ struct MlpDesc {
   const float* wft;     // float, packed B fragments of W_l itself (l >= 1), for the adjoint
   const float* bias;    // [depth][W]
   const float* wout;    // [W]
+  const float* bias2;   // [depth][W] bias x log2 e (register evaluator: base-2 pre-activations)
+  const float* wout2;   // [W] output weights x ln 2 (register evaluator)
   const float* omegas;  // [F]
   const float* omrev;   // [16] w_k / 2pi (turns per unit; zero past F), for the hardware sine
   int F, W, depth, k1;  // k1 = 3 + 6F features
   int precision;
   int relu;             // hidden activation: 0 softplus, 1 ReLU max(z, 0)
-  float act_ln2, act_one;  // ln 2 and 1 for softplus, 0 and 0 for ReLU (act_hw, act_f32)
+  float act_one;        // 1 for softplus, 0 for ReLU (act_hw, act_f32)
   int split;            // tiles with few rows: 1 never split, 2 split <= 32 rows, 3 also <= 64 rows
   float a_s, r0, a_n, b, b_out;
   float eps;            // |f_bf16 - f_fp32| bound used by the hop test
@@ -144,14 +148,16 @@ struct MlpSmemF32 {
 // functions (FP32 evaluator).
 __device__ __forceinline__ float softplus_f32(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
 
-// Hidden-layer activation of the bf16 evaluators, max(z, 0) + c log2(1 +
-// 2^(-|z| log2 e)) with the hardware base-2 exponential and logarithm (about
-// 1 ulp each: absolute error near 2e-7, far below the bf16 roundings that
-// follow): softplus for c = ln 2, ReLU for c = 0 (the log term is finite, so
-// c = 0 leaves max(z, 0) exactly).  One instruction stream for both: a
-// branch on the activation here measurably slowed the softplus networks.
+// Hidden-layer activation of the bf16 evaluators on a base-2 pre-activation
+// z' = z log2 e (the weights are scaled for it, see sdb_describe):
+// u = max(z', 0) + c log2(1 + 2^-|z'|) with the hardware base-2 exponential
+// and logarithm (about 1 ulp each, far below the bf16 roundings that follow)
+// is softplus(z) / ln 2 for c = 1 and ReLU(z) / ln 2 for c = 0 (the log term
+// is finite, so c = 0 leaves max(z', 0) exactly).  One instruction stream
+// for both: a branch on the activation here measurably slowed the softplus
+// networks.
 __device__ __forceinline__ float act_hw(float z, float c) {
-  const float e = __builtin_amdgcn_exp2f(-fabsf(z) * 1.44269504088896341f);
+  const float e = __builtin_amdgcn_exp2f(-fabsf(z));
   return fmaf(__builtin_amdgcn_logf(1.f + e), c, fmaxf(z, 0.f));
 }
 
@@ -333,8 +339,8 @@ template <int P, int W, int NT, bool kLast>
 __device__ __forceinline__ float mlp_epilogue(const MlpDesc& m, int l, int c0, f32x16_t (&acc)[NT],
                                               bf16x8_t (&x)[2 * NT], bf16x8_t (&xl)[2 * NT]) {
   const int h = (threadIdx.x >> 5) & 1;
-  const float4* __restrict__ bias4 = reinterpret_cast<const float4*>(m.bias + (size_t)l * W) + h;
-  const float4* __restrict__ wout4 = reinterpret_cast<const float4*>(m.wout) + h;
+  const float4* __restrict__ bias4 = reinterpret_cast<const float4*>(m.bias2 + (size_t)l * W) + h;
+  const float4* __restrict__ wout4 = reinterpret_cast<const float4*>(m.wout2) + h;
   float dt[NT];  // per-tile output dots (kLast)
   float4 bv[4], wv[4];
 #pragma unroll
@@ -348,10 +354,10 @@ __device__ __forceinline__ float mlp_epilogue(const MlpDesc& m, int l, int c0, f
     float dot = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      a[4 * j + 0] = act_hw(acc[c][4 * j + 0] + bv[j].x, m.act_ln2);
-      a[4 * j + 1] = act_hw(acc[c][4 * j + 1] + bv[j].y, m.act_ln2);
-      a[4 * j + 2] = act_hw(acc[c][4 * j + 2] + bv[j].z, m.act_ln2);
-      a[4 * j + 3] = act_hw(acc[c][4 * j + 3] + bv[j].w, m.act_ln2);
+      a[4 * j + 0] = act_hw(acc[c][4 * j + 0] + bv[j].x, m.act_one);
+      a[4 * j + 1] = act_hw(acc[c][4 * j + 1] + bv[j].y, m.act_one);
+      a[4 * j + 2] = act_hw(acc[c][4 * j + 2] + bv[j].z, m.act_one);
+      a[4 * j + 3] = act_hw(acc[c][4 * j + 3] + bv[j].w, m.act_one);
       if constexpr (kLast) {
         dot += a[4 * j + 0] * wv[j].x;
         dot += a[4 * j + 1] * wv[j].y;
