@@ -252,8 +252,10 @@ def test_hexprism_closed_forms():
 
 def test_new_primitives_are_distance_bounds():
     # |f| <= distance to the zero set, sampled: the zero set is located on
-    # segments from each inside point to far outside points by bisection, and
-    # every outside sample's |f| must not exceed its distance to those points
+    # segments from each inside point to far outside points by bisection (to
+    # 2^-59), and every sample's |f| must not exceed its distance to those
+    # points, which is at least its distance to the zero set; a bound 1 %
+    # too large (the planted mistake) fails on every shape
     rng = np.random.default_rng(7)
     for recs in (W.cylinder_scene(0.3, 0.2), W.cone_scene(0.25, 0.5), W.hexprism_scene(0.2, 0.3)):
         inside = np.zeros((1, 3))
@@ -268,7 +270,8 @@ def test_new_primitives_are_distance_bounds():
         Q = rng.uniform(-1, 1, (3000, 3))
         f = sdb.union_f64(recs, Q)
         dist = np.min(np.linalg.norm(Q[:, None, :] - surf[None, :, :], axis=2), axis=1)
-        assert np.all(np.abs(f) <= dist + 2e-3), np.max(np.abs(f) - dist)
+        assert np.all(np.abs(f) <= dist + 1e-12), np.max(np.abs(f) - dist)
+        assert np.any(np.abs(1.01 * f) > dist + 1e-12)
 
 
 def test_genus2_function_and_bound():
