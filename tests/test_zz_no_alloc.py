@@ -1,7 +1,8 @@
 """gh_polygonize_noalloc (gh_hop + gh_mc on the library's fixed workspace,
 no allocation) against gh_hop + gh_mc on a caller workspace, through the C
 ABI: the same counters and bit-identical outputs on two calls in a row, the
-second on a smaller grid, for an analytic bound and a network bound."""
+second on a smaller grid, for an analytic bound and network bounds (FP32,
+and plain bf16 on the lean kernels)."""
 import numpy as np
 import pytest
 
@@ -76,15 +77,24 @@ def test_noalloc_equals_hop_and_mc_twice(gh):
         _same(c_ref, ref, c, got, label)
 
 
-def test_noalloc_network_twice(gh):
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_noalloc_network_twice(gh, prec):
+    # plain bf16 takes the shrunk hop and the lean kernels, with two-step
+    # certified corner signs
     torch, N, P = gh
-    net = W.neural_scene(0, 64)
-    bound = P.Bound.mlp(net, "fp32")
+    width = 64 if prec == "fp32" else 256
+    net = W.neural_scene(0, width)
+    if prec == "fp32":
+        bound = P.Bound.mlp(net, "fp32")
+    else:
+        probe = W.probe_points(seed=3, n=65536)
+        bound = P.Bound.mlp(net, "bf16", margin=P.bf16_margin(net, probe, "bf16"), hop="shrink",
+                            margin3=P.bf16_margin(net, probe, "bf16x3"))
     for n in (40, 24):
         _, lo, h = W.grid(n)
         poly, c_ref, ref = _reference(gh, bound, n, lo, h)
         c, got = _noalloc(gh, bound, n, lo, h, 0, poly.vert_cap, poly.tri_cap, poly.cell_cap)
-        _same(c_ref, ref, c, got, f"network w64 n={n}")
+        _same(c_ref, ref, c, got, f"network {prec} w{width} n={n}")
 
 
 def test_noalloc_refuses_a_grid_beyond_the_fixed_workspace(gh):
