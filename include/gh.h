@@ -7,9 +7,14 @@
  * continued past the surface (Section 3, eq. iter and Algorithm 1), then
  * marching cubes on the cells the rays stop in.  Each step evaluates the
  * signed distance bound f at the centroid of cell (i, j, k) of the column and
- * skips s = floor(|f|/h) cells; s == 0 marks the cell as a candidate and moves
- * on by one.  Section 5 requires the same mesh as marching cubes over every
- * cell ("enumeration", Section 2), which gh_dense provides for comparison.
+ * skips s = floor(|f|/h) cells; s == 0 moves on by one and marks the cell as
+ * a candidate when |f| <= (sqrt 3 / 2 + 1/32) h (a cell the surface crosses
+ * holds a zero within half its diagonal of the centroid, and |f| is at most
+ * the distance to the surface; h/32 covers float32 error up to h/64 in the
+ * values, and grids with h below 2^-12 of the largest of 1, |lo| and
+ * |lo + n h| take every cell with s == 0).  Section 5 requires the same mesh as marching
+ * cubes over every cell ("enumeration", Section 2), which gh_dense provides
+ * for comparison.
  *
  * Conventions shared by every entry point
  *  - Pointers are DEVICE pointers unless their name ends in _h (host).
@@ -37,8 +42,10 @@
  *
  * Arithmetic: the analytic bounds are evaluated in float32 with one rounding
  * per operation in a documented order (no contraction); the hop test
- * s = floor(|f| * inv_h), inv_h = float32(1/h), is taken in float32; vertex
- * parameters t = f_a/(f_a - f_b) are float32.
+ * s = floor(|f| * inv_h), inv_h = float32(1/h), and the candidate test
+ * |f| <= float32((sqrt 3 / 2 + 1/32) h) (factor and product in double,
+ * rounded once) are taken in float32; vertex parameters t = f_a/(f_a - f_b)
+ * are float32.
  */
 #ifndef GH_H
 #define GH_H
@@ -100,14 +107,16 @@ enum { GH_PREC_FP32 = 0, GH_PREC_BF16 = 1, GH_PREC_BF16X3 = 2 };
 enum { GH_ACT_SOFTPLUS = 0, GH_ACT_RELU = 1 };
 /* Hop rule of the bf16 modes (the corner and lattice signs are certified in
  * either, so the mesh is the FP32 one):
- *   GH_BF16_HOP_FP32    a value whose step floor(|f|/h) could change within
- *                       bf16_margin is re-evaluated in FP32 first: the hop
- *                       schedule, candidates and counts are the FP32 ones
- *   GH_BF16_HOP_SHRINK  the step is floor(max(|f| - bf16_margin, 0)/h) from
- *                       the bf16 value alone (|f| - bf16_margin bounds the
- *                       FP32 value's magnitude from below, so no cell the
- *                       surface crosses is skipped): no FP32 in the hop, at
- *                       the price of shorter steps and more candidates */
+ *   GH_BF16_HOP_FP32    a value whose step floor(|f|/h) or candidate test
+ *                       could change within bf16_margin is re-evaluated in
+ *                       FP32 first: the hop schedule, candidates and counts
+ *                       are the FP32 ones
+ *   GH_BF16_HOP_SHRINK  the step and the candidate test take
+ *                       max(|f| - bf16_margin, 0) from the bf16 value alone
+ *                       (it bounds the FP32 value's magnitude from below, so
+ *                       no cell the surface crosses is skipped or left
+ *                       unmarked): no FP32 in the hop, at the price of
+ *                       shorter steps and more candidates */
 enum { GH_BF16_HOP_FP32 = 0, GH_BF16_HOP_SHRINK = 1 };
 
 /* Primitive record: 16 float32 values.

@@ -59,6 +59,13 @@ gh_status read_grid(const gh_grid* grid_h, gh::Grid* g) {
   g->lo = grid_h->lo;
   g->h = grid_h->h;
   g->inv_h = (float)(1.0 / (double)grid_h->h);
+  // Candidate threshold: half a cell's diagonal, where a cell the surface
+  // crosses keeps its centroid value, plus h/32 for the float32 error of the
+  // values (which must stay below h/64); on grids whose cells are small
+  // against the coordinates, h (every cell with a zero step).
+  const double hd = grid_h->h, lod = grid_h->lo;
+  const double scale = fmax(1.0, fmax(fabs(lod), fabs(lod + grid_h->n * hd)));
+  g->cand_thr = (float)((hd >= ldexp(1.0, -12) * scale ? sqrt(3.0) / 2.0 + 1.0 / 32.0 : 1.0) * hd);
   return GH_OK;
 }
 

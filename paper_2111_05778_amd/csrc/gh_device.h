@@ -36,6 +36,8 @@ struct Grid {
   float lo;     // origin
   float h;      // cell size
   float inv_h;  // float32(1/h), computed in double and rounded once
+  float cand_thr;  // candidate threshold float32((sqrt 3 / 2 + 1/32) h), or h on grids of cells small against
+                   // the coordinates (h < 2^-12 max(1, |lo|, |lo + n h|)); in double, rounded once
 };
 
 // Cell centroid coordinate lo + (idx + 1/2) h (eq. cells): one rounded

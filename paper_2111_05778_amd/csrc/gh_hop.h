@@ -116,8 +116,11 @@ __device__ __forceinline__ float lane_union(const float* __restrict__ srec, cons
 }
 
 // Hop rule (Section 3, eq. iter, cell-quantised): at the centroid of cell k,
-// s = floor(|f| * inv_h); s >= 1 skips s cells, s == 0 marks cell k as a
-// candidate and moves to k + 1; the ray ends when k >= n.  One block tile of
+// s = floor(|f| * inv_h); s >= 1 skips s cells, s == 0 moves to k + 1 and
+// marks cell k as a candidate when |f| <= cand_thr (a cell with a sign
+// change holds a zero within half its diagonal of the centroid, and |f| is
+// at most the distance to it; cand_thr adds h/32 for float32 error); the
+// ray ends when k >= n.  One block tile of
 // columns; srec holds the primitive records in LDS.
 // kRegs and kTypes as for lane_union: with kRegs the records live in
 // registers for the whole ray instead of being read from LDS at every step.
@@ -169,15 +172,17 @@ __device__ __forceinline__ void hop_prims_tile(const float* __restrict__ srec, c
       bad = bad || !(d <= FLT_MAX);
       const float s = floorf(d * g.inv_h);
       if (s == 0.f) {
-        const int kw = k >> 5;
-        if (kw != wi) {
-          if (word && q == 0) colbits[(size_t)wi * ncol + col] = word;
-          if (word) mask |= 1ull << wi;
-          word = 0;
-          wi = kw;
+        if (d <= g.cand_thr) {
+          const int kw = k >> 5;
+          if (kw != wi) {
+            if (word && q == 0) colbits[(size_t)wi * ncol + col] = word;
+            if (word) mask |= 1ull << wi;
+            word = 0;
+            wi = kw;
+          }
+          word |= 1u << (k & 31);
+          ++cands;
         }
-        word |= 1u << (k & 31);
-        ++cands;
         ++k;
       } else {
         k += (int)fminf(s, nf);
@@ -268,15 +273,17 @@ __device__ __forceinline__ void hop_window_rays(const float* __restrict__ srec, 
         }
         const float s = floorf(dk * g.inv_h);
         if (s == 0.f) {
-          const int kw = k >> 5;
-          if (kw != wi) {
-            if (word && l == 0) colbits[(size_t)wi * ncol + col] = word;
-            if (word) mask |= 1ull << wi;
-            word = 0;
-            wi = kw;
+          if (dk <= g.cand_thr) {
+            const int kw = k >> 5;
+            if (kw != wi) {
+              if (word && l == 0) colbits[(size_t)wi * ncol + col] = word;
+              if (word) mask |= 1ull << wi;
+              word = 0;
+              wi = kw;
+            }
+            word |= 1u << (k & 31);
+            ++cands;
           }
-          word |= 1u << (k & 31);
-          ++cands;
           ++k;
         } else {
           k += (int)fminf(s, nf);
@@ -475,8 +482,9 @@ __device__ __forceinline__ float reeval_fp32(const MlpDesc& m, Sm& sm, int* s_cn
 //  * normally the current hop points of up to R live rays (R = tile rows),
 //    packed into the first rows, in the kernel's precision; in the bf16
 //    precisions a value whose hop decision is ambiguous within the margin
-//    (floor((d - eps)/h) != floor((d + eps)/h)) is not used: its ray waits
-//    for an FP32 value;
+//    (floor((d - eps)/h) != floor((d + eps)/h), or d - eps and d + eps on
+//    either side of the candidate threshold) is not used: its ray waits for
+//    an FP32 value;
 //  * an FP32 tile of up to kF32Rows waiting rays once that many wait, or
 //    when every live ray waits.
 // Deferring the FP32 values fills their tiles instead of paying a mostly
@@ -517,17 +525,19 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
     } else {
       const float s = floorf(d * g.inv_h);
       if (s == 0.f) {
-        const int kw = k >> 5;
-        if (kw != wi) {
-          if (word) {
-            colbits[(size_t)wi * ncol + col] = word;
-            mask |= 1ull << wi;
+        if (d <= g.cand_thr) {
+          const int kw = k >> 5;
+          if (kw != wi) {
+            if (word) {
+              colbits[(size_t)wi * ncol + col] = word;
+              mask |= 1ull << wi;
+            }
+            word = 0;
+            wi = kw;
           }
-          word = 0;
-          wi = kw;
+          word |= 1u << (k & 31);
+          ++cands;
         }
-        word |= 1u << (k & 31);
-        ++cands;
         ++k;
       } else {
         k += (int)fminf(s, nf);
@@ -624,7 +634,11 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
             // (a non-finite value stays non-finite)
             d = d <= FLT_MAX ? fmaxf(d - m.eps, 0.f) : d;
           } else {
-            amb = d <= FLT_MAX && floorf(fmaxf(d - m.eps, 0.f) * g.inv_h) != floorf((d + m.eps) * g.inv_h);
+            // the FP32 value lies in [d - eps, d + eps]: wait for it when the
+            // step or the candidate test could differ there
+            const float dl = fmaxf(d - m.eps, 0.f), dh = d + m.eps;
+            amb = d <= FLT_MAX &&
+                  (floorf(dl * g.inv_h) != floorf(dh * g.inv_h) || (dl <= g.cand_thr) != (dh <= g.cand_thr));
           }
         }
         if (amb) {

@@ -53,6 +53,80 @@ def test_plane_perpendicular_closed_form(n):
     assert len(cells) == 2 * len(cols)
 
 
+def test_candidates_within_half_a_diagonal():
+    """The candidate test: a cell is marked only when its centroid value is at
+    most half the cell's diagonal plus h/32, (sqrt 3 / 2 + 1/32) h.  A plane
+    at z = C placed so that the two cells within h of it sit at 0.07 h and
+    0.93 h from their centroids: the far one is stepped over, each column
+    marks exactly the cell holding the plane, the evaluation count keeps its
+    closed form, and the mesh equals enumeration's."""
+    n = 64
+    _, lo, h = W.grid(n)
+    lo, h = float(lo), float(h)
+    k1 = 35
+    C = lo + (k1 + 0.5 + 0.93) * h
+    S = sdb.SDB.prims(W.plane_scene((0, 0, 1), C))
+    cells, total, per_col = hop.hop(S, n, lo, h)
+    assert (per_col == round(math.log2(n)) + 2).all()
+    np.testing.assert_array_equal(cells % n, np.full(n * n, k1 + 1))
+    dense, _ = mc.enumerate_mesh(S, n, lo, h)
+    assert _mesh_equal(hop.gridhop(S, n, lo, h).mesh, dense)
+    # parallel to the rays: columns between the threshold and h from the
+    # plane take one evaluation per cell and mark nothing
+    T = (np.sqrt(3) / 2 + 1 / 32) * h
+    assert np.isclose(hop.candidate_threshold_f64(n, lo, h), T)
+    S = sdb.SDB.prims(W.plane_scene((1, 0, 0), C))
+    cells, total, per_col = hop.hop(S, n, lo, h)
+    xs = lo + (np.arange(n) + 0.5) * h
+    dist = np.abs(xs - C)
+    assert ((dist > T) & (dist < h)).sum() == 1
+    marked = np.unique(cells // (n * n))
+    np.testing.assert_array_equal(marked, np.nonzero(dist <= T)[0])
+    assert total == n * int(np.where(dist < h, n, np.ceil(n / np.maximum(np.floor(dist / h), 1))).sum())
+
+
+def test_float32_threshold_margin_keeps_corner_zeros(monkeypatch):
+    """The Sierpinski tetrahedron of depth 5 at N = 96 has zeros on lattice
+    points, so some sign-change cells hold their zero at a corner, exactly
+    half a diagonal from the centroid.  In float32 the centroid value comes
+    out a little above (sqrt 3 / 2) h; the h/32 of the threshold keeps those
+    cells (the twin's candidates hold every float32 sign-change cell), and a
+    threshold of (sqrt 3 / 2) h alone (the planted mistake) loses them."""
+    S = sdb.SDB.prims(W.sierpinski_scene(5))
+    n, lo, h = W.grid(96)
+    dense, _ = mc.enumerate_mesh(S, n, lo, h, precision="f32")
+    cells, _, _ = hop.hop(S, n, lo, h, precision="f32")
+    assert np.all(np.isin(dense.cells, cells))
+    monkeypatch.setattr(hop, "candidate_threshold_f32",
+                        lambda nn, ll, hh: np.float32(np.float64(np.float32(hh)) * (np.sqrt(3.0) / 2.0)))
+    cells, _, _ = hop.hop(S, n, lo, h, precision="f32")
+    assert not np.all(np.isin(dense.cells, cells))
+
+
+def test_candidate_threshold_on_small_cells():
+    # h below 2^-12 of the coordinate scale: every cell with a zero step is
+    # a candidate (threshold h); the twin's float32 threshold rounds once
+    assert hop.candidate_threshold_f64(64, 1000.0, 1e-3) == 1e-3
+    assert hop.candidate_threshold_f64(64, -1.0, 2 / 64) == (np.sqrt(3.0) / 2.0 + 1.0 / 32.0) * (2 / 64)
+    t32 = hop.candidate_threshold_f32(512, -1.0, 2 / 512)
+    assert t32 == np.float32((np.sqrt(3.0) / 2.0 + 1.0 / 32.0) * np.float64(np.float32(2 / 512)))
+
+
+@pytest.mark.parametrize("scene", ["sphere", "csg"])
+def test_half_diagonal_is_needed(scene, monkeypatch):
+    """Planted mistake: a threshold of h / 2 instead of half the diagonal
+    leaves sign-change cells whose zero lies towards a corner unmarked, and
+    the mesh loses triangles."""
+    recs = W.sphere_scene(0.5) if scene == "sphere" else W.csg_scene(1)
+    S = sdb.SDB.prims(recs)
+    n, lo, h = W.grid(48)
+    dense, _ = mc.enumerate_mesh(S, n, lo, h)
+    assert _mesh_equal(hop.gridhop(S, n, lo, h).mesh, dense)
+    monkeypatch.setattr(hop, "candidate_threshold_f64", lambda nn, ll, hh: 0.5 * np.float64(hh))
+    cells, _, _ = hop.hop(S, n, lo, h)
+    assert not np.all(np.isin(dense.cells, cells))
+
+
 @pytest.mark.parametrize("n", [16, 64, 256])
 def test_plane_parallel_count_and_harmonic_bound(n):
     C = 0.1234
@@ -137,7 +211,7 @@ def test_vectorised_hopper_matches_plain_loop():
         def f(k):
             return float(sdb.union_f64(recs, np.array([[x, y, lo + (k + 0.5) * h]]))[0])
 
-        ks, ev = hop.hop_column(f, n, h)
+        ks, ev = hop.hop_column(f, n, h, lo)
         assert ev == per_col[q]
         mine = cells[(cells // n) == c] % n
         assert list(mine) == ks
