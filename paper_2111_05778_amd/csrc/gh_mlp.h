@@ -123,6 +123,27 @@ struct MlpSmemBf16 {
   float part[4][kBf16Rows];
 };
 
+// Resident weights for a small plain bf16 network: every layer's A fragments
+// held in LDS for the whole kernel (no chunk copies, no per-chunk waits or
+// barriers), with the points and values of a tile; at most 72 KB, so two
+// blocks share a CU.  Tiles are never split (no exchange).  The first
+// layer's zero k-step is not copied.
+constexpr int kResidentW = 64;
+constexpr int kResidentBytes = 70 * 1024;
+struct MlpSmemRes {
+  uint4 wres[kResidentBytes / 16];
+  float pts[kBf16Rows][3];
+  float f[kBf16Rows];
+};
+// Offset (bf16 elements) of layer l's fragments in the resident copy, and
+// the bytes of a network of the given depth.
+__host__ __device__ constexpr size_t mlpr_layer_offset(int l, int W) {
+  return l == 0 ? 0 : (size_t)16 * kK0Steps * W + (size_t)(l - 1) * W * W;
+}
+__host__ __device__ constexpr bool mlp_resident_fits(int depth, int W) {
+  return W == kResidentW && depth >= 1 && mlpr_layer_offset(depth, W) * 2 <= (size_t)kResidentBytes;
+}
+
 // On the lean layout the widest network runs every tile split over two or
 // more waves per group (at most 64 rows), so that a wave holds half of a
 // layer's accumulators and two waves fit one SIMD.
@@ -472,11 +493,14 @@ __device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, Sm& sm, int c0, 
                                               const uint16_t* __restrict__ lo, const uint16_t* __restrict__ next_hi,
                                               const uint16_t* __restrict__ next_lo, f32x16_t (&acc)[NT],
                                               const bf16x8_t (&x)[W / 16], const bf16x8_t (&xl)[W / 16], float px,
-                                              float py, float pz) {
+                                              float py, float pz, size_t roff = 0) {
   constexpr int CT = W / 32;
   constexpr int NCH = (NS + kChunkSteps - 1) / kChunkSteps;
   constexpr int CE = kChunkSteps * CT * 512;  // bf16 elements per chunk
   static_assert(NCH % 2 == 0, "layers must have an even number of chunks");
+  // resident weights: the layer's fragments sit in LDS at roff (bf16
+  // elements) for the whole kernel, so nothing is copied or waited for
+  constexpr bool kRes = std::is_same_v<Sm, MlpSmemRes>;
   const int lane = threadIdx.x & 63;
   if constexpr (kActive) {
 #pragma unroll
@@ -487,11 +511,15 @@ __device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, Sm& sm, int c0, 
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
     const int cur = ch & 1;
-    if (ch + 1 < NCH) ChunkDma<P, W>::issue(hi + (size_t)(ch + 1) * CE, lo + (size_t)(ch + 1) * CE, sm, cur ^ 1);
-    else if (next_hi) ChunkDma<P, W>::issue(next_hi, next_lo, sm, cur ^ 1);
+    if constexpr (!kRes) {
+      if (ch + 1 < NCH) ChunkDma<P, W>::issue(hi + (size_t)(ch + 1) * CE, lo + (size_t)(ch + 1) * CE, sm, cur ^ 1);
+      else if (next_hi) ChunkDma<P, W>::issue(next_hi, next_lo, sm, cur ^ 1);
+    }
     __builtin_amdgcn_sched_barrier(0);  // the copy starts before this chunk's products
     if constexpr (kActive) {
-      const bf16x8_t* __restrict__ sa = reinterpret_cast<const bf16x8_t*>(sm.stage[cur][0]);
+      const bf16x8_t* __restrict__ sa;
+      if constexpr (kRes) sa = reinterpret_cast<const bf16x8_t*>(sm.wres) + (roff + (size_t)ch * CE) / 8;
+      else sa = reinterpret_cast<const bf16x8_t*>(sm.stage[cur][0]);
       const bf16x8_t* __restrict__ sal = sa;  // the lo parts (BF16x3 only)
       if constexpr (P == kPrecBf16x3) sal = reinterpret_cast<const bf16x8_t*>(sm.stage[cur][1]);
       // Read the fragments of FS k-steps at once, then multiply: the reads
@@ -533,8 +561,20 @@ __device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, Sm& sm, int c0, 
       }
     }
     __builtin_amdgcn_sched_barrier(0);  // and is waited for only after them
-    ChunkDma<P, W>::wait_and_sync();
+    if constexpr (!kRes) ChunkDma<P, W>::wait_and_sync();
   }
+}
+
+// Copies every layer's bf16 A fragments of the network into the resident
+// layout (the first layer without its zero k-step), then synchronises.
+template <int W>
+__device__ __forceinline__ void mlp_load_resident(const MlpDesc& m, MlpSmemRes& sm) {
+  const size_t n0 = mlpr_layer_offset(1, W) / 8, nh = (mlpr_layer_offset(m.depth, W) - mlpr_layer_offset(1, W)) / 8;
+  const uint4* __restrict__ g0 = reinterpret_cast<const uint4*>(m.wa);
+  const uint4* __restrict__ g1 = reinterpret_cast<const uint4*>(m.wa + mlpa_layer_offset(1, W));
+  for (size_t i = threadIdx.x; i < n0; i += blockDim.x) sm.wres[i] = g0[i];
+  for (size_t i = threadIdx.x; i < nh; i += blockDim.x) sm.wres[n0 + i] = g1[i];
+  __syncthreads();
 }
 
 // Hands this wave's new B fragments (tiles c0 .. c0 + NT - 1) to the other
@@ -572,12 +612,15 @@ __device__ __forceinline__ float mlp_wave(const MlpDesc& m, Sm& sm, float px, fl
   f32x16_t acc[NT];
   bf16x8_t x[KS], xl[KS];
   {
-    ChunkDma<P, W>::issue(m.wa, m.wal, sm, 0);
-    ChunkDma<P, W>::wait_and_sync();
+    if constexpr (!std::is_same_v<Sm, MlpSmemRes>) {
+      ChunkDma<P, W>::issue(m.wa, m.wal, sm, 0);
+      ChunkDma<P, W>::wait_and_sync();
+    }
     const size_t on = mlpa_layer_offset(1, W);
     const bool deeper = m.depth > 1;
     mlp_layer_reg<P, W, NT, kK0Steps, true, kActive>(m, sm, c0, m.wa, m.wal, deeper ? m.wa + on : nullptr,
-                                                     deeper ? m.wal + on : nullptr, acc, x, xl, px, py, pz);
+                                                     deeper ? m.wal + on : nullptr, acc, x, xl, px, py, pz,
+                                                     mlpr_layer_offset(0, W));
   }
   float dot = 0.f;
   for (int l = 0;; ++l) {
@@ -596,7 +639,8 @@ __device__ __forceinline__ float mlp_wave(const MlpDesc& m, Sm& sm, float px, fl
     const size_t o = mlpa_layer_offset(l + 1, W), on = mlpa_layer_offset(l + 2, W);
     const bool deeper = l + 2 < m.depth;
     mlp_layer_reg<P, W, NT, KS, false, kActive>(m, sm, c0, m.wa + o, m.wal + o, deeper ? m.wa + on : nullptr,
-                                                deeper ? m.wal + on : nullptr, acc, x, xl, px, py, pz);
+                                                deeper ? m.wal + on : nullptr, acc, x, xl, px, py, pz,
+                                                mlpr_layer_offset(l + 1, W));
   }
   return dot;
 }
@@ -642,7 +686,9 @@ __device__ __forceinline__ void mlp_tile_split(const MlpDesc& m, Sm& sm, int nro
 template <int P, int W, class Sm>
 __device__ __forceinline__ void mlp_tile_reg(const MlpDesc& m, Sm& sm, int nrows) {
   constexpr int kS4 = W / 32 >= 4 ? 4 : W / 32;  // at least one m-tile per wave
-  if constexpr (mlp_split_only<W, Sm>()) {
+  if constexpr (std::is_same_v<Sm, MlpSmemRes>) {
+    mlp_tile_split<P, W, 1>(m, sm, nrows);  // resident weights: no exchange buffer
+  } else if constexpr (mlp_split_only<W, Sm>()) {
     // nrows <= 64: every layer is split over two or four waves per group
     if (m.split >= 2 && nrows <= 32) mlp_tile_split<P, W, kS4>(m, sm, nrows);
     else mlp_tile_split<P, W, 2>(m, sm, nrows);

@@ -306,6 +306,47 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   hop_mlp_pool<kPrecBf16, W>(m, g, colmask, colbits, ctr, sm, s_cnt, &s_base, QueueRays{queue, 0, (int64_t)g.n * g.n});
 }
 
+// The same two kernels for a small network whose weights stay resident in
+// LDS (mlp_resident_fits): loaded once per block, no copies per tile.
+template <int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hop_mlp_res(
+    MlpDesc m, Grid g, uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits, unsigned int* __restrict__ queue,
+    gh_counters* __restrict__ ctr) {
+  __shared__ MlpSmemRes sm;
+  __shared__ int s_cnt[kBlock / 64];
+  __shared__ unsigned int s_base;
+  mlp_load_resident<W>(m, sm);
+  hop_mlp_pool<kPrecBf16, W>(m, g, colmask, colbits, ctr, sm, s_cnt, &s_base, QueueRays{queue, 0, (int64_t)g.n * g.n});
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_corners_res(
+    MlpDesc m, Grid g, Workspace ws) {
+  __shared__ MlpSmemRes sm;
+  constexpr int R = kBf16Rows;
+  const int64_t count = ws.nlist[0];
+  if (count > ws.cap) return;
+  mlp_load_resident<W>(m, sm);
+  const int n1 = g.n + 1;
+  const int64_t tiles = (count + R - 1) / R;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t i0 = tile * R;
+    const int nrows = (int)(count - i0 < R ? count - i0 : R);
+    const bool mine = (int)threadIdx.x < nrows;
+    if (mine) {
+      const int64_t i = i0 + threadIdx.x;
+      const int L = ws.cl[i], a = L / n1, b = L - a * n1;
+      sm.pts[threadIdx.x][0] = lattice(g, a);
+      sm.pts[threadIdx.x][1] = lattice(g, b);
+      sm.pts[threadIdx.x][2] = lattice(g, ws.ck[i]);
+    }
+    __syncthreads();
+    mlp_tile<kPrecBf16, W>(m, sm, nrows);
+    if (mine) ws.cf[i0 + threadIdx.x] = sm.f[threadIdx.x];
+    __syncthreads();
+  }
+}
+
 // ================================================================ launchers
 template <class K>
 static int mlp_grid(K kernel, int64_t tiles) {
@@ -331,8 +372,18 @@ static hipError_t launch_mlp_w(int what, const DevSdb& d, const Grid& g, const W
       if constexpr (P == kPrecBf16) {
         if (current_tuning().mlp_lean == 1) {  // all values on the lean layout, then the certification
           constexpr int RL = mlp_tile_rows<kPrecBf16, W, MlpSmemBf16>();
-          auto ka = k_mlp_corners_lean<W>;
-          hipLaunchKernelGGL(ka, dim3(mlp_grid(ka, (ws->cap + RL - 1) / RL)), dim3(kBlock), 0, s, d.mlp, g, *ws);
+          bool res = false;
+          if constexpr (W == kResidentW) {
+            if ((res = mlp_resident_fits(d.mlp.depth, W))) {
+              auto kr = k_mlp_corners_res<W>;
+              hipLaunchKernelGGL(kr, dim3(mlp_grid(kr, (ws->cap + kBf16Rows - 1) / kBf16Rows)), dim3(kBlock), 0, s,
+                                 d.mlp, g, *ws);
+            }
+          }
+          if (!res) {
+            auto ka = k_mlp_corners_lean<W>;
+            hipLaunchKernelGGL(ka, dim3(mlp_grid(ka, (ws->cap + RL - 1) / RL)), dim3(kBlock), 0, s, d.mlp, g, *ws);
+          }
           auto kb = k_mlp_corners<P, W, true>;
           hipLaunchKernelGGL(kb, dim3(mlp_grid(kb, (ws->cap + R - 1) / R)), dim3(kBlock), 0, s, d.mlp, g, *ws, ctr);
           break;
@@ -354,8 +405,13 @@ static hipError_t launch_mlp_w(int what, const DevSdb& d, const Grid& g, const W
       auto k = k_hop_mlp<P, W>;
       // the shrunk plain bf16 hop never waits for FP32 values: by default it
       // runs on the lean layout, two blocks per CU
-      if constexpr (P == kPrecBf16)
-        if (d.mlp.hop_shrink && current_tuning().mlp_lean == 1) k = k_hop_mlp_lean<W>;
+      if constexpr (P == kPrecBf16) {
+        if (d.mlp.hop_shrink && current_tuning().mlp_lean == 1) {
+          k = k_hop_mlp_lean<W>;
+          if constexpr (W == kResidentW)
+            if (mlp_resident_fits(d.mlp.depth, W)) k = k_hop_mlp_res<W>;
+        }
+      }
       const int64_t rays = (int64_t)g.n * g.n;
       hipLaunchKernelGGL(k, dim3(mlp_grid(k, (rays + R - 1) / R)), dim3(kBlock), 0, s, d.mlp, g, ws->colmask,
                          ws->colbits, &ws->ticket[kTicketRays], ctr);
