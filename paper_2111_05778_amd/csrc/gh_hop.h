@@ -499,7 +499,7 @@ __device__ __forceinline__ void hop_mlp_pool(const MlpDesc& m, const Grid& g, ui
   constexpr int R = mlp_tile_rows<P, W, Sm>();
   // The lean layout holds no FP32 activations: it serves the shrunk bf16 hop,
   // which never waits for an FP32 value.
-  constexpr bool kLean = std::is_same_v<Sm, MlpSmemBf16> || std::is_same_v<Sm, MlpSmemRes>;
+  constexpr bool kLean = std::is_same_v<Sm, MlpSmemBf16> || mlp_resident_layout<Sm>();
   static_assert(!kLean || P == kPrecBf16, "the lean layout runs the plain bf16 evaluator only");
   const int n = g.n;
   const size_t ncol = (size_t)n * n;

@@ -135,6 +135,14 @@ struct MlpSmemRes {
   float pts[kBf16Rows][3];
   float f[kBf16Rows];
 };
+// The same layout for a ReLU network: its kernels apply max(z, 0) alone
+// (bit-identical to the shared activation with c = 0, without the log term
+// that c = 0 discards).
+struct MlpSmemResRelu : MlpSmemRes {};
+template <class Sm>
+__host__ __device__ constexpr bool mlp_resident_layout() {
+  return std::is_base_of_v<MlpSmemRes, Sm>;
+}
 // Offset (bf16 elements) of layer l's fragments in the resident copy, and
 // the bytes of a network of the given depth.
 __host__ __device__ constexpr size_t mlpr_layer_offset(int l, int W) {
@@ -181,6 +189,11 @@ __device__ __forceinline__ float act_hw(float z, float c) {
   const float e = __builtin_amdgcn_exp2f(-fabsf(z));
   return fmaf(__builtin_amdgcn_logf(1.f + e), c, fmaxf(z, 0.f));
 }
+
+// act_hw for c = 0 without the log term: max(z, 0) + (+0), the same bits
+// (the product of the finite log term and 0 is +0, which also turns -0 into
+// +0).
+__device__ __forceinline__ float act_relu(float z) { return fmaf(0.f, 0.f, fmaxf(z, 0.f)); }
 
 // The same for the FP32 evaluator: max(z, 0) + c log(1 + e^-|z|), softplus
 // for c = 1 (1 x is exact), ReLU for c = 0.
@@ -356,7 +369,7 @@ __device__ __forceinline__ f32x16_t mfma_step(const bf16x8_t& a, const bf16x8_t&
 // next tile are loaded while a tile is processed, and a scheduling barrier
 // per tile keeps the compiler from hoisting every load of the layer (which
 // would cost registers instead of latency).
-template <int P, int W, int NT, bool kLast>
+template <int P, int W, int NT, bool kLast, bool kRelu = false>
 __device__ __forceinline__ float mlp_epilogue(const MlpDesc& m, int l, int c0, f32x16_t (&acc)[NT],
                                               bf16x8_t (&x)[2 * NT], bf16x8_t (&xl)[2 * NT]) {
   const int h = (threadIdx.x >> 5) & 1;
@@ -375,10 +388,10 @@ __device__ __forceinline__ float mlp_epilogue(const MlpDesc& m, int l, int c0, f
     float dot = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      a[4 * j + 0] = act_hw(acc[c][4 * j + 0] + bv[j].x, m.act_one);
-      a[4 * j + 1] = act_hw(acc[c][4 * j + 1] + bv[j].y, m.act_one);
-      a[4 * j + 2] = act_hw(acc[c][4 * j + 2] + bv[j].z, m.act_one);
-      a[4 * j + 3] = act_hw(acc[c][4 * j + 3] + bv[j].w, m.act_one);
+      a[4 * j + 0] = kRelu ? act_relu(acc[c][4 * j + 0] + bv[j].x) : act_hw(acc[c][4 * j + 0] + bv[j].x, m.act_one);
+      a[4 * j + 1] = kRelu ? act_relu(acc[c][4 * j + 1] + bv[j].y) : act_hw(acc[c][4 * j + 1] + bv[j].y, m.act_one);
+      a[4 * j + 2] = kRelu ? act_relu(acc[c][4 * j + 2] + bv[j].z) : act_hw(acc[c][4 * j + 2] + bv[j].z, m.act_one);
+      a[4 * j + 3] = kRelu ? act_relu(acc[c][4 * j + 3] + bv[j].w) : act_hw(acc[c][4 * j + 3] + bv[j].w, m.act_one);
       if constexpr (kLast) {
         dot += a[4 * j + 0] * wv[j].x;
         dot += a[4 * j + 1] * wv[j].y;
@@ -500,7 +513,7 @@ __device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, Sm& sm, int c0, 
   static_assert(NCH % 2 == 0, "layers must have an even number of chunks");
   // resident weights: the layer's fragments sit in LDS at roff (bf16
   // elements) for the whole kernel, so nothing is copied or waited for
-  constexpr bool kRes = std::is_same_v<Sm, MlpSmemRes>;
+  constexpr bool kRes = mlp_resident_layout<Sm>();
   const int lane = threadIdx.x & 63;
   if constexpr (kActive) {
 #pragma unroll
@@ -568,7 +581,7 @@ __device__ __forceinline__ void mlp_layer_reg(const MlpDesc& m, Sm& sm, int c0, 
 // Copies every layer's bf16 A fragments of the network into the resident
 // layout (the first layer without its zero k-step), then synchronises.
 template <int W>
-__device__ __forceinline__ void mlp_load_resident(const MlpDesc& m, MlpSmemRes& sm) {
+__device__ __forceinline__ void mlp_load_resident(const MlpDesc& m, MlpSmemRes& sm) {  // either resident layout
   const size_t n0 = mlpr_layer_offset(1, W) / 8, nh = (mlpr_layer_offset(m.depth, W) - mlpr_layer_offset(1, W)) / 8;
   const uint4* __restrict__ g0 = reinterpret_cast<const uint4*>(m.wa);
   const uint4* __restrict__ g1 = reinterpret_cast<const uint4*>(m.wa + mlpa_layer_offset(1, W));
@@ -607,12 +620,13 @@ __device__ __forceinline__ void mlp_exchange(Sm& sm, int grp, int c0, const bf16
 template <int P, int W, int S, bool kActive, class Sm>
 __device__ __forceinline__ float mlp_wave(const MlpDesc& m, Sm& sm, float px, float py, float pz) {
   constexpr int KS = W / 16, NT = W / 32 / S;
+  constexpr bool kRelu = std::is_same_v<Sm, MlpSmemResRelu>;
   const int w = threadIdx.x >> 6;
   const int grp = w / S, c0 = (w % S) * NT;
   f32x16_t acc[NT];
   bf16x8_t x[KS], xl[KS];
   {
-    if constexpr (!std::is_same_v<Sm, MlpSmemRes>) {
+    if constexpr (!mlp_resident_layout<Sm>()) {
       ChunkDma<P, W>::issue(m.wa, m.wal, sm, 0);
       ChunkDma<P, W>::wait_and_sync();
     }
@@ -626,14 +640,14 @@ __device__ __forceinline__ float mlp_wave(const MlpDesc& m, Sm& sm, float px, fl
   for (int l = 0;; ++l) {
     if (l + 1 == m.depth) {
       bf16x8_t xo[2 * NT], xol[2 * NT];  // unused by the last layer
-      if constexpr (kActive) dot = mlp_epilogue<P, W, NT, true>(m, l, c0, acc, xo, xol);
+      if constexpr (kActive) dot = mlp_epilogue<P, W, NT, true, kRelu>(m, l, c0, acc, xo, xol);
       break;
     }
     if constexpr (S == 1) {
-      if constexpr (kActive) mlp_epilogue<P, W, NT, false>(m, l, c0, acc, x, xl);
+      if constexpr (kActive) mlp_epilogue<P, W, NT, false, kRelu>(m, l, c0, acc, x, xl);
     } else {
       bf16x8_t xo[2 * NT], xol[2 * NT];
-      if constexpr (kActive) mlp_epilogue<P, W, NT, false>(m, l, c0, acc, xo, xol);
+      if constexpr (kActive) mlp_epilogue<P, W, NT, false, kRelu>(m, l, c0, acc, xo, xol);
       mlp_exchange<P, W, NT>(sm, grp, c0, xo, xol, x, xl);
     }
     const size_t o = mlpa_layer_offset(l + 1, W), on = mlpa_layer_offset(l + 2, W);
@@ -686,7 +700,7 @@ __device__ __forceinline__ void mlp_tile_split(const MlpDesc& m, Sm& sm, int nro
 template <int P, int W, class Sm>
 __device__ __forceinline__ void mlp_tile_reg(const MlpDesc& m, Sm& sm, int nrows) {
   constexpr int kS4 = W / 32 >= 4 ? 4 : W / 32;  // at least one m-tile per wave
-  if constexpr (std::is_same_v<Sm, MlpSmemRes>) {
+  if constexpr (mlp_resident_layout<Sm>()) {
     mlp_tile_split<P, W, 1>(m, sm, nrows);  // resident weights: no exchange buffer
   } else if constexpr (mlp_split_only<W, Sm>()) {
     // nrows <= 64: every layer is split over two or four waves per group

@@ -307,22 +307,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 }
 
 // The same two kernels for a small network whose weights stay resident in
-// LDS (mlp_resident_fits): loaded once per block, no copies per tile.
-template <int W>
+// LDS (mlp_resident_fits): loaded once per block, no copies per tile.  Sm is
+// MlpSmemRes, or MlpSmemResRelu for a ReLU network (max(z, 0) alone).
+template <int W, class Sm>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hop_mlp_res(
     MlpDesc m, Grid g, uint64_t* __restrict__ colmask, uint32_t* __restrict__ colbits, unsigned int* __restrict__ queue,
     gh_counters* __restrict__ ctr) {
-  __shared__ MlpSmemRes sm;
+  __shared__ Sm sm;
   __shared__ int s_cnt[kBlock / 64];
   __shared__ unsigned int s_base;
   mlp_load_resident<W>(m, sm);
   hop_mlp_pool<kPrecBf16, W>(m, g, colmask, colbits, ctr, sm, s_cnt, &s_base, QueueRays{queue, 0, (int64_t)g.n * g.n});
 }
 
-template <int W>
+template <int W, class Sm>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_corners_res(
     MlpDesc m, Grid g, Workspace ws) {
-  __shared__ MlpSmemRes sm;
+  __shared__ Sm sm;
   constexpr int R = kBf16Rows;
   const int64_t count = ws.nlist[0];
   if (count > ws.cap) return;
@@ -375,7 +376,7 @@ static hipError_t launch_mlp_w(int what, const DevSdb& d, const Grid& g, const W
           bool res = false;
           if constexpr (W == kResidentW) {
             if ((res = mlp_resident_fits(d.mlp.depth, W))) {
-              auto kr = k_mlp_corners_res<W>;
+              auto kr = d.mlp.relu ? k_mlp_corners_res<W, MlpSmemResRelu> : k_mlp_corners_res<W, MlpSmemRes>;
               hipLaunchKernelGGL(kr, dim3(mlp_grid(kr, (ws->cap + kBf16Rows - 1) / kBf16Rows)), dim3(kBlock), 0, s,
                                  d.mlp, g, *ws);
             }
@@ -409,7 +410,8 @@ static hipError_t launch_mlp_w(int what, const DevSdb& d, const Grid& g, const W
         if (d.mlp.hop_shrink && current_tuning().mlp_lean == 1) {
           k = k_hop_mlp_lean<W>;
           if constexpr (W == kResidentW)
-            if (mlp_resident_fits(d.mlp.depth, W)) k = k_hop_mlp_res<W>;
+            if (mlp_resident_fits(d.mlp.depth, W))
+              k = d.mlp.relu ? k_hop_mlp_res<W, MlpSmemResRelu> : k_hop_mlp_res<W, MlpSmemRes>;
         }
       }
       const int64_t rays = (int64_t)g.n * g.n;

@@ -279,14 +279,16 @@ def test_shrunk_bf16_hop_gives_the_fp32_mesh(gh, prec, width, n):
     assert cb["n_hop_evals"] >= 0.9 * ca["n_hop_evals"]
 
 
-@pytest.mark.parametrize("width,n", [(64, 77), (128, 100), (256, 128), (256, 512)])
+@pytest.mark.parametrize("width,n", [(64, 77), (128, 100), (256, 128), (256, 512), ("paper", 77)])
 def test_lean_layout_changes_nothing(gh, width, n):
     # the shrunk plain bf16 hop and the corner values on the lean layout (two
     # blocks per CU, at width 256 every tile split over two waves per group,
     # corner signs certified in a pass of their own) and on the full layout:
     # the same counters, candidates, vertices and triangles
+    # ("paper": the 8 x 64 ReLU network, whose width-64 kernels keep the
+    # weights resident and apply max(z, 0) alone)
     native, P = gh
-    net = W.neural_scene(0, width)
+    net = W.paper_net_scene() if width == "paper" else W.neural_scene(0, width)
     probe = W.probe_points(seed=3, n=65536)
     b = P.Bound.mlp(net, "bf16", margin=P.bf16_margin(net, probe, "bf16"), hop="shrink",
                     margin3=P.bf16_margin(net, probe, "bf16x3"))
