@@ -232,11 +232,16 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16", dense
         workload = f"mlp_w{width}_d4_f16_seed0_n{n}"
     n, lo, h = W.grid(n)
     probe = W.probe_points(seed=3, n=65536)
-    margin = bf16_margin(net, probe, precision) if precision != "fp32" else 0.0
-    # plain bf16: corner values near zero are certified by the split form first
+    # plain bf16: the measured offset of its error is removed (a smaller
+    # margin), and corner values near zero are certified by the split form first
+    offset = 0.0
+    if precision == "bf16":
+        margin, offset = bf16_margin(net, probe, precision, with_offset=True)
+    else:
+        margin = bf16_margin(net, probe, precision) if precision != "fp32" else 0.0
     margin3 = bf16_margin(net, probe, "bf16x3") if precision == "bf16" else 0.0
     poly = Polygonizer(Bound.mlp(net, precision, margin=margin if precision != "fp32" else None, device=dev, hop=hop,
-                                 margin3=margin3), n, lo, h, device=dev, keep_cells=False)
+                                 margin3=margin3, offset=offset), n, lo, h, device=dev, keep_cells=False)
     c0 = dict(poly.run().counters)
     tuning = None
     if tune:
@@ -252,7 +257,7 @@ def neural_section(dev, steps, warmup, n=512, width=256, precision="bf16", dense
     fpp = mlp_flop_per_point(width, depth, n_freq)
     flop = c0["n_hop_evals"] * fpp
     out = {"workload": workload, "precision": precision, "hop_rule": hop, "margin": margin, "margin3": margin3,
-           "tuning": tuning,
+           "offset": offset, "tuning": tuning,
            "value": n ** 3 / ((hop_ms + mc_ms) * 1e-3), "unit": "cells/s", "hop_ms": hop_ms, "mc_ms": mc_ms,
            "counters": {k: c0[k] for k in ("n_hop_evals", "n_cand", "n_reeval", "n_corner", "n_vert", "n_tri")},
            "roofline": {"bound": "mfma", "kernel": "k_hop_mlp", "achieved": flop / (hop_ms * 1e-3) / 1e12,
@@ -330,10 +335,11 @@ def batch_section(dev, steps, warmup, precision="bf16", tune=True):
             b = Bound.prims(W.csg_scene(sc["seed"], sc["n_prim"]), dev)
         else:
             net = W.neural_scene(sc["seed"], sc["width"])
-            plain = precision == "bf16"   # shrunk hop, two-step corner certification
-            b = Bound.mlp(net, precision, margin=bf16_margin(net, probe, precision), device=dev,
-                          hop="shrink" if plain else "fp32",
-                          margin3=bf16_margin(net, probe, "bf16x3") if plain else 0.0)
+            plain = precision == "bf16"   # shrunk hop, offset removed, two-step corner certification
+            margin, offset = (bf16_margin(net, probe, precision, with_offset=True) if plain
+                              else (bf16_margin(net, probe, precision), 0.0))
+            b = Bound.mlp(net, precision, margin=margin, device=dev, hop="shrink" if plain else "fp32",
+                          margin3=bf16_margin(net, probe, "bf16x3") if plain else 0.0, offset=offset)
         shapes.append((b, n, lo, h))
     tuning = None
     if tune:

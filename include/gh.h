@@ -170,6 +170,9 @@ typedef struct {
   float bf16x3_margin;           /* GH_PREC_BF16 only: eps3 >= max |f_bf16x3 - f_fp32| > 0 certifies the corner
                                     values within bf16_margin of zero in two steps, bf16x3 first and FP32 only
                                     within eps3 of zero; 0: those corners go to FP32 directly */
+  float bf16_offset;             /* GH_PREC_BF16 only: subtracted from every plain bf16 value (hop, corners,
+                                    points); with the offset gh_bf16_margin measures, bf16_margin bounds
+                                    |f_bf16 - bf16_offset - f_fp32|; 0 elsewhere */
 } gh_sdb_spec;
 
 /* Opaque, caller-owned, plain-old-data handle filled by sdb_describe.  It
@@ -320,15 +323,22 @@ gh_status gh_backward(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws
  * in bf16 adds an error that the hop test and the corner signs must also
  * absorb, and this measures it: the bound at m points xyz [m][3] in FP32 into
  * f32 [m] and in `precision` (GH_PREC_BF16 or GH_PREC_BF16X3) into flp [m],
- * both with the library's own evaluators, then
- *   *margin = factor * max_i |flp[i] - f32[i]|      (one float, device)
- * with a fixed reduction order (the same bits every run), or NaN when a value
- * or difference is not finite.  The descriptor may hold any precision (it
- * carries both weight forms).  factor in [1, 1000]; m = 0 gives 0.  Pass the
- * result as gh_sdb_spec.bf16_margin: it is a measured bound over the points
- * given, not a proof, so the points should cover the grid's cube. */
+ * both with the library's own evaluators (raw values: no bf16_offset), then,
+ * with d_i = flp[i] - f32[i],
+ *   offset NULL:  *margin = factor * max_i |d_i|
+ *   otherwise:    *offset = (max_i d_i + min_i d_i) / 2 and
+ *                 *margin = factor * (max_i d_i - min_i d_i) / 2
+ * (one float each, device) with a fixed reduction order (the same bits every
+ * run), or NaN when a value or difference is not finite.  The descriptor
+ * may hold any precision (it carries both weight forms).  factor in
+ * [1, 1000]; m = 0 gives 0.  Pass the results as gh_sdb_spec.bf16_margin
+ * and bf16_offset (the offset only for GH_PREC_BF16): the offset removes
+ * the part of the bf16 error that is the same everywhere (most of the
+ * weights' rounding), which shrinks the margin.  It is a measured bound over
+ * the points given, not a proof, so the points should cover the grid's
+ * cube. */
 gh_status gh_bf16_margin(const gh_sdb_desc* desc_h, int32_t precision, const float* xyz, int64_t m, float factor,
-                         float* f32, float* flp, float* margin, void* stream);
+                         float* f32, float* flp, float* margin, float* offset, void* stream);
 
 /* Evaluate the bound at m points xyz [m][3] (device) into f [m] (device). */
 gh_status gh_eval_points(const gh_sdb_desc* desc_h, const float* xyz, float* f, int64_t m, void* stream);

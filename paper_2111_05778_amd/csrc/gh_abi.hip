@@ -120,6 +120,9 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   if (!(sp->bf16x3_margin >= 0.f && sp->bf16x3_margin <= 1e6f)) return fail(GH_EINVAL, "bf16x3_margin must be >= 0");
   if (sp->bf16x3_margin > 0.f && sp->precision != GH_PREC_BF16)
     return fail(GH_EINVAL, "bf16x3_margin applies to GH_PREC_BF16 only");
+  if (!(fabsf(sp->bf16_offset) <= 1e6f)) return fail(GH_EINVAL, "bf16_offset must be finite");
+  if (sp->bf16_offset != 0.f && sp->precision != GH_PREC_BF16)
+    return fail(GH_EINVAL, "bf16_offset applies to GH_PREC_BF16 only");
   const int k1 = 3 + 6 * F;
   for (int l = 0; l <= D; ++l) {
     const int fi = l == 0 ? k1 : W, fo = l == D ? 1 : W;
@@ -259,6 +262,7 @@ gh_status describe_mlp(const gh_sdb_spec* sp, void* dev_blob, size_t blob_bytes,
   m.eps = sp->bf16_margin;
   m.hop_shrink = sp->precision != GH_PREC_FP32 && sp->bf16_hop == GH_BF16_HOP_SHRINK ? 1 : 0;
   m.eps3 = sp->bf16x3_margin;
+  m.off = sp->bf16_offset;
   m.relu = sp->activation == GH_ACT_RELU ? 1 : 0;
   m.act_one = m.relu ? 0.f : 1.f;
   m.split = 3;
@@ -698,7 +702,7 @@ gh_status gh_backward(const gh_sdb_desc* desc_h, const gh_grid* grid_h, void* ws
 }
 
 gh_status gh_bf16_margin(const gh_sdb_desc* desc_h, int32_t precision, const float* xyz, int64_t m, float factor,
-                         float* f32, float* flp, float* margin, void* stream) {
+                         float* f32, float* flp, float* margin, float* offset, void* stream) {
   gh::DevSdb d;
   gh_status st;
   if ((st = read_desc(desc_h, &d)) != GH_OK) return st;
@@ -709,7 +713,7 @@ gh_status gh_bf16_margin(const gh_sdb_desc* desc_h, int32_t precision, const flo
   if (!(factor >= 1.f && factor <= 1e3f)) return fail(GH_EINVAL, "factor must be in [1, 1000]");
   if (!margin || (m > 0 && (!xyz || !f32 || !flp))) return fail(GH_EINVAL, "NULL buffer");
   const int prec = precision == GH_PREC_BF16 ? gh::kPrecBf16 : gh::kPrecBf16x3;
-  return hip_status(gh::launch_bf16_margin(d, prec, xyz, m, factor, f32, flp, margin, (hipStream_t)stream),
+  return hip_status(gh::launch_bf16_margin(d, prec, xyz, m, factor, f32, flp, margin, offset, (hipStream_t)stream),
                     "bf16 margin");
 }
 

@@ -102,7 +102,7 @@ hipError_t launch_eval_points(const DevSdb& d, const float* xyz, float* f, int64
 // Network values at m points in FP32 (f32) and in bf16 precision prec (flp),
 // then factor * max |flp - f32| into *out (NaN if any value is not finite).
 hipError_t launch_bf16_margin(const DevSdb& d, int prec, const float* xyz, int64_t m, float factor, float* f32,
-                              float* flp, float* out, hipStream_t s);
+                              float* flp, float* margin, float* offset, hipStream_t s);
 // Workspace of the adjoint (gh_backward).
 constexpr int kVjpBlocks = 256;  // blocks of the network VJP, each with its own partial gradient
 struct BackwardWs {

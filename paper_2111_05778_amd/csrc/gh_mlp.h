@@ -71,6 +71,7 @@ struct MlpDesc {
   float eps;            // |f_bf16 - f_fp32| bound used by the hop test
   int hop_shrink;       // bf16 hop: 0 FP32 values for ambiguous steps, 1 steps of floor(max(|f| - eps, 0)/h)
   float eps3;           // plain bf16: |f_bf16x3 - f_fp32| bound for two-step corner certification (0: none)
+  float off;            // plain bf16: offset subtracted from every plain bf16 value (0 elsewhere)
   int pool_tiles;       // network hop: ray slots of a block, in tiles (launch shape)
   int spec_rows;        // network hop: rows of a draining tile given out as windows ahead of the rays
 };
@@ -676,8 +677,10 @@ __device__ __forceinline__ void mlp_tile_split(const MlpDesc& m, Sm& sm, int nro
   } else {
     (void)mlp_wave<P, W, S, false>(m, sm, 0.f, 0.f, 0.f);
   }
+  // plain bf16 values drop the measured offset of their error (exact for 0)
+  const float off = P == kPrecBf16 ? m.off : 0.f;
   if constexpr (S == 1) {
-    if (active && lane < 32 && row < nrows) sm.f[row] = mlp_value(m, x, y, z, m.b_out + part);
+    if (active && lane < 32 && row < nrows) sm.f[row] = mlp_value(m, x, y, z, m.b_out + part) - off;
   } else {
     if (active && lane < 32) sm.part[w % S][row] = part;
     __syncthreads();
@@ -689,7 +692,7 @@ __device__ __forceinline__ void mlp_tile_split(const MlpDesc& m, Sm& sm, int nro
       for (int span = 1; span < S; span *= 2)  // the same pairwise tree as within a wave
 #pragma unroll
         for (int q = 0; q + span < S; q += 2 * span) p[q] += p[q + span];
-      sm.f[row] = mlp_value(m, x, y, z, m.b_out + p[0]);
+      sm.f[row] = mlp_value(m, x, y, z, m.b_out + p[0]) - off;
     }
   }
   __syncthreads();

@@ -449,33 +449,50 @@ hipError_t launch_mlp(int what, const DevSdb& d0, const Grid& g, const Workspace
   }
 }
 
-// factor * max_i |b[i] - a[i]| into *out with one block in a fixed order (no
-// clearing, the same bits every run); NaN when a value or difference is not
+// The margin of b against a with one block in a fixed order (no clearing,
+// the same bits every run): with d_i = b[i] - a[i], factor * max |d_i| into
+// *out, or with off non-null (max d + min d) / 2 into *off and factor *
+// (max d - min d) / 2 into *out; NaN when a value or difference is not
 // finite, so that the margin cannot pass for a valid one.
 __global__ __launch_bounds__(1024) void k_margin(const float* __restrict__ a, const float* __restrict__ b, int64_t m,
-                                                 float factor, float* __restrict__ out) {
-  __shared__ float s_max[1024];
-  float mx = 0.f;
+                                                 float factor, float* __restrict__ out, float* __restrict__ off) {
+  __shared__ float s_max[1024], s_min[1024];
+  float mx = -FLT_MAX, mn = FLT_MAX;
   int bad = 0;
   for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
-    const float d = fabsf(b[i] - a[i]);
-    bad |= !(d <= FLT_MAX);
+    const float d = b[i] - a[i];
+    bad |= !(fabsf(d) <= FLT_MAX);
     mx = fmaxf(mx, d);
+    mn = fminf(mn, d);
   }
   bad = __syncthreads_or(bad);
   s_max[threadIdx.x] = mx;
+  s_min[threadIdx.x] = mn;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s_max[threadIdx.x] = fmaxf(s_max[threadIdx.x], s_max[threadIdx.x + w]);
+    if ((int)threadIdx.x < w) {
+      s_max[threadIdx.x] = fmaxf(s_max[threadIdx.x], s_max[threadIdx.x + w]);
+      s_min[threadIdx.x] = fminf(s_min[threadIdx.x], s_min[threadIdx.x + w]);
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = bad ? __builtin_nanf("") : factor * s_max[0];
+  if (threadIdx.x == 0) {
+    const float hi = m > 0 ? s_max[0] : 0.f, lo = m > 0 ? s_min[0] : 0.f;
+    const float nan = __builtin_nanf("");
+    if (off) {
+      *off = bad ? nan : 0.5f * (hi + lo);
+      *out = bad ? nan : factor * (0.5f * (hi - lo));
+    } else {
+      *out = bad ? nan : factor * fmaxf(hi, -lo);
+    }
+  }
 }
 
 hipError_t launch_bf16_margin(const DevSdb& d0, int prec, const float* xyz, int64_t m, float factor, float* f32,
-                              float* flp, float* out, hipStream_t s) {
+                              float* flp, float* out, float* off, hipStream_t s) {
   if (d0.kind != GH_SDB_MLP) return hipErrorInvalidValue;
   DevSdb d = d0;
+  d.mlp.off = 0.f;  // raw values: the offset is what is being measured
   hipError_t e = hipSuccess;
   if (m > 0) {
     d.mlp.precision = kPrecF32;
@@ -483,7 +500,7 @@ hipError_t launch_bf16_margin(const DevSdb& d0, int prec, const float* xyz, int6
     d.mlp.precision = prec;
     if ((e = launch_mlp(0, d, Grid{}, nullptr, nullptr, xyz, flp, m, nullptr, s)) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_margin, dim3(1), dim3(1024), 0, s, f32, flp, m, factor, out);
+  hipLaunchKernelGGL(k_margin, dim3(1), dim3(1024), 0, s, f32, flp, m, factor, out, off);
   return hipGetLastError();
 }
 

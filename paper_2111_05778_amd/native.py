@@ -52,7 +52,7 @@ class gh_sdb_spec(ctypes.Structure):
                 ("biases_h", ctypes.POINTER(ctypes.POINTER(ctypes.c_float))),
                 ("a_s", ctypes.c_float), ("r0", ctypes.c_float), ("a_n", ctypes.c_float), ("b", ctypes.c_float),
                 ("bf16_margin", ctypes.c_float), ("activation", ctypes.c_int32), ("bf16_hop", ctypes.c_int32),
-                ("bf16x3_margin", ctypes.c_float)]
+                ("bf16x3_margin", ctypes.c_float), ("bf16_offset", ctypes.c_float)]
 
 
 class gh_tuning(ctypes.Structure):
@@ -213,9 +213,9 @@ def gh_eval_points(desc, xyz, f, m, stream=None):
     return lib.gh_eval_points(ctypes.byref(desc), ptr(xyz), ptr(f), int(m), stream_handle(stream))
 
 
-def gh_bf16_margin(desc, precision, xyz, m, factor, f32, flp, margin, stream=None):
+def gh_bf16_margin(desc, precision, xyz, m, factor, f32, flp, margin, offset=None, stream=None):
     return lib.gh_bf16_margin(ctypes.byref(desc), int(precision), ptr(xyz), int(m), float(factor), ptr(f32), ptr(flp),
-                              ptr(margin), stream_handle(stream))
+                              ptr(margin), ptr(offset), stream_handle(stream))
 
 
 def gh_set_tuning(hop_lanes_per_ray=0, scan_blocks_per_cu=0, batch_rays_per_item=0, mlp_split=0,

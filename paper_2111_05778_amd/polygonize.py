@@ -38,7 +38,7 @@ class Bound:
         return Bound(spec, [rec], device)
 
     @staticmethod
-    def mlp(net, precision="fp32", margin=None, device="cuda", hop="fp32", margin3=0.0):
+    def mlp(net, precision="fp32", margin=None, device="cuda", hop="fp32", margin3=0.0, offset=0.0):
         """Neural bound f = a_s (||p|| - r0) + a_n NN(gamma(p)) + b.
 
         net: dict with "omegas" (F), "weights" (depth+1 arrays, fan_out x
@@ -53,7 +53,10 @@ class Bound:
         floor(max(|f| - margin, 0)/h) from the bf16 value alone).
         margin3 (plain bf16 only): eps3 >= |f_bf16x3 - f_fp32|; corner values
         within margin of zero are then certified by a split-bf16 value first
-        and go to FP32 only within margin3 of zero (0: FP32 directly)."""
+        and go to FP32 only within margin3 of zero (0: FP32 directly).
+        offset (plain bf16 only): subtracted from every bf16 value; measure it
+        with the margin, bf16_margin(..., with_offset=True), which then
+        bounds |f_bf16 - offset - f_fp32|."""
         if precision != "fp32" and margin is None:
             raise ValueError(f"precision {precision!r} needs a margin: pass margin=bf16_margin(net, points, "
                              f"{precision!r}) with points covering the grid's cube")
@@ -77,6 +80,7 @@ class Bound:
         spec.bf16_margin = float(margin or 0.0)
         spec.bf16_hop = {"fp32": N.GH_BF16_HOP_FP32, "shrink": N.GH_BF16_HOP_SHRINK}[hop]
         spec.bf16x3_margin = float(margin3)
+        spec.bf16_offset = float(offset)
         return Bound(spec, [ws, bs, om, wptr, bptr], device)
 
     def eval(self, xyz):
@@ -87,19 +91,25 @@ class Bound:
         return f
 
 
-def bf16_margin(net, points, precision="bf16", factor=2.0, device="cuda"):
+def bf16_margin(net, points, precision="bf16", factor=2.0, device="cuda", with_offset=False):
     """Margin of the bf16 decisions: factor * max |f_bf16 - f_fp32| over the
     given points, computed by gh_bf16_margin with the library's own
-    evaluators (one call; the result is read back)."""
+    evaluators (one call; the result is read back).  with_offset: returns
+    (margin, offset), offset the midrange of f_bf16 - f_fp32 and margin
+    factor times half its range, to pass as Bound.mlp(margin=, offset=)."""
     pts = torch.as_tensor(np.asarray(points, dtype=np.float32), device=device).reshape(-1, 3).contiguous()
     m = pts.shape[0]
     bound = Bound.mlp(net, "fp32", device=device)
     f32 = torch.empty(max(m, 1), dtype=torch.float32, device=device)
     flp = torch.empty(max(m, 1), dtype=torch.float32, device=device)
-    out = torch.empty(1, dtype=torch.float32, device=device)
+    out = torch.empty(2, dtype=torch.float32, device=device)
     prec = {"bf16": N.GH_PREC_BF16, "bf16x3": N.GH_PREC_BF16X3}[precision]
-    N.check(N.gh_bf16_margin(bound.desc, prec, pts, m, factor, f32, flp, out), "gh_bf16_margin")
-    return float(out.item())
+    N.check(N.gh_bf16_margin(bound.desc, prec, pts, m, factor, f32, flp, out[0:1], out[1:2] if with_offset else None),
+            "gh_bf16_margin")
+    if with_offset:
+        margin, offset = out.tolist()
+        return margin, offset
+    return float(out[0].item())
 
 
 def counters_dict(ctr):

@@ -154,7 +154,23 @@ def test_bf16_network_needs_a_positive_margin():
     assert N.lib.sdb_describe(ctypes.byref(s), None, 0, ctypes.byref(need), None, None) == N.GH_OK
 
 
+def test_bf16_offset_only_for_plain_bf16():
+    # the offset is a property of the plain bf16 evaluation error
+    net = W.mlp_net(seed=0, width=64, depth=2, n_freq=2)
+    net.update(a_s=1.0, r0=0.5, a_n=0.01, b=0.0)
+    need = ctypes.c_size_t(0)
+    for prec, margin, offset, want in ((N.GH_PREC_BF16, 1e-3, 2e-4, N.GH_OK),
+                                       (N.GH_PREC_BF16, 1e-3, float("nan"), N.GH_EINVAL),
+                                       (N.GH_PREC_BF16, 1e-3, float("inf"), N.GH_EINVAL),
+                                       (N.GH_PREC_BF16X3, 1e-3, 2e-4, N.GH_EINVAL),
+                                       (N.GH_PREC_FP32, 0.0, 2e-4, N.GH_EINVAL)):
+        s, keep = _mlp_spec(net, prec, margin)
+        s.bf16_offset = offset
+        assert N.lib.sdb_describe(ctypes.byref(s), None, 0, ctypes.byref(need), None, None) == want, (prec, offset)
+
+
 def test_bf16_margin_validates_before_enqueuing():
     desc = N.gh_sdb_desc()
-    st = N.lib.gh_bf16_margin(ctypes.byref(desc), N.GH_PREC_BF16, None, 0, 2.0, None, None, ctypes.c_void_p(256), None)
+    st = N.lib.gh_bf16_margin(ctypes.byref(desc), N.GH_PREC_BF16, None, 0, 2.0, None, None, ctypes.c_void_p(256), None,
+                              None)
     assert st == N.GH_EINVAL and b"sdb_describe" in N.lib.gh_last_error()

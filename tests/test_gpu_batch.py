@@ -40,14 +40,15 @@ def _bound(P, sc, precision, margin_cache):
     net = W.neural_scene(sc["seed"], sc["width"])
     margin = None
 
-    def measured(prec):
-        key = (sc["seed"], sc["width"], prec)
+    def measured(prec, with_offset=False):
+        key = (sc["seed"], sc["width"], prec, with_offset)
         if key not in margin_cache:
-            margin_cache[key] = P.bf16_margin(net, W.probe_points(seed=3, n=65536), prec)
+            margin_cache[key] = P.bf16_margin(net, W.probe_points(seed=3, n=65536), prec, with_offset=with_offset)
         return margin_cache[key]
 
-    if precision == "bf16":  # plain bf16: shrunk hop, two-step corner certification
-        return P.Bound.mlp(net, precision, margin=measured("bf16"), hop="shrink", margin3=measured("bf16x3"))
+    if precision == "bf16":  # plain bf16: shrunk hop, offset removed, two-step corner certification
+        margin, offset = measured("bf16", True)
+        return P.Bound.mlp(net, precision, margin=margin, hop="shrink", margin3=measured("bf16x3"), offset=offset)
     if precision != "fp32":
         margin = measured(precision)
     return P.Bound.mlp(net, precision, margin=margin)

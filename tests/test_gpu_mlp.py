@@ -307,6 +307,34 @@ def test_lean_layout_changes_nothing(gh, width, n):
     np.testing.assert_array_equal(lean["verts"].view(np.uint64), full["verts"].view(np.uint64))
 
 
+@pytest.mark.parametrize("width,n", [(64, 77), (256, 128), (256, 512)])
+def test_offset_removed_from_bf16_values(gh, width, n):
+    """Plain bf16 with the measured offset of its error removed: the margin of
+    the offset values is at most the plain one, |f_bf16 - offset - f_fp32|
+    stays within it on other points, and the shrunk hop with two-step
+    signs still gives the FP32 path's cells, cases, edges and triangles."""
+    import torch
+    native, P = gh
+    net = W.neural_scene(0, width)
+    probe = W.probe_points(seed=3, n=65536)
+    eps_plain = P.bf16_margin(net, probe, "bf16")
+    eps, off = P.bf16_margin(net, probe, "bf16", with_offset=True)
+    eps3 = P.bf16_margin(net, probe, "bf16x3")
+    print(f"w{width}: margin {eps_plain:.3e} plain, {eps:.3e} after the offset {off:.3e}", flush=True)
+    assert 0 < eps <= eps_plain
+    b = P.Bound.mlp(net, "bf16", margin=eps, hop="shrink", margin3=eps3, offset=off)
+    pts = torch.tensor(_points(20000, seed=8), device="cuda")
+    f32 = P.Bound.mlp(net, "fp32").eval(pts).cpu().numpy().astype(np.float64)
+    fb = b.eval(pts).cpu().numpy().astype(np.float64)
+    assert np.abs(fb - f32).max() <= eps
+    g = W.grid(n)
+    a = _run(gh, P.Bound.mlp(net, "fp32"), *g)
+    c = _run(gh, b, *g)
+    assert c["ctr"]["flags"] == 0 and np.all(np.isin(a["cells"], c["cand"]))
+    for key in ("cells", "cases", "edge", "tri_e"):
+        np.testing.assert_array_equal(a[key], c[key])
+
+
 @pytest.mark.parametrize("n", [128, 512])
 def test_two_step_corner_certification(gh, n):
     """Plain bf16 with the split form's margin eps3: corner values within eps
