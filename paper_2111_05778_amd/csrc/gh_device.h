@@ -306,16 +306,26 @@ struct ScanOut {
   uint64_t total;  // inclusive prefix at the end of this tile
 };
 
-// The whole block does the look-back, kBlock * 4 predecessors per round:
-// thread t reads the words of tiles base - 4t - r, r = 0..3 (distance 0 is
-// the closest).  The closest predecessor holding an inclusive prefix ends
-// the walk; every word before it must at least hold its aggregate, else the
-// round is retried.  Tiles before 0 read as prefix 0.  All tiles of a kernel
-// start at about the same time, so one wide round replaces a long chain of
-// narrow ones.  The wait is bounded: should it exceed kSpinLimit rounds
-// (only possible through a library bug), *err gets GH_FLAG_INTERNAL and the
-// tile carries on with a partial prefix; every write stays inside its
-// capacity check, so the result is flagged rather than the device hung.
+// The whole block does the look-back over a window of kBlock * 4
+// predecessors, thread t reading the words of tiles base - (r kBlock + t),
+// r = 0..3 (distance 0 is the closest), so that consecutive lanes read
+// consecutive words and a wave's load touches four cache lines.  A round
+// consumes the words nearer than the closest unpublished one, up to and
+// including the closest inclusive prefix; tiles before 0 read as prefix 0.
+// A round that stopped at an unpublished word polls that word alone until it
+// is published, then takes the next window from there.  All tiles of a kernel
+// start at about the same time, so one wide window replaces a long chain of
+// narrow ones, and the polls of waiting tiles stay one word each.  The wait is
+// bounded: should it exceed kSpinLimit polls (only possible through a library
+// bug), *err gets GH_FLAG_INTERNAL and the tile carries on with a partial
+// prefix; every write stays inside its capacity check, so the result is
+// flagged rather than the device hung.
+//
+// The scan comes in two halves so that a tile can do work that needs only
+// its own offsets (staging outputs in LDS) while its predecessors finish:
+// block_scan_publish scans the block and publishes the tile's aggregate,
+// block_lookback returns the tile's base.  A coherent load of a look-back
+// word takes microseconds while marching cubes keep memory busy.
 constexpr int kSpinLimit = 1 << 22;
 constexpr int kLookWindow = kBlock * 4;
 
@@ -323,17 +333,18 @@ struct NoAggHook {
   __device__ void operator()(uint64_t) const {}
 };
 
+struct LocalScan {
+  uint64_t excl;  // exclusive prefix of this thread within the tile
+  uint64_t agg;   // the tile's total
+};
+
 // on_agg(tile aggregate) runs in thread 0 before the tile publishes it.
 template <class OnAgg = NoAggHook>
-__device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* flags, int tile, unsigned int* err,
-                                                       OnAgg on_agg = OnAgg{}) {
+__device__ __forceinline__ LocalScan block_scan_publish(uint64_t v, uint64_t* flags, int tile,
+                                                        OnAgg on_agg = OnAgg{}) {
   __shared__ uint64_t s_wave[kBlock / 64];
-  __shared__ uint64_t s_sum[kBlock / 64];
-  __shared__ int s_first, s_empty;
-  __shared__ uint64_t s_prev;
   const uint64_t incl = wave_incl_scan_u64(v);
   if (lane_id() == 63) s_wave[wave_id()] = incl;
-  if (threadIdx.x == 0) s_prev = 0;
   __syncthreads();
   uint64_t wave_off = 0, agg = 0;
 #pragma unroll
@@ -342,74 +353,99 @@ __device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* fla
     if (w < wave_id()) wave_off += s;
     agg += s;
   }
-  if (threadIdx.x == 0) on_agg(agg);
-  if (tile == 0) {
-    if (threadIdx.x == 0)
-      __hip_atomic_store(&flags[0], kScanPrefix | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    if (threadIdx.x == 0)
-      __hip_atomic_store(&flags[tile], kScanAgg | (agg & kScanValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int base = tile - 1;
-    int spins = 0;
-    while (true) {
-      uint64_t f[4];
-      int first = kLookWindow;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int pos = 4 * (int)threadIdx.x + r;
-        const int j = base - pos;
-        f[r] = j >= 0 ? __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanPrefix;
-        if ((f[r] & ~kScanValMask) == kScanPrefix && pos < first) first = pos;
-      }
-      if (threadIdx.x == 0) {
-        s_first = kLookWindow;
-        s_empty = 0;
-      }
+  if (threadIdx.x == 0) {
+    on_agg(agg);
+    __hip_atomic_store(&flags[tile], (tile == 0 ? kScanPrefix : kScanAgg) | (agg & kScanValMask), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();  // s_wave is free for the next tile
+  return {wave_off + incl - v, agg};
+}
+
+// The tile's exclusive prefix over the grid; agg is its published total.
+__device__ __forceinline__ uint64_t block_lookback(uint64_t* flags, int tile, uint64_t agg, unsigned int* err) {
+  __shared__ uint64_t s_sum[kBlock / 64];
+  __shared__ int s_first, s_empty, s_ready;
+  __shared__ uint64_t s_prev;
+  if (tile == 0) return 0;
+  if (threadIdx.x == 0) s_prev = 0;
+  int base = tile - 1;
+  int spins = 0;
+  bool probe = false;  // the last round stopped at an unpublished word: poll that one first
+  while (true) {
+    if (probe) {
+      if (threadIdx.x == 0)
+        s_ready = (__hip_atomic_load(&flags[base], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ~kScanValMask) != 0;
       __syncthreads();
-      if (first < kLookWindow) atomicMin(&s_first, first);
+      const bool ready = s_ready != 0;
       __syncthreads();
-      first = s_first;
-      uint64_t part = 0;
-      bool empty = false;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int pos = 4 * (int)threadIdx.x + r;
-        if (pos > first) continue;
-        if ((f[r] & ~kScanValMask) == 0) empty = true;
-        part += f[r] & kScanValMask;
-      }
-      if (empty) s_empty = 1;
-      part = wave_sum_u64(part);
-      if (lane_id() == 0) s_sum[wave_id()] = part;
-      __syncthreads();
-      const bool retry = s_empty != 0;
-      if (retry) {
+      if (!ready) {
         if (++spins > kSpinLimit) {
           if (threadIdx.x == 0) atomicOr(err, GH_FLAG_INTERNAL);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        __syncthreads();
         continue;
       }
-      if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        for (int w = 0; w < kBlock / 64; ++w) t += s_sum[w];
-        s_prev += t;
-      }
-      __syncthreads();
-      if (first < kLookWindow) break;
-      base -= kLookWindow;
     }
-    if (threadIdx.x == 0)
-      __hip_atomic_store(&flags[tile], kScanPrefix | ((s_prev + agg) & kScanValMask), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t f[4];
+    int first = kLookWindow, empty = kLookWindow;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pos = r * kBlock + (int)threadIdx.x;
+      const int j = base - pos;
+      f[r] = j >= 0 ? __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanPrefix;
+      const uint64_t st = f[r] & ~kScanValMask;
+      if (st == kScanPrefix && pos < first) first = pos;
+      if (st == 0 && pos < empty) empty = pos;
+    }
+    if (threadIdx.x == 0) {
+      s_first = kLookWindow;
+      s_empty = kLookWindow;
+    }
+    __syncthreads();
+    if (first < kLookWindow) atomicMin(&s_first, first);
+    if (empty < kLookWindow) atomicMin(&s_empty, empty);
+    __syncthreads();
+    first = s_first;
+    empty = s_empty;
+    const int last = first < empty ? first : empty - 1;
+    uint64_t part = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (r * kBlock + (int)threadIdx.x <= last) part += f[r] & kScanValMask;
+    part = wave_sum_u64(part);
+    if (lane_id() == 0) s_sum[wave_id()] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+      for (int w = 0; w < kBlock / 64; ++w) t += s_sum[w];
+      s_prev += t;
+    }
+    __syncthreads();
+    if (first < empty) break;
+    base -= empty;  // the closest unpublished word, or past the whole window
+    probe = empty < kLookWindow;
   }
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&flags[tile], kScanPrefix | ((s_prev + agg) & kScanValMask), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
+  const uint64_t prev = s_prev;
+  __syncthreads();  // s_prev is free for the next tile
+  return prev;
+}
+
+// Both halves back to back.
+template <class OnAgg = NoAggHook>
+__device__ __forceinline__ ScanOut block_scan_lookback(uint64_t v, uint64_t* flags, int tile, unsigned int* err,
+                                                       OnAgg on_agg = OnAgg{}) {
+  const LocalScan ls = block_scan_publish(v, flags, tile, on_agg);
+  const uint64_t base = block_lookback(flags, tile, ls.agg, err);
   ScanOut o;
-  o.excl = s_prev + wave_off + incl - v;
-  o.base = s_prev;
-  o.total = s_prev + agg;
+  o.excl = base + ls.excl;
+  o.base = base;
+  o.total = base + ls.agg;
   return o;
 }
 

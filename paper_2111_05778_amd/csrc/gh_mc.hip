@@ -460,47 +460,61 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
       if (zn && ((fn < 0.f) != neg)) msk[r] |= 4u;
       cnt += __popc(msk[r]);
     }
-    const ScanOut so = block_scan_lookback(cnt, scan_verts(ws), tile, &ctr->flags);
-    const int64_t vbase = (int64_t)so.base, tile_v = (int64_t)(so.total - so.base);
+    const LocalScan ls = block_scan_publish(cnt, scan_verts(ws), tile);
+    const int64_t tile_v = (int64_t)ls.agg;
     const bool stage = tile_v <= kStageV;
-    int64_t v = (int64_t)so.excl;
+    // Vertices of item r from vertex vv on (a place in the tile's stage or
+    // in the output).
+    auto put_verts = [&](int r, int64_t vv, bool staged) {
+      const int L = Ls[r], k = ks[r];
+      const int a = L / n1, b = L - a * n1;
+      const float fa = fs[r];
+      const float xa = lattice(g, a), ya = lattice(g, b), za = lattice(g, k);
+      const int64_t pid = ((int64_t)L * n1 + k) * 3;
+#pragma unroll
+      for (int axis = 0; axis < 3; ++axis) {
+        if (!((msk[r] >> axis) & 1)) continue;
+        const float fb = fe[r][axis];
+        const float t = fa / (fa - fb);
+        const float px = axis == 0 ? xa + t * g.h : xa;
+        const float py = axis == 1 ? ya + t * g.h : ya;
+        const float pz = axis == 2 ? za + t * g.h : za;
+        if (staged) {
+          s_v[3 * vv + 0] = px;
+          s_v[3 * vv + 1] = py;
+          s_v[3 * vv + 2] = pz;
+          s_e[vv] = pid + axis;
+          s_t[vv] = t;
+        } else {
+          verts[3 * vv + 0] = px;
+          verts[3 * vv + 1] = py;
+          verts[3 * vv + 2] = pz;
+          if (vert_edge) vert_edge[vv] = pid + axis;
+          if (vert_t) vert_t[vv] = t;
+        }
+        ++vv;
+      }
+    };
+    // A staged tile computes its vertices into LDS before the look-back, so
+    // that this work overlaps the wait for the predecessors.
+    if (stage) {
+      int64_t lv = (int64_t)ls.excl;
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        if (c0 + r >= m) break;
+        if (msk[r]) put_verts(r, lv, true);
+        lv += __popc(msk[r]);
+      }
+    }
+    const int64_t vbase = (int64_t)block_lookback(scan_verts(ws), tile, ls.agg, &ctr->flags);
+    const uint64_t total = (uint64_t)vbase + ls.agg;
+    int64_t v = vbase + (int64_t)ls.excl;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const int64_t ci = c0 + r;
       if (ci >= m) break;
       ws.cinfo[ci] = cinfo_pack(v, msk[r], fs[r] < 0.f);
-      if (msk[r] && (stage || v + __popc(msk[r]) <= vert_cap)) {
-        const int L = Ls[r], k = ks[r];
-        const int a = L / n1, b = L - a * n1;
-        const float fa = fs[r];
-        const float xa = lattice(g, a), ya = lattice(g, b), za = lattice(g, k);
-        const int64_t pid = ((int64_t)L * n1 + k) * 3;
-        int64_t vv = v;
-#pragma unroll
-        for (int axis = 0; axis < 3; ++axis) {
-          if (!((msk[r] >> axis) & 1)) continue;
-          const float fb = fe[r][axis];
-          const float t = fa / (fa - fb);
-          const float px = axis == 0 ? xa + t * g.h : xa;
-          const float py = axis == 1 ? ya + t * g.h : ya;
-          const float pz = axis == 2 ? za + t * g.h : za;
-          if (stage) {
-            const int64_t lv = vv - vbase;
-            s_v[3 * lv + 0] = px;
-            s_v[3 * lv + 1] = py;
-            s_v[3 * lv + 2] = pz;
-            s_e[lv] = pid + axis;
-            s_t[lv] = t;
-          } else {
-            verts[3 * vv + 0] = px;
-            verts[3 * vv + 1] = py;
-            verts[3 * vv + 2] = pz;
-            if (vert_edge) vert_edge[vv] = pid + axis;
-            if (vert_t) vert_t[vv] = t;
-          }
-          ++vv;
-        }
-      }
+      if (!stage && msk[r] && v + __popc(msk[r]) <= vert_cap) put_verts(r, v, false);
       v += __popc(msk[r]);
     }
     __syncthreads();
@@ -513,8 +527,8 @@ __global__ __launch_bounds__(kBlock) void k_verts(Grid g, Workspace ws, float* _
         for (int64_t i = threadIdx.x; i < nv; i += kBlock) vert_t[vbase + i] = s_t[i];
     }
     if (threadIdx.x == 0 && tile == ntiles - 1) {
-      ctr->n_vert = (int64_t)so.total;
-      if (so.total > (uint64_t)vert_cap) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
+      ctr->n_vert = (int64_t)total;
+      if (total > (uint64_t)vert_cap) atomicOr(&ctr->flags, GH_FLAG_CAPACITY);
     }
   }
 }
@@ -637,45 +651,60 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
     // most 5 n^3) can reach 2^31, as in the corner pass
     unsigned long long* const pc = pack_counts(ws);
     const bool exact = (int64_t)5 * n * n * n >= ((int64_t)1 << 31);
-    const ScanOut so = block_scan_lookback(pack, scan_tris(ws), tile, &ctr->flags, [pc, exact](uint64_t agg) {
+    const LocalScan ls = block_scan_publish(pack, scan_tris(ws), tile, [pc, exact](uint64_t agg) {
       if (!exact) return;
       atomicAdd(&pc[2], (unsigned long long)(agg & 0x7fffffffull));
       atomicAdd(&pc[3], (unsigned long long)(agg >> 31));
       counts_done();
     });
-    int64_t t0 = (int64_t)(so.excl & 0x7fffffffull), c = (int64_t)(so.excl >> 31);
-    const int64_t tbase = (int64_t)(so.base & 0x7fffffffull), cbase = (int64_t)(so.base >> 31);
-    const int64_t tile_t = (int64_t)(so.total & 0x7fffffffull) - tbase;
-    const int64_t tile_c = (int64_t)(so.total >> 31) - cbase;
-    const bool wrapped = tile_t < 0 || tile_c < 0;  // a field wrapped here: the pass is void, write nothing
+    const int64_t tile_t = (int64_t)(ls.agg & 0x7fffffffull), tile_c = (int64_t)(ls.agg >> 31);
+    const int64_t lt = (int64_t)(ls.excl & 0x7fffffffull), lc = (int64_t)(ls.excl >> 31);  // within the tile
     const bool stage = tile_t <= kStageT;  // the cells always fit: at most one per candidate
+    // Welded vertex ids of item r's triangles, from triangle t on.
+    auto put_tris = [&](int r, int64_t t, int32_t* __restrict__ dst) {
+      const McCase mcc = s_mc[cs[r]];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      if (!nt[r]) continue;
-      if (verts_ok && !wrapped) {
-        s_cell[c - cbase] = cell[r];
-        s_case[c - cbase] = (uint8_t)cs[r];
-        if (stage || t0 + (int64_t)nt[r] <= tri_cap) {
-          const McCase mcc = s_mc[cs[r]];
+      for (unsigned tq = 0; tq < 5; ++tq) {
+        if (tq >= nt[r]) break;
 #pragma unroll
-          for (unsigned tq = 0; tq < 5; ++tq) {
-            if (tq >= nt[r]) break;
+        for (int v = 0; v < 3; ++v) {
+          const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
+          const int lcr = (int)((kEdgeLower >> (3 * e)) & 7), axis = e >> 2;
+          uint32_t in = C[r].info[0];
 #pragma unroll
-            for (int v = 0; v < 3; ++v) {
-              const int e = (int)((mcc.tri >> (12 * tq + 4 * v)) & 15);
-              const int lc = (int)((kEdgeLower >> (3 * e)) & 7), axis = e >> 2;
-              uint32_t in = C[r].info[0];
-#pragma unroll
-              for (int q = 1; q < 7; ++q) in = lc == q ? C[r].info[q] : in;
-              const int32_t vid = (int32_t)(cinfo_vbase(in) + __popc(cinfo_mask(in) & ((1u << axis) - 1u)));
-              if (stage) s_tri[3 * (t0 - tbase + tq) + v] = vid;
-              else tris[3 * (t0 + tq) + v] = vid;
-            }
-          }
+          for (int q = 1; q < 7; ++q) in = lcr == q ? C[r].info[q] : in;
+          dst[3 * (t + tq) + v] = (int32_t)(cinfo_vbase(in) + __popc(cinfo_mask(in) & ((1u << axis) - 1u)));
         }
       }
-      t0 += nt[r];
-      ++c;
+    };
+    // Cells, cases and a staged tile's triangles go to LDS at their places in
+    // the tile before the look-back, so that this work overlaps the wait for
+    // the predecessors; only the flush needs the tile's place in the lists.
+    if (verts_ok) {
+      int64_t t = lt, c = lc;
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        if (!nt[r]) continue;
+        s_cell[c] = cell[r];
+        s_case[c] = (uint8_t)cs[r];
+        if (stage) put_tris(r, t, s_tri);
+        t += nt[r];
+        ++c;
+      }
+    }
+    const uint64_t base = block_lookback(scan_tris(ws), tile, ls.agg, &ctr->flags);
+    const uint64_t total = base + ls.agg;
+    const int64_t tbase = (int64_t)(base & 0x7fffffffull), cbase = (int64_t)(base >> 31);
+    // a field wrapped here: the pass is void, write nothing
+    const bool wrapped = (int64_t)(total & 0x7fffffffull) < tbase || (int64_t)(total >> 31) < cbase;
+    if (verts_ok && !wrapped && !stage) {
+      int64_t t0 = tbase + lt;
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        if (!nt[r]) continue;
+        if (t0 + (int64_t)nt[r] <= tri_cap) put_tris(r, t0, tris);
+        t0 += nt[r];
+      }
     }
     __syncthreads();
     if (verts_ok && !wrapped) {
@@ -690,7 +719,7 @@ __global__ __launch_bounds__(kBlock) void k_tris(Grid g, Workspace ws, int32_t* 
         for (int64_t i = threadIdx.x; i < nc; i += kBlock) cases[cbase + i] = s_case[i];
     }
     if (threadIdx.x == 0 && tile == ntiles - 1) {
-      int64_t tt = (int64_t)(so.total & 0x7fffffffull), tc = (int64_t)(so.total >> 31);
+      int64_t tt = (int64_t)(total & 0x7fffffffull), tc = (int64_t)(total >> 31);
       if (exact) {
         const unsigned long long et = __hip_atomic_load(&pc[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long ec = __hip_atomic_load(&pc[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
