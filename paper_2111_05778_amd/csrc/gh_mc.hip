@@ -159,21 +159,23 @@ __device__ __forceinline__ void walk_corner_words(const LatAdj& A, const uint32_
 
 // Outputs a tile stages in LDS before writing them out with coalesced stores
 // (a tile's outputs are one contiguous range of each list); a tile with more
-// writes its entries directly.
-// Outputs a tile stages in LDS before writing them out with coalesced stores
-// (a tile's outputs are one contiguous range of each list); a tile with more
-// writes its entries directly.
-constexpr int kStageCorners = 2048;
-constexpr int kStageCands = 1024;
+// writes its entries directly.  A staged entry is one 32-bit word, the
+// thread's index in the tile above a 12-bit corner or cell index k (k <= n
+// <= 2048); the flush rebuilds the list values from the tile's first column.
+constexpr int kStageCorners = 4096;
+constexpr int kStageCands = 3072;
+constexpr int kStageKBits = 12;
+static_assert(kBlock <= (1 << (32 - kStageKBits)), "thread index field");
+static_assert(kMaxN < (1 << kStageKBits), "corner index field");
+static_assert(kBlock == kLatTile, "a corner tile is one block of lattice columns");
 
 // One thread per lattice column (a, b): its corner words, their starting
 // list indices, its corners, and, when (a, b) is also a cell column, its
 // candidate cells.  One packed scan: (candidates << 31) | corners.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_corners(Grid g, Workspace ws,
                                                                                         gh_counters* __restrict__ ctr) {
-  __shared__ __align__(16) int32_t s_ck[kStageCorners];
-  __shared__ __align__(16) int32_t s_cl[kStageCorners];
-  __shared__ int64_t s_cand[kStageCands];
+  __shared__ __align__(16) uint32_t s_c[kStageCorners];
+  __shared__ uint32_t s_k[kStageCands];
   const int n = g.n, n1 = n + 1;
   const size_t ncol = (size_t)n * n, nl = (size_t)n1 * n1;
   // A new pass: the capacity flag of an earlier one goes.  Every tile that
@@ -209,29 +211,44 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   // totals, which the last tile compares with the scan's.
   unsigned long long* const pc = pack_counts(ws);
   const bool exact = (int64_t)n1 * n1 * n1 >= ((int64_t)1 << 31);
-  const ScanOut so = block_scan_lookback((ncand << 31) | ncorner, scan_corners(ws), tile, &ctr->flags,
-                                         [pc, exact](uint64_t agg) {
-                                           if (!exact) return;
-                                           atomicAdd(&pc[0], (unsigned long long)(agg & 0x7fffffffull));
-                                           atomicAdd(&pc[1], (unsigned long long)(agg >> 31));
-                                           counts_done();
-                                         });
-  const uint64_t c0 = so.excl & 0x7fffffffull, k0 = so.excl >> 31;
-  const uint64_t cbase = so.base & 0x7fffffffull, kbase = so.base >> 31;
-  // a field that wrapped inside this tile: the pass is void (flagged by the
-  // last tile), and this tile writes nothing
-  const bool wrapped = (so.total & 0x7fffffffull) < cbase || (so.total >> 31) < kbase;
-  const uint64_t tile_c = (so.total & 0x7fffffffull) - cbase, tile_k = (so.total >> 31) - kbase;
-  const bool stage_c = !wrapped && tile_c <= (uint64_t)kStageCorners;
-  const bool stage_k = !wrapped && tile_k <= (uint64_t)kStageCands;
-  const bool fits = !wrapped && L < nl && c0 + ncorner <= (uint64_t)ws.cap;
-  int64_t o = (int64_t)c0, oc = (int64_t)k0;
+  const LocalScan ls = block_scan_publish((ncand << 31) | ncorner, scan_corners(ws), tile, [pc, exact](uint64_t agg) {
+    if (!exact) return;
+    atomicAdd(&pc[0], (unsigned long long)(agg & 0x7fffffffull));
+    atomicAdd(&pc[1], (unsigned long long)(agg >> 31));
+    counts_done();
+  });
+  const uint64_t tile_c = ls.agg & 0x7fffffffull, tile_k = ls.agg >> 31;
+  const bool stage_c = tile_c <= (uint64_t)kStageCorners, stage_k = tile_k <= (uint64_t)kStageCands;
+  // A tile whose corners and candidates both fit the stage emits them before
+  // its look-back, so that the write pass overlaps the wait for the
+  // predecessors; the word records carry list indices relative to the tile's
+  // first corner (lbase holds that), so they need no base either.
+  const bool early = stage_c && stage_k;
+  const uint32_t tag = (uint32_t)threadIdx.x << kStageKBits;
+  int64_t o = 0, oc = 0;        // this thread's next corner and candidate, within the tile
+  int64_t cdst = 0, kdst = 0;   // list index of the tile's first corner and candidate (direct writes)
+  bool on = false;              // whether this thread emits
   // A full word (32 consecutive corners, the columns along a wall parallel
   // to them) goes out as 16-byte stores once its position is 4-aligned.
-  // dk, dl: the list (off 0) or the tile's LDS stage (off the tile's base).
-  auto emit_word = [&](int32_t* __restrict__ dk, int32_t* __restrict__ dl, int64_t off, int w, uint32_t cw) {
+  auto emit_staged = [&](int w, uint32_t cw) {
+    int64_t i = o;
+    if (cw == 0xffffffffu) {
+      const uint32_t e0 = tag | (uint32_t)(32 * w);
+      int j = 0;
+      for (; j < 32 && (i & 3); ++j, ++i) s_c[i] = e0 + j;
+      for (; j + 4 <= 32; j += 4, i += 4)
+        *reinterpret_cast<uint4*>(s_c + i) = make_uint4(e0 + j, e0 + j + 1, e0 + j + 2, e0 + j + 3);
+      for (; j < 32; ++j, ++i) s_c[i] = e0 + j;
+    } else {
+      for (uint32_t bb = cw; bb; bb &= bb - 1, ++i) s_c[i] = tag | (uint32_t)(32 * w + __builtin_ctz(bb));
+    }
+    o = i;
+  };
+  auto emit_direct = [&](int w, uint32_t cw) {
     const int32_t Li = (int32_t)L;
-    int64_t i = o - off;
+    int32_t* __restrict__ dk = ws.ck;
+    int32_t* __restrict__ dl = ws.cl;
+    int64_t i = cdst + o;
     if (cw == 0xffffffffu) {
       const int32_t k0 = 32 * w;
       int j = 0;
@@ -253,56 +270,83 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         dl[i] = Li;
       }
     }
-    o = i + off;
+    o = i - cdst;
   };
   auto put = [&](int w, uint32_t cw, uint32_t ow) {
     if (cw) ws.lrec[(size_t)w * nl + L] = ((uint64_t)(uint32_t)o << 32) | cw;
-    if (stage_c) emit_word(s_ck, s_cl, (int64_t)cbase, w, cw);
-    else emit_word(ws.ck, ws.cl, 0, w, cw);
+    if (stage_c) emit_staged(w, cw);
+    else emit_direct(w, cw);
     for (uint32_t bb = ow; bb; bb &= bb - 1) {
-      const int64_t id = (int64_t)own_col * n + 32 * w + __builtin_ctz(bb);
-      if (stage_k) s_cand[oc - (int64_t)kbase] = id;
-      else ws.cand[oc] = id;
+      const int kc = 32 * w + __builtin_ctz(bb);
+      if (stage_k) s_k[oc] = tag | (uint32_t)kc;
+      else ws.cand[kdst + oc] = (int64_t)own_col * n + kc;
       ++oc;
     }
   };
   // Write pass over the wave's corner words, loads grouped as in the walk;
   // every own cell word w has corner word w.
-  const uint64_t wave_lm = wave_uniform_or(fits ? lm : 0ull);
-  const size_t Lq = L < nl ? L : 0;
-  for (uint64_t r = wave_lm; r;) {
-    int wg[kWalk];
-    uint32_t cw[kWalk], ow[kWalk];
+  auto write_pass = [&]() {
+    o = (int64_t)(ls.excl & 0x7fffffffull);
+    oc = (int64_t)(ls.excl >> 31);
+    const uint64_t wave_lm = wave_uniform_or(on ? lm : 0ull);
+    const size_t Lq = L < nl ? L : 0;
+    for (uint64_t r = wave_lm; r;) {
+      int wg[kWalk];
+      uint32_t cw[kWalk], ow[kWalk];
 #pragma unroll
-    for (int g = 0; g < kWalk; ++g) {
-      const int w = r ? __builtin_ctzll(r) : -1;
-      r &= r - 1;
-      wg[g] = w;
-      // unconditional loads at clamped in-bounds addresses, masked after
-      const int wl = w >= 0 && w < words1 ? w : 0, wc = w >= 0 && w < words ? w : 0;
-      const uint32_t lw = (uint32_t)ws.lrec[(size_t)wl * nl + Lq];
-      const uint32_t cwd = ws.colbits[(size_t)wc * ncol + own_col];
-      cw[g] = fits && w >= 0 && ((lm >> w) & 1) ? lw : 0u;
-      ow[g] = fits && w >= 0 && ((own >> w) & 1) ? cwd : 0u;
+      for (int g = 0; g < kWalk; ++g) {
+        const int w = r ? __builtin_ctzll(r) : -1;
+        r &= r - 1;
+        wg[g] = w;
+        // unconditional loads at clamped in-bounds addresses, masked after
+        const int wl = w >= 0 && w < words1 ? w : 0, wc = w >= 0 && w < words ? w : 0;
+        const uint32_t lw = (uint32_t)ws.lrec[(size_t)wl * nl + Lq];
+        const uint32_t cwd = ws.colbits[(size_t)wc * ncol + own_col];
+        cw[g] = on && w >= 0 && ((lm >> w) & 1) ? lw : 0u;
+        ow[g] = on && w >= 0 && ((own >> w) & 1) ? cwd : 0u;
+      }
+#pragma unroll
+      for (int g = 0; g < kWalk; ++g)
+        if (wg[g] >= 0) put(wg[g], cw[g], ow[g]);
     }
-#pragma unroll
-    for (int g = 0; g < kWalk; ++g)
-      if (wg[g] >= 0) put(wg[g], cw[g], ow[g]);
+    if (on && hi) put(64, (uint32_t)ws.lrec[(size_t)64 * nl + L], 0u);
+  };
+  if (early) {
+    on = L < nl;
+    write_pass();
   }
-  if (fits && hi) put(64, (uint32_t)ws.lrec[(size_t)64 * nl + L], 0u);
+  const uint64_t base = block_lookback(scan_corners(ws), tile, ls.agg, &ctr->flags);
+  const uint64_t total = base + ls.agg;
+  const uint64_t cbase = base & 0x7fffffffull, kbase = base >> 31;
+  // a field that wrapped inside this tile: the pass is void (flagged by the
+  // last tile), and this tile writes nothing
+  const bool wrapped = (total & 0x7fffffffull) < cbase || (total >> 31) < kbase;
+  const bool fits = !wrapped && L < nl && cbase + (ls.excl & 0x7fffffffull) + ncorner <= (uint64_t)ws.cap;
+  if (!early) {
+    on = fits;
+    cdst = (int64_t)cbase;
+    kdst = (int64_t)kbase;
+    write_pass();
+  }
+  if (threadIdx.x == 0) ws.lbase[tile] = (int64_t)cbase;
   __syncthreads();
-  if (stage_c)
+  const int32_t Lt = tile * kBlock;  // the tile's first lattice column
+  if (stage_c && !wrapped)
     for (int64_t i = threadIdx.x; i < (int64_t)tile_c; i += kBlock) {
       const int64_t gi = (int64_t)cbase + i;
+      const uint32_t e = s_c[i];
       if (gi < ws.cap) {
-        ws.ck[gi] = s_ck[i];
-        ws.cl[gi] = s_cl[i];
+        ws.ck[gi] = (int32_t)(e & ((1u << kStageKBits) - 1));
+        ws.cl[gi] = Lt + (int32_t)(e >> kStageKBits);
       }
     }
-  if (stage_k)
+  if (stage_k && !wrapped)
     for (int64_t i = threadIdx.x; i < (int64_t)tile_k; i += kBlock) {
       const int64_t gi = (int64_t)kbase + i;
-      if (gi < ws.cap) ws.cand[gi] = s_cand[i];
+      const uint32_t e = s_k[i];
+      // the staging thread's lattice column (a, b) is cell column (a, b)
+      const int32_t Le = Lt + (int32_t)(e >> kStageKBits), a = Le / n1, b = Le - a * n1;
+      if (gi < ws.cap) ws.cand[gi] = ((int64_t)a * n + b) * n + (int64_t)(e & ((1u << kStageKBits) - 1));
     }
   if (L < nl) {
     ws.lmask[L] = fits ? lm : 0ull;
@@ -310,7 +354,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   }
   if (threadIdx.x == 0 && tile == (int)ws.tiles_lat - 1) {
     // every tile added its counts before publishing them, so they are all in
-    int64_t tc = (int64_t)(so.total & 0x7fffffffull), tk = (int64_t)(so.total >> 31);
+    int64_t tc = (int64_t)(total & 0x7fffffffull), tk = (int64_t)(total >> 31);
     if (exact) {
       const unsigned long long ec = __hip_atomic_load(&pc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned long long ek = __hip_atomic_load(&pc[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
