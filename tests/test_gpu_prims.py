@@ -112,6 +112,40 @@ def test_matches_fp32_twin(gh, scene, n):
     _check_against_twin(out, ref, *[float(x) for x in g])
 
 
+def _lattice_tile_loads(cells, n, tile=256):
+    """Corners and candidates per tile of `tile` consecutive lattice columns
+    (a * (n + 1) + b), from a candidate list (numpy)."""
+    n1 = n + 1
+    col, k = cells // n, cells % n
+    i, j = col // n, col % n
+    corners = np.unique(np.concatenate([((i + di) * n1 + (j + dj)) * n1 + (k + dk)
+                                        for di in (0, 1) for dj in (0, 1) for dk in (0, 1)]))
+    per_c = np.bincount(corners // n1 // tile)
+    per_k = np.bincount((i * n1 + j) // tile)
+    return per_c, per_k
+
+
+@pytest.mark.parametrize("scene,n", [("plane_x", 128), ("box_walls", 160)])
+def test_tiles_beyond_the_stage_match_twin(gh, scene, n):
+    """Walls parallel to the lattice columns put far more corners and
+    candidates in a tile of 256 lattice columns than the corner pass's LDS
+    stage holds (4,096 and 3,072): such a tile writes its lists directly
+    after its look-back, with word records relative to the tile's first
+    corner.  The mesh still equals the FP32 twin's, and the tile sizes are
+    checked on the host so that the path is really taken."""
+    if scene == "plane_x":
+        recs = W.plane_scene((1, 0, 0), 0.1234)
+    else:
+        recs = W.box_scene((0.6, 0.55, 0.8), (0.013, -0.021, 0.008))
+    g = W.grid(n)
+    ref = ohop.gridhop(osdb.SDB.prims(recs), *g, precision="f32")
+    per_c, per_k = _lattice_tile_loads(ref.candidates, n)
+    print(f"{scene} n={n}: largest tile {per_c.max()} corners, {per_k.max()} candidates", flush=True)
+    assert per_c.max() > 4096 and per_k.max() > 3072
+    out = _run(gh, recs, *g)
+    _check_against_twin(out, ref, *[float(x) for x in g])
+
+
 def _prim(ptype, centre, params):
     return W._record(ptype, centre, np.eye(3), params)[None, :]
 
