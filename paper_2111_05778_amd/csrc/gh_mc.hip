@@ -169,9 +169,10 @@ static_assert(kBlock <= (1 << (32 - kStageKBits)), "thread index field");
 static_assert(kMaxN < (1 << kStageKBits), "corner index field");
 static_assert(kBlock == kLatTile, "a corner tile is one block of lattice columns");
 
-// One thread per lattice column (a, b): its corner words, their starting
-// list indices, its corners, and, when (a, b) is also a cell column, its
-// candidate cells.  One packed scan: (candidates << 31) | corners.
+// One thread per lattice column (a, b): its corner words, the index of each
+// word's first corner within the tile, its corners, and, when (a, b) is also
+// a cell column, its candidate cells; thread 0 writes the tile's first list
+// index to lbase.  One packed scan: (candidates << 31) | corners.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_corners(Grid g, Workspace ws,
                                                                                         gh_counters* __restrict__ ctr) {
   __shared__ __align__(16) uint32_t s_c[kStageCorners];
@@ -193,8 +194,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   const uint64_t wave_words = wave_uniform_or(A.uni | (A.uni << 1));
   const bool wave_hi = wave_uniform_or(A.uni >> 63) != 0;
   uint64_t ncorner = 0, ncand = 0;
-  // Corner words go to lbits as they are found (they do not depend on the
-  // scan); the write pass reads them back.
+  // Corner words go to the records lrec as they are found (they do not
+  // depend on the scan); the write pass reads them back.
   uint64_t lm = 0;
   uint32_t hi = 0;
   const int words = (n + 31) >> 5, words1 = (n + 32) >> 5;
