@@ -475,6 +475,35 @@ def test_graph_replay_matches_eager(gh):
             other.run()  # eager work between replays
 
 
+def test_mesh_repeatable_full_size(gh):
+    """The step at full size (CSG-12, N = 512: about 1,000 tiles per scan,
+    each publishing its total, building its outputs in LDS, then looking
+    back) replayed 50 times from its graph, with eager runs of the same
+    step in between: every replay gives the first run's counters, vertices,
+    triangles, cells and cases bit for bit."""
+    import torch
+    native, P = gh
+    n, lo, h = W.grid(512)
+    poly = P.Polygonizer(P.Bound.prims(W.csg_scene(0)), n, lo, h)
+    ref = poly.run()
+    c_ref = dict(ref.counters)
+    keep = {k: getattr(ref, k).clone() for k in ("verts", "vert_edge", "tris", "cells", "cases")}
+    poly.capture()
+    for rep in range(50):
+        poly.replay()
+        if rep % 10 == 9:
+            poly.run()  # eager work between replays
+        torch.cuda.synchronize()
+        c = P.counters_dict(poly.ctr)
+        for k in ("n_hop_evals", "n_cand", "n_corner", "n_cells", "n_vert", "n_tri", "flags"):
+            assert c[k] == c_ref[k], (rep, k)
+        assert torch.equal(poly.verts[:c["n_vert"]], keep["verts"]), rep
+        assert torch.equal(poly.vert_edge[:c["n_vert"]], keep["vert_edge"]), rep
+        assert torch.equal(poly.tris[:c["n_tri"]], keep["tris"]), rep
+        assert torch.equal(poly.cells[:c["n_cells"]], keep["cells"]), rep
+        assert torch.equal(poly.cases[:c["n_cells"]], keep["cases"]), rep
+
+
 def test_csg_n1024_candidates_and_counts(gh):
     # twice the headline size: the candidate cells and every counter of the
     # hop equal the twin's, and the mesh is closed and oriented
